@@ -1,0 +1,184 @@
+/*
+ * cpm.h -- C-ABI of libcpm, the MI355X (gfx950) constant-potential-method
+ * electrode charge solve of the ELECTRODE paper (Ahrens-Iwers et al.,
+ * arXiv 2203.15461).
+ *
+ * The problem (Sec. II.A, Eq. 2): electrode atoms i = 0..n-1 carry Gaussian
+ * charges q_i of reciprocal width eta (the rho_i of Sec. III.B).  Their
+ * Coulomb energy is U = 1/2 q^T A q - b^T q - v^T q, where A (the elastance
+ * matrix) is fixed while the electrodes do not move, b depends on the
+ * electrolyte positions and must be recomputed every step, and v = G v~
+ * holds the applied potential of each atom's electrode (Sec. II.B, Eq. 5).
+ * With total charge held at zero the minimiser is q = S (b + v), with
+ * S = A^-1 - A^-1 e e^T A^-1 / (e^T A^-1 e) (Eqs. 3, 4, 6).  The slab
+ * geometry adds the EW3DC dipole term (Eq. 10), split into an electrode part
+ * that enters A and an electrolyte cross term that enters b (Eq. 12).
+ *
+ * Call order: cpm_create -> cpm_set_electrolyte -> cpm_build_elastance ->
+ * cpm_invert -> cpm_set_potential -> (cpm_potential_vector ->
+ * cpm_solve_charges)*.  Anything else returns CPM_ESTATE.
+ *
+ * Conventions (every entry point):
+ *  - units: Angstrom, elementary charge e, volt.  b is minus the electrolyte
+ *    potential at the electrode atoms (V), so that A q = b + v at the minimum.
+ *  - pointers named d_* are device (HBM) pointers owned by the caller; h_*
+ *    are host pointers owned by the caller.  The context owns everything it
+ *    allocates (A, S and its FP32 / split-BF16 copies, u, d, k-set tables,
+ *    workspaces) and frees it in cpm_destroy.
+ *  - work is enqueued on the HIP stream given to cpm_create (NULL = the
+ *    default stream) and is asynchronous unless stated otherwise.  A kernel
+ *    fault surfaces as CPM_EHIP at the next synchronising call.
+ *  - arguments are validated on the host before any device work; on error
+ *    nothing is enqueued and cpm_last_error() says why.
+ *  - one context per stream; contexts are not thread safe.
+ */
+#ifndef CPM_H
+#define CPM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct cpm_ctx cpm_ctx;
+
+typedef enum {
+  CPM_OK = 0,
+  CPM_EINVAL = 1,        /* bad argument (size, range, non-finite, non-neutral) */
+  CPM_ESTATE = 2,        /* call out of order                                   */
+  CPM_ENOMEM = 3,        /* device allocation failed                            */
+  CPM_EHIP = 4,          /* HIP runtime error (launch, fault, copy)             */
+  CPM_ENOTPD = 5,        /* A is not positive definite (Cholesky pivot <= 0)     */
+  CPM_EUNSUPPORTED = 6   /* valid request this build does not provide          */
+} cpm_status;
+
+/* Boundary geometry.  Only the slab (x, y periodic, EW3DC in z) runs here. */
+typedef enum { CPM_GEOM_SLAB_EW3DC = 0 } cpm_geom;
+
+/* Which copies of S cpm_invert keeps (bit set).  FP64 is always kept. */
+enum { CPM_STORE_F64 = 1, CPM_STORE_F32 = 2, CPM_STORE_BF16X2 = 4 };
+
+/* Solve modes for cpm_solve_charges.  The low byte picks the copy of S that
+ * is streamed; CPM_SOLVE_REFINE adds one FP64 refinement step against A. */
+enum {
+  CPM_SOLVE_F64 = 0,
+  CPM_SOLVE_F32 = 1,
+  CPM_SOLVE_BF16X2 = 2,
+  CPM_SOLVE_REFINE = 0x100
+};
+
+/* Keys for cpm_get_info. */
+enum {
+  CPM_INFO_N = 0,             /* electrode atoms                                  */
+  CPM_INFO_NK = 1,            /* half-space k-vectors |K+|                        */
+  CPM_INFO_NE = 2,            /* electrodes                                       */
+  CPM_INFO_S_SUM = 3,         /* s = e^T A^-1 e (e/V), after cpm_invert           */
+  CPM_INFO_PIVOT = 4,         /* failing Cholesky pivot index after CPM_ENOTPD    */
+  CPM_INFO_LZ = 5,            /* Ewald cell height slab_factor * h (A)            */
+  CPM_INFO_KCUT = 6,          /* k-space cutoff used (1/A)                        */
+  CPM_INFO_M = 7,             /* electrolyte charges                              */
+  CPM_INFO_WORKSPACE = 8,     /* device bytes held by the context                 */
+  CPM_INFO_NPAD = 9           /* padded matrix order (multiple of 64)             */
+};
+
+/* Method knobs; they map onto the paper's `fix electrode` keywords and the
+ * Ewald solver (Sec. S-I.A). */
+typedef struct {
+  double Lx, Ly;        /* in-plane periodic cell (A)                               */
+  double h;             /* slab height z_top - z_bot of the electrodes (A)          */
+  double slab_factor;   /* Ewald cell height Lz = slab_factor * h; needs
+                           (slab_factor - 1) * h > rcut                             */
+  double eta;           /* Gaussian reciprocal width of electrode charges (1/A)    */
+  double alpha;         /* Ewald splitting parameter (1/A)                          */
+  double rcut;          /* real-space cutoff (A), strict r < rcut                   */
+  double kspace_eps;    /* k_c = 2 alpha sqrt(ln(1/kspace_eps)) if kcut <= 0        */
+  double kcut;          /* explicit k-space cutoff (1/A), |k| <= kcut; 0 = derive   */
+  double coulomb_k;     /* e/(4 pi eps0) in V A / e; 0 = 14.399645478425668         */
+  int geometry;         /* cpm_geom                                                 */
+} cpm_params;
+
+/* Create a context bound to `hip_stream` (a hipStream_t, or NULL).
+ * Validates params (finite, positive, slab clearance).  *out is NULL on error. */
+cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out);
+
+/* Electrolyte point charges h_q[m] (e), fixed for the run.  Host pointer,
+ * copied; the charges must sum to zero within 1e-10 sum|q| (the slab term of
+ * Eq. 12 assumes a neutral electrolyte), else CPM_EINVAL.  m >= 0. */
+cpm_status cpm_set_electrolyte(cpm_ctx* ctx, int m, const double* h_q);
+
+/* Assemble the n x n elastance matrix A in FP64 on the device (Eq. 2, A
+ * fixed and precomputed, Sec. II.A): Ewald real space over periodic images,
+ * k space over K+, Gaussian self term, background and the electrode part of
+ * the slab dipole term (Eq. 12).  d_xyz: n x 3 row-major FP64 electrode
+ * coordinates; d_electrode_id: n int32 ids in [0, n_e); d_diag_extra: n FP64
+ * (V/e) added to the diagonal, or NULL.  Validates ids and coordinates
+ * (copying them to the host once).  Synchronous. */
+cpm_status cpm_build_elastance(cpm_ctx* ctx, int n, const double* d_xyz,
+                               const int* d_electrode_id, int n_e,
+                               const double* d_diag_extra);
+
+/* Invert A in FP64 (blocked Cholesky A = L L^T, then A^-1 = L^-T L^-1,
+ * Eq. 3), form u = A^-1 e, s = e^T u and the charge-neutral S of Eq. 4, and
+ * keep the copies of S named by store_flags (CPM_STORE_*).  Synchronous;
+ * returns CPM_ENOTPD (pivot via CPM_INFO_PIVOT) if A is not positive
+ * definite. */
+cpm_status cpm_invert(cpm_ctx* ctx, unsigned store_flags);
+
+/* Applied potentials h_v_electrode[n_e] (V), one per electrode (v = G v~,
+ * Eq. 5).  Precomputes d = S v (Eq. 6 with the S G response cached), so a
+ * solve only adds it.  Host pointer, copied. */
+cpm_status cpm_set_potential(cpm_ctx* ctx, const double* h_v_electrode);
+
+/* b for `batch` electrolyte configurations (Sec. II.A: the per-step cost).
+ * d_xyz: batch x m x 3 FP64 positions (row-major, snapshot-major).
+ * d_b: batch x n output, FP64 (b_is_f32 = 0) or FP32 (b_is_f32 = 1; the
+ * k-space sums then accumulate in FP32, phases are still FP64).  b includes
+ * the real-space erfc sum, the k-space structure-factor term and the
+ * electrolyte cross term of the slab correction (Eq. 12). */
+cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
+                                void* d_b, int b_is_f32);
+
+/* q = S (b + v) for `batch` vectors b (Eqs. 3, 4, 6), then the FP64
+ * neutrality projection q -= (e^T q / s) u, and electrode totals
+ * Q~ = G^T q (Eq. 7 left-hand side).  d_b: batch x n (FP64 or FP32 per
+ * b_is_f32); d_q: batch x n FP64 output; d_Qe: batch x n_e FP64 output or
+ * NULL.  mode: CPM_SOLVE_* (| CPM_SOLVE_REFINE).  batch == 1 streams S once
+ * (matvec); batch > 1 runs Q = S B as one MFMA GEMM.  The chosen copy of S
+ * must have been kept by cpm_invert, else CPM_EINVAL. */
+cpm_status cpm_solve_charges(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32,
+                             unsigned mode, double* d_q, double* d_Qe);
+
+/* Copy a context matrix (n x n, row-major FP64) into caller memory d_out:
+ * which = 0: A, 1: A^-1, 2: S.  Enqueued on the context stream. */
+cpm_status cpm_copy_matrix(const cpm_ctx* ctx, int which, double* d_out);
+
+/* Copy u = A^-1 e (n FP64) or d = S v (which = 1) into caller memory d_out. */
+cpm_status cpm_copy_vector(const cpm_ctx* ctx, int which, double* d_out);
+
+/* Scalar information (CPM_INFO_*). */
+cpm_status cpm_get_info(const cpm_ctx* ctx, int key, double* out);
+
+/* Kernel timing.  While on, every kernel the library launches on the context
+ * stream is bracketed by HIP events and its elapsed time is accumulated per
+ * kernel family (for example "structure_factor", "kspace_project",
+ * "real_space_b", "matvec_f64", "gemm_f64").  Turning it on clears the
+ * totals.  Adds two event records per launch. */
+cpm_status cpm_enable_timing(cpm_ctx* ctx, int on);
+
+/* Total milliseconds and launch count of kernel family `name` recorded since
+ * timing was enabled.  Synchronises the context stream.  A family that never
+ * ran reports 0 and 0. */
+cpm_status cpm_get_timing(cpm_ctx* ctx, const char* name, double* total_ms, long long* count);
+
+/* Wait for all work of the context and report any pending HIP error. */
+cpm_status cpm_synchronize(cpm_ctx* ctx);
+
+/* Human-readable reason for the last non-OK status of ctx (never NULL). */
+const char* cpm_last_error(const cpm_ctx* ctx);
+
+/* Free everything the context owns.  NULL is a no-op. */
+void cpm_destroy(cpm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPM_H */

@@ -1,0 +1,281 @@
+"""Thin ctypes binding of libcpm (include/cpm.h).
+
+Argument marshalling only: device memory comes from torch tensors, the HIP
+stream from torch's current stream, and every step of the charge solve runs
+in the library's HIP kernels.  There is no CPU fallback: if libcpm.so is not
+built, `lib()` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpm.so")
+
+# status codes
+OK, EINVAL, ESTATE, ENOMEM, EHIP, ENOTPD, EUNSUPPORTED = range(7)
+STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_ESTATE", 3: "CPM_ENOMEM", 4: "CPM_EHIP",
+                5: "CPM_ENOTPD", 6: "CPM_EUNSUPPORTED"}
+# store flags, solve modes, info keys
+STORE_F64, STORE_F32, STORE_BF16X2 = 1, 2, 4
+SOLVE_F64, SOLVE_F32, SOLVE_BF16X2, SOLVE_REFINE = 0, 1, 2, 0x100
+INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, npad=9)
+
+EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
+           "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",
+           "cpm_copy_vector", "cpm_get_info", "cpm_enable_timing", "cpm_get_timing",
+           "cpm_synchronize", "cpm_last_error", "cpm_destroy")
+
+
+class CpmParams(ctypes.Structure):
+    _fields_ = [("Lx", ctypes.c_double), ("Ly", ctypes.c_double), ("h", ctypes.c_double),
+                ("slab_factor", ctypes.c_double), ("eta", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("rcut", ctypes.c_double),
+                ("kspace_eps", ctypes.c_double), ("kcut", ctypes.c_double),
+                ("coulomb_k", ctypes.c_double), ("geometry", ctypes.c_int)]
+
+
+class CpmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_LIB = None
+
+
+def lib(path: str | None = None) -> ctypes.CDLL:
+    """Open libcpm.so (built by paper_2203_15461_amd.build); raise if absent."""
+    global _LIB
+    if _LIB is not None and path is None:
+        return _LIB
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is not built: run `python -m paper_2203_15461_amd.build`")
+    L = ctypes.CDLL(p)
+    vp, i, d, u = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
+    sig = {
+        "cpm_create": ([ctypes.POINTER(CpmParams), vp, ctypes.POINTER(vp)], i),
+        "cpm_set_electrolyte": ([vp, i, vp], i),
+        "cpm_build_elastance": ([vp, i, vp, vp, i, vp], i),
+        "cpm_invert": ([vp, u], i),
+        "cpm_set_potential": ([vp, vp], i),
+        "cpm_potential_vector": ([vp, i, vp, vp, i], i),
+        "cpm_solve_charges": ([vp, i, vp, i, u, vp, vp], i),
+        "cpm_copy_matrix": ([vp, i, vp], i),
+        "cpm_copy_vector": ([vp, i, vp], i),
+        "cpm_get_info": ([vp, i, ctypes.POINTER(d)], i),
+        "cpm_enable_timing": ([vp, i], i),
+        "cpm_get_timing": ([vp, ctypes.c_char_p, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)], i),
+        "cpm_synchronize": ([vp], i),
+        "cpm_last_error": ([vp], ctypes.c_char_p),
+        "cpm_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    if path is None:
+        _LIB = L
+    return L
+
+
+@dataclass
+class Params:
+    """Method knobs (cpm_params).  Lz = slab_factor * h."""
+    Lx: float
+    Ly: float
+    h: float
+    slab_factor: float = 3.0
+    eta: float = 1.979
+    alpha: float = 0.3
+    rcut: float = 12.0
+    kspace_eps: float = 1e-8
+    kcut: float = 0.0
+    coulomb_k: float = 0.0
+    geometry: int = 0
+
+    def to_c(self) -> CpmParams:
+        return CpmParams(self.Lx, self.Ly, self.h, self.slab_factor, self.eta, self.alpha,
+                         self.rcut, self.kspace_eps, self.kcut, self.coulomb_k, self.geometry)
+
+    @staticmethod
+    def of(w) -> "Params":
+        return Params(w.Lx, w.Ly, w.h, w.slab_factor, w.eta, w.alpha, w.rcut, w.kspace_eps)
+
+
+def _ptr(t) -> ctypes.c_void_p | None:
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream) -> ctypes.c_void_p:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Context:
+    """One CPM charge-solve context on one HIP stream (see include/cpm.h)."""
+
+    def __init__(self, params: Params, stream=None):
+        self._lib = lib()
+        self._h = ctypes.c_void_p()
+        self._stream = stream
+        p = params.to_c()
+        st = self._lib.cpm_create(ctypes.byref(p), _stream_handle(stream), ctypes.byref(self._h))
+        if st != OK:
+            raise CpmError(st, "cpm_create rejected the parameters")
+        self.params = params
+
+    # -- plumbing -----------------------------------------------------------
+    def _check(self, st: int, what: str):
+        if st != OK:
+            msg = self._lib.cpm_last_error(self._h).decode(errors="replace")
+            raise CpmError(st, f"{what}: {msg}")
+
+    def close(self):
+        if self._h:
+            self._lib.cpm_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self, key: str) -> float:
+        out = ctypes.c_double()
+        self._check(self._lib.cpm_get_info(self._h, INFO[key], ctypes.byref(out)), "cpm_get_info")
+        return out.value
+
+    def enable_timing(self, on: bool = True):
+        """Per-kernel-family HIP event timing on the context stream (clears totals)."""
+        self._check(self._lib.cpm_enable_timing(self._h, int(on)), "cpm_enable_timing")
+
+    def timing(self, name: str):
+        """(total_ms, launches) of one kernel family since timing was enabled."""
+        ms, cnt = ctypes.c_double(), ctypes.c_longlong()
+        self._check(self._lib.cpm_get_timing(self._h, name.encode(), ctypes.byref(ms), ctypes.byref(cnt)),
+                    "cpm_get_timing")
+        return ms.value, cnt.value
+
+    def synchronize(self):
+        self._check(self._lib.cpm_synchronize(self._h), "cpm_synchronize")
+
+    # -- the C-ABI entry points --------------------------------------------
+    def set_electrolyte(self, q):
+        """Electrolyte charges (host array-like of float64), fixed for the run."""
+        import numpy as np
+        qa = np.ascontiguousarray(q, dtype=np.float64)
+        self._check(self._lib.cpm_set_electrolyte(self._h, len(qa), qa.ctypes.data_as(ctypes.c_void_p)),
+                    "cpm_set_electrolyte")
+
+    def build_elastance(self, xyz, eid, n_e: int, diag_extra=None):
+        """xyz: (n, 3) float64 CUDA tensor; eid: (n,) int32 CUDA tensor."""
+        _expect(xyz, "float64", 2)
+        _expect(eid, "int32", 1)
+        if xyz.shape[1] != 3 or eid.shape[0] != xyz.shape[0]:
+            raise ValueError("xyz must be (n, 3) and eid (n,)")
+        if diag_extra is not None:
+            _expect(diag_extra, "float64", 1)
+            if diag_extra.shape[0] != xyz.shape[0]:
+                raise ValueError("diag_extra must be (n,)")
+        self._check(self._lib.cpm_build_elastance(self._h, xyz.shape[0], _ptr(xyz), _ptr(eid), n_e,
+                                                  _ptr(diag_extra)), "cpm_build_elastance")
+
+    def invert(self, store: int = STORE_F64):
+        self._check(self._lib.cpm_invert(self._h, store), "cpm_invert")
+
+    def set_potential(self, v_electrode):
+        """One potential (V) per electrode."""
+        import numpy as np
+        va = np.ascontiguousarray(v_electrode, dtype=np.float64).ravel()
+        if len(va) != int(self.info("ne")):
+            raise ValueError(f"need {int(self.info('ne'))} electrode potentials, got {len(va)}")
+        self._check(self._lib.cpm_set_potential(self._h, va.ctypes.data_as(ctypes.c_void_p)),
+                    "cpm_set_potential")
+
+    def potential_vector(self, xyz, out):
+        """xyz: (batch, m, 3) float64 CUDA tensor; out: (batch, n) float64 or float32."""
+        _expect(xyz, "float64", 3)
+        f32 = _is_f32(out)
+        n, m = int(self.info("n")), int(self.info("m"))
+        if tuple(xyz.shape[1:]) != (m, 3) or tuple(out.shape) != (xyz.shape[0], n):
+            raise ValueError(f"shapes {tuple(xyz.shape)}, {tuple(out.shape)} do not match m={m}, n={n}")
+        self._check(self._lib.cpm_potential_vector(self._h, xyz.shape[0], _ptr(xyz), _ptr(out), f32),
+                    "cpm_potential_vector")
+        return out
+
+    def solve_charges(self, b, mode: int, q_out, Qe_out=None):
+        """b: (batch, n) float64/float32; q_out: (batch, n) float64; Qe_out: (batch, n_e) or None."""
+        _expect(q_out, "float64", 2)
+        f32 = _is_f32(b)
+        n, ne = int(self.info("n")), int(self.info("ne"))
+        if n == 0:   # no elastance yet: the library reports the call-order error
+            self._check(self._lib.cpm_solve_charges(self._h, b.shape[0], _ptr(b), f32, mode,
+                                                    _ptr(q_out), _ptr(Qe_out)), "cpm_solve_charges")
+        if b.dim() != 2 or tuple(b.shape) != tuple(q_out.shape) or b.shape[1] != n:
+            raise ValueError(f"b {tuple(b.shape)} and q {tuple(q_out.shape)} must both be (batch, {n})")
+        if Qe_out is not None:
+            _expect(Qe_out, "float64", 2)
+            if tuple(Qe_out.shape) != (b.shape[0], ne):
+                raise ValueError(f"Qe must be (batch, {ne})")
+        self._check(self._lib.cpm_solve_charges(self._h, b.shape[0], _ptr(b), f32, mode, _ptr(q_out),
+                                                _ptr(Qe_out)), "cpm_solve_charges")
+        return q_out
+
+    def copy_matrix(self, which: int, out):
+        """which 0: A, 1: A^-1, 2: S into an (n, n) float64 tensor."""
+        _expect(out, "float64", 2)
+        n = int(self.info("n"))
+        if tuple(out.shape) != (n, n):
+            raise ValueError(f"need an ({n}, {n}) tensor")
+        self._check(self._lib.cpm_copy_matrix(self._h, which, _ptr(out)), "cpm_copy_matrix")
+        return out
+
+    def copy_vector(self, which: int, out):
+        """which 0: u = A^-1 e, 1: d = S v into an (n,) float64 tensor."""
+        _expect(out, "float64", 1)
+        if out.shape[0] != int(self.info("n")):
+            raise ValueError("need an (n,) tensor")
+        self._check(self._lib.cpm_copy_vector(self._h, which, _ptr(out)), "cpm_copy_vector")
+        return out
+
+
+def _expect(t, dtype: str, ndim: int):
+    if not t.is_cuda:
+        raise ValueError("expected a device (HIP) tensor")
+    if str(t.dtype) != "torch." + dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if t.dim() != ndim or not t.is_contiguous():
+        raise ValueError(f"expected a contiguous {ndim}-d tensor")
+
+
+def _is_f32(t) -> int:
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    if str(t.dtype) == "torch.float32":
+        return 1
+    if str(t.dtype) == "torch.float64":
+        return 0
+    raise ValueError(f"expected float32 or float64, got {t.dtype}")
+
+
+def setup(w, store: int = STORE_F64, stream=None, params: Params | None = None,
+          v_electrode=None) -> Context:
+    """Create a context for a generated workload: electrolyte charges, A, S, v."""
+    import torch
+    ctx = Context(params or Params.of(w), stream)
+    ctx.set_electrolyte(w.electrolyte_q)
+    xyz = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device="cuda").contiguous()
+    eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device="cuda").contiguous()
+    ctx.build_elastance(xyz, eid, int(w.electrode_id.max()) + 1)
+    ctx.invert(store)
+    ctx.set_potential(w.v_electrode if v_electrode is None else v_electrode)
+    return ctx

@@ -1,0 +1,154 @@
+// Assembly of the elastance matrix A in FP64 (ELECTRODE paper, Eq. 2: A is
+// fixed while the electrodes do not move, so it is built once).
+//
+//   A_ij = k_e { sum_t [erfc(alpha r) - erfc(eta_ee r)] / r      (real space)
+//              + sum_{k in K+} 2 W(k) cos(k.(R_i - R_j))          (k space)
+//              - pi / (V alpha^2)                                  (background)
+//              + delta_ij (sqrt(2) eta - 2 alpha) / sqrt(pi)       (Gaussian self)
+//              + (4 pi / V) z_i z_j }                              (slab, Eq. 12)
+//          + delta_ij x_i                                          (optional diagonal)
+//
+// eta_ee = eta / sqrt(2) is the Gaussian-Gaussian width.  The real-space sum
+// runs over all in-plane images t with 0 < r < r_c; the slab clearance
+// (slab_factor - 1) h > r_c means no z image is ever inside r_c.  The
+// k-space sum is a rank-2|K+| symmetric product T T^T with
+// T_i = sqrt(2 k_e W(k)) [cos(k.R_i), sin(k.R_i)], done on FP64 MFMA by the
+// dense kernels; this file builds T chunk by chunk.
+#include "cpm_internal.h"
+
+namespace cpm {
+
+__global__ void k_prep_electrodes(int n, const double* __restrict__ xyz, double Lx, double Ly,
+                                  double Lz, double* ex, double* ey, double* ez, double* fx,
+                                  double* fy, double* fz) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double x = xyz[3 * i + 0], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+  x -= Lx * floor(x / Lx);
+  y -= Ly * floor(y / Ly);
+  ex[i] = x; ey[i] = y; ez[i] = z;
+  fx[i] = x / Lx; fy[i] = y / Ly; fz[i] = z / Lz;
+}
+
+void launch_prep_electrodes(hipStream_t st, int n, const double* xyz, double Lx, double Ly,
+                            double Lz, Buffers& b) {
+  hipLaunchKernelGGL(k_prep_electrodes, dim3((n + 255) / 256), dim3(256), 0, st, n, xyz, Lx, Ly,
+                     Lz, b.ex, b.ey, b.ez, b.efx, b.efy, b.efz);
+}
+
+// Real-space, self, background and slab parts of A, lower triangle only
+// (the upper triangle is mirrored after the k-space product).  Padding rows
+// and columns (index >= n) get the identity.
+__global__ void __launch_bounds__(256) k_real_space_A(
+    int n, int npad, const double* __restrict__ ex, const double* __restrict__ ey,
+    const double* __restrict__ ez, double Lx, double Ly, double rc, double alpha, double eta_ee,
+    double diag_self, double background, double slab_coef, double ke,
+    const double* __restrict__ diag_extra, double* __restrict__ A) {
+  if (blockIdx.x > blockIdx.y) return;               // strictly upper tile
+  const int j = blockIdx.x * 16 + threadIdx.x;
+  const int i = blockIdx.y * 16 + threadIdx.y;
+  if (i >= npad || j >= npad || j > i) return;
+  double val;
+  if (i >= n || j >= n) {
+    val = (i == j) ? 1.0 : 0.0;
+  } else {
+    const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
+    double dx = ex[i] - ex[j], dy = ey[i] - ey[j], dz = ez[i] - ez[j];
+    dx -= Lx * rint(dx * invLx);
+    dy -= Ly * rint(dy * invLy);
+    double sum = 0.0;
+    if (fabs(dz) < rc) {
+      const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
+      const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
+      for (int a = alo; a <= ahi; ++a) {
+        const double X = dx + a * Lx;
+        for (int bb = blo; bb <= bhi; ++bb) {
+          const double Y = dy + bb * Ly;
+          const double r2 = X * X + Y * Y + dz * dz;
+          if (r2 > 0.0 && r2 < rc2 * (1.0 + 1e-12)) {
+            const double r = sqrt(r2);
+            if (r < rc) sum += (erfc(alpha * r) - erfc(eta_ee * r)) / r;
+          }
+        }
+      }
+    }
+    val = sum + background + slab_coef * ez[i] * ez[j];
+    if (i == j) val += diag_self;
+    val *= ke;
+    if (i == j && diag_extra) val += diag_extra[i];
+  }
+  A[(size_t)i * npad + j] = val;
+}
+
+void launch_real_space_A(hipStream_t st, int n, int npad, const Buffers& b, double Lx, double Ly,
+                         double rc, double alpha, double eta_ee, double diag_self,
+                         double background, double slab_coef, double ke, const double* diag_extra,
+                         double* A) {
+  dim3 grid(npad / 16, npad / 16), block(16, 16);
+  hipLaunchKernelGGL(k_real_space_A, grid, block, 0, st, n, npad, b.ex, b.ey, b.ez, Lx, Ly, rc,
+                     alpha, eta_ee, diag_self, background, slab_coef, ke, diag_extra, A);
+}
+
+// Phase table for k indices [k0, k0 + kc) of the flat k list:
+//   T[i][2c] = sqrt(k_e 2W) cos(k.R_i),  T[i][2c+1] = sqrt(k_e 2W) sin(k.R_i).
+// Phases come from fractional coordinates: k.R = 2 pi (nx fx + ny fy + nz fz),
+// reduced to [-1/2, 1/2] turns in FP64 before the sincospi.
+__global__ void k_phase_table(int n, int npad, int k0, int kc, int nk, const int* __restrict__ knx,
+                              const int* __restrict__ kny, const int* __restrict__ knz,
+                              const double* __restrict__ w2, const double* __restrict__ fx,
+                              const double* __restrict__ fy, const double* __restrict__ fz,
+                              double ke, double* __restrict__ T) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y;
+  if (c >= kc) return;
+  const int t = k0 + c;
+  double cv = 0.0, sv = 0.0;
+  if (i < n && t < nk) {
+    double th = knx[t] * fx[i] + kny[t] * fy[i] + knz[t] * fz[i];
+    th -= rint(th);
+    double s, co;
+    sincospi(2.0 * th, &s, &co);
+    const double amp = sqrt(ke * w2[t]);
+    cv = amp * co;
+    sv = amp * s;
+  }
+  double2* row = reinterpret_cast<double2*>(T + (size_t)i * (2 * kc));
+  row[c] = make_double2(cv, sv);
+}
+
+void launch_phase_table(hipStream_t st, int n, int npad, int k0, int kc, int nk, const Buffers& b,
+                        double ke, double* table) {
+  dim3 grid((kc + 127) / 128, npad), block(128);
+  hipLaunchKernelGGL(k_phase_table, grid, block, 0, st, n, npad, k0, kc, nk, b.knx,
+                     b.kny, b.knz, b.w2, b.efx, b.efy, b.efz, ke, table);
+}
+
+// Copy the lower triangle onto the upper one (tiled transpose through LDS).
+__global__ void k_mirror_lower(int npad, double* A) {
+  __shared__ double tile[32][33];
+  const int bx = blockIdx.x, by = blockIdx.y;         // source tile (row by, col bx), by > bx
+  if (by <= bx) {
+    if (by == bx) {                                    // diagonal tile: in place
+      const int r = by * 32 + threadIdx.y, c = bx * 32 + threadIdx.x;
+      for (int yy = 0; yy < 32; yy += 8) {
+        const int rr = r + yy;
+        if (c > rr) A[(size_t)rr * npad + c] = A[(size_t)c * npad + rr];
+      }
+    }
+    return;
+  }
+  for (int yy = 0; yy < 32; yy += 8)
+    tile[threadIdx.y + yy][threadIdx.x] =
+        A[(size_t)(by * 32 + threadIdx.y + yy) * npad + bx * 32 + threadIdx.x];
+  __syncthreads();
+  for (int yy = 0; yy < 32; yy += 8)
+    A[(size_t)(bx * 32 + threadIdx.y + yy) * npad + by * 32 + threadIdx.x] =
+        tile[threadIdx.x][threadIdx.y + yy];
+}
+
+void launch_mirror_lower(hipStream_t st, int npad, double* A) {
+  dim3 grid(npad / 32, npad / 32), block(32, 8);
+  hipLaunchKernelGGL(k_mirror_lower, grid, block, 0, st, npad, A);
+}
+
+}  // namespace cpm

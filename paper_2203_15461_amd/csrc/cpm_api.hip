@@ -1,0 +1,690 @@
+// Host side of libcpm: argument validation, the k-space set, device buffers
+// and the launch sequences behind each C-ABI entry point (include/cpm.h).
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "cpm_internal.h"
+
+using namespace cpm;
+
+namespace {
+
+cpm_status fail(cpm_ctx* c, cpm_status st, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return st;
+}
+
+#define HIP_TRY(ctx, expr)                                                               \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail((ctx), CPM_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+  } while (0)
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+template <typename T>
+cpm_status dalloc(cpm_ctx* c, T** p, size_t count) {
+  if (*p) return CPM_OK;
+  void* q = nullptr;
+  if (hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 16) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(c, CPM_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
+  }
+  c->bytes += count * sizeof(T);
+  *p = static_cast<T*>(q);
+  return CPM_OK;
+}
+
+template <typename T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+#define TRY(expr)                  \
+  do {                             \
+    cpm_status s_ = (expr);        \
+    if (s_ != CPM_OK) return s_;   \
+  } while (0)
+
+// check for launch errors without synchronising
+cpm_status launched(cpm_ctx* c, const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, CPM_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return CPM_OK;
+}
+
+// ---- kernel timing ---------------------------------------------------------
+hipEvent_t take_event(cpm_ctx* c) {
+  if (!c->evpool.empty()) {
+    hipEvent_t e = c->evpool.back();
+    c->evpool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// fold finished (or, with wait, all) pending event pairs into the totals
+void resolve_timing(cpm_ctx* c, bool wait) {
+  std::vector<cpm_ctx::Pending> keep;
+  for (auto& p : c->pending) {
+    if (!wait && hipEventQuery(p.b) != hipSuccess) {
+      keep.push_back(p);
+      continue;
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto& t = c->totals[p.name];
+      t.first += ms;
+      t.second += 1;
+    }
+    c->evpool.push_back(p.a);
+    c->evpool.push_back(p.b);
+  }
+  c->pending.swap(keep);
+  (void)hipGetLastError();
+}
+
+// brackets the launches of one kernel family with events while timing is on
+struct Timed {
+  cpm_ctx* c;
+  const char* name;
+  hipEvent_t a = nullptr;
+  Timed(cpm_ctx* c_, const char* n) : c(c_), name(n) {
+    if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, c->stream);
+  }
+  ~Timed() {
+    if (!a) return;
+    hipEvent_t b = take_event(c);
+    if (!b) return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({name, a, b});
+    if (c->pending.size() > 4096) resolve_timing(c, false);
+  }
+};
+
+// Half-space k set K+ with |k| <= kc, walked column by column ((nx, ny) with
+// nx ascending, then ny ascending) and nz ascending inside a column, cut into
+// runs of at most RUN consecutive nz.
+void build_kset(cpm_ctx* c, std::vector<KRun>& runs, std::vector<double>& w2,
+                std::vector<int>& kx, std::vector<int>& ky, std::vector<int>& kz) {
+  const double twopi = 2.0 * M_PI;
+  const double Lx = c->p.Lx, Ly = c->p.Ly, Lz = c->Lz, kc = c->kc;
+  const int nxm = (int)std::floor(kc * Lx / twopi);
+  const int nym = (int)std::floor(kc * Ly / twopi);
+  const int nzm = (int)std::floor(kc * Lz / twopi);
+  const double a2 = 4.0 * c->p.alpha * c->p.alpha;
+  for (int nx = 0; nx <= nxm; ++nx)
+    for (int ny = -nym; ny <= nym; ++ny) {
+      if (nx == 0 && ny < 0) continue;
+      const int zlo = (nx == 0 && ny == 0) ? 1 : -nzm;
+      int run_start = -1, cnt = 0;
+      for (int nz = zlo; nz <= nzm; ++nz) {
+        const double gx = twopi * nx / Lx, gy = twopi * ny / Ly, gz = twopi * nz / Lz;
+        const double k2 = gx * gx + gy * gy + gz * gz;
+        const bool keep = k2 <= kc * kc;
+        if (keep) {
+          if (run_start < 0 || cnt == RUN || nz != run_start + cnt) {
+            runs.push_back(KRun{nx, ny, nz, 0, (int)w2.size(), 0});
+            run_start = nz;
+            cnt = 0;
+          }
+          w2.push_back(2.0 * (4.0 * M_PI / c->V) * std::exp(-k2 / a2) / k2);
+          kx.push_back(nx); ky.push_back(ny); kz.push_back(nz);
+          ++cnt;
+          runs.back().len = cnt;
+        }
+      }
+    }
+}
+
+cpm_status ensure_step_buffers(cpm_ctx* c) {
+  Buffers& b = c->b;
+  if (b.sf_part) return CPM_OK;
+  // chunking of the per-snapshot sums (fixed per context, so results are
+  // reproducible): ~512 workgroups per kernel, >= 64 charges per SF chunk,
+  // >= 32 charges per real-space chunk
+  const int run_blocks = (c->nruns + 255) / 256;
+  c->mchunks = std::max(1, std::min((512 + run_blocks - 1) / run_blocks, std::max(1, c->m / 64)));
+  const int atom_blocks = (c->n + 255) / 256;
+  c->rchunks = std::max(1, std::min((512 + atom_blocks - 1) / atom_blocks, std::max(1, c->m / 32)));
+  TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
+  TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
+  TRY(dalloc(c, &b.phik_part, (size_t)c->n * c->kchunks));
+  TRY(dalloc(c, &b.phir_part, (size_t)c->n * c->rchunks));
+  TRY(dalloc(c, &b.mz, 1));
+  return CPM_OK;
+}
+
+cpm_status ensure_solve_buffers(cpm_ctx* c, int batch) {
+  Buffers& b = c->b;
+  if (batch > b.bpad_rows) {
+    const size_t old = (size_t)b.bpad_rows * c->npad * sizeof(double);
+    if (b.qt) c->bytes -= 4 * old;
+    dfree(b.qt); dfree(b.res); dfree(b.qpad); dfree(b.bpad);
+    const size_t sz = (size_t)batch * c->npad;
+    TRY(dalloc(c, &b.qt, sz));
+    TRY(dalloc(c, &b.res, sz));
+    TRY(dalloc(c, &b.qpad, sz));
+    TRY(dalloc(c, &b.bpad, sz));
+    dfree(b.means);
+    TRY(dalloc(c, &b.means, (size_t)batch));
+    // padding rows and columns of these buffers are read by the GEMMs: zero them once
+    HIP_TRY(c, hipMemsetAsync(b.qt, 0, sz * sizeof(double), c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.res, 0, sz * sizeof(double), c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.qpad, 0, sz * sizeof(double), c->stream));
+    HIP_TRY(c, hipMemsetAsync(b.bpad, 0, sz * sizeof(double), c->stream));
+    b.bpad_rows = batch;
+  }
+  return CPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out) {
+  if (!out) return CPM_EINVAL;
+  *out = nullptr;
+  if (!params) return CPM_EINVAL;
+  cpm_ctx* c = new (std::nothrow) cpm_ctx();
+  if (!c) return CPM_ENOMEM;
+  c->p = *params;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  const cpm_params& p = c->p;
+  cpm_status st = CPM_OK;
+  if (p.geometry != CPM_GEOM_SLAB_EW3DC)
+    st = fail(c, CPM_EUNSUPPORTED, "geometry %d: only the EW3DC slab runs here", p.geometry);
+  else if (!finite_pos(p.Lx) || !finite_pos(p.Ly) || !finite_pos(p.h))
+    st = fail(c, CPM_EINVAL, "Lx, Ly, h must be finite and > 0");
+  else if (!(std::isfinite(p.slab_factor) && p.slab_factor > 1.0))
+    st = fail(c, CPM_EINVAL, "slab_factor must be > 1");
+  else if (!finite_pos(p.eta) || !finite_pos(p.alpha) || !finite_pos(p.rcut))
+    st = fail(c, CPM_EINVAL, "eta, alpha, rcut must be finite and > 0");
+  else if (!(p.kcut > 0.0) && !(p.kspace_eps > 0.0 && p.kspace_eps < 1.0))
+    st = fail(c, CPM_EINVAL, "need kcut > 0 or 0 < kspace_eps < 1");
+  else if (!std::isfinite(p.kcut) || !std::isfinite(p.coulomb_k) || p.coulomb_k < 0.0)
+    st = fail(c, CPM_EINVAL, "kcut and coulomb_k must be finite (coulomb_k >= 0)");
+  else if ((p.slab_factor - 1.0) * p.h <= p.rcut)
+    st = fail(c, CPM_EINVAL, "slab clearance (slab_factor - 1) * h = %g must exceed rcut = %g",
+              (p.slab_factor - 1.0) * p.h, p.rcut);
+  if (st != CPM_OK) {
+    // keep the message reachable through a static buffer for a NULL context
+    static thread_local std::string last;
+    last = c->err;
+    delete c;
+    return st;
+  }
+  c->Lz = p.slab_factor * p.h;
+  c->V = p.Lx * p.Ly * c->Lz;
+  c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
+  c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
+
+  std::vector<KRun> runs;
+  std::vector<double> w2;
+  std::vector<int> kx, ky, kz;
+  build_kset(c, runs, w2, kx, ky, kz);
+  c->nk = (int)w2.size();
+  c->nruns = (int)runs.size();
+  if (c->nk == 0) {
+    delete c;
+    return CPM_EINVAL;
+  }
+  Buffers& b = c->b;
+  if ((st = dalloc(c, &b.runs, runs.size())) != CPM_OK ||
+      (st = dalloc(c, &b.w2, w2.size())) != CPM_OK ||
+      (st = dalloc(c, &b.knx, kx.size())) != CPM_OK ||
+      (st = dalloc(c, &b.kny, ky.size())) != CPM_OK ||
+      (st = dalloc(c, &b.knz, kz.size())) != CPM_OK ||
+      (st = dalloc(c, &b.flag, 4)) != CPM_OK || (st = dalloc(c, &b.scal, 8)) != CPM_OK) {
+    cpm_destroy(c);
+    return st;
+  }
+  if (hipMemcpy(b.runs, runs.data(), runs.size() * sizeof(KRun), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b.w2, w2.data(), w2.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b.knx, kx.data(), kx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b.kny, ky.data(), ky.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(b.knz, kz.data(), kz.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
+    cpm_destroy(c);
+    return CPM_EHIP;
+  }
+  // projection: 64 runs per chunk (LDS holds 64 * RUN weighted k values)
+  c->runs_per_kchunk = 64;
+  c->kchunks = (c->nruns + 63) / 64;
+  *out = c;
+  return CPM_OK;
+}
+
+cpm_status cpm_set_electrolyte(cpm_ctx* c, int m, const double* h_q) {
+  if (!c) return CPM_EINVAL;
+  if (m < 0 || (m > 0 && !h_q)) return fail(c, CPM_EINVAL, "m must be >= 0 and h_q non-NULL");
+  double sum = 0.0, asum = 0.0;
+  for (int j = 0; j < m; ++j) {
+    if (!std::isfinite(h_q[j])) return fail(c, CPM_EINVAL, "electrolyte charge %d not finite", j);
+    sum += h_q[j];
+    asum += std::fabs(h_q[j]);
+  }
+  if (std::fabs(sum) > 1e-10 * std::max(asum, 1e-300) && m > 0)
+    return fail(c, CPM_EINVAL, "electrolyte not neutral: sum q = %g", sum);
+  if (c->have_elyt) return fail(c, CPM_ESTATE, "electrolyte already set for this context");
+  c->m = m;
+  TRY(dalloc(c, &c->b.elq, (size_t)std::max(m, 1)));
+  if (m > 0)
+    HIP_TRY(c, hipMemcpy(c->b.elq, h_q, (size_t)m * sizeof(double), hipMemcpyHostToDevice));
+  c->have_elyt = true;
+  return CPM_OK;
+}
+
+cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
+                               const double* d_diag_extra) {
+  if (!c) return CPM_EINVAL;
+  if (n <= 0 || n_e <= 0 || !d_xyz || !d_eid)
+    return fail(c, CPM_EINVAL, "need n > 0, n_e > 0 and non-NULL coordinates and ids");
+  if (c->have_A && n != c->n)
+    return fail(c, CPM_EINVAL, "rebuild with n = %d differs from n = %d of this context", n, c->n);
+  c->h_xyz.resize((size_t)3 * n);
+  c->h_eid.resize(n);
+  HIP_TRY(c, hipMemcpy(c->h_xyz.data(), d_xyz, (size_t)3 * n * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(c, hipMemcpy(c->h_eid.data(), d_eid, (size_t)n * sizeof(int), hipMemcpyDeviceToHost));
+  double zmin = 1e300, zmax = -1e300;
+  for (int i = 0; i < n; ++i) {
+    for (int a = 0; a < 3; ++a)
+      if (!std::isfinite(c->h_xyz[3 * i + a])) return fail(c, CPM_EINVAL, "coordinate of atom %d not finite", i);
+    if (c->h_eid[i] < 0 || c->h_eid[i] >= n_e)
+      return fail(c, CPM_EINVAL, "electrode id %d of atom %d outside [0, %d)", c->h_eid[i], i, n_e);
+    zmin = std::min(zmin, c->h_xyz[3 * i + 2]);
+    zmax = std::max(zmax, c->h_xyz[3 * i + 2]);
+  }
+  if (c->Lz - (zmax - zmin) <= c->p.rcut)
+    return fail(c, CPM_EINVAL, "electrode z extent %g leaves no slab clearance in Lz = %g", zmax - zmin, c->Lz);
+  c->have_A = c->have_inv = c->have_v = false;
+  c->n = n;
+  c->n_e = n_e;
+  c->npad = ((n + TILE - 1) / TILE) * TILE;
+  const int npad = c->npad;
+  Buffers& b = c->b;
+  TRY(dalloc(c, &b.ex, n)); TRY(dalloc(c, &b.ey, n)); TRY(dalloc(c, &b.ez, n));
+  TRY(dalloc(c, &b.efx, n)); TRY(dalloc(c, &b.efy, n)); TRY(dalloc(c, &b.efz, n));
+  TRY(dalloc(c, &b.eid, n));
+  TRY(dalloc(c, &b.A, (size_t)npad * npad));
+  HIP_TRY(c, hipMemcpyAsync(b.eid, d_eid, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
+  const cpm_params& p = c->p;
+  launch_prep_electrodes(c->stream, n, d_xyz, p.Lx, p.Ly, c->Lz, b);
+  TRY(launched(c, "prep_electrodes"));
+  const double eta_ee = p.eta / std::sqrt(2.0);
+  const double diag_self = (std::sqrt(2.0) * p.eta - 2.0 * p.alpha) / std::sqrt(M_PI);
+  const double background = -M_PI / (c->V * p.alpha * p.alpha);
+  const double slab_coef = 4.0 * M_PI / c->V;
+  launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, p.rcut, p.alpha, eta_ee, diag_self,
+                      background, slab_coef, c->ke, d_diag_extra, b.A);
+  TRY(launched(c, "real_space_A"));
+  // k space: A += T T^T over chunks of KC k-vectors (2 KC columns)
+  const int KC = 2048;
+  TRY(dalloc(c, &b.table, (size_t)npad * 2 * KC));
+  for (int k0 = 0; k0 < c->nk; k0 += KC) {
+    launch_phase_table(c->stream, n, npad, k0, KC, c->nk, b, c->ke, b.table);
+    launch_gemm_f64(c->stream, false, true, npad, npad, 2 * KC, 1.0, b.table, 2 * KC, b.table,
+                    2 * KC, 1.0, b.A, npad, /*tri=*/1, 0);
+    TRY(launched(c, "kspace syrk"));
+  }
+  launch_mirror_lower(c->stream, npad, b.A);
+  TRY(launched(c, "mirror"));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  dfree(b.table);
+  c->have_A = true;
+  return CPM_OK;
+}
+
+cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_A) return fail(c, CPM_ESTATE, "cpm_invert before cpm_build_elastance");
+  if (store_flags & ~(unsigned)(CPM_STORE_F64 | CPM_STORE_F32 | CPM_STORE_BF16X2))
+    return fail(c, CPM_EINVAL, "unknown store flags 0x%x", store_flags);
+  const int n = c->n, npad = c->npad, nb = npad / TILE;
+  Buffers& b = c->b;
+  TRY(dalloc(c, &b.L, (size_t)npad * npad));
+  TRY(dalloc(c, &b.Dinv, (size_t)nb * TILE * TILE));
+  TRY(dalloc(c, &b.Ainv, (size_t)npad * npad));
+  TRY(dalloc(c, &b.S, (size_t)npad * npad));
+  TRY(dalloc(c, &b.u, npad));
+  TRY(dalloc(c, &b.d, npad));
+  TRY(dalloc(c, &b.vat, npad));
+  hipStream_t st = c->stream;
+  HIP_TRY(c, hipMemcpyAsync(b.L, b.A, (size_t)npad * npad * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(c, hipMemsetAsync(b.flag, 0, sizeof(int), st));
+  HIP_TRY(c, hipMemsetAsync(b.u, 0, npad * sizeof(double), st));
+  // blocked right-looking Cholesky on the lower triangle of L
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * TILE, rest = npad - k0 - TILE;
+    double* diag = b.L + (size_t)k0 * npad + k0;
+    launch_potrf_diag(st, diag, npad, b.Dinv + (size_t)kb * TILE * TILE, b.flag, k0);
+    if (rest > 0) {
+      double* panel = b.L + (size_t)(k0 + TILE) * npad + k0;
+      // L21 = A21 L11^-T
+      launch_gemm_f64(st, false, true, rest, TILE, TILE, 1.0, panel, npad,
+                      b.Dinv + (size_t)kb * TILE * TILE, TILE, 0.0, panel, npad, 0, 0);
+      // A22 -= L21 L21^T (lower tiles)
+      double* trail = b.L + (size_t)(k0 + TILE) * npad + (k0 + TILE);
+      launch_gemm_f64(st, false, true, rest, rest, TILE, -1.0, panel, npad, panel, npad, 1.0, trail,
+                      npad, 1, 0);
+    }
+    TRY(launched(c, "cholesky"));
+  }
+  int flag = 0;
+  HIP_TRY(c, hipMemcpyAsync(&flag, b.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  if (flag != 0) {
+    c->pivot = flag - 1;
+    return fail(c, CPM_ENOTPD, "elastance matrix not positive definite at pivot %d", c->pivot);
+  }
+  // X = L^-1 by blocked forward substitution (X stored in Ainv's buffer first)
+  double* X = b.Ainv;
+  launch_set_identity(st, npad, X);
+  for (int kb = 0; kb < nb; ++kb) {
+    const int k0 = kb * TILE, cols = k0 + TILE, rest = npad - k0 - TILE;
+    double* Xk = X + (size_t)k0 * npad;
+    // X_k = L_kk^-1 X_k on the columns that can be non-zero
+    launch_gemm_f64(st, false, false, TILE, cols, TILE, 1.0, b.Dinv + (size_t)kb * TILE * TILE,
+                    TILE, Xk, npad, 0.0, Xk, npad, 0, 0);
+    if (rest > 0) {
+      // X_below -= L_below,k X_k
+      launch_gemm_f64(st, false, false, rest, cols, TILE, -1.0,
+                      b.L + (size_t)(k0 + TILE) * npad + k0, npad, Xk, npad, 1.0,
+                      X + (size_t)(k0 + TILE) * npad, npad, 0, 0);
+    }
+    TRY(launched(c, "trtri"));
+  }
+  // A^-1 = X^T X (lower tiles, k from max(row, col)), result into L's buffer,
+  // then swap names so Ainv holds A^-1
+  launch_gemm_f64(st, true, false, npad, npad, npad, 1.0, X, npad, X, npad, 0.0, b.L, npad, 1, 1);
+  launch_mirror_lower(st, npad, b.L);
+  TRY(launched(c, "lauum"));
+  std::swap(b.L, b.Ainv);
+  // u = A^-1 e, s = e^T u, S = A^-1 - u u^T / s (Eq. 4)
+  launch_row_sums(st, n, npad, b.Ainv, b.u);
+  launch_sum_vector(st, n, b.u, b.scal);
+  launch_make_S(st, n, npad, b.Ainv, b.u, b.scal, b.S);
+  TRY(launched(c, "projection"));
+  if (store_flags & CPM_STORE_F32) {
+    TRY(dalloc(c, &b.S32, (size_t)npad * npad));
+  }
+  if (store_flags & CPM_STORE_BF16X2) {
+    TRY(dalloc(c, &b.Shi, (size_t)npad * npad));
+    TRY(dalloc(c, &b.Slo, (size_t)npad * npad));
+  }
+  if (store_flags & (CPM_STORE_F32 | CPM_STORE_BF16X2))
+    launch_convert_S(st, npad, b.S, (store_flags & CPM_STORE_F32) ? b.S32 : nullptr,
+                     (store_flags & CPM_STORE_BF16X2) ? b.Shi : nullptr,
+                     (store_flags & CPM_STORE_BF16X2) ? b.Slo : nullptr);
+  TRY(launched(c, "convert"));
+  HIP_TRY(c, hipMemcpyAsync(&c->s_sum, b.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  c->store = store_flags | CPM_STORE_F64;
+  c->have_inv = true;
+  return CPM_OK;
+}
+
+cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_set_potential before cpm_invert");
+  if (!h_v_electrode) return fail(c, CPM_EINVAL, "h_v_electrode is NULL");
+  for (int a = 0; a < c->n_e; ++a)
+    if (!std::isfinite(h_v_electrode[a])) return fail(c, CPM_EINVAL, "potential %d not finite", a);
+  c->h_v.assign(h_v_electrode, h_v_electrode + c->n_e);
+  std::vector<double> vat(c->npad, 0.0);
+  for (int i = 0; i < c->n; ++i) vat[i] = c->h_v[c->h_eid[i]];
+  HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  // d = S v  (S G v~ of Eq. 6, cached)
+  launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
+                0.0, c->b.d, c->npad, 0);
+  TRY(launched(c, "set_potential"));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->have_v = true;
+  return CPM_OK;
+}
+
+cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_A || !c->have_elyt)
+    return fail(c, CPM_ESTATE, "cpm_potential_vector needs cpm_set_electrolyte and cpm_build_elastance");
+  if (batch <= 0 || !d_b || (c->m > 0 && !d_xyz))
+    return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL buffers");
+  if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
+  TRY(ensure_step_buffers(c));
+  const cpm_params& p = c->p;
+  const int n = c->n, m = c->m;
+  const size_t esz = b_is_f32 ? sizeof(float) : sizeof(double);
+  Buffers& b = c->b;
+  hipStream_t st = c->stream;
+  for (int s = 0; s < batch; ++s) {
+    const double* xyz = d_xyz ? d_xyz + (size_t)s * m * 3 : nullptr;
+    void* out = static_cast<char*>(d_b) + (size_t)s * n * esz;
+    if (m == 0) {
+      HIP_TRY(c, hipMemsetAsync(out, 0, n * esz, st));
+      continue;
+    }
+    { Timed t(c, "structure_factor");
+      launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz, b.elq,
+                                p.Lx, p.Ly, c->Lz, b.sf_part); }
+    { Timed t(c, "sf_reduce");
+      launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
+    { Timed t(c, "kspace_project");
+      launch_b_kspace_project(st, b_is_f32, n, c->nruns, c->kchunks, c->runs_per_kchunk, b.runs, b,
+                              b.sfw, b.phik_part); }
+    { Timed t(c, "real_space_b");
+      launch_b_real_space(st, n, m, c->rchunks, b, xyz, b.elq, p.Lx, p.Ly, p.rcut, p.alpha, p.eta,
+                          b.phir_part); }
+    { Timed t(c, "dipole");
+      launch_b_dipole(st, m, xyz, b.elq, b.mz); }
+    { Timed t(c, "combine");
+      launch_b_combine(st, n, c->kchunks, c->rchunks, b.phik_part, b.phir_part, b, b.mz,
+                       4.0 * M_PI / c->V, c->ke, out, b_is_f32); }
+    TRY(launched(c, "potential_vector"));
+  }
+  return CPM_OK;
+}
+
+cpm_status cpm_solve_charges(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
+                             double* d_q, double* d_Qe) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_v) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_set_potential");
+  if (batch <= 0 || !d_b || !d_q) return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL b, q");
+  if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
+  const unsigned prec = mode & 0xffu;
+  const bool refine = (mode & CPM_SOLVE_REFINE) != 0;
+  if ((mode & ~0x1ffu) != 0 || prec > 2) return fail(c, CPM_EINVAL, "unknown solve mode 0x%x", mode);
+  if (prec == 1 && !(c->store & CPM_STORE_F32)) return fail(c, CPM_EINVAL, "FP32 copy of S not kept");
+  if (prec == 2 && !(c->store & CPM_STORE_BF16X2))
+    return fail(c, CPM_EINVAL, "split-BF16 copy of S not kept");
+  if (prec == 2 && batch < GEMM_MIN_BATCH)
+    return fail(c, CPM_EUNSUPPORTED, "split-BF16 solves run as a batched GEMM (batch >= %d)",
+                GEMM_MIN_BATCH);
+  const int n = c->n, npad = c->npad;
+  const bool gemm = batch >= GEMM_MIN_BATCH && prec != 1;
+  const int rows = gemm ? ((batch + TILE - 1) / TILE) * TILE : batch;
+  TRY(ensure_solve_buffers(c, rows));
+  Buffers& b = c->b;
+  hipStream_t st = c->stream;
+  const void* Sm = (prec == 1) ? (const void*)b.S32 : (const void*)b.S;
+  const int which = (prec == 1) ? 1 : 0;
+  const char* mv_name = (prec == 1) ? "matvec_f32" : "matvec_f64";
+
+  // S~ x for a batch stored row-wise (stride npad) -> y (stride npad) (+ add)
+  auto apply_S = [&](const double* x, double* y, bool accumulate) {
+    if (prec == 0) {
+      Timed t(c, "gemm_f64");
+      launch_gemm_f64(st, false, false, rows, npad, npad, 1.0, x, npad, b.S, npad,
+                      accumulate ? 1.0 : 0.0, y, npad, 0, 0);
+    } else {
+      Timed t(c, "gemm_bf16x3");
+      launch_gemm_bf16x3(st, rows, npad, npad, x, b.Shi, b.Slo, y, accumulate ? 1 : 0);
+    }
+  };
+
+  // Every product with S~ acts on a centred vector: S e = 0 makes that exact,
+  // and it keeps the rounding of a low-precision S~ away from the large
+  // uniform part of b and of the refinement residual.
+  if (!gemm) {
+    // q~ = S~ (b - mean(b) e) + d, one streaming pass over S~ per vector
+    { Timed t(c, "row_means");
+      launch_row_means(st, n, batch, d_b, b_is_f32, n, b.means); }
+    { Timed t(c, mv_name);
+      launch_matvec(st, which, n, npad, Sm, batch, d_b, b_is_f32, n, b.means, b.d, 0, 1.0, b.qt,
+                    npad, 0); }
+    if (!refine) {
+      Timed t(c, "finalize");
+      launch_finalize(st, n, batch, b.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe);
+      return launched(c, "solve");
+    }
+    // one refinement step (FP64 except the products with S~):
+    //   qp = P q~ (P: neutrality projection), r = (b + v) - A qp, q = P (qp + S~ r).
+    // Valid because S A qp = qp when e^T qp = 0.
+    { Timed t(c, "finalize");
+      launch_finalize(st, n, batch, b.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, b.qpad, npad,
+                      nullptr); }
+    { Timed t(c, "make_rhs");
+      launch_make_rhs(st, n, npad, batch, d_b, b_is_f32, b.vat, b.res); }
+    { Timed t(c, "matvec_f64");
+      launch_matvec(st, 0, n, npad, b.A, batch, b.qpad, 0, npad, nullptr, b.res, npad, 1.0, b.qt,
+                    npad, 1); }
+    { Timed t(c, "row_means");
+      launch_row_means(st, n, batch, b.qt, 0, npad, b.means); }
+    { Timed t(c, mv_name);
+      launch_matvec(st, which, n, npad, Sm, batch, b.qt, 0, npad, b.means, b.qpad, npad, 1.0, b.res,
+                    npad, 0); }
+    { Timed t(c, "finalize");
+      launch_finalize(st, n, batch, b.res, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
+    return launched(c, "solve (refined)");
+  }
+
+  // batched: Q~ = B S~ as one MFMA GEMM over all vectors (rows padded to 64)
+  { Timed t(c, "row_means");
+    launch_row_means(st, n, batch, d_b, b_is_f32, n, b.means); }
+  { Timed t(c, "pad_rows");
+    launch_pad_rows(st, n, npad, batch, rows, d_b, b_is_f32, b.means, b.bpad); }
+  apply_S(b.bpad, b.qpad, false);
+  if (!refine) {
+    Timed t(c, "finalize");
+    launch_finalize(st, n, batch, b.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe);
+    return launched(c, "solve (batched)");
+  }
+  { Timed t(c, "finalize");
+    launch_finalize(st, n, batch, b.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, b.qt, npad,
+                    nullptr); }
+  { Timed t(c, "make_rhs");
+    launch_make_rhs(st, n, npad, batch, d_b, b_is_f32, b.vat, b.res); }
+  // R = C - Qp A (FP64 MFMA), centred, then Q = Qp + R S~
+  { Timed t(c, "gemm_f64");
+    launch_gemm_f64(st, false, false, rows, npad, npad, -1.0, b.qt, npad, b.A, npad, 1.0, b.res,
+                    npad, 0, 0); }
+  { Timed t(c, "center_rows");
+    launch_center_rows(st, n, npad, batch, b.res); }
+  apply_S(b.res, b.qt, true);
+  { Timed t(c, "finalize");
+    launch_finalize(st, n, batch, b.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
+  return launched(c, "solve (batched, refined)");
+}
+
+cpm_status cpm_enable_timing(cpm_ctx* c, int on) {
+  if (!c) return CPM_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  resolve_timing(c, true);
+  c->totals.clear();
+  c->timing = on != 0;
+  return CPM_OK;
+}
+
+cpm_status cpm_get_timing(cpm_ctx* c, const char* name, double* total_ms, long long* count) {
+  if (!c || !name || !total_ms || !count) return CPM_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  resolve_timing(c, true);
+  auto it = c->totals.find(name);
+  *total_ms = (it == c->totals.end()) ? 0.0 : it->second.first;
+  *count = (it == c->totals.end()) ? 0 : it->second.second;
+  return CPM_OK;
+}
+
+cpm_status cpm_copy_matrix(const cpm_ctx* c, int which, double* d_out) {
+  if (!c || !d_out) return CPM_EINVAL;
+  const double* src = nullptr;
+  if (which == 0 && c->have_A) src = c->b.A;
+  if (which == 1 && c->have_inv) src = c->b.Ainv;
+  if (which == 2 && c->have_inv) src = c->b.S;
+  if (!src) return CPM_ESTATE;
+  const int n = c->n, npad = c->npad;
+  if (hipMemcpy2DAsync(d_out, n * sizeof(double), src, npad * sizeof(double), n * sizeof(double), n,
+                       hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return CPM_EHIP;
+  return CPM_OK;
+}
+
+cpm_status cpm_copy_vector(const cpm_ctx* c, int which, double* d_out) {
+  if (!c || !d_out) return CPM_EINVAL;
+  const double* src = nullptr;
+  if (which == 0 && c->have_inv) src = c->b.u;
+  if (which == 1 && c->have_v) src = c->b.d;
+  if (!src) return CPM_ESTATE;
+  if (hipMemcpyAsync(d_out, src, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
+    return CPM_EHIP;
+  return CPM_OK;
+}
+
+cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
+  if (!c || !out) return CPM_EINVAL;
+  switch (key) {
+    case CPM_INFO_N: *out = c->n; return CPM_OK;
+    case CPM_INFO_NK: *out = c->nk; return CPM_OK;
+    case CPM_INFO_NE: *out = c->n_e; return CPM_OK;
+    case CPM_INFO_S_SUM: *out = c->s_sum; return c->have_inv ? CPM_OK : CPM_ESTATE;
+    case CPM_INFO_PIVOT: *out = c->pivot; return CPM_OK;
+    case CPM_INFO_LZ: *out = c->Lz; return CPM_OK;
+    case CPM_INFO_KCUT: *out = c->kc; return CPM_OK;
+    case CPM_INFO_M: *out = c->m; return CPM_OK;
+    case CPM_INFO_WORKSPACE: *out = (double)c->bytes; return CPM_OK;
+    case CPM_INFO_NPAD: *out = c->npad; return CPM_OK;
+    default: return CPM_EINVAL;
+  }
+}
+
+cpm_status cpm_synchronize(cpm_ctx* c) {
+  if (!c) return CPM_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipGetLastError());
+  return CPM_OK;
+}
+
+const char* cpm_last_error(const cpm_ctx* c) {
+  if (!c) return "no context";
+  return c->err.c_str();
+}
+
+void cpm_destroy(cpm_ctx* c) {
+  if (!c) return;
+  Buffers& b = c->b;
+  dfree(b.ex); dfree(b.ey); dfree(b.ez); dfree(b.efx); dfree(b.efy); dfree(b.efz); dfree(b.eid);
+  dfree(b.runs); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
+  dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
+  dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
+  dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.mz); dfree(b.qt);
+  dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (auto& pe : c->pending) { (void)hipEventDestroy(pe.a); (void)hipEventDestroy(pe.b); }
+  for (auto e : c->evpool) (void)hipEventDestroy(e);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,165 @@
+// Library-internal declarations of libcpm (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/cpm.h"
+
+namespace cpm {
+
+constexpr int TILE = 64;           // dense-matrix tile; matrices are padded to it
+constexpr int RUN = 16;            // consecutive k_z values per k-space run
+constexpr int GEMM_MIN_BATCH = 4;  // batches this large solve as one MFMA GEMM
+constexpr double KE_DEFAULT = 14.399645478425668;
+
+// One run of the k-space set: a column (nx, ny) and up to RUN consecutive nz.
+struct KRun {
+  int nx, ny, nz0, len;
+  int koff;                        // index of its first k in the flat k arrays
+  int pad;
+};
+
+struct Buffers {
+  // electrode geometry (internal order = caller order), SoA, x and y wrapped
+  double* ex = nullptr;  double* ey = nullptr;  double* ez = nullptr;
+  double* efx = nullptr; double* efy = nullptr; double* efz = nullptr;  // fractional
+  int* eid = nullptr;
+  // k-set
+  KRun* runs = nullptr;            // nruns
+  double* w2 = nullptr;            // 2 W(k), nk (flat run order)
+  int* knx = nullptr; int* kny = nullptr; int* knz = nullptr;     // nk
+  // dense matrices, npad x npad row-major FP64 unless noted
+  double* A = nullptr;             // elastance (kept for refinement)
+  double* L = nullptr;             // work: Cholesky factor, later X = L^-1
+  double* Dinv = nullptr;          // nb x 64 x 64 inverses of diagonal blocks of L
+  double* Ainv = nullptr;          // A^-1
+  double* S = nullptr;             // charge-neutral capacitance (Eq. 4)
+  float* S32 = nullptr;            // FP32 copy
+  uint16_t* Shi = nullptr;         // split-BF16 copy: S ~ hi + lo
+  uint16_t* Slo = nullptr;
+  double* u = nullptr;             // A^-1 e (n)
+  double* d = nullptr;             // S v (npad)
+  double* vat = nullptr;           // per-atom applied potential v = G v~ (npad)
+  double* table = nullptr;         // k-space phase table chunk for the A SYRK
+  double* elq = nullptr;           // electrolyte charges (m)
+  int* flag = nullptr;             // device status word (Cholesky pivot)
+  // per-step workspaces
+  double* sf_part = nullptr;       // m-chunk partial structure factors (2 * nk * mchunks)
+  double* sfw = nullptr;           // 2W-weighted structure factor (2 * nk)
+  double* phik_part = nullptr;     // k-chunk partial potentials (n * kchunks)
+  double* phir_part = nullptr;     // m-chunk partial real-space potentials (n * rchunks)
+  double* mz = nullptr;            // electrolyte dipole M_z (per snapshot)
+  double* qt = nullptr;            // q-tilde (batch x npad)
+  double* res = nullptr;           // refinement residual / corrections (batch x npad)
+  double* bpad = nullptr;          // padded b for batched solves (bpad_rows x npad)
+  double* qpad = nullptr;          // padded GEMM output (bpad_rows x npad)
+  double* means = nullptr;         // per-vector uniform part removed before S products
+  int bpad_rows = 0;
+  double* scal = nullptr;          // small scalars (s and friends)
+};
+
+}  // namespace cpm
+
+struct cpm_ctx {
+  cpm_params p{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  bool have_elyt = false, have_A = false, have_inv = false, have_v = false;
+  int n = 0, npad = 0, n_e = 0, m = 0;
+  double Lz = 0, V = 0, kc = 0, ke = 0;
+  int nk = 0, nruns = 0;
+  int mchunks = 1, kchunks = 1, rchunks = 1;
+  int runs_per_kchunk = 0;
+  unsigned store = 0;
+  double s_sum = 0;                // e^T A^-1 e
+  int pivot = -1;
+  size_t bytes = 0;
+  std::vector<double> h_v;         // per-electrode potential
+  std::vector<double> h_xyz;       // electrode coordinates (host copy)
+  std::vector<int> h_eid;
+  cpm::Buffers b;
+  // kernel timing (cpm_enable_timing)
+  bool timing = false;
+  struct Pending { const char* name; hipEvent_t a, b; };
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> evpool;
+  std::map<std::string, std::pair<double, long long>> totals;
+};
+
+namespace cpm {
+
+// ---- launchers (each enqueues on `st`; shapes are checked by the caller) ----
+// assembly
+void launch_prep_electrodes(hipStream_t st, int n, const double* xyz, double Lx, double Ly,
+                            double Lz, Buffers& b);
+void launch_real_space_A(hipStream_t st, int n, int npad, const Buffers& b, double Lx,
+                         double Ly, double rc, double alpha, double eta_ee, double diag_self,
+                         double background, double slab_coef, double ke, const double* diag_extra,
+                         double* A);
+void launch_phase_table(hipStream_t st, int n, int npad, int k0, int kc, int nk, const Buffers& b,
+                        double ke, double* table);
+void launch_mirror_lower(hipStream_t st, int npad, double* A);
+
+// dense FP64 algebra (MFMA)
+// C = beta C + alpha op(A) op(B); M, N multiples of 64; K multiple of 16.
+// tri: 0 all tiles, 1 lower tiles only.  kmode: 0 K range [0,K), 1 [max(m0,n0), K).
+void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int K,
+                     double alpha, const double* A, int lda, const double* B, int ldb,
+                     double beta, double* C, int ldc, int tri, int kmode);
+void launch_potrf_diag(hipStream_t st, double* Lblk, int ld, double* Dinv, int* flag, int k0);
+void launch_set_identity(hipStream_t st, int npad, double* X);
+void launch_row_sums(hipStream_t st, int n, int npad, const double* M, double* out);
+void launch_sum_vector(hipStream_t st, int n, const double* v, double* out);
+void launch_make_S(hipStream_t st, int n, int npad, const double* Ainv, const double* u,
+                   const double* s_dev, double* S);
+void launch_convert_S(hipStream_t st, int npad, const double* S, float* S32, uint16_t* hi,
+                      uint16_t* lo);
+
+// per-step solve
+// y[b] = sign * M x[b] + addscale * add[b * add_ld + .]   (add may be NULL)
+// (x[b] - xshift[b] e when xshift is given)
+void launch_matvec(hipStream_t st, int which /*0 f64, 1 f32*/, int n, int npad,
+                   const void* M, int batch, const void* x, int x_is_f32, int ldx,
+                   const double* xshift, const double* add, int add_ld, double addscale, double* y,
+                   int ldy, int negate);
+void launch_row_means(hipStream_t st, int n, int batch, const void* x, int x_is_f32, int ldx,
+                      double* means);
+void launch_center_rows(hipStream_t st, int n, int ld, int batch, double* x);
+void launch_make_rhs(hipStream_t st, int n, int npad, int batch, const void* bsrc, int b_is_f32,
+                     const double* v, double* c);
+// q[b] = (qt[b] + add) - (e^T (qt[b] + add) / s) u ; Qe[b] = G^T q[b]   (add may be NULL)
+void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldqt, const double* add,
+                     const double* u, const double* s_dev, const int* eid, int n_e, double* q,
+                     int ldq, double* Qe);
+void launch_pad_rows(hipStream_t st, int n, int npad, int batch, int rows, const void* src,
+                     int src_is_f32, const double* shift, double* dst);
+// C (M x N, FP64) (+)= Bm (M x K, FP64, split to BF16 hi/lo on load) * S, with
+// S symmetric given as BF16 hi/lo (N x K row-major): 3 MFMA products, FP32
+// accumulation.  M, N multiples of 64, K multiple of 32.
+void launch_gemm_bf16x3(hipStream_t st, int M, int N, int K, const double* Bm, const uint16_t* Shi,
+                        const uint16_t* Slo, double* C, int accumulate);
+
+// b vector
+void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk,
+                               int m, int mchunks, const double* xyz, const double* q,
+                               double Lx, double Ly, double Lz, double* part);
+void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
+                        const double* w2, double* sfw);
+void launch_b_kspace_project(hipStream_t st, int fp32, int n, int nruns, int kchunks,
+                             int runs_per_chunk, const KRun* runs, const Buffers& b,
+                             const double* sfw, double* part);
+void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
+                         const double* xyz, const double* q, double Lx, double Ly, double rc,
+                         double alpha, double eta, double* part);
+void launch_b_dipole(hipStream_t st, int m, const double* xyz, const double* q, double* mz);
+void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
+                      const double* phir, const Buffers& b, const double* mz, double slab_coef,
+                      double ke, void* out, int out_is_f32);
+
+}  // namespace cpm

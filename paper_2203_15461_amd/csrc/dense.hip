@@ -1,0 +1,546 @@
+// Dense FP64 linear algebra on CDNA4 matrix cores and the HBM-streaming solve.
+//
+// The paper obtains the capacitance matrix by inverting the elastance A
+// (Sec. II.A, Eq. 3) and projects it onto the charge-neutral subspace (Eq. 4).
+// Here A = L L^T by a blocked right-looking Cholesky (64-wide panels: a
+// one-workgroup diagonal factorisation, a panel solve and a trailing
+// symmetric update as MFMA GEMMs), X = L^-1 by blocked forward substitution,
+// and A^-1 = X^T X as a triangular-aware MFMA GEMM.
+//
+// v_mfma_f64_16x16x4f64 operand layout (lane l of a wave64):
+//   A operand: element (row l%16, k l/16); B operand: (k l/16, col l%16);
+//   result register r: element (row l/16 + 4 r, col l%16).
+#include "cpm_internal.h"
+
+namespace cpm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// GEMM: C = beta C + alpha op(A) op(B), 64x64 tile per 256-thread workgroup,
+// each wave a 32x32 quadrant of 2x2 MFMA blocks, K staged through LDS in
+// slabs of 16 with the next slab prefetched into registers.
+// ---------------------------------------------------------------------------
+template <bool TA, bool TB>
+__global__ void __launch_bounds__(256) k_gemm_f64(int M, int N, int K, double alpha,
+                                                  const double* __restrict__ A, int lda,
+                                                  const double* __restrict__ B, int ldb,
+                                                  double beta, double* C, int ldc, int tri,
+                                                  int kmode) {
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  if (tri && n0 > m0) return;
+  const int kbeg = kmode ? (m0 > n0 ? m0 : n0) : 0;
+  __shared__ double As[16][64 + 4];
+  __shared__ double Bs[16][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+    if (!TA) {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      const double* src = A + (size_t)(m0 + r) * lda + k0 + c;
+      for (int t = 0; t < 4; ++t) ra[t] = src[t];
+    } else {
+      const int r = tid >> 4, c = (tid & 15) * 4;
+      const double* src = A + (size_t)(k0 + r) * lda + m0 + c;
+      for (int t = 0; t < 4; ++t) ra[t] = src[t];
+    }
+    if (!TB) {
+      const int r = tid >> 4, c = (tid & 15) * 4;
+      const double* src = B + (size_t)(k0 + r) * ldb + n0 + c;
+      for (int t = 0; t < 4; ++t) rb[t] = src[t];
+    } else {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      const double* src = B + (size_t)(n0 + r) * ldb + k0 + c;
+      for (int t = 0; t < 4; ++t) rb[t] = src[t];
+    }
+  };
+  auto store = [&]() {
+    if (!TA) {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      for (int t = 0; t < 4; ++t) As[c + t][r] = ra[t];
+    } else {
+      const int r = tid >> 4, c = (tid & 15) * 4;
+      for (int t = 0; t < 4; ++t) As[r][c + t] = ra[t];
+    }
+    if (!TB) {
+      const int r = tid >> 4, c = (tid & 15) * 4;
+      for (int t = 0; t < 4; ++t) Bs[r][c + t] = rb[t];
+    } else {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      for (int t = 0; t < 4; ++t) Bs[c + t][r] = rb[t];
+    }
+  };
+
+  if (kbeg < K) load(kbeg);
+  for (int k0 = kbeg; k0 < K; k0 += 16) {
+    store();
+    __syncthreads();
+    if (k0 + 16 < K) load(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), cc = lane & 15;
+      const double a0 = As[kr][wm + cc], a1 = As[kr][wm + 16 + cc];
+      const double b0 = Bs[kr][wn + cc], b1 = Bs[kr][wn + 16 + cc];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + a * 16 + (lane >> 4) + 4 * r;
+        const int col = n0 + wn + b * 16 + (lane & 15);
+        double* cp = C + (size_t)row * ldc + col;
+        const double v = alpha * acc[a][b][r];
+        *cp = (beta != 0.0) ? v + beta * (*cp) : v;
+      }
+}
+
+void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int K, double alpha,
+                     const double* A, int lda, const double* B, int ldb, double beta, double* C,
+                     int ldc, int tri, int kmode) {
+  if (M <= 0 || N <= 0) return;
+  dim3 grid(N / 64, M / 64), block(256);
+  if (!transA && !transB)
+    hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc, tri, kmode);
+  else if (!transA && transB)
+    hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc, tri, kmode);
+  else if (transA && !transB)
+    hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc, tri, kmode);
+  else
+    hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
+                       ldb, beta, C, ldc, tri, kmode);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal 64x64 block of the Cholesky factorisation, in one workgroup:
+// unblocked right-looking factorisation in LDS, then the inverse of the
+// triangular factor (one column per thread).  A pivot <= 0 (or NaN) records
+// 1 + its global index in *flag (first one wins) and continues with 1.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_potrf_diag(double* Lblk, int ld, double* Dinv, int* flag,
+                                                    int k0) {
+  __shared__ double a[64][65];
+  __shared__ double inv[64][65];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    a[i][j] = (j <= i) ? Lblk[(size_t)i * ld + j] : 0.0;
+  }
+  __syncthreads();
+  for (int j = 0; j < 64; ++j) {
+    if (tid == 0) {
+      double piv = a[j][j];
+      if (!(piv > 0.0)) {
+        atomicCAS(flag, 0, k0 + j + 1);
+        piv = 1.0;
+      }
+      a[j][j] = sqrt(piv);
+    }
+    __syncthreads();
+    const double djj = a[j][j];
+    if (tid > j && tid < 64) a[tid][j] /= djj;
+    __syncthreads();
+    const int i = tid & 63;
+    if (i > j) {
+      const double lij = a[i][j];
+      for (int l = j + 1 + (tid >> 6); l <= i; l += 4) a[i][l] -= lij * a[l][j];
+    }
+    __syncthreads();
+  }
+  if (tid < 64) {
+    const int c = tid;
+    for (int r = 0; r < c; ++r) inv[r][c] = 0.0;
+    inv[c][c] = 1.0 / a[c][c];
+    for (int r = c + 1; r < 64; ++r) {
+      double s = 0.0;
+      for (int t = c; t < r; ++t) s += a[r][t] * inv[t][c];
+      inv[r][c] = -s / a[r][r];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < 64 * 64; e += 256) {
+    const int i = e >> 6, j = e & 63;
+    Lblk[(size_t)i * ld + j] = (j <= i) ? a[i][j] : 0.0;
+    Dinv[e] = inv[i][j];
+  }
+}
+
+void launch_potrf_diag(hipStream_t st, double* Lblk, int ld, double* Dinv, int* flag, int k0) {
+  hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, Lblk, ld, Dinv, flag, k0);
+}
+
+__global__ void k_set_identity(int npad, double* X) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)npad * npad) return;
+  const int i = (int)(e / npad), j = (int)(e % npad);
+  X[e] = (i == j) ? 1.0 : 0.0;
+}
+
+void launch_set_identity(hipStream_t st, int npad, double* X) {
+  const size_t tot = (size_t)npad * npad;
+  hipLaunchKernelGGL(k_set_identity, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, npad,
+                     X);
+}
+
+// ---------------------------------------------------------------------------
+// wave64 helpers
+// ---------------------------------------------------------------------------
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// block-wide sum of 256 threads in a fixed order; result valid in every thread
+__device__ inline double block_sum256(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  const double t = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  __syncthreads();
+  return t;
+}
+
+// out[i] = sum_{j<n} M[i][j] for i < n (one wave per row, fixed order)
+__global__ void k_row_sums(int n, int npad, const double* __restrict__ M, double* out) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += M[(size_t)row * npad + j];
+  s = wave_sum(s);
+  if (lane == 0) out[row] = s;
+}
+
+void launch_row_sums(hipStream_t st, int n, int npad, const double* M, double* out) {
+  hipLaunchKernelGGL(k_row_sums, dim3((n + 3) / 4), dim3(256), 0, st, n, npad, M, out);
+}
+
+__global__ void k_sum_vector(int n, const double* __restrict__ v, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += v[i];
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+void launch_sum_vector(hipStream_t st, int n, const double* v, double* out) {
+  hipLaunchKernelGGL(k_sum_vector, dim3(1), dim3(256), 0, st, n, v, out);
+}
+
+// S = A^-1 - u u^T / s on the n x n block (Eq. 4); zero in the padding.
+__global__ void k_make_S(int n, int npad, const double* __restrict__ Ainv,
+                         const double* __restrict__ u, const double* __restrict__ s_dev,
+                         double* __restrict__ S) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)npad * npad) return;
+  const int i = (int)(e / npad), j = (int)(e % npad);
+  double v = 0.0;
+  if (i < n && j < n) v = Ainv[e] - u[i] * u[j] / (*s_dev);
+  S[e] = v;
+}
+
+void launch_make_S(hipStream_t st, int n, int npad, const double* Ainv, const double* u,
+                   const double* s_dev, double* S) {
+  const size_t tot = (size_t)npad * npad;
+  hipLaunchKernelGGL(k_make_S, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, npad,
+                     Ainv, u, s_dev, S);
+}
+
+// round-to-nearest-even FP32 -> BF16
+__device__ inline uint16_t f32_to_bf16(float f) {
+  uint32_t x = __float_as_uint(f);
+  if ((x & 0x7f800000u) == 0x7f800000u) return (uint16_t)(x >> 16);
+  x += 0x7fffu + ((x >> 16) & 1u);
+  return (uint16_t)(x >> 16);
+}
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+
+// FP32 copy and split-BF16 pair of S (hi = bf16(S), lo = bf16(S - hi)).
+__global__ void k_convert_S(size_t tot, const double* __restrict__ S, float* S32, uint16_t* hi,
+                            uint16_t* lo) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= tot) return;
+  const double v = S[e];
+  if (S32) S32[e] = (float)v;
+  if (hi) {
+    const uint16_t h = f32_to_bf16((float)v);
+    hi[e] = h;
+    lo[e] = f32_to_bf16((float)(v - (double)bf16_to_f32(h)));
+  }
+}
+
+void launch_convert_S(hipStream_t st, int npad, const double* S, float* S32, uint16_t* hi,
+                      uint16_t* lo) {
+  const size_t tot = (size_t)npad * npad;
+  hipLaunchKernelGGL(k_convert_S, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, tot, S,
+                     S32, hi, lo);
+}
+
+// ---------------------------------------------------------------------------
+// Matrix-vector product y[b] = sign * M x[b] + addscale * add, streaming the
+// npad x npad matrix M (FP64 or FP32) once per vector.  One wave per row:
+// 16-byte coalesced loads of the row, x read through the cache, wave
+// reduction in a fixed order.
+// ---------------------------------------------------------------------------
+template <typename TM>
+__global__ void __launch_bounds__(256) k_matvec(int n, int npad, const TM* __restrict__ M,
+                                                const void* __restrict__ xv, int x_is_f32, int ldx,
+                                                const double* __restrict__ xshift,
+                                                const double* __restrict__ add, int add_ld,
+                                                double addscale, double* __restrict__ y, int ldy,
+                                                int negate) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int b = blockIdx.y;
+  if (row >= npad) return;
+  constexpr int VEC = 16 / sizeof(TM);
+  const TM* mrow = M + (size_t)row * npad;
+  const double* xd = reinterpret_cast<const double*>(xv) + (size_t)b * ldx;
+  const float* xf = reinterpret_cast<const float*>(xv) + (size_t)b * ldx;
+  const double sh = xshift ? xshift[b] : 0.0;
+  double s = 0.0;
+  for (int j0 = lane * VEC; j0 < npad; j0 += 64 * VEC) {
+    TM mv[VEC];
+    if constexpr (VEC == 2) {
+      const double2 t = *reinterpret_cast<const double2*>(mrow + j0);
+      mv[0] = t.x; mv[1] = t.y;
+    } else {
+      const float4 t = *reinterpret_cast<const float4*>(mrow + j0);
+      mv[0] = t.x; mv[1] = t.y; mv[2] = t.z; mv[3] = t.w;
+    }
+#pragma unroll
+    for (int t = 0; t < VEC; ++t) {
+      const int j = j0 + t;
+      double xj = 0.0;
+      if (j < n) xj = (x_is_f32 ? (double)xf[j] : xd[j]) - sh;
+      s += (double)mv[t] * xj;
+    }
+  }
+  s = wave_sum(s);
+  if (lane == 0 && row < npad) {
+    double v = negate ? -s : s;
+    if (add) v += addscale * add[(size_t)b * add_ld + row];
+    y[(size_t)b * ldy + row] = v;
+  }
+}
+
+void launch_matvec(hipStream_t st, int which, int n, int npad, const void* M, int batch,
+                   const void* x, int x_is_f32, int ldx, const double* xshift, const double* add,
+                   int add_ld, double addscale, double* y, int ldy, int negate) {
+  dim3 grid(npad / 4, batch), block(256);
+  if (which == 0)
+    hipLaunchKernelGGL(k_matvec<double>, grid, block, 0, st, n, npad, (const double*)M, x,
+                       x_is_f32, ldx, xshift, add, add_ld, addscale, y, ldy, negate);
+  else
+    hipLaunchKernelGGL(k_matvec<float>, grid, block, 0, st, n, npad, (const float*)M, x,
+                       x_is_f32, ldx, xshift, add, add_ld, addscale, y, ldy, negate);
+}
+
+// means[b] = (1/n) sum_{i<n} x[b][i]: the uniform part of a right-hand side.
+// S e = 0, so S x = S (x - mean e); removing it first keeps the rounding of a
+// low-precision S from acting on the (large) uniform potential.
+__global__ void __launch_bounds__(256) k_row_means(int n, const void* __restrict__ x, int x_is_f32,
+                                                   int ldx, double* __restrict__ means) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256)
+    s += x_is_f32 ? (double)reinterpret_cast<const float*>(x)[(size_t)b * ldx + i]
+                  : reinterpret_cast<const double*>(x)[(size_t)b * ldx + i];
+  s = block_sum256(s, sh);
+  if (threadIdx.x == 0) means[b] = s / n;
+}
+
+void launch_row_means(hipStream_t st, int n, int batch, const void* x, int x_is_f32, int ldx,
+                      double* means) {
+  hipLaunchKernelGGL(k_row_means, dim3(batch), dim3(256), 0, st, n, x, x_is_f32, ldx, means);
+}
+
+// x[b][i] -= mean_b over i < n (in place, FP64, stride ld)
+__global__ void __launch_bounds__(256) k_center_rows(int n, int ld, double* __restrict__ x) {
+  __shared__ double sh[4];
+  double* row = x + (size_t)blockIdx.x * ld;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += row[i];
+  s = block_sum256(s, sh) / n;
+  for (int i = threadIdx.x; i < n; i += 256) row[i] -= s;
+}
+
+void launch_center_rows(hipStream_t st, int n, int ld, int batch, double* x) {
+  hipLaunchKernelGGL(k_center_rows, dim3(batch), dim3(256), 0, st, n, ld, x);
+}
+
+// c[b] = b[b] + v (FP64, npad stride, zero padding): the right-hand side of
+// A q = b + v used by the refinement residual.
+__global__ void k_make_rhs(int n, int npad, const void* __restrict__ bsrc, int b_is_f32,
+                           const double* __restrict__ v, double* __restrict__ c) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, b = blockIdx.y;
+  if (i >= npad) return;
+  double x = 0.0;
+  if (i < n)
+    x = (b_is_f32 ? (double)reinterpret_cast<const float*>(bsrc)[(size_t)b * n + i]
+                  : reinterpret_cast<const double*>(bsrc)[(size_t)b * n + i]) + v[i];
+  c[(size_t)b * npad + i] = x;
+}
+
+void launch_make_rhs(hipStream_t st, int n, int npad, int batch, const void* bsrc, int b_is_f32,
+                     const double* v, double* c) {
+  hipLaunchKernelGGL(k_make_rhs, dim3((npad + 255) / 256, batch), dim3(256), 0, st, n, npad, bsrc,
+                     b_is_f32, v, c);
+}
+
+// ---------------------------------------------------------------------------
+// Neutrality projection and electrode totals, one workgroup per vector:
+//   q = qt - (e^T qt / s) u,   Q_alpha = sum_{i in alpha} q_i  (FP64).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_finalize(int n, const double* __restrict__ qt, int ldqt,
+                                                  const double* __restrict__ add,
+                                                  const double* __restrict__ u,
+                                                  const double* __restrict__ s_dev,
+                                                  const int* __restrict__ eid, int n_e,
+                                                  double* __restrict__ q, int ldq,
+                                                  double* __restrict__ Qe) {
+  __shared__ double sh[4];
+  const int b = blockIdx.x;
+  const double* x = qt + (size_t)b * ldqt;
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += add ? x[i] + add[i] : x[i];
+  s = block_sum256(s, sh);
+  const double mu = s / (*s_dev);
+  double* qo = q + (size_t)b * ldq;
+  for (int i = threadIdx.x; i < n; i += 256) qo[i] = (add ? x[i] + add[i] : x[i]) - mu * u[i];
+  if (Qe) {
+    __syncthreads();
+    for (int a = 0; a < n_e; ++a) {
+      double t = 0.0;
+      for (int i = threadIdx.x; i < n; i += 256)
+        if (eid[i] == a) t += qo[i];
+      t = block_sum256(t, sh);
+      if (threadIdx.x == 0) Qe[(size_t)b * n_e + a] = t;
+    }
+  }
+}
+
+void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldqt, const double* add,
+                     const double* u, const double* s_dev, const int* eid, int n_e, double* q,
+                     int ldq, double* Qe) {
+  hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, st, n, qt, ldqt, add, u, s_dev, eid,
+                     n_e, q, ldq, Qe);
+}
+
+// dst (rows x npad, FP64) = src (batch x n) zero-padded in both directions
+__global__ void k_pad_rows(int n, int npad, int batch, int rows, const void* __restrict__ src,
+                           int src_is_f32, const double* __restrict__ shift,
+                           double* __restrict__ dst) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rows * npad) return;
+  const int r = (int)(e / npad), j = (int)(e % npad);
+  double v = 0.0;
+  if (r < batch && j < n)
+    v = (src_is_f32 ? (double)reinterpret_cast<const float*>(src)[(size_t)r * n + j]
+                    : reinterpret_cast<const double*>(src)[(size_t)r * n + j]) -
+        (shift ? shift[r] : 0.0);
+  dst[e] = v;
+}
+
+void launch_pad_rows(hipStream_t st, int n, int npad, int batch, int rows, const void* src,
+                     int src_is_f32, const double* shift, double* dst) {
+  const size_t tot = (size_t)rows * npad;
+  hipLaunchKernelGGL(k_pad_rows, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, npad,
+                     batch, rows, src, src_is_f32, shift, dst);
+}
+
+// ---------------------------------------------------------------------------
+// Batched solve on BF16 matrix cores: C (+)= Bm S with both operands split as
+// x ~ hi + lo (BF16 pairs) and three products hi*hi + hi*lo + lo*hi
+// accumulated in FP32 (the lo*lo term is below FP32 resolution of the sum).
+// S is symmetric, so its rows serve as the columns of the right operand and
+// both operands are read K-contiguous.  64x64 tile, 4 waves of 2x2
+// v_mfma_f32_16x16x32_bf16 blocks, K slabs of 32 through LDS.
+//   operand layout (lane l): A (row l%16, k 8(l/16)..+7); B (k 8(l/16)..+7,
+//   col l%16); result register r: (row 4(l/16) + r, col l%16).
+// ---------------------------------------------------------------------------
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K,
+                                                     const double* __restrict__ Bm,
+                                                     const uint16_t* __restrict__ Shi,
+                                                     const uint16_t* __restrict__ Slo,
+                                                     double* __restrict__ C, int accumulate) {
+  constexpr int P = 40;  // LDS row pitch in BF16 elements (32 + 8)
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[64 * P], Al[64 * P], Bh[64 * P], Bl[64 * P];
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  v4f acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lc = (tid & 3) * 8;   // this thread's load slot: row, first k
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    {
+      const double* src = Bm + (size_t)(m0 + lr) * K + k0 + lc;
+      uint16_t hi[8], lo[8];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float f = (float)src[t];
+        hi[t] = f32_to_bf16(f);
+        lo[t] = f32_to_bf16(f - bf16_to_f32(hi[t]));
+      }
+      *reinterpret_cast<uint4*>(&Ah[lr * P + lc]) = *reinterpret_cast<const uint4*>(hi);
+      *reinterpret_cast<uint4*>(&Al[lr * P + lc]) = *reinterpret_cast<const uint4*>(lo);
+      const size_t so = (size_t)(n0 + lr) * K + k0 + lc;
+      *reinterpret_cast<uint4*>(&Bh[lr * P + lc]) = *reinterpret_cast<const uint4*>(Shi + so);
+      *reinterpret_cast<uint4*>(&Bl[lr * P + lc]) = *reinterpret_cast<const uint4*>(Slo + so);
+    }
+    __syncthreads();
+    const int kk = 8 * (lane >> 4), rr = lane & 15;
+    v8bf ah[2], al[2], bh[2], bl[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      ah[a] = *reinterpret_cast<const v8bf*>(&Ah[(wm + a * 16 + rr) * P + kk]);
+      al[a] = *reinterpret_cast<const v8bf*>(&Al[(wm + a * 16 + rr) * P + kk]);
+      bh[a] = *reinterpret_cast<const v8bf*>(&Bh[(wn + a * 16 + rr) * P + kk]);
+      bl[a] = *reinterpret_cast<const v8bf*>(&Bl[(wn + a * 16 + rr) * P + kk]);
+    }
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wm + a * 16 + 4 * (lane >> 4) + r;
+        const int col = n0 + wn + b * 16 + (lane & 15);
+        double* cp = C + (size_t)row * N + col;
+        const double v = (double)acc[a][b][r];
+        *cp = accumulate ? *cp + v : v;
+      }
+}
+
+void launch_gemm_bf16x3(hipStream_t st, int M, int N, int K, const double* Bm, const uint16_t* Shi,
+                        const uint16_t* Slo, double* C, int accumulate) {
+  dim3 grid(N / 64, M / 64), block(256);
+  hipLaunchKernelGGL(k_gemm_bf16x3, grid, block, 0, st, M, N, K, Bm, Shi, Slo, C, accumulate);
+}
+
+}  // namespace cpm

@@ -1,0 +1,297 @@
+"""Parity of the HIP charge-solve path (through the C-ABI) with the FP64 oracle.
+
+Tolerances (FP64 path): 1e-10 relative (max-norm) on q, b, S; 1e-11 on A;
+|sum q| <= 1e-12 e on every path.  FP32 / split-BF16 paths: 1e-5 relative
+on q.  Small capacitors are compared in full against a live oracle run; the
+2880-atom capacitor against stored oracle results (tests/golden).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpm_oracle as O
+from paper_2203_15461_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "graphite_capacitor_2880.npz")
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def cpm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_15461_amd import cpm as C
+    C.lib()
+    return C
+
+
+def run(C, w, store=1, b_f32=False, mode=0, snaps=(0,), params=None, xyz_list=None):
+    ctx = C.setup(w, store=store, params=params)
+    n = w.n
+    A = ctx.copy_matrix(0, torch.empty((n, n), dtype=torch.float64, device="cuda"))
+    S = ctx.copy_matrix(2, torch.empty((n, n), dtype=torch.float64, device="cuda"))
+    u = ctx.copy_vector(0, torch.empty(n, dtype=torch.float64, device="cuda"))
+    if xyz_list is None:
+        xyz_list = [I.snapshot(w, s) for s in snaps]
+    xyz = torch.as_tensor(np.stack(xyz_list), dtype=torch.float64, device="cuda").contiguous()
+    bt = torch.empty((len(xyz_list), n), dtype=torch.float32 if b_f32 else torch.float64,
+                     device="cuda")
+    ctx.potential_vector(xyz, bt)
+    q = torch.empty((len(xyz_list), n), dtype=torch.float64, device="cuda")
+    Qe = torch.empty((len(xyz_list), int(w.electrode_id.max()) + 1), dtype=torch.float64,
+                     device="cuda")
+    ctx.solve_charges(bt, mode, q, Qe)
+    ctx.synchronize()
+    out = dict(A=A.cpu().numpy(), S=S.cpu().numpy(), u=u.cpu().numpy(),
+               b=bt.double().cpu().numpy(), q=q.cpu().numpy(), Qe=Qe.cpu().numpy(),
+               s=ctx.info("s_sum"), nk=ctx.info("nk"), xyz=xyz_list)
+    ctx.close()
+    return out
+
+
+def oracle_of(w, xyz_list, n_e=2, v_e=None):
+    p = O.params_for(w)
+    A = O.elastance(w.electrode_xyz, p)
+    cap = O.capacitance(A)
+    v = O.applied_potential(w.electrode_id, w.v_electrode if v_e is None else v_e)
+    bs = [O.potential_vector(w.electrode_xyz, r, w.electrolyte_q, p) for r in xyz_list]
+    qs = [O.charges(cap.S, b, v) for b in bs]
+    Qs = [O.electrode_totals(q, w.electrode_id, n_e) for q in qs]
+    return dict(A=A, S=cap.S, u=cap.u, s=cap.s, b=np.array(bs), q=np.array(qs), Q=np.array(Qs),
+                nk=len(O.kvectors(p)[2]))
+
+
+@pytest.mark.parametrize("variant", ["a", "b"])
+def test_small_capacitor_fp64(cpm, variant):
+    w = I.small_capacitor(variant)
+    say(f"small_capacitor_{variant} fp64 n={w.n} m={w.m}")
+    g = run(cpm, w, snaps=(0, 1))
+    o = oracle_of(w, g["xyz"])
+    assert g["nk"] == o["nk"]
+    assert rel(g["A"], o["A"]) < 1e-11
+    assert np.array_equal(g["A"], g["A"].T)
+    assert rel(g["S"], o["S"]) < 1e-10
+    assert rel(g["u"], o["u"]) < 1e-10
+    assert abs(g["s"] / o["s"] - 1) < 1e-10
+    assert rel(g["b"], o["b"]) < 1e-10
+    assert rel(g["q"], o["q"]) < 1e-10
+    assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
+    assert rel(g["Qe"], o["Q"]) < 1e-10
+
+
+def test_small_capacitor_fp32_paths(cpm):
+    w = I.small_capacitor("a")
+    say("small_capacitor_a fp32 / fp32+refine")
+    xyz = [I.snapshot(w, s) for s in (0, 1, 2)]
+    o = oracle_of(w, xyz)
+    for mode, tol in ((cpm.SOLVE_F32, 1e-5), (cpm.SOLVE_F32 | cpm.SOLVE_REFINE, 1e-5)):
+        g = run(cpm, w, store=cpm.STORE_F32, b_f32=True, mode=mode, xyz_list=xyz)
+        err = rel(g["q"], o["q"])
+        say(f"  mode {mode:#x}: q err {err:.3e} b err {rel(g['b'], o['b']):.3e}")
+        assert err < tol
+        assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
+
+
+def test_three_electrodes_and_no_electrolyte(cpm):
+    """n_e = 3 (the top layer split in two) and an empty electrolyte (b = 0)."""
+    w = I.small_capacitor("a")
+    eid = w.electrode_id.copy()
+    eid[(eid == 1) & (w.electrode_xyz[:, 0] > w.Lx / 2)] = 2
+    w3 = w.with_(electrode_id=eid.astype(np.int32))
+    v_e = np.array([-0.5, 0.5, 0.2])
+    say("three electrodes")
+    ctx = cpm.setup(w3, v_electrode=v_e)
+    xyz = torch.as_tensor(I.snapshot(w3, 0)[None], device="cuda").contiguous()
+    b = torch.empty((1, w.n), dtype=torch.float64, device="cuda")
+    ctx.potential_vector(xyz, b)
+    q = torch.empty((1, w.n), dtype=torch.float64, device="cuda")
+    Qe = torch.empty((1, 3), dtype=torch.float64, device="cuda")
+    ctx.solve_charges(b, 0, q, Qe)
+    ctx.synchronize()
+    o = oracle_of(w3, [I.snapshot(w3, 0)], n_e=3, v_e=v_e)
+    assert rel(q.cpu().numpy(), o["q"]) < 1e-10
+    assert rel(Qe.cpu().numpy(), o["Q"]) < 1e-10
+    ctx.close()
+
+    say("empty electrolyte")
+    w0 = w.with_(electrolyte_xyz=np.zeros((0, 3)), electrolyte_q=np.zeros(0))
+    ctx = cpm.setup(w0)
+    xyz = torch.zeros((1, 0, 3), dtype=torch.float64, device="cuda")
+    b = torch.full((1, w.n), 7.0, dtype=torch.float64, device="cuda")
+    ctx.potential_vector(xyz, b)
+    q = torch.empty((1, w.n), dtype=torch.float64, device="cuda")
+    ctx.solve_charges(b, 0, q)
+    ctx.synchronize()
+    assert torch.count_nonzero(b).item() == 0
+    p = O.params_for(w)
+    S = O.capacitance(O.elastance(w.electrode_xyz, p)).S
+    qo = S @ O.applied_potential(w.electrode_id, w.v_electrode)
+    assert rel(q.cpu().numpy()[0], qo) < 1e-10
+    ctx.close()
+
+
+def test_not_positive_definite(cpm):
+    """A large negative diagonal term makes A indefinite: CPM_ENOTPD at that pivot."""
+    w = I.small_capacitor("a")
+    say("not positive definite")
+    ctx = cpm.Context(cpm.Params.of(w))
+    ctx.set_electrolyte(w.electrolyte_q)
+    xyz = torch.as_tensor(w.electrode_xyz, device="cuda").contiguous()
+    eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device="cuda").contiguous()
+    extra = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    extra[5] = -1000.0
+    ctx.build_elastance(xyz, eid, 2, extra)
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.invert()
+    assert ei.value.status == cpm.ENOTPD
+    assert ctx.info("pivot") == 5
+    ctx.close()
+
+
+def test_call_order_and_mode_errors(cpm):
+    w = I.small_capacitor("b")
+    say("call order")
+    ctx = cpm.Context(cpm.Params.of(w))
+    b = torch.zeros((1, w.n), dtype=torch.float64, device="cuda")
+    q = torch.zeros((1, w.n), dtype=torch.float64, device="cuda")
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.solve_charges(b, 0, q)
+    assert ei.value.status == cpm.ESTATE
+    ctx.close()
+    ctx = cpm.setup(w, store=cpm.STORE_F64)
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.solve_charges(b, cpm.SOLVE_F32, q)
+    assert ei.value.status == cpm.EINVAL
+    ctx.close()
+    with pytest.raises(cpm.CpmError) as ei:
+        cpm.Context(cpm.Params.of(w)).set_electrolyte([1.0, 1.0])
+    assert ei.value.status == cpm.EINVAL
+
+
+def test_bitwise_reproducible(cpm):
+    w = I.small_capacitor("a")
+    say("reproducibility")
+    g1 = run(cpm, w, snaps=(3,))
+    g2 = run(cpm, w, snaps=(3,))
+    assert np.array_equal(g1["q"], g2["q"]) and np.array_equal(g1["b"], g2["b"])
+    assert np.array_equal(g1["S"], g2["S"])
+
+
+@pytest.fixture(scope="module")
+def golden():
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py")
+    return dict(np.load(GOLDEN))
+
+
+def test_graphite_capacitor_2880_fp64(cpm, golden):
+    """Full-size 2880-atom capacitor, 3 snapshots, against stored oracle results."""
+    sys.path.insert(0, os.path.dirname(GOLDEN))
+    import make_golden
+    w = I.graphite_capacitor()
+    snaps = [I.snapshot(w, int(s)) for s in golden["snapshots"]]
+    assert make_golden.input_hash(w, snaps) == str(golden["input_sha256"])
+    say(f"graphite_capacitor_2880 fp64 n={w.n} m={w.m}")
+    g = run(cpm, w, xyz_list=snaps)
+    rows = golden["rows"]
+    assert g["nk"] == golden["nk"]
+    assert rel(g["A"][rows], golden["A_rows"]) < 1e-11
+    assert rel(np.diag(g["A"]), golden["A_diag"]) < 1e-11
+    assert rel(g["S"][rows], golden["S_rows"]) < 1e-10
+    assert rel(g["u"], golden["u"]) < 1e-10
+    assert rel(g["b"], golden["b"]) < 1e-10
+    assert rel(g["q"], golden["q"]) < 1e-10
+    assert rel(g["Qe"], golden["Q"]) < 1e-10
+    assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
+
+
+def test_graphite_capacitor_2880_fp32(cpm, golden):
+    w = I.graphite_capacitor()
+    snaps = [I.snapshot(w, int(s)) for s in golden["snapshots"]]
+    say("graphite_capacitor_2880 fp32 + refine")
+    g = run(cpm, w, store=cpm.STORE_F32, b_f32=True, mode=cpm.SOLVE_F32 | cpm.SOLVE_REFINE,
+            xyz_list=snaps)
+    err = rel(g["q"], golden["q"])
+    say(f"  q err {err:.3e}  b err {rel(g['b'], golden['b']):.3e}")
+    assert err < 1e-5
+    assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
+
+
+@pytest.mark.parametrize("store,mode,b_f32,tol", [
+    (1, 0x000, False, 1e-10),          # FP64 MFMA GEMM
+    (1, 0x100, False, 1e-10),          # FP64 GEMM + refinement
+    (4, 0x002, False, 5e-4),           # split-BF16 GEMM, unrefined: ~16-bit S, not a product mode
+    (4, 0x102, False, 1e-5),           # split-BF16 + FP64 refinement
+    (4, 0x102, True, 1e-5),            # split-BF16 + refinement, FP32-accumulated b
+])
+def test_batched_gemm_paths(cpm, store, mode, b_f32, tol):
+    """Batches of >= 4 vectors solve as one MFMA GEMM (rows padded to 64):
+    70 snapshots span two row tiles and a ragged tail."""
+    w = I.small_capacitor("a")
+    say(f"batched gemm store={store} mode={mode:#x} b_f32={b_f32}")
+    xyz = [I.snapshot(w, s) for s in range(70)]
+    g = run(cpm, w, store=store | 1, b_f32=b_f32, mode=mode, xyz_list=xyz)
+    o = oracle_of(w, xyz)
+    err = rel(g["q"], o["q"])
+    say(f"  q err {err:.3e}  Q err {rel(g['Qe'], o['Q']):.3e}")
+    assert err < tol
+    assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
+
+
+def test_fp32_refined_fp64_b_is_tight(cpm):
+    """FP32 S with one FP64 refinement step on an FP64 b reaches ~FP64 accuracy."""
+    w = I.small_capacitor("a")
+    xyz = [I.snapshot(w, s) for s in (0, 1, 2)]
+    o = oracle_of(w, xyz)
+    g = run(cpm, w, store=cpm.STORE_F32, b_f32=False, mode=cpm.SOLVE_F32 | cpm.SOLVE_REFINE,
+            xyz_list=xyz)
+    say(f"fp32 S + refine, fp64 b: q err {rel(g['q'], o['q']):.3e}")
+    assert rel(g["q"], o["q"]) < 1e-9
+
+
+def test_batched_2880_gemm(cpm, golden):
+    """Full-size batched solves (FP64 GEMM and split-BF16 + refinement) against
+    the stored oracle charges, 8 vectors (three snapshots repeated)."""
+    w = I.graphite_capacitor()
+    idx = [0, 1, 2, 0, 1, 2, 0, 1]
+    snaps = [I.snapshot(w, int(golden["snapshots"][i])) for i in idx]
+    ref = golden["q"][idx]
+    for store, mode, tol in ((1, 0x000, 1e-10), (5, 0x102, 1e-5)):
+        say(f"graphite_capacitor_2880 batched store={store} mode={mode:#x}")
+        g = run(cpm, w, store=store, mode=mode, xyz_list=snaps)
+        err = rel(g["q"], ref)
+        say(f"  q err {err:.3e}")
+        assert err < tol
+        assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
+
+
+def test_kernel_timing(cpm):
+    w = I.small_capacitor("b")
+    say("timing")
+    ctx = cpm.setup(w)
+    ctx.enable_timing(True)
+    xyz = torch.as_tensor(np.stack([I.snapshot(w, s) for s in range(2)]), device="cuda").contiguous()
+    b = torch.empty((2, w.n), dtype=torch.float64, device="cuda")
+    ctx.potential_vector(xyz, b)
+    q = torch.empty((2, w.n), dtype=torch.float64, device="cuda")
+    ctx.solve_charges(b, 0, q)
+    for fam in ("structure_factor", "kspace_project", "real_space_b", "matvec_f64", "finalize"):
+        ms, cnt = ctx.timing(fam)
+        assert cnt >= 1 and ms > 0, fam
+    assert ctx.timing("no_such_kernel") == (0.0, 0)
+    ctx.close()
