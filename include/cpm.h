@@ -77,7 +77,8 @@ enum {
   CPM_INFO_KCUT = 6,          /* k-space cutoff used (1/A)                        */
   CPM_INFO_M = 7,             /* electrolyte charges                              */
   CPM_INFO_WORKSPACE = 8,     /* device bytes held by the context                 */
-  CPM_INFO_NPAD = 9           /* padded matrix order (multiple of 64)             */
+  CPM_INFO_NPAD = 9,          /* padded matrix order (multiple of 64)             */
+  CPM_INFO_NRUNS = 10         /* k-space runs (<= 16 consecutive k_z each)        */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -97,12 +98,15 @@ typedef struct {
 } cpm_params;
 
 /* Create a context bound to `hip_stream` (a hipStream_t, or NULL).
- * Validates params (finite, positive, slab clearance).  *out is NULL on error. */
+ * Validates params (finite, positive, slab clearance) and builds the k set on
+ * the host; no device work happens before cpm_build_elastance.  *out is NULL
+ * on error. */
 cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out);
 
 /* Electrolyte point charges h_q[m] (e), fixed for the run.  Host pointer,
- * copied; the charges must sum to zero within 1e-10 sum|q| (the slab term of
- * Eq. 12 assumes a neutral electrolyte), else CPM_EINVAL.  m >= 0. */
+ * copied (uploaded on first device use); the charges must sum to zero within
+ * 1e-10 sum|q| (the slab term of Eq. 12 assumes a neutral electrolyte), else
+ * CPM_EINVAL.  m >= 0.  Call once per context (CPM_ESTATE otherwise). */
 cpm_status cpm_set_electrolyte(cpm_ctx* ctx, int m, const double* h_q);
 
 /* Assemble the n x n elastance matrix A in FP64 on the device (Eq. 2, A

@@ -23,61 +23,80 @@
 namespace cpm {
 
 // ---------------------------------------------------------------------------
-// Structure factors: one thread per k run, electrolyte staged in LDS tiles.
+// Structure factors: one thread per k run; the electrolyte is staged in LDS in
+// tiles of up to SF_TJ charges together with per-charge phase tables
+//   tx[n] = q_j e^{2 pi i n fx_j} (n = 0..nxm), ty[n] = e^{2 pi i n fy_j}
+//   (n = 0..nym), tz[n] = e^{2 pi i n fz_j} (n = 0..nzm),
+// each entry computed directly in FP64 (negative indices use the conjugate).
+// The start of a run is tx[nx] ty[ny] tz[nz0] (two complex products), the
+// rest of the run a rotation by tz[1] in FP64.  T is the accumulation type.
 // part[(chunk * nk + k) * 2 + {0,1}] = partial S(k) over the chunk's charges.
 // ---------------------------------------------------------------------------
-constexpr int SF_TILE = 256;
+constexpr int SF_TJ = 32;
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
 
 template <typename T>
 __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun* __restrict__ runs,
-                                                          int nk, int m, int chunk_size,
+                                                          int nk, int m, int chunk_size, int tj,
                                                           const double* __restrict__ xyz,
                                                           const double* __restrict__ q, double Lx,
-                                                          double Ly, double Lz,
-                                                          double* __restrict__ part) {
-  __shared__ double s_fx[SF_TILE], s_fy[SF_TILE], s_fz[SF_TILE], s_q[SF_TILE];
-  __shared__ T s_cz[SF_TILE], s_sz[SF_TILE];
+                                                          double Ly, double Lz, int nxm, int nym,
+                                                          int nzm, double* __restrict__ part) {
+  extern __shared__ double2 tab[];                  // [tj][W]
+  __shared__ double s_f[3][SF_TJ], s_q[SF_TJ];
+  const int W = nxm + nym + nzm + 3, oy = nxm + 1, oz = nxm + nym + 2;
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const int chunk = blockIdx.y;
   const int j0 = chunk * chunk_size;
   const int j1 = min(m, j0 + chunk_size);
   KRun run = {0, 0, 0, 0, 0, 0};
   if (rid < nruns) run = runs[rid];
+  const int iy = oy + abs(run.ny), iz = oz + abs(run.nz0);
+  const double sy = run.ny < 0 ? -1.0 : 1.0, sz0 = run.nz0 < 0 ? -1.0 : 1.0;
   T are[RUN], aim[RUN];
 #pragma unroll
   for (int r = 0; r < RUN; ++r) { are[r] = 0; aim[r] = 0; }
 
-  for (int jt = j0; jt < j1; jt += SF_TILE) {
-    const int nt = min(SF_TILE, j1 - jt);
+  for (int jt = j0; jt < j1; jt += tj) {
+    const int nt = min(tj, j1 - jt);
     __syncthreads();
     if ((int)threadIdx.x < nt) {
       const int j = jt + threadIdx.x;
-      double fx = xyz[3 * j] / Lx, fy = xyz[3 * j + 1] / Ly, fz = xyz[3 * j + 2] / Lz;
-      fx -= floor(fx);
-      fy -= floor(fy);
-      s_fx[threadIdx.x] = fx; s_fy[threadIdx.x] = fy; s_fz[threadIdx.x] = fz;
+      double fx = xyz[3 * j] / Lx, fy = xyz[3 * j + 1] / Ly;
+      s_f[0][threadIdx.x] = fx - floor(fx);
+      s_f[1][threadIdx.x] = fy - floor(fy);
+      s_f[2][threadIdx.x] = xyz[3 * j + 2] / Lz;
       s_q[threadIdx.x] = q[j];
-      double sz, cz;
-      sincospi(2.0 * (fz - rint(fz)), &sz, &cz);
-      s_cz[threadIdx.x] = (T)cz; s_sz[threadIdx.x] = (T)sz;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nt * W; e += blockDim.x) {
+      const int t = e / W, idx = e - t * W;
+      const int ax = idx < oy ? 0 : (idx < oz ? 1 : 2);
+      const int nn = idx - (ax == 0 ? 0 : (ax == 1 ? oy : oz));
+      double th = nn * s_f[ax][t];
+      th -= rint(th);
+      double sn, cs;
+      sincospi(2.0 * th, &sn, &cs);
+      const double sc = ax == 0 ? s_q[t] : 1.0;
+      tab[e] = make_double2(sc * cs, sc * sn);
     }
     __syncthreads();
     if (rid < nruns) {
       for (int t = 0; t < nt; ++t) {
-        double th = run.nx * s_fx[t] + run.ny * s_fy[t] + run.nz0 * s_fz[t];
-        th -= rint(th);
-        double sn, cs;
-        sincospi(2.0 * th, &sn, &cs);
-        const double qq = s_q[t];
-        T wr = (T)(qq * cs), wi = (T)(qq * sn);
-        const T cz = s_cz[t], sz = s_sz[t];
+        const double2* tt = tab + t * W;
+        double2 ey = tt[iy], ez = tt[iz];
+        ey.y *= sy;
+        ez.y *= sz0;
+        double2 w = cmul(cmul(tt[run.nx], ey), ez);
+        const double2 st = tt[oz + 1];
 #pragma unroll
         for (int r = 0; r < RUN; ++r) {
-          are[r] += wr;
-          aim[r] += wi;
-          const T nr = wr * cz - wi * sz;
-          wi = wr * sz + wi * cz;
-          wr = nr;
+          are[r] += (T)w.x;
+          aim[r] += (T)w.y;
+          w = cmul(w, st);
         }
       }
     }
@@ -91,17 +110,25 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
   }
 }
 
+int sf_tile(int nxm, int nym, int nzm) {
+  const int W = nxm + nym + nzm + 3;
+  int tj = (int)(61440 / (W * sizeof(double2)));   // <= 60 KB of dynamic LDS
+  return tj < 1 ? 1 : (tj > SF_TJ ? SF_TJ : tj);
+}
+
 void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk, int m,
                                int mchunks, const double* xyz, const double* q, double Lx,
-                               double Ly, double Lz, double* part) {
+                               double Ly, double Lz, int nxm, int nym, int nzm, double* part) {
   const int chunk_size = (m + mchunks - 1) / mchunks;
+  const int tj = sf_tile(nxm, nym, nzm);
+  const size_t shm = (size_t)tj * (nxm + nym + nzm + 3) * sizeof(double2);
   dim3 grid((nruns + 255) / 256, mchunks), block(256);
   if (fp32)
-    hipLaunchKernelGGL(k_structure_factor<float>, grid, block, 0, st, nruns, runs, nk, m,
-                       chunk_size, xyz, q, Lx, Ly, Lz, part);
+    hipLaunchKernelGGL(k_structure_factor<float>, grid, block, shm, st, nruns, runs, nk, m,
+                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part);
   else
-    hipLaunchKernelGGL(k_structure_factor<double>, grid, block, 0, st, nruns, runs, nk, m,
-                       chunk_size, xyz, q, Lx, Ly, Lz, part);
+    hipLaunchKernelGGL(k_structure_factor<double>, grid, block, shm, st, nruns, runs, nk, m,
+                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part);
 }
 
 // sfw[k] = 2 W(k) * sum_chunks part[chunk][k]   (fixed chunk order)
@@ -110,6 +137,7 @@ __global__ void k_sf_reduce(int nk, int mchunks, const double* __restrict__ part
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= nk) return;
   double re = 0.0, im = 0.0;
+#pragma unroll 4
   for (int c = 0; c < mchunks; ++c) {
     re += part[((size_t)c * nk + k) * 2];
     im += part[((size_t)c * nk + k) * 2 + 1];
@@ -125,69 +153,71 @@ void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
 }
 
 // ---------------------------------------------------------------------------
-// k-space potential at the electrode atoms: one thread per atom, the chunk's
-// weighted structure factors staged in LDS (every lane reads the same k).
+// k-space potential at the electrode atoms: one thread per atom, a chunk of
+// whole (k_x, k_y) columns per workgroup with the columns' weighted structure
+// factors staged in LDS (every lane reads the same k).  Per column the phase
+// e^{i k.R_i} is computed once in FP64 (sincospi) and then rotated along k_z
+// in FP64; two interleaved sub-sequences (even and odd k_z, rotated by
+// e^{2i k_z1 z_i}) keep two independent dependency chains in flight.
 // part[chunk * n + i] = sum over the chunk's k of Re[e^{-i k.R_i} 2W S(k)].
 // ---------------------------------------------------------------------------
-constexpr int PJ_MAXK = 64 * RUN;      // k values staged per chunk (runs_per_chunk <= 64)
-
 template <typename T>
-__global__ void __launch_bounds__(256) k_kspace_project(int n, int nruns, int runs_per_chunk,
-                                                        const KRun* __restrict__ runs,
+__global__ void __launch_bounds__(128) k_kspace_project(int n, const KCol* __restrict__ cols,
+                                                        const int* __restrict__ chunk_col,
                                                         const double* __restrict__ fx,
                                                         const double* __restrict__ fy,
                                                         const double* __restrict__ fz,
                                                         const double* __restrict__ sfw,
                                                         double* __restrict__ part) {
-  __shared__ KRun s_runs[64];
-  __shared__ T s_re[PJ_MAXK], s_im[PJ_MAXK];
+  __shared__ double2 s_w[PJ_MAXK];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int chunk = blockIdx.y;
-  const int r0 = chunk * runs_per_chunk;
-  const int r1 = min(nruns, r0 + runs_per_chunk);
-  if (r0 >= r1) return;
-  const int kbase = runs[r0].koff;
-  const int kend = runs[r1 - 1].koff + runs[r1 - 1].len;
-  for (int t = threadIdx.x; t < r1 - r0; t += blockDim.x) s_runs[t] = runs[r0 + t];
-  for (int t = threadIdx.x; t < kend - kbase; t += blockDim.x) {
-    s_re[t] = (T)sfw[2 * (kbase + t)];
-    s_im[t] = (T)sfw[2 * (kbase + t) + 1];
-  }
+  const int c0 = chunk_col[chunk], c1 = chunk_col[chunk + 1];
+  const int kbase = cols[c0].koff;
+  const int kend = cols[c1 - 1].koff + cols[c1 - 1].len;
+  for (int t = threadIdx.x; t < kend - kbase; t += blockDim.x)
+    s_w[t] = make_double2(sfw[2 * (kbase + t)], sfw[2 * (kbase + t) + 1]);
   __syncthreads();
   if (i >= n) return;
   const double ax = fx[i], ay = fy[i], az = fz[i];
-  double szd, czd;
-  sincospi(2.0 * (az - rint(az)), &szd, &czd);
-  const T cz = (T)czd, sz = (T)szd;
-  T acc = 0;
-  for (int rr = 0; rr < r1 - r0; ++rr) {
-    const KRun run = s_runs[rr];
-    double th = run.nx * ax + run.ny * ay + run.nz0 * az;
+  double s1, c1d, s2, c2d;
+  sincospi(2.0 * (az - rint(az)), &s1, &c1d);
+  const double a2 = 2.0 * az;
+  sincospi(2.0 * (a2 - rint(a2)), &s2, &c2d);
+  const double2 z2 = make_double2(c2d, s2);
+  const double2 z1 = make_double2(c1d, s1);
+  T acc0 = 0, acc1 = 0;
+  for (int c = c0; c < c1; ++c) {
+    const KCol col = cols[c];
+    double th = col.nx * ax + col.ny * ay + col.lo * az;
     th -= rint(th);
     double sn, cs;
     sincospi(2.0 * th, &sn, &cs);
-    T er = (T)cs, ei = (T)sn;
-    const int kb = run.koff - kbase;
-    for (int r = 0; r < run.len; ++r) {
-      acc += er * s_re[kb + r] + ei * s_im[kb + r];
-      const T nr = er * cz - ei * sz;
-      ei = er * sz + ei * cz;
-      er = nr;
+    double2 e0 = make_double2(cs, sn);           // k_z = lo, lo + 2, ...
+    double2 e1 = cmul(e0, z1);                   // k_z = lo + 1, lo + 3, ...
+    const double2* w = s_w + (col.koff - kbase);
+    int r = 0;
+    for (; r + 1 < col.len; r += 2) {
+      acc0 += (T)(e0.x * w[r].x + e0.y * w[r].y);
+      acc1 += (T)(e1.x * w[r + 1].x + e1.y * w[r + 1].y);
+      e0 = cmul(e0, z2);
+      e1 = cmul(e1, z2);
     }
+    if (r < col.len) acc0 += (T)(e0.x * w[r].x + e0.y * w[r].y);
   }
-  part[(size_t)chunk * n + i] = (double)acc;
+  part[(size_t)chunk * n + i] = (double)acc0 + (double)acc1;
 }
 
-void launch_b_kspace_project(hipStream_t st, int fp32, int n, int nruns, int kchunks,
-                             int runs_per_chunk, const KRun* runs, const Buffers& b,
-                             const double* sfw, double* part) {
-  dim3 grid((n + 255) / 256, kchunks), block(256);
+void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const KCol* cols,
+                             const int* chunk_col, const Buffers& b, const double* sfw,
+                             double* part) {
+  dim3 grid((n + 127) / 128, kchunks), block(128);
   if (fp32)
-    hipLaunchKernelGGL(k_kspace_project<float>, grid, block, 0, st, n, nruns, runs_per_chunk, runs,
-                       b.efx, b.efy, b.efz, sfw, part);
+    hipLaunchKernelGGL(k_kspace_project<float>, grid, block, 0, st, n, cols, chunk_col, b.efx,
+                       b.efy, b.efz, sfw, part);
   else
-    hipLaunchKernelGGL(k_kspace_project<double>, grid, block, 0, st, n, nruns, runs_per_chunk,
-                       runs, b.efx, b.efy, b.efz, sfw, part);
+    hipLaunchKernelGGL(k_kspace_project<double>, grid, block, 0, st, n, cols, chunk_col, b.efx,
+                       b.efy, b.efz, sfw, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -290,8 +320,11 @@ __global__ void k_combine(int n, int kchunks, int rchunks, const double* __restr
                           int out_is_f32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  // fixed-order sums; the loads are independent, so unrolling keeps many in flight
   double pk = 0.0, pr = 0.0;
+#pragma unroll 8
   for (int c = 0; c < kchunks; ++c) pk += phik[(size_t)c * n + i];
+#pragma unroll 8
   for (int c = 0; c < rchunks; ++c) pr += phir[(size_t)c * n + i];
   const double b = -ke * (pk + pr + slab_coef * ez[i] * (*mz));
   if (out_is_f32)
@@ -303,7 +336,7 @@ __global__ void k_combine(int n, int kchunks, int rchunks, const double* __restr
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
                       const double* phir, const Buffers& b, const double* mz, double slab_coef,
                       double ke, void* out, int out_is_f32) {
-  hipLaunchKernelGGL(k_combine, dim3((n + 255) / 256), dim3(256), 0, st, n, kchunks, rchunks, phik,
+  hipLaunchKernelGGL(k_combine, dim3((n + 63) / 64), dim3(64), 0, st, n, kchunks, rchunks, phik,
                      phir, b.ez, mz, slab_coef, ke, out, out_is_f32);
 }
 

@@ -127,18 +127,23 @@ void build_kset(cpm_ctx* c, std::vector<KRun>& runs, std::vector<double>& w2,
   const int nxm = (int)std::floor(kc * Lx / twopi);
   const int nym = (int)std::floor(kc * Ly / twopi);
   const int nzm = (int)std::floor(kc * Lz / twopi);
+  c->nxm = nxm;
+  c->nym = nym;
+  c->nzm = nzm;
   const double a2 = 4.0 * c->p.alpha * c->p.alpha;
   for (int nx = 0; nx <= nxm; ++nx)
     for (int ny = -nym; ny <= nym; ++ny) {
       if (nx == 0 && ny < 0) continue;
       const int zlo = (nx == 0 && ny == 0) ? 1 : -nzm;
-      int run_start = -1, cnt = 0;
+      bool open = false;
+      int run_start = 0, cnt = 0;
       for (int nz = zlo; nz <= nzm; ++nz) {
         const double gx = twopi * nx / Lx, gy = twopi * ny / Ly, gz = twopi * nz / Lz;
         const double k2 = gx * gx + gy * gy + gz * gz;
         const bool keep = k2 <= kc * kc;
         if (keep) {
-          if (run_start < 0 || cnt == RUN || nz != run_start + cnt) {
+          if (!open || cnt == RUN || nz != run_start + cnt) {
+            open = true;
             runs.push_back(KRun{nx, ny, nz, 0, (int)w2.size(), 0});
             run_start = nz;
             cnt = 0;
@@ -193,6 +198,36 @@ cpm_status ensure_solve_buffers(cpm_ctx* c, int batch) {
   return CPM_OK;
 }
 
+// upload the k set and electrolyte charges on first device use
+cpm_status ensure_uploaded(cpm_ctx* c) {
+  Buffers& b = c->b;
+  if (!b.runs) {
+    TRY(dalloc(c, &b.runs, c->h_runs.size()));
+    TRY(dalloc(c, &b.w2, c->h_w2.size()));
+    TRY(dalloc(c, &b.knx, c->h_kx.size()));
+    TRY(dalloc(c, &b.kny, c->h_ky.size()));
+    TRY(dalloc(c, &b.knz, c->h_kz.size()));
+    TRY(dalloc(c, &b.cols, c->h_cols.size()));
+    TRY(dalloc(c, &b.chunk_col, c->h_chunk_col.size()));
+    TRY(dalloc(c, &b.flag, 4));
+    TRY(dalloc(c, &b.scal, 8));
+    HIP_TRY(c, hipMemcpy(b.runs, c->h_runs.data(), c->h_runs.size() * sizeof(KRun), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.w2, c->h_w2.data(), c->h_w2.size() * sizeof(double), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.knx, c->h_kx.data(), c->h_kx.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.kny, c->h_ky.data(), c->h_ky.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.knz, c->h_kz.data(), c->h_kz.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.cols, c->h_cols.data(), c->h_cols.size() * sizeof(KCol), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.chunk_col, c->h_chunk_col.data(), c->h_chunk_col.size() * sizeof(int),
+                         hipMemcpyHostToDevice));
+  }
+  if (c->have_elyt && !b.elq) {
+    TRY(dalloc(c, &b.elq, (size_t)std::max(c->m, 1)));
+    if (c->m > 0)
+      HIP_TRY(c, hipMemcpy(b.elq, c->h_q.data(), (size_t)c->m * sizeof(double), hipMemcpyHostToDevice));
+  }
+  return CPM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -223,9 +258,6 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
     st = fail(c, CPM_EINVAL, "slab clearance (slab_factor - 1) * h = %g must exceed rcut = %g",
               (p.slab_factor - 1.0) * p.h, p.rcut);
   if (st != CPM_OK) {
-    // keep the message reachable through a static buffer for a NULL context
-    static thread_local std::string last;
-    last = c->err;
     delete c;
     return st;
   }
@@ -234,37 +266,37 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
 
-  std::vector<KRun> runs;
-  std::vector<double> w2;
-  std::vector<int> kx, ky, kz;
-  build_kset(c, runs, w2, kx, ky, kz);
-  c->nk = (int)w2.size();
-  c->nruns = (int)runs.size();
+  build_kset(c, c->h_runs, c->h_w2, c->h_kx, c->h_ky, c->h_kz);
+  c->nk = (int)c->h_w2.size();
+  c->nruns = (int)c->h_runs.size();
   if (c->nk == 0) {
     delete c;
     return CPM_EINVAL;
   }
-  Buffers& b = c->b;
-  if ((st = dalloc(c, &b.runs, runs.size())) != CPM_OK ||
-      (st = dalloc(c, &b.w2, w2.size())) != CPM_OK ||
-      (st = dalloc(c, &b.knx, kx.size())) != CPM_OK ||
-      (st = dalloc(c, &b.kny, ky.size())) != CPM_OK ||
-      (st = dalloc(c, &b.knz, kz.size())) != CPM_OK ||
-      (st = dalloc(c, &b.flag, 4)) != CPM_OK || (st = dalloc(c, &b.scal, 8)) != CPM_OK) {
-    cpm_destroy(c);
-    return st;
+  // projection: column segments (consecutive runs of one (nx, ny), at most
+  // PJ_MAXK k values) grouped greedily into chunks of at most PJ_MAXK k values
+  for (const KRun& r : c->h_runs) {
+    if (!c->h_cols.empty()) {
+      KCol& last = c->h_cols.back();
+      if (last.nx == r.nx && last.ny == r.ny && last.lo + last.len == r.nz0 &&
+          last.len + r.len <= PJ_MAXK) {
+        last.len += r.len;
+        continue;
+      }
+    }
+    c->h_cols.push_back(KCol{r.nx, r.ny, r.nz0, r.len, r.koff, 0});
   }
-  if (hipMemcpy(b.runs, runs.data(), runs.size() * sizeof(KRun), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b.w2, w2.data(), w2.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b.knx, kx.data(), kx.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b.kny, ky.data(), ky.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(b.knz, kz.data(), kz.size() * sizeof(int), hipMemcpyHostToDevice) != hipSuccess) {
-    cpm_destroy(c);
-    return CPM_EHIP;
+  c->h_chunk_col.push_back(0);
+  int acc = 0;
+  for (int k = 0; k < (int)c->h_cols.size(); ++k) {
+    if (acc + c->h_cols[k].len > PJ_MAXK) {
+      c->h_chunk_col.push_back(k);
+      acc = 0;
+    }
+    acc += c->h_cols[k].len;
   }
-  // projection: 64 runs per chunk (LDS holds 64 * RUN weighted k values)
-  c->runs_per_kchunk = 64;
-  c->kchunks = (c->nruns + 63) / 64;
+  c->h_chunk_col.push_back((int)c->h_cols.size());
+  c->kchunks = (int)c->h_chunk_col.size() - 1;
   *out = c;
   return CPM_OK;
 }
@@ -282,9 +314,7 @@ cpm_status cpm_set_electrolyte(cpm_ctx* c, int m, const double* h_q) {
     return fail(c, CPM_EINVAL, "electrolyte not neutral: sum q = %g", sum);
   if (c->have_elyt) return fail(c, CPM_ESTATE, "electrolyte already set for this context");
   c->m = m;
-  TRY(dalloc(c, &c->b.elq, (size_t)std::max(m, 1)));
-  if (m > 0)
-    HIP_TRY(c, hipMemcpy(c->b.elq, h_q, (size_t)m * sizeof(double), hipMemcpyHostToDevice));
+  c->h_q.assign(h_q, h_q + m);
   c->have_elyt = true;
   return CPM_OK;
 }
@@ -296,6 +326,7 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
     return fail(c, CPM_EINVAL, "need n > 0, n_e > 0 and non-NULL coordinates and ids");
   if (c->have_A && n != c->n)
     return fail(c, CPM_EINVAL, "rebuild with n = %d differs from n = %d of this context", n, c->n);
+  TRY(ensure_uploaded(c));
   c->h_xyz.resize((size_t)3 * n);
   c->h_eid.resize(n);
   HIP_TRY(c, hipMemcpy(c->h_xyz.data(), d_xyz, (size_t)3 * n * sizeof(double), hipMemcpyDeviceToHost));
@@ -464,6 +495,7 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
   if (batch <= 0 || !d_b || (c->m > 0 && !d_xyz))
     return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL buffers");
   if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
+  TRY(ensure_uploaded(c));
   TRY(ensure_step_buffers(c));
   const cpm_params& p = c->p;
   const int n = c->n, m = c->m;
@@ -479,12 +511,12 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
     }
     { Timed t(c, "structure_factor");
       launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz, b.elq,
-                                p.Lx, p.Ly, c->Lz, b.sf_part); }
+                                p.Lx, p.Ly, c->Lz, c->nxm, c->nym, c->nzm, b.sf_part); }
     { Timed t(c, "sf_reduce");
       launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
     { Timed t(c, "kspace_project");
-      launch_b_kspace_project(st, b_is_f32, n, c->nruns, c->kchunks, c->runs_per_kchunk, b.runs, b,
-                              b.sfw, b.phik_part); }
+      launch_b_kspace_project(st, b_is_f32, n, c->kchunks, b.cols, b.chunk_col, b, b.sfw,
+                              b.phik_part); }
     { Timed t(c, "real_space_b");
       launch_b_real_space(st, n, m, c->rchunks, b, xyz, b.elq, p.Lx, p.Ly, p.rcut, p.alpha, p.eta,
                           b.phir_part); }
@@ -656,6 +688,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_M: *out = c->m; return CPM_OK;
     case CPM_INFO_WORKSPACE: *out = (double)c->bytes; return CPM_OK;
     case CPM_INFO_NPAD: *out = c->npad; return CPM_OK;
+    case CPM_INFO_NRUNS: *out = c->nruns; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -676,7 +709,7 @@ void cpm_destroy(cpm_ctx* c) {
   if (!c) return;
   Buffers& b = c->b;
   dfree(b.ex); dfree(b.ey); dfree(b.ez); dfree(b.efx); dfree(b.efy); dfree(b.efz); dfree(b.eid);
-  dfree(b.runs); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
+  dfree(b.runs); dfree(b.cols); dfree(b.chunk_col); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.mz); dfree(b.qt);

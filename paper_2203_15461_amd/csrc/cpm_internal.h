@@ -25,6 +25,16 @@ struct KRun {
   int pad;
 };
 
+// One column segment of the k-space set: fixed (nx, ny), len consecutive k_z
+// starting at lo (at most PJ_MAXK of them).
+struct KCol {
+  int nx, ny, lo, len;
+  int koff;                        // index of its first k in the flat k arrays
+  int pad;
+};
+
+constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
+
 struct Buffers {
   // electrode geometry (internal order = caller order), SoA, x and y wrapped
   double* ex = nullptr;  double* ey = nullptr;  double* ez = nullptr;
@@ -32,6 +42,8 @@ struct Buffers {
   int* eid = nullptr;
   // k-set
   KRun* runs = nullptr;            // nruns
+  KCol* cols = nullptr;            // ncols
+  int* chunk_col = nullptr;        // kchunks + 1 column boundaries of the projection chunks
   double* w2 = nullptr;            // 2 W(k), nk (flat run order)
   int* knx = nullptr; int* kny = nullptr; int* knz = nullptr;     // nk
   // dense matrices, npad x npad row-major FP64 unless noted
@@ -75,7 +87,6 @@ struct cpm_ctx {
   double Lz = 0, V = 0, kc = 0, ke = 0;
   int nk = 0, nruns = 0;
   int mchunks = 1, kchunks = 1, rchunks = 1;
-  int runs_per_kchunk = 0;
   unsigned store = 0;
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;
@@ -83,6 +94,13 @@ struct cpm_ctx {
   std::vector<double> h_v;         // per-electrode potential
   std::vector<double> h_xyz;       // electrode coordinates (host copy)
   std::vector<int> h_eid;
+  std::vector<double> h_q;         // electrolyte charges (host copy)
+  std::vector<cpm::KRun> h_runs;   // k set, built on the host at create time
+  std::vector<cpm::KCol> h_cols;
+  std::vector<int> h_chunk_col;
+  int nxm = 0, nym = 0, nzm = 0;   // largest |n| per axis in the k set
+  std::vector<double> h_w2;
+  std::vector<int> h_kx, h_ky, h_kz;
   cpm::Buffers b;
   // kernel timing (cpm_enable_timing)
   bool timing = false;
@@ -148,12 +166,13 @@ void launch_gemm_bf16x3(hipStream_t st, int M, int N, int K, const double* Bm, c
 // b vector
 void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk,
                                int m, int mchunks, const double* xyz, const double* q,
-                               double Lx, double Ly, double Lz, double* part);
+                               double Lx, double Ly, double Lz, int nxm, int nym, int nzm,
+                               double* part);
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
                         const double* w2, double* sfw);
-void launch_b_kspace_project(hipStream_t st, int fp32, int n, int nruns, int kchunks,
-                             int runs_per_chunk, const KRun* runs, const Buffers& b,
-                             const double* sfw, double* part);
+void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const KCol* cols,
+                             const int* chunk_col, const Buffers& b, const double* sfw,
+                             double* part);
 void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
                          const double* xyz, const double* q, double Lx, double Ly, double rc,
                          double alpha, double eta, double* part);

@@ -64,3 +64,55 @@ def test_null_arguments():
     assert L.cpm_solve_charges(None, 1, None, 0, 0, None, None) == cpm.EINVAL
     assert L.cpm_last_error(None) == b"no context"
     L.cpm_destroy(None)
+
+
+def _ctx(w, **over):
+    p = cpm.Params.of(w)
+    for k, v in over.items():
+        setattr(p, k, v)
+    return cpm.Context(p, stream=_NullStream())
+
+
+class _NullStream:
+    """Stands in for a torch stream: cpm_create stores the handle only."""
+    cuda_stream = 0
+
+
+@pytest.mark.parametrize("variant", ["small_a", "small_b", "graphite_2880"])
+def test_kset_matches_oracle(variant):
+    """cpm_create builds K+ on the host: same count as the oracle, and the runs
+    are maximal (each (nx, ny) column split into ceil(len/16) runs)."""
+    import math
+    from oracle import cpm_oracle as O
+    from paper_2203_15461_amd import inputs as I
+    w = {"small_a": lambda: I.small_capacitor("a"), "small_b": lambda: I.small_capacitor("b"),
+         "graphite_2880": I.graphite_capacitor}[variant]()
+    ctx = _ctx(w)
+    g, _, _ = O.kvectors(O.params_for(w))
+    assert int(ctx.info("nk")) == len(g)
+    cols = {}
+    for nx, ny, nz in g:
+        cols.setdefault((nx, ny), []).append(nz)
+    assert all(max(v) - min(v) + 1 == len(v) for v in cols.values())   # contiguous columns
+    assert int(ctx.info("nruns")) == sum(math.ceil(len(v) / 16) for v in cols.values())
+    assert abs(ctx.info("kcut") - O.params_for(w).k_cut) < 1e-15
+    assert abs(ctx.info("lz") - 3 * w.h) < 1e-12
+    ctx.close()
+
+
+def test_electrolyte_validation_on_host():
+    from paper_2203_15461_amd import inputs as I
+    w = I.small_capacitor("a")
+    ctx = _ctx(w)
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.set_electrolyte([1.0, 1.0, -1.5])
+    assert ei.value.status == cpm.EINVAL
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.set_electrolyte([1.0, float("nan")])
+    assert ei.value.status == cpm.EINVAL
+    ctx.set_electrolyte(w.electrolyte_q)
+    assert int(ctx.info("m")) == w.m
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.set_electrolyte(w.electrolyte_q)
+    assert ei.value.status == cpm.ESTATE
+    ctx.close()
