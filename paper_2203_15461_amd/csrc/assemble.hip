@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(256) k_real_space_A(
     val = (i == j) ? 1.0 : 0.0;
   } else {
     const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
+    const double r2_gauss = eta_ee > alpha ? 45.0 / (eta_ee * eta_ee - alpha * alpha) : 1e300;
     double dx = ex[i] - ex[j], dy = ey[i] - ey[j], dz = ez[i] - ez[j];
     dx -= Lx * rint(dx * invLx);
     dy -= Ly * rint(dy * invLy);
@@ -67,7 +68,9 @@ __global__ void __launch_bounds__(256) k_real_space_A(
           const double r2 = X * X + Y * Y + dz * dz;
           if (r2 > 0.0 && r2 < rc2 * (1.0 + 1e-12)) {
             const double r = sqrt(r2);
-            if (r < rc) sum += (erfc(alpha * r) - erfc(eta_ee * r)) / r;
+            // erfc(eta_ee r) is below FP64 rounding of the difference once
+            // (eta_ee^2 - alpha^2) r^2 > 45 (erfc(x) <= e^{-x^2})
+            if (r < rc) sum += (r2 > r2_gauss ? erfc(alpha * r) : erfc(alpha * r) - erfc(eta_ee * r)) / r;
           }
         }
       }

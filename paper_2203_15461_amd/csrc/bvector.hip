@@ -23,16 +23,22 @@
 namespace cpm {
 
 // ---------------------------------------------------------------------------
-// Structure factors: one thread per k run; the electrolyte is staged in LDS in
-// tiles of up to SF_TJ charges together with per-charge phase tables
+// Structure factors.  One thread per k run (256 runs per workgroup) and a
+// chunk of the electrolyte per workgroup, staged in LDS tiles of up to SF_TJ
+// charges together with per-charge phase tables
 //   tx[n] = q_j e^{2 pi i n fx_j} (n = 0..nxm), ty[n] = e^{2 pi i n fy_j}
 //   (n = 0..nym), tz[n] = e^{2 pi i n fz_j} (n = 0..nzm),
-// each entry computed directly in FP64 (negative indices use the conjugate).
-// The start of a run is tx[nx] ty[ny] tz[nz0] (two complex products), the
-// rest of the run a rotation by tz[1] in FP64.  T is the accumulation type.
-// part[(chunk * nk + k) * 2 + {0,1}] = partial S(k) over the chunk's charges.
+// built in segments of SF_SEG entries: an exact FP64 sincospi at the first
+// entry, then rotations by e^{2 pi i f}.  Negative indices use the conjugate.
+// A run starts at tx[nx] ty[ny] tz[nz0] (two complex products) and advances
+// along k_z by tz[1] (FP64 rotation).  Two charges are walked together so
+// two independent rotation chains are in flight.  T is the accumulation type.
+// part[(chunk * nk + k) * 2 + {0,1}] = partial S(k) over the chunk's charges;
+// the workgroups of the first run block also leave the chunk's partial dipole
+// sum_j q_j z_j in mz_part[chunk].
 // ---------------------------------------------------------------------------
-constexpr int SF_TJ = 32;
+constexpr int SF_TJ = 16;
+constexpr int SF_SEG = 8;
 
 __device__ inline double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -44,10 +50,15 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
                                                           const double* __restrict__ xyz,
                                                           const double* __restrict__ q, double Lx,
                                                           double Ly, double Lz, int nxm, int nym,
-                                                          int nzm, double* __restrict__ part) {
+                                                          int nzm, double* __restrict__ part,
+                                                          double* __restrict__ mz_part) {
   extern __shared__ double2 tab[];                  // [tj][W]
   __shared__ double s_f[3][SF_TJ], s_q[SF_TJ];
+  __shared__ double2 s_e1[3][SF_TJ];
+  __shared__ double s_mz[4];
   const int W = nxm + nym + nzm + 3, oy = nxm + 1, oz = nxm + nym + 2;
+  const int nsx = (nxm + SF_SEG) / SF_SEG, nsy = (nym + SF_SEG) / SF_SEG,
+            nsz = (nzm + SF_SEG) / SF_SEG, nseg = nsx + nsy + nsz;
   const int rid = blockIdx.x * blockDim.x + threadIdx.x;
   const int chunk = blockIdx.y;
   const int j0 = chunk * chunk_size;
@@ -59,44 +70,80 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
   T are[RUN], aim[RUN];
 #pragma unroll
   for (int r = 0; r < RUN; ++r) { are[r] = 0; aim[r] = 0; }
+  double mz = 0.0;
 
   for (int jt = j0; jt < j1; jt += tj) {
     const int nt = min(tj, j1 - jt);
     __syncthreads();
     if ((int)threadIdx.x < nt) {
-      const int j = jt + threadIdx.x;
-      double fx = xyz[3 * j] / Lx, fy = xyz[3 * j + 1] / Ly;
-      s_f[0][threadIdx.x] = fx - floor(fx);
-      s_f[1][threadIdx.x] = fy - floor(fy);
-      s_f[2][threadIdx.x] = xyz[3 * j + 2] / Lz;
-      s_q[threadIdx.x] = q[j];
+      const int t = threadIdx.x, j = jt + t;
+      const double x = xyz[3 * j], y = xyz[3 * j + 1], z = xyz[3 * j + 2];
+      const double fx = x / Lx, fy = y / Ly;
+      s_f[0][t] = fx - floor(fx);
+      s_f[1][t] = fy - floor(fy);
+      s_f[2][t] = z / Lz;
+      s_q[t] = q[j];
+      if (blockIdx.x == 0) mz += q[j] * z;
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < nt * W; e += blockDim.x) {
-      const int t = e / W, idx = e - t * W;
-      const int ax = idx < oy ? 0 : (idx < oz ? 1 : 2);
-      const int nn = idx - (ax == 0 ? 0 : (ax == 1 ? oy : oz));
-      double th = nn * s_f[ax][t];
+    if ((int)threadIdx.x < 3 * nt) {
+      const int ax = threadIdx.x / nt, t = threadIdx.x - ax * nt;
+      const double f = s_f[ax][t];
+      double sn, cs;
+      sincospi(2.0 * (f - rint(f)), &sn, &cs);
+      s_e1[ax][t] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nt * nseg; e += blockDim.x) {
+      const int t = e / nseg, sg = e - t * nseg;
+      const int ax = sg < nsx ? 0 : (sg < nsx + nsy ? 1 : 2);
+      const int s0 = sg - (ax == 0 ? 0 : (ax == 1 ? nsx : nsx + nsy));
+      const int nmax = ax == 0 ? nxm : (ax == 1 ? nym : nzm);
+      const int off = ax == 0 ? 0 : (ax == 1 ? oy : oz);
+      const int n0 = s0 * SF_SEG, n1 = min(nmax, n0 + SF_SEG - 1);
+      double th = n0 * s_f[ax][t];
       th -= rint(th);
       double sn, cs;
       sincospi(2.0 * th, &sn, &cs);
       const double sc = ax == 0 ? s_q[t] : 1.0;
-      tab[e] = make_double2(sc * cs, sc * sn);
+      double2 v = make_double2(cs, sn);
+      const double2 e1 = s_e1[ax][t];
+      double2* dst = tab + t * W + off;
+      for (int nn = n0; nn <= n1; ++nn) {
+        dst[nn] = make_double2(sc * v.x, sc * v.y);
+        v = cmul(v, e1);
+      }
     }
     __syncthreads();
     if (rid < nruns) {
-      for (int t = 0; t < nt; ++t) {
-        const double2* tt = tab + t * W;
-        double2 ey = tt[iy], ez = tt[iz];
-        ey.y *= sy;
-        ez.y *= sz0;
-        double2 w = cmul(cmul(tt[run.nx], ey), ez);
-        const double2 st = tt[oz + 1];
+      int t = 0;
+      for (; t + 1 < nt; t += 2) {
+        const double2* ta = tab + t * W;
+        const double2* tb = ta + W;
+        double2 eya = ta[iy], eza = ta[iz], eyb = tb[iy], ezb = tb[iz];
+        eya.y *= sy; eza.y *= sz0; eyb.y *= sy; ezb.y *= sz0;
+        double2 wa = cmul(cmul(ta[run.nx], eya), eza);
+        double2 wb = cmul(cmul(tb[run.nx], eyb), ezb);
+        const double2 sa = ta[oz + 1], sb = tb[oz + 1];
 #pragma unroll
         for (int r = 0; r < RUN; ++r) {
-          are[r] += (T)w.x;
-          aim[r] += (T)w.y;
-          w = cmul(w, st);
+          are[r] += (T)(wa.x + wb.x);
+          aim[r] += (T)(wa.y + wb.y);
+          wa = cmul(wa, sa);
+          wb = cmul(wb, sb);
+        }
+      }
+      if (t < nt) {
+        const double2* ta = tab + t * W;
+        double2 eya = ta[iy], eza = ta[iz];
+        eya.y *= sy; eza.y *= sz0;
+        double2 wa = cmul(cmul(ta[run.nx], eya), eza);
+        const double2 sa = ta[oz + 1];
+#pragma unroll
+        for (int r = 0; r < RUN; ++r) {
+          are[r] += (T)wa.x;
+          aim[r] += (T)wa.y;
+          wa = cmul(wa, sa);
         }
       }
     }
@@ -108,27 +155,35 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
       out[2 * r + 1] = (double)aim[r];
     }
   }
+  if (blockIdx.x == 0) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) mz += __shfl_xor(mz, o, 64);
+    if (lane == 0) s_mz[wave] = mz;
+    __syncthreads();
+    if (threadIdx.x == 0) mz_part[chunk] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
+  }
 }
 
 int sf_tile(int nxm, int nym, int nzm) {
   const int W = nxm + nym + nzm + 3;
-  int tj = (int)(61440 / (W * sizeof(double2)));   // <= 60 KB of dynamic LDS
+  int tj = (int)(30720 / (W * sizeof(double2)));   // <= 30 KB of dynamic LDS
   return tj < 1 ? 1 : (tj > SF_TJ ? SF_TJ : tj);
 }
 
 void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk, int m,
                                int mchunks, const double* xyz, const double* q, double Lx,
-                               double Ly, double Lz, int nxm, int nym, int nzm, double* part) {
+                               double Ly, double Lz, int nxm, int nym, int nzm, double* part,
+                               double* mz_part) {
   const int chunk_size = (m + mchunks - 1) / mchunks;
   const int tj = sf_tile(nxm, nym, nzm);
   const size_t shm = (size_t)tj * (nxm + nym + nzm + 3) * sizeof(double2);
   dim3 grid((nruns + 255) / 256, mchunks), block(256);
   if (fp32)
     hipLaunchKernelGGL(k_structure_factor<float>, grid, block, shm, st, nruns, runs, nk, m,
-                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part);
+                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part, mz_part);
   else
     hipLaunchKernelGGL(k_structure_factor<double>, grid, block, shm, st, nruns, runs, nk, m,
-                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part);
+                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part, mz_part);
 }
 
 // sfw[k] = 2 W(k) * sum_chunks part[chunk][k]   (fixed chunk order)
@@ -226,6 +281,15 @@ void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const
 // ---------------------------------------------------------------------------
 constexpr int RS_TILE = 256;
 
+// erfc(alpha r) - erfc(eta r).  Beyond r2_gauss = 45 / (eta^2 - alpha^2) the
+// second term is below e^-45 of the first (erfc(x) <= e^{-x^2}), i.e. under
+// FP64 rounding of the difference, and is not evaluated.
+__device__ inline double pair_kernel(double r, double r2, double alpha, double eta,
+                                     double r2_gauss) {
+  const double a = erfc(alpha * r);
+  return r2 > r2_gauss ? a : a - erfc(eta * r);
+}
+
 __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_size,
                                                       const double* __restrict__ ex,
                                                       const double* __restrict__ ey,
@@ -239,6 +303,7 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
   const int chunk = blockIdx.y;
   const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
   const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
+  const double r2_gauss = eta > alpha ? 45.0 / (eta * eta - alpha * alpha) : 1e300;
   const bool single = (Lx >= 2.0 * rc) && (Ly >= 2.0 * rc);
   double xi = 0, yi = 0, zi = 0;
   if (i < n) { xi = ex[i]; yi = ey[i]; zi = ez[i]; }
@@ -266,7 +331,7 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
         const double r2 = dx * dx + dy * dy + dz * dz;
         if (r2 < rc2 * (1.0 + 1e-12)) {
           const double r = sqrt(r2);
-          if (r < rc) acc += s_q[t] * (erfc(alpha * r) - erfc(eta * r)) / r;
+          if (r < rc) acc += s_q[t] * pair_kernel(r, r2, alpha, eta, r2_gauss) / r;
         }
       } else {
         const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
@@ -278,7 +343,7 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
             const double r2 = X * X + Y * Y + dz * dz;
             if (r2 < rc2 * (1.0 + 1e-12)) {
               const double r = sqrt(r2);
-              if (r < rc) acc += s_q[t] * (erfc(alpha * r) - erfc(eta * r)) / r;
+              if (r < rc) acc += s_q[t] * pair_kernel(r, r2, alpha, eta, r2_gauss) / r;
             }
           }
         }
@@ -297,27 +362,11 @@ void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffer
                      Lx, Ly, rc, alpha, eta, part);
 }
 
-// M_z = sum_j q_j z_j in one workgroup, fixed order.
-__global__ void __launch_bounds__(256) k_dipole(int m, const double* __restrict__ xyz,
-                                                const double* __restrict__ q, double* mz) {
-  __shared__ double sh[4];
-  double s = 0.0;
-  for (int j = threadIdx.x; j < m; j += 256) s += q[j] * xyz[3 * j + 2];
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
-  __syncthreads();
-  if (threadIdx.x == 0) *mz = (sh[0] + sh[1]) + (sh[2] + sh[3]);
-}
-
-void launch_b_dipole(hipStream_t st, int m, const double* xyz, const double* q, double* mz) {
-  hipLaunchKernelGGL(k_dipole, dim3(1), dim3(256), 0, st, m, xyz, q, mz);
-}
-
 // b_i = -k_e (sum of k-space partials + sum of real-space partials + (4 pi/V) z_i M_z)
-__global__ void k_combine(int n, int kchunks, int rchunks, const double* __restrict__ phik,
-                          const double* __restrict__ phir, const double* __restrict__ ez,
-                          const double* __restrict__ mz, double slab_coef, double ke, void* out,
-                          int out_is_f32) {
+__global__ void k_combine(int n, int kchunks, int rchunks, int mchunks,
+                          const double* __restrict__ phik, const double* __restrict__ phir,
+                          const double* __restrict__ ez, const double* __restrict__ mz_part,
+                          double slab_coef, double ke, void* out, int out_is_f32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   // fixed-order sums; the loads are independent, so unrolling keeps many in flight
@@ -326,18 +375,21 @@ __global__ void k_combine(int n, int kchunks, int rchunks, const double* __restr
   for (int c = 0; c < kchunks; ++c) pk += phik[(size_t)c * n + i];
 #pragma unroll 8
   for (int c = 0; c < rchunks; ++c) pr += phir[(size_t)c * n + i];
-  const double b = -ke * (pk + pr + slab_coef * ez[i] * (*mz));
+  double mz = 0.0;
+  for (int c = 0; c < mchunks; ++c) mz += mz_part[c];
+  const double b = -ke * (pk + pr + slab_coef * ez[i] * mz);
   if (out_is_f32)
     reinterpret_cast<float*>(out)[i] = (float)b;
   else
     reinterpret_cast<double*>(out)[i] = b;
 }
 
-void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
-                      const double* phir, const Buffers& b, const double* mz, double slab_coef,
-                      double ke, void* out, int out_is_f32) {
-  hipLaunchKernelGGL(k_combine, dim3((n + 63) / 64), dim3(64), 0, st, n, kchunks, rchunks, phik,
-                     phir, b.ez, mz, slab_coef, ke, out, out_is_f32);
+void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchunks,
+                      const double* phik, const double* phir, const Buffers& b,
+                      const double* mz_part, double slab_coef, double ke, void* out,
+                      int out_is_f32) {
+  hipLaunchKernelGGL(k_combine, dim3((n + 63) / 64), dim3(64), 0, st, n, kchunks, rchunks, mchunks,
+                     phik, phir, b.ez, mz_part, slab_coef, ke, out, out_is_f32);
 }
 
 }  // namespace cpm

@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -164,14 +165,15 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   // reproducible): ~512 workgroups per kernel, >= 64 charges per SF chunk,
   // >= 32 charges per real-space chunk
   const int run_blocks = (c->nruns + 255) / 256;
-  c->mchunks = std::max(1, std::min((512 + run_blocks - 1) / run_blocks, std::max(1, c->m / 64)));
+  const int sf_target = c->sf_wg_target;
+  c->mchunks = std::max(1, std::min((sf_target + run_blocks - 1) / run_blocks, std::max(1, c->m / 64)));
   const int atom_blocks = (c->n + 255) / 256;
   c->rchunks = std::max(1, std::min((512 + atom_blocks - 1) / atom_blocks, std::max(1, c->m / 32)));
   TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
   TRY(dalloc(c, &b.phik_part, (size_t)c->n * c->kchunks));
   TRY(dalloc(c, &b.phir_part, (size_t)c->n * c->rchunks));
-  TRY(dalloc(c, &b.mz, 1));
+  TRY(dalloc(c, &b.mz, (size_t)c->mchunks));
   return CPM_OK;
 }
 
@@ -263,6 +265,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   }
   c->Lz = p.slab_factor * p.h;
   c->V = p.Lx * p.Ly * c->Lz;
+  if (const char* ev = std::getenv("CPM_SF_WG_TARGET")) c->sf_wg_target = std::max(64, std::atoi(ev));
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
 
@@ -511,7 +514,7 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
     }
     { Timed t(c, "structure_factor");
       launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz, b.elq,
-                                p.Lx, p.Ly, c->Lz, c->nxm, c->nym, c->nzm, b.sf_part); }
+                                p.Lx, p.Ly, c->Lz, c->nxm, c->nym, c->nzm, b.sf_part, b.mz); }
     { Timed t(c, "sf_reduce");
       launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
     { Timed t(c, "kspace_project");
@@ -520,10 +523,8 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
     { Timed t(c, "real_space_b");
       launch_b_real_space(st, n, m, c->rchunks, b, xyz, b.elq, p.Lx, p.Ly, p.rcut, p.alpha, p.eta,
                           b.phir_part); }
-    { Timed t(c, "dipole");
-      launch_b_dipole(st, m, xyz, b.elq, b.mz); }
     { Timed t(c, "combine");
-      launch_b_combine(st, n, c->kchunks, c->rchunks, b.phik_part, b.phir_part, b, b.mz,
+      launch_b_combine(st, n, c->kchunks, c->rchunks, c->mchunks, b.phik_part, b.phir_part, b, b.mz,
                        4.0 * M_PI / c->V, c->ke, out, b_is_f32); }
     TRY(launched(c, "potential_vector"));
   }

@@ -66,7 +66,7 @@ struct Buffers {
   double* sfw = nullptr;           // 2W-weighted structure factor (2 * nk)
   double* phik_part = nullptr;     // k-chunk partial potentials (n * kchunks)
   double* phir_part = nullptr;     // m-chunk partial real-space potentials (n * rchunks)
-  double* mz = nullptr;            // electrolyte dipole M_z (per snapshot)
+  double* mz = nullptr;            // electrolyte dipole partials M_z (per SF chunk)
   double* qt = nullptr;            // q-tilde (batch x npad)
   double* res = nullptr;           // refinement residual / corrections (batch x npad)
   double* bpad = nullptr;          // padded b for batched solves (bpad_rows x npad)
@@ -87,6 +87,7 @@ struct cpm_ctx {
   double Lz = 0, V = 0, kc = 0, ke = 0;
   int nk = 0, nruns = 0;
   int mchunks = 1, kchunks = 1, rchunks = 1;
+  int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
   unsigned store = 0;
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;
@@ -167,7 +168,7 @@ void launch_gemm_bf16x3(hipStream_t st, int M, int N, int K, const double* Bm, c
 void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk,
                                int m, int mchunks, const double* xyz, const double* q,
                                double Lx, double Ly, double Lz, int nxm, int nym, int nzm,
-                               double* part);
+                               double* part, double* mz_part);
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
                         const double* w2, double* sfw);
 void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const KCol* cols,
@@ -176,9 +177,9 @@ void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const
 void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
                          const double* xyz, const double* q, double Lx, double Ly, double rc,
                          double alpha, double eta, double* part);
-void launch_b_dipole(hipStream_t st, int m, const double* xyz, const double* q, double* mz);
-void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
-                      const double* phir, const Buffers& b, const double* mz, double slab_coef,
-                      double ke, void* out, int out_is_f32);
+void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchunks,
+                      const double* phik, const double* phir, const Buffers& b,
+                      const double* mz_part, double slab_coef, double ke, void* out,
+                      int out_is_f32);
 
 }  // namespace cpm
