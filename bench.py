@@ -41,8 +41,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=1000)
+    ap.add_argument("--batch", type=int, default=None,
+                    help="snapshots per step (default 1000 at n=2880, 128 at n=20064)")
     ap.add_argument("--mode", default="bf16r", choices=sorted(MODES))
+    ap.add_argument("--workload", default="graphite_capacitor_2880",
+                    choices=["graphite_capacitor_2880", "graphite_capacitor_20064"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
@@ -65,8 +68,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     store, b_f32, mode, dtype = MODES[args.mode]
-    w = I.graphite_capacitor()
-    B = args.batch
+    if args.workload == "graphite_capacitor_2880":
+        w = I.graphite_capacitor()
+        B = args.batch or 1000
+    else:
+        w = I.scaled_graphite_capacitor(20000)
+        B = args.batch or 128
     t0 = time.time()
     rng = np.random.default_rng(I.BASE_SEED + 1)
     base = w.electrolyte_xyz
@@ -135,17 +142,34 @@ def main():
     solve_s = time.perf_counter() - ts
     qsum = float(q.sum(dim=1).abs().max().item())
 
+    # plain FP64 per-step path for comparison: one snapshot at a time,
+    # b then q = S (b + v) as a streaming FP64 matvec (A and S already built)
+    ctx.invert(1)
+    ctx.set_potential(w.v_electrode)
+    n_plain = min(B, 100 if w.n < 10000 else 8)
+    b1 = torch.empty((1, w.n), dtype=torch.float64, device=dev)
+    q1 = torch.empty((1, w.n), dtype=torch.float64, device=dev)
+    Qe1 = torch.empty((1, 2), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for s_ in range(n_plain):
+        ctx.potential_vector(xyz[s_:s_ + 1], b1)
+        ctx.solve_charges(b1, 0x000, q1, Qe1)
+    torch.cuda.synchronize()
+    plain_rate = n_plain / (time.perf_counter() - ts)
+
     # dominant kernel: the structure factors (FP64 / FP32 VALU)
     nk = int(ctx.info("nk"))
     sf_ms, sf_cnt = timing["structure_factor"]
     sf_avg = sf_ms / max(sf_cnt, 1) * 1e-3
     flop_per_launch = 8.0 * nk * w.m          # complex rotation + accumulate per (k, charge)
     achieved = flop_per_launch / sf_avg if sf_avg > 0 else 0.0
-    peak = PEAK_FP32_VALU if b_f32 else PEAK_FP64_VALU
+    peak = PEAK_FP64_VALU      # the phases and rotations are FP64 in every mode
+    traffic = stored_traffic(args.workload, sf_cnt)
 
     value = B * args.steps / elapsed
     out = {
-        "metric": "charge solves/sec (N_elec=2880)",
+        "metric": f"charge solves/sec (N_elec={w.n})",
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
@@ -157,24 +181,44 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": "graphite_capacitor_2880", "n_elec": w.n, "m_elyt": w.m,
+        "config": {"workload": args.workload, "n_elec": w.n, "m_elyt": w.m,
                    "snapshots_per_step": B, "n_k": nk, "alpha": w.alpha, "rcut": w.rcut,
                    "eta": w.eta, "mode": args.mode,
                    "step": "assemble A + invert + S + set v + b and q for every snapshot"},
         "roofline": {"kernel": "structure_factor", "bound": "alu",
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak, "traffic": traffic,
                      "flop_per_launch": flop_per_launch, "avg_launch_us": sf_avg * 1e6},
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),
+        "plain_fp64_per_step_rate": plain_rate,
+        "plain_fp64_sample": f"{n_plain} snapshots, b + FP64 matvec solve one at a time, setup excluded",
         "kernel_ms_per_step": {f: v[0] / args.steps for f, v in timing.items() if v[1]},
         "max_abs_sum_q": qsum,
     }
     ctx.close()
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and w.n < 10000:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
+
+
+def stored_traffic(workload, launches):
+    """HBM bytes per structure-factor launch from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a 1 GiB copy), or None when the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "structure_factor_traffic.json")
+    src = os.path.join(ROOT, "paper_2203_15461_amd", "csrc", "bvector.hip")
+    try:
+        rec = json.load(open(path))
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(workload)
+    if not entry or rec.get("bvector_sha256") != digest:
+        return None
+    return entry["bytes_per_launch"]
 
 
 def cpu_baseline(w):
