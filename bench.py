@@ -166,6 +166,7 @@ def main():
     achieved = flop_per_launch / sf_avg if sf_avg > 0 else 0.0
     peak = PEAK_FP64_VALU      # the phases and rotations are FP64 in every mode
     traffic = stored_traffic(args.workload, sf_cnt)
+    sf_bound = "mfma" if (ctx.info("sf_matrix") == 1.0 and not b_f32) else "alu"
 
     value = B * args.steps / elapsed
     out = {
@@ -185,7 +186,7 @@ def main():
                    "snapshots_per_step": B, "n_k": nk, "alpha": w.alpha, "rcut": w.rcut,
                    "eta": w.eta, "mode": args.mode,
                    "step": "assemble A + invert + S + set v + b and q for every snapshot"},
-        "roofline": {"kernel": "structure_factor", "bound": "alu",
+        "roofline": {"kernel": "structure_factor", "bound": sf_bound,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
                      "flop_per_launch": flop_per_launch, "avg_launch_us": sf_avg * 1e6},

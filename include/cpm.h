@@ -78,7 +78,10 @@ enum {
   CPM_INFO_M = 7,             /* electrolyte charges                              */
   CPM_INFO_WORKSPACE = 8,     /* device bytes held by the context                 */
   CPM_INFO_NPAD = 9,          /* padded matrix order (multiple of 64)             */
-  CPM_INFO_NRUNS = 10         /* k-space runs (<= 16 consecutive k_z each)        */
+  CPM_INFO_NRUNS = 10,        /* k-space runs (<= 16 consecutive k_z each)        */
+  CPM_INFO_NLAYERS = 11,      /* z planes of the electrodes when <= 64 (planar    */
+                              /* factorisation of the k-space projection), else 0 */
+  CPM_INFO_SF_MATRIX = 12     /* 1: FP64 structure factors run on matrix cores    */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -145,9 +148,10 @@ cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
  * neutrality projection q -= (e^T q / s) u, and electrode totals
  * Q~ = G^T q (Eq. 7 left-hand side).  d_b: batch x n (FP64 or FP32 per
  * b_is_f32); d_q: batch x n FP64 output; d_Qe: batch x n_e FP64 output or
- * NULL.  mode: CPM_SOLVE_* (| CPM_SOLVE_REFINE).  batch == 1 streams S once
- * (matvec); batch > 1 runs Q = S B as one MFMA GEMM.  The chosen copy of S
- * must have been kept by cpm_invert, else CPM_EINVAL. */
+ * NULL.  mode: CPM_SOLVE_* (| CPM_SOLVE_REFINE).  FP64 with batch < 4 and
+ * FP32 stream S once per vector (matvec); FP64 with batch >= 4 and split-BF16
+ * (any batch) run Q = B S as one MFMA GEMM with rows padded to 64.  The
+ * chosen copy of S must have been kept by cpm_invert, else CPM_EINVAL. */
 cpm_status cpm_solve_charges(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32,
                              unsigned mode, double* d_q, double* d_Qe);
 

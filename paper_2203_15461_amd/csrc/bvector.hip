@@ -186,6 +186,226 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
                        chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part, mz_part);
 }
 
+// ---------------------------------------------------------------------------
+// Structure factors on FP64 matrix cores.  For a (k_x, k_y) column c,
+//   S(c, +-n) = sum_j C_cj (Zr_jn +- i Zi_jn),  C_cj = q_j e^{i(k_x x_j + k_y y_j)},
+//   Z_jn = e^{2 pi i n z_j / Lz},  n >= 0,
+// so with rows (Re C_c, Im C_c) and columns (Zr_n, Zi_n) one real GEMM over
+// the charges gives Pr, Qr, Pi, Qi and both S(c, n) = (Pr - Qi) + i (Pi + Qr)
+// and S(c, -n) = (Pr + Qi) + i (Pi - Qr).  Columns are sorted by their k_z
+// extent and grouped 32 per M tile (64 rows); each workgroup takes one M tile,
+// one half of its n range and one chunk of the electrolyte.  Per LDS tile of
+// 16 charges it builds the phase tables (segments of exact sincospi plus FP64
+// rotations), the A operand C_cj and runs v_mfma_f64_16x16x4f64 with the
+// Z table as the B operand.  Wave w owns rows 16w..16w+15.
+// part[((chunk * mtiles + mt) * 64 + row) * npadc + col]: this chunk's sums.
+// ---------------------------------------------------------------------------
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+constexpr int SFM_TJ = 16;             // charges per LDS tile (4 MFMA k-steps)
+constexpr int SFM_NB = 6;              // max 16-wide n blocks per workgroup (half a tile)
+
+__global__ void __launch_bounds__(256) k_sf_mfma(int m, int chunk_size, int mtiles,
+                                                 const int* __restrict__ sc_nx,
+                                                 const int* __restrict__ sc_ny,
+                                                 const int* __restrict__ tile_nb, int ncolsort,
+                                                 const double* __restrict__ xyz,
+                                                 const double* __restrict__ q, double Lx,
+                                                 double Ly, double Lz, int nxm, int nym,
+                                                 int npadc, double* __restrict__ part,
+                                                 double* __restrict__ mz_part) {
+  __shared__ double s_f[3][SFM_TJ], s_q[SFM_TJ];
+  __shared__ double s_mz[4];
+  __shared__ double2 s_e1[3][SFM_TJ];
+  __shared__ int s_nx[32], s_ny[32];
+  __shared__ double A_l[64][SFM_TJ + 1];
+  extern __shared__ double dyn[];
+  const int TX = nxm + 1, TY = nym + 1;
+  double2* tx = reinterpret_cast<double2*>(dyn);              // [SFM_TJ][TX]
+  double2* ty = tx + SFM_TJ * TX;                              // [SFM_TJ][TY]
+  double* tzd = reinterpret_cast<double*>(ty + SFM_TJ * TY);   // [SFM_TJ][16 * SFM_NB]
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int mt = blockIdx.x >> 1, half = blockIdx.x & 1;
+  const int chunk = blockIdx.y;
+  const int nbt = tile_nb[mt];                     // n blocks of this M tile
+  const int nb_lo = half ? (nbt + 1) / 2 : 0;
+  const int nb_hi = half ? nbt : (nbt + 1) / 2;
+  const int nbw = nb_hi - nb_lo;                   // blocks of this workgroup (<= SFM_NB)
+  const int n_lo = nb_lo * 8;                      // first complex n of this workgroup
+  const int c_base = mt * 32;
+  const int ncol = min(32, ncolsort - c_base);
+  if (tid < 32) {
+    s_nx[tid] = tid < ncol ? sc_nx[c_base + tid] : 0;
+    s_ny[tid] = tid < ncol ? sc_ny[c_base + tid] : 0;
+  }
+  const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
+  v4d_t acc[SFM_NB];
+#pragma unroll
+  for (int b = 0; b < SFM_NB; ++b) acc[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+  double mz = 0.0;
+
+  for (int jt = j0; jt < j1; jt += SFM_TJ) {
+    const int nt = min(SFM_TJ, j1 - jt);
+    __syncthreads();
+    if (tid < SFM_TJ) {
+      double fx = 0, fy = 0, fz = 0, qq = 0;
+      if (tid < nt) {
+        const int j = jt + tid;
+        fx = xyz[3 * j] / Lx;
+        fy = xyz[3 * j + 1] / Ly;
+        fz = xyz[3 * j + 2] / Lz;
+        fx -= floor(fx);
+        fy -= floor(fy);
+        qq = q[j];
+        if (blockIdx.x == 0) mz += qq * xyz[3 * j + 2];
+      }
+      s_f[0][tid] = fx; s_f[1][tid] = fy; s_f[2][tid] = fz; s_q[tid] = qq;
+    }
+    __syncthreads();
+    if (tid < 3 * SFM_TJ) {
+      const int ax = tid / SFM_TJ, t = tid - ax * SFM_TJ;
+      const double f = s_f[ax][t];
+      double sn, cs;
+      sincospi(2.0 * (f - rint(f)), &sn, &cs);
+      s_e1[ax][t] = make_double2(cs, sn);
+    }
+    __syncthreads();
+    // tables in segments of 8 entries: tx (q folded), ty, tz (this n range)
+    {
+      const int sx = (TX + 7) / 8, sy = (TY + 7) / 8, sz = nbw;   // n range is 8 * nbw
+      const int nseg = sx + sy + sz;
+      for (int e = tid; e < SFM_TJ * nseg; e += 256) {
+        const int t = e / nseg, sg = e - t * nseg;
+        const int ax = sg < sx ? 0 : (sg < sx + sy ? 1 : 2);
+        const int s0 = sg - (ax == 0 ? 0 : (ax == 1 ? sx : sx + sy));
+        const int n0 = (ax == 2 ? n_lo : 0) + 8 * s0;
+        const int cnt = ax == 0 ? min(8, TX - 8 * s0) : (ax == 1 ? min(8, TY - 8 * s0) : 8);
+        double th = n0 * s_f[ax][t];
+        th -= rint(th);
+        double sn, cs;
+        sincospi(2.0 * th, &sn, &cs);
+        double2 v = make_double2(cs, sn);
+        const double2 e1 = s_e1[ax][t];
+        const double sc = ax == 0 ? s_q[t] : 1.0;
+        for (int u = 0; u < cnt; ++u) {
+          if (ax == 0) tx[t * TX + 8 * s0 + u] = make_double2(sc * v.x, sc * v.y);
+          else if (ax == 1) ty[t * TY + 8 * s0 + u] = v;
+          else {
+            const int col = 2 * (8 * s0 + u);
+            tzd[t * (16 * SFM_NB) + col] = v.x;
+            tzd[t * (16 * SFM_NB) + col + 1] = v.y;
+          }
+          v = cmul(v, e1);
+        }
+      }
+    }
+    __syncthreads();
+    // A operand: rows (Re C, Im C) of the tile's 32 columns, one per charge
+    for (int e = tid; e < 32 * SFM_TJ; e += 256) {
+      const int cl = e / SFM_TJ, t = e - cl * SFM_TJ;
+      double2 cv = make_double2(0.0, 0.0);
+      if (cl < ncol) {
+        const int ny = s_ny[cl];
+        double2 y = ty[t * TY + abs(ny)];
+        if (ny < 0) y.y = -y.y;
+        cv = cmul(tx[t * TX + s_nx[cl]], y);      // zero for padding charges (q = 0)
+      }
+      A_l[2 * cl][t] = cv.x;
+      A_l[2 * cl + 1][t] = cv.y;
+    }
+    __syncthreads();
+    const int r16 = lane & 15, kq = lane >> 4;
+#pragma unroll
+    for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
+      const double a = A_l[16 * wave + r16][4 * ks + kq];
+      const double* brow = tzd + (4 * ks + kq) * (16 * SFM_NB);
+#pragma unroll
+      for (int b = 0; b < SFM_NB; ++b)
+        if (b < nbw) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[16 * b + r16], acc[b], 0, 0, 0);
+    }
+  }
+  // result register r of lane l: row (l >> 4) + 4 r, column l & 15 of block b
+  double* out = part + ((size_t)chunk * mtiles + mt) * 64 * (size_t)npadc;
+#pragma unroll
+  for (int b = 0; b < SFM_NB; ++b) {
+    if (b >= nbw) continue;
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * wave + (lane >> 4) + 4 * r;
+      const int col = 16 * (nb_lo + b) + (lane & 15);
+      out[(size_t)row * npadc + col] = acc[b][r];
+    }
+  }
+  if (blockIdx.x == 0) {   // this chunk's electrolyte dipole sum_j q_j z_j
+    for (int o = 32; o > 0; o >>= 1) mz += __shfl_xor(mz, o, 64);
+    if (lane == 0) s_mz[wave] = mz;
+    __syncthreads();
+    if (tid == 0) mz_part[chunk] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
+  }
+}
+
+size_t sf_mfma_lds(int nxm, int nym) {
+  return (size_t)SFM_TJ * ((nxm + 1) + (nym + 1)) * sizeof(double2) +
+         (size_t)SFM_TJ * 16 * SFM_NB * sizeof(double);
+}
+
+void launch_b_sf_mfma(hipStream_t st, int m, int mchunks, int mtiles, const int* sc_nx,
+                      const int* sc_ny, const int* tile_nb, int ncolsort, const double* xyz,
+                      const double* q, double Lx, double Ly, double Lz, int nxm, int nym,
+                      int npadc, double* part, double* mz_part) {
+  const int chunk_size = (m + mchunks - 1) / mchunks;
+  dim3 grid(2 * mtiles, mchunks), block(256);
+  hipLaunchKernelGGL(k_sf_mfma, grid, block, sf_mfma_lds(nxm, nym), st, m, chunk_size, mtiles,
+                     sc_nx, sc_ny, tile_nb, ncolsort, xyz, q, Lx, Ly, Lz, nxm, nym, npadc, part,
+                     mz_part);
+}
+
+// Sum the chunks of the matrix-core structure factors and scatter them to
+// the flat k order: thread per (sorted column, n >= 0); sfw = 2W S.
+__global__ void k_sf_mfma_reduce(int ncolsort, int mtiles, int mchunks, int npadc,
+                                 const int* __restrict__ sc_lo, const int* __restrict__ sc_len,
+                                 const int* __restrict__ sc_koff, const int* __restrict__ sc_n0,
+                                 const double* __restrict__ part, const double* __restrict__ w2,
+                                 double* __restrict__ sfw, const int* __restrict__ n_index) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_index[ncolsort]) return;
+  // binary search of the column owning entry e
+  int lo = 0, hi = ncolsort;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (n_index[mid] <= e) lo = mid; else hi = mid;
+  }
+  const int c = lo, n = e - n_index[c] + sc_n0[c];
+  const int mt = c >> 5, cl = c & 31;
+  double pr = 0, qr = 0, pi = 0, qi = 0;
+  for (int ch = 0; ch < mchunks; ++ch) {
+    const double* base = part + ((size_t)ch * mtiles + mt) * 64 * (size_t)npadc;
+    pr += base[(size_t)(2 * cl) * npadc + 2 * n];
+    qr += base[(size_t)(2 * cl) * npadc + 2 * n + 1];
+    pi += base[(size_t)(2 * cl + 1) * npadc + 2 * n];
+    qi += base[(size_t)(2 * cl + 1) * npadc + 2 * n + 1];
+  }
+  const int clo = sc_lo[c], chi = sc_lo[c] + sc_len[c] - 1;
+  if (n >= clo && n <= chi) {
+    const int k = sc_koff[c] + (n - clo);
+    sfw[2 * k] = w2[k] * (pr - qi);
+    sfw[2 * k + 1] = w2[k] * (pi + qr);
+  }
+  if (n > 0 && -n >= clo && -n <= chi) {
+    const int k = sc_koff[c] + (-n - clo);
+    sfw[2 * k] = w2[k] * (pr + qi);
+    sfw[2 * k + 1] = w2[k] * (pi - qr);
+  }
+}
+
+void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int mtiles, int mchunks, int npadc,
+                             const int* sc_lo, const int* sc_len, const int* sc_koff,
+                             const int* sc_n0, const int* n_index, int n_total,
+                             const double* part, const double* w2, double* sfw) {
+  hipLaunchKernelGGL(k_sf_mfma_reduce, dim3((n_total + 255) / 256), dim3(256), 0, st, ncolsort,
+                     mtiles, mchunks, npadc, sc_lo, sc_len, sc_koff, sc_n0, part, w2, sfw,
+                     n_index);
+}
+
 // sfw[k] = 2 W(k) * sum_chunks part[chunk][k]   (fixed chunk order)
 __global__ void k_sf_reduce(int nk, int mchunks, const double* __restrict__ part,
                             const double* __restrict__ w2, double* __restrict__ sfw) {
@@ -274,6 +494,94 @@ void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const
     hipLaunchKernelGGL(k_kspace_project<double>, grid, block, 0, st, n, cols, chunk_col, b.efx,
                        b.efy, b.efz, sfw, part);
 }
+
+// ---------------------------------------------------------------------------
+// k-space potential for electrodes made of a few planes of equal z (planar
+// electrodes).  With theta = k_x x + k_y y the k-space sum factorises exactly:
+//   phi_i = sum_cols Re[ e^{-i theta_c(R_i)} T(c, z_i) ],
+//   T(c, z) = sum_{k_z in c} 2W(k) S(k) e^{-i k_z z},
+// so T is formed once per (column, plane) and the per-atom work drops from
+// |K+| to the number of columns.
+// ---------------------------------------------------------------------------
+// One wave per column: lanes take k_z values, each phase e^{-i k_z z_L} is
+// computed exactly (sincospi), and a fixed-order wave reduction forms
+// T(c, L) for every plane L.
+__global__ void __launch_bounds__(64) k_layer_sum(int ncols, int nlayers,
+                                                  const KCol* __restrict__ cols,
+                                                  const double* __restrict__ layer_fz,
+                                                  const double* __restrict__ sfw,
+                                                  double2* __restrict__ T) {
+  const int c = blockIdx.x, lane = threadIdx.x;
+  const KCol col = cols[c];
+  for (int L = 0; L < nlayers; ++L) {
+    const double fz = layer_fz[L];
+    double tr = 0.0, ti = 0.0;
+    for (int r = lane; r < col.len; r += 64) {
+      double th = (col.lo + r) * fz;
+      th -= rint(th);
+      double sn, cs;
+      sincospi(2.0 * th, &sn, &cs);
+      const double wr = sfw[2 * (col.koff + r)], wi = sfw[2 * (col.koff + r) + 1];
+      // e^{-i k_z z} * (wr + i wi)
+      tr += cs * wr + sn * wi;
+      ti += cs * wi - sn * wr;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      tr += __shfl_xor(tr, o, 64);
+      ti += __shfl_xor(ti, o, 64);
+    }
+    if (lane == 0) T[(size_t)c * nlayers + L] = make_double2(tr, ti);
+  }
+}
+
+constexpr int LP_COLS = 32;           // columns per projection chunk (layer path)
+
+__global__ void __launch_bounds__(64) k_layer_project(int n, int ncols, int nlayers,
+                                                      const KCol* __restrict__ cols,
+                                                      const int* __restrict__ layer_of,
+                                                      const double* __restrict__ fx,
+                                                      const double* __restrict__ fy,
+                                                      const double2* __restrict__ T,
+                                                      double* __restrict__ part) {
+  __shared__ int s_nx[LP_COLS], s_ny[LP_COLS];
+  __shared__ double2 s_T[LP_COLS * MAX_LAYERS];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int chunk = blockIdx.y;
+  const int c0 = chunk * LP_COLS, c1 = min(ncols, c0 + LP_COLS);
+  for (int t = threadIdx.x; t < c1 - c0; t += blockDim.x) {
+    s_nx[t] = cols[c0 + t].nx;
+    s_ny[t] = cols[c0 + t].ny;
+  }
+  for (int t = threadIdx.x; t < (c1 - c0) * nlayers; t += blockDim.x)
+    s_T[t] = T[(size_t)c0 * nlayers + t];
+  __syncthreads();
+  if (i >= n) return;
+  const double ax = fx[i], ay = fy[i];
+  const int L = layer_of[i];
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int c = 0; c < c1 - c0; ++c) {
+    double th = s_nx[c] * ax + s_ny[c] * ay;
+    th -= rint(th);
+    double sn, cs;
+    sincospi(2.0 * th, &sn, &cs);
+    const double2 t = s_T[c * nlayers + L];
+    acc0 += cs * t.x;
+    acc1 += sn * t.y;
+  }
+  part[(size_t)chunk * n + i] = acc0 + acc1;
+}
+
+void launch_b_layer_project(hipStream_t st, int n, int ncols, int nlayers, const KCol* cols,
+                            const int* layer_of, const double* layer_fz, const Buffers& b,
+                            const double* sfw, double2* T, double* part) {
+  hipLaunchKernelGGL(k_layer_sum, dim3(ncols), dim3(64), 0, st, ncols, nlayers, cols, layer_fz,
+                     sfw, T);
+  dim3 grid((n + 63) / 64, (ncols + LP_COLS - 1) / LP_COLS), block(64);
+  hipLaunchKernelGGL(k_layer_project, grid, block, 0, st, n, ncols, nlayers, cols, layer_of,
+                     b.efx, b.efy, T, part);
+}
+
+int layer_project_chunks(int ncols) { return (ncols + LP_COLS - 1) / LP_COLS; }
 
 // ---------------------------------------------------------------------------
 // Real-space pair sum: one thread per electrode atom, electrolyte tiles in LDS.

@@ -170,10 +170,17 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   const int atom_blocks = (c->n + 255) / 256;
   c->rchunks = std::max(1, std::min((512 + atom_blocks - 1) / atom_blocks, std::max(1, c->m / 32)));
   TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
+  if (c->sf_mfma) {
+    const int wg_per_chunk = 2 * c->sfm_tiles;
+    c->sfm_chunks = std::max(1, std::min((c->sf_wg_target + wg_per_chunk - 1) / wg_per_chunk,
+                                         std::max(1, c->m / 64)));
+    TRY(dalloc(c, &b.sfm_part, (size_t)c->sfm_chunks * c->sfm_tiles * 64 * c->sfm_npadc));
+  }
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
-  TRY(dalloc(c, &b.phik_part, (size_t)c->n * c->kchunks));
+  const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
+  TRY(dalloc(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
   TRY(dalloc(c, &b.phir_part, (size_t)c->n * c->rchunks));
-  TRY(dalloc(c, &b.mz, (size_t)c->mchunks));
+  TRY(dalloc(c, &b.mz, (size_t)std::max(c->mchunks, c->sfm_chunks)));
   return CPM_OK;
 }
 
@@ -210,6 +217,16 @@ cpm_status ensure_uploaded(cpm_ctx* c) {
     TRY(dalloc(c, &b.kny, c->h_ky.size()));
     TRY(dalloc(c, &b.knz, c->h_kz.size()));
     TRY(dalloc(c, &b.cols, c->h_cols.size()));
+    if (c->sf_mfma) {
+      auto up = [&](int** dst, const std::vector<int>& v) -> cpm_status {
+        TRY(dalloc(c, dst, v.size()));
+        HIP_TRY(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(int), hipMemcpyHostToDevice));
+        return CPM_OK;
+      };
+      TRY(up(&b.sc_nx, c->h_sc_nx)); TRY(up(&b.sc_ny, c->h_sc_ny)); TRY(up(&b.sc_lo, c->h_sc_lo));
+      TRY(up(&b.sc_len, c->h_sc_len)); TRY(up(&b.sc_koff, c->h_sc_koff)); TRY(up(&b.sc_n0, c->h_sc_n0));
+      TRY(up(&b.sc_nidx, c->h_sc_nidx)); TRY(up(&b.tile_nb, c->h_tile_nb));
+    }
     TRY(dalloc(c, &b.chunk_col, c->h_chunk_col.size()));
     TRY(dalloc(c, &b.flag, 4));
     TRY(dalloc(c, &b.scal, 8));
@@ -266,6 +283,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   c->Lz = p.slab_factor * p.h;
   c->V = p.Lx * p.Ly * c->Lz;
   if (const char* ev = std::getenv("CPM_SF_WG_TARGET")) c->sf_wg_target = std::max(64, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
 
@@ -300,6 +318,44 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   }
   c->h_chunk_col.push_back((int)c->h_cols.size());
   c->kchunks = (int)c->h_chunk_col.size() - 1;
+  // matrix-core structure factors: whole columns, sorted by k_z extent e = max |n|
+  {
+    struct FC { int nx, ny, lo, len, koff, e; };
+    std::vector<FC> fc;
+    for (const KRun& r : c->h_runs) {
+      if (!fc.empty() && fc.back().nx == r.nx && fc.back().ny == r.ny &&
+          fc.back().lo + fc.back().len == r.nz0) {
+        fc.back().len += r.len;
+      } else {
+        fc.push_back(FC{r.nx, r.ny, r.nz0, r.len, r.koff, 0});
+      }
+    }
+    int emax = 0;
+    for (FC& f : fc) {
+      f.e = std::max(std::abs(f.lo), std::abs(f.lo + f.len - 1));
+      emax = std::max(emax, f.e);
+    }
+    std::stable_sort(fc.begin(), fc.end(), [](const FC& a, const FC& b) { return a.e > b.e; });
+    c->ncolsort = (int)fc.size();
+    c->sfm_tiles = (c->ncolsort + 31) / 32;
+    int nbmax = 0;
+    c->h_sc_nidx.push_back(0);
+    for (int k = 0; k < c->ncolsort; ++k) {
+      const FC& f = fc[k];
+      c->h_sc_nx.push_back(f.nx); c->h_sc_ny.push_back(f.ny); c->h_sc_lo.push_back(f.lo);
+      c->h_sc_len.push_back(f.len); c->h_sc_koff.push_back(f.koff); c->h_sc_n0.push_back(0);
+      c->h_sc_nidx.push_back(c->h_sc_nidx.back() + f.e + 1);
+      if (k % 32 == 0) {
+        const int nb = (2 * (f.e + 1) + 15) / 16;   // first column of a tile has its largest extent
+        c->h_tile_nb.push_back(nb);
+        nbmax = std::max(nbmax, nb);
+      }
+    }
+    c->sfm_ntot = c->h_sc_nidx.back();
+    c->sfm_npadc = 16 * nbmax;
+    c->sf_mfma = nbmax <= 12;                  // two halves of <= 6 blocks each
+    (void)emax;
+  }
   *out = c;
   return CPM_OK;
 }
@@ -345,7 +401,16 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   }
   if (c->Lz - (zmax - zmin) <= c->p.rcut)
     return fail(c, CPM_EINVAL, "electrode z extent %g leaves no slab clearance in Lz = %g", zmax - zmin, c->Lz);
+  // planar electrodes: atoms sharing an exact z value form a plane
+  std::vector<double> zs;
+  for (int i = 0; i < n; ++i) zs.push_back(c->h_xyz[3 * i + 2]);
+  std::sort(zs.begin(), zs.end());
+  zs.erase(std::unique(zs.begin(), zs.end()), zs.end());
+  const int nlayers = (int)zs.size() <= MAX_LAYERS ? (int)zs.size() : 0;
+  if (c->have_A && (nlayers != c->nlayers))
+    return fail(c, CPM_EINVAL, "rebuild changes the electrode plane structure; create a new context");
   c->have_A = c->have_inv = c->have_v = false;
+  c->nlayers = nlayers;
   c->n = n;
   c->n_e = n_e;
   c->npad = ((n + TILE - 1) / TILE) * TILE;
@@ -355,6 +420,18 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   TRY(dalloc(c, &b.efx, n)); TRY(dalloc(c, &b.efy, n)); TRY(dalloc(c, &b.efz, n));
   TRY(dalloc(c, &b.eid, n));
   TRY(dalloc(c, &b.A, (size_t)npad * npad));
+  if (c->nlayers > 0) {
+    std::vector<int> lay(n);
+    std::vector<double> lfz(c->nlayers);
+    for (int L = 0; L < c->nlayers; ++L) lfz[L] = zs[L] / c->Lz;
+    for (int i = 0; i < n; ++i)
+      lay[i] = (int)(std::lower_bound(zs.begin(), zs.end(), c->h_xyz[3 * i + 2]) - zs.begin());
+    TRY(dalloc(c, &b.layer_of, n));
+    TRY(dalloc(c, &b.layer_fz, c->nlayers));
+    TRY(dalloc(c, &b.layerT, c->h_cols.size() * (size_t)c->nlayers));
+    HIP_TRY(c, hipMemcpy(b.layer_of, lay.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.layer_fz, lfz.data(), c->nlayers * sizeof(double), hipMemcpyHostToDevice));
+  }
   HIP_TRY(c, hipMemcpyAsync(b.eid, d_eid, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
   const cpm_params& p = c->p;
   launch_prep_electrodes(c->stream, n, d_xyz, p.Lx, p.Ly, c->Lz, b);
@@ -512,19 +589,43 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
       HIP_TRY(c, hipMemsetAsync(out, 0, n * esz, st));
       continue;
     }
-    { Timed t(c, "structure_factor");
-      launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz, b.elq,
-                                p.Lx, p.Ly, c->Lz, c->nxm, c->nym, c->nzm, b.sf_part, b.mz); }
-    { Timed t(c, "sf_reduce");
-      launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
-    { Timed t(c, "kspace_project");
+    // FP64 structure factors on matrix cores when the k set fits the kernel;
+    // both structure-factor kernels also leave the electrolyte dipole partials
+    const bool mfma = c->sf_mfma && !b_is_f32 && c->use_sf_mfma;
+    const int mz_parts = mfma ? c->sfm_chunks : c->mchunks;
+    if (mfma) {
+      { Timed t(c, "structure_factor");
+        launch_b_sf_mfma(st, m, c->sfm_chunks, c->sfm_tiles, b.sc_nx, b.sc_ny, b.tile_nb,
+                         c->ncolsort, xyz, b.elq, p.Lx, p.Ly, c->Lz, c->nxm, c->nym,
+                         c->sfm_npadc, b.sfm_part, b.mz); }
+      { Timed t(c, "sf_reduce");
+        launch_b_sf_mfma_reduce(st, c->ncolsort, c->sfm_tiles, c->sfm_chunks, c->sfm_npadc,
+                                b.sc_lo, b.sc_len, b.sc_koff, b.sc_n0, b.sc_nidx, c->sfm_ntot,
+                                b.sfm_part, b.w2, b.sfw); }
+    } else {
+      { Timed t(c, "structure_factor");
+        launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz,
+                                  b.elq, p.Lx, p.Ly, c->Lz, c->nxm, c->nym, c->nzm, b.sf_part,
+                                  b.mz); }
+      { Timed t(c, "sf_reduce");
+        launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
+    }
+    int kparts = c->kchunks;
+    if (c->nlayers > 0) {
+      Timed t(c, "kspace_project");
+      launch_b_layer_project(st, n, (int)c->h_cols.size(), c->nlayers, b.cols, b.layer_of,
+                             b.layer_fz, b, b.sfw, b.layerT, b.phik_part);
+      kparts = layer_project_chunks((int)c->h_cols.size());
+    } else {
+      Timed t(c, "kspace_project");
       launch_b_kspace_project(st, b_is_f32, n, c->kchunks, b.cols, b.chunk_col, b, b.sfw,
-                              b.phik_part); }
+                              b.phik_part);
+    }
     { Timed t(c, "real_space_b");
       launch_b_real_space(st, n, m, c->rchunks, b, xyz, b.elq, p.Lx, p.Ly, p.rcut, p.alpha, p.eta,
                           b.phir_part); }
     { Timed t(c, "combine");
-      launch_b_combine(st, n, c->kchunks, c->rchunks, c->mchunks, b.phik_part, b.phir_part, b, b.mz,
+      launch_b_combine(st, n, kparts, c->rchunks, mz_parts, b.phik_part, b.phir_part, b, b.mz,
                        4.0 * M_PI / c->V, c->ke, out, b_is_f32); }
     TRY(launched(c, "potential_vector"));
   }
@@ -543,11 +644,10 @@ cpm_status cpm_solve_charges(cpm_ctx* c, int batch, const void* d_b, int b_is_f3
   if (prec == 1 && !(c->store & CPM_STORE_F32)) return fail(c, CPM_EINVAL, "FP32 copy of S not kept");
   if (prec == 2 && !(c->store & CPM_STORE_BF16X2))
     return fail(c, CPM_EINVAL, "split-BF16 copy of S not kept");
-  if (prec == 2 && batch < GEMM_MIN_BATCH)
-    return fail(c, CPM_EUNSUPPORTED, "split-BF16 solves run as a batched GEMM (batch >= %d)",
-                GEMM_MIN_BATCH);
   const int n = c->n, npad = c->npad;
-  const bool gemm = batch >= GEMM_MIN_BATCH && prec != 1;
+  // split-BF16 always runs on matrix cores (rows padded to 64); FP64 from
+  // GEMM_MIN_BATCH vectors on; FP32 streams S32 per vector
+  const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
   const int rows = gemm ? ((batch + TILE - 1) / TILE) * TILE : batch;
   TRY(ensure_solve_buffers(c, rows));
   Buffers& b = c->b;
@@ -690,6 +790,8 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_WORKSPACE: *out = (double)c->bytes; return CPM_OK;
     case CPM_INFO_NPAD: *out = c->npad; return CPM_OK;
     case CPM_INFO_NRUNS: *out = c->nruns; return CPM_OK;
+    case CPM_INFO_NLAYERS: *out = c->nlayers; return CPM_OK;
+    case CPM_INFO_SF_MATRIX: *out = (c->sf_mfma && c->use_sf_mfma) ? 1.0 : 0.0; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -710,6 +812,9 @@ void cpm_destroy(cpm_ctx* c) {
   if (!c) return;
   Buffers& b = c->b;
   dfree(b.ex); dfree(b.ey); dfree(b.ez); dfree(b.efx); dfree(b.efy); dfree(b.efz); dfree(b.eid);
+  dfree(b.layer_of); dfree(b.layer_fz); dfree(b.layerT);
+  dfree(b.sc_nx); dfree(b.sc_ny); dfree(b.sc_lo); dfree(b.sc_len); dfree(b.sc_koff); dfree(b.sc_n0);
+  dfree(b.sc_nidx); dfree(b.tile_nb); dfree(b.sfm_part);
   dfree(b.runs); dfree(b.cols); dfree(b.chunk_col); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);

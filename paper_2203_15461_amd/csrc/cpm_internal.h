@@ -34,16 +34,24 @@ struct KCol {
 };
 
 constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
+constexpr int MAX_LAYERS = 64;     // planar-electrode factorisation up to this many z planes
 
 struct Buffers {
   // electrode geometry (internal order = caller order), SoA, x and y wrapped
   double* ex = nullptr;  double* ey = nullptr;  double* ez = nullptr;
   double* efx = nullptr; double* efy = nullptr; double* efz = nullptr;  // fractional
   int* eid = nullptr;
+  int* layer_of = nullptr;         // plane index per atom (planar electrodes)
+  double* layer_fz = nullptr;      // fractional z of each plane
+  double2* layerT = nullptr;       // T(column, plane)
   // k-set
   KRun* runs = nullptr;            // nruns
   KCol* cols = nullptr;            // ncols
   int* chunk_col = nullptr;        // kchunks + 1 column boundaries of the projection chunks
+  // matrix-core structure factors: full (k_x, k_y) columns sorted by k_z extent
+  int* sc_nx = nullptr; int* sc_ny = nullptr; int* sc_lo = nullptr; int* sc_len = nullptr;
+  int* sc_koff = nullptr; int* sc_n0 = nullptr; int* sc_nidx = nullptr; int* tile_nb = nullptr;
+  double* sfm_part = nullptr;      // chunk partials [chunk][tile][64][npadc]
   double* w2 = nullptr;            // 2 W(k), nk (flat run order)
   int* knx = nullptr; int* kny = nullptr; int* knz = nullptr;     // nk
   // dense matrices, npad x npad row-major FP64 unless noted
@@ -100,6 +108,11 @@ struct cpm_ctx {
   std::vector<cpm::KCol> h_cols;
   std::vector<int> h_chunk_col;
   int nxm = 0, nym = 0, nzm = 0;   // largest |n| per axis in the k set
+  int nlayers = 0;                 // > 0: electrodes lie on this many z planes (factorised projection)
+  bool sf_mfma = false;            // structure factors on FP64 matrix cores (k set fits)
+  bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
+  int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_chunks = 1, sfm_ntot = 0;
+  std::vector<int> h_sc_nx, h_sc_ny, h_sc_lo, h_sc_len, h_sc_koff, h_sc_n0, h_sc_nidx, h_tile_nb;
   std::vector<double> h_w2;
   std::vector<int> h_kx, h_ky, h_kz;
   cpm::Buffers b;
@@ -169,11 +182,24 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
                                int m, int mchunks, const double* xyz, const double* q,
                                double Lx, double Ly, double Lz, int nxm, int nym, int nzm,
                                double* part, double* mz_part);
+void launch_b_sf_mfma(hipStream_t st, int m, int mchunks, int mtiles, const int* sc_nx,
+                      const int* sc_ny, const int* tile_nb, int ncolsort, const double* xyz,
+                      const double* q, double Lx, double Ly, double Lz, int nxm, int nym,
+                      int npadc, double* part, double* mz_part);
+void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int mtiles, int mchunks, int npadc,
+                             const int* sc_lo, const int* sc_len, const int* sc_koff,
+                             const int* sc_n0, const int* n_index, int n_total,
+                             const double* part, const double* w2, double* sfw);
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
                         const double* w2, double* sfw);
 void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const KCol* cols,
                              const int* chunk_col, const Buffers& b, const double* sfw,
                              double* part);
+// planar electrodes: T(column, plane) then phi per atom over columns
+void launch_b_layer_project(hipStream_t st, int n, int ncols, int nlayers, const KCol* cols,
+                            const int* layer_of, const double* layer_fz, const Buffers& b,
+                            const double* sfw, double2* T, double* part);
+int layer_project_chunks(int ncols);
 void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
                          const double* xyz, const double* q, double Lx, double Ly, double rc,
                          double alpha, double eta, double* part);

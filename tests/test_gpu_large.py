@@ -1,0 +1,107 @@
+"""The ~20k-atom capacitor (20064 electrode atoms, ~2e5 electrolyte charges)
+on the GPU.  The oracle cannot assemble a 20k x 20k matrix, so parity uses
+outputs it can compute one by one, and properties that hold at any size:
+
+* sampled elements A_ij against the oracle on the two-atom sub-problem
+  {R_i, R_j} in the same cell (A_ij depends on nothing else);
+* b for a small neutral electrolyte (60 waters) at the full electrode size and
+  full k set, sampled rows against the oracle;
+* q: sum q = 0 and A q - (b + v) uniform (the Lagrange potential), with the
+  device A that the sampled elements pinned.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpm_oracle as O
+from paper_2203_15461_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-large] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def big():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return I.scaled_graphite_capacitor(20000)
+
+
+def test_large_capacitor(big):
+    from paper_2203_15461_amd import cpm
+    w = big
+    n = w.n
+    say(f"n={n} m={w.m}: small-electrolyte context (60 waters)")
+    small_q = w.electrolyte_q[:180]
+    small_r = w.electrolyte_xyz[:180]
+    assert abs(small_q.sum()) < 1e-12
+    ws = w.with_(electrolyte_xyz=small_r, electrolyte_q=small_q)
+    ctx = cpm.setup(ws, store=cpm.STORE_F64 | cpm.STORE_BF16X2)
+    p = O.params_for(w)
+    assert int(ctx.info("nk")) == len(O.kvectors(p)[2])
+
+    A = ctx.copy_matrix(0, torch.empty((n, n), dtype=torch.float64, device="cuda"))
+    pairs = [(0, 0), (0, 1), (0, 5003), (123, 19999), (10030, 10031), (20063, 20063),
+             (7777, 2222), (15000, 4999)]
+    for i, j in pairs:
+        sub = O.elastance(w.electrode_xyz[[i, j]] if i != j else w.electrode_xyz[[i]], p)
+        ref = sub[0, 1] if i != j else sub[0, 0]
+        got = float(A[i, j].item())
+        assert abs(got - ref) <= 1e-11 * abs(O.elastance(w.electrode_xyz[[0]], p)[0, 0]), (i, j, got, ref)
+    assert torch.equal(A, A.T)
+    say("  sampled A elements match")
+
+    xyz = torch.as_tensor(small_r[None], dtype=torch.float64, device="cuda").contiguous()
+    b = torch.empty((1, n), dtype=torch.float64, device="cuda")
+    ctx.potential_vector(xyz, b)
+    rows = np.array([0, 1, 4000, 10031, 16000, 20063])
+    bo = O.potential_vector(w.electrode_xyz, small_r, small_q, p, rows=rows)
+    bg = b.cpu().numpy()[0][rows]
+    assert np.max(np.abs(bg - bo)) <= 1e-10 * np.max(np.abs(bo))
+    say("  sampled b rows match")
+
+    for mode, tol in ((0x000, 1e-10), (0x102, 1e-5)):
+        q = torch.empty((1, n), dtype=torch.float64, device="cuda")
+        ctx.solve_charges(b, mode, q)
+        ctx.synchronize()
+        v = torch.as_tensor(O.applied_potential(w.electrode_id, w.v_electrode), device="cuda")
+        res = torch.mv(A, q[0]) - (b[0] + v)
+        spread = float((res - res.mean()).abs().max().item())
+        scale = float((b[0] + v).abs().max().item())
+        say(f"  mode {mode:#x}: residual spread {spread / scale:.2e}, sum q {float(q.sum()):.1e}")
+        assert abs(float(q.sum().item())) <= 1e-12
+        assert spread <= tol * scale
+    ctx.close()
+
+
+def test_large_capacitor_full_electrolyte(big):
+    """The full ~2e5-charge electrolyte: batched split-BF16 + refinement, 4
+    snapshots; neutral charges and a uniform residual against the device A."""
+    from paper_2203_15461_amd import cpm
+    w = big
+    n = w.n
+    say(f"full electrolyte m={w.m}")
+    ctx = cpm.setup(w, store=cpm.STORE_F64 | cpm.STORE_BF16X2)
+    A = ctx.copy_matrix(0, torch.empty((n, n), dtype=torch.float64, device="cuda"))
+    xyz = torch.as_tensor(np.stack([I.snapshot(w, s) for s in range(4)]), device="cuda").contiguous()
+    b = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    ctx.potential_vector(xyz, b)
+    q = torch.empty((4, n), dtype=torch.float64, device="cuda")
+    Qe = torch.empty((4, 2), dtype=torch.float64, device="cuda")
+    ctx.solve_charges(b, 0x102, q, Qe)
+    ctx.synchronize()
+    v = torch.as_tensor(O.applied_potential(w.electrode_id, w.v_electrode), device="cuda")
+    for s in range(4):
+        res = torch.mv(A, q[s]) - (b[s] + v)
+        spread = float((res - res.mean()).abs().max().item()) / float((b[s] + v).abs().max().item())
+        assert spread <= 1e-5, spread
+        assert abs(float(q[s].sum().item())) <= 1e-12
+        assert abs(float(Qe[s].sum().item())) <= 1e-12
+    say(f"  Q = {Qe.cpu().numpy()[0]}")
+    ctx.close()

@@ -295,3 +295,47 @@ def test_kernel_timing(cpm):
         assert cnt >= 1 and ms > 0, fam
     assert ctx.timing("no_such_kernel") == (0.0, 0)
     ctx.close()
+
+
+def test_general_projection_path(cpm):
+    """Electrode atoms whose z values all differ (tiny jitter) take the
+    general per-atom k-space projection instead of the planar factorisation;
+    both agree with the oracle."""
+    w = I.small_capacitor("a")
+    ctx = cpm.setup(w)
+    assert int(ctx.info("nlayers")) == 2
+    ctx.close()
+    rng = np.random.default_rng(7)
+    R = w.electrode_xyz.copy()
+    R[:, 2] += rng.uniform(-1e-3, 1e-3, len(R))
+    wj = w.with_(electrode_xyz=R, h=float(R[:, 2].max() - R[:, 2].min()))
+    say("general projection path (z jittered)")
+    g = run(cpm, wj, snaps=(0, 1))
+    ctx = cpm.setup(wj)
+    assert int(ctx.info("nlayers")) == 0
+    ctx.close()
+    o = oracle_of(wj, g["xyz"])
+    assert rel(g["b"], o["b"]) < 1e-10
+    assert rel(g["q"], o["q"]) < 1e-10
+
+
+def test_structure_factor_paths_agree(cpm, monkeypatch):
+    """FP64 structure factors run on matrix cores by default; the VALU kernel
+    (CPM_SF_MFMA=0) gives the same b and q to FP64 rounding, and both match
+    the oracle."""
+    w = I.small_capacitor("b")
+    xyz = [I.snapshot(w, s) for s in (0, 1)]
+    say("structure factors: matrix cores vs VALU")
+    ctx = cpm.setup(w)
+    assert ctx.info("sf_matrix") == 1.0
+    ctx.close()
+    g1 = run(cpm, w, xyz_list=xyz)
+    monkeypatch.setenv("CPM_SF_MFMA", "0")
+    ctx = cpm.setup(w)
+    assert ctx.info("sf_matrix") == 0.0
+    ctx.close()
+    g0 = run(cpm, w, xyz_list=xyz)
+    o = oracle_of(w, xyz)
+    assert rel(g1["b"], o["b"]) < 1e-10 and rel(g0["b"], o["b"]) < 1e-10
+    assert rel(g1["b"], g0["b"]) < 1e-12
+    assert rel(g1["q"], o["q"]) < 1e-10
