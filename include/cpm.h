@@ -155,6 +155,25 @@ cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
 cpm_status cpm_solve_charges(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32,
                              unsigned mode, double* d_q, double* d_Qe);
 
+/* Capture one batched step -- cpm_potential_vector for `batch`
+ * configurations followed by cpm_solve_charges -- for these exact buffers
+ * and mode into a HIP graph held by the context, replacing any earlier
+ * capture.  The context stream must not be the default stream.  Work
+ * buffers are allocated before capture; the graph holds kernel launches
+ * only.  Nothing runs until cpm_replay_step. */
+cpm_status cpm_capture_step(cpm_ctx* ctx, int batch, const double* d_xyz, void* d_b,
+                            int b_is_f32, unsigned mode, double* d_q, double* d_Qe);
+
+/* Launch the captured step on the context stream (asynchronous).  The caller
+ * refreshes d_xyz between replays (stream-ordered before the replay); the
+ * results land in the d_b, d_q, d_Qe given at capture.  cpm_set_potential
+ * and a same-size cpm_invert between replays are seen by the next replay.
+ * Returns CPM_ESTATE without launching if the context has allocated or
+ * freed device memory since the capture (an eager call with a larger batch,
+ * a rebuild) or no longer keeps the copy of S the captured mode reads:
+ * capture again in that case. */
+cpm_status cpm_replay_step(cpm_ctx* ctx);
+
 /* Copy a context matrix (n x n, row-major FP64) into caller memory d_out:
  * which = 0: A, 1: A^-1, 2: S.  Enqueued on the context stream. */
 cpm_status cpm_copy_matrix(const cpm_ctx* ctx, int which, double* d_out);

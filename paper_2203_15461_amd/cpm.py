@@ -26,7 +26,8 @@ INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, n
 
 EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
            "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",
-           "cpm_copy_vector", "cpm_get_info", "cpm_enable_timing", "cpm_get_timing",
+           "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_get_info",
+           "cpm_enable_timing", "cpm_get_timing",
            "cpm_synchronize", "cpm_last_error", "cpm_destroy")
 
 
@@ -66,6 +67,8 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_potential_vector": ([vp, i, vp, vp, i], i),
         "cpm_solve_charges": ([vp, i, vp, i, u, vp, vp], i),
         "cpm_copy_matrix": ([vp, i, vp], i),
+        "cpm_capture_step": ([vp, i, vp, vp, i, u, vp, vp], i),
+        "cpm_replay_step": ([vp], i),
         "cpm_copy_vector": ([vp, i, vp], i),
         "cpm_get_info": ([vp, i, ctypes.POINTER(d)], i),
         "cpm_enable_timing": ([vp, i], i),
@@ -230,6 +233,25 @@ class Context:
                                                 _ptr(Qe_out)), "cpm_solve_charges")
         return q_out
 
+    def capture_step(self, xyz, b, mode: int, q_out, Qe_out=None):
+        """Capture b for xyz (batch, m, 3) and the solve into a HIP graph."""
+        _expect(xyz, "float64", 3)
+        _expect(q_out, "float64", 2)
+        f32 = _is_f32(b)
+        n, m = int(self.info("n")), int(self.info("m"))
+        if tuple(xyz.shape[1:]) != (m, 3) or tuple(b.shape) != (xyz.shape[0], n) \
+                or tuple(q_out.shape) != (xyz.shape[0], n):
+            raise ValueError("capture_step: shapes do not match (batch, m, 3), (batch, n)")
+        if Qe_out is not None:
+            _expect(Qe_out, "float64", 2)
+            if tuple(Qe_out.shape) != (xyz.shape[0], int(self.info("ne"))):
+                raise ValueError("capture_step: Qe must be (batch, n_e)")
+        self._check(self._lib.cpm_capture_step(self._h, xyz.shape[0], _ptr(xyz), _ptr(b), f32, mode,
+                                               _ptr(q_out), _ptr(Qe_out)), "cpm_capture_step")
+
+    def replay_step(self):
+        self._check(self._lib.cpm_replay_step(self._h), "cpm_replay_step")
+
     def copy_matrix(self, which: int, out):
         """which 0: A, 1: A^-1, 2: S into an (n, n) float64 tensor."""
         _expect(out, "float64", 2)
@@ -275,6 +297,8 @@ def setup(w, store: int = STORE_F64, stream=None, params: Params | None = None,
     ctx.set_electrolyte(w.electrolyte_q)
     xyz = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device="cuda").contiguous()
     eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device="cuda").contiguous()
+    if stream is not None:      # the copies above ran on torch's current stream
+        torch.cuda.current_stream().synchronize()
     ctx.build_elastance(xyz, eid, int(w.electrode_id.max()) + 1)
     ctx.invert(store)
     ctx.set_potential(w.v_electrode if v_electrode is None else v_electrode)

@@ -193,16 +193,32 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
 // so with rows (Re C_c, Im C_c) and columns (Zr_n, Zi_n) one real GEMM over
 // the charges gives Pr, Qr, Pi, Qi and both S(c, n) = (Pr - Qi) + i (Pi + Qr)
 // and S(c, -n) = (Pr + Qi) + i (Pi - Qr).  Columns are sorted by their k_z
-// extent and grouped 32 per M tile (64 rows); each workgroup takes one M tile,
-// one half of its n range and one chunk of the electrolyte.  Per LDS tile of
-// 16 charges it builds the phase tables (segments of exact sincospi plus FP64
-// rotations), the A operand C_cj and runs v_mfma_f64_16x16x4f64 with the
-// Z table as the B operand.  Wave w owns rows 16w..16w+15.
-// part[((chunk * mtiles + mt) * 64 + row) * npadc + col]: this chunk's sums.
+// extent and grouped 16 per M tile (32 rows).  A workgroup takes one M tile,
+// one half of its n range and one chunk of the electrolyte; each of its waves
+// walks its own tiles of 16 charges (no workgroup barrier inside the loop):
+// it writes C for its charges and the first 8 phases e^{2 pi i n fz} of its
+// n range into a wave-private LDS area (exact FP64 sincospi), then runs
+// v_mfma_f64_16x16x4f64 with the B operand advanced in registers by
+// e^{2 pi i 8 fz} per 16-wide block.  The 4 waves are summed in a fixed order.
+// part[((chunk * mtiles + mt) * 32 + row) * npadc + col]: this chunk's sums.
 // ---------------------------------------------------------------------------
 typedef double v4d_t __attribute__((ext_vector_type(4)));
-constexpr int SFM_TJ = 16;             // charges per LDS tile (4 MFMA k-steps)
-constexpr int SFM_NB = 6;              // max 16-wide n blocks per workgroup (half a tile)
+constexpr int SFM_TJ = 16;             // charges per wave tile (4 MFMA k-steps)
+constexpr int SFM_NB = 4;              // max 16-wide n blocks per workgroup (a third of a tile)
+constexpr int SFM_SPLIT = 3;           // workgroups per M tile along n
+constexpr int SFM_COLS = 16;           // columns per M tile (32 GEMM rows)
+
+struct SfmWave {                        // wave-private LDS area
+  double C[2 * SFM_COLS][SFM_TJ + 1];  // A operand rows (Re C, Im C) x charges
+  double2 z0[SFM_TJ][8];               // e^{2 pi i (n_lo + j) fz_t}, j = 0..7
+  double2 r8[SFM_TJ];                  // e^{2 pi i 8 fz_t}
+};
+
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __global__ void __launch_bounds__(256) k_sf_mfma(int m, int chunk_size, int mtiles,
                                                  const int* __restrict__ sc_nx,
@@ -210,129 +226,130 @@ __global__ void __launch_bounds__(256) k_sf_mfma(int m, int chunk_size, int mtil
                                                  const int* __restrict__ tile_nb, int ncolsort,
                                                  const double* __restrict__ xyz,
                                                  const double* __restrict__ q, double Lx,
-                                                 double Ly, double Lz, int nxm, int nym,
-                                                 int npadc, double* __restrict__ part,
+                                                 double Ly, double Lz, int npadc,
+                                                 double* __restrict__ part,
                                                  double* __restrict__ mz_part) {
-  __shared__ double s_f[3][SFM_TJ], s_q[SFM_TJ];
+  __shared__ SfmWave wl[4];
+  __shared__ double red[64 * 2 * SFM_NB * 4];      // one wave's accumulators
+  __shared__ int s_nx[SFM_COLS], s_ny[SFM_COLS];
   __shared__ double s_mz[4];
-  __shared__ double2 s_e1[3][SFM_TJ];
-  __shared__ int s_nx[32], s_ny[32];
-  __shared__ double A_l[64][SFM_TJ + 1];
-  extern __shared__ double dyn[];
-  const int TX = nxm + 1, TY = nym + 1;
-  double2* tx = reinterpret_cast<double2*>(dyn);              // [SFM_TJ][TX]
-  double2* ty = tx + SFM_TJ * TX;                              // [SFM_TJ][TY]
-  double* tzd = reinterpret_cast<double*>(ty + SFM_TJ * TY);   // [SFM_TJ][16 * SFM_NB]
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mt = blockIdx.x >> 1, half = blockIdx.x & 1;
+  const int mt = blockIdx.x / SFM_SPLIT, part_n = blockIdx.x % SFM_SPLIT;
   const int chunk = blockIdx.y;
-  const int nbt = tile_nb[mt];                     // n blocks of this M tile
-  const int nb_lo = half ? (nbt + 1) / 2 : 0;
-  const int nb_hi = half ? nbt : (nbt + 1) / 2;
+  const int nbt = tile_nb[mt];
+  const int nb_lo = (nbt * part_n) / SFM_SPLIT;
+  const int nb_hi = (nbt * (part_n + 1)) / SFM_SPLIT;
   const int nbw = nb_hi - nb_lo;                   // blocks of this workgroup (<= SFM_NB)
   const int n_lo = nb_lo * 8;                      // first complex n of this workgroup
-  const int c_base = mt * 32;
-  const int ncol = min(32, ncolsort - c_base);
-  if (tid < 32) {
+  const int c_base = mt * SFM_COLS;
+  const int ncol = min(SFM_COLS, ncolsort - c_base);
+  if (tid < SFM_COLS) {
     s_nx[tid] = tid < ncol ? sc_nx[c_base + tid] : 0;
     s_ny[tid] = tid < ncol ? sc_ny[c_base + tid] : 0;
   }
+  __syncthreads();
   const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
-  v4d_t acc[SFM_NB];
+  SfmWave& W = wl[wave];
+  v4d_t acc0[SFM_NB], acc1[SFM_NB];
 #pragma unroll
-  for (int b = 0; b < SFM_NB; ++b) acc[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+  for (int b = 0; b < SFM_NB; ++b) {
+    acc0[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+    acc1[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+  }
   double mz = 0.0;
-
-  for (int jt = j0; jt < j1; jt += SFM_TJ) {
+  const int t_l = lane & 15, g_l = lane >> 4;     // this lane's charge in the tile, lane group
+  for (int jt = j0 + wave * SFM_TJ; jt < j1; jt += 4 * SFM_TJ) {
     const int nt = min(SFM_TJ, j1 - jt);
-    __syncthreads();
-    if (tid < SFM_TJ) {
-      double fx = 0, fy = 0, fz = 0, qq = 0;
-      if (tid < nt) {
-        const int j = jt + tid;
-        fx = xyz[3 * j] / Lx;
-        fy = xyz[3 * j + 1] / Ly;
-        fz = xyz[3 * j + 2] / Lz;
-        fx -= floor(fx);
-        fy -= floor(fy);
-        qq = q[j];
-        if (blockIdx.x == 0) mz += qq * xyz[3 * j + 2];
-      }
-      s_f[0][tid] = fx; s_f[1][tid] = fy; s_f[2][tid] = fz; s_q[tid] = qq;
+    double fx = 0.0, fy = 0.0, fz = 0.0, qq = 0.0;
+    if (t_l < nt) {
+      const int j = jt + t_l;
+      fx = xyz[3 * j] / Lx;
+      fy = xyz[3 * j + 1] / Ly;
+      fz = xyz[3 * j + 2] / Lz;
+      fx -= floor(fx);
+      fy -= floor(fy);
+      qq = q[j];
+      if (blockIdx.x == 0 && g_l == 0) mz += qq * xyz[3 * j + 2];
     }
-    __syncthreads();
-    if (tid < 3 * SFM_TJ) {
-      const int ax = tid / SFM_TJ, t = tid - ax * SFM_TJ;
-      const double f = s_f[ax][t];
-      double sn, cs;
-      sincospi(2.0 * (f - rint(f)), &sn, &cs);
-      s_e1[ax][t] = make_double2(cs, sn);
-    }
-    __syncthreads();
-    // tables in segments of 8 entries: tx (q folded), ty, tz (this n range)
+    // A operand: C for columns g_l, g_l + 4, g_l + 8, g_l + 12 of charge t_l,
+    // and the first phases of the n range (j = 2 g_l, 2 g_l + 1); the seven
+    // independent sincospi are written out so their chains interleave
     {
-      const int sx = (TX + 7) / 8, sy = (TY + 7) / 8, sz = nbw;   // n range is 8 * nbw
-      const int nseg = sx + sy + sz;
-      for (int e = tid; e < SFM_TJ * nseg; e += 256) {
-        const int t = e / nseg, sg = e - t * nseg;
-        const int ax = sg < sx ? 0 : (sg < sx + sy ? 1 : 2);
-        const int s0 = sg - (ax == 0 ? 0 : (ax == 1 ? sx : sx + sy));
-        const int n0 = (ax == 2 ? n_lo : 0) + 8 * s0;
-        const int cnt = ax == 0 ? min(8, TX - 8 * s0) : (ax == 1 ? min(8, TY - 8 * s0) : 8);
-        double th = n0 * s_f[ax][t];
-        th -= rint(th);
-        double sn, cs;
-        sincospi(2.0 * th, &sn, &cs);
-        double2 v = make_double2(cs, sn);
-        const double2 e1 = s_e1[ax][t];
-        const double sc = ax == 0 ? s_q[t] : 1.0;
-        for (int u = 0; u < cnt; ++u) {
-          if (ax == 0) tx[t * TX + 8 * s0 + u] = make_double2(sc * v.x, sc * v.y);
-          else if (ax == 1) ty[t * TY + 8 * s0 + u] = v;
-          else {
-            const int col = 2 * (8 * s0 + u);
-            tzd[t * (16 * SFM_NB) + col] = v.x;
-            tzd[t * (16 * SFM_NB) + col + 1] = v.y;
-          }
-          v = cmul(v, e1);
+      double th[7];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) th[u] = s_nx[g_l + 4 * u] * fx + s_ny[g_l + 4 * u] * fy;
+      th[4] = (n_lo + 2 * g_l) * fz;
+      th[5] = (n_lo + 2 * g_l + 1) * fz;
+      th[6] = 8.0 * fz;
+      double sn[7], cs[7];
+#pragma unroll
+      for (int u = 0; u < 7; ++u) sincospi(2.0 * (th[u] - rint(th[u])), &sn[u], &cs[u]);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int cl = g_l + 4 * u;
+        const bool ok = cl < ncol;
+        W.C[2 * cl][t_l] = ok ? qq * cs[u] : 0.0;
+        W.C[2 * cl + 1][t_l] = ok ? qq * sn[u] : 0.0;
+      }
+      W.z0[t_l][2 * g_l] = make_double2(cs[4], sn[4]);
+      W.z0[t_l][2 * g_l + 1] = make_double2(cs[5], sn[5]);
+      if (g_l == 0) W.r8[t_l] = make_double2(cs[6], sn[6]);
+    }
+    wave_lds_sync();
+#pragma unroll 1
+    for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
+      const int kc = 4 * ks + g_l;                    // k index (charge) of this lane's operands
+      const double a0 = W.C[t_l][kc];                 // rows 0..15
+      const double a1 = W.C[16 + t_l][kc];            // rows 16..31
+      double2 z = W.z0[kc][t_l >> 1];
+      const double2 r8 = W.r8[kc];
+      const bool im = t_l & 1;
+#pragma unroll
+      for (int b = 0; b < SFM_NB; ++b) {
+        if (b < nbw) {
+          const double bv = im ? z.y : z.x;
+          acc0[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0[b], 0, 0, 0);
+          acc1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1[b], 0, 0, 0);
+          z = cmul(z, r8);
         }
       }
     }
+    wave_lds_sync();
+  }
+  // fixed-order sum of the waves' accumulators (3 + 2 + 1 into wave 0)
+  for (int src = 3; src >= 1; --src) {
     __syncthreads();
-    // A operand: rows (Re C, Im C) of the tile's 32 columns, one per charge
-    for (int e = tid; e < 32 * SFM_TJ; e += 256) {
-      const int cl = e / SFM_TJ, t = e - cl * SFM_TJ;
-      double2 cv = make_double2(0.0, 0.0);
-      if (cl < ncol) {
-        const int ny = s_ny[cl];
-        double2 y = ty[t * TY + abs(ny)];
-        if (ny < 0) y.y = -y.y;
-        cv = cmul(tx[t * TX + s_nx[cl]], y);      // zero for padding charges (q = 0)
-      }
-      A_l[2 * cl][t] = cv.x;
-      A_l[2 * cl + 1][t] = cv.y;
-    }
-    __syncthreads();
-    const int r16 = lane & 15, kq = lane >> 4;
-#pragma unroll
-    for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
-      const double a = A_l[16 * wave + r16][4 * ks + kq];
-      const double* brow = tzd + (4 * ks + kq) * (16 * SFM_NB);
+    if (wave == src)
 #pragma unroll
       for (int b = 0; b < SFM_NB; ++b)
-        if (b < nbw) acc[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, brow[16 * b + r16], acc[b], 0, 0, 0);
-    }
-  }
-  // result register r of lane l: row (l >> 4) + 4 r, column l & 15 of block b
-  double* out = part + ((size_t)chunk * mtiles + mt) * 64 * (size_t)npadc;
 #pragma unroll
-  for (int b = 0; b < SFM_NB; ++b) {
-    if (b >= nbw) continue;
-    for (int r = 0; r < 4; ++r) {
-      const int row = 16 * wave + (lane >> 4) + 4 * r;
-      const int col = 16 * (nb_lo + b) + (lane & 15);
-      out[(size_t)row * npadc + col] = acc[b][r];
+        for (int r = 0; r < 4; ++r) {
+          red[((0 * SFM_NB + b) * 4 + r) * 64 + lane] = acc0[b][r];
+          red[((1 * SFM_NB + b) * 4 + r) * 64 + lane] = acc1[b][r];
+        }
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int b = 0; b < SFM_NB; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc0[b][r] += red[((0 * SFM_NB + b) * 4 + r) * 64 + lane];
+          acc1[b][r] += red[((1 * SFM_NB + b) * 4 + r) * 64 + lane];
+        }
+  }
+  if (wave == 0) {
+    // result register r of lane l: row (l >> 4) + 4 r, column l & 15 of block b
+    double* out = part + ((size_t)chunk * mtiles + mt) * 32 * (size_t)npadc;
+#pragma unroll
+    for (int b = 0; b < SFM_NB; ++b) {
+      if (b >= nbw) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = (lane >> 4) + 4 * r;
+        const int col = 16 * (nb_lo + b) + (lane & 15);
+        out[(size_t)row * npadc + col] = acc0[b][r];
+        out[(size_t)(16 + row) * npadc + col] = acc1[b][r];
+      }
     }
   }
   if (blockIdx.x == 0) {   // this chunk's electrolyte dipole sum_j q_j z_j
@@ -343,20 +360,15 @@ __global__ void __launch_bounds__(256) k_sf_mfma(int m, int chunk_size, int mtil
   }
 }
 
-size_t sf_mfma_lds(int nxm, int nym) {
-  return (size_t)SFM_TJ * ((nxm + 1) + (nym + 1)) * sizeof(double2) +
-         (size_t)SFM_TJ * 16 * SFM_NB * sizeof(double);
-}
-
 void launch_b_sf_mfma(hipStream_t st, int m, int mchunks, int mtiles, const int* sc_nx,
                       const int* sc_ny, const int* tile_nb, int ncolsort, const double* xyz,
                       const double* q, double Lx, double Ly, double Lz, int nxm, int nym,
                       int npadc, double* part, double* mz_part) {
+  (void)nxm; (void)nym;
   const int chunk_size = (m + mchunks - 1) / mchunks;
-  dim3 grid(2 * mtiles, mchunks), block(256);
-  hipLaunchKernelGGL(k_sf_mfma, grid, block, sf_mfma_lds(nxm, nym), st, m, chunk_size, mtiles,
-                     sc_nx, sc_ny, tile_nb, ncolsort, xyz, q, Lx, Ly, Lz, nxm, nym, npadc, part,
-                     mz_part);
+  dim3 grid(SFM_SPLIT * mtiles, mchunks), block(256);
+  hipLaunchKernelGGL(k_sf_mfma, grid, block, 0, st, m, chunk_size, mtiles, sc_nx, sc_ny, tile_nb,
+                     ncolsort, xyz, q, Lx, Ly, Lz, npadc, part, mz_part);
 }
 
 // Sum the chunks of the matrix-core structure factors and scatter them to
@@ -375,10 +387,11 @@ __global__ void k_sf_mfma_reduce(int ncolsort, int mtiles, int mchunks, int npad
     if (n_index[mid] <= e) lo = mid; else hi = mid;
   }
   const int c = lo, n = e - n_index[c] + sc_n0[c];
-  const int mt = c >> 5, cl = c & 31;
+  const int mt = c / SFM_COLS, cl = c % SFM_COLS;
   double pr = 0, qr = 0, pi = 0, qi = 0;
+#pragma unroll 4
   for (int ch = 0; ch < mchunks; ++ch) {
-    const double* base = part + ((size_t)ch * mtiles + mt) * 64 * (size_t)npadc;
+    const double* base = part + ((size_t)ch * mtiles + mt) * 32 * (size_t)npadc;
     pr += base[(size_t)(2 * cl) * npadc + 2 * n];
     qr += base[(size_t)(2 * cl) * npadc + 2 * n + 1];
     pi += base[(size_t)(2 * cl + 1) * npadc + 2 * n];
@@ -607,7 +620,10 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
                                                       double Ly, double rc, double alpha,
                                                       double eta, double* __restrict__ part) {
   __shared__ double s_x[RS_TILE], s_y[RS_TILE], s_z[RS_TILE], s_q[RS_TILE];
+  __shared__ double s_zr[2][4];
+  __shared__ int s_cnt[4];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int chunk = blockIdx.y;
   const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
   const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
@@ -615,21 +631,46 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
   const bool single = (Lx >= 2.0 * rc) && (Ly >= 2.0 * rc);
   double xi = 0, yi = 0, zi = 0;
   if (i < n) { xi = ex[i]; yi = ey[i]; zi = ez[i]; }
+  // z interval of this workgroup's atoms: charges farther than rc from it
+  // cannot contribute and are dropped when a tile is staged
+  double zlo = i < n ? zi : 1e300, zhi = i < n ? zi : -1e300;
+  for (int o = 32; o > 0; o >>= 1) {
+    zlo = fmin(zlo, __shfl_xor(zlo, o, 64));
+    zhi = fmax(zhi, __shfl_xor(zhi, o, 64));
+  }
+  if (lane == 0) { s_zr[0][wave] = zlo; s_zr[1][wave] = zhi; }
+  __syncthreads();
+  zlo = fmin(fmin(s_zr[0][0], s_zr[0][1]), fmin(s_zr[0][2], s_zr[0][3]));
+  zhi = fmax(fmax(s_zr[1][0], s_zr[1][1]), fmax(s_zr[1][2], s_zr[1][3]));
   double acc = 0.0;
   for (int jt = j0; jt < j1; jt += RS_TILE) {
     const int nt = min(RS_TILE, j1 - jt);
-    __syncthreads();
+    double x = 0, y = 0, z = 0, qq = 0;
+    bool keep = false;
     if ((int)threadIdx.x < nt) {
       const int j = jt + threadIdx.x;
-      double x = xyz[3 * j], y = xyz[3 * j + 1];
+      x = xyz[3 * j]; y = xyz[3 * j + 1]; z = xyz[3 * j + 2];
       x -= Lx * floor(x * invLx);
       y -= Ly * floor(y * invLy);
-      s_x[threadIdx.x] = x; s_y[threadIdx.x] = y; s_z[threadIdx.x] = xyz[3 * j + 2];
-      s_q[threadIdx.x] = q[j];
+      qq = q[j];
+      keep = (z > zlo - rc) && (z < zhi + rc);
+    }
+    // order-preserving compaction: ballot within the wave, wave offsets via LDS
+    const unsigned long long bal = __ballot(keep);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    __syncthreads();
+    if (lane == 0) s_cnt[wave] = __popcll(bal);
+    __syncthreads();
+    int off = 0;
+    for (int w2 = 0; w2 < wave; ++w2) off += s_cnt[w2];
+    const int kept = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    if (keep) {
+      s_x[off + before] = x; s_y[off + before] = y; s_z[off + before] = z;
+      s_q[off + before] = qq;
     }
     __syncthreads();
     if (i >= n) continue;
-    for (int t = 0; t < nt; ++t) {
+    for (int t = 0; t < kept; ++t) {
       const double dz = zi - s_z[t];
       if (fabs(dz) >= rc) continue;
       double dx = xi - s_x[t], dy = yi - s_y[t];
@@ -670,22 +711,32 @@ void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffer
                      Lx, Ly, rc, alpha, eta, part);
 }
 
-// b_i = -k_e (sum of k-space partials + sum of real-space partials + (4 pi/V) z_i M_z)
-__global__ void k_combine(int n, int kchunks, int rchunks, int mchunks,
-                          const double* __restrict__ phik, const double* __restrict__ phir,
-                          const double* __restrict__ ez, const double* __restrict__ mz_part,
-                          double slab_coef, double ke, void* out, int out_is_f32) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  // fixed-order sums; the loads are independent, so unrolling keeps many in flight
-  double pk = 0.0, pr = 0.0;
-#pragma unroll 8
-  for (int c = 0; c < kchunks; ++c) pk += phik[(size_t)c * n + i];
-#pragma unroll 8
-  for (int c = 0; c < rchunks; ++c) pr += phir[(size_t)c * n + i];
+// b_i = -k_e (sum of k-space partials + sum of real-space partials
+//            + (4 pi / V) z_i M_z), M_z from the structure-factor chunks.
+// Four lanes per atom sum interleaved partial rows; the four sums are added
+// in a fixed order.
+__global__ void __launch_bounds__(256) k_combine(int n, int kchunks, int rchunks, int mchunks,
+                                                 const double* __restrict__ phik,
+                                                 const double* __restrict__ phir,
+                                                 const double* __restrict__ ez,
+                                                 const double* __restrict__ mz_part,
+                                                 double slab_coef, double ke, void* out,
+                                                 int out_is_f32) {
+  __shared__ double sh[4][64];
+  const int sub = threadIdx.x >> 6, li = threadIdx.x & 63;
+  const int i = blockIdx.x * 64 + li;
+  double acc = 0.0;
+  if (i < n) {
+    for (int c = sub; c < kchunks; c += 4) acc += phik[(size_t)c * n + i];
+    for (int c = sub; c < rchunks; c += 4) acc += phir[(size_t)c * n + i];
+  }
+  sh[sub][li] = acc;
+  __syncthreads();
+  if (sub != 0 || i >= n) return;
   double mz = 0.0;
   for (int c = 0; c < mchunks; ++c) mz += mz_part[c];
-  const double b = -ke * (pk + pr + slab_coef * ez[i] * mz);
+  const double phi = (sh[0][li] + sh[1][li]) + (sh[2][li] + sh[3][li]);
+  const double b = -ke * (phi + slab_coef * ez[i] * mz);
   if (out_is_f32)
     reinterpret_cast<float*>(out)[i] = (float)b;
   else
@@ -696,8 +747,8 @@ void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchun
                       const double* phik, const double* phir, const Buffers& b,
                       const double* mz_part, double slab_coef, double ke, void* out,
                       int out_is_f32) {
-  hipLaunchKernelGGL(k_combine, dim3((n + 63) / 64), dim3(64), 0, st, n, kchunks, rchunks, mchunks,
-                     phik, phir, b.ez, mz_part, slab_coef, ke, out, out_is_f32);
+  hipLaunchKernelGGL(k_combine, dim3((n + 63) / 64), dim3(256), 0, st, n, kchunks, rchunks,
+                     mchunks, phik, phir, b.ez, mz_part, slab_coef, ke, out, out_is_f32);
 }
 
 }  // namespace cpm

@@ -44,6 +44,7 @@ cpm_status dalloc(cpm_ctx* c, T** p, size_t count) {
     return fail(c, CPM_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
   }
   c->bytes += count * sizeof(T);
+  ++c->alloc_gen;
   *p = static_cast<T*>(q);
   return CPM_OK;
 }
@@ -52,6 +53,12 @@ template <typename T>
 void dfree(T*& p) {
   if (p) (void)hipFree(p);
   p = nullptr;
+}
+
+template <typename T>
+void dfree(cpm_ctx* c, T*& p) {
+  if (p) ++c->alloc_gen;
+  dfree(p);
 }
 
 #define TRY(expr)                  \
@@ -171,10 +178,10 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   c->rchunks = std::max(1, std::min((512 + atom_blocks - 1) / atom_blocks, std::max(1, c->m / 32)));
   TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
   if (c->sf_mfma) {
-    const int wg_per_chunk = 2 * c->sfm_tiles;
+    const int wg_per_chunk = 3 * c->sfm_tiles;
     c->sfm_chunks = std::max(1, std::min((c->sf_wg_target + wg_per_chunk - 1) / wg_per_chunk,
                                          std::max(1, c->m / 64)));
-    TRY(dalloc(c, &b.sfm_part, (size_t)c->sfm_chunks * c->sfm_tiles * 64 * c->sfm_npadc));
+    TRY(dalloc(c, &b.sfm_part, (size_t)c->sfm_chunks * c->sfm_tiles * 32 * c->sfm_npadc));
   }
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
   const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
@@ -189,13 +196,13 @@ cpm_status ensure_solve_buffers(cpm_ctx* c, int batch) {
   if (batch > b.bpad_rows) {
     const size_t old = (size_t)b.bpad_rows * c->npad * sizeof(double);
     if (b.qt) c->bytes -= 4 * old;
-    dfree(b.qt); dfree(b.res); dfree(b.qpad); dfree(b.bpad);
+    dfree(c, b.qt); dfree(c, b.res); dfree(c, b.qpad); dfree(c, b.bpad);
     const size_t sz = (size_t)batch * c->npad;
     TRY(dalloc(c, &b.qt, sz));
     TRY(dalloc(c, &b.res, sz));
     TRY(dalloc(c, &b.qpad, sz));
     TRY(dalloc(c, &b.bpad, sz));
-    dfree(b.means);
+    dfree(c, b.means);
     TRY(dalloc(c, &b.means, (size_t)batch));
     // padding rows and columns of these buffers are read by the GEMMs: zero them once
     HIP_TRY(c, hipMemsetAsync(b.qt, 0, sz * sizeof(double), c->stream));
@@ -337,7 +344,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
     }
     std::stable_sort(fc.begin(), fc.end(), [](const FC& a, const FC& b) { return a.e > b.e; });
     c->ncolsort = (int)fc.size();
-    c->sfm_tiles = (c->ncolsort + 31) / 32;
+    c->sfm_tiles = (c->ncolsort + 15) / 16;
     int nbmax = 0;
     c->h_sc_nidx.push_back(0);
     for (int k = 0; k < c->ncolsort; ++k) {
@@ -345,7 +352,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
       c->h_sc_nx.push_back(f.nx); c->h_sc_ny.push_back(f.ny); c->h_sc_lo.push_back(f.lo);
       c->h_sc_len.push_back(f.len); c->h_sc_koff.push_back(f.koff); c->h_sc_n0.push_back(0);
       c->h_sc_nidx.push_back(c->h_sc_nidx.back() + f.e + 1);
-      if (k % 32 == 0) {
+      if (k % 16 == 0) {
         const int nb = (2 * (f.e + 1) + 15) / 16;   // first column of a tile has its largest extent
         c->h_tile_nb.push_back(nb);
         nbmax = std::max(nbmax, nb);
@@ -353,7 +360,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
     }
     c->sfm_ntot = c->h_sc_nidx.back();
     c->sfm_npadc = 16 * nbmax;
-    c->sf_mfma = nbmax <= 12;                  // two halves of <= 6 blocks each
+    c->sf_mfma = nbmax <= 12;                  // three parts of <= 4 blocks each
     (void)emax;
   }
   *out = c;
@@ -455,7 +462,7 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   launch_mirror_lower(c->stream, npad, b.A);
   TRY(launched(c, "mirror"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  dfree(b.table);
+  dfree(c, b.table);
   c->have_A = true;
   return CPM_OK;
 }
@@ -568,8 +575,12 @@ cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
   return CPM_OK;
 }
 
-cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32) {
-  if (!c) return CPM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// validation and (first-use) allocation for cpm_potential_vector
+cpm_status pv_prepare(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32) {
   if (!c->have_A || !c->have_elyt)
     return fail(c, CPM_ESTATE, "cpm_potential_vector needs cpm_set_electrolyte and cpm_build_elastance");
   if (batch <= 0 || !d_b || (c->m > 0 && !d_xyz))
@@ -577,6 +588,11 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
   if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
   TRY(ensure_uploaded(c));
   TRY(ensure_step_buffers(c));
+  return CPM_OK;
+}
+
+// kernel launches of cpm_potential_vector (no allocation, copy or memset)
+cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32) {
   const cpm_params& p = c->p;
   const int n = c->n, m = c->m;
   const size_t esz = b_is_f32 ? sizeof(float) : sizeof(double);
@@ -586,7 +602,7 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
     const double* xyz = d_xyz ? d_xyz + (size_t)s * m * 3 : nullptr;
     void* out = static_cast<char*>(d_b) + (size_t)s * n * esz;
     if (m == 0) {
-      HIP_TRY(c, hipMemsetAsync(out, 0, n * esz, st));
+      launch_fill_zero(st, n * esz / sizeof(float), static_cast<float*>(out));
       continue;
     }
     // FP64 structure factors on matrix cores when the k set fits the kernel;
@@ -632,24 +648,34 @@ cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void
   return CPM_OK;
 }
 
-cpm_status cpm_solve_charges(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
-                             double* d_q, double* d_Qe) {
-  if (!c) return CPM_EINVAL;
+// validation and (first-use) allocation for cpm_solve_charges
+cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
+                      double* d_q) {
   if (!c->have_v) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_set_potential");
   if (batch <= 0 || !d_b || !d_q) return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL b, q");
   if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
   const unsigned prec = mode & 0xffu;
-  const bool refine = (mode & CPM_SOLVE_REFINE) != 0;
   if ((mode & ~0x1ffu) != 0 || prec > 2) return fail(c, CPM_EINVAL, "unknown solve mode 0x%x", mode);
   if (prec == 1 && !(c->store & CPM_STORE_F32)) return fail(c, CPM_EINVAL, "FP32 copy of S not kept");
   if (prec == 2 && !(c->store & CPM_STORE_BF16X2))
     return fail(c, CPM_EINVAL, "split-BF16 copy of S not kept");
+  const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
+  const int rows = gemm ? ((batch + TILE - 1) / TILE) * TILE : batch;
+  return ensure_solve_buffers(c, rows);
+}
+
+// kernel launches of cpm_solve_charges (no allocation, copy or memset)
+cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
+                      double* d_q, double* d_Qe) {
+  if (batch <= 0 || !d_b || !d_q) return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL b, q");
+  if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
+  const unsigned prec = mode & 0xffu;
+  const bool refine = (mode & CPM_SOLVE_REFINE) != 0;
   const int n = c->n, npad = c->npad;
   // split-BF16 always runs on matrix cores (rows padded to 64); FP64 from
   // GEMM_MIN_BATCH vectors on; FP32 streams S32 per vector
   const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
   const int rows = gemm ? ((batch + TILE - 1) / TILE) * TILE : batch;
-  TRY(ensure_solve_buffers(c, rows));
   Buffers& b = c->b;
   hipStream_t st = c->stream;
   const void* Sm = (prec == 1) ? (const void*)b.S32 : (const void*)b.S;
@@ -730,6 +756,66 @@ cpm_status cpm_solve_charges(cpm_ctx* c, int batch, const void* d_b, int b_is_f3
   { Timed t(c, "finalize");
     launch_finalize(st, n, batch, b.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
   return launched(c, "solve (batched, refined)");
+}
+
+}  // namespace
+
+extern "C" {
+
+cpm_status cpm_potential_vector(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32) {
+  if (!c) return CPM_EINVAL;
+  TRY(pv_prepare(c, batch, d_xyz, d_b, b_is_f32));
+  return pv_enqueue(c, batch, d_xyz, d_b, b_is_f32);
+}
+
+cpm_status cpm_solve_charges(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
+                             double* d_q, double* d_Qe) {
+  if (!c) return CPM_EINVAL;
+  TRY(sc_prepare(c, batch, d_b, b_is_f32, mode, d_q));
+  return sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe);
+}
+
+cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32,
+                            unsigned mode, double* d_q, double* d_Qe) {
+  if (!c) return CPM_EINVAL;
+  if (!c->stream)
+    return fail(c, CPM_EINVAL, "graph capture needs a non-default stream for the context");
+  TRY(pv_prepare(c, batch, d_xyz, d_b, b_is_f32));
+  TRY(sc_prepare(c, batch, d_b, b_is_f32, mode, d_q));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
+  if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+  const bool timing = c->timing;
+  c->timing = false;                               // no event nodes in the graph
+  HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  cpm_status st = pv_enqueue(c, batch, d_xyz, d_b, b_is_f32);
+  if (st == CPM_OK) st = sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->timing = timing;
+  if (st != CPM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(c, CPM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  c->graph = g;
+  HIP_TRY(c, hipGraphInstantiate(&c->graph_exec, c->graph, nullptr, nullptr, 0));
+  c->graph_gen = c->alloc_gen;
+  const unsigned prec = mode & 0xffu;
+  c->graph_store = prec == 1 ? CPM_STORE_F32 : prec == 2 ? CPM_STORE_BF16X2 : CPM_STORE_F64;
+  return CPM_OK;
+}
+
+cpm_status cpm_replay_step(cpm_ctx* c) {
+  if (!c) return CPM_EINVAL;
+  if (!c->graph_exec) return fail(c, CPM_ESTATE, "cpm_replay_step before cpm_capture_step");
+  // the graph holds raw device addresses: any reallocation since capture
+  // (a larger eager batch, a rebuild) or a dropped copy of S invalidates it
+  if (c->alloc_gen != c->graph_gen || !c->have_inv || !c->have_v ||
+      (c->store & c->graph_store) != c->graph_store)
+    return fail(c, CPM_ESTATE, "context buffers changed since cpm_capture_step; capture again");
+  HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+  return CPM_OK;
 }
 
 cpm_status cpm_enable_timing(cpm_ctx* c, int on) {
@@ -821,6 +907,8 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.mz); dfree(b.qt);
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   for (auto& pe : c->pending) { (void)hipEventDestroy(pe.a); (void)hipEventDestroy(pe.b); }
   for (auto e : c->evpool) (void)hipEventDestroy(e);
   delete c;

@@ -100,6 +100,7 @@ struct cpm_ctx {
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;
   size_t bytes = 0;
+  unsigned long long alloc_gen = 0;    // bumped by every device allocation / free
   std::vector<double> h_v;         // per-electrode potential
   std::vector<double> h_xyz;       // electrode coordinates (host copy)
   std::vector<int> h_eid;
@@ -116,6 +117,11 @@ struct cpm_ctx {
   std::vector<double> h_w2;
   std::vector<int> h_kx, h_ky, h_kz;
   cpm::Buffers b;
+  // captured step (cpm_capture_step / cpm_replay_step)
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  unsigned long long graph_gen = 0;    // alloc_gen when the graph was captured
+  unsigned graph_store = 0;            // copies of S the captured solve reads
   // kernel timing (cpm_enable_timing)
   bool timing = false;
   struct Pending { const char* name; hipEvent_t a, b; };
@@ -169,6 +175,7 @@ void launch_make_rhs(hipStream_t st, int n, int npad, int batch, const void* bsr
 void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldqt, const double* add,
                      const double* u, const double* s_dev, const int* eid, int n_e, double* q,
                      int ldq, double* Qe);
+void launch_fill_zero(hipStream_t st, size_t count, float* p);
 void launch_pad_rows(hipStream_t st, int n, int npad, int batch, int rows, const void* src,
                      int src_is_f32, const double* shift, double* dst);
 // C (M x N, FP64) (+)= Bm (M x K, FP64, split to BF16 hi/lo on load) * S, with

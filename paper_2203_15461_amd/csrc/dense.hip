@@ -441,6 +441,17 @@ void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldq
                      n_e, q, ldq, Qe);
 }
 
+// p[0 .. count) = 0 (a kernel, so it can sit inside a captured graph)
+__global__ void k_fill_zero(size_t count, float* p) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < count) p[e] = 0.0f;
+}
+
+void launch_fill_zero(hipStream_t st, size_t count, float* p) {
+  if (count == 0) return;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count, p);
+}
+
 // dst (rows x npad, FP64) = src (batch x n) zero-padded in both directions
 __global__ void k_pad_rows(int n, int npad, int batch, int rows, const void* __restrict__ src,
                            int src_is_f32, const double* __restrict__ shift,

@@ -62,6 +62,8 @@ def test_null_arguments():
     assert L.cpm_set_electrolyte(None, 0, None) == cpm.EINVAL
     assert L.cpm_invert(None, 1) == cpm.EINVAL
     assert L.cpm_solve_charges(None, 1, None, 0, 0, None, None) == cpm.EINVAL
+    assert L.cpm_capture_step(None, 1, None, None, 0, 0, None, None) == cpm.EINVAL
+    assert L.cpm_replay_step(None) == cpm.EINVAL
     assert L.cpm_last_error(None) == b"no context"
     L.cpm_destroy(None)
 

@@ -1,0 +1,150 @@
+"""Captured batched step (cpm_capture_step / cpm_replay_step) against eager calls.
+
+The graph holds kernel launches only (no memset or copy nodes).  Each test
+replays it several times with new electrolyte positions, runs the eager path
+on the same context between replays, and requires every replay to equal the
+eager result bit for bit (same kernels, same fixed reduction order) and the
+first replay to match the FP64 oracle.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpm_oracle as O
+from paper_2203_15461_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cpm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_15461_amd import cpm as C
+    C.lib()
+    return C
+
+
+def _positions(w, first, batch):
+    return np.stack([I.snapshot(w, first + j) for j in range(batch)])
+
+
+# (store flags, solve mode, b in FP32, batch, oracle tolerance on q)
+CASES = [
+    (1, 0x000, False, 1, 1e-10),       # FP64 matvec path
+    (1, 0x000, False, 5, 1e-10),       # FP64 matrix-core path
+    (1 | 2, 0x101, True, 2, 1e-5),     # FP32 S, refined
+    (1 | 4, 0x102, False, 3, 1e-5),    # split-BF16 S, refined
+]
+
+
+@pytest.mark.parametrize("store,mode,b_f32,batch,tol", CASES)
+def test_replay_matches_eager(cpm, store, mode, b_f32, batch, tol):
+    w = I.small_capacitor("a")
+    say(f"graph replay small_capacitor_a mode=0x{mode:x} batch={batch}")
+    s = torch.cuda.Stream()
+    ctx = cpm.setup(w, store=store, stream=s)
+    n, ne = w.n, 2
+    bdt = torch.float32 if b_f32 else torch.float64
+    with torch.cuda.stream(s):
+        xyz = torch.empty((batch, w.m, 3), dtype=torch.float64, device="cuda")
+        b = torch.empty((batch, n), dtype=bdt, device="cuda")
+        q = torch.full((batch, n), float("nan"), dtype=torch.float64, device="cuda")
+        Qe = torch.empty((batch, ne), dtype=torch.float64, device="cuda")
+        b2, q2, Qe2 = torch.empty_like(b), torch.empty_like(q), torch.empty_like(Qe)
+    s.synchronize()
+    ctx.capture_step(xyz, b, mode, q, Qe)
+    assert torch.isnan(q).all(), "capture must not run the step"
+    first_q = None
+    for r in range(4):
+        pos = _positions(w, 10 * r, batch)
+        with torch.cuda.stream(s):
+            xyz.copy_(torch.as_tensor(pos, dtype=torch.float64))
+        ctx.replay_step()
+        s.synchronize()
+        qr, br, Qr = q.cpu().numpy(), b.cpu().numpy(), Qe.cpu().numpy()
+        # eager work on the same context and stream between replays
+        with torch.cuda.stream(s):
+            ctx.potential_vector(xyz, b2)
+            ctx.solve_charges(b2, mode, q2, Qe2)
+        s.synchronize()
+        assert np.array_equal(br, b2.cpu().numpy()), f"replay {r}: b differs from eager"
+        assert np.array_equal(qr, q2.cpu().numpy()), f"replay {r}: q differs from eager"
+        assert np.array_equal(Qr, Qe2.cpu().numpy()), f"replay {r}: Q differs from eager"
+        assert np.abs(qr.sum(axis=1)).max() <= 1e-12
+        if r == 0:
+            first_q = qr
+    p = O.params_for(w)
+    cap = O.capacitance(O.elastance(w.electrode_xyz, p))
+    v = O.applied_potential(w.electrode_id, w.v_electrode)
+    pos0 = _positions(w, 0, batch)
+    for j in range(batch):
+        qo = O.charges(cap.S, O.potential_vector(w.electrode_xyz, pos0[j], w.electrolyte_q, p), v)
+        err = np.abs(first_q[j] - qo).max() / np.abs(qo).max()
+        assert err < tol, (j, err)
+    ctx.close()
+
+
+def test_replay_sees_new_potential_and_rejects_reallocation(cpm):
+    w = I.small_capacitor("a")
+    say("graph replay: set_potential between replays; stale graph after reallocation")
+    s = torch.cuda.Stream()
+    ctx = cpm.setup(w, store=1, stream=s)
+    with torch.cuda.stream(s):
+        xyz = torch.as_tensor(_positions(w, 0, 2), dtype=torch.float64, device="cuda")
+        b = torch.empty((2, w.n), dtype=torch.float64, device="cuda")
+        q = torch.empty_like(b)
+        Qe = torch.empty((2, 2), dtype=torch.float64, device="cuda")
+    s.synchronize()
+    ctx.capture_step(xyz, b, 0, q, Qe)
+    ctx.replay_step()
+    s.synchronize()
+    q_a = q.cpu().numpy()
+    ctx.set_potential([-1.5, 1.5])               # d = S v changes in place
+    ctx.replay_step()
+    s.synchronize()
+    q_b = q.cpu().numpy()
+    p = O.params_for(w)
+    S = O.capacitance(O.elastance(w.electrode_xyz, p)).S
+    dv = O.applied_potential(w.electrode_id, [-1.0, 1.0])    # v(3 V) - v(1 V)
+    assert np.abs((q_b - q_a) - (S @ dv)[None]).max() < 1e-10 * np.abs(q_a).max() + 1e-13
+    # an eager call with a larger batch reallocates the solve buffers
+    with torch.cuda.stream(s):
+        xyz8 = torch.as_tensor(_positions(w, 0, 8), dtype=torch.float64, device="cuda")
+        b8 = torch.empty((8, w.n), dtype=torch.float64, device="cuda")
+        q8 = torch.empty_like(b8)
+    s.synchronize()
+    ctx.potential_vector(xyz8, b8)
+    ctx.solve_charges(b8, 0, q8, None)
+    s.synchronize()
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.replay_step()
+    assert ei.value.status == cpm.ESTATE
+    ctx.capture_step(xyz, b, 0, q, Qe)           # a fresh capture works again
+    ctx.replay_step()
+    s.synchronize()
+    assert np.array_equal(q.cpu().numpy(), q_b)
+    ctx.close()
+
+
+def test_capture_errors(cpm):
+    w = I.small_capacitor("a")
+    ctx = cpm.setup(w, store=1, stream=None)
+    say("graph capture: errors")
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.replay_step()
+    assert ei.value.status == cpm.ESTATE
+    xyz = torch.as_tensor(_positions(w, 0, 1), dtype=torch.float64, device="cuda")
+    b = torch.empty((1, w.n), dtype=torch.float64, device="cuda")
+    q = torch.empty_like(b)
+    with pytest.raises(cpm.CpmError) as ei:     # the legacy default stream cannot be captured
+        ctx.capture_step(xyz, b, 0, q)
+    assert ei.value.status == cpm.EINVAL
+    ctx.close()
