@@ -184,12 +184,13 @@ cpm_status cpm_copy_vector(const cpm_ctx* ctx, int which, double* d_out);
 /* Scalar information (CPM_INFO_*). */
 cpm_status cpm_get_info(const cpm_ctx* ctx, int key, double* out);
 
-/* Kernel timing.  While on, every kernel the library launches on the context
- * stream is bracketed by HIP events and its elapsed time is accumulated per
- * kernel family (for example "structure_factor", "kspace_project",
- * "real_space_b", "matvec_f64", "gemm_f64").  Turning it on clears the
- * totals.  Adds two event records per launch. */
-cpm_status cpm_enable_timing(cpm_ctx* ctx, int on);
+/* Kernel timing.  families = NULL or "" turns it off; "*" times every
+ * kernel the library launches on the context stream; otherwise a
+ * comma-separated list of kernel families (for example "structure_factor",
+ * "kspace_project", "real_space_b", "matvec_f64", "gemm_f64") restricts it to
+ * those.  Each timed launch is bracketed by two HIP event records and its
+ * elapsed time is accumulated per family.  Every call clears the totals. */
+cpm_status cpm_enable_timing(cpm_ctx* ctx, const char* families);
 
 /* Total milliseconds and launch count of kernel family `name` recorded since
  * timing was enabled.  Synchronises the context stream.  A family that never

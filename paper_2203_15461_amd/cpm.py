@@ -71,7 +71,7 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_replay_step": ([vp], i),
         "cpm_copy_vector": ([vp, i, vp], i),
         "cpm_get_info": ([vp, i, ctypes.POINTER(d)], i),
-        "cpm_enable_timing": ([vp, i], i),
+        "cpm_enable_timing": ([vp, ctypes.c_char_p], i),
         "cpm_get_timing": ([vp, ctypes.c_char_p, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)], i),
         "cpm_synchronize": ([vp], i),
         "cpm_last_error": ([vp], ctypes.c_char_p),
@@ -157,9 +157,20 @@ class Context:
         self._check(self._lib.cpm_get_info(self._h, INFO[key], ctypes.byref(out)), "cpm_get_info")
         return out.value
 
-    def enable_timing(self, on: bool = True):
-        """Per-kernel-family HIP event timing on the context stream (clears totals)."""
-        self._check(self._lib.cpm_enable_timing(self._h, int(on)), "cpm_enable_timing")
+    def enable_timing(self, on=True):
+        """Per-kernel-family HIP event timing on the context stream (clears totals).
+
+        on: True (every family), False/None (off), or an iterable / comma-separated
+        string of family names to time only those."""
+        if on is True:
+            spec = b"*"
+        elif not on:
+            spec = None
+        elif isinstance(on, str):
+            spec = on.encode()
+        else:
+            spec = ",".join(on).encode()
+        self._check(self._lib.cpm_enable_timing(self._h, spec), "cpm_enable_timing")
 
     def timing(self, name: str):
         """(total_ms, launches) of one kernel family since timing was enabled."""

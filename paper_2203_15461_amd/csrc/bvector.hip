@@ -187,25 +187,11 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
 }
 
 // ---------------------------------------------------------------------------
-// Structure factors on FP64 matrix cores.  For a (k_x, k_y) column c,
-//   S(c, +-n) = sum_j C_cj (Zr_jn +- i Zi_jn),  C_cj = q_j e^{i(k_x x_j + k_y y_j)},
-//   Z_jn = e^{2 pi i n z_j / Lz},  n >= 0,
-// so with rows (Re C_c, Im C_c) and columns (Zr_n, Zi_n) one real GEMM over
-// the charges gives Pr, Qr, Pi, Qi and both S(c, n) = (Pr - Qi) + i (Pi + Qr)
-// and S(c, -n) = (Pr + Qi) + i (Pi - Qr).  Columns are sorted by their k_z
-// extent and grouped 16 per M tile (32 rows).  A workgroup takes one M tile,
-// one half of its n range and one chunk of the electrolyte; each of its waves
-// walks its own tiles of 16 charges (no workgroup barrier inside the loop):
-// it writes C for its charges and the first 8 phases e^{2 pi i n fz} of its
-// n range into a wave-private LDS area (exact FP64 sincospi), then runs
-// v_mfma_f64_16x16x4f64 with the B operand advanced in registers by
-// e^{2 pi i 8 fz} per 16-wide block.  The 4 waves are summed in a fixed order.
-// part[((chunk * mtiles + mt) * 32 + row) * npadc + col]: this chunk's sums.
+// Structure factors on FP64 matrix cores: per-charge phase tables, then one
+// real GEMM per group of (k_x, k_y) columns (details at k_sf_mfma).
 // ---------------------------------------------------------------------------
 typedef double v4d_t __attribute__((ext_vector_type(4)));
 constexpr int SFM_TJ = 16;             // charges per wave tile (4 MFMA k-steps)
-constexpr int SFM_NB = 4;              // max 16-wide n blocks per workgroup (a third of a tile)
-constexpr int SFM_SPLIT = 3;           // workgroups per M tile along n
 constexpr int SFM_COLS = 16;           // columns per M tile (32 GEMM rows)
 
 struct SfmWave {                        // wave-private LDS area
@@ -220,35 +206,122 @@ __device__ inline void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ void __launch_bounds__(256) k_sf_mfma(int m, int chunk_size, int mtiles,
+__device__ inline double2 cmul2(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Per-charge phase tables of one configuration, rows of mpad double2
+// (charges j >= m are zero), each entry an exact FP64 sincospi of the reduced
+// fractional phase:
+//   rows [0, nxm]              X_a(j) = e^{2 pi i a fx_j}
+//   rows nxm+1 + [0, 2 nym]    Y_b(j) = q_j e^{2 pi i (b - nym) fy_j}
+//   next 8 rows                Z1_i(j) = e^{2 pi i i fz_j}
+//   next nbz rows              Z8_c(j) = e^{2 pi i 8 c fz_j}
+// Workgroups of row 0 also leave M_z partials sum q_j z_j per 256 charges.
+__global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int nym, int nbz,
+                                                   const double* __restrict__ xyz,
+                                                   const double* __restrict__ q, double Lx,
+                                                   double Ly, double Lz,
+                                                   double2* __restrict__ tab,
+                                                   double* __restrict__ mz_part) {
+  __shared__ double s_mz[4];
+  const int row = blockIdx.y;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  const int ny_rows = 2 * nym + 1;
+  const int rX = 0, rY = nxm + 1, rZ1 = rY + ny_rows, rZ8 = rZ1 + 8;
+  (void)rX;
+  (void)nbz;
+  double qq = 0.0, zz = 0.0;
+  if (j < m) { qq = q[j]; zz = xyz[3 * j + 2]; }
+  if (j < mpad) {
+    double2 v = make_double2(0.0, 0.0);
+    if (j < m) {
+      double f, idx, scale = 1.0;
+      if (row < rY) {
+        f = xyz[3 * j] / Lx; f -= floor(f); idx = row;
+      } else if (row < rZ1) {
+        f = xyz[3 * j + 1] / Ly; f -= floor(f); idx = row - rY - nym; scale = qq;
+      } else if (row < rZ8) {
+        f = zz / Lz; f -= floor(f); idx = row - rZ1;
+      } else {
+        f = zz / Lz; f -= floor(f); idx = 8.0 * (row - rZ8);
+      }
+      double th = idx * f;
+      th -= rint(th);
+      double sn, cs;
+      sincospi(2.0 * th, &sn, &cs);
+      v = make_double2(scale * cs, scale * sn);
+    }
+    tab[(size_t)row * mpad + j] = v;
+  }
+  if (row == 0) {
+    double mz = qq * zz;
+    for (int o = 32; o > 0; o >>= 1) mz += __shfl_xor(mz, o, 64);
+    if ((threadIdx.x & 63) == 0) s_mz[threadIdx.x >> 6] = mz;
+    __syncthreads();
+    if (threadIdx.x == 0) mz_part[blockIdx.x] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
+  }
+}
+
+void launch_b_sf_tables(hipStream_t st, int m, int mpad, int nxm, int nym, int nbz,
+                        const double* xyz, const double* q, double Lx, double Ly, double Lz,
+                        double2* tab, double* mz_part) {
+  const int rows = (nxm + 1) + (2 * nym + 1) + 8 + nbz;
+  dim3 grid((mpad + 255) / 256, rows), block(256);
+  hipLaunchKernelGGL(k_sf_tables, grid, block, 0, st, m, mpad, nxm, nym, nbz, xyz, q, Lx, Ly, Lz,
+                     tab, mz_part);
+}
+
+// Structure factors of full (k_x, k_y) columns as a real GEMM on FP64 matrix
+// cores.  For column c = (nx, ny) and charge j let C = q_j e^{i(kx x + ky y)}
+// = X_nx(j) Y_ny(j) and Z = e^{i n kz1 z_j}; then over the charges
+//   Pr = sum Re C Re Z,  Qr = sum Re C Im Z,  Pi = sum Im C Re Z,  Qi = sum Im C Im Z
+// give S(c, +n) = (Pr - Qi) + i (Pi + Qr) and S(c, -n) = (Pr + Qi) + i (Pi - Qr)
+// for n >= 0.  Columns are sorted by k_z extent and grouped 16 per M tile
+// (32 rows); a work item is one M tile and at most SFM_NB blocks of 8
+// consecutive n.  A workgroup takes one item and one chunk of charges; each
+// wave walks its own tiles of 16 charges (no workgroup barrier inside the
+// loop): it forms C from the X and Y tables and the first 8 phases of its n
+// range from Z8 x Z1 into a wave-private LDS area, then runs
+// v_mfma_f64_16x16x4f64 with the B operand advanced in registers by
+// e^{2 pi i 8 fz} per 16-wide block.  The 4 waves are summed in a fixed order.
+// part[((chunk * mtiles + mt) * 32 + row) * npadc + col]: this chunk's sums.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_sf_mfma(int mpad, int chunk_size, int mtiles,
+                                                 int nitems, const int4* __restrict__ items,
                                                  const int* __restrict__ sc_nx,
-                                                 const int* __restrict__ sc_ny,
-                                                 const int* __restrict__ tile_nb, int ncolsort,
-                                                 const double* __restrict__ xyz,
-                                                 const double* __restrict__ q, double Lx,
-                                                 double Ly, double Lz, int npadc,
-                                                 double* __restrict__ part,
-                                                 double* __restrict__ mz_part) {
+                                                 const int* __restrict__ sc_ny, int ncolsort,
+                                                 int nxm, int nym,
+                                                 const double2* __restrict__ tab, int npadc,
+                                                 double* __restrict__ part) {
   __shared__ SfmWave wl[4];
   __shared__ double red[64 * 2 * SFM_NB * 4];      // one wave's accumulators
-  __shared__ int s_nx[SFM_COLS], s_ny[SFM_COLS];
-  __shared__ double s_mz[4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int mt = blockIdx.x / SFM_SPLIT, part_n = blockIdx.x % SFM_SPLIT;
-  const int chunk = blockIdx.y;
-  const int nbt = tile_nb[mt];
-  const int nb_lo = (nbt * part_n) / SFM_SPLIT;
-  const int nb_hi = (nbt * (part_n + 1)) / SFM_SPLIT;
-  const int nbw = nb_hi - nb_lo;                   // blocks of this workgroup (<= SFM_NB)
-  const int n_lo = nb_lo * 8;                      // first complex n of this workgroup
+  // workgroups go round-robin to the 8 XCDs; keep every charge chunk on one
+  // XCD (chunk = xcd mod 8) so its table rows stay in that XCD's L2
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int item = slot % nitems;
+  const int chunk = xcd + 8 * (slot / nitems);
+  const int4 it = items[item];
+  const int mt = it.x, nb_lo = it.y, nbw = it.z;
   const int c_base = mt * SFM_COLS;
   const int ncol = min(SFM_COLS, ncolsort - c_base);
-  if (tid < SFM_COLS) {
-    s_nx[tid] = tid < ncol ? sc_nx[c_base + tid] : 0;
-    s_ny[tid] = tid < ncol ? sc_ny[c_base + tid] : 0;
+  const int j0 = chunk * chunk_size, j1 = min(mpad, j0 + chunk_size);
+  const int t_l = lane & 15, g_l = lane >> 4;     // this lane's charge in the tile, lane group
+  const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
+  // table rows of this lane's four columns g_l + 4u (columns past the end: C = 0)
+  // (32-bit element offsets: the tables stay far below 2^31 entries)
+  int xoff[4], yoff[4];
+  bool ok[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int cl = g_l + 4 * u;
+    ok[u] = cl < ncol;
+    const int nx = ok[u] ? sc_nx[c_base + cl] : 0, ny = ok[u] ? sc_ny[c_base + cl] : 0;
+    xoff[u] = nx * mpad + t_l;
+    yoff[u] = (rY + ny + nym) * mpad + t_l;
   }
-  __syncthreads();
-  const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
+  const int z8off = (rZ8 + nb_lo) * mpad + t_l, r8off = (rZ8 + 1) * mpad + t_l;
+  const int z1off = (rZ1 + 2 * g_l) * mpad + t_l;
   SfmWave& W = wl[wave];
   v4d_t acc0[SFM_NB], acc1[SFM_NB];
 #pragma unroll
@@ -256,46 +329,29 @@ __global__ void __launch_bounds__(256) k_sf_mfma(int m, int chunk_size, int mtil
     acc0[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
     acc1[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
   }
-  double mz = 0.0;
-  const int t_l = lane & 15, g_l = lane >> 4;     // this lane's charge in the tile, lane group
+  // table entries of the next tile are loaded while the current one runs
+  double2 xv[4], yv[4], z8, za, zb, r8n;
+  auto fetch = [&](int jt) {                        // jt + t_l < mpad: chunks are multiples of 16
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { xv[u] = tab[xoff[u] + jt]; yv[u] = tab[yoff[u] + jt]; }
+    z8 = tab[z8off + jt]; za = tab[z1off + jt]; zb = tab[z1off + mpad + jt]; r8n = tab[r8off + jt];
+  };
+  if (j0 + wave * SFM_TJ < j1) fetch(j0 + wave * SFM_TJ);
   for (int jt = j0 + wave * SFM_TJ; jt < j1; jt += 4 * SFM_TJ) {
-    const int nt = min(SFM_TJ, j1 - jt);
-    double fx = 0.0, fy = 0.0, fz = 0.0, qq = 0.0;
-    if (t_l < nt) {
-      const int j = jt + t_l;
-      fx = xyz[3 * j] / Lx;
-      fy = xyz[3 * j + 1] / Ly;
-      fz = xyz[3 * j + 2] / Lz;
-      fx -= floor(fx);
-      fy -= floor(fy);
-      qq = q[j];
-      if (blockIdx.x == 0 && g_l == 0) mz += qq * xyz[3 * j + 2];
-    }
-    // A operand: C for columns g_l, g_l + 4, g_l + 8, g_l + 12 of charge t_l,
-    // and the first phases of the n range (j = 2 g_l, 2 g_l + 1); the seven
-    // independent sincospi are written out so their chains interleave
     {
-      double th[7];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) th[u] = s_nx[g_l + 4 * u] * fx + s_ny[g_l + 4 * u] * fy;
-      th[4] = (n_lo + 2 * g_l) * fz;
-      th[5] = (n_lo + 2 * g_l + 1) * fz;
-      th[6] = 8.0 * fz;
-      double sn[7], cs[7];
-#pragma unroll
-      for (int u = 0; u < 7; ++u) sincospi(2.0 * (th[u] - rint(th[u])), &sn[u], &cs[u]);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int cl = g_l + 4 * u;
-        const bool ok = cl < ncol;
-        W.C[2 * cl][t_l] = ok ? qq * cs[u] : 0.0;
-        W.C[2 * cl + 1][t_l] = ok ? qq * sn[u] : 0.0;
+        const double2 cv = cmul2(xv[u], yv[u]);
+        W.C[2 * cl][t_l] = ok[u] ? cv.x : 0.0;
+        W.C[2 * cl + 1][t_l] = ok[u] ? cv.y : 0.0;
       }
-      W.z0[t_l][2 * g_l] = make_double2(cs[4], sn[4]);
-      W.z0[t_l][2 * g_l + 1] = make_double2(cs[5], sn[5]);
-      if (g_l == 0) W.r8[t_l] = make_double2(cs[6], sn[6]);
+      W.z0[t_l][2 * g_l] = cmul2(z8, za);
+      W.z0[t_l][2 * g_l + 1] = cmul2(z8, zb);
+      if (g_l == 0) W.r8[t_l] = r8n;
     }
     wave_lds_sync();
+    if (jt + 4 * SFM_TJ < j1) fetch(jt + 4 * SFM_TJ);
 #pragma unroll 1
     for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
       const int kc = 4 * ks + g_l;                    // k index (charge) of this lane's operands
@@ -352,23 +408,16 @@ __global__ void __launch_bounds__(256) k_sf_mfma(int m, int chunk_size, int mtil
       }
     }
   }
-  if (blockIdx.x == 0) {   // this chunk's electrolyte dipole sum_j q_j z_j
-    for (int o = 32; o > 0; o >>= 1) mz += __shfl_xor(mz, o, 64);
-    if (lane == 0) s_mz[wave] = mz;
-    __syncthreads();
-    if (tid == 0) mz_part[chunk] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
-  }
 }
 
-void launch_b_sf_mfma(hipStream_t st, int m, int mchunks, int mtiles, const int* sc_nx,
-                      const int* sc_ny, const int* tile_nb, int ncolsort, const double* xyz,
-                      const double* q, double Lx, double Ly, double Lz, int nxm, int nym,
-                      int npadc, double* part, double* mz_part) {
-  (void)nxm; (void)nym;
-  const int chunk_size = (m + mchunks - 1) / mchunks;
-  dim3 grid(SFM_SPLIT * mtiles, mchunks), block(256);
-  hipLaunchKernelGGL(k_sf_mfma, grid, block, 0, st, m, chunk_size, mtiles, sc_nx, sc_ny, tile_nb,
-                     ncolsort, xyz, q, Lx, Ly, Lz, npadc, part, mz_part);
+void launch_b_sf_mfma(hipStream_t st, int mpad, int mchunks, int nitems, const int4* items,
+                      int mtiles, const int* sc_nx, const int* sc_ny, int ncolsort, int nxm,
+                      int nym, const double2* tab, int npadc, double* part) {
+  // mchunks is a multiple of 8 (one residue class of chunks per XCD)
+  const int chunk_size = sf_mfma_chunk(mpad, mchunks);
+  dim3 grid(nitems * mchunks), block(256);
+  hipLaunchKernelGGL(k_sf_mfma, grid, block, 0, st, mpad, chunk_size, mtiles, nitems, items, sc_nx,
+                     sc_ny, ncolsort, nxm, nym, tab, npadc, part);
 }
 
 // Sum the chunks of the matrix-core structure factors and scatter them to
@@ -602,23 +651,84 @@ int layer_project_chunks(int ncols) { return (ncols + LP_COLS - 1) / LP_COLS; }
 // ---------------------------------------------------------------------------
 constexpr int RS_TILE = 256;
 
-// erfc(alpha r) - erfc(eta r).  Beyond r2_gauss = 45 / (eta^2 - alpha^2) the
-// second term is below e^-45 of the first (erfc(x) <= e^{-x^2}), i.e. under
-// FP64 rounding of the difference, and is not evaluated.
-__device__ inline double pair_kernel(double r, double r2, double alpha, double eta,
-                                     double r2_gauss) {
-  const double a = erfc(alpha * r);
-  return r2 > r2_gauss ? a : a - erfc(eta * r);
+// Electrode-point pair function g(r) = (erfc(alpha r) - erfc(eta r)) / r
+// (the Gaussian-smeared electrode charge seen from a point charge, minus
+// the part carried by the Ewald k-space sum), tabulated on RS_NT equal
+// intervals of [0, rc] as (g, g', g'') per node.  g is even and smooth at
+// r = 0, so while eta r < 1.5 the nodes come from its Taylor series
+// g = sum_k c_k r^{2k}, c_k = (2/sqrt(pi)) (-1)^k (eta^{2k+1} - alpha^{2k+1}) / (k! (2k+1));
+// beyond, from h = erfc(alpha r) - erfc(eta r):  g = h/r, g' = (h' - g)/r,
+// g'' = (h'' - 2 g')/r.  Quintic Hermite interpolation between the nodes
+// reproduces g to a few 1e-15 (absolute, 1/A) at eta ~ 2, alpha ~ 0.3,
+// rc ~ 12 A; the interpolation error grows as (eta rc / RS_NT)^6.
+__global__ void k_pair_table(double alpha, double eta, double h, double* __restrict__ tab) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > RS_NT) return;
+  const double r = k * h, two_rpi = 1.1283791670955126;   // 2 / sqrt(pi)
+  double g, g1, g2;
+  if (r * fmax(eta, alpha) < 1.5) {
+    // Taylor series in r^2 while eta r < 1.5 (terms stay below ~2, so no
+    // cancellation); 40 terms: the last is below 1e-33
+    double a2k1 = alpha, e2k1 = eta, fact = 1.0, r2k = 1.0;
+    const double a2 = alpha * alpha, e2 = eta * eta, r2 = r * r;
+    g = 0.0; g1 = 0.0; g2 = 0.0;
+    for (int kk = 0; kk < 40; ++kk) {
+      const double ck = two_rpi * ((kk & 1) ? -1.0 : 1.0) * (e2k1 - a2k1) / (fact * (2 * kk + 1));
+      g += ck * r2k;                                       // c_k r^{2k}
+      if (kk >= 1 && k > 0) {
+        g1 += 2.0 * kk * ck * r2k / r;                     // 2k c_k r^{2k-1}
+        g2 += 2.0 * kk * (2.0 * kk - 1.0) * ck * r2k / r2; // 2k(2k-1) c_k r^{2k-2}
+      }
+      a2k1 *= a2; e2k1 *= e2; fact *= (kk + 1); r2k *= r2;
+    }
+    if (k == 0) { g1 = 0.0; g2 = 2.0 * (-two_rpi * (eta * e2 - alpha * a2) / 3.0); }
+  } else {
+    const double ea = exp(-alpha * alpha * r * r), ee = exp(-eta * eta * r * r);
+    const double hv = erfc(alpha * r) - erfc(eta * r);
+    const double h1 = two_rpi * (eta * ee - alpha * ea);
+    const double h2 = 2.0 * two_rpi * r * (alpha * alpha * alpha * ea - eta * eta * eta * ee);
+    g = hv / r;
+    g1 = (h1 - g) / r;
+    g2 = (h2 - 2.0 * g1) / r;
+  }
+  tab[3 * k] = g;
+  tab[3 * k + 1] = g1;
+  tab[3 * k + 2] = g2;
 }
 
+void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab) {
+  hipLaunchKernelGGL(k_pair_table, dim3((RS_NT + 1 + 255) / 256), dim3(256), 0, st, alpha, eta,
+                     rc / RS_NT, tab);
+}
+
+// g(r) from the node table in LDS (quintic Hermite on the node's interval)
+__device__ inline double pair_g(const double* __restrict__ T, double r, double inv_h, double h) {
+  const double u = r * inv_h;
+  const int k = min((int)u, RS_NT - 1);
+  const double t = u - k;
+  const double g0 = T[3 * k], d0 = h * T[3 * k + 1], e0 = h * h * T[3 * k + 2];
+  const double g1 = T[3 * k + 3], d1 = h * T[3 * k + 4], e1 = h * h * T[3 * k + 5];
+  const double D = g1 - g0;
+  const double c3 = 10.0 * D - 6.0 * d0 - 4.0 * d1 - 1.5 * e0 + 0.5 * e1;
+  const double c4 = -15.0 * D + 8.0 * d0 + 7.0 * d1 + 1.5 * e0 - e1;
+  const double c5 = 6.0 * D - 3.0 * d0 - 3.0 * d1 - 0.5 * e0 + 0.5 * e1;
+  return g0 + t * (d0 + t * (0.5 * e0 + t * (c3 + t * (c4 + t * c5))));
+}
+
+// Real-space part of phi_i over one chunk of the electrolyte: workgroup of
+// 256 electrode atoms; electrolyte tiles staged in LDS, keeping only charges
+// within rc in z of the workgroup's atoms (order-preserving compaction);
+// all in-plane images within rc; g(r) from the LDS pair table.
 __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_size,
                                                       const double* __restrict__ ex,
                                                       const double* __restrict__ ey,
                                                       const double* __restrict__ ez,
                                                       const double* __restrict__ xyz,
                                                       const double* __restrict__ q, double Lx,
-                                                      double Ly, double rc, double alpha,
-                                                      double eta, double* __restrict__ part) {
+                                                      double Ly, double rc,
+                                                      const double* __restrict__ ptab,
+                                                      double* __restrict__ part) {
+  __shared__ double s_tab[3 * (RS_NT + 1)];
   __shared__ double s_x[RS_TILE], s_y[RS_TILE], s_z[RS_TILE], s_q[RS_TILE];
   __shared__ double s_zr[2][4];
   __shared__ int s_cnt[4];
@@ -627,8 +737,9 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
   const int chunk = blockIdx.y;
   const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
   const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
-  const double r2_gauss = eta > alpha ? 45.0 / (eta * eta - alpha * alpha) : 1e300;
+  const double h = rc / RS_NT, inv_h = RS_NT / rc;
   const bool single = (Lx >= 2.0 * rc) && (Ly >= 2.0 * rc);
+  for (int t = threadIdx.x; t < 3 * (RS_NT + 1); t += 256) s_tab[t] = ptab[t];
   double xi = 0, yi = 0, zi = 0;
   if (i < n) { xi = ex[i]; yi = ey[i]; zi = ez[i]; }
   // z interval of this workgroup's atoms: charges farther than rc from it
@@ -678,10 +789,7 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
       dy -= Ly * rint(dy * invLy);
       if (single) {
         const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < rc2 * (1.0 + 1e-12)) {
-          const double r = sqrt(r2);
-          if (r < rc) acc += s_q[t] * pair_kernel(r, r2, alpha, eta, r2_gauss) / r;
-        }
+        if (r2 < rc2) acc += s_q[t] * pair_g(s_tab, sqrt(r2), inv_h, h);
       } else {
         const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
         const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
@@ -690,10 +798,7 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
           for (int bb = blo; bb <= bhi; ++bb) {
             const double Y = dy + bb * Ly;
             const double r2 = X * X + Y * Y + dz * dz;
-            if (r2 < rc2 * (1.0 + 1e-12)) {
-              const double r = sqrt(r2);
-              if (r < rc) acc += s_q[t] * pair_kernel(r, r2, alpha, eta, r2_gauss) / r;
-            }
+            if (r2 < rc2) acc += s_q[t] * pair_g(s_tab, sqrt(r2), inv_h, h);
           }
         }
       }
@@ -704,11 +809,11 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
 
 void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
                          const double* xyz, const double* q, double Lx, double Ly, double rc,
-                         double alpha, double eta, double* part) {
+                         double* part) {
   const int chunk_size = (m + rchunks - 1) / rchunks;
   dim3 grid((n + 255) / 256, rchunks), block(256);
   hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, n, m, chunk_size, b.ex, b.ey, b.ez, xyz, q,
-                     Lx, Ly, rc, alpha, eta, part);
+                     Lx, Ly, rc, b.rtab, part);
 }
 
 // b_i = -k_e (sum of k-space partials + sum of real-space partials

@@ -8,6 +8,7 @@
 #include <cstring>
 #include <new>
 
+#include <string>
 #include "cpm_internal.h"
 
 using namespace cpm;
@@ -113,7 +114,11 @@ struct Timed {
   const char* name;
   hipEvent_t a = nullptr;
   Timed(cpm_ctx* c_, const char* n) : c(c_), name(n) {
-    if (c->timing && (a = take_event(c))) (void)hipEventRecord(a, c->stream);
+    if (!c->timing) return;
+    if (!c->timing_only.empty() &&
+        std::find(c->timing_only.begin(), c->timing_only.end(), n) == c->timing_only.end())
+      return;
+    if ((a = take_event(c))) (void)hipEventRecord(a, c->stream);
   }
   ~Timed() {
     if (!a) return;
@@ -178,16 +183,26 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   c->rchunks = std::max(1, std::min((512 + atom_blocks - 1) / atom_blocks, std::max(1, c->m / 32)));
   TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
   if (c->sf_mfma) {
-    const int wg_per_chunk = 3 * c->sfm_tiles;
-    c->sfm_chunks = std::max(1, std::min((c->sf_wg_target + wg_per_chunk - 1) / wg_per_chunk,
-                                         std::max(1, c->m / 64)));
+    c->mpad = std::max(16, (c->m + 15) / 16 * 16);
+    // a multiple of 8 chunks (the kernel keeps each chunk on one XCD), about
+    // sfm_wg_target workgroups; chunks past the charges contribute zeros
+    const int per8 = 8 * c->sfm_nitems;
+    const int r = std::max(1, std::min((c->sfm_wg_target + per8 / 2) / per8,
+                                       std::max(1, c->mpad / (8 * 64))));
+    c->sfm_chunks = 8 * r;
+    c->sft_rows = (c->nxm + 1) + (2 * c->nym + 1) + 8 + c->sfm_nbz;
+    c->sft_blocks = (c->mpad + 255) / 256;
     TRY(dalloc(c, &b.sfm_part, (size_t)c->sfm_chunks * c->sfm_tiles * 32 * c->sfm_npadc));
+    TRY(dalloc(c, &b.sft, (size_t)c->sft_rows * c->mpad));
   }
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
   const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
   TRY(dalloc(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
   TRY(dalloc(c, &b.phir_part, (size_t)c->n * c->rchunks));
-  TRY(dalloc(c, &b.mz, (size_t)std::max(c->mchunks, c->sfm_chunks)));
+  TRY(dalloc(c, &b.mz, (size_t)std::max(c->mchunks, c->sft_blocks)));
+  TRY(dalloc(c, &b.rtab, (size_t)3 * (RS_NT + 1)));
+  launch_pair_table(c->stream, c->p.alpha, c->p.eta, c->p.rcut, b.rtab);
+  TRY(launched(c, "pair table"));
   return CPM_OK;
 }
 
@@ -233,6 +248,9 @@ cpm_status ensure_uploaded(cpm_ctx* c) {
       TRY(up(&b.sc_nx, c->h_sc_nx)); TRY(up(&b.sc_ny, c->h_sc_ny)); TRY(up(&b.sc_lo, c->h_sc_lo));
       TRY(up(&b.sc_len, c->h_sc_len)); TRY(up(&b.sc_koff, c->h_sc_koff)); TRY(up(&b.sc_n0, c->h_sc_n0));
       TRY(up(&b.sc_nidx, c->h_sc_nidx)); TRY(up(&b.tile_nb, c->h_tile_nb));
+      TRY(dalloc(c, &b.sfm_items, c->h_sfm_items.size()));
+      HIP_TRY(c, hipMemcpy(b.sfm_items, c->h_sfm_items.data(), c->h_sfm_items.size() * sizeof(int4),
+                           hipMemcpyHostToDevice));
     }
     TRY(dalloc(c, &b.chunk_col, c->h_chunk_col.size()));
     TRY(dalloc(c, &b.flag, 4));
@@ -290,6 +308,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   c->Lz = p.slab_factor * p.h;
   c->V = p.Lx * p.Ly * c->Lz;
   if (const char* ev = std::getenv("CPM_SF_WG_TARGET")) c->sf_wg_target = std::max(64, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_SFM_WG_TARGET")) c->sfm_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
@@ -360,7 +379,18 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
     }
     c->sfm_ntot = c->h_sc_nidx.back();
     c->sfm_npadc = 16 * nbmax;
-    c->sf_mfma = nbmax <= 12;                  // three parts of <= 4 blocks each
+    c->sfm_nbz = std::max(2, nbmax);           // Z8 rows: first block of every item, and e^{2 pi i 8 fz}
+    // work items: each M tile's n blocks split evenly into parts of <= SFM_NB
+    for (int mt = 0; mt < c->sfm_tiles; ++mt) {
+      const int nb = c->h_tile_nb[mt];
+      const int parts = (nb + SFM_NB - 1) / SFM_NB;
+      for (int q = 0; q < parts; ++q) {
+        const int lo = nb * q / parts, hi = nb * (q + 1) / parts;
+        c->h_sfm_items.push_back(make_int4(mt, lo, hi - lo, 0));
+      }
+    }
+    c->sfm_nitems = (int)c->h_sfm_items.size();
+    c->sf_mfma = c->sfm_nitems > 0;
     (void)emax;
   }
   *out = c;
@@ -608,12 +638,15 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
     // FP64 structure factors on matrix cores when the k set fits the kernel;
     // both structure-factor kernels also leave the electrolyte dipole partials
     const bool mfma = c->sf_mfma && !b_is_f32 && c->use_sf_mfma;
-    const int mz_parts = mfma ? c->sfm_chunks : c->mchunks;
+    const int mz_parts = mfma ? c->sft_blocks : c->mchunks;
     if (mfma) {
+      { Timed t(c, "sf_tables");
+        launch_b_sf_tables(st, m, c->mpad, c->nxm, c->nym, c->sfm_nbz, xyz, b.elq, p.Lx, p.Ly,
+                           c->Lz, b.sft, b.mz); }
       { Timed t(c, "structure_factor");
-        launch_b_sf_mfma(st, m, c->sfm_chunks, c->sfm_tiles, b.sc_nx, b.sc_ny, b.tile_nb,
-                         c->ncolsort, xyz, b.elq, p.Lx, p.Ly, c->Lz, c->nxm, c->nym,
-                         c->sfm_npadc, b.sfm_part, b.mz); }
+        launch_b_sf_mfma(st, c->mpad, c->sfm_chunks, c->sfm_nitems, b.sfm_items, c->sfm_tiles,
+                         b.sc_nx, b.sc_ny, c->ncolsort, c->nxm, c->nym, b.sft, c->sfm_npadc,
+                         b.sfm_part); }
       { Timed t(c, "sf_reduce");
         launch_b_sf_mfma_reduce(st, c->ncolsort, c->sfm_tiles, c->sfm_chunks, c->sfm_npadc,
                                 b.sc_lo, b.sc_len, b.sc_koff, b.sc_n0, b.sc_nidx, c->sfm_ntot,
@@ -638,8 +671,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
                               b.phik_part);
     }
     { Timed t(c, "real_space_b");
-      launch_b_real_space(st, n, m, c->rchunks, b, xyz, b.elq, p.Lx, p.Ly, p.rcut, p.alpha, p.eta,
-                          b.phir_part); }
+      launch_b_real_space(st, n, m, c->rchunks, b, xyz, b.elq, p.Lx, p.Ly, p.rcut, b.phir_part); }
     { Timed t(c, "combine");
       launch_b_combine(st, n, kparts, c->rchunks, mz_parts, b.phik_part, b.phir_part, b, b.mz,
                        4.0 * M_PI / c->V, c->ke, out, b_is_f32); }
@@ -818,12 +850,25 @@ cpm_status cpm_replay_step(cpm_ctx* c) {
   return CPM_OK;
 }
 
-cpm_status cpm_enable_timing(cpm_ctx* c, int on) {
+cpm_status cpm_enable_timing(cpm_ctx* c, const char* families) {
   if (!c) return CPM_EINVAL;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   resolve_timing(c, true);
   c->totals.clear();
-  c->timing = on != 0;
+  c->timing_only.clear();
+  c->timing = families && families[0];
+  if (c->timing && std::strcmp(families, "*") != 0) {
+    std::string cur;
+    for (const char* p = families;; ++p) {
+      if (*p == ',' || *p == 0) {
+        if (!cur.empty()) c->timing_only.push_back(cur);
+        cur.clear();
+        if (*p == 0) break;
+      } else if (*p != ' ') {
+        cur.push_back(*p);
+      }
+    }
+  }
   return CPM_OK;
 }
 
@@ -900,12 +945,12 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.ex); dfree(b.ey); dfree(b.ez); dfree(b.efx); dfree(b.efy); dfree(b.efz); dfree(b.eid);
   dfree(b.layer_of); dfree(b.layer_fz); dfree(b.layerT);
   dfree(b.sc_nx); dfree(b.sc_ny); dfree(b.sc_lo); dfree(b.sc_len); dfree(b.sc_koff); dfree(b.sc_n0);
-  dfree(b.sc_nidx); dfree(b.tile_nb); dfree(b.sfm_part);
+  dfree(b.sc_nidx); dfree(b.tile_nb); dfree(b.sfm_part); dfree(b.sfm_items); dfree(b.sft);
   dfree(b.runs); dfree(b.cols); dfree(b.chunk_col); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.mz); dfree(b.qt);
-  dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means);
+  dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

@@ -33,6 +33,15 @@ struct KCol {
   int pad;
 };
 
+constexpr int SFM_NB = 4;          // 16-wide n blocks per matrix-core structure-factor work item
+
+// charges per chunk of the matrix-core structure factors (a multiple of 16)
+inline int sf_mfma_chunk(int mpad, int mchunks) {
+  return (((mpad + mchunks - 1) / mchunks) + 15) / 16 * 16;
+}
+
+constexpr int RS_NT = 2048;        // intervals of the real-space pair table on [0, rc]
+
 constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
 constexpr int MAX_LAYERS = 64;     // planar-electrode factorisation up to this many z planes
 
@@ -51,7 +60,9 @@ struct Buffers {
   // matrix-core structure factors: full (k_x, k_y) columns sorted by k_z extent
   int* sc_nx = nullptr; int* sc_ny = nullptr; int* sc_lo = nullptr; int* sc_len = nullptr;
   int* sc_koff = nullptr; int* sc_n0 = nullptr; int* sc_nidx = nullptr; int* tile_nb = nullptr;
-  double* sfm_part = nullptr;      // chunk partials [chunk][tile][64][npadc]
+  double* sfm_part = nullptr;      // chunk partials [chunk][tile][32][npadc]
+  int4* sfm_items = nullptr;       // work items {M tile, first n block, n blocks, 0}
+  double2* sft = nullptr;          // per-charge phase tables (rows x mpad)
   double* w2 = nullptr;            // 2 W(k), nk (flat run order)
   int* knx = nullptr; int* kny = nullptr; int* knz = nullptr;     // nk
   // dense matrices, npad x npad row-major FP64 unless noted
@@ -75,6 +86,7 @@ struct Buffers {
   double* phik_part = nullptr;     // k-chunk partial potentials (n * kchunks)
   double* phir_part = nullptr;     // m-chunk partial real-space potentials (n * rchunks)
   double* mz = nullptr;            // electrolyte dipole partials M_z (per SF chunk)
+  double* rtab = nullptr;          // real-space pair table (g, g', g'') x (RS_NT + 1)
   double* qt = nullptr;            // q-tilde (batch x npad)
   double* res = nullptr;           // refinement residual / corrections (batch x npad)
   double* bpad = nullptr;          // padded b for batched solves (bpad_rows x npad)
@@ -96,6 +108,7 @@ struct cpm_ctx {
   int nk = 0, nruns = 0;
   int mchunks = 1, kchunks = 1, rchunks = 1;
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
+  int sfm_wg_target = 768;         // the same for the matrix-core kernel
   unsigned store = 0;
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;
@@ -113,6 +126,8 @@ struct cpm_ctx {
   bool sf_mfma = false;            // structure factors on FP64 matrix cores (k set fits)
   bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
   int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_chunks = 1, sfm_ntot = 0;
+  int sfm_nbz = 2, sfm_nitems = 0, mpad = 0, sft_rows = 0, sft_blocks = 1;
+  std::vector<int4> h_sfm_items;
   std::vector<int> h_sc_nx, h_sc_ny, h_sc_lo, h_sc_len, h_sc_koff, h_sc_n0, h_sc_nidx, h_tile_nb;
   std::vector<double> h_w2;
   std::vector<int> h_kx, h_ky, h_kz;
@@ -124,6 +139,7 @@ struct cpm_ctx {
   unsigned graph_store = 0;            // copies of S the captured solve reads
   // kernel timing (cpm_enable_timing)
   bool timing = false;
+  std::vector<std::string> timing_only;   // empty: every family
   struct Pending { const char* name; hipEvent_t a, b; };
   std::vector<Pending> pending;
   std::vector<hipEvent_t> evpool;
@@ -189,10 +205,12 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
                                int m, int mchunks, const double* xyz, const double* q,
                                double Lx, double Ly, double Lz, int nxm, int nym, int nzm,
                                double* part, double* mz_part);
-void launch_b_sf_mfma(hipStream_t st, int m, int mchunks, int mtiles, const int* sc_nx,
-                      const int* sc_ny, const int* tile_nb, int ncolsort, const double* xyz,
-                      const double* q, double Lx, double Ly, double Lz, int nxm, int nym,
-                      int npadc, double* part, double* mz_part);
+void launch_b_sf_tables(hipStream_t st, int m, int mpad, int nxm, int nym, int nbz,
+                        const double* xyz, const double* q, double Lx, double Ly, double Lz,
+                        double2* tab, double* mz_part);
+void launch_b_sf_mfma(hipStream_t st, int mpad, int mchunks, int nitems, const int4* items,
+                      int mtiles, const int* sc_nx, const int* sc_ny, int ncolsort, int nxm,
+                      int nym, const double2* tab, int npadc, double* part);
 void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int mtiles, int mchunks, int npadc,
                              const int* sc_lo, const int* sc_len, const int* sc_koff,
                              const int* sc_n0, const int* n_index, int n_total,
@@ -207,9 +225,10 @@ void launch_b_layer_project(hipStream_t st, int n, int ncols, int nlayers, const
                             const int* layer_of, const double* layer_fz, const Buffers& b,
                             const double* sfw, double2* T, double* part);
 int layer_project_chunks(int ncols);
+void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab);
 void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
                          const double* xyz, const double* q, double Lx, double Ly, double rc,
-                         double alpha, double eta, double* part);
+                         double* part);
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchunks,
                       const double* phik, const double* phir, const Buffers& b,
                       const double* mz_part, double slab_coef, double ke, void* out,

@@ -292,61 +292,97 @@ void launch_convert_S(hipStream_t st, int npad, const double* S, float* S32, uin
 
 // ---------------------------------------------------------------------------
 // Matrix-vector product y[b] = sign * M x[b] + addscale * add, streaming the
-// npad x npad matrix M (FP64 or FP32) once per vector.  One wave per row:
-// 16-byte coalesced loads of the row, x read through the cache, wave
-// reduction in a fixed order.
+// npad x npad matrix M (FP64 or FP32) once per vector.  One wave per R
+// consecutive rows: 16-byte coalesced loads of each row, every x element
+// read once per wave (through the cache) for all R rows, FP64 accumulation,
+// wave reductions in a fixed order.
 // ---------------------------------------------------------------------------
-template <typename TM>
+template <typename TM, int R>
 __global__ void __launch_bounds__(256) k_matvec(int n, int npad, const TM* __restrict__ M,
                                                 const void* __restrict__ xv, int x_is_f32, int ldx,
                                                 const double* __restrict__ xshift,
                                                 const double* __restrict__ add, int add_ld,
                                                 double addscale, double* __restrict__ y, int ldy,
                                                 int negate) {
-  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
+  const int row0 = (blockIdx.x * 4 + (threadIdx.x >> 6)) * R;   // R consecutive rows per wave
   const int b = blockIdx.y;
-  if (row >= npad) return;
+  if (row0 >= npad) return;                  // npad is a multiple of 64, so all R rows exist
   constexpr int VEC = 16 / sizeof(TM);
-  const TM* mrow = M + (size_t)row * npad;
+  const TM* mrow = M + (size_t)row0 * npad;
   const double* xd = reinterpret_cast<const double*>(xv) + (size_t)b * ldx;
   const float* xf = reinterpret_cast<const float*>(xv) + (size_t)b * ldx;
   const double sh = xshift ? xshift[b] : 0.0;
-  double s = 0.0;
+  double acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = 0.0;
+#pragma unroll 2
   for (int j0 = lane * VEC; j0 < npad; j0 += 64 * VEC) {
-    TM mv[VEC];
-    if constexpr (VEC == 2) {
-      const double2 t = *reinterpret_cast<const double2*>(mrow + j0);
-      mv[0] = t.x; mv[1] = t.y;
-    } else {
-      const float4 t = *reinterpret_cast<const float4*>(mrow + j0);
-      mv[0] = t.x; mv[1] = t.y; mv[2] = t.z; mv[3] = t.w;
+    // the R row segments first (R x 16 B in flight per lane), then x once for all rows
+    TM mv[R][VEC];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if constexpr (VEC == 2) {
+        const double2 t = *reinterpret_cast<const double2*>(mrow + (size_t)r * npad + j0);
+        mv[r][0] = t.x; mv[r][1] = t.y;
+      } else {
+        const float4 t = *reinterpret_cast<const float4*>(mrow + (size_t)r * npad + j0);
+        mv[r][0] = t.x; mv[r][1] = t.y; mv[r][2] = t.z; mv[r][3] = t.w;
+      }
     }
+    double xj[VEC];
 #pragma unroll
     for (int t = 0; t < VEC; ++t) {
       const int j = j0 + t;
-      double xj = 0.0;
-      if (j < n) xj = (x_is_f32 ? (double)xf[j] : xd[j]) - sh;
-      s += (double)mv[t] * xj;
+      xj[t] = j < n ? (x_is_f32 ? (double)xf[j] : xd[j]) - sh : 0.0;
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int t = 0; t < VEC; ++t) acc[r] += (double)mv[r][t] * xj[t];
   }
-  s = wave_sum(s);
-  if (lane == 0 && row < npad) {
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r] = wave_sum(acc[r]);
+  if (lane < R) {
+    double s = acc[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r)
+      if (lane == r) s = acc[r];
+    const int row = row0 + lane;
     double v = negate ? -s : s;
     if (add) v += addscale * add[(size_t)b * add_ld + row];
     y[(size_t)b * ldy + row] = v;
   }
 }
 
+template <typename TM>
+void launch_matvec_t(hipStream_t st, int n, int npad, const TM* M, int batch, const void* x,
+                     int x_is_f32, int ldx, const double* xshift, const double* add, int add_ld,
+                     double addscale, double* y, int ldy, int negate) {
+  // rows per wave: enough waves to fill the chip (>= ~2048 per vector), and
+  // as many rows as that allows so each x load serves R rows
+  const int R = npad >= 16384 ? 8 : npad >= 8192 ? 4 : npad >= 4096 ? 2 : 1;
+  dim3 grid((npad / R + 3) / 4, batch), block(256);
+#define CPM_MV(RR)                                                                           \
+  hipLaunchKernelGGL((k_matvec<TM, RR>), grid, block, 0, st, n, npad, M, x, x_is_f32, ldx,   \
+                     xshift, add, add_ld, addscale, y, ldy, negate)
+  if (R == 8) CPM_MV(8); else if (R == 4) CPM_MV(4); else if (R == 2) CPM_MV(2); else CPM_MV(1);
+#undef CPM_MV
+}
+
+// One matrix-vector product per right-hand side: y = M (x - shift) (+ add),
+// M npad x npad row-major (FP64 or FP32), streamed once per vector with
+// 16-byte coalesced loads; R rows per wave share each x load; fixed-order
+// wave reductions.
 void launch_matvec(hipStream_t st, int which, int n, int npad, const void* M, int batch,
                    const void* x, int x_is_f32, int ldx, const double* xshift, const double* add,
                    int add_ld, double addscale, double* y, int ldy, int negate) {
-  dim3 grid(npad / 4, batch), block(256);
   if (which == 0)
-    hipLaunchKernelGGL(k_matvec<double>, grid, block, 0, st, n, npad, (const double*)M, x,
-                       x_is_f32, ldx, xshift, add, add_ld, addscale, y, ldy, negate);
+    launch_matvec_t(st, n, npad, (const double*)M, batch, x, x_is_f32, ldx, xshift, add, add_ld,
+                    addscale, y, ldy, negate);
   else
-    hipLaunchKernelGGL(k_matvec<float>, grid, block, 0, st, n, npad, (const float*)M, x,
-                       x_is_f32, ldx, xshift, add, add_ld, addscale, y, ldy, negate);
+    launch_matvec_t(st, n, npad, (const float*)M, batch, x, x_is_f32, ldx, xshift, add, add_ld,
+                    addscale, y, ldy, negate);
 }
 
 // means[b] = (1/n) sum_{i<n} x[b][i]: the uniform part of a right-hand side.

@@ -294,6 +294,14 @@ def test_kernel_timing(cpm):
         ms, cnt = ctx.timing(fam)
         assert cnt >= 1 and ms > 0, fam
     assert ctx.timing("no_such_kernel") == (0.0, 0)
+    ctx.enable_timing(["structure_factor", "matvec_f64"])     # only these two families
+    ctx.potential_vector(xyz, b)
+    ctx.solve_charges(b, 0, q)
+    assert ctx.timing("structure_factor")[1] >= 1 and ctx.timing("matvec_f64")[1] >= 1
+    assert ctx.timing("real_space_b") == (0.0, 0) and ctx.timing("finalize") == (0.0, 0)
+    ctx.enable_timing(False)
+    ctx.potential_vector(xyz, b)
+    assert ctx.timing("structure_factor") == (0.0, 0)
     ctx.close()
 
 
