@@ -170,11 +170,14 @@ def main():
     # dominant kernel: the structure factors
     nk = int(ctx.info("nk"))
     sf_avg = sf_ms / max(sf_cnt, 1) * 1e-3
-    flop_per_launch = 8.0 * nk * w.m          # complex rotation + accumulate per (k, charge)
+    # 8 flop per (k, charge) pair (complex rotate-and-accumulate); one launch
+    # covers the configurations of one launch group
+    snaps_per_launch = B * args.steps / max(sf_cnt, 1)
+    flop_per_launch = 8.0 * nk * w.m * snaps_per_launch
     achieved = flop_per_launch / sf_avg if sf_avg > 0 else 0.0
     peak = PEAK_FP64_VALU      # the phases and rotations are FP64 in every mode
     traffic = stored_traffic(args.workload, sf_cnt)
-    sf_bound = "mfma" if (ctx.info("sf_matrix") == 1.0 and not b_f32) else "alu"
+    sf_bound = "mfma" if ctx.info("sf_matrix") == 1.0 else "alu"
 
     value = B * args.steps / elapsed
     out = {
@@ -197,7 +200,8 @@ def main():
         "roofline": {"kernel": "structure_factor", "bound": sf_bound,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "flop_per_launch": flop_per_launch, "avg_launch_us": sf_avg * 1e6},
+                     "flop_per_launch": flop_per_launch, "avg_launch_us": sf_avg * 1e6,
+                     "configurations_per_launch": snaps_per_launch},
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),
         "plain_fp64_per_step_rate": plain_rate,

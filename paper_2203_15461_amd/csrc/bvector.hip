@@ -196,7 +196,7 @@ constexpr int SFM_COLS = 16;           // columns per M tile (32 GEMM rows)
 
 struct SfmWave {                        // wave-private LDS area
   double C[2 * SFM_COLS][SFM_TJ + 1];  // A operand rows (Re C, Im C) x charges
-  double2 z0[SFM_TJ][8];               // e^{2 pi i (n_lo + j) fz_t}, j = 0..7
+  double2 z0[8][SFM_TJ + 1];           // e^{2 pi i (n_lo + j) fz_t}, j = 0..7 (padded rows)
   double2 r8[SFM_TJ];                  // e^{2 pi i 8 fz_t}
 };
 
@@ -217,20 +217,22 @@ __device__ inline double2 cmul2(double2 a, double2 b) {
 //   rows nxm+1 + [0, 2 nym]    Y_b(j) = q_j e^{2 pi i (b - nym) fy_j}
 //   next 8 rows                Z1_i(j) = e^{2 pi i i fz_j}
 //   next nbz rows              Z8_c(j) = e^{2 pi i 8 c fz_j}
-// Workgroups of row 0 also leave M_z partials sum q_j z_j per 256 charges.
-__global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int nym, int nbz,
+//   last row                   zero (the C operand of absent columns)
+// blockIdx.z selects the configuration of the group (tables tab_stride
+// apart).  Workgroups of row 0 also leave M_z partials sum q_j z_j per 256
+// charges (mz_stride apart per configuration).
+__global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int nym,
                                                    const double* __restrict__ xyz,
                                                    const double* __restrict__ q, double Lx,
-                                                   double Ly, double Lz,
-                                                   double2* __restrict__ tab,
+                                                   double Ly, double Lz, size_t tab_stride,
+                                                   double2* __restrict__ tab, int mz_stride,
                                                    double* __restrict__ mz_part) {
   __shared__ double s_mz[4];
-  const int row = blockIdx.y;
+  const int row = blockIdx.y, snap = blockIdx.z;
   const int j = blockIdx.x * 256 + threadIdx.x;
-  const int ny_rows = 2 * nym + 1;
-  const int rX = 0, rY = nxm + 1, rZ1 = rY + ny_rows, rZ8 = rZ1 + 8;
-  (void)rX;
-  (void)nbz;
+  const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
+  xyz += (size_t)snap * m * 3;
+  tab += (size_t)snap * tab_stride;
   double qq = 0.0, zz = 0.0;
   if (j < m) { qq = q[j]; zz = xyz[3 * j + 2]; }
   if (j < mpad) {
@@ -243,8 +245,10 @@ __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int
         f = xyz[3 * j + 1] / Ly; f -= floor(f); idx = row - rY - nym; scale = qq;
       } else if (row < rZ8) {
         f = zz / Lz; f -= floor(f); idx = row - rZ1;
-      } else {
+      } else if (row < (int)gridDim.y - 1) {
         f = zz / Lz; f -= floor(f); idx = 8.0 * (row - rZ8);
+      } else {
+        f = 0.0; idx = 0.0; scale = 0.0;
       }
       double th = idx * f;
       th -= rint(th);
@@ -259,17 +263,21 @@ __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int
     for (int o = 32; o > 0; o >>= 1) mz += __shfl_xor(mz, o, 64);
     if ((threadIdx.x & 63) == 0) s_mz[threadIdx.x >> 6] = mz;
     __syncthreads();
-    if (threadIdx.x == 0) mz_part[blockIdx.x] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
+    if (threadIdx.x == 0)
+      mz_part[(size_t)snap * mz_stride + blockIdx.x] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
   }
 }
 
-void launch_b_sf_tables(hipStream_t st, int m, int mpad, int nxm, int nym, int nbz,
+int sf_table_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) + 8 + nbz + 1; }
+
+void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
                         double2* tab, double* mz_part) {
-  const int rows = (nxm + 1) + (2 * nym + 1) + 8 + nbz;
-  dim3 grid((mpad + 255) / 256, rows), block(256);
-  hipLaunchKernelGGL(k_sf_tables, grid, block, 0, st, m, mpad, nxm, nym, nbz, xyz, q, Lx, Ly, Lz,
-                     tab, mz_part);
+  const int rows = sf_table_rows(nxm, nym, nbz);
+  const int blocks = (mpad + 255) / 256;
+  dim3 grid(blocks, rows, g), block(256);
+  hipLaunchKernelGGL(k_sf_tables, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly, Lz,
+                     (size_t)rows * mpad, tab, blocks, mz_part);
 }
 
 // Structure factors of full (k_x, k_y) columns as a real GEMM on FP64 matrix
@@ -285,22 +293,25 @@ void launch_b_sf_tables(hipStream_t st, int m, int mpad, int nxm, int nym, int n
 // range from Z8 x Z1 into a wave-private LDS area, then runs
 // v_mfma_f64_16x16x4f64 with the B operand advanced in registers by
 // e^{2 pi i 8 fz} per 16-wide block.  The 4 waves are summed in a fixed order.
-// part[((chunk * mtiles + mt) * 32 + row) * npadc + col]: this chunk's sums.
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_sf_mfma(int mpad, int chunk_size, int mtiles,
-                                                 int nitems, const int4* __restrict__ items,
-                                                 const int* __restrict__ sc_nx,
-                                                 const int* __restrict__ sc_ny, int ncolsort,
-                                                 int nxm, int nym,
-                                                 const double2* __restrict__ tab, int npadc,
-                                                 double* __restrict__ part) {
+// Output, per configuration s and chunk: tile mt's 32 x 16 nb_mt block at
+// part + (s * nchunks + chunk) * pchunk + toff[mt], row-major.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_sf_mfma(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restrict__ items,
+          const int* __restrict__ sc_nx, const int* __restrict__ sc_ny, int ncolsort, int nxm,
+          int nym, const double2* __restrict__ tab, size_t tab_stride,
+          const int* __restrict__ tile_nb, const int* __restrict__ toff, int pchunk,
+          double* __restrict__ part) {
   __shared__ SfmWave wl[4];
   __shared__ double red[64 * 2 * SFM_NB * 4];      // one wave's accumulators
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  // workgroups go round-robin to the 8 XCDs; keep every charge chunk on one
-  // XCD (chunk = xcd mod 8) so its table rows stay in that XCD's L2
+  // workgroups go round-robin to the 8 XCDs; keep every (configuration,
+  // charge chunk) pair on one XCD (pair = xcd mod 8) so its table rows stay
+  // in that XCD's L2
   const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
   const int item = slot % nitems;
-  const int chunk = xcd + 8 * (slot / nitems);
+  const int pair = xcd + 8 * (slot / nitems);
+  const int snap = pair / nchunks, chunk = pair % nchunks;
+  tab += (size_t)snap * tab_stride;
   const int4 it = items[item];
   const int mt = it.x, nb_lo = it.y, nbw = it.z;
   const int c_base = mt * SFM_COLS;
@@ -309,16 +320,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   const int t_l = lane & 15, g_l = lane >> 4;     // this lane's charge in the tile, lane group
   const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
   // table rows of this lane's four columns g_l + 4u (columns past the end: C = 0)
-  // (32-bit element offsets: the tables stay far below 2^31 entries)
+  // (32-bit element offsets: the tables stay far below 2^31 entries);
+  // columns past the end read the zero row, so their C is zero
+  const int rzero = (int)(tab_stride / mpad) - 1;
   int xoff[4], yoff[4];
-  bool ok[4];
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int cl = g_l + 4 * u;
-    ok[u] = cl < ncol;
-    const int nx = ok[u] ? sc_nx[c_base + cl] : 0, ny = ok[u] ? sc_ny[c_base + cl] : 0;
-    xoff[u] = nx * mpad + t_l;
-    yoff[u] = (rY + ny + nym) * mpad + t_l;
+    const bool ok = cl < ncol;
+    xoff[u] = (ok ? sc_nx[c_base + cl] : rzero) * mpad + t_l;
+    yoff[u] = (ok ? rY + sc_ny[c_base + cl] + nym : rzero) * mpad + t_l;
   }
   const int z8off = (rZ8 + nb_lo) * mpad + t_l, r8off = (rZ8 + 1) * mpad + t_l;
   const int z1off = (rZ1 + 2 * g_l) * mpad + t_l;
@@ -343,11 +354,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       for (int u = 0; u < 4; ++u) {
         const int cl = g_l + 4 * u;
         const double2 cv = cmul2(xv[u], yv[u]);
-        W.C[2 * cl][t_l] = ok[u] ? cv.x : 0.0;
-        W.C[2 * cl + 1][t_l] = ok[u] ? cv.y : 0.0;
+        W.C[2 * cl][t_l] = cv.x;
+        W.C[2 * cl + 1][t_l] = cv.y;
       }
-      W.z0[t_l][2 * g_l] = cmul2(z8, za);
-      W.z0[t_l][2 * g_l + 1] = cmul2(z8, zb);
+      W.z0[2 * g_l][t_l] = cmul2(z8, za);
+      W.z0[2 * g_l + 1][t_l] = cmul2(z8, zb);
       if (g_l == 0) W.r8[t_l] = r8n;
     }
     wave_lds_sync();
@@ -357,7 +368,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       const int kc = 4 * ks + g_l;                    // k index (charge) of this lane's operands
       const double a0 = W.C[t_l][kc];                 // rows 0..15
       const double a1 = W.C[16 + t_l][kc];            // rows 16..31
-      double2 z = W.z0[kc][t_l >> 1];
+      double2 z = W.z0[t_l >> 1][kc];
       const double2 r8 = W.r8[kc];
       const bool im = t_l & 1;
 #pragma unroll
@@ -395,7 +406,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
   }
   if (wave == 0) {
     // result register r of lane l: row (l >> 4) + 4 r, column l & 15 of block b
-    double* out = part + ((size_t)chunk * mtiles + mt) * 32 * (size_t)npadc;
+    const int ldc = 16 * tile_nb[mt];
+    double* out = part + ((size_t)snap * nchunks + chunk) * pchunk + toff[mt];
 #pragma unroll
     for (int b = 0; b < SFM_NB; ++b) {
       if (b >= nbw) continue;
@@ -403,30 +415,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
       for (int r = 0; r < 4; ++r) {
         const int row = (lane >> 4) + 4 * r;
         const int col = 16 * (nb_lo + b) + (lane & 15);
-        out[(size_t)row * npadc + col] = acc0[b][r];
-        out[(size_t)(16 + row) * npadc + col] = acc1[b][r];
+        out[row * ldc + col] = acc0[b][r];
+        out[(16 + row) * ldc + col] = acc1[b][r];
       }
     }
   }
 }
 
-void launch_b_sf_mfma(hipStream_t st, int mpad, int mchunks, int nitems, const int4* items,
-                      int mtiles, const int* sc_nx, const int* sc_ny, int ncolsort, int nxm,
-                      int nym, const double2* tab, int npadc, double* part) {
-  // mchunks is a multiple of 8 (one residue class of chunks per XCD)
-  const int chunk_size = sf_mfma_chunk(mpad, mchunks);
-  dim3 grid(nitems * mchunks), block(256);
-  hipLaunchKernelGGL(k_sf_mfma, grid, block, 0, st, mpad, chunk_size, mtiles, nitems, items, sc_nx,
-                     sc_ny, ncolsort, nxm, nym, tab, npadc, part);
+void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
+                      const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
+                      const double2* tab, const int* tile_nb, const int* toff, int pchunk,
+                      double* part) {
+  // nchunks is a multiple of 8 (one residue class of pairs per XCD)
+  const int chunk_size = sf_mfma_chunk(mpad, nchunks);
+  const size_t tab_stride = (size_t)sf_table_rows(nxm, nym, nbz) * mpad;
+  dim3 grid(nitems * nchunks * g), block(256);
+  hipLaunchKernelGGL(k_sf_mfma, grid, block, 0, st, mpad, chunk_size, nchunks, nitems, items, sc_nx,
+                     sc_ny, ncolsort, nxm, nym, tab, tab_stride, tile_nb, toff, pchunk, part);
 }
 
 // Sum the chunks of the matrix-core structure factors and scatter them to
 // the flat k order: thread per (sorted column, n >= 0); sfw = 2W S.
-__global__ void k_sf_mfma_reduce(int ncolsort, int mtiles, int mchunks, int npadc,
+__global__ void k_sf_mfma_reduce(int ncolsort, int nchunks, int pchunk,
+                                 const int* __restrict__ tile_nb, const int* __restrict__ toff,
                                  const int* __restrict__ sc_lo, const int* __restrict__ sc_len,
-                                 const int* __restrict__ sc_koff, const int* __restrict__ sc_n0,
-                                 const double* __restrict__ part, const double* __restrict__ w2,
-                                 double* __restrict__ sfw, const int* __restrict__ n_index) {
+                                 const int* __restrict__ sc_koff, const double* __restrict__ part,
+                                 const double* __restrict__ w2, double* __restrict__ sfw,
+                                 const int* __restrict__ n_index) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n_index[ncolsort]) return;
   // binary search of the column owning entry e
@@ -435,16 +450,16 @@ __global__ void k_sf_mfma_reduce(int ncolsort, int mtiles, int mchunks, int npad
     const int mid = (lo + hi) >> 1;
     if (n_index[mid] <= e) lo = mid; else hi = mid;
   }
-  const int c = lo, n = e - n_index[c] + sc_n0[c];
-  const int mt = c / SFM_COLS, cl = c % SFM_COLS;
+  const int c = lo, n = e - n_index[c];
+  const int mt = c / SFM_COLS, cl = c % SFM_COLS, ldc = 16 * tile_nb[mt];
   double pr = 0, qr = 0, pi = 0, qi = 0;
 #pragma unroll 4
-  for (int ch = 0; ch < mchunks; ++ch) {
-    const double* base = part + ((size_t)ch * mtiles + mt) * 32 * (size_t)npadc;
-    pr += base[(size_t)(2 * cl) * npadc + 2 * n];
-    qr += base[(size_t)(2 * cl) * npadc + 2 * n + 1];
-    pi += base[(size_t)(2 * cl + 1) * npadc + 2 * n];
-    qi += base[(size_t)(2 * cl + 1) * npadc + 2 * n + 1];
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const double* base = part + (size_t)ch * pchunk + toff[mt];
+    pr += base[(2 * cl) * ldc + 2 * n];
+    qr += base[(2 * cl) * ldc + 2 * n + 1];
+    pi += base[(2 * cl + 1) * ldc + 2 * n];
+    qi += base[(2 * cl + 1) * ldc + 2 * n + 1];
   }
   const int clo = sc_lo[c], chi = sc_lo[c] + sc_len[c] - 1;
   if (n >= clo && n <= chi) {
@@ -459,13 +474,119 @@ __global__ void k_sf_mfma_reduce(int ncolsort, int mtiles, int mchunks, int npad
   }
 }
 
-void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int mtiles, int mchunks, int npadc,
-                             const int* sc_lo, const int* sc_len, const int* sc_koff,
-                             const int* sc_n0, const int* n_index, int n_total,
-                             const double* part, const double* w2, double* sfw) {
+void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int nchunks, int pchunk,
+                             const int* tile_nb, const int* toff, const int* sc_lo,
+                             const int* sc_len, const int* sc_koff, const int* n_index,
+                             int n_total, const double* part, const double* w2, double* sfw) {
   hipLaunchKernelGGL(k_sf_mfma_reduce, dim3((n_total + 255) / 256), dim3(256), 0, st, ncolsort,
-                     mtiles, mchunks, npadc, sc_lo, sc_len, sc_koff, sc_n0, part, w2, sfw,
+                     nchunks, pchunk, tile_nb, toff, sc_lo, sc_len, sc_koff, part, w2, sfw,
                      n_index);
+}
+
+// Planar electrodes: sum the chunks of the matrix-core structure factors and
+// fold k_z into the electrode planes in one pass.  For sorted column c and
+// plane L,
+//   T(c, L) = sum_{n in column} 2W(c, n) S(c, n) e^{-i n kz1 z_L},
+// so that phi_i = sum_c Re[e^{-i (kx x_i + ky y_i)} T(c, L_i)].  One wave per
+// (column, configuration): lanes take n >= 0 (both signs), keep the weighted
+// S(c, +-n) in LDS, then one fixed-order wave sum per plane.
+// pz[L * nzt + n] = e^{-2 pi i n fz_L};  T[(c * nlayers + L) * g + s].
+__global__ void __launch_bounds__(64) k_sf_layer_reduce(
+    int ncolsort, int nchunks, int pchunk, int nlayers, int nzt, const int* __restrict__ tile_nb,
+    const int* __restrict__ toff, const int* __restrict__ sc_lo, const int* __restrict__ sc_len,
+    const int* __restrict__ sc_koff, const int* __restrict__ n_index,
+    const double* __restrict__ part, const double* __restrict__ w2,
+    const double2* __restrict__ pz, double2* __restrict__ T) {
+  extern __shared__ double2 s_sw[];                    // [2][n count]: S(+n) w, S(-n) w
+  const int c = blockIdx.x, snap = blockIdx.y, lane = threadIdx.x;
+  const int ncnt = n_index[c + 1] - n_index[c];        // n = 0 .. ncnt - 1
+  const int mt = c / SFM_COLS, cl = c % SFM_COLS, ldc = 16 * tile_nb[mt];
+  const int clo = sc_lo[c], chi = sc_lo[c] + sc_len[c] - 1, koff = sc_koff[c];
+  const double* base0 = part + (size_t)snap * nchunks * pchunk + toff[mt];
+  for (int n = lane; n < ncnt; n += 64) {
+    double pr = 0, qr = 0, pi = 0, qi = 0;
+    for (int ch = 0; ch < nchunks; ++ch) {
+      const double* base = base0 + (size_t)ch * pchunk;
+      pr += base[(2 * cl) * ldc + 2 * n];
+      qr += base[(2 * cl) * ldc + 2 * n + 1];
+      pi += base[(2 * cl + 1) * ldc + 2 * n];
+      qi += base[(2 * cl + 1) * ldc + 2 * n + 1];
+    }
+    double2 sp = make_double2(0.0, 0.0), sm = make_double2(0.0, 0.0);
+    if (n >= clo && n <= chi) {
+      const double w = w2[koff + (n - clo)];
+      sp = make_double2(w * (pr - qi), w * (pi + qr));
+    }
+    if (n > 0 && -n >= clo && -n <= chi) {
+      const double w = w2[koff + (-n - clo)];
+      sm = make_double2(w * (pr + qi), w * (pi - qr));
+    }
+    s_sw[n] = sp;
+    s_sw[ncnt + n] = sm;
+  }
+  __syncthreads();
+  for (int L = 0; L < nlayers; ++L) {
+    double tr = 0.0, ti = 0.0;
+    for (int n = lane; n < ncnt; n += 64) {
+      const double2 p = pz[(size_t)L * nzt + n];      // e^{-i n kz1 z_L}
+      const double2 sp = s_sw[n], sm = s_sw[ncnt + n];
+      // sp * p + sm * conj(p)
+      tr += (sp.x * p.x - sp.y * p.y) + (sm.x * p.x + sm.y * p.y);
+      ti += (sp.x * p.y + sp.y * p.x) + (sm.y * p.x - sm.x * p.y);
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      tr += __shfl_xor(tr, o, 64);
+      ti += __shfl_xor(ti, o, 64);
+    }
+    if (lane == 0) T[((size_t)c * nlayers + L) * gridDim.y + snap] = make_double2(tr, ti);
+  }
+}
+
+void launch_b_sf_layer_reduce(hipStream_t st, int g, int ncolsort, int nchunks, int pchunk,
+                              int nlayers, int nzt, int max_ncnt, const int* tile_nb,
+                              const int* toff, const int* sc_lo, const int* sc_len,
+                              const int* sc_koff, const int* n_index, const double* part,
+                              const double* w2, const double2* pz, double2* T) {
+  const size_t shm = (size_t)2 * max_ncnt * sizeof(double2);
+  hipLaunchKernelGGL(k_sf_layer_reduce, dim3(ncolsort, g), dim3(64), shm, st, ncolsort, nchunks,
+                     pchunk, nlayers, nzt, tile_nb, toff, sc_lo, sc_len, sc_koff, n_index, part,
+                     w2, pz, T);
+}
+
+// Electrode in-plane phases of the sorted columns, E[c * n + i] =
+// (cos, sin)(kx x_i + ky y_i), and plane phases pz[L * nzt + n] =
+// e^{-2 pi i n fz_L}; both fixed while the electrodes are.
+__global__ void k_electrode_phase(int n, const int* __restrict__ sc_nx,
+                                  const int* __restrict__ sc_ny, const double* __restrict__ fx,
+                                  const double* __restrict__ fy, double2* __restrict__ E) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (i >= n) return;
+  double th = sc_nx[c] * fx[i] + sc_ny[c] * fy[i];
+  th -= rint(th);
+  double sn, cs;
+  sincospi(2.0 * th, &sn, &cs);
+  E[(size_t)c * n + i] = make_double2(cs, sn);
+}
+
+__global__ void k_plane_phase(int nlayers, int nzt, const double* __restrict__ layer_fz,
+                              double2* __restrict__ pz) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nlayers * nzt) return;
+  const int L = e / nzt, nn = e % nzt;
+  double th = nn * layer_fz[L];
+  th -= rint(th);
+  double sn, cs;
+  sincospi(2.0 * th, &sn, &cs);
+  pz[e] = make_double2(cs, -sn);
+}
+
+void launch_electrode_phases(hipStream_t st, int n, int ncolsort, const int* sc_nx,
+                             const int* sc_ny, const Buffers& b, int nlayers, int nzt,
+                             double2* E, double2* pz) {
+  hipLaunchKernelGGL(k_electrode_phase, dim3((n + 255) / 256, ncolsort), dim3(256), 0, st, n, sc_nx,
+                     sc_ny, b.efx, b.efy, E);
+  hipLaunchKernelGGL(k_plane_phase, dim3((nlayers * nzt + 255) / 256), dim3(256), 0, st, nlayers,
+                     nzt, b.layer_fz, pz);
 }
 
 // sfw[k] = 2 W(k) * sum_chunks part[chunk][k]   (fixed chunk order)
@@ -701,13 +822,26 @@ void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, doub
                      rc / RS_NT, tab);
 }
 
-// g(r) from the node table in LDS (quintic Hermite on the node's interval)
-__device__ inline double pair_g(const double* __restrict__ T, double r, double inv_h, double h) {
+// g(r) at r = sqrt(r2), 0 < r2 < rc^2, from the node table in LDS (quintic
+// Hermite on the node's interval).  sqrt by the hardware reciprocal square
+// root and two Newton steps (r2 is far from the denormal and overflow range
+// here, so no rescaling is needed).
+__device__ inline double pair_g(const double* __restrict__ T, double r2, double inv_h, double h) {
+  r2 = fmax(r2, 1e-200);
+  double y = __builtin_amdgcn_rsq(r2);
+  double r = r2 * y, hy = 0.5 * y;
+  double e = fma(-hy, r, 0.5);
+  r = fma(r, e, r); hy = fma(hy, e, hy);
+  e = fma(-r, r, r2);
+  r = fma(e, hy, r);
+  e = fma(-r, r, r2);
+  r = fma(e, hy, r);
   const double u = r * inv_h;
   const int k = min((int)u, RS_NT - 1);
   const double t = u - k;
-  const double g0 = T[3 * k], d0 = h * T[3 * k + 1], e0 = h * h * T[3 * k + 2];
-  const double g1 = T[3 * k + 3], d1 = h * T[3 * k + 4], e1 = h * h * T[3 * k + 5];
+  const double* Tk = T + 3 * k;
+  const double g0 = Tk[0], d0 = h * Tk[1], e0 = h * h * Tk[2];
+  const double g1 = Tk[3], d1 = h * Tk[4], e1 = h * h * Tk[5];
   const double D = g1 - g0;
   const double c3 = 10.0 * D - 6.0 * d0 - 4.0 * d1 - 1.5 * e0 + 0.5 * e1;
   const double c4 = -15.0 * D + 8.0 * d0 + 7.0 * d1 + 1.5 * e0 - e1;
@@ -715,11 +849,18 @@ __device__ inline double pair_g(const double* __restrict__ T, double r, double i
   return g0 + t * (d0 + t * (0.5 * e0 + t * (c3 + t * (c4 + t * c5))));
 }
 
-// Real-space part of phi_i over one chunk of the electrolyte: workgroup of
-// 256 electrode atoms; electrolyte tiles staged in LDS, keeping only charges
-// within rc in z of the workgroup's atoms (order-preserving compaction);
-// all in-plane images within rc; g(r) from the LDS pair table.
-__global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_size,
+// Real-space part of phi_i over one chunk of the electrolyte, for each of the
+// g configurations of a group (xyz m x 3 apart; output rows
+// part[(s * rchunks + chunk) * n + i]).  Threads map to electrode atoms
+// through amap, which groups the atoms of one z plane into whole waves (-1
+// pads), so each wave's z extent is small.  Every wave walks the chunk 64
+// charges at a time on its own: it keeps the charges within rc in z of its
+// atoms (order-preserving ballot compaction into a wave-private LDS area),
+// then each lane sums over them with all in-plane images within rc; g(r)
+// comes from the LDS pair table, staged once per workgroup.  The next 64
+// charges are loaded while the current ones are summed.
+__global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int chunk_size,
+                                                      const int* __restrict__ amap, int nmap,
                                                       const double* __restrict__ ex,
                                                       const double* __restrict__ ey,
                                                       const double* __restrict__ ez,
@@ -729,91 +870,97 @@ __global__ void __launch_bounds__(256) k_real_space_b(int n, int m, int chunk_si
                                                       const double* __restrict__ ptab,
                                                       double* __restrict__ part) {
   __shared__ double s_tab[3 * (RS_NT + 1)];
-  __shared__ double s_x[RS_TILE], s_y[RS_TILE], s_z[RS_TILE], s_q[RS_TILE];
-  __shared__ double s_zr[2][4];
-  __shared__ int s_cnt[4];
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ double s_c[4][4][64];                     // per wave: x, y, z, q of kept charges
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int chunk = blockIdx.y;
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  const int atom = slot < nmap ? amap[slot] : -1;
+  const int chunk = blockIdx.y, rchunks = gridDim.y;
   const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
   const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
   const double h = rc / RS_NT, inv_h = RS_NT / rc;
   const bool single = (Lx >= 2.0 * rc) && (Ly >= 2.0 * rc);
   for (int t = threadIdx.x; t < 3 * (RS_NT + 1); t += 256) s_tab[t] = ptab[t];
+  __syncthreads();
   double xi = 0, yi = 0, zi = 0;
-  if (i < n) { xi = ex[i]; yi = ey[i]; zi = ez[i]; }
-  // z interval of this workgroup's atoms: charges farther than rc from it
-  // cannot contribute and are dropped when a tile is staged
-  double zlo = i < n ? zi : 1e300, zhi = i < n ? zi : -1e300;
+  if (atom >= 0) { xi = ex[atom]; yi = ey[atom]; zi = ez[atom]; }
+  // this wave's z extent; charges farther than rc from it are dropped
+  double zlo = atom >= 0 ? zi : 1e300, zhi = atom >= 0 ? zi : -1e300;
   for (int o = 32; o > 0; o >>= 1) {
     zlo = fmin(zlo, __shfl_xor(zlo, o, 64));
     zhi = fmax(zhi, __shfl_xor(zhi, o, 64));
   }
-  if (lane == 0) { s_zr[0][wave] = zlo; s_zr[1][wave] = zhi; }
-  __syncthreads();
-  zlo = fmin(fmin(s_zr[0][0], s_zr[0][1]), fmin(s_zr[0][2], s_zr[0][3]));
-  zhi = fmax(fmax(s_zr[1][0], s_zr[1][1]), fmax(s_zr[1][2], s_zr[1][3]));
+  const double wlo = zlo - rc, whi = zhi + rc;
+  double (*C)[64] = s_c[wave];
+  const int nblk = j1 > j0 ? (j1 - j0 + 63) / 64 : 0;
+  const int steps = g * nblk;
+  double px = 0, py = 0, pzz = 0, pq = 0;
+  auto fetch = [&](int step) {
+    const int snap = step / nblk, j = j0 + (step % nblk) * 64 + lane;
+    if (j < j1) {
+      const double* r = xyz + ((size_t)snap * m + j) * 3;
+      px = r[0]; py = r[1]; pzz = r[2];
+      pq = q[j];
+    }
+  };
+  if (steps > 0) fetch(0);
   double acc = 0.0;
-  for (int jt = j0; jt < j1; jt += RS_TILE) {
-    const int nt = min(RS_TILE, j1 - jt);
-    double x = 0, y = 0, z = 0, qq = 0;
-    bool keep = false;
-    if ((int)threadIdx.x < nt) {
-      const int j = jt + threadIdx.x;
-      x = xyz[3 * j]; y = xyz[3 * j + 1]; z = xyz[3 * j + 2];
-      x -= Lx * floor(x * invLx);
-      y -= Ly * floor(y * invLy);
-      qq = q[j];
-      keep = (z > zlo - rc) && (z < zhi + rc);
-    }
-    // order-preserving compaction: ballot within the wave, wave offsets via LDS
+  for (int step = 0; step < steps; ++step) {
+    const int snap = step / nblk, blk = step % nblk;
+    const bool valid = j0 + blk * 64 + lane < j1;
+    double x = px, y = py, z = pzz, qq = pq;
+    if (step + 1 < steps) fetch(step + 1);
+    const bool keep = valid && z > wlo && z < whi;
     const unsigned long long bal = __ballot(keep);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    __syncthreads();
-    if (lane == 0) s_cnt[wave] = __popcll(bal);
-    __syncthreads();
-    int off = 0;
-    for (int w2 = 0; w2 < wave; ++w2) off += s_cnt[w2];
-    const int kept = s_cnt[0] + s_cnt[1] + s_cnt[2] + s_cnt[3];
+    const int kept = __popcll(bal);
     if (keep) {
-      s_x[off + before] = x; s_y[off + before] = y; s_z[off + before] = z;
-      s_q[off + before] = qq;
+      const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+      C[0][pos] = x - Lx * floor(x * invLx);
+      C[1][pos] = y - Ly * floor(y * invLy);
+      C[2][pos] = z;
+      C[3][pos] = qq;
     }
-    __syncthreads();
-    if (i >= n) continue;
-    for (int t = 0; t < kept; ++t) {
-      const double dz = zi - s_z[t];
-      if (fabs(dz) >= rc) continue;
-      double dx = xi - s_x[t], dy = yi - s_y[t];
-      dx -= Lx * rint(dx * invLx);
-      dy -= Ly * rint(dy * invLy);
-      if (single) {
-        const double r2 = dx * dx + dy * dy + dz * dz;
-        if (r2 < rc2) acc += s_q[t] * pair_g(s_tab, sqrt(r2), inv_h, h);
-      } else {
-        const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
-        const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
-        for (int a = alo; a <= ahi; ++a) {
-          const double X = dx + a * Lx;
-          for (int bb = blo; bb <= bhi; ++bb) {
-            const double Y = dy + bb * Ly;
-            const double r2 = X * X + Y * Y + dz * dz;
-            if (r2 < rc2) acc += s_q[t] * pair_g(s_tab, sqrt(r2), inv_h, h);
+    wave_lds_sync();
+    if (atom >= 0) {
+      for (int t = 0; t < kept; ++t) {
+        const double dz = zi - C[2][t];
+        if (fabs(dz) >= rc) continue;
+        double dx = xi - C[0][t], dy = yi - C[1][t];
+        dx -= Lx * rint(dx * invLx);
+        dy -= Ly * rint(dy * invLy);
+        if (single) {
+          const double r2 = dx * dx + dy * dy + dz * dz;
+          if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
+        } else {
+          const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
+          const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
+          for (int a = alo; a <= ahi; ++a) {
+            const double X = dx + a * Lx;
+            for (int bb = blo; bb <= bhi; ++bb) {
+              const double Y = dy + bb * Ly;
+              const double r2 = X * X + Y * Y + dz * dz;
+              if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
+            }
           }
         }
       }
     }
+    wave_lds_sync();
+    if (blk == nblk - 1) {
+      if (atom >= 0) part[((size_t)snap * rchunks + chunk) * n + atom] = acc;
+      acc = 0.0;
+    }
   }
-  if (i < n) part[(size_t)chunk * n + i] = acc;
+  if (nblk == 0 && atom >= 0)
+    for (int snap = 0; snap < g; ++snap) part[((size_t)snap * rchunks + chunk) * n + atom] = 0.0;
 }
 
-void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
-                         const double* xyz, const double* q, double Lx, double Ly, double rc,
-                         double* part) {
+void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
+                         int nmap, const double* xyz, const double* q, double Lx, double Ly,
+                         double rc, double* part) {
   const int chunk_size = (m + rchunks - 1) / rchunks;
-  dim3 grid((n + 255) / 256, rchunks), block(256);
-  hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, n, m, chunk_size, b.ex, b.ey, b.ez, xyz, q,
-                     Lx, Ly, rc, b.rtab, part);
+  dim3 grid((nmap + 255) / 256, rchunks), block(256);
+  hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, chunk_size, b.amap, nmap, b.ex,
+                     b.ey, b.ez, xyz, q, Lx, Ly, rc, b.rtab, part);
 }
 
 // b_i = -k_e (sum of k-space partials + sum of real-space partials
@@ -847,6 +994,88 @@ __global__ void __launch_bounds__(256) k_combine(int n, int kchunks, int rchunks
   else
     reinterpret_cast<double*>(out)[i] = b;
 }
+
+// Planar electrodes, a group of g configurations, step 1: partial k-space
+// potentials phi_k = sum_c [cos th_ci Re T(c, L_i) + sin th_ci Im T(c, L_i)]
+// over one group of columns, from the precomputed electrode phases E.
+// Workgroup: 64 atoms x 4 lanes groups; lane group u takes every 4th column
+// of the workgroup's column group and accumulates all g configurations;
+// the 4 partial sums are added in a fixed order.
+// part[(cg * g + s) * n + i].
+constexpr int LC_MAXG = 32;
+
+__global__ void __launch_bounds__(256) k_layer_project_g(int g, int n, int ncolsort, int cpg,
+                                                         int nlayers,
+                                                         const double2* __restrict__ E,
+                                                         const int* __restrict__ layer_of,
+                                                         const double2* __restrict__ T,
+                                                         double* __restrict__ part) {
+  __shared__ double red[3][LC_MAXG][64];
+  const int li = threadIdx.x & 63, u = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + li, cg = blockIdx.y;
+  const int c0 = cg * cpg, c1 = min(ncolsort, c0 + cpg);
+  const int L = i < n ? layer_of[i] : 0;
+  double acc[LC_MAXG];
+#pragma unroll
+  for (int s = 0; s < LC_MAXG; ++s) acc[s] = 0.0;
+  if (i < n) {
+    for (int c = c0 + u; c < c1; c += 4) {
+      const double2 e = E[(size_t)c * n + i];
+      const double2* tc = T + ((size_t)c * nlayers + L) * g;
+#pragma unroll
+      for (int s = 0; s < LC_MAXG; ++s)
+        if (s < g) {
+          const double2 t = tc[s];
+          acc[s] += e.x * t.x + e.y * t.y;
+        }
+    }
+  }
+  if (u > 0)
+#pragma unroll
+    for (int s = 0; s < LC_MAXG; ++s)
+      if (s < g) red[u - 1][s][li] = acc[s];
+  __syncthreads();
+  if (u == 0 && i < n)
+#pragma unroll
+    for (int s = 0; s < LC_MAXG; ++s)
+      if (s < g)
+        part[((size_t)cg * g + s) * n + i] =
+            (acc[s] + red[0][s][li]) + (red[1][s][li] + red[2][s][li]);
+}
+
+// step 2: b_i = -k_e (sum of column-group partials + sum of real-space
+// partials + (4 pi / V) z_i M_z), thread per (atom, configuration).
+__global__ void k_layer_final(int g, int n, int cgroups, const double* __restrict__ phik,
+                              const double* __restrict__ phir, int rchunks,
+                              const double* __restrict__ ez, const double* __restrict__ mz_part,
+                              int mz_parts, double slab_coef, double ke, void* out,
+                              int out_is_f32) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
+  if (i >= n) return;
+  double pk = 0.0, pr = 0.0, mz = 0.0;
+  for (int r = 0; r < cgroups; ++r) pk += phik[((size_t)r * g + s) * n + i];
+  for (int r = 0; r < rchunks; ++r) pr += phir[((size_t)s * rchunks + r) * n + i];
+  for (int r = 0; r < mz_parts; ++r) mz += mz_part[(size_t)s * mz_parts + r];
+  const double bv = -ke * ((pk + pr) + slab_coef * ez[i] * mz);
+  if (out_is_f32)
+    reinterpret_cast<float*>(out)[(size_t)s * n + i] = (float)bv;
+  else
+    reinterpret_cast<double*>(out)[(size_t)s * n + i] = bv;
+}
+
+void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlayers, int cgroups,
+                            const double2* E, const int* layer_of, const double2* T,
+                            double* phik, const double* phir, int rchunks, const double* ez,
+                            const double* mz_part, int mz_parts, double slab_coef, double ke,
+                            void* out, int out_is_f32) {
+  const int cpg = (ncolsort + cgroups - 1) / cgroups;
+  hipLaunchKernelGGL(k_layer_project_g, dim3((n + 63) / 64, cgroups), dim3(256), 0, st, g, n,
+                     ncolsort, cpg, nlayers, E, layer_of, T, phik);
+  hipLaunchKernelGGL(k_layer_final, dim3((n + 255) / 256, g), dim3(256), 0, st, g, n, cgroups,
+                     phik, phir, rchunks, ez, mz_part, mz_parts, slab_coef, ke, out, out_is_f32);
+}
+
+int layer_combine_max_group() { return LC_MAXG; }
 
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchunks,
                       const double* phik, const double* phir, const Buffers& b,

@@ -170,6 +170,17 @@ void build_kset(cpm_ctx* c, std::vector<KRun>& runs, std::vector<double>& w2,
     }
 }
 
+// charge chunks per configuration for a group of g configurations on the
+// matrix-core structure-factor path: about sfm_wg_target workgroups, and
+// g * chunks a multiple of 8 (the kernel keeps each (configuration, chunk)
+// pair on one XCD)
+int sf_chunks_for(const cpm_ctx* c, int g) {
+  const int base = std::max(1, (c->sfm_wg_target + c->sfm_nitems * g - 1) / (c->sfm_nitems * g));
+  int step = 8;
+  while (step > 1 && g % (8 / step * 2) == 0) step /= 2;   // step = 8 / gcd(g, 8)
+  return (base + step - 1) / step * step;
+}
+
 cpm_status ensure_step_buffers(cpm_ctx* c) {
   Buffers& b = c->b;
   if (b.sf_part) return CPM_OK;
@@ -179,27 +190,41 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   const int run_blocks = (c->nruns + 255) / 256;
   const int sf_target = c->sf_wg_target;
   c->mchunks = std::max(1, std::min((sf_target + run_blocks - 1) / run_blocks, std::max(1, c->m / 64)));
-  const int atom_blocks = (c->n + 255) / 256;
-  c->rchunks = std::max(1, std::min((512 + atom_blocks - 1) / atom_blocks, std::max(1, c->m / 32)));
+  // real space: at most 2 workgroups per CU fit (pair table in LDS), so keep
+  // the grid within one round of 512
+  const int atom_blocks = (c->nmap + 255) / 256;
+  c->rchunks = std::max(1, std::min(512 / atom_blocks, std::max(1, c->m / 32)));
   TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
+  const bool fast = c->sf_mfma && c->nlayers > 0;
   if (c->sf_mfma) {
     c->mpad = std::max(16, (c->m + 15) / 16 * 16);
-    // a multiple of 8 chunks (the kernel keeps each chunk on one XCD), about
-    // sfm_wg_target workgroups; chunks past the charges contribute zeros
-    const int per8 = 8 * c->sfm_nitems;
-    const int r = std::max(1, std::min((c->sfm_wg_target + per8 / 2) / per8,
-                                       std::max(1, c->mpad / (8 * 64))));
-    c->sfm_chunks = 8 * r;
-    c->sft_rows = (c->nxm + 1) + (2 * c->nym + 1) + 8 + c->sfm_nbz;
+    c->sft_rows = sf_table_rows(c->nxm, c->nym, c->sfm_nbz);
     c->sft_blocks = (c->mpad + 255) / 256;
-    TRY(dalloc(c, &b.sfm_part, (size_t)c->sfm_chunks * c->sfm_tiles * 32 * c->sfm_npadc));
-    TRY(dalloc(c, &b.sft, (size_t)c->sft_rows * c->mpad));
+    // planar electrodes: configurations per launch group, within ~512 MB of
+    // per-configuration workspace and the combine kernel's LDS
+    if (fast) {
+      const double per = 16.0 * c->sft_rows * c->mpad + 8.0 * c->sfm_pchunk +
+                         16.0 * c->ncolsort * c->nlayers + 8.0 * c->rchunks * c->n +
+                         8.0 * c->sft_blocks;
+      c->pv_group = std::max(1, std::min(layer_combine_max_group(),
+                                         (int)(512.0 * 1024 * 1024 / per)));
+      // column groups of the projection: ~1024 workgroups, >= 8 columns each
+      c->lp_groups = std::max(1, std::min((1024 + (c->n + 63) / 64 - 1) / ((c->n + 63) / 64),
+                                          c->ncolsort / 8));
+    }
+    const int G = c->pv_group;
+    size_t part_rows = 0;                 // (configuration, chunk) blocks of sfm_part
+    for (int g = 1; g <= G; ++g) part_rows = std::max(part_rows, (size_t)g * sf_chunks_for(c, g));
+    TRY(dalloc(c, &b.sfm_part, part_rows * c->sfm_pchunk));
+    TRY(dalloc(c, &b.sft, (size_t)G * c->sft_rows * c->mpad));
+    if (fast) TRY(dalloc(c, &b.sflT, (size_t)G * c->ncolsort * c->nlayers));
   }
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
   const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
-  TRY(dalloc(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
-  TRY(dalloc(c, &b.phir_part, (size_t)c->n * c->rchunks));
-  TRY(dalloc(c, &b.mz, (size_t)std::max(c->mchunks, c->sft_blocks)));
+  TRY(dalloc(c, &b.phik_part,
+             (size_t)c->n * std::max({pk_rows, c->kchunks, c->lp_groups * c->pv_group})));
+  TRY(dalloc(c, &b.phir_part, (size_t)c->pv_group * c->n * c->rchunks));
+  TRY(dalloc(c, &b.mz, (size_t)c->pv_group * std::max(c->mchunks, c->sft_blocks)));
   TRY(dalloc(c, &b.rtab, (size_t)3 * (RS_NT + 1)));
   launch_pair_table(c->stream, c->p.alpha, c->p.eta, c->p.rcut, b.rtab);
   TRY(launched(c, "pair table"));
@@ -248,6 +273,7 @@ cpm_status ensure_uploaded(cpm_ctx* c) {
       TRY(up(&b.sc_nx, c->h_sc_nx)); TRY(up(&b.sc_ny, c->h_sc_ny)); TRY(up(&b.sc_lo, c->h_sc_lo));
       TRY(up(&b.sc_len, c->h_sc_len)); TRY(up(&b.sc_koff, c->h_sc_koff)); TRY(up(&b.sc_n0, c->h_sc_n0));
       TRY(up(&b.sc_nidx, c->h_sc_nidx)); TRY(up(&b.tile_nb, c->h_tile_nb));
+      TRY(up(&b.tile_off, c->h_tile_off));
       TRY(dalloc(c, &b.sfm_items, c->h_sfm_items.size()));
       HIP_TRY(c, hipMemcpy(b.sfm_items, c->h_sfm_items.data(), c->h_sfm_items.size() * sizeof(int4),
                            hipMemcpyHostToDevice));
@@ -391,6 +417,15 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
     }
     c->sfm_nitems = (int)c->h_sfm_items.size();
     c->sf_mfma = c->sfm_nitems > 0;
+    // compact partial layout: tile mt holds a 32 x 16 nb_mt block
+    int off = 0;
+    for (int mt = 0; mt < c->sfm_tiles; ++mt) {
+      c->h_tile_off.push_back(off);
+      off += 32 * 16 * c->h_tile_nb[mt];
+    }
+    c->sfm_pchunk = off;
+    for (int k = 0; k < c->ncolsort; ++k)
+      c->sfm_maxcnt = std::max(c->sfm_maxcnt, c->h_sc_nidx[k + 1] - c->h_sc_nidx[k]);
     (void)emax;
   }
   *out = c;
@@ -469,10 +504,40 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
     HIP_TRY(c, hipMemcpy(b.layer_of, lay.data(), n * sizeof(int), hipMemcpyHostToDevice));
     HIP_TRY(c, hipMemcpy(b.layer_fz, lfz.data(), c->nlayers * sizeof(double), hipMemcpyHostToDevice));
   }
+  {
+    // real-space thread map: the atoms of each z plane fill whole waves
+    // (non-planar electrodes: caller order); -1 pads each group to 64
+    std::vector<int> amap;
+    if (c->nlayers > 0) {
+      std::vector<std::vector<int>> per(c->nlayers);
+      for (int i = 0; i < n; ++i)
+        per[std::lower_bound(zs.begin(), zs.end(), c->h_xyz[3 * i + 2]) - zs.begin()].push_back(i);
+      for (auto& v : per) {
+        amap.insert(amap.end(), v.begin(), v.end());
+        while (amap.size() % 64) amap.push_back(-1);
+      }
+    } else {
+      for (int i = 0; i < n; ++i) amap.push_back(i);
+      while (amap.size() % 64) amap.push_back(-1);
+    }
+    if (b.amap && (int)amap.size() != c->nmap) dfree(c, b.amap);
+    c->nmap = (int)amap.size();
+    TRY(dalloc(c, &b.amap, amap.size()));
+    HIP_TRY(c, hipMemcpy(b.amap, amap.data(), amap.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
   HIP_TRY(c, hipMemcpyAsync(b.eid, d_eid, (size_t)n * sizeof(int), hipMemcpyDeviceToDevice, c->stream));
   const cpm_params& p = c->p;
   launch_prep_electrodes(c->stream, n, d_xyz, p.Lx, p.Ly, c->Lz, b);
   TRY(launched(c, "prep_electrodes"));
+  if (c->nlayers > 0 && c->sf_mfma) {
+    // fixed electrode phases for the planar k-space projection
+    const int nzt = c->sfm_npadc / 2;
+    TRY(dalloc(c, &b.ephase, (size_t)c->ncolsort * n));
+    TRY(dalloc(c, &b.pz, (size_t)c->nlayers * nzt));
+    launch_electrode_phases(c->stream, n, c->ncolsort, b.sc_nx, b.sc_ny, b, c->nlayers, nzt,
+                            b.ephase, b.pz);
+    TRY(launched(c, "electrode phases"));
+  }
   const double eta_ee = p.eta / std::sqrt(2.0);
   const double diag_self = (std::sqrt(2.0) * p.eta - 2.0 * p.alpha) / std::sqrt(M_PI);
   const double background = -M_PI / (c->V * p.alpha * p.alpha);
@@ -628,29 +693,30 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   const size_t esz = b_is_f32 ? sizeof(float) : sizeof(double);
   Buffers& b = c->b;
   hipStream_t st = c->stream;
-  for (int s = 0; s < batch; ++s) {
-    const double* xyz = d_xyz ? d_xyz + (size_t)s * m * 3 : nullptr;
-    void* out = static_cast<char*>(d_b) + (size_t)s * n * esz;
+  // FP64 structure factors on matrix cores unless switched off; planar
+  // electrodes then take the grouped path (pv_group configurations per
+  // launch, k_z folded into the planes, projection fused into the combine)
+  const bool mfma = c->sf_mfma && c->use_sf_mfma;
+  const bool fast = mfma && c->nlayers > 0;
+  const int G = fast ? c->pv_group : 1;
+  const double slab_coef = 4.0 * M_PI / c->V;
+  for (int s0 = 0; s0 < batch; s0 += G) {
+    const int g = std::min(G, batch - s0);
+    const double* xyz = d_xyz ? d_xyz + (size_t)s0 * m * 3 : nullptr;
+    void* out = static_cast<char*>(d_b) + (size_t)s0 * n * esz;
     if (m == 0) {
-      launch_fill_zero(st, n * esz / sizeof(float), static_cast<float*>(out));
+      launch_fill_zero(st, (size_t)g * n * esz / sizeof(float), static_cast<float*>(out));
       continue;
     }
-    // FP64 structure factors on matrix cores when the k set fits the kernel;
-    // both structure-factor kernels also leave the electrolyte dipole partials
-    const bool mfma = c->sf_mfma && !b_is_f32 && c->use_sf_mfma;
-    const int mz_parts = mfma ? c->sft_blocks : c->mchunks;
+    const int nch = mfma ? sf_chunks_for(c, g) : 0;
     if (mfma) {
       { Timed t(c, "sf_tables");
-        launch_b_sf_tables(st, m, c->mpad, c->nxm, c->nym, c->sfm_nbz, xyz, b.elq, p.Lx, p.Ly,
+        launch_b_sf_tables(st, g, m, c->mpad, c->nxm, c->nym, c->sfm_nbz, xyz, b.elq, p.Lx, p.Ly,
                            c->Lz, b.sft, b.mz); }
       { Timed t(c, "structure_factor");
-        launch_b_sf_mfma(st, c->mpad, c->sfm_chunks, c->sfm_nitems, b.sfm_items, c->sfm_tiles,
-                         b.sc_nx, b.sc_ny, c->ncolsort, c->nxm, c->nym, b.sft, c->sfm_npadc,
-                         b.sfm_part); }
-      { Timed t(c, "sf_reduce");
-        launch_b_sf_mfma_reduce(st, c->ncolsort, c->sfm_tiles, c->sfm_chunks, c->sfm_npadc,
-                                b.sc_lo, b.sc_len, b.sc_koff, b.sc_n0, b.sc_nidx, c->sfm_ntot,
-                                b.sfm_part, b.w2, b.sfw); }
+        launch_b_sf_mfma(st, g, c->mpad, nch, c->sfm_nitems, b.sfm_items, b.sc_nx, b.sc_ny,
+                         c->ncolsort, c->nxm, c->nym, c->sfm_nbz, b.sft, b.tile_nb, b.tile_off,
+                         c->sfm_pchunk, b.sfm_part); }
     } else {
       { Timed t(c, "structure_factor");
         launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz,
@@ -658,6 +724,29 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
                                   b.mz); }
       { Timed t(c, "sf_reduce");
         launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
+    }
+    { Timed t(c, "real_space_b");
+      launch_b_real_space(st, g, n, m, c->rchunks, b, c->nmap, xyz, b.elq, p.Lx, p.Ly, p.rcut,
+                          b.phir_part); }
+    if (fast) {
+      { Timed t(c, "sf_reduce");
+        launch_b_sf_layer_reduce(st, g, c->ncolsort, nch, c->sfm_pchunk, c->nlayers,
+                                 c->sfm_npadc / 2, c->sfm_maxcnt, b.tile_nb, b.tile_off, b.sc_lo,
+                                 b.sc_len, b.sc_koff, b.sc_nidx, b.sfm_part, b.w2, b.pz,
+                                 b.sflT); }
+      { Timed t(c, "combine");
+        launch_b_layer_combine(st, g, n, c->ncolsort, c->nlayers, c->lp_groups, b.ephase,
+                               b.layer_of, b.sflT, b.phik_part, b.phir_part, c->rchunks, b.ez,
+                               b.mz, c->sft_blocks, slab_coef, c->ke, out, b_is_f32); }
+      TRY(launched(c, "potential_vector"));
+      continue;
+    }
+    // general path, one configuration (g == 1)
+    if (mfma) {
+      Timed t(c, "sf_reduce");
+      launch_b_sf_mfma_reduce(st, c->ncolsort, nch, c->sfm_pchunk, b.tile_nb, b.tile_off, b.sc_lo,
+                              b.sc_len, b.sc_koff, b.sc_nidx, c->sfm_ntot, b.sfm_part, b.w2,
+                              b.sfw);
     }
     int kparts = c->kchunks;
     if (c->nlayers > 0) {
@@ -670,11 +759,9 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
       launch_b_kspace_project(st, b_is_f32, n, c->kchunks, b.cols, b.chunk_col, b, b.sfw,
                               b.phik_part);
     }
-    { Timed t(c, "real_space_b");
-      launch_b_real_space(st, n, m, c->rchunks, b, xyz, b.elq, p.Lx, p.Ly, p.rcut, b.phir_part); }
     { Timed t(c, "combine");
-      launch_b_combine(st, n, kparts, c->rchunks, mz_parts, b.phik_part, b.phir_part, b, b.mz,
-                       4.0 * M_PI / c->V, c->ke, out, b_is_f32); }
+      launch_b_combine(st, n, kparts, c->rchunks, mfma ? c->sft_blocks : c->mchunks, b.phik_part,
+                       b.phir_part, b, b.mz, slab_coef, c->ke, out, b_is_f32); }
     TRY(launched(c, "potential_vector"));
   }
   return CPM_OK;
@@ -943,9 +1030,10 @@ void cpm_destroy(cpm_ctx* c) {
   if (!c) return;
   Buffers& b = c->b;
   dfree(b.ex); dfree(b.ey); dfree(b.ez); dfree(b.efx); dfree(b.efy); dfree(b.efz); dfree(b.eid);
-  dfree(b.layer_of); dfree(b.layer_fz); dfree(b.layerT);
+  dfree(b.layer_of); dfree(b.layer_fz); dfree(b.layerT); dfree(b.amap);
   dfree(b.sc_nx); dfree(b.sc_ny); dfree(b.sc_lo); dfree(b.sc_len); dfree(b.sc_koff); dfree(b.sc_n0);
   dfree(b.sc_nidx); dfree(b.tile_nb); dfree(b.sfm_part); dfree(b.sfm_items); dfree(b.sft);
+  dfree(b.tile_off); dfree(b.ephase); dfree(b.pz); dfree(b.sflT);
   dfree(b.runs); dfree(b.cols); dfree(b.chunk_col); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);

@@ -51,6 +51,7 @@ struct Buffers {
   double* efx = nullptr; double* efy = nullptr; double* efz = nullptr;  // fractional
   int* eid = nullptr;
   int* layer_of = nullptr;         // plane index per atom (planar electrodes)
+  int* amap = nullptr;             // real-space thread -> atom map: whole waves per plane, -1 pads
   double* layer_fz = nullptr;      // fractional z of each plane
   double2* layerT = nullptr;       // T(column, plane)
   // k-set
@@ -62,6 +63,10 @@ struct Buffers {
   int* sc_koff = nullptr; int* sc_n0 = nullptr; int* sc_nidx = nullptr; int* tile_nb = nullptr;
   double* sfm_part = nullptr;      // chunk partials [chunk][tile][32][npadc]
   int4* sfm_items = nullptr;       // work items {M tile, first n block, n blocks, 0}
+  int* tile_off = nullptr;         // offset of each M tile's block in a chunk of sfm_part
+  double2* ephase = nullptr;       // electrode in-plane phases per sorted column (ncolsort x n)
+  double2* pz = nullptr;           // plane phases e^{-i n kz1 z_L} (nlayers x nzt)
+  double2* sflT = nullptr;         // T(c, L) per configuration of a group
   double2* sft = nullptr;          // per-charge phase tables (rows x mpad)
   double* w2 = nullptr;            // 2 W(k), nk (flat run order)
   int* knx = nullptr; int* kny = nullptr; int* knz = nullptr;     // nk
@@ -125,8 +130,14 @@ struct cpm_ctx {
   int nlayers = 0;                 // > 0: electrodes lie on this many z planes (factorised projection)
   bool sf_mfma = false;            // structure factors on FP64 matrix cores (k set fits)
   bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
-  int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_chunks = 1, sfm_ntot = 0;
+  int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_ntot = 0;
   int sfm_nbz = 2, sfm_nitems = 0, mpad = 0, sft_rows = 0, sft_blocks = 1;
+  int sfm_pchunk = 0;              // doubles per (configuration, chunk) of sfm_part
+  int sfm_maxcnt = 0;              // largest number of n >= 0 of a sorted column
+  int pv_group = 1;                // configurations per launch group (planar fast path)
+  int lp_groups = 1;               // column groups of the planar projection
+  int nmap = 0;                    // length of the real-space atom map
+  std::vector<int> h_tile_off;
   std::vector<int4> h_sfm_items;
   std::vector<int> h_sc_nx, h_sc_ny, h_sc_lo, h_sc_len, h_sc_koff, h_sc_n0, h_sc_nidx, h_tile_nb;
   std::vector<double> h_w2;
@@ -205,16 +216,32 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
                                int m, int mchunks, const double* xyz, const double* q,
                                double Lx, double Ly, double Lz, int nxm, int nym, int nzm,
                                double* part, double* mz_part);
-void launch_b_sf_tables(hipStream_t st, int m, int mpad, int nxm, int nym, int nbz,
+void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
                         double2* tab, double* mz_part);
-void launch_b_sf_mfma(hipStream_t st, int mpad, int mchunks, int nitems, const int4* items,
-                      int mtiles, const int* sc_nx, const int* sc_ny, int ncolsort, int nxm,
-                      int nym, const double2* tab, int npadc, double* part);
-void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int mtiles, int mchunks, int npadc,
-                             const int* sc_lo, const int* sc_len, const int* sc_koff,
-                             const int* sc_n0, const int* n_index, int n_total,
-                             const double* part, const double* w2, double* sfw);
+void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
+                      const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
+                      const double2* tab, const int* tile_nb, const int* toff, int pchunk,
+                      double* part);
+void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int nchunks, int pchunk,
+                             const int* tile_nb, const int* toff, const int* sc_lo,
+                             const int* sc_len, const int* sc_koff, const int* n_index,
+                             int n_total, const double* part, const double* w2, double* sfw);
+void launch_b_sf_layer_reduce(hipStream_t st, int g, int ncolsort, int nchunks, int pchunk,
+                              int nlayers, int nzt, int max_ncnt, const int* tile_nb,
+                              const int* toff, const int* sc_lo, const int* sc_len,
+                              const int* sc_koff, const int* n_index, const double* part,
+                              const double* w2, const double2* pz, double2* T);
+void launch_electrode_phases(hipStream_t st, int n, int ncolsort, const int* sc_nx,
+                             const int* sc_ny, const Buffers& b, int nlayers, int nzt,
+                             double2* E, double2* pz);
+void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlayers, int cgroups,
+                            const double2* E, const int* layer_of, const double2* T,
+                            double* phik, const double* phir, int rchunks, const double* ez,
+                            const double* mz_part, int mz_parts, double slab_coef, double ke,
+                            void* out, int out_is_f32);
+int layer_combine_max_group();
+int sf_table_rows(int nxm, int nym, int nbz);
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
                         const double* w2, double* sfw);
 void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const KCol* cols,
@@ -226,9 +253,9 @@ void launch_b_layer_project(hipStream_t st, int n, int ncols, int nlayers, const
                             const double* sfw, double2* T, double* part);
 int layer_project_chunks(int ncols);
 void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab);
-void launch_b_real_space(hipStream_t st, int n, int m, int rchunks, const Buffers& b,
-                         const double* xyz, const double* q, double Lx, double Ly, double rc,
-                         double* part);
+void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
+                         int nmap, const double* xyz, const double* q, double Lx, double Ly,
+                         double rc, double* part);
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchunks,
                       const double* phik, const double* phir, const Buffers& b,
                       const double* mz_part, double slab_coef, double ke, void* out,

@@ -290,7 +290,8 @@ def test_kernel_timing(cpm):
     ctx.potential_vector(xyz, b)
     q = torch.empty((2, w.n), dtype=torch.float64, device="cuda")
     ctx.solve_charges(b, 0, q)
-    for fam in ("structure_factor", "kspace_project", "real_space_b", "matvec_f64", "finalize"):
+    for fam in ("sf_tables", "structure_factor", "sf_reduce", "real_space_b", "combine", "matvec_f64",
+                "finalize"):
         ms, cnt = ctx.timing(fam)
         assert cnt >= 1 and ms > 0, fam
     assert ctx.timing("no_such_kernel") == (0.0, 0)
