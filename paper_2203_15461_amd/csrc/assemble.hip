@@ -126,6 +126,106 @@ void launch_phase_table(hipStream_t st, int n, int npad, int k0, int kc, int nk,
                      b.kny, b.knz, b.w2, b.efx, b.efy, b.efz, ke, table);
 }
 
+// ---------------------------------------------------------------------------
+// k-space part of A for electrodes on z planes.  For a (k_x, k_y) column c
+// and atoms i, j on planes L_i, L_j the column's terms regroup exactly as
+//   sum_n 2W(c, n) cos(k . (R_i - R_j)) = Re[E_i(c) conj(E_j(c)) Q_c(L_i, L_j)],
+//   E_i(c) = e^{i (kx x_i + ky y_i)},  Q_c(L, L') = sum_n 2W(c, n) e^{i n kz1 (z_L - z_L')},
+// so for the atoms of plane L the rows of A gain G_L F^L with
+//   G_L[i][2c] = cos th_c(i), G_L[i][2c+1] = -sin th_c(i)   (rows in plane order),
+//   F^L[2c][j] = Re, F^L[2c+1][j] = Im of conj(E_j(c)) Q_c(L, L_j):
+// one MFMA GEMM with K = 2 x (number of columns) per plane instead of the
+// rank-2|K+| product.
+// ---------------------------------------------------------------------------
+
+// Q[(c * nlayers + L) * nlayers + L'] = Q_c(L, L'), thread per (c, L, L')
+__global__ void k_plane_pair_weights(int ncolsort, int nlayers, const int* __restrict__ sc_lo,
+                                     const int* __restrict__ sc_len,
+                                     const int* __restrict__ sc_koff,
+                                     const double* __restrict__ w2,
+                                     const double* __restrict__ layer_fz,
+                                     double2* __restrict__ Q) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ncolsort * nlayers * nlayers) return;
+  const int c = e / (nlayers * nlayers), L = (e / nlayers) % nlayers, L2 = e % nlayers;
+  const double dfz = layer_fz[L] - layer_fz[L2];
+  double qr = 0.0, qi = 0.0;
+  for (int t = 0; t < sc_len[c]; ++t) {
+    double th = (sc_lo[c] + t) * dfz;
+    th -= rint(th);
+    double sn, cs;
+    sincospi(2.0 * th, &sn, &cs);
+    const double w = w2[sc_koff[c] + t];
+    qr += w * cs;
+    qi += w * sn;
+  }
+  Q[e] = make_double2(qr, qi);
+}
+
+void launch_plane_pair_weights(hipStream_t st, int ncolsort, int nlayers, const int* sc_lo,
+                                const int* sc_len, const int* sc_koff, const double* w2,
+                                const double* layer_fz, double2* Q) {
+  const int tot = ncolsort * nlayers * nlayers;
+  hipLaunchKernelGGL(k_plane_pair_weights, dim3((tot + 255) / 256), dim3(256), 0, st, ncolsort,
+                     nlayers, sc_lo, sc_len, sc_koff, w2, layer_fz, Q);
+}
+
+// G (nmap x ldG, rows in atom-map order, -1 rows and columns >= 2 ncolsort zero)
+__global__ void k_build_G(int nmap, int ncolsort, int ldG, const int* __restrict__ amap,
+                          const int* __restrict__ sc_nx, const int* __restrict__ sc_ny,
+                          const double* __restrict__ fx, const double* __restrict__ fy,
+                          double* __restrict__ G) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (2 * c >= ldG) return;
+  const int a = amap[r];
+  double cs = 0.0, sn = 0.0;
+  if (a >= 0 && c < ncolsort) {
+    double th = sc_nx[c] * fx[a] + sc_ny[c] * fy[a];
+    th -= rint(th);
+    sincospi(2.0 * th, &sn, &cs);
+  }
+  reinterpret_cast<double2*>(G + (size_t)r * ldG)[c] = make_double2(cs, -sn);
+}
+
+void launch_build_G(hipStream_t st, int nmap, int ncolsort, int ldG, const int* amap,
+                    const int* sc_nx, const int* sc_ny, const Buffers& b, double* G) {
+  dim3 grid((ldG / 2 + 127) / 128, nmap), block(128);
+  hipLaunchKernelGGL(k_build_G, grid, block, 0, st, nmap, ncolsort, ldG, amap, sc_nx, sc_ny, b.efx,
+                     b.efy, G);
+}
+
+// F^L (ldG x npad): column j < n holds conj(E_j(c)) Q_c(L, L_j) as (Re, Im)
+// in rows (2c, 2c + 1); padding zero
+__global__ void k_build_F(int L, int n, int npad, int nlayers, int ncolsort, int ldG,
+                          const int* __restrict__ sc_nx, const int* __restrict__ sc_ny,
+                          const double* __restrict__ fx, const double* __restrict__ fy,
+                          const int* __restrict__ layer_of, const double2* __restrict__ Q,
+                          double* __restrict__ F) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (j >= npad) return;
+  double fr = 0.0, fi = 0.0;
+  if (j < n && c < ncolsort) {
+    double th = sc_nx[c] * fx[j] + sc_ny[c] * fy[j];
+    th -= rint(th);
+    double sn, cs;
+    sincospi(2.0 * th, &sn, &cs);
+    const double2 q = Q[((size_t)c * nlayers + L) * nlayers + layer_of[j]];
+    // (cs - i sn) (q.x + i q.y)
+    fr = cs * q.x + sn * q.y;
+    fi = cs * q.y - sn * q.x;
+  }
+  F[(size_t)(2 * c) * npad + j] = fr;
+  F[(size_t)(2 * c + 1) * npad + j] = fi;
+}
+
+void launch_build_F(hipStream_t st, int L, int n, int npad, int nlayers, int ncolsort, int ldG,
+                    const int* sc_nx, const int* sc_ny, const Buffers& b, const double2* Q,
+                    double* F) {
+  dim3 grid((npad + 255) / 256, ldG / 2), block(256);
+  hipLaunchKernelGGL(k_build_F, grid, block, 0, st, L, n, npad, nlayers, ncolsort, ldG, sc_nx,
+                     sc_ny, b.efx, b.efy, b.layer_of, Q, F);
+}
+
 // Copy the lower triangle onto the upper one (tiled transpose through LDS).
 __global__ void k_mirror_lower(int npad, double* A) {
   __shared__ double tile[32][33];

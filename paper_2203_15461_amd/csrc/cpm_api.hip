@@ -512,9 +512,12 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
       std::vector<std::vector<int>> per(c->nlayers);
       for (int i = 0; i < n; ++i)
         per[std::lower_bound(zs.begin(), zs.end(), c->h_xyz[3 * i + 2]) - zs.begin()].push_back(i);
+      c->h_plane_rows.clear();
       for (auto& v : per) {
+        const size_t before = amap.size();
         amap.insert(amap.end(), v.begin(), v.end());
         while (amap.size() % 64) amap.push_back(-1);
+        c->h_plane_rows.push_back((int)(amap.size() - before));
       }
     } else {
       for (int i = 0; i < n; ++i) amap.push_back(i);
@@ -545,19 +548,46 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, p.rcut, p.alpha, eta_ee, diag_self,
                       background, slab_coef, c->ke, d_diag_extra, b.A);
   TRY(launched(c, "real_space_A"));
-  // k space: A += T T^T over chunks of KC k-vectors (2 KC columns)
-  const int KC = 2048;
-  TRY(dalloc(c, &b.table, (size_t)npad * 2 * KC));
-  for (int k0 = 0; k0 < c->nk; k0 += KC) {
-    launch_phase_table(c->stream, n, npad, k0, KC, c->nk, b, c->ke, b.table);
-    launch_gemm_f64(c->stream, false, true, npad, npad, 2 * KC, 1.0, b.table, 2 * KC, b.table,
-                    2 * KC, 1.0, b.A, npad, /*tri=*/1, 0);
-    TRY(launched(c, "kspace syrk"));
+  if (c->nlayers > 0 && c->sf_mfma) {
+    // planar electrodes: per plane, A[rows of L] += k_e G_L F^L (K = 2 x columns)
+    const int ldG = (2 * c->ncolsort + 15) / 16 * 16;
+    double2* Q = nullptr;
+    double* G = nullptr;
+    double* F = nullptr;
+    TRY(dalloc(c, &Q, (size_t)c->ncolsort * c->nlayers * c->nlayers));
+    TRY(dalloc(c, &G, (size_t)c->nmap * ldG));
+    TRY(dalloc(c, &F, (size_t)ldG * npad));
+    launch_plane_pair_weights(c->stream, c->ncolsort, c->nlayers, b.sc_lo, b.sc_len, b.sc_koff,
+                              b.w2, b.layer_fz, Q);
+    launch_build_G(c->stream, c->nmap, c->ncolsort, ldG, b.amap, b.sc_nx, b.sc_ny, b, G);
+    int row0 = 0;
+    for (int L = 0; L < c->nlayers; ++L) {
+      const int rows = c->h_plane_rows[L];              // this plane's rows of the map (x 64)
+      launch_build_F(c->stream, L, n, npad, c->nlayers, c->ncolsort, ldG, b.sc_nx, b.sc_ny, b, Q,
+                     F);
+      launch_gemm_f64(c->stream, false, false, rows, npad, ldG, c->ke, G + (size_t)row0 * ldG,
+                      ldG, F, npad, 1.0, b.A, npad, 0, 0, b.amap + row0);
+      TRY(launched(c, "kspace planes"));
+      row0 += rows;
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, Q); dfree(c, G); dfree(c, F);
+  } else {
+    // k space: A += T T^T over chunks of KC k-vectors (2 KC columns)
+    const int KC = 2048;
+    TRY(dalloc(c, &b.table, (size_t)npad * 2 * KC));
+    for (int k0 = 0; k0 < c->nk; k0 += KC) {
+      launch_phase_table(c->stream, n, npad, k0, KC, c->nk, b, c->ke, b.table);
+      launch_gemm_f64(c->stream, false, true, npad, npad, 2 * KC, 1.0, b.table, 2 * KC, b.table,
+                      2 * KC, 1.0, b.A, npad, /*tri=*/1, 0);
+      TRY(launched(c, "kspace syrk"));
+    }
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    dfree(c, b.table);
   }
   launch_mirror_lower(c->stream, npad, b.A);
   TRY(launched(c, "mirror"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  dfree(c, b.table);
   c->have_A = true;
   return CPM_OK;
 }

@@ -137,6 +137,7 @@ struct cpm_ctx {
   int pv_group = 1;                // configurations per launch group (planar fast path)
   int lp_groups = 1;               // column groups of the planar projection
   int nmap = 0;                    // length of the real-space atom map
+  std::vector<int> h_plane_rows;   // rows of the atom map per plane (multiples of 64)
   std::vector<int> h_tile_off;
   std::vector<int4> h_sfm_items;
   std::vector<int> h_sc_nx, h_sc_ny, h_sc_lo, h_sc_len, h_sc_koff, h_sc_n0, h_sc_nidx, h_tile_nb;
@@ -169,6 +170,14 @@ void launch_real_space_A(hipStream_t st, int n, int npad, const Buffers& b, doub
                          double* A);
 void launch_phase_table(hipStream_t st, int n, int npad, int k0, int kc, int nk, const Buffers& b,
                         double ke, double* table);
+void launch_plane_pair_weights(hipStream_t st, int ncolsort, int nlayers, const int* sc_lo,
+                                const int* sc_len, const int* sc_koff, const double* w2,
+                                const double* layer_fz, double2* Q);
+void launch_build_G(hipStream_t st, int nmap, int ncolsort, int ldG, const int* amap,
+                    const int* sc_nx, const int* sc_ny, const Buffers& b, double* G);
+void launch_build_F(hipStream_t st, int L, int n, int npad, int nlayers, int ncolsort, int ldG,
+                    const int* sc_nx, const int* sc_ny, const Buffers& b, const double2* Q,
+                    double* F);
 void launch_mirror_lower(hipStream_t st, int npad, double* A);
 
 // dense FP64 algebra (MFMA)
@@ -176,7 +185,7 @@ void launch_mirror_lower(hipStream_t st, int npad, double* A);
 // tri: 0 all tiles, 1 lower tiles only.  kmode: 0 K range [0,K), 1 [max(m0,n0), K).
 void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int K,
                      double alpha, const double* A, int lda, const double* B, int ldb,
-                     double beta, double* C, int ldc, int tri, int kmode);
+                     double beta, double* C, int ldc, int tri, int kmode, const int* rowmap = nullptr);
 void launch_potrf_diag(hipStream_t st, double* Lblk, int ld, double* Dinv, int* flag, int k0);
 void launch_set_identity(hipStream_t st, int npad, double* X);
 void launch_row_sums(hipStream_t st, int n, int npad, const double* M, double* out);

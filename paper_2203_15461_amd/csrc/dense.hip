@@ -26,7 +26,7 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int M, int N, int K, double al
                                                   const double* __restrict__ A, int lda,
                                                   const double* __restrict__ B, int ldb,
                                                   double beta, double* C, int ldc, int tri,
-                                                  int kmode) {
+                                                  int kmode, const int* __restrict__ rowmap) {
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   if (tri && n0 > m0) return;
   const int kbeg = kmode ? (m0 > n0 ? m0 : n0) : 0;
@@ -96,7 +96,11 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int M, int N, int K, double al
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + a * 16 + (lane >> 4) + 4 * r;
+        int row = m0 + wm + a * 16 + (lane >> 4) + 4 * r;
+        if (rowmap) {                                  // scattered output rows (-1: skip)
+          row = rowmap[row];
+          if (row < 0) continue;
+        }
         const int col = n0 + wn + b * 16 + (lane & 15);
         double* cp = C + (size_t)row * ldc + col;
         const double v = alpha * acc[a][b][r];
@@ -106,21 +110,21 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int M, int N, int K, double al
 
 void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int K, double alpha,
                      const double* A, int lda, const double* B, int ldb, double beta, double* C,
-                     int ldc, int tri, int kmode) {
+                     int ldc, int tri, int kmode, const int* rowmap) {
   if (M <= 0 || N <= 0) return;
   dim3 grid(N / 64, M / 64), block(256);
   if (!transA && !transB)
     hipLaunchKernelGGL((k_gemm_f64<false, false>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, tri, kmode);
+                       ldb, beta, C, ldc, tri, kmode, rowmap);
   else if (!transA && transB)
     hipLaunchKernelGGL((k_gemm_f64<false, true>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, tri, kmode);
+                       ldb, beta, C, ldc, tri, kmode, rowmap);
   else if (transA && !transB)
     hipLaunchKernelGGL((k_gemm_f64<true, false>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, tri, kmode);
+                       ldb, beta, C, ldc, tri, kmode, rowmap);
   else
     hipLaunchKernelGGL((k_gemm_f64<true, true>), grid, block, 0, st, M, N, K, alpha, A, lda, B,
-                       ldb, beta, C, ldc, tri, kmode);
+                       ldb, beta, C, ldc, tri, kmode, rowmap);
 }
 
 // ---------------------------------------------------------------------------
