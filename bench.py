@@ -170,14 +170,19 @@ def main():
     # dominant kernel: the structure factors
     nk = int(ctx.info("nk"))
     sf_avg = sf_ms / max(sf_cnt, 1) * 1e-3
-    # 8 flop per (k, charge) pair (complex rotate-and-accumulate); one launch
-    # covers the configurations of one launch group
+    # algorithmic work of one launch (it covers one launch group of
+    # configurations): on matrix cores, 4 flop per (k, charge) pair (one
+    # real 2 x 2 product of (Re C, Im C) with (Re Z, Im Z) serves k and its
+    # mirror in k_z: 8 flop per 2 k); on the VALU kernel, 8 flop per pair (a
+    # complex rotation and a complex accumulate)
     snaps_per_launch = B * args.steps / max(sf_cnt, 1)
-    flop_per_launch = 8.0 * nk * w.m * snaps_per_launch
+    matrix = ctx.info("sf_matrix") == 1.0
+    flop_per_pair = 4.0 if matrix else 8.0
+    flop_per_launch = flop_per_pair * nk * w.m * snaps_per_launch
     achieved = flop_per_launch / sf_avg if sf_avg > 0 else 0.0
-    peak = PEAK_FP64_VALU      # the phases and rotations are FP64 in every mode
-    traffic = stored_traffic(args.workload, sf_cnt)
-    sf_bound = "mfma" if ctx.info("sf_matrix") == 1.0 else "alu"
+    peak = PEAK_FP64_VALU      # FP64 MFMA and FP64 vector peaks are both 78.6 TFLOP/s
+    traffic = stored_traffic(args.workload, snaps_per_launch)
+    sf_bound = "mfma" if matrix else "alu"
 
     value = B * args.steps / elapsed
     out = {
@@ -200,7 +205,8 @@ def main():
         "roofline": {"kernel": "structure_factor", "bound": sf_bound,
                      "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "flop_per_launch": flop_per_launch, "avg_launch_us": sf_avg * 1e6,
+                     "flop_per_launch": flop_per_launch, "flop_per_k_charge_pair": flop_per_pair,
+                     "avg_launch_us": sf_avg * 1e6,
                      "configurations_per_launch": snaps_per_launch},
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),
@@ -246,10 +252,11 @@ def matvec_roofline(ctx, w, xyz, dev, reps=20):
     return out
 
 
-def stored_traffic(workload, launches):
+def stored_traffic(workload, configs_per_launch):
     """HBM bytes per structure-factor launch from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary (scaled by a 1 GiB copy), or None when the
-    kernel source changed since the counters were taken."""
+    kernel source changed since the counters were taken or the launch shape
+    differs by more than 5%."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "structure_factor_traffic.json")
     src = os.path.join(ROOT, "paper_2203_15461_amd", "csrc", "bvector.hip")
@@ -261,7 +268,11 @@ def stored_traffic(workload, launches):
     entry = rec.get(workload)
     if not entry or rec.get("bvector_sha256") != digest:
         return None
-    return entry["bytes_per_launch"]
+    per = entry.get("configurations_per_launch", 1)
+    if abs(per - configs_per_launch) > 0.05 * per:
+        return None
+    # per configuration, times the timed run's average configurations per launch
+    return entry["bytes_per_launch"] / per * configs_per_launch
 
 
 def cpu_baseline(w):
