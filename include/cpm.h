@@ -81,7 +81,13 @@ enum {
   CPM_INFO_NRUNS = 10,        /* k-space runs (<= 16 consecutive k_z each)        */
   CPM_INFO_NLAYERS = 11,      /* z planes of the electrodes when <= 64 (planar    */
                               /* factorisation of the k-space projection), else 0 */
-  CPM_INFO_SF_MATRIX = 12     /* 1: FP64 structure factors run on matrix cores    */
+  CPM_INFO_SF_MATRIX = 12,    /* 1: FP64 structure factors run on matrix cores    */
+  CPM_INFO_TUNE_BM = 13,      /* last cpm_autotune: rows of X per GEMM tile       */
+  CPM_INFO_TUNE_KS = 14,      /*   ... parts the K dimension is split into        */
+  CPM_INFO_TUNE_GRID = 15,    /*   ... workgroups of the persistent launch        */
+  CPM_INFO_TUNE_US = 16,      /*   ... measured microseconds per product          */
+  CPM_INFO_GROUP = 17         /* configurations per launch group of              */
+                              /* cpm_potential_vector (planar electrodes)         */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -154,6 +160,28 @@ cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
  * chosen copy of S must have been kept by cpm_invert, else CPM_EINVAL. */
 cpm_status cpm_solve_charges(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32,
                              unsigned mode, double* d_q, double* d_Qe);
+
+/* Autotune the split-BF16 batched product Q~ = B S~ (the matrix-core solve
+ * of Eqs. 3 and 6) for batches of `batch` vectors (rows padded to 64): times
+ * every tile height (32, 64, 128 rows), K split (1, 2, 4) and persistent grid
+ * size on this context's S, `reps` launches each, and keeps the fastest for
+ * later cpm_solve_charges calls with the same padded row count.  Needs
+ * cpm_invert with CPM_STORE_BF16X2.  Synchronous.  The choice changes only
+ * the FP32 summation order of the product; results stay within the path's
+ * tolerance.  CPM_INFO_TUNE_* report the choice. */
+cpm_status cpm_autotune(cpm_ctx* ctx, int batch, int reps);
+
+/* Solve several contexts at once (electrodes of uneven size): the same as
+ * cpm_solve_charges on each of the n_ctx <= 8 contexts, with every product
+ * with S~ of all contexts done in one persistent split-BF16 launch (two with
+ * CPM_SOLVE_REFINE).  mode must be CPM_SOLVE_BF16X2, optionally with
+ * CPM_SOLVE_REFINE (else CPM_EUNSUPPORTED).  batch, d_b, d_q and d_Qe
+ * (may be NULL, or hold NULL entries) are host arrays of n_ctx entries; the
+ * contexts must be distinct and share one stream.  Errors are reported on
+ * ctxs[0]. */
+cpm_status cpm_solve_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
+                             const void* const* d_b, int b_is_f32, unsigned mode,
+                             double* const* d_q, double* const* d_Qe);
 
 /* Capture one batched step -- cpm_potential_vector for `batch`
  * configurations followed by cpm_solve_charges -- for these exact buffers

@@ -22,11 +22,13 @@ STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_ESTATE", 3: "CPM_ENOMEM", 
 # store flags, solve modes, info keys
 STORE_F64, STORE_F32, STORE_BF16X2 = 1, 2, 4
 SOLVE_F64, SOLVE_F32, SOLVE_BF16X2, SOLVE_REFINE = 0, 1, 2, 0x100
-INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, npad=9, nruns=10, nlayers=11, sf_matrix=12)
+INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, npad=9, nruns=10,
+            nlayers=11, sf_matrix=12, tune_bm=13, tune_ks=14, tune_grid=15, tune_us=16, group=17)
 
 EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
            "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",
-           "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_get_info",
+           "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_autotune",
+           "cpm_solve_grouped", "cpm_get_info",
            "cpm_enable_timing", "cpm_get_timing",
            "cpm_synchronize", "cpm_last_error", "cpm_destroy")
 
@@ -69,6 +71,9 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_copy_matrix": ([vp, i, vp], i),
         "cpm_capture_step": ([vp, i, vp, vp, i, u, vp, vp], i),
         "cpm_replay_step": ([vp], i),
+        "cpm_autotune": ([vp, i, i], i),
+        "cpm_solve_grouped": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(vp), i, u,
+                               ctypes.POINTER(vp), ctypes.POINTER(vp)], i),
         "cpm_copy_vector": ([vp, i, vp], i),
         "cpm_get_info": ([vp, i, ctypes.POINTER(d)], i),
         "cpm_enable_timing": ([vp, ctypes.c_char_p], i),
@@ -244,6 +249,12 @@ class Context:
                                                 _ptr(Qe_out)), "cpm_solve_charges")
         return q_out
 
+    def autotune(self, batch: int, reps: int = 5) -> dict:
+        """Time the split-BF16 batched product's tile shapes for `batch` vectors;
+        later solves with the same padded row count use the fastest."""
+        self._check(self._lib.cpm_autotune(self._h, int(batch), int(reps)), "cpm_autotune")
+        return {k: self.info("tune_" + k) for k in ("bm", "ks", "grid", "us")}
+
     def capture_step(self, xyz, b, mode: int, q_out, Qe_out=None):
         """Capture b for xyz (batch, m, 3) and the solve into a HIP graph."""
         _expect(xyz, "float64", 3)
@@ -279,6 +290,36 @@ class Context:
             raise ValueError("need an (n,) tensor")
         self._check(self._lib.cpm_copy_vector(self._h, which, _ptr(out)), "cpm_copy_vector")
         return out
+
+
+def solve_grouped(ctxs, bs, mode: int, qs, Qes=None):
+    """cpm_solve_grouped: one split-BF16 solve over several contexts (sharing one
+    stream); bs[i] (batch_i, n_i), qs[i] (batch_i, n_i), Qes[i] (batch_i, n_e_i) or None."""
+    k = len(ctxs)
+    if not (len(bs) == len(qs) == k) or (Qes is not None and len(Qes) != k):
+        raise ValueError("one b, q (and Qe) per context")
+    f32 = {_is_f32(b) for b in bs}
+    if len(f32) != 1:
+        raise ValueError("all b must have the same dtype")
+    for c, b, q, i in zip(ctxs, bs, qs, range(k)):
+        _expect(q, "float64", 2)
+        n, ne = int(c.info("n")), int(c.info("ne"))
+        if b.dim() != 2 or tuple(b.shape) != tuple(q.shape) or b.shape[1] != n:
+            raise ValueError(f"context {i}: b and q must both be (batch, {n})")
+        if Qes is not None and Qes[i] is not None:
+            _expect(Qes[i], "float64", 2)
+            if tuple(Qes[i].shape) != (b.shape[0], ne):
+                raise ValueError(f"context {i}: Qe must be (batch, {ne})")
+    vp = ctypes.c_void_p
+    H = (vp * k)(*[c._h.value for c in ctxs])
+    Bt = (ctypes.c_int * k)(*[b.shape[0] for b in bs])
+    Bp = (vp * k)(*[_ptr(b) for b in bs])
+    Qp = (vp * k)(*[_ptr(q) for q in qs])
+    Ep = (vp * k)(*[_ptr(e) for e in Qes]) if Qes is not None else None
+    st = lib().cpm_solve_grouped(H, k, Bt, Bp, f32.pop(), mode, Qp, Ep)
+    if st != OK:
+        raise CpmError(st, "cpm_solve_grouped: " + lib().cpm_last_error(ctxs[0]._h).decode(errors="replace"))
+    return qs
 
 
 def _expect(t, dtype: str, ndim: int):

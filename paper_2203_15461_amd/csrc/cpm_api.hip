@@ -254,6 +254,35 @@ cpm_status ensure_solve_buffers(cpm_ctx* c, int batch) {
   return CPM_OK;
 }
 
+// split-BF16 GEMM configuration for a padded row count: the autotuned one,
+// else 64-row tiles, no K split, one workgroup per tile
+cpm_ctx::GemmCfg bf16_cfg(const cpm_ctx* c, int rows) {
+  auto it = c->tuned.find(rows);
+  if (it != c->tuned.end()) return it->second;
+  return cpm_ctx::GemmCfg{};
+}
+
+cpm_status ensure_kpart(cpm_ctx* c, size_t len) {
+  Buffers& b = c->b;
+  if (len <= b.kpart_len) return CPM_OK;
+  dfree(c, b.kpart);
+  TRY(dalloc(c, &b.kpart, len));
+  b.kpart_len = len;
+  return CPM_OK;
+}
+
+// one split-BF16 product C (+)= X S~ over `rows` rows of this context
+void enqueue_bf16(cpm_ctx* c, const double* x, double* y, int rows, bool accumulate,
+                  const cpm_ctx::GemmCfg& cfg) {
+  const int npad = c->npad;
+  GemmGroupBf grp{};
+  grp.nprob = 1;
+  grp.p[0] = gemm_bf16x3_problem(rows, npad, npad, x, npad, c->b.Shi, c->b.Slo, npad, y, npad,
+                                 accumulate ? 1 : 0, cfg.bm, cfg.ks, c->b.kpart);
+  group_finish(grp);
+  launch_gemm_bf16x3_group(c->stream, grp, cfg.bm, cfg.grid > 0 ? cfg.grid : grp.total);
+}
+
 // upload the k set and electrolyte charges on first device use
 cpm_status ensure_uploaded(cpm_ctx* c) {
   Buffers& b = c->b;
@@ -810,7 +839,12 @@ cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
     return fail(c, CPM_EINVAL, "split-BF16 copy of S not kept");
   const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
   const int rows = gemm ? ((batch + TILE - 1) / TILE) * TILE : batch;
-  return ensure_solve_buffers(c, rows);
+  TRY(ensure_solve_buffers(c, rows));
+  if (prec == 2) {
+    const cpm_ctx::GemmCfg cfg = bf16_cfg(c, rows);
+    if (cfg.ks > 1) TRY(ensure_kpart(c, (size_t)cfg.ks * rows * c->npad));
+  }
+  return CPM_OK;
 }
 
 // kernel launches of cpm_solve_charges (no allocation, copy or memset)
@@ -839,7 +873,7 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
                       accumulate ? 1.0 : 0.0, y, npad, 0, 0);
     } else {
       Timed t(c, "gemm_bf16x3");
-      launch_gemm_bf16x3(st, rows, npad, npad, x, b.Shi, b.Slo, y, accumulate ? 1 : 0);
+      enqueue_bf16(c, x, y, rows, accumulate, bf16_cfg(c, rows));
     }
   };
 
@@ -967,6 +1001,118 @@ cpm_status cpm_replay_step(cpm_ctx* c) {
   return CPM_OK;
 }
 
+cpm_status cpm_autotune(cpm_ctx* c, int batch, int reps) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_inv || !(c->store & CPM_STORE_BF16X2) || !c->b.Shi)
+    return fail(c, CPM_ESTATE, "cpm_autotune needs cpm_invert with the split-BF16 copy of S");
+  if (batch <= 0 || reps <= 0) return fail(c, CPM_EINVAL, "need batch > 0 and reps > 0");
+  const int rows = ((batch + TILE - 1) / TILE) * TILE, npad = c->npad;
+  TRY(ensure_solve_buffers(c, rows));
+  TRY(ensure_kpart(c, (size_t)4 * rows * npad));
+  hipEvent_t e0, e1;
+  HIP_TRY(c, hipEventCreate(&e0));
+  HIP_TRY(c, hipEventCreate(&e1));
+  cpm_ctx::GemmCfg best;
+  best.us = 1e300;
+  for (int bm : {32, 64, 128}) {
+    if (rows % bm) continue;
+    for (int ks : {1, 2, 4}) {
+      const int total = rows / bm * (npad / 64) * ks;
+      std::vector<int> grids{total};
+      for (int g : {256, 512, 1024})
+        if (g < total) grids.push_back(g);
+      for (int grid : grids) {
+        cpm_ctx::GemmCfg cfg;
+        cfg.bm = bm; cfg.ks = ks; cfg.grid = grid;
+        enqueue_bf16(c, c->b.bpad, c->b.qt, rows, false, cfg);    // warm-up
+        HIP_TRY(c, hipEventRecord(e0, c->stream));
+        for (int r = 0; r < reps; ++r) enqueue_bf16(c, c->b.bpad, c->b.qt, rows, false, cfg);
+        HIP_TRY(c, hipEventRecord(e1, c->stream));
+        TRY(launched(c, "autotune"));
+        HIP_TRY(c, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&ms, e0, e1));
+        cfg.us = 1e3 * ms / reps;
+        if (cfg.us < best.us) best = cfg;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  c->tuned[rows] = best;
+  c->last_tune = best;
+  return CPM_OK;
+}
+
+cpm_status cpm_solve_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
+                             const void* const* d_b, int b_is_f32, unsigned mode,
+                             double* const* d_q, double* const* d_Qe) {
+  if (!ctxs || n_ctx <= 0 || !batch || !d_b || !d_q) return CPM_EINVAL;
+  cpm_ctx* c0 = ctxs[0];
+  if (!c0) return CPM_EINVAL;
+  if (n_ctx > GB_MAXP) return fail(c0, CPM_EINVAL, "at most %d contexts per group", GB_MAXP);
+  if ((mode & 0xffu) != CPM_SOLVE_BF16X2 || (mode & ~0x1ffu))
+    return fail(c0, CPM_EUNSUPPORTED, "grouped solves run the split-BF16 mode (0x2 or 0x102)");
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctxs[i]) return fail(c0, CPM_EINVAL, "context %d is NULL", i);
+    if (ctxs[i]->stream != c0->stream)
+      return fail(c0, CPM_EINVAL, "grouped contexts must share one stream");
+    for (int j = 0; j < i; ++j)
+      if (ctxs[j] == ctxs[i]) return fail(c0, CPM_EINVAL, "context %d appears twice", i);
+    TRY(sc_prepare(ctxs[i], batch[i], d_b[i], b_is_f32, mode, d_q[i]));
+  }
+  const bool refine = (mode & CPM_SOLVE_REFINE) != 0;
+  hipStream_t st = c0->stream;
+  // one persistent launch of S~ products over every context's tiles
+  auto group_apply = [&](bool second) {
+    GemmGroupBf grp{};
+    grp.nprob = n_ctx;
+    for (int i = 0; i < n_ctx; ++i) {
+      cpm_ctx* c = ctxs[i];
+      const int rows = ((batch[i] + TILE - 1) / TILE) * TILE;
+      grp.p[i] = gemm_bf16x3_problem(rows, c->npad, c->npad, second ? c->b.res : c->b.bpad,
+                                     c->npad, c->b.Shi, c->b.Slo, c->npad,
+                                     second ? c->b.qt : c->b.qpad, c->npad, second ? 1 : 0, 64,
+                                     1, nullptr);
+    }
+    group_finish(grp);
+    Timed t(c0, "gemm_bf16x3_grouped");
+    launch_gemm_bf16x3_group(st, grp, 64, std::min(grp.total, 1024));
+  };
+  for (int i = 0; i < n_ctx; ++i) {
+    cpm_ctx* c = ctxs[i];
+    launch_row_means(st, c->n, batch[i], d_b[i], b_is_f32, c->n, c->b.means);
+    launch_pad_rows(st, c->n, c->npad, batch[i], ((batch[i] + TILE - 1) / TILE) * TILE, d_b[i],
+                    b_is_f32, c->b.means, c->b.bpad);
+  }
+  group_apply(false);
+  for (int i = 0; i < n_ctx; ++i) {
+    cpm_ctx* c = ctxs[i];
+    Buffers& b = c->b;
+    const int n = c->n, npad = c->npad, rows = ((batch[i] + TILE - 1) / TILE) * TILE;
+    double* Qe = d_Qe ? d_Qe[i] : nullptr;
+    if (!refine) {
+      launch_finalize(st, n, batch[i], b.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, d_q[i], n, Qe);
+      continue;
+    }
+    launch_finalize(st, n, batch[i], b.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, b.qt, npad,
+                    nullptr);
+    launch_make_rhs(st, n, npad, batch[i], d_b[i], b_is_f32, b.vat, b.res);
+    launch_gemm_f64(st, false, false, rows, npad, npad, -1.0, b.qt, npad, b.A, npad, 1.0, b.res,
+                    npad, 0, 0);
+    launch_center_rows(st, n, npad, batch[i], b.res);
+  }
+  if (refine) {
+    group_apply(true);
+    for (int i = 0; i < n_ctx; ++i) {
+      cpm_ctx* c = ctxs[i];
+      launch_finalize(st, c->n, batch[i], c->b.qt, c->npad, nullptr, c->b.u, c->b.scal, c->b.eid,
+                      c->n_e, d_q[i], c->n, d_Qe ? d_Qe[i] : nullptr);
+    }
+  }
+  return launched(c0, "grouped solve");
+}
+
 cpm_status cpm_enable_timing(cpm_ctx* c, const char* families) {
   if (!c) return CPM_EINVAL;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1040,6 +1186,11 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_NRUNS: *out = c->nruns; return CPM_OK;
     case CPM_INFO_NLAYERS: *out = c->nlayers; return CPM_OK;
     case CPM_INFO_SF_MATRIX: *out = (c->sf_mfma && c->use_sf_mfma) ? 1.0 : 0.0; return CPM_OK;
+    case CPM_INFO_TUNE_BM: *out = c->last_tune.bm; return CPM_OK;
+    case CPM_INFO_TUNE_KS: *out = c->last_tune.ks; return CPM_OK;
+    case CPM_INFO_TUNE_GRID: *out = c->last_tune.grid; return CPM_OK;
+    case CPM_INFO_TUNE_US: *out = c->last_tune.us; return CPM_OK;
+    case CPM_INFO_GROUP: *out = c->pv_group; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -1069,6 +1220,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.mz); dfree(b.qt);
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
+  dfree(b.kpart);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

@@ -97,6 +97,8 @@ struct Buffers {
   double* bpad = nullptr;          // padded b for batched solves (bpad_rows x npad)
   double* qpad = nullptr;          // padded GEMM output (bpad_rows x npad)
   double* means = nullptr;         // per-vector uniform part removed before S products
+  double* kpart = nullptr;         // split-K partial slices of the batched split-BF16 GEMM
+  size_t kpart_len = 0;
   int bpad_rows = 0;
   double* scal = nullptr;          // small scalars (s and friends)
 };
@@ -144,6 +146,10 @@ struct cpm_ctx {
   std::vector<double> h_w2;
   std::vector<int> h_kx, h_ky, h_kz;
   cpm::Buffers b;
+  // split-BF16 batched GEMM configuration per padded row count (cpm_autotune)
+  struct GemmCfg { int bm = 64, ks = 1, grid = 0; double us = 0.0; };
+  std::map<int, GemmCfg> tuned;
+  GemmCfg last_tune;
   // captured step (cpm_capture_step / cpm_replay_step)
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
@@ -217,8 +223,22 @@ void launch_pad_rows(hipStream_t st, int n, int npad, int batch, int rows, const
 // C (M x N, FP64) (+)= Bm (M x K, FP64, split to BF16 hi/lo on load) * S, with
 // S symmetric given as BF16 hi/lo (N x K row-major): 3 MFMA products, FP32
 // accumulation.  M, N multiples of 64, K multiple of 32.
-void launch_gemm_bf16x3(hipStream_t st, int M, int N, int K, const double* Bm, const uint16_t* Shi,
-                        const uint16_t* Slo, double* C, int accumulate);
+// split-BF16 GEMM problems, one persistent launch per group (see dense.hip)
+constexpr int GB_MAXP = 8;
+struct GemmProbBf {
+  const double* X; const uint16_t* Shi; const uint16_t* Slo; double* C; double* part;
+  int M, N, K, ldx, lds, ldc, tiles_m, tiles_n, ks, accumulate;
+};
+struct GemmGroupBf {
+  int nprob, total;
+  int start[GB_MAXP + 1];
+  GemmProbBf p[GB_MAXP];
+};
+GemmProbBf gemm_bf16x3_problem(int M, int N, int K, const double* X, int ldx,
+                               const uint16_t* Shi, const uint16_t* Slo, int lds, double* C,
+                               int ldc, int accumulate, int bm, int ks, double* part);
+void group_finish(GemmGroupBf& grp);
+void launch_gemm_bf16x3_group(hipStream_t st, const GemmGroupBf& grp, int bm, int grid);
 
 // b vector
 void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk,

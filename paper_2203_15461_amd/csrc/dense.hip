@@ -10,6 +10,8 @@
 // v_mfma_f64_16x16x4f64 operand layout (lane l of a wave64):
 //   A operand: element (row l%16, k l/16); B operand: (k l/16, col l%16);
 //   result register r: element (row l/16 + 4 r, col l%16).
+#include <algorithm>
+
 #include "cpm_internal.h"
 
 namespace cpm {
@@ -515,83 +517,189 @@ void launch_pad_rows(hipStream_t st, int n, int npad, int batch, int rows, const
 }
 
 // ---------------------------------------------------------------------------
-// Batched solve on BF16 matrix cores: C (+)= Bm S with both operands split as
+// Batched solve on BF16 matrix cores: C (+)= X S with both operands split as
 // x ~ hi + lo (BF16 pairs) and three products hi*hi + hi*lo + lo*hi
 // accumulated in FP32 (the lo*lo term is below FP32 resolution of the sum).
 // S is symmetric, so its rows serve as the columns of the right operand and
-// both operands are read K-contiguous.  64x64 tile, 4 waves of 2x2
-// v_mfma_f32_16x16x32_bf16 blocks, K slabs of 32 through LDS.
+// both operands are read K-contiguous.
+//
+// One persistent kernel serves a group of up to GB_MAXP independent
+// problems (contexts of different sizes): the tiles of all problems form one
+// list that the workgroups walk with a stride of the grid size.  Tile shape
+// BM x 64 (BM = 32, 64 or 128 rows of X) and the split of K into ks parts
+// are chosen per problem size by the autotuner; with ks > 1 each part
+// writes its own slice of a partial buffer and k_sum_ksplit adds the slices
+// in a fixed order.  4 waves in a 2 x 2 layout, v_mfma_f32_16x16x32_bf16,
+// K slabs of 32 through LDS with the next slab prefetched into registers.
 //   operand layout (lane l): A (row l%16, k 8(l/16)..+7); B (k 8(l/16)..+7,
 //   col l%16); result register r: (row 4(l/16) + r, col l%16).
 // ---------------------------------------------------------------------------
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__global__ void __launch_bounds__(256) k_gemm_bf16x3(int M, int N, int K,
-                                                     const double* __restrict__ Bm,
-                                                     const uint16_t* __restrict__ Shi,
-                                                     const uint16_t* __restrict__ Slo,
-                                                     double* __restrict__ C, int accumulate) {
-  constexpr int P = 40;  // LDS row pitch in BF16 elements (32 + 8)
-  __shared__ __attribute__((aligned(16))) uint16_t Ah[64 * P], Al[64 * P], Bh[64 * P], Bl[64 * P];
-  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+template <int BM>
+__global__ void __launch_bounds__(256) k_gemm_bf16x3(GemmGroupBf grp) {
+  constexpr int P = 40;                 // LDS row pitch in BF16 elements (32 + 8)
+  constexpr int FM = BM / 32;           // 16-row blocks per wave
+  constexpr int XR = BM / 64 > 0 ? BM / 64 : 1;   // X rows per thread and slab (BM >= 64)
+  __shared__ __attribute__((aligned(16))) uint16_t Ah[BM * P], Al[BM * P], Bh[64 * P], Bl[64 * P];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  v4f acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lc = (tid & 3) * 8;   // this thread's load slot: row, first k
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    {
-      const double* src = Bm + (size_t)(m0 + lr) * K + k0 + lc;
-      uint16_t hi[8], lo[8];
+  const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * 32;
+  for (int t = blockIdx.x; t < grp.total; t += gridDim.x) {
+    int p = 0;
+    while (p + 1 < grp.nprob && t >= grp.start[p + 1]) ++p;
+    const GemmProbBf& pr = grp.p[p];
+    const int local = t - grp.start[p];
+    const int kpart = local % pr.ks, rest = local / pr.ks;
+    const int m0 = (rest / pr.tiles_n) * BM, n0 = (rest % pr.tiles_n) * 64;
+    const int kchunk = ((pr.K + pr.ks - 1) / pr.ks + 31) / 32 * 32;
+    const int kb = kpart * kchunk, ke = min(pr.K, kb + kchunk);
+    v4f acc[FM][2];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
-        const float f = (float)src[t];
-        hi[t] = f32_to_bf16(f);
-        lo[t] = f32_to_bf16(f - bf16_to_f32(hi[t]));
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+    // loader slots: X rows (BM x 32 FP64 per slab), S rows (64 x 32 BF16 hi and lo)
+    const int sr = tid >> 2, sc = (tid & 3) * 8;
+    double xv[XR][8 / (BM >= 64 ? 1 : 2)];
+    uint4 sh, sl;
+    auto load = [&](int k0) {
+      if constexpr (BM >= 64) {
+#pragma unroll
+        for (int u = 0; u < XR; ++u) {
+          const double* src = pr.X + (size_t)(m0 + sr + 64 * u) * pr.ldx + k0 + sc;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) xv[u][q] = src[q];
+        }
+      } else {
+        const double* src = pr.X + (size_t)(m0 + (tid >> 3)) * pr.ldx + k0 + (tid & 7) * 4;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) xv[0][q] = src[q];
       }
-      *reinterpret_cast<uint4*>(&Ah[lr * P + lc]) = *reinterpret_cast<const uint4*>(hi);
-      *reinterpret_cast<uint4*>(&Al[lr * P + lc]) = *reinterpret_cast<const uint4*>(lo);
-      const size_t so = (size_t)(n0 + lr) * K + k0 + lc;
-      *reinterpret_cast<uint4*>(&Bh[lr * P + lc]) = *reinterpret_cast<const uint4*>(Shi + so);
-      *reinterpret_cast<uint4*>(&Bl[lr * P + lc]) = *reinterpret_cast<const uint4*>(Slo + so);
-    }
-    __syncthreads();
-    const int kk = 8 * (lane >> 4), rr = lane & 15;
-    v8bf ah[2], al[2], bh[2], bl[2];
+      const size_t so = (size_t)(n0 + sr) * pr.lds + k0 + sc;
+      sh = *reinterpret_cast<const uint4*>(pr.Shi + so);
+      sl = *reinterpret_cast<const uint4*>(pr.Slo + so);
+    };
+    auto store = [&]() {
+      if constexpr (BM >= 64) {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      ah[a] = *reinterpret_cast<const v8bf*>(&Ah[(wm + a * 16 + rr) * P + kk]);
-      al[a] = *reinterpret_cast<const v8bf*>(&Al[(wm + a * 16 + rr) * P + kk]);
-      bh[a] = *reinterpret_cast<const v8bf*>(&Bh[(wn + a * 16 + rr) * P + kk]);
-      bl[a] = *reinterpret_cast<const v8bf*>(&Bl[(wn + a * 16 + rr) * P + kk]);
-    }
+        for (int u = 0; u < XR; ++u) {
+          uint16_t hi[8], lo[8];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+          for (int q = 0; q < 8; ++q) {
+            const float f = (float)xv[u][q];
+            hi[q] = f32_to_bf16(f);
+            lo[q] = f32_to_bf16(f - bf16_to_f32(hi[q]));
+          }
+          *reinterpret_cast<uint4*>(&Ah[(sr + 64 * u) * P + sc]) = *reinterpret_cast<const uint4*>(hi);
+          *reinterpret_cast<uint4*>(&Al[(sr + 64 * u) * P + sc]) = *reinterpret_cast<const uint4*>(lo);
+        }
+      } else {
+        uint16_t hi[4], lo[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float f = (float)xv[0][q];
+          hi[q] = f32_to_bf16(f);
+          lo[q] = f32_to_bf16(f - bf16_to_f32(hi[q]));
+        }
+        const int r = tid >> 3, c4 = (tid & 7) * 4;
+        *reinterpret_cast<uint2*>(&Ah[r * P + c4]) = *reinterpret_cast<const uint2*>(hi);
+        *reinterpret_cast<uint2*>(&Al[r * P + c4]) = *reinterpret_cast<const uint2*>(lo);
+      }
+      *reinterpret_cast<uint4*>(&Bh[sr * P + sc]) = sh;
+      *reinterpret_cast<uint4*>(&Bl[sr * P + sc]) = sl;
+    };
+    if (kb < ke) load(kb);
+    for (int k0 = kb; k0 < ke; k0 += 32) {
+      __syncthreads();                 // the previous slab (or tile) is no longer read
+      store();
+      __syncthreads();
+      if (k0 + 32 < ke) load(k0 + 32);
+      const int kk = 8 * (lane >> 4), rr = lane & 15;
+      v8bf ah[FM], al[FM], bh[2], bl[2];
+#pragma unroll
+      for (int a = 0; a < FM; ++a) {
+        ah[a] = *reinterpret_cast<const v8bf*>(&Ah[(wm + a * 16 + rr) * P + kk]);
+        al[a] = *reinterpret_cast<const v8bf*>(&Al[(wm + a * 16 + rr) * P + kk]);
+      }
 #pragma unroll
       for (int b = 0; b < 2; ++b) {
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+        bh[b] = *reinterpret_cast<const v8bf*>(&Bh[(wn + b * 16 + rr) * P + kk]);
+        bl[b] = *reinterpret_cast<const v8bf*>(&Bl[(wn + b * 16 + rr) * P + kk]);
       }
-    __syncthreads();
+#pragma unroll
+      for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
+          acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
+        }
+    }
+    // ks == 1: C (+)= result; ks > 1: slice kpart of the partial buffer
+    double* out = pr.ks > 1 ? pr.part + (size_t)kpart * pr.M * pr.ldc : pr.C;
+    const bool acc_c = pr.ks == 1 && pr.accumulate;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = m0 + wm + a * 16 + 4 * (lane >> 4) + r;
+          const int col = n0 + wn + b * 16 + (lane & 15);
+          double* cp = out + (size_t)row * pr.ldc + col;
+          const double v = (double)acc[a][b][r];
+          *cp = acc_c ? *cp + v : v;
+        }
   }
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b)
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wm + a * 16 + 4 * (lane >> 4) + r;
-        const int col = n0 + wn + b * 16 + (lane & 15);
-        double* cp = C + (size_t)row * N + col;
-        const double v = (double)acc[a][b][r];
-        *cp = accumulate ? *cp + v : v;
-      }
 }
 
-void launch_gemm_bf16x3(hipStream_t st, int M, int N, int K, const double* Bm, const uint16_t* Shi,
-                        const uint16_t* Slo, double* C, int accumulate) {
-  dim3 grid(N / 64, M / 64), block(256);
-  hipLaunchKernelGGL(k_gemm_bf16x3, grid, block, 0, st, M, N, K, Bm, Shi, Slo, C, accumulate);
+// C (+)= sum over ks slices of part, in slice order (fixed), M x ldc elements
+__global__ void k_sum_ksplit(size_t count, int ks, const double* __restrict__ part,
+                             double* __restrict__ C, int accumulate) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  double s = part[e];
+  for (int k = 1; k < ks; ++k) s += part[(size_t)k * count + e];
+  C[e] = accumulate ? C[e] + s : s;
+}
+
+void launch_gemm_bf16x3_group(hipStream_t st, const GemmGroupBf& grp, int bm, int grid) {
+  if (grp.total <= 0) return;
+  const int g = std::max(1, std::min(grid, grp.total));
+  if (bm == 32)
+    hipLaunchKernelGGL(k_gemm_bf16x3<32>, dim3(g), dim3(256), 0, st, grp);
+  else if (bm == 128)
+    hipLaunchKernelGGL(k_gemm_bf16x3<128>, dim3(g), dim3(256), 0, st, grp);
+  else
+    hipLaunchKernelGGL(k_gemm_bf16x3<64>, dim3(g), dim3(256), 0, st, grp);
+  for (int p = 0; p < grp.nprob; ++p) {
+    const GemmProbBf& pr = grp.p[p];
+    if (pr.ks > 1) {
+      const size_t count = (size_t)pr.M * pr.ldc;
+      hipLaunchKernelGGL(k_sum_ksplit, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st,
+                         count, pr.ks, pr.part, pr.C, pr.accumulate);
+    }
+  }
+}
+
+// Fill one problem of a group: X (M x K, ld ldx), S hi/lo (N x K, ld lds),
+// C (M x ldc); part: ks x M x ldc doubles when ks > 1.
+GemmProbBf gemm_bf16x3_problem(int M, int N, int K, const double* X, int ldx,
+                               const uint16_t* Shi, const uint16_t* Slo, int lds, double* C,
+                               int ldc, int accumulate, int bm, int ks, double* part) {
+  GemmProbBf pr{};
+  pr.X = X; pr.Shi = Shi; pr.Slo = Slo; pr.C = C; pr.part = part;
+  pr.M = M; pr.N = N; pr.K = K; pr.ldx = ldx; pr.lds = lds; pr.ldc = ldc;
+  pr.tiles_m = M / bm; pr.tiles_n = N / 64; pr.ks = ks; pr.accumulate = accumulate;
+  return pr;
+}
+
+void group_finish(GemmGroupBf& grp) {
+  grp.start[0] = 0;
+  for (int p = 0; p < grp.nprob; ++p)
+    grp.start[p + 1] = grp.start[p] + grp.p[p].tiles_m * grp.p[p].tiles_n * grp.p[p].ks;
+  grp.total = grp.start[grp.nprob];
 }
 
 }  // namespace cpm

@@ -64,6 +64,8 @@ def test_null_arguments():
     assert L.cpm_solve_charges(None, 1, None, 0, 0, None, None) == cpm.EINVAL
     assert L.cpm_capture_step(None, 1, None, None, 0, 0, None, None) == cpm.EINVAL
     assert L.cpm_replay_step(None) == cpm.EINVAL
+    assert L.cpm_autotune(None, 64, 1) == cpm.EINVAL
+    assert L.cpm_solve_grouped(None, 1, None, None, 0, 0x102, None, None) == cpm.EINVAL
     assert L.cpm_last_error(None) == b"no context"
     L.cpm_destroy(None)
 

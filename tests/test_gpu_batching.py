@@ -1,0 +1,148 @@
+"""Autotuned and grouped split-BF16 batched solves against single solves and the oracle.
+
+cpm_autotune picks the tile height, K split and persistent grid of the
+split-BF16 product Q~ = B S~ by timing; whatever it picks, the refined
+charges must stay within the split-BF16 tolerance (1e-5 relative, |sum q| <=
+1e-12).  cpm_solve_grouped solves contexts of uneven size with one
+persistent launch per S~ product; with the untuned tile configuration it
+runs the same per-tile arithmetic as cpm_solve_charges, so the results are
+bitwise equal.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpm_oracle as O
+from paper_2203_15461_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def cpm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_15461_amd import cpm as C
+    C.lib()
+    return C
+
+
+def _b_for(ctx, w, snaps):
+    xyz = torch.as_tensor(np.stack([I.snapshot(w, s) for s in snaps]), dtype=torch.float64,
+                          device="cuda").contiguous()
+    b = torch.empty((len(snaps), w.n), dtype=torch.float64, device="cuda")
+    ctx.potential_vector(xyz, b)
+    return b
+
+
+def _oracle_q(w, snaps):
+    p = O.params_for(w)
+    S = O.capacitance(O.elastance(w.electrode_xyz, p)).S
+    v = O.applied_potential(w.electrode_id, w.v_electrode)
+    return np.array([O.charges(S, O.potential_vector(w.electrode_xyz, I.snapshot(w, s),
+                                                     w.electrolyte_q, p), v) for s in snaps])
+
+
+def test_autotune_keeps_parity(cpm):
+    w = I.small_capacitor("a")
+    snaps = list(range(70))                     # 128 padded rows: every tile height is eligible
+    say(f"autotune small_capacitor_a batch={len(snaps)}")
+    ctx = cpm.setup(w, store=1 | 4)
+    b = _b_for(ctx, w, snaps)
+    q0 = torch.empty_like(b)
+    ctx.solve_charges(b, 0x102, q0)
+    cfg = ctx.autotune(len(snaps), reps=3)
+    say(f"autotune picked {cfg}")
+    assert cfg["bm"] in (32, 64, 128) and cfg["ks"] in (1, 2, 4) and cfg["grid"] >= 1
+    assert cfg["us"] > 0
+    q1 = torch.empty_like(b)
+    Qe = torch.empty((len(snaps), 2), dtype=torch.float64, device="cuda")
+    ctx.solve_charges(b, 0x102, q1, Qe)
+    ctx.synchronize()
+    q0, q1 = q0.cpu().numpy(), q1.cpu().numpy()
+    qo = _oracle_q(w, snaps[:6])
+    for j in range(6):
+        assert np.abs(q1[j] - qo[j]).max() / np.abs(qo[j]).max() < 1e-5
+    assert np.abs(q1 - q0).max() / np.abs(q0).max() < 1e-5
+    assert np.abs(q1.sum(axis=1)).max() <= 1e-12
+    Qo = np.array([O.electrode_totals(q, w.electrode_id, 2) for q in qo])
+    assert np.abs(Qe.cpu().numpy()[:6] - Qo).max() <= 1e-5 * np.abs(Qo).max()
+    ctx.close()
+
+
+def test_autotune_2880(cpm):
+    w = I.graphite_capacitor()
+    say("autotune graphite_capacitor_2880 batch=256")
+    ctx = cpm.setup(w, store=1 | 4)
+    cfg = ctx.autotune(256, reps=3)
+    say(f"autotune picked {cfg}")
+    b = _b_for(ctx, w, range(256))
+    q = torch.empty_like(b)
+    ctx.solve_charges(b, 0x102, q)
+    q64 = torch.empty_like(b)
+    ctx.solve_charges(b, 0x000, q64)
+    ctx.synchronize()
+    q, q64 = q.cpu().numpy(), q64.cpu().numpy()
+    assert np.abs(q - q64).max() / np.abs(q64).max() < 1e-5
+    assert np.abs(q.sum(axis=1)).max() <= 1e-12
+    ctx.close()
+
+
+@pytest.mark.parametrize("mode", [0x002, 0x102])
+def test_grouped_matches_single(cpm, mode):
+    ws = [I.small_capacitor("a"), I.small_capacitor("b"), I.graphite_capacitor()]
+    batches = [5, 70, 3]
+    say(f"grouped solve of {[w.n for w in ws]} atoms, batches {batches}, mode 0x{mode:x}")
+    s = torch.cuda.Stream()
+    ctxs = [cpm.setup(w, store=1 | 4, stream=s) for w in ws]
+    with torch.cuda.stream(s):
+        bs = [_b_for(c, w, range(k)) for c, w, k in zip(ctxs, ws, batches)]
+        single = [torch.empty_like(b) for b in bs]
+        grouped = [torch.full_like(b, float("nan")) for b in bs]
+        Qes = [torch.empty((k, 2), dtype=torch.float64, device="cuda") for k in batches]
+        for c, b, q in zip(ctxs, bs, single):
+            c.solve_charges(b, mode, q)
+        cpm.solve_grouped(ctxs, bs, mode, grouped, Qes)
+    s.synchronize()
+    for i, (w, q1, q2, Qe) in enumerate(zip(ws, single, grouped, Qes)):
+        q1, q2 = q1.cpu().numpy(), q2.cpu().numpy()
+        assert np.array_equal(q1, q2), f"context {i}"
+        assert np.abs(q2.sum(axis=1)).max() <= 1e-12
+        Q = np.array([O.electrode_totals(q, w.electrode_id, 2) for q in q2])
+        assert np.allclose(Qe.cpu().numpy(), Q, rtol=0, atol=1e-12 * max(1.0, np.abs(Q).max()))
+    # the first context against the oracle
+    qo = _oracle_q(ws[0], range(batches[0]))
+    tol = 1e-5 if mode & 0x100 else 5e-4
+    assert np.abs(grouped[0].cpu().numpy() - qo).max() / np.abs(qo).max() < tol
+    for c in ctxs:
+        c.close()
+
+
+def test_grouped_errors(cpm):
+    w = I.small_capacitor("a")
+    say("grouped solve: errors")
+    s = torch.cuda.Stream()
+    c1 = cpm.setup(w, store=1 | 4, stream=s)
+    c2 = cpm.setup(w, store=1 | 4)                 # another stream
+    with torch.cuda.stream(s):
+        b = _b_for(c1, w, range(2))
+        q = torch.empty_like(b)
+    s.synchronize()
+    with pytest.raises(cpm.CpmError) as ei:
+        cpm.solve_grouped([c1, c1], [b, b], 0x102, [q, q])
+    assert ei.value.status == cpm.EINVAL
+    with pytest.raises(cpm.CpmError) as ei:
+        cpm.solve_grouped([c1], [b], 0x000, [q])
+    assert ei.value.status == cpm.EUNSUPPORTED
+    with pytest.raises(cpm.CpmError) as ei:
+        cpm.solve_grouped([c1, c2], [b, b], 0x102, [q, torch.empty_like(q)])
+    assert ei.value.status == cpm.EINVAL
+    c1.close()
+    c2.close()
