@@ -46,7 +46,9 @@ def parse():
                     help="snapshots per step (default 1000 at n=2880, 128 at n=20064)")
     ap.add_argument("--mode", default="bf16r", choices=sorted(MODES))
     ap.add_argument("--workload", default="graphite_capacitor_2880",
-                    choices=["graphite_capacitor_2880", "graphite_capacitor_20064"])
+                    choices=["graphite_capacitor_2880", "graphite_capacitor_20064", "mixed8"])
+    ap.add_argument("--no-20k", action="store_true",
+                    help="skip the secondary one-step measurement at N = 20064")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
@@ -60,40 +62,69 @@ def main():
                                    "design note, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2203_15461_amd import cpm
     from paper_2203_15461_amd import inputs as I
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
-    store, b_f32, mode, dtype = MODES[args.mode]
+    cpm.lib()
+    if args.workload == "mixed8":
+        out = run_mixed(args)
+        print(json.dumps(out), flush=True)
+        return
     if args.workload == "graphite_capacitor_2880":
         w = I.graphite_capacitor()
         B = args.batch or 1000
     else:
         w = I.scaled_graphite_capacitor(20000)
         B = args.batch or 128
-    t0 = time.time()
-    rng = np.random.default_rng(I.BASE_SEED + 1)
+    out = run_workload(args, w, B, args.workload, args.steps, args.warmup, args.calibrate_copy)
+    if args.workload == "graphite_capacitor_2880" and not args.no_20k:
+        # the metric's second point: one step of 32 configurations at N = 20064
+        w20 = I.scaled_graphite_capacitor(20000)
+        r = run_workload(args, w20, 32, "graphite_capacitor_20064", 1, 1, False)
+        out["workload_20064"] = {k: r[k] for k in ("value", "ms_per_step", "config", "roofline",
+                                                   "phase_s", "solve_only_rate",
+                                                   "plain_fp64_per_step_rate", "matvec_roofline",
+                                                   "max_abs_sum_q")}
+    if not args.no_cpu_baseline and w.n < 10000:
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out), flush=True)
+
+
+def synthetic_configurations(w, B, seed, dev):
+    """B Gaussian-jittered (sigma 0.1 A) copies of the electrolyte, x and y wrapped."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(seed)
     base = w.electrolyte_xyz
     snaps = base[None] + rng.normal(0.0, 0.1, size=(B,) + base.shape)
     snaps[..., 0] %= w.Lx
     snaps[..., 1] %= w.Ly
-    xyz = torch.as_tensor(snaps, dtype=torch.float64, device=dev).contiguous()
+    return torch.as_tensor(snaps, dtype=torch.float64, device=dev).contiguous()
+
+
+def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
+    import torch
+    from paper_2203_15461_amd import cpm
+    from paper_2203_15461_amd import inputs as I
+    dev = torch.device("cuda:0")
+    store, b_f32, mode, dtype = MODES[args.mode]
+    t0 = time.time()
+    xyz = synthetic_configurations(w, B, I.BASE_SEED + 1, dev)
     R = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device=dev).contiguous()
     eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device=dev).contiguous()
     bvec = torch.empty((B, w.n), dtype=torch.float32 if b_f32 else torch.float64, device=dev)
     q = torch.empty((B, w.n), dtype=torch.float64, device=dev)
     Qe = torch.empty((B, 2), dtype=torch.float64, device=dev)
-    if args.calibrate_copy:
+    if calibrate_copy:
         src = torch.ones(1 << 27, dtype=torch.float64, device=dev)   # 1 GiB
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    print(f"[bench] inputs ready in {time.time() - t0:.1f}s: n={w.n} m={w.m} batch={B} "
+    print(f"[bench] {name}: inputs ready in {time.time() - t0:.1f}s: n={w.n} m={w.m} batch={B} "
           f"mode={args.mode}", file=sys.stderr, flush=True)
 
     ctx = cpm.Context(cpm.Params.of(w))
@@ -106,21 +137,24 @@ def main():
         ctx.potential_vector(xyz, bvec)
         ctx.solve_charges(bvec, mode, q, Qe)
 
-    for i in range(args.warmup):
+    tune = None
+    for i in range(warmup):
         step()
         torch.cuda.synchronize()
-        print(f"[bench] warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+        if i == 0 and store & cpm.STORE_BF16X2:
+            tune = ctx.autotune(B, reps=3)      # tile shapes of the batched product
+        print(f"[bench] {name}: warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
 
     # timed region: HIP events bracket only the dominant kernel's launches
     ctx.enable_timing(DOMINANT)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     sf_ms, sf_cnt = ctx.timing(DOMINANT)
-    print(f"[bench] {args.steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
+    print(f"[bench] {name}: {steps} steps in {elapsed:.3f}s", file=sys.stderr, flush=True)
 
     # per-family kernel breakdown from one more step with every launch timed
     ctx.enable_timing(True)
@@ -175,30 +209,30 @@ def main():
     # real 2 x 2 product of (Re C, Im C) with (Re Z, Im Z) serves k and its
     # mirror in k_z: 8 flop per 2 k); on the VALU kernel, 8 flop per pair (a
     # complex rotation and a complex accumulate)
-    snaps_per_launch = B * args.steps / max(sf_cnt, 1)
+    snaps_per_launch = B * steps / max(sf_cnt, 1)
     matrix = ctx.info("sf_matrix") == 1.0
     flop_per_pair = 4.0 if matrix else 8.0
     flop_per_launch = flop_per_pair * nk * w.m * snaps_per_launch
     achieved = flop_per_launch / sf_avg if sf_avg > 0 else 0.0
     peak = PEAK_FP64_VALU      # FP64 MFMA and FP64 vector peaks are both 78.6 TFLOP/s
-    traffic = stored_traffic(args.workload, snaps_per_launch)
+    traffic = stored_traffic(name, snaps_per_launch)
     sf_bound = "mfma" if matrix else "alu"
 
-    value = B * args.steps / elapsed
+    value = B * steps / elapsed
     out = {
         "metric": f"charge solves/sec (N_elec={w.n})",
         "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "steps": steps,
+        "warmup": warmup,
+        "ms_per_step": elapsed / steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": args.workload, "n_elec": w.n, "m_elyt": w.m,
+        "config": {"workload": name, "n_elec": w.n, "m_elyt": w.m,
                    "snapshots_per_step": B, "n_k": nk, "alpha": w.alpha, "rcut": w.rcut,
                    "eta": w.eta, "mode": args.mode,
                    "step": "assemble A + invert + S + set v + b and q for every snapshot"},
@@ -214,13 +248,77 @@ def main():
         "plain_fp64_sample": f"{n_plain} snapshots, b + FP64 matvec solve one at a time, setup excluded",
         "kernel_ms_per_step": {f: v[0] for f, v in timing.items() if v[1]},
         "matvec_roofline": matvec,
+        "autotune": tune,
         "max_abs_sum_q": qsum,
     }
     ctx.close()
+    return out
 
-    if not args.no_cpu_baseline and w.n < 10000:
-        out["cpu_baseline"] = cpu_baseline(w)
-    print(json.dumps(out), flush=True)
+
+def run_mixed(args):
+    """Eight capacitors of uneven size (N from U{2000..20000}, snapped to whole
+    graphene cells; electrolyte 10 N water charges + 1 M ions), 128
+    configurations each: per step every A is assembled and inverted, b is
+    computed per instance, and all instances are solved by cpm_solve_grouped
+    (split-BF16, refined) in one persistent launch per S~ product."""
+    import numpy as np
+    import torch
+    from paper_2203_15461_amd import cpm
+    from paper_2203_15461_amd import inputs as I
+    dev = torch.device("cuda:0")
+    B = args.batch or 128
+    rng = np.random.default_rng(5)
+    targets = sorted(int(t) for t in rng.integers(2000, 20001, size=8))
+    ws = [I.scaled_graphite_capacitor(t) for t in targets]
+    s = torch.cuda.Stream()
+    ctxs, data = [], []
+    for k, w in enumerate(ws):
+        c = cpm.Context(cpm.Params.of(w), stream=s)
+        c.set_electrolyte(w.electrolyte_q)
+        xyz = synthetic_configurations(w, B, I.BASE_SEED + 1 + k, dev)
+        R = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device=dev).contiguous()
+        eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device=dev).contiguous()
+        data.append((xyz, R, eid, torch.empty((B, w.n), dtype=torch.float64, device=dev),
+                     torch.empty((B, w.n), dtype=torch.float64, device=dev)))
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    print(f"[bench] mixed8: n = {[w.n for w in ws]}, m = {[w.m for w in ws]}", file=sys.stderr,
+          flush=True)
+
+    def step():
+        with torch.cuda.stream(s):
+            for c, w, (xyz, R, eid, b, q) in zip(ctxs, ws, data):
+                c.build_elastance(R, eid, 2)
+                c.invert(1 | 4)
+                c.set_potential(w.v_electrode)
+                c.potential_vector(xyz, b)
+            cpm.solve_grouped(ctxs, [d[3] for d in data], 0x102, [d[4] for d in data])
+
+    for i in range(args.warmup):
+        step()
+        s.synchronize()
+        print(f"[bench] mixed8: warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    s.synchronize()
+    t_start = time.perf_counter()
+    for i in range(args.steps):
+        step()
+    s.synchronize()
+    elapsed = time.perf_counter() - t_start
+    qsum = max(float(d[4].sum(dim=1).abs().max().item()) for d in data)
+    nconf = 8 * B
+    for c in ctxs:
+        c.close()
+    return {"metric": "charge solves/sec (8 capacitors, N_elec 2000-20000)",
+            "value": nconf * args.steps / elapsed, "unit": "solves/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3+f64-refine",
+            "data": "synthetic",
+            "config": {"workload": "mixed8", "n_elec": [w.n for w in ws],
+                       "m_elyt": [w.m for w in ws], "snapshots_per_step_per_instance": B,
+                       "step": "per instance: assemble A + invert + S + set v + b; then one "
+                               "grouped split-BF16 solve of all instances"},
+            "max_abs_sum_q": qsum}
 
 
 def matvec_roofline(ctx, w, xyz, dev, reps=20):
