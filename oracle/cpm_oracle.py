@@ -327,6 +327,23 @@ def electrode_capacitance(S: np.ndarray, eid: np.ndarray, n_e: int) -> np.ndarra
     return G.T @ S @ G
 
 
+def constrained_charges(Ainv: np.ndarray, eid: np.ndarray, n_e: int, b: np.ndarray,
+                        Q_target) -> tuple:
+    """Constrained charge method (Sec. II.C, Eq. 7): with q = A^-1 (b + G v~),
+    G^T q = G^T A^-1 b + G^T A^-1 G v~ = q~_b + C~ v~; solve C~ v~ = Q - q~_b and
+    return (q, v~).  The targets must sum to zero (the slab correction and the
+    neutral electrolyte need a neutral system)."""
+    Q = np.asarray(Q_target, np.float64)
+    if abs(Q.sum()) > 1e-12 * max(np.abs(Q).sum(), 1e-300):
+        raise ValueError("electrode charge targets must sum to zero")
+    G = np.zeros((len(eid), n_e))
+    G[np.arange(len(eid)), np.asarray(eid)] = 1.0
+    y = Ainv @ np.asarray(b, np.float64)
+    Ct = G.T @ Ainv @ G
+    vt = np.linalg.solve(Ct, Q - G.T @ y)
+    return y + Ainv @ (G @ vt), vt
+
+
 def energy(A, b, v, q) -> float:
     """U_elec of Eq. 2 (eV)."""
     return 0.5 * q @ A @ q - b @ q - v @ q

@@ -291,3 +291,78 @@ def test_pins_catch_sign_of_b(monkeypatch, small):
     C0 = O.electrode_capacitance(s.cap.S, small.electrode_id, 2)[1, 1]
     pred = -C0 * (q @ r[:, 2]) / (O.EPS0 * small.Lx * small.Ly)
     assert abs(s.Q[1] / pred - 1) > 0.5
+
+
+# ---------------------------------------------------------------------------
+# constrained charge method (Sec. II.C, Eq. 7)
+# ---------------------------------------------------------------------------
+
+def _small_system():
+    w = I.small_capacitor("a")
+    p = O.params_for(w)
+    A = O.elastance(w.electrode_xyz, p)
+    cap = O.capacitance(A)
+    b = O.potential_vector(w.electrode_xyz, I.snapshot(w, 0), w.electrolyte_q, p)
+    return w, A, cap, b
+
+
+def test_ccm_reproduces_cpm_charges():
+    """CCM at the electrode charges a CPM solve produced returns the CPM charges,
+    and the recovered potentials differ from the applied ones by a common shift."""
+    w, A, cap, b = _small_system()
+    v_e = np.array([-0.7, 0.45])
+    q_cpm = O.charges(cap.S, b, O.applied_potential(w.electrode_id, v_e))
+    Q = O.electrode_totals(q_cpm, w.electrode_id, 2)
+    q, vt = O.constrained_charges(cap.Ainv, w.electrode_id, 2, b, Q)
+    assert np.abs(q - q_cpm).max() <= 1e-10 * np.abs(q_cpm).max()
+    shift = vt - v_e
+    assert abs(shift[0] - shift[1]) <= 1e-9 * np.abs(v_e).max()
+
+
+def test_ccm_meets_targets_and_minimises_energy():
+    """G^T q equals the targets, and q is the constrained energy minimum: any
+    perturbation that keeps every electrode total raises U of Eq. 2 (v = 0)."""
+    w, A, cap, b = _small_system()
+    Q = np.array([0.8, -0.8])
+    q, _ = O.constrained_charges(cap.Ainv, w.electrode_id, 2, b, Q)
+    assert np.abs(O.electrode_totals(q, w.electrode_id, 2) - Q).max() <= 1e-12
+    rng = np.random.default_rng(3)
+    U0 = O.energy(A, b, np.zeros(w.n), q)
+    for _ in range(5):
+        d = rng.normal(size=w.n)
+        for e in range(2):                      # remove each electrode's mean: G^T d = 0
+            m = w.electrode_id == e
+            d[m] -= d[m].mean()
+        d *= 1e-3
+        assert O.energy(A, b, np.zeros(w.n), q + d) > U0
+    # the stationarity condition: A q - b is constant on each electrode
+    g = A @ q - b
+    for e in range(2):
+        ge = g[w.electrode_id == e]
+        assert np.ptp(ge) <= 1e-9 * np.abs(g).max()
+
+
+def test_ccm_rejects_charged_targets():
+    w, A, cap, b = _small_system()
+    with pytest.raises(ValueError):
+        O.constrained_charges(cap.Ainv, w.electrode_id, 2, b, [0.5, 0.4])
+
+
+def test_ccm_planted_mistakes_are_caught():
+    """Two plausible slips in the CCM algebra fail the pins above: dropping the
+    electrolyte term q~_b from the solve for v~ misses the targets, and a flipped
+    sign of b meets them but is no longer the constrained energy minimum."""
+    w, A, cap, b = _small_system()
+    Q = np.array([0.8, -0.8])
+    G = np.zeros((w.n, 2)); G[np.arange(w.n), w.electrode_id] = 1.0
+    Ct = G.T @ cap.Ainv @ G
+    # (a) v~ = C~^-1 Q
+    y = cap.Ainv @ b
+    q_a = y + cap.Ainv @ (G @ np.linalg.solve(Ct, Q))
+    assert np.abs(O.electrode_totals(q_a, w.electrode_id, 2) - Q).max() > 1e-6
+    # (b) y = -A^-1 b
+    y = -cap.Ainv @ b
+    q_b = y + cap.Ainv @ (G @ np.linalg.solve(Ct, Q - G.T @ y))
+    assert np.abs(O.electrode_totals(q_b, w.electrode_id, 2) - Q).max() <= 1e-12
+    g = A @ q_b - b
+    assert max(np.ptp(g[w.electrode_id == e]) for e in range(2)) > 1e-6
