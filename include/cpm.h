@@ -63,7 +63,10 @@ enum {
   CPM_SOLVE_F64 = 0,
   CPM_SOLVE_F32 = 1,
   CPM_SOLVE_BF16X2 = 2,
-  CPM_SOLVE_REFINE = 0x100
+  CPM_SOLVE_REFINE = 0x100,
+  CPM_SOLVE_CCM = 0x200       /* constrained electrode charges (Eq. 7) instead of
+                                 the applied potential; FP64 only, needs
+                                 cpm_set_charge                                    */
 };
 
 /* Keys for cpm_get_info. */
@@ -160,6 +163,15 @@ cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
  * chosen copy of S must have been kept by cpm_invert, else CPM_EINVAL. */
 cpm_status cpm_solve_charges(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32,
                              unsigned mode, double* d_q, double* d_Qe);
+
+/* Constrained charge method (Sec. II.C, Eq. 7): set the total charge of
+ * each electrode, h_Q[n_e] (e, host memory; must sum to zero within 1e-12
+ * relative, else CPM_EINVAL; n_e <= 16).  Computes U = A^-1 G and the
+ * inverse of the electrode capacitance matrix C~ = G^T A^-1 G.  Later
+ * cpm_solve_charges calls with CPM_SOLVE_F64 | CPM_SOLVE_CCM return
+ * q = A^-1 (b + G v~) with v~ = C~^-1 (Q - G^T A^-1 b), so G^T q = Q.  Needs
+ * cpm_invert (and again after every cpm_invert).  Synchronous. */
+cpm_status cpm_set_charge(cpm_ctx* ctx, const double* h_Q);
 
 /* Autotune the split-BF16 batched product Q~ = B S~ (the matrix-core solve
  * of Eqs. 3 and 6) for batches of `batch` vectors (rows padded to 64): times

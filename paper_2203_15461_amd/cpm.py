@@ -21,14 +21,14 @@ STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_ESTATE", 3: "CPM_ENOMEM", 
                 5: "CPM_ENOTPD", 6: "CPM_EUNSUPPORTED"}
 # store flags, solve modes, info keys
 STORE_F64, STORE_F32, STORE_BF16X2 = 1, 2, 4
-SOLVE_F64, SOLVE_F32, SOLVE_BF16X2, SOLVE_REFINE = 0, 1, 2, 0x100
+SOLVE_F64, SOLVE_F32, SOLVE_BF16X2, SOLVE_REFINE, SOLVE_CCM = 0, 1, 2, 0x100, 0x200
 INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, npad=9, nruns=10,
             nlayers=11, sf_matrix=12, tune_bm=13, tune_ks=14, tune_grid=15, tune_us=16, group=17)
 
 EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
            "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",
            "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_autotune",
-           "cpm_solve_grouped", "cpm_get_info",
+           "cpm_solve_grouped", "cpm_set_charge", "cpm_get_info",
            "cpm_enable_timing", "cpm_get_timing",
            "cpm_synchronize", "cpm_last_error", "cpm_destroy")
 
@@ -72,6 +72,7 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_capture_step": ([vp, i, vp, vp, i, u, vp, vp], i),
         "cpm_replay_step": ([vp], i),
         "cpm_autotune": ([vp, i, i], i),
+        "cpm_set_charge": ([vp, ctypes.POINTER(d)], i),
         "cpm_solve_grouped": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(vp), i, u,
                                ctypes.POINTER(vp), ctypes.POINTER(vp)], i),
         "cpm_copy_vector": ([vp, i, vp], i),
@@ -219,6 +220,15 @@ class Context:
             raise ValueError(f"need {int(self.info('ne'))} electrode potentials, got {len(va)}")
         self._check(self._lib.cpm_set_potential(self._h, va.ctypes.data_as(ctypes.c_void_p)),
                     "cpm_set_potential")
+
+    def set_charge(self, Q_electrode):
+        """Constrained charge method: total charge (e) per electrode, summing to zero."""
+        import numpy as np
+        Qa = np.ascontiguousarray(Q_electrode, dtype=np.float64).ravel()
+        if len(Qa) != int(self.info("ne")):
+            raise ValueError(f"need {int(self.info('ne'))} electrode charges, got {len(Qa)}")
+        self._check(self._lib.cpm_set_charge(self._h, Qa.ctypes.data_as(ctypes.POINTER(ctypes.c_double))),
+                    "cpm_set_charge")
 
     def potential_vector(self, xyz, out):
         """xyz: (batch, m, 3) float64 CUDA tensor; out: (batch, n) float64 or float32."""

@@ -510,7 +510,7 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   const int nlayers = (int)zs.size() <= MAX_LAYERS ? (int)zs.size() : 0;
   if (c->have_A && (nlayers != c->nlayers))
     return fail(c, CPM_EINVAL, "rebuild changes the electrode plane structure; create a new context");
-  c->have_A = c->have_inv = c->have_v = false;
+  c->have_A = c->have_inv = c->have_v = c->have_q = false;
   c->nlayers = nlayers;
   c->n = n;
   c->n_e = n_e;
@@ -707,6 +707,7 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   HIP_TRY(c, hipStreamSynchronize(st));
   c->store = store_flags | CPM_STORE_F64;
   c->have_inv = true;
+  c->have_q = false;                     // charge targets refer to the previous inverse
   return CPM_OK;
 }
 
@@ -833,7 +834,12 @@ cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
   if (batch <= 0 || !d_b || !d_q) return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL b, q");
   if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
   const unsigned prec = mode & 0xffu;
-  if ((mode & ~0x1ffu) != 0 || prec > 2) return fail(c, CPM_EINVAL, "unknown solve mode 0x%x", mode);
+  if ((mode & ~0x3ffu) != 0 || prec > 2) return fail(c, CPM_EINVAL, "unknown solve mode 0x%x", mode);
+  if (mode & CPM_SOLVE_CCM) {
+    if (prec != 0 || (mode & CPM_SOLVE_REFINE))
+      return fail(c, CPM_EUNSUPPORTED, "constrained charges run in FP64 without refinement");
+    if (!c->have_q) return fail(c, CPM_ESTATE, "CPM_SOLVE_CCM before cpm_set_charge");
+  }
   if (prec == 1 && !(c->store & CPM_STORE_F32)) return fail(c, CPM_EINVAL, "FP32 copy of S not kept");
   if (prec == 2 && !(c->store & CPM_STORE_BF16X2))
     return fail(c, CPM_EINVAL, "split-BF16 copy of S not kept");
@@ -864,6 +870,26 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
   const void* Sm = (prec == 1) ? (const void*)b.S32 : (const void*)b.S;
   const int which = (prec == 1) ? 1 : 0;
   const char* mv_name = (prec == 1) ? "matvec_f32" : "matvec_f64";
+
+  if (mode & CPM_SOLVE_CCM) {
+    // constrained charges (Eq. 7): y = A^-1 b in FP64, then the per-electrode
+    // correction q = y + U C~^-1 (Q - G^T y)
+    if (!gemm) {
+      Timed t(c, "matvec_f64");
+      launch_matvec(st, 0, n, npad, b.Ainv, batch, d_b, b_is_f32, n, nullptr, nullptr, 0, 0.0, b.qt,
+                    npad, 0);
+    } else {
+      { Timed t(c, "pad_rows");
+        launch_pad_rows(st, n, npad, batch, rows, d_b, b_is_f32, nullptr, b.bpad); }
+      Timed t(c, "gemm_f64");
+      launch_gemm_f64(st, false, false, rows, npad, npad, 1.0, b.bpad, npad, b.Ainv, npad, 0.0, b.qt,
+                      npad, 0, 0);
+    }
+    { Timed t(c, "finalize");
+      launch_ccm_finalize(st, n, batch, b.qt, npad, b.ccmU, b.ccmC, b.ccmC + c->n_e * c->n_e, b.eid,
+                          c->n_e, d_q, n, d_Qe); }
+    return launched(c, "solve (constrained charges)");
+  }
 
   // S~ x for a batch stored row-wise (stride npad) -> y (stride npad) (+ add)
   auto apply_S = [&](const double* x, double* y, bool accumulate) {
@@ -986,6 +1012,7 @@ cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_
   c->graph_gen = c->alloc_gen;
   const unsigned prec = mode & 0xffu;
   c->graph_store = prec == 1 ? CPM_STORE_F32 : prec == 2 ? CPM_STORE_BF16X2 : CPM_STORE_F64;
+  c->graph_ccm = (mode & CPM_SOLVE_CCM) != 0;
   return CPM_OK;
 }
 
@@ -995,9 +1022,61 @@ cpm_status cpm_replay_step(cpm_ctx* c) {
   // the graph holds raw device addresses: any reallocation since capture
   // (a larger eager batch, a rebuild) or a dropped copy of S invalidates it
   if (c->alloc_gen != c->graph_gen || !c->have_inv || !c->have_v ||
-      (c->store & c->graph_store) != c->graph_store)
+      (c->store & c->graph_store) != c->graph_store || (c->graph_ccm && !c->have_q))
     return fail(c, CPM_ESTATE, "context buffers changed since cpm_capture_step; capture again");
   HIP_TRY(c, hipGraphLaunch(c->graph_exec, c->stream));
+  return CPM_OK;
+}
+
+cpm_status cpm_set_charge(cpm_ctx* c, const double* h_Q) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_set_charge before cpm_invert");
+  if (!h_Q) return fail(c, CPM_EINVAL, "h_Q is NULL");
+  const int ne = c->n_e, n = c->n;
+  if (ne > CCM_MAXE) return fail(c, CPM_EUNSUPPORTED, "at most %d electrodes for constrained charges", CCM_MAXE);
+  double sum = 0.0, asum = 0.0;
+  for (int a = 0; a < ne; ++a) {
+    if (!std::isfinite(h_Q[a])) return fail(c, CPM_EINVAL, "charge target %d not finite", a);
+    sum += h_Q[a];
+    asum += std::fabs(h_Q[a]);
+  }
+  if (std::fabs(sum) > 1e-12 * std::max(asum, 1e-300))
+    return fail(c, CPM_EINVAL, "electrode charge targets must sum to zero (sum = %g)", sum);
+  Buffers& b = c->b;
+  TRY(dalloc(c, &b.ccmU, (size_t)n * ne));
+  TRY(dalloc(c, &b.ccmC, (size_t)ne * ne + ne));
+  launch_ccm_response(c->stream, n, c->npad, b.Ainv, b.eid, ne, b.ccmU);
+  TRY(launched(c, "ccm response"));
+  std::vector<double> U((size_t)n * ne);
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpy(U.data(), b.ccmU, U.size() * sizeof(double), hipMemcpyDeviceToHost));
+  // C~ = G^T A^-1 G, then its inverse by Gauss-Jordan with partial pivoting
+  std::vector<double> M((size_t)ne * 2 * ne, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int a = 0; a < ne; ++a) M[(size_t)c->h_eid[i] * 2 * ne + a] += U[(size_t)i * ne + a];
+  for (int a = 0; a < ne; ++a) M[(size_t)a * 2 * ne + ne + a] = 1.0;
+  for (int col = 0; col < ne; ++col) {
+    int piv = col;
+    for (int r = col + 1; r < ne; ++r)
+      if (std::fabs(M[(size_t)r * 2 * ne + col]) > std::fabs(M[(size_t)piv * 2 * ne + col])) piv = r;
+    if (!(std::fabs(M[(size_t)piv * 2 * ne + col]) > 0.0))
+      return fail(c, CPM_ENOTPD, "electrode capacitance matrix is singular");
+    if (piv != col)
+      for (int k = 0; k < 2 * ne; ++k) std::swap(M[(size_t)col * 2 * ne + k], M[(size_t)piv * 2 * ne + k]);
+    const double d = M[(size_t)col * 2 * ne + col];
+    for (int k = 0; k < 2 * ne; ++k) M[(size_t)col * 2 * ne + k] /= d;
+    for (int r = 0; r < ne; ++r) {
+      if (r == col) continue;
+      const double f = M[(size_t)r * 2 * ne + col];
+      for (int k = 0; k < 2 * ne; ++k) M[(size_t)r * 2 * ne + k] -= f * M[(size_t)col * 2 * ne + k];
+    }
+  }
+  std::vector<double> h((size_t)ne * ne + ne);
+  for (int a = 0; a < ne; ++a)
+    for (int k = 0; k < ne; ++k) h[(size_t)a * ne + k] = M[(size_t)a * 2 * ne + ne + k];
+  for (int a = 0; a < ne; ++a) h[(size_t)ne * ne + a] = h_Q[a];
+  HIP_TRY(c, hipMemcpy(b.ccmC, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  c->have_q = true;
   return CPM_OK;
 }
 
@@ -1220,7 +1299,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.mz); dfree(b.qt);
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
-  dfree(b.kpart);
+  dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

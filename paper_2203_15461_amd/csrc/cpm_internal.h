@@ -33,6 +33,7 @@ struct KCol {
   int pad;
 };
 
+constexpr int CCM_MAXE = 16;       // electrodes supported by the constrained charge method
 constexpr int SFM_NB = 4;          // 16-wide n blocks per matrix-core structure-factor work item
 
 // charges per chunk of the matrix-core structure factors (a multiple of 16)
@@ -98,6 +99,8 @@ struct Buffers {
   double* qpad = nullptr;          // padded GEMM output (bpad_rows x npad)
   double* means = nullptr;         // per-vector uniform part removed before S products
   double* kpart = nullptr;         // split-K partial slices of the batched split-BF16 GEMM
+  double* ccmU = nullptr;          // constrained charges: U = A^-1 G (n x n_e)
+  double* ccmC = nullptr;          // C~^-1 (n_e x n_e) followed by the targets Q (n_e)
   size_t kpart_len = 0;
   int bpad_rows = 0;
   double* scal = nullptr;          // small scalars (s and friends)
@@ -109,7 +112,7 @@ struct cpm_ctx {
   cpm_params p{};
   hipStream_t stream = nullptr;
   std::string err;
-  bool have_elyt = false, have_A = false, have_inv = false, have_v = false;
+  bool have_elyt = false, have_A = false, have_inv = false, have_v = false, have_q = false;
   int n = 0, npad = 0, n_e = 0, m = 0;
   double Lz = 0, V = 0, kc = 0, ke = 0;
   int nk = 0, nruns = 0;
@@ -155,6 +158,7 @@ struct cpm_ctx {
   hipGraphExec_t graph_exec = nullptr;
   unsigned long long graph_gen = 0;    // alloc_gen when the graph was captured
   unsigned graph_store = 0;            // copies of S the captured solve reads
+  bool graph_ccm = false;              // the captured solve needs the charge targets
   // kernel timing (cpm_enable_timing)
   bool timing = false;
   std::vector<std::string> timing_only;   // empty: every family
@@ -218,6 +222,11 @@ void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldq
                      const double* u, const double* s_dev, const int* eid, int n_e, double* q,
                      int ldq, double* Qe);
 void launch_fill_zero(hipStream_t st, size_t count, float* p);
+void launch_ccm_response(hipStream_t st, int n, int npad, const double* Ainv, const int* eid,
+                         int n_e, double* U);
+void launch_ccm_finalize(hipStream_t st, int n, int batch, const double* yt, int ldy,
+                         const double* U, const double* Cinv, const double* Qt, const int* eid,
+                         int n_e, double* q, int ldq, double* Qe);
 void launch_pad_rows(hipStream_t st, int n, int npad, int batch, int rows, const void* src,
                      int src_is_f32, const double* shift, double* dst);
 // C (M x N, FP64) (+)= Bm (M x K, FP64, split to BF16 hi/lo on load) * S, with

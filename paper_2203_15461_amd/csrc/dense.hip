@@ -483,6 +483,84 @@ void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldq
                      n_e, q, ldq, Qe);
 }
 
+// ---------------------------------------------------------------------------
+// Constrained charge method (Eq. 7).  U = A^-1 G (n x n_e, row-major): row
+// sums of A^-1 over each electrode's columns.
+// ---------------------------------------------------------------------------
+__global__ void k_ccm_response(int n, int npad, const double* __restrict__ Ainv,
+                               const int* __restrict__ eid, int n_e, double* __restrict__ U) {
+  const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (i >= n) return;
+  const double* row = Ainv + (size_t)i * npad;
+  for (int a = 0; a < n_e; ++a) {
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64)
+      if (eid[j] == a) s += row[j];
+    s = wave_sum(s);
+    if (lane == 0) U[(size_t)i * n_e + a] = s;
+  }
+}
+
+void launch_ccm_response(hipStream_t st, int n, int npad, const double* Ainv, const int* eid,
+                         int n_e, double* U) {
+  hipLaunchKernelGGL(k_ccm_response, dim3((n + 3) / 4), dim3(256), 0, st, n, npad, Ainv, eid, n_e, U);
+}
+
+// Per configuration b (one workgroup): y = A^-1 b is given (row b of yt);
+// q~_b = G^T y, v~ = C~^-1 (Q - q~_b), q = y + U v~, Qe = G^T q.  Sums per
+// electrode in a fixed order; n_e <= CCM_MAXE.
+__global__ void __launch_bounds__(256) k_ccm_finalize(int n, const double* __restrict__ yt, int ldy,
+                                                      const double* __restrict__ U,
+                                                      const double* __restrict__ Cinv,
+                                                      const double* __restrict__ Qt,
+                                                      const int* __restrict__ eid, int n_e,
+                                                      double* __restrict__ q, int ldq,
+                                                      double* __restrict__ Qe) {
+  __shared__ double sh[4];
+  __shared__ double s_v[CCM_MAXE];
+  __shared__ double s_g[CCM_MAXE];
+  const int b = blockIdx.x;
+  const double* y = yt + (size_t)b * ldy;
+  for (int a = 0; a < n_e; ++a) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += 256)
+      if (eid[i] == a) t += y[i];
+    t = block_sum256(t, sh);
+    if (threadIdx.x == 0) s_g[a] = t;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int a = 0; a < n_e; ++a) {
+      double v = 0.0;
+      for (int c = 0; c < n_e; ++c) v += Cinv[a * n_e + c] * (Qt[c] - s_g[c]);
+      s_v[a] = v;
+    }
+  __syncthreads();
+  double* qo = q + (size_t)b * ldq;
+  for (int i = threadIdx.x; i < n; i += 256) {
+    double v = y[i];
+    for (int a = 0; a < n_e; ++a) v += U[(size_t)i * n_e + a] * s_v[a];
+    qo[i] = v;
+  }
+  if (Qe) {
+    __syncthreads();
+    for (int a = 0; a < n_e; ++a) {
+      double t = 0.0;
+      for (int i = threadIdx.x; i < n; i += 256)
+        if (eid[i] == a) t += qo[i];
+      t = block_sum256(t, sh);
+      if (threadIdx.x == 0) Qe[(size_t)b * n_e + a] = t;
+    }
+  }
+}
+
+void launch_ccm_finalize(hipStream_t st, int n, int batch, const double* yt, int ldy,
+                         const double* U, const double* Cinv, const double* Qt, const int* eid,
+                         int n_e, double* q, int ldq, double* Qe) {
+  hipLaunchKernelGGL(k_ccm_finalize, dim3(batch), dim3(256), 0, st, n, yt, ldy, U, Cinv, Qt, eid,
+                     n_e, q, ldq, Qe);
+}
+
 // p[0 .. count) = 0 (a kernel, so it can sit inside a captured graph)
 __global__ void k_fill_zero(size_t count, float* p) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -65,6 +65,7 @@ def test_null_arguments():
     assert L.cpm_capture_step(None, 1, None, None, 0, 0, None, None) == cpm.EINVAL
     assert L.cpm_replay_step(None) == cpm.EINVAL
     assert L.cpm_autotune(None, 64, 1) == cpm.EINVAL
+    assert L.cpm_set_charge(None, None) == cpm.EINVAL
     assert L.cpm_solve_grouped(None, 1, None, None, 0, 0x102, None, None) == cpm.EINVAL
     assert L.cpm_last_error(None) == b"no context"
     L.cpm_destroy(None)
