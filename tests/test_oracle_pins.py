@@ -118,6 +118,45 @@ def test_alpha_independence(small):
         assert rel(out[a].q, ref.q) < 1e-8
 
 
+@pytest.mark.parametrize("geometry,Lz", [("tinfoil", 45.0), ("wire", 45.0)])
+def test_alpha_independence_other_geometries(small, geometry, Lz):
+    """The same invariance in a 3D-periodic tin-foil cell (the finite-field
+    setting, Sec. II.F) and with the wire correction (Eq. 11): the dipole term
+    differs, the Ewald split must still drop out of A, b and q."""
+    out = {}
+    for a in (0.25, 0.35):
+        p = O.params_for(small, alpha=a, rcut=5.0 / a, kspace_eps=1e-13, Lz=Lz, geometry=geometry)
+        out[a] = O.solve(small.electrode_xyz, small.electrode_id, small.electrolyte_xyz,
+                         small.electrolyte_q, p, small.v_electrode)
+    assert rel(out[0.25].A, out[0.35].A) < 1e-8
+    assert rel(out[0.25].b, out[0.35].b) < 1e-8
+    assert rel(out[0.25].q, out[0.35].q) < 1e-8
+
+
+def test_finite_field_is_cpm_with_field_potential(small):
+    """Finite field (Eqs. 13-14): q = S (b - dv0 zeta) is the CPM with the
+    applied potential replaced by -dv0 zeta, so it minimises
+    1/2 q^T A q - b^T q + dv0 zeta^T q over neutral q; and a common offset of
+    zeta changes nothing (S e = 0)."""
+    p = O.params_for(small, Lz=45.0, geometry="tinfoil")
+    A = O.elastance(small.electrode_xyz, p)
+    cap = O.capacitance(A)
+    b = O.potential_vector(small.electrode_xyz, small.electrolyte_xyz, small.electrolyte_q, p)
+    zeta = I.finite_field_zeta(small.electrode_xyz[:, 2], small.electrode_id, 45.0)
+    dv0 = 1.3
+    q = O.charges(cap.S, b, -dv0 * zeta)
+    assert abs(q.sum()) < 1e-12
+    q2 = O.charges(cap.S, b, -dv0 * (zeta + 0.37))
+    assert rel(q2, q) < 1e-12
+    # stationarity on the neutral subspace: A q - b + dv0 zeta is uniform
+    g = A @ q - b + dv0 * zeta
+    assert np.ptp(g) < 1e-9 * np.abs(A @ q).max()
+    # without electrolyte the field alone charges the electrodes: the bottom one
+    # (zeta offset by +1, so the lower applied potential) goes negative
+    Q = O.electrode_totals(O.charges(cap.S, 0 * b, -dv0 * zeta), small.electrode_id, 2)
+    assert Q[0] < 0 < Q[1] and abs(Q.sum()) < 1e-12
+
+
 # --- slab dipole term ------------------------------------------------------------
 
 def _plates(gap):
