@@ -51,8 +51,19 @@ typedef enum {
   CPM_EUNSUPPORTED = 6   /* valid request this build does not provide          */
 } cpm_status;
 
-/* Boundary geometry.  Only the slab (x, y periodic, EW3DC in z) runs here. */
-typedef enum { CPM_GEOM_SLAB_EW3DC = 0 } cpm_geom;
+/* Boundary geometry (Sec. II.E).  All three use the Ewald sum of the
+ * Lx x Ly x Lz cell, Lz = slab_factor * h, with every periodic image within
+ * rcut in real space, plus a dipole term:
+ *   CPM_GEOM_SLAB_EW3DC: x, y periodic, vacuum in z (Eq. 10; (slab_factor -
+ *     1) * h > rcut required); A += k_e (4 pi / V) z z^T, b -= k_e (4 pi / V) z M_z.
+ *   CPM_GEOM_WIRE: periodic in z only, the x, y box extended (Eq. 11);
+ *     A += k_e (2 pi / V)(x x^T + y y^T), b -= k_e (2 pi / V)(x M_x + y M_y).
+ *   CPM_GEOM_3D: periodic in x, y and z with no dipole term (tin foil), the
+ *     setting of the finite-field method (Sec. II.F; pass slab_factor 1 and
+ *     h = the cell height, and the field potential through
+ *     cpm_set_potential_atoms).
+ * Dipole terms use the coordinates as given (not wrapped). */
+typedef enum { CPM_GEOM_SLAB_EW3DC = 0, CPM_GEOM_WIRE = 1, CPM_GEOM_3D = 2 } cpm_geom;
 
 /* Which copies of S cpm_invert keeps (bit set).  FP64 is always kept. */
 enum { CPM_STORE_F64 = 1, CPM_STORE_F32 = 2, CPM_STORE_BF16X2 = 4 };
@@ -143,6 +154,11 @@ cpm_status cpm_invert(cpm_ctx* ctx, unsigned store_flags);
  * Eq. 5).  Precomputes d = S v (Eq. 6 with the S G response cached), so a
  * solve only adds it.  Host pointer, copied. */
 cpm_status cpm_set_potential(cpm_ctx* ctx, const double* h_v_electrode);
+
+/* The same with one potential per electrode atom, h_v[n] (V, host memory):
+ * d = S v for any v, e.g. the finite-field potential v = -dv0 zeta of
+ * Eqs. 13-14 (zeta = normalised z positions). */
+cpm_status cpm_set_potential_atoms(cpm_ctx* ctx, const double* h_v);
 
 /* b for `batch` electrolyte configurations (Sec. II.A: the per-step cost).
  * d_xyz: batch x m x 3 FP64 positions (row-major, snapshot-major).

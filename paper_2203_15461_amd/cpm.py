@@ -28,7 +28,7 @@ INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, n
 EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
            "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",
            "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_autotune",
-           "cpm_solve_grouped", "cpm_set_charge", "cpm_get_info",
+           "cpm_solve_grouped", "cpm_set_charge", "cpm_set_potential_atoms", "cpm_get_info",
            "cpm_enable_timing", "cpm_get_timing",
            "cpm_synchronize", "cpm_last_error", "cpm_destroy")
 
@@ -73,6 +73,7 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_replay_step": ([vp], i),
         "cpm_autotune": ([vp, i, i], i),
         "cpm_set_charge": ([vp, ctypes.POINTER(d)], i),
+        "cpm_set_potential_atoms": ([vp, ctypes.POINTER(d)], i),
         "cpm_solve_grouped": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(vp), i, u,
                                ctypes.POINTER(vp), ctypes.POINTER(vp)], i),
         "cpm_copy_vector": ([vp, i, vp], i),
@@ -220,6 +221,15 @@ class Context:
             raise ValueError(f"need {int(self.info('ne'))} electrode potentials, got {len(va)}")
         self._check(self._lib.cpm_set_potential(self._h, va.ctypes.data_as(ctypes.c_void_p)),
                     "cpm_set_potential")
+
+    def set_potential_atoms(self, v_atoms):
+        """One potential (V) per electrode atom (e.g. the finite-field -dv0 zeta)."""
+        import numpy as np
+        va = np.ascontiguousarray(v_atoms, dtype=np.float64).ravel()
+        if len(va) != int(self.info("n")):
+            raise ValueError(f"need {int(self.info('n'))} atom potentials, got {len(va)}")
+        self._check(self._lib.cpm_set_potential_atoms(
+            self._h, va.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "cpm_set_potential_atoms")
 
     def set_charge(self, Q_electrode):
         """Constrained charge method: total charge (e) per electrode, summing to zero."""

@@ -23,11 +23,11 @@ __global__ void k_prep_electrodes(int n, const double* __restrict__ xyz, double 
                                   double* fy, double* fz) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double x = xyz[3 * i + 0], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
-  x -= Lx * floor(x / Lx);
-  y -= Ly * floor(y / Ly);
+  // raw coordinates (the dipole terms need them; pair distances use the
+  // nearest image), fractional x and y wrapped into [0, 1)
+  const double x = xyz[3 * i + 0], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
   ex[i] = x; ey[i] = y; ez[i] = z;
-  fx[i] = x / Lx; fy[i] = y / Ly; fz[i] = z / Lz;
+  fx[i] = x / Lx - floor(x / Lx); fy[i] = y / Ly - floor(y / Ly); fz[i] = z / Lz;
 }
 
 void launch_prep_electrodes(hipStream_t st, int n, const double* xyz, double Lx, double Ly,
@@ -36,14 +36,14 @@ void launch_prep_electrodes(hipStream_t st, int n, const double* xyz, double Lx,
                      Lz, b.ex, b.ey, b.ez, b.efx, b.efy, b.efz);
 }
 
-// Real-space, self, background and slab parts of A, lower triangle only
+// Real-space, self, background and dipole parts of A, lower triangle only
 // (the upper triangle is mirrored after the k-space product).  Padding rows
 // and columns (index >= n) get the identity.
 __global__ void __launch_bounds__(256) k_real_space_A(
     int n, int npad, const double* __restrict__ ex, const double* __restrict__ ey,
-    const double* __restrict__ ez, double Lx, double Ly, double rc, double alpha, double eta_ee,
-    double diag_self, double background, double slab_coef, double ke,
-    const double* __restrict__ diag_extra, double* __restrict__ A) {
+    const double* __restrict__ ez, double Lx, double Ly, double Lz, double rc, double alpha,
+    double eta_ee, double diag_self, double background, double cx, double cy, double cz,
+    double ke, const double* __restrict__ diag_extra, double* __restrict__ A) {
   if (blockIdx.x > blockIdx.y) return;               // strictly upper tile
   const int j = blockIdx.x * 16 + threadIdx.x;
   const int i = blockIdx.y * 16 + threadIdx.y;
@@ -52,30 +52,35 @@ __global__ void __launch_bounds__(256) k_real_space_A(
   if (i >= n || j >= n) {
     val = (i == j) ? 1.0 : 0.0;
   } else {
-    const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
+    const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, invLz = 1.0 / Lz, rc2 = rc * rc;
     const double r2_gauss = eta_ee > alpha ? 45.0 / (eta_ee * eta_ee - alpha * alpha) : 1e300;
     double dx = ex[i] - ex[j], dy = ey[i] - ey[j], dz = ez[i] - ez[j];
     dx -= Lx * rint(dx * invLx);
     dy -= Ly * rint(dy * invLy);
+    dz -= Lz * rint(dz * invLz);
     double sum = 0.0;
-    if (fabs(dz) < rc) {
+    if (fabs(dz) < rc) {               // dz is the nearest image: no image is closer
       const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
       const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
-      for (int a = alo; a <= ahi; ++a) {
-        const double X = dx + a * Lx;
-        for (int bb = blo; bb <= bhi; ++bb) {
-          const double Y = dy + bb * Ly;
-          const double r2 = X * X + Y * Y + dz * dz;
-          if (r2 > 0.0 && r2 < rc2 * (1.0 + 1e-12)) {
-            const double r = sqrt(r2);
-            // erfc(eta_ee r) is below FP64 rounding of the difference once
-            // (eta_ee^2 - alpha^2) r^2 > 45 (erfc(x) <= e^{-x^2})
-            if (r < rc) sum += (r2 > r2_gauss ? erfc(alpha * r) : erfc(alpha * r) - erfc(eta_ee * r)) / r;
+      const int clo = (int)ceil((-rc - dz) * invLz) - 1, chi = (int)floor((rc - dz) * invLz) + 1;
+      for (int cc = clo; cc <= chi; ++cc) {
+        const double Z = dz + cc * Lz;
+        for (int a = alo; a <= ahi; ++a) {
+          const double X = dx + a * Lx;
+          for (int bb = blo; bb <= bhi; ++bb) {
+            const double Y = dy + bb * Ly;
+            const double r2 = X * X + Y * Y + Z * Z;
+            if (r2 > 0.0 && r2 < rc2 * (1.0 + 1e-12)) {
+              const double r = sqrt(r2);
+              // erfc(eta_ee r) is below FP64 rounding of the difference once
+              // (eta_ee^2 - alpha^2) r^2 > 45 (erfc(x) <= e^{-x^2})
+              if (r < rc) sum += (r2 > r2_gauss ? erfc(alpha * r) : erfc(alpha * r) - erfc(eta_ee * r)) / r;
+            }
           }
         }
       }
     }
-    val = sum + background + slab_coef * ez[i] * ez[j];
+    val = sum + background + cx * ex[i] * ex[j] + cy * ey[i] * ey[j] + cz * ez[i] * ez[j];
     if (i == j) val += diag_self;
     val *= ke;
     if (i == j && diag_extra) val += diag_extra[i];
@@ -84,12 +89,14 @@ __global__ void __launch_bounds__(256) k_real_space_A(
 }
 
 void launch_real_space_A(hipStream_t st, int n, int npad, const Buffers& b, double Lx, double Ly,
-                         double rc, double alpha, double eta_ee, double diag_self,
-                         double background, double slab_coef, double ke, const double* diag_extra,
-                         double* A) {
-  dim3 grid(npad / 16, npad / 16), block(16, 16);
-  hipLaunchKernelGGL(k_real_space_A, grid, block, 0, st, n, npad, b.ex, b.ey, b.ez, Lx, Ly, rc,
-                     alpha, eta_ee, diag_self, background, slab_coef, ke, diag_extra, A);
+                         double Lz, double rc, double alpha, double eta_ee, double diag_self,
+                         double background, const double* cdip, double ke,
+                         const double* diag_extra, double* A) {
+  const int nt = (npad + 15) / 16;
+  dim3 grid(nt, nt), block(16, 16);
+  hipLaunchKernelGGL(k_real_space_A, grid, block, 0, st, n, npad, b.ex, b.ey, b.ez, Lx, Ly, Lz, rc,
+                     alpha, eta_ee, diag_self, background, cdip[0], cdip[1], cdip[2], ke,
+                     diag_extra, A);
 }
 
 // Phase table for k indices [k0, k0 + kc) of the flat k list:

@@ -33,9 +33,7 @@ namespace cpm {
 // A run starts at tx[nx] ty[ny] tz[nz0] (two complex products) and advances
 // along k_z by tz[1] (FP64 rotation).  Two charges are walked together so
 // two independent rotation chains are in flight.  T is the accumulation type.
-// part[(chunk * nk + k) * 2 + {0,1}] = partial S(k) over the chunk's charges;
-// the workgroups of the first run block also leave the chunk's partial dipole
-// sum_j q_j z_j in mz_part[chunk].
+// part[(chunk * nk + k) * 2 + {0,1}] = partial S(k) over the chunk's charges.
 // ---------------------------------------------------------------------------
 constexpr int SF_TJ = 16;
 constexpr int SF_SEG = 8;
@@ -50,12 +48,10 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
                                                           const double* __restrict__ xyz,
                                                           const double* __restrict__ q, double Lx,
                                                           double Ly, double Lz, int nxm, int nym,
-                                                          int nzm, double* __restrict__ part,
-                                                          double* __restrict__ mz_part) {
+                                                          int nzm, double* __restrict__ part) {
   extern __shared__ double2 tab[];                  // [tj][W]
   __shared__ double s_f[3][SF_TJ], s_q[SF_TJ];
   __shared__ double2 s_e1[3][SF_TJ];
-  __shared__ double s_mz[4];
   const int W = nxm + nym + nzm + 3, oy = nxm + 1, oz = nxm + nym + 2;
   const int nsx = (nxm + SF_SEG) / SF_SEG, nsy = (nym + SF_SEG) / SF_SEG,
             nsz = (nzm + SF_SEG) / SF_SEG, nseg = nsx + nsy + nsz;
@@ -70,7 +66,6 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
   T are[RUN], aim[RUN];
 #pragma unroll
   for (int r = 0; r < RUN; ++r) { are[r] = 0; aim[r] = 0; }
-  double mz = 0.0;
 
   for (int jt = j0; jt < j1; jt += tj) {
     const int nt = min(tj, j1 - jt);
@@ -83,7 +78,6 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
       s_f[1][t] = fy - floor(fy);
       s_f[2][t] = z / Lz;
       s_q[t] = q[j];
-      if (blockIdx.x == 0) mz += q[j] * z;
     }
     __syncthreads();
     if ((int)threadIdx.x < 3 * nt) {
@@ -155,13 +149,6 @@ __global__ void __launch_bounds__(256) k_structure_factor(int nruns, const KRun*
       out[2 * r + 1] = (double)aim[r];
     }
   }
-  if (blockIdx.x == 0) {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int o = 32; o > 0; o >>= 1) mz += __shfl_xor(mz, o, 64);
-    if (lane == 0) s_mz[wave] = mz;
-    __syncthreads();
-    if (threadIdx.x == 0) mz_part[chunk] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
-  }
 }
 
 int sf_tile(int nxm, int nym, int nzm) {
@@ -172,18 +159,17 @@ int sf_tile(int nxm, int nym, int nzm) {
 
 void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk, int m,
                                int mchunks, const double* xyz, const double* q, double Lx,
-                               double Ly, double Lz, int nxm, int nym, int nzm, double* part,
-                               double* mz_part) {
+                               double Ly, double Lz, int nxm, int nym, int nzm, double* part) {
   const int chunk_size = (m + mchunks - 1) / mchunks;
   const int tj = sf_tile(nxm, nym, nzm);
   const size_t shm = (size_t)tj * (nxm + nym + nzm + 3) * sizeof(double2);
   dim3 grid((nruns + 255) / 256, mchunks), block(256);
   if (fp32)
     hipLaunchKernelGGL(k_structure_factor<float>, grid, block, shm, st, nruns, runs, nk, m,
-                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part, mz_part);
+                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part);
   else
     hipLaunchKernelGGL(k_structure_factor<double>, grid, block, shm, st, nruns, runs, nk, m,
-                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part, mz_part);
+                       chunk_size, tj, xyz, q, Lx, Ly, Lz, nxm, nym, nzm, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -219,15 +205,12 @@ __device__ inline double2 cmul2(double2 a, double2 b) {
 //   next nbz rows              Z8_c(j) = e^{2 pi i 8 c fz_j}
 //   last row                   zero (the C operand of absent columns)
 // blockIdx.z selects the configuration of the group (tables tab_stride
-// apart).  Workgroups of row 0 also leave M_z partials sum q_j z_j per 256
-// charges (mz_stride apart per configuration).
+// apart).
 __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int nym,
                                                    const double* __restrict__ xyz,
                                                    const double* __restrict__ q, double Lx,
                                                    double Ly, double Lz, size_t tab_stride,
-                                                   double2* __restrict__ tab, int mz_stride,
-                                                   double* __restrict__ mz_part) {
-  __shared__ double s_mz[4];
+                                                   double2* __restrict__ tab) {
   const int row = blockIdx.y, snap = blockIdx.z;
   const int j = blockIdx.x * 256 + threadIdx.x;
   const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
@@ -258,26 +241,58 @@ __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int
     }
     tab[(size_t)row * mpad + j] = v;
   }
-  if (row == 0) {
-    double mz = qq * zz;
-    for (int o = 32; o > 0; o >>= 1) mz += __shfl_xor(mz, o, 64);
-    if ((threadIdx.x & 63) == 0) s_mz[threadIdx.x >> 6] = mz;
-    __syncthreads();
-    if (threadIdx.x == 0)
-      mz_part[(size_t)snap * mz_stride + blockIdx.x] = (s_mz[0] + s_mz[1]) + (s_mz[2] + s_mz[3]);
-  }
 }
 
 int sf_table_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) + 8 + nbz + 1; }
 
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
-                        double2* tab, double* mz_part) {
+                        double2* tab) {
   const int rows = sf_table_rows(nxm, nym, nbz);
   const int blocks = (mpad + 255) / 256;
   dim3 grid(blocks, rows, g), block(256);
   hipLaunchKernelGGL(k_sf_tables, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly, Lz,
-                     (size_t)rows * mpad, tab, blocks, mz_part);
+                     (size_t)rows * mpad, tab);
+}
+
+// Electrolyte dipole partials of each configuration of a group, per 256
+// charges and axis: dip[((s * blocks + blk) * 3 + d] = sum q_j r_jd (raw
+// coordinates; the dipole corrections of Eqs. 10-12 and 11 use them).
+__global__ void __launch_bounds__(256) k_elyt_dipole(int m, const double* __restrict__ xyz,
+                                                     const double* __restrict__ q,
+                                                     double* __restrict__ dip) {
+  __shared__ double sh[3][4];
+  const int j = blockIdx.x * 256 + threadIdx.x, snap = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (j < m) {
+    const double* r = xyz + ((size_t)snap * m + j) * 3;
+    const double qq = q[j];
+    v[0] = qq * r[0]; v[1] = qq * r[1]; v[2] = qq * r[2];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    for (int o = 32; o > 0; o >>= 1) v[d] += __shfl_xor(v[d], o, 64);
+    if (lane == 0) sh[d][wave] = v[d];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    dip[((size_t)snap * gridDim.x + blockIdx.x) * 3 + d] = (sh[d][0] + sh[d][1]) + (sh[d][2] + sh[d][3]);
+  }
+}
+
+void launch_b_elyt_dipole(hipStream_t st, int g, int m, const double* xyz, const double* q,
+                          double* dip) {
+  hipLaunchKernelGGL(k_elyt_dipole, dim3((m + 255) / 256, g), dim3(256), 0, st, m, xyz, q, dip);
+}
+
+// the electrolyte dipole of configuration s from its partials (fixed order)
+__device__ inline void elyt_dipole(const double* __restrict__ dip, int blocks, int s, double M[3]) {
+  M[0] = M[1] = M[2] = 0.0;
+  for (int r = 0; r < blocks; ++r)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) M[d] += dip[((size_t)s * blocks + r) * 3 + d];
 }
 
 // Structure factors of full (k_x, k_y) columns as a real GEMM on FP64 matrix
@@ -866,7 +881,7 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
                                                       const double* __restrict__ ez,
                                                       const double* __restrict__ xyz,
                                                       const double* __restrict__ q, double Lx,
-                                                      double Ly, double rc,
+                                                      double Ly, double Lz, double rc,
                                                       const double* __restrict__ ptab,
                                                       double* __restrict__ part) {
   __shared__ double s_tab[3 * (RS_NT + 1)];
@@ -876,9 +891,10 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
   const int atom = slot < nmap ? amap[slot] : -1;
   const int chunk = blockIdx.y, rchunks = gridDim.y;
   const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
-  const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, rc2 = rc * rc;
+  const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, invLz = 1.0 / Lz, rc2 = rc * rc;
   const double h = rc / RS_NT, inv_h = RS_NT / rc;
-  const bool single = (Lx >= 2.0 * rc) && (Ly >= 2.0 * rc);
+  // only the nearest image can lie within rc when every cell length is >= 2 rc
+  const bool single = (Lx >= 2.0 * rc) && (Ly >= 2.0 * rc) && (Lz >= 2.0 * rc);
   for (int t = threadIdx.x; t < 3 * (RS_NT + 1); t += 256) s_tab[t] = ptab[t];
   __syncthreads();
   double xi = 0, yi = 0, zi = 0;
@@ -889,7 +905,10 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
     zlo = fmin(zlo, __shfl_xor(zlo, o, 64));
     zhi = fmax(zhi, __shfl_xor(zhi, o, 64));
   }
+  // z window [wlo, whi) of charges that can come within rc (some periodic
+  // image in z of the charge must fall inside it)
   const double wlo = zlo - rc, whi = zhi + rc;
+  const bool keep_all = whi - wlo >= Lz;
   double (*C)[64] = s_c[wave];
   const int nblk = j1 > j0 ? (j1 - j0 + 63) / 64 : 0;
   const int steps = g * nblk;
@@ -909,7 +928,7 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
     const bool valid = j0 + blk * 64 + lane < j1;
     double x = px, y = py, z = pzz, qq = pq;
     if (step + 1 < steps) fetch(step + 1);
-    const bool keep = valid && z > wlo && z < whi;
+    const bool keep = valid && (keep_all || (z - Lz * floor((z - wlo) * invLz)) < whi);
     const unsigned long long bal = __ballot(keep);
     const int kept = __popcll(bal);
     if (keep) {
@@ -922,8 +941,9 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
     wave_lds_sync();
     if (atom >= 0) {
       for (int t = 0; t < kept; ++t) {
-        const double dz = zi - C[2][t];
-        if (fabs(dz) >= rc) continue;
+        double dz = zi - C[2][t];
+        dz -= Lz * rint(dz * invLz);
+        if (fabs(dz) >= rc) continue;          // dz is the nearest image
         double dx = xi - C[0][t], dy = yi - C[1][t];
         dx -= Lx * rint(dx * invLx);
         dy -= Ly * rint(dy * invLy);
@@ -933,12 +953,16 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
         } else {
           const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
           const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
-          for (int a = alo; a <= ahi; ++a) {
-            const double X = dx + a * Lx;
-            for (int bb = blo; bb <= bhi; ++bb) {
-              const double Y = dy + bb * Ly;
-              const double r2 = X * X + Y * Y + dz * dz;
-              if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
+          const int clo = (int)ceil((-rc - dz) * invLz) - 1, chi = (int)floor((rc - dz) * invLz) + 1;
+          for (int cc = clo; cc <= chi; ++cc) {
+            const double Z = dz + cc * Lz;
+            for (int a = alo; a <= ahi; ++a) {
+              const double X = dx + a * Lx;
+              for (int bb = blo; bb <= bhi; ++bb) {
+                const double Y = dy + bb * Ly;
+                const double r2 = X * X + Y * Y + Z * Z;
+                if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
+              }
             }
           }
         }
@@ -956,24 +980,28 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
 
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
                          int nmap, const double* xyz, const double* q, double Lx, double Ly,
-                         double rc, double* part) {
+                         double Lz, double rc, double* part) {
   const int chunk_size = (m + rchunks - 1) / rchunks;
   dim3 grid((nmap + 255) / 256, rchunks), block(256);
   hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, chunk_size, b.amap, nmap, b.ex,
-                     b.ey, b.ez, xyz, q, Lx, Ly, rc, b.rtab, part);
+                     b.ey, b.ez, xyz, q, Lx, Ly, Lz, rc, b.rtab, part);
 }
 
 // b_i = -k_e (sum of k-space partials + sum of real-space partials
-//            + (4 pi / V) z_i M_z), M_z from the structure-factor chunks.
+//            + sum_d c_d r_id M_d): the electrolyte part of the geometry's
+// dipole term (slab: c_z = 4 pi / V, Eq. 12; wire: c_x = c_y = 2 pi / V,
+// Eq. 11; tin foil: none), M from the electrolyte dipole partials.
 // Four lanes per atom sum interleaved partial rows; the four sums are added
 // in a fixed order.
-__global__ void __launch_bounds__(256) k_combine(int n, int kchunks, int rchunks, int mchunks,
+__global__ void __launch_bounds__(256) k_combine(int n, int kchunks, int rchunks,
                                                  const double* __restrict__ phik,
                                                  const double* __restrict__ phir,
+                                                 const double* __restrict__ ex,
+                                                 const double* __restrict__ ey,
                                                  const double* __restrict__ ez,
-                                                 const double* __restrict__ mz_part,
-                                                 double slab_coef, double ke, void* out,
-                                                 int out_is_f32) {
+                                                 const double* __restrict__ dip, int dip_blocks,
+                                                 double cx, double cy, double cz, double ke,
+                                                 void* out, int out_is_f32) {
   __shared__ double sh[4][64];
   const int sub = threadIdx.x >> 6, li = threadIdx.x & 63;
   const int i = blockIdx.x * 64 + li;
@@ -985,10 +1013,10 @@ __global__ void __launch_bounds__(256) k_combine(int n, int kchunks, int rchunks
   sh[sub][li] = acc;
   __syncthreads();
   if (sub != 0 || i >= n) return;
-  double mz = 0.0;
-  for (int c = 0; c < mchunks; ++c) mz += mz_part[c];
+  double M[3];
+  elyt_dipole(dip, dip_blocks, 0, M);
   const double phi = (sh[0][li] + sh[1][li]) + (sh[2][li] + sh[3][li]);
-  const double b = -ke * (phi + slab_coef * ez[i] * mz);
+  const double b = -ke * (phi + (cx * ex[i] * M[0] + cy * ey[i] * M[1] + cz * ez[i] * M[2]));
   if (out_is_f32)
     reinterpret_cast<float*>(out)[i] = (float)b;
   else
@@ -1044,19 +1072,20 @@ __global__ void __launch_bounds__(256) k_layer_project_g(int g, int n, int ncols
 }
 
 // step 2: b_i = -k_e (sum of column-group partials + sum of real-space
-// partials + (4 pi / V) z_i M_z), thread per (atom, configuration).
+// partials + sum_d c_d r_id M_d), thread per (atom, configuration).
 __global__ void k_layer_final(int g, int n, int cgroups, const double* __restrict__ phik,
                               const double* __restrict__ phir, int rchunks,
-                              const double* __restrict__ ez, const double* __restrict__ mz_part,
-                              int mz_parts, double slab_coef, double ke, void* out,
-                              int out_is_f32) {
+                              const double* __restrict__ ex, const double* __restrict__ ey,
+                              const double* __restrict__ ez, const double* __restrict__ dip,
+                              int dip_blocks, double cx, double cy, double cz, double ke,
+                              void* out, int out_is_f32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
   if (i >= n) return;
-  double pk = 0.0, pr = 0.0, mz = 0.0;
+  double pk = 0.0, pr = 0.0, M[3];
   for (int r = 0; r < cgroups; ++r) pk += phik[((size_t)r * g + s) * n + i];
   for (int r = 0; r < rchunks; ++r) pr += phir[((size_t)s * rchunks + r) * n + i];
-  for (int r = 0; r < mz_parts; ++r) mz += mz_part[(size_t)s * mz_parts + r];
-  const double bv = -ke * ((pk + pr) + slab_coef * ez[i] * mz);
+  elyt_dipole(dip, dip_blocks, s, M);
+  const double bv = -ke * ((pk + pr) + (cx * ex[i] * M[0] + cy * ey[i] * M[1] + cz * ez[i] * M[2]));
   if (out_is_f32)
     reinterpret_cast<float*>(out)[(size_t)s * n + i] = (float)bv;
   else
@@ -1065,24 +1094,25 @@ __global__ void k_layer_final(int g, int n, int cgroups, const double* __restric
 
 void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlayers, int cgroups,
                             const double2* E, const int* layer_of, const double2* T,
-                            double* phik, const double* phir, int rchunks, const double* ez,
-                            const double* mz_part, int mz_parts, double slab_coef, double ke,
+                            double* phik, const double* phir, int rchunks, const Buffers& b,
+                            const double* dip, int dip_blocks, const double* cdip, double ke,
                             void* out, int out_is_f32) {
   const int cpg = (ncolsort + cgroups - 1) / cgroups;
   hipLaunchKernelGGL(k_layer_project_g, dim3((n + 63) / 64, cgroups), dim3(256), 0, st, g, n,
                      ncolsort, cpg, nlayers, E, layer_of, T, phik);
   hipLaunchKernelGGL(k_layer_final, dim3((n + 255) / 256, g), dim3(256), 0, st, g, n, cgroups,
-                     phik, phir, rchunks, ez, mz_part, mz_parts, slab_coef, ke, out, out_is_f32);
+                     phik, phir, rchunks, b.ex, b.ey, b.ez, dip, dip_blocks, cdip[0], cdip[1],
+                     cdip[2], ke, out, out_is_f32);
 }
 
 int layer_combine_max_group() { return LC_MAXG; }
 
-void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchunks,
-                      const double* phik, const double* phir, const Buffers& b,
-                      const double* mz_part, double slab_coef, double ke, void* out,
-                      int out_is_f32) {
-  hipLaunchKernelGGL(k_combine, dim3((n + 63) / 64), dim3(256), 0, st, n, kchunks, rchunks,
-                     mchunks, phik, phir, b.ez, mz_part, slab_coef, ke, out, out_is_f32);
+void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
+                      const double* phir, const Buffers& b, const double* dip, int dip_blocks,
+                      const double* cdip, double ke, void* out, int out_is_f32) {
+  hipLaunchKernelGGL(k_combine, dim3((n + 63) / 64), dim3(256), 0, st, n, kchunks, rchunks, phik,
+                     phir, b.ex, b.ey, b.ez, dip, dip_blocks, cdip[0], cdip[1], cdip[2], ke, out,
+                     out_is_f32);
 }
 
 }  // namespace cpm

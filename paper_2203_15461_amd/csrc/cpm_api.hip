@@ -205,7 +205,7 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     if (fast) {
       const double per = 16.0 * c->sft_rows * c->mpad + 8.0 * c->sfm_pchunk +
                          16.0 * c->ncolsort * c->nlayers + 8.0 * c->rchunks * c->n +
-                         8.0 * c->sft_blocks;
+                         24.0 * ((c->m + 255) / 256);
       c->pv_group = std::max(1, std::min(layer_combine_max_group(),
                                          (int)(512.0 * 1024 * 1024 / per)));
       // column groups of the projection: ~1024 workgroups, >= 8 columns each
@@ -224,7 +224,8 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   TRY(dalloc(c, &b.phik_part,
              (size_t)c->n * std::max({pk_rows, c->kchunks, c->lp_groups * c->pv_group})));
   TRY(dalloc(c, &b.phir_part, (size_t)c->pv_group * c->n * c->rchunks));
-  TRY(dalloc(c, &b.mz, (size_t)c->pv_group * std::max(c->mchunks, c->sft_blocks)));
+  c->dip_blocks = std::max(1, (c->m + 255) / 256);
+  TRY(dalloc(c, &b.dip, (size_t)c->pv_group * c->dip_blocks * 3));
   TRY(dalloc(c, &b.rtab, (size_t)3 * (RS_NT + 1)));
   launch_pair_table(c->stream, c->p.alpha, c->p.eta, c->p.rcut, b.rtab);
   TRY(launched(c, "pair table"));
@@ -341,19 +342,22 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   c->stream = static_cast<hipStream_t>(hip_stream);
   const cpm_params& p = c->p;
   cpm_status st = CPM_OK;
-  if (p.geometry != CPM_GEOM_SLAB_EW3DC)
-    st = fail(c, CPM_EUNSUPPORTED, "geometry %d: only the EW3DC slab runs here", p.geometry);
+  const bool slab = p.geometry == CPM_GEOM_SLAB_EW3DC;
+  if (p.geometry != CPM_GEOM_SLAB_EW3DC && p.geometry != CPM_GEOM_WIRE && p.geometry != CPM_GEOM_3D)
+    st = fail(c, CPM_EUNSUPPORTED, "geometry %d is not one of slab (0), wire (1), 3D (2)", p.geometry);
   else if (!finite_pos(p.Lx) || !finite_pos(p.Ly) || !finite_pos(p.h))
     st = fail(c, CPM_EINVAL, "Lx, Ly, h must be finite and > 0");
-  else if (!(std::isfinite(p.slab_factor) && p.slab_factor > 1.0))
+  else if (slab && !(std::isfinite(p.slab_factor) && p.slab_factor > 1.0))
     st = fail(c, CPM_EINVAL, "slab_factor must be > 1");
+  else if (!slab && !(std::isfinite(p.slab_factor) && p.slab_factor >= 1.0))
+    st = fail(c, CPM_EINVAL, "slab_factor must be >= 1");
   else if (!finite_pos(p.eta) || !finite_pos(p.alpha) || !finite_pos(p.rcut))
     st = fail(c, CPM_EINVAL, "eta, alpha, rcut must be finite and > 0");
   else if (!(p.kcut > 0.0) && !(p.kspace_eps > 0.0 && p.kspace_eps < 1.0))
     st = fail(c, CPM_EINVAL, "need kcut > 0 or 0 < kspace_eps < 1");
   else if (!std::isfinite(p.kcut) || !std::isfinite(p.coulomb_k) || p.coulomb_k < 0.0)
     st = fail(c, CPM_EINVAL, "kcut and coulomb_k must be finite (coulomb_k >= 0)");
-  else if ((p.slab_factor - 1.0) * p.h <= p.rcut)
+  else if (slab && (p.slab_factor - 1.0) * p.h <= p.rcut)
     st = fail(c, CPM_EINVAL, "slab clearance (slab_factor - 1) * h = %g must exceed rcut = %g",
               (p.slab_factor - 1.0) * p.h, p.rcut);
   if (st != CPM_OK) {
@@ -362,6 +366,12 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   }
   c->Lz = p.slab_factor * p.h;
   c->V = p.Lx * p.Ly * c->Lz;
+  // dipole term of the boundary geometry, A += k_e sum_d cdip_d r_d r_d^T:
+  // slab (x, y periodic, EW3DC in z, Eqs. 10, 12): 4 pi / V on z;
+  // wire (z periodic, Eq. 11): 2 pi / V on x and y; 3D periodic (tin foil,
+  // the finite-field setting): none
+  if (p.geometry == CPM_GEOM_SLAB_EW3DC) c->cdip[2] = 4.0 * M_PI / c->V;
+  if (p.geometry == CPM_GEOM_WIRE) c->cdip[0] = c->cdip[1] = 2.0 * M_PI / c->V;
   if (const char* ev = std::getenv("CPM_SF_WG_TARGET")) c->sf_wg_target = std::max(64, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_WG_TARGET")) c->sfm_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
@@ -500,7 +510,7 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
     zmin = std::min(zmin, c->h_xyz[3 * i + 2]);
     zmax = std::max(zmax, c->h_xyz[3 * i + 2]);
   }
-  if (c->Lz - (zmax - zmin) <= c->p.rcut)
+  if (c->p.geometry == CPM_GEOM_SLAB_EW3DC && c->Lz - (zmax - zmin) <= c->p.rcut)
     return fail(c, CPM_EINVAL, "electrode z extent %g leaves no slab clearance in Lz = %g", zmax - zmin, c->Lz);
   // planar electrodes: atoms sharing an exact z value form a plane
   std::vector<double> zs;
@@ -573,9 +583,8 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   const double eta_ee = p.eta / std::sqrt(2.0);
   const double diag_self = (std::sqrt(2.0) * p.eta - 2.0 * p.alpha) / std::sqrt(M_PI);
   const double background = -M_PI / (c->V * p.alpha * p.alpha);
-  const double slab_coef = 4.0 * M_PI / c->V;
-  launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, p.rcut, p.alpha, eta_ee, diag_self,
-                      background, slab_coef, c->ke, d_diag_extra, b.A);
+  launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha, eta_ee,
+                      diag_self, background, c->cdip, c->ke, d_diag_extra, b.A);
   TRY(launched(c, "real_space_A"));
   if (c->nlayers > 0 && c->sf_mfma) {
     // planar electrodes: per plane, A[rows of L] += k_e G_L F^L (K = 2 x columns)
@@ -730,6 +739,24 @@ cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
   return CPM_OK;
 }
 
+cpm_status cpm_set_potential_atoms(cpm_ctx* c, const double* h_v) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_set_potential_atoms before cpm_invert");
+  if (!h_v) return fail(c, CPM_EINVAL, "h_v is NULL");
+  for (int i = 0; i < c->n; ++i)
+    if (!std::isfinite(h_v[i])) return fail(c, CPM_EINVAL, "potential of atom %d not finite", i);
+  c->h_v.clear();
+  std::vector<double> vat(c->npad, 0.0);
+  for (int i = 0; i < c->n; ++i) vat[i] = h_v[i];
+  HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
+                0.0, c->b.d, c->npad, 0);
+  TRY(launched(c, "set_potential_atoms"));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->have_v = true;
+  return CPM_OK;
+}
+
 }  // extern "C"
 
 namespace {
@@ -759,7 +786,6 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   const bool mfma = c->sf_mfma && c->use_sf_mfma;
   const bool fast = mfma && c->nlayers > 0;
   const int G = fast ? c->pv_group : 1;
-  const double slab_coef = 4.0 * M_PI / c->V;
   for (int s0 = 0; s0 < batch; s0 += G) {
     const int g = std::min(G, batch - s0);
     const double* xyz = d_xyz ? d_xyz + (size_t)s0 * m * 3 : nullptr;
@@ -769,10 +795,12 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
       continue;
     }
     const int nch = mfma ? sf_chunks_for(c, g) : 0;
+    { Timed t(c, "dipole");
+      launch_b_elyt_dipole(st, g, m, xyz, b.elq, b.dip); }
     if (mfma) {
       { Timed t(c, "sf_tables");
         launch_b_sf_tables(st, g, m, c->mpad, c->nxm, c->nym, c->sfm_nbz, xyz, b.elq, p.Lx, p.Ly,
-                           c->Lz, b.sft, b.mz); }
+                           c->Lz, b.sft); }
       { Timed t(c, "structure_factor");
         launch_b_sf_mfma(st, g, c->mpad, nch, c->sfm_nitems, b.sfm_items, b.sc_nx, b.sc_ny,
                          c->ncolsort, c->nxm, c->nym, c->sfm_nbz, b.sft, b.tile_nb, b.tile_off,
@@ -780,14 +808,13 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
     } else {
       { Timed t(c, "structure_factor");
         launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz,
-                                  b.elq, p.Lx, p.Ly, c->Lz, c->nxm, c->nym, c->nzm, b.sf_part,
-                                  b.mz); }
+                                  b.elq, p.Lx, p.Ly, c->Lz, c->nxm, c->nym, c->nzm, b.sf_part); }
       { Timed t(c, "sf_reduce");
         launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
     }
     { Timed t(c, "real_space_b");
-      launch_b_real_space(st, g, n, m, c->rchunks, b, c->nmap, xyz, b.elq, p.Lx, p.Ly, p.rcut,
-                          b.phir_part); }
+      launch_b_real_space(st, g, n, m, c->rchunks, b, c->nmap, xyz, b.elq, p.Lx, p.Ly, c->Lz,
+                          p.rcut, b.phir_part); }
     if (fast) {
       { Timed t(c, "sf_reduce");
         launch_b_sf_layer_reduce(st, g, c->ncolsort, nch, c->sfm_pchunk, c->nlayers,
@@ -796,8 +823,8 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
                                  b.sflT); }
       { Timed t(c, "combine");
         launch_b_layer_combine(st, g, n, c->ncolsort, c->nlayers, c->lp_groups, b.ephase,
-                               b.layer_of, b.sflT, b.phik_part, b.phir_part, c->rchunks, b.ez,
-                               b.mz, c->sft_blocks, slab_coef, c->ke, out, b_is_f32); }
+                               b.layer_of, b.sflT, b.phik_part, b.phir_part, c->rchunks, b,
+                               b.dip, c->dip_blocks, c->cdip, c->ke, out, b_is_f32); }
       TRY(launched(c, "potential_vector"));
       continue;
     }
@@ -820,8 +847,8 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
                               b.phik_part);
     }
     { Timed t(c, "combine");
-      launch_b_combine(st, n, kparts, c->rchunks, mfma ? c->sft_blocks : c->mchunks, b.phik_part,
-                       b.phir_part, b, b.mz, slab_coef, c->ke, out, b_is_f32); }
+      launch_b_combine(st, n, kparts, c->rchunks, b.phik_part, b.phir_part, b, b.dip,
+                       c->dip_blocks, c->cdip, c->ke, out, b_is_f32); }
     TRY(launched(c, "potential_vector"));
   }
   return CPM_OK;
@@ -1297,7 +1324,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.runs); dfree(b.cols); dfree(b.chunk_col); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
-  dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.mz); dfree(b.qt);
+  dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.dip); dfree(b.qt);
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
   if (c->stream) (void)hipStreamSynchronize(c->stream);

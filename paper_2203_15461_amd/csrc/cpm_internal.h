@@ -91,7 +91,7 @@ struct Buffers {
   double* sfw = nullptr;           // 2W-weighted structure factor (2 * nk)
   double* phik_part = nullptr;     // k-chunk partial potentials (n * kchunks)
   double* phir_part = nullptr;     // m-chunk partial real-space potentials (n * rchunks)
-  double* mz = nullptr;            // electrolyte dipole partials M_z (per SF chunk)
+  double* dip = nullptr;           // electrolyte dipole partials (per 256 charges, 3 axes)
   double* rtab = nullptr;          // real-space pair table (g, g', g'') x (RS_NT + 1)
   double* qt = nullptr;            // q-tilde (batch x npad)
   double* res = nullptr;           // refinement residual / corrections (batch x npad)
@@ -115,6 +115,8 @@ struct cpm_ctx {
   bool have_elyt = false, have_A = false, have_inv = false, have_v = false, have_q = false;
   int n = 0, npad = 0, n_e = 0, m = 0;
   double Lz = 0, V = 0, kc = 0, ke = 0;
+  double cdip[3] = {0, 0, 0};      // dipole term A += k_e sum_d cdip_d r_d r_d^T (geometry)
+  int dip_blocks = 1;              // electrolyte dipole partials per configuration
   int nk = 0, nruns = 0;
   int mchunks = 1, kchunks = 1, rchunks = 1;
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
@@ -174,10 +176,10 @@ namespace cpm {
 // assembly
 void launch_prep_electrodes(hipStream_t st, int n, const double* xyz, double Lx, double Ly,
                             double Lz, Buffers& b);
-void launch_real_space_A(hipStream_t st, int n, int npad, const Buffers& b, double Lx,
-                         double Ly, double rc, double alpha, double eta_ee, double diag_self,
-                         double background, double slab_coef, double ke, const double* diag_extra,
-                         double* A);
+void launch_real_space_A(hipStream_t st, int n, int npad, const Buffers& b, double Lx, double Ly,
+                         double Lz, double rc, double alpha, double eta_ee, double diag_self,
+                         double background, const double* cdip, double ke,
+                         const double* diag_extra, double* A);
 void launch_phase_table(hipStream_t st, int n, int npad, int k0, int kc, int nk, const Buffers& b,
                         double ke, double* table);
 void launch_plane_pair_weights(hipStream_t st, int ncolsort, int nlayers, const int* sc_lo,
@@ -253,10 +255,12 @@ void launch_gemm_bf16x3_group(hipStream_t st, const GemmGroupBf& grp, int bm, in
 void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* runs, int nk,
                                int m, int mchunks, const double* xyz, const double* q,
                                double Lx, double Ly, double Lz, int nxm, int nym, int nzm,
-                               double* part, double* mz_part);
+                               double* part);
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
-                        double2* tab, double* mz_part);
+                        double2* tab);
+void launch_b_elyt_dipole(hipStream_t st, int g, int m, const double* xyz, const double* q,
+                          double* dip);
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
@@ -275,8 +279,8 @@ void launch_electrode_phases(hipStream_t st, int n, int ncolsort, const int* sc_
                              double2* E, double2* pz);
 void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlayers, int cgroups,
                             const double2* E, const int* layer_of, const double2* T,
-                            double* phik, const double* phir, int rchunks, const double* ez,
-                            const double* mz_part, int mz_parts, double slab_coef, double ke,
+                            double* phik, const double* phir, int rchunks, const Buffers& b,
+                            const double* dip, int dip_blocks, const double* cdip, double ke,
                             void* out, int out_is_f32);
 int layer_combine_max_group();
 int sf_table_rows(int nxm, int nym, int nbz);
@@ -293,10 +297,9 @@ int layer_project_chunks(int ncols);
 void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab);
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
                          int nmap, const double* xyz, const double* q, double Lx, double Ly,
-                         double rc, double* part);
-void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, int mchunks,
-                      const double* phik, const double* phir, const Buffers& b,
-                      const double* mz_part, double slab_coef, double ke, void* out,
-                      int out_is_f32);
+                         double Lz, double rc, double* part);
+void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
+                      const double* phir, const Buffers& b, const double* dip, int dip_blocks,
+                      const double* cdip, double ke, void* out, int out_is_f32);
 
 }  // namespace cpm

@@ -50,10 +50,21 @@ def _create(**over):
     (dict(alpha=float("inf")), cpm.EINVAL),
     (dict(kspace_eps=0.0), cpm.EINVAL),
     (dict(kspace_eps=2.0), cpm.EINVAL),
-    (dict(geometry=1), cpm.EUNSUPPORTED),
+    (dict(geometry=3), cpm.EUNSUPPORTED),
+    (dict(geometry=1, slab_factor=0.5), cpm.EINVAL),
+    (dict(geometry=2, slab_factor=0.9), cpm.EINVAL),
 ])
 def test_create_validation(over, status):
     assert _create(**over) == status
+
+
+@pytest.mark.parametrize("geometry", [1, 2])
+def test_other_geometries_accepted(geometry):
+    """Wire and 3D-periodic cells need no slab clearance (slab_factor 1)."""
+    p = cpm.Params(20.0, 20.0, 10.0, 1.0, geometry=geometry).to_c()
+    h = ctypes.c_void_p()
+    assert cpm.lib().cpm_create(ctypes.byref(p), None, ctypes.byref(h)) == cpm.OK
+    cpm.lib().cpm_destroy(h)
 
 
 def test_null_arguments():
@@ -66,6 +77,7 @@ def test_null_arguments():
     assert L.cpm_replay_step(None) == cpm.EINVAL
     assert L.cpm_autotune(None, 64, 1) == cpm.EINVAL
     assert L.cpm_set_charge(None, None) == cpm.EINVAL
+    assert L.cpm_set_potential_atoms(None, None) == cpm.EINVAL
     assert L.cpm_solve_grouped(None, 1, None, None, 0, 0x102, None, None) == cpm.EINVAL
     assert L.cpm_last_error(None) == b"no context"
     L.cpm_destroy(None)

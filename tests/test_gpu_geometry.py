@@ -1,0 +1,119 @@
+"""Wire (Eq. 11) and 3D-periodic / finite-field (Eqs. 13-14) geometries on the GPU.
+
+Both run the same Ewald sum as the slab with every periodic image within
+r_c, and differ in the dipole term.  FP64 parity with the oracle: A within
+1e-11 relative, b and q within 1e-10, |sum q| <= 1e-12 e.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import cpm_oracle as O
+from paper_2203_15461_amd import inputs as I
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+@pytest.fixture(scope="module")
+def cpm():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_15461_amd import cpm as C
+    C.lib()
+    return C
+
+
+def _run(C, params, R, eid, r, qy, v_atoms=None, v_e=None):
+    dev = "cuda"
+    n = len(R)
+    ctx = C.Context(params)
+    ctx.set_electrolyte(qy)
+    ctx.build_elastance(torch.as_tensor(R, dtype=torch.float64, device=dev).contiguous(),
+                        torch.as_tensor(eid, dtype=torch.int32, device=dev).contiguous(),
+                        int(eid.max()) + 1)
+    ctx.invert(1)
+    if v_atoms is not None:
+        ctx.set_potential_atoms(v_atoms)
+    else:
+        ctx.set_potential(v_e)
+    A = ctx.copy_matrix(0, torch.empty((n, n), dtype=torch.float64, device=dev)).cpu().numpy()
+    b = torch.empty((1, n), dtype=torch.float64, device=dev)
+    xyz = torch.as_tensor(np.asarray(r, np.float64).reshape(1, -1, 3), device=dev).contiguous()
+    ctx.potential_vector(xyz, b)
+    q = torch.empty_like(b)
+    ctx.solve_charges(b, 0, q)
+    ctx.synchronize()
+    out = A, b.cpu().numpy()[0], q.cpu().numpy()[0], ctx.info("nlayers")
+    ctx.close()
+    return out
+
+
+@pytest.mark.parametrize("Lz", [45.0, 35.0])
+def test_finite_field_3d_periodic(cpm, Lz):
+    """Small capacitor in a 3D-periodic tin-foil cell; at Lz = 35 the top layer
+    (z = 30) and the periodic image of the bottom one (z = 35) are 5 A apart,
+    so real-space pairs cross the z boundary.  Finite-field potential
+    v = -dv0 zeta."""
+    w = I.small_capacitor("a")
+    say(f"3D periodic small_capacitor_a Lz={Lz}")
+    p = O.params_for(w, Lz=Lz, geometry="tinfoil")
+    zeta = I.finite_field_zeta(w.electrode_xyz[:, 2], w.electrode_id, Lz)
+    dv0 = 1.5
+    r = I.snapshot(w, 2)
+    A = O.elastance(w.electrode_xyz, p)
+    cap = O.capacitance(A)
+    b = O.potential_vector(w.electrode_xyz, r, w.electrolyte_q, p)
+    q = O.charges(cap.S, b, -dv0 * zeta)
+    gp = cpm.Params(w.Lx, w.Ly, Lz, 1.0, w.eta, w.alpha, w.rcut, w.kspace_eps, geometry=2)
+    Ag, bg, qg, nl = _run(cpm, gp, w.electrode_xyz, w.electrode_id, r, w.electrolyte_q,
+                          v_atoms=-dv0 * zeta)
+    assert nl == 2
+    assert rel(Ag, A) < 1e-11
+    assert rel(bg, b) < 1e-10
+    assert rel(qg, q) < 1e-10
+    assert abs(qg.sum()) <= 1e-12
+
+
+def test_wire_coaxial_tubes(cpm):
+    """Co-axial armchair tubes (4,4)@(8,8), one axial period (2.46 A << 2 r_c:
+    many z images), with four ions between the tubes."""
+    R, eid, R1, R2, per = I.coaxial_tubes(4, 8)
+    Lxy = 2 * R2 + 40.0
+    c = np.array([Lxy / 2, Lxy / 2, 0.0])
+    R = R + c
+    rad = 0.5 * (R1 + R2)
+    ang = np.array([0.3, 1.9, 3.4, 5.0])
+    r = np.column_stack([c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang),
+                         np.array([0.2, 0.9, 1.5, 2.1])])
+    qy = np.array([1.0, -1.0, 1.0, -1.0])
+    say(f"wire: tubes n={len(R)}, period {per:.4f} A, box {Lxy:.2f} A")
+    p = O.Params(Lxy, Lxy, per, eta=1.979, alpha=0.3, rcut=12.0, kspace_eps=1e-8, geometry="wire")
+    A = O.elastance(R, p)
+    cap = O.capacitance(A)
+    b = O.potential_vector(R, r, qy, p)
+    v = O.applied_potential(eid, [-0.5, 0.5])
+    q = O.charges(cap.S, b, v)
+    gp = cpm.Params(Lxy, Lxy, per, 1.0, 1.979, 0.3, 12.0, 1e-8, geometry=1)
+    Ag, bg, qg, nl = _run(cpm, gp, R, eid, r, qy, v_e=[-0.5, 0.5])
+    say(f"wire: planes detected {nl}")
+    assert rel(Ag, A) < 1e-11
+    assert rel(bg, b) < 1e-10
+    assert rel(qg, q) < 1e-10
+    assert abs(qg.sum()) <= 1e-12
+    # capacitance per length against the co-axial closed form (loose: small radii)
+    C0 = O.electrode_capacitance(cap.S, eid, 2)[0, 0]
+    ana = 2 * math.pi * O.EPS0 * per / math.log(R2 / R1)
+    assert 0 < C0 / ana - 1 < 0.2
