@@ -48,7 +48,8 @@ typedef enum {
   CPM_ENOMEM = 3,        /* device allocation failed                            */
   CPM_EHIP = 4,          /* HIP runtime error (launch, fault, copy)             */
   CPM_ENOTPD = 5,        /* A is not positive definite (Cholesky pivot <= 0)     */
-  CPM_EUNSUPPORTED = 6   /* valid request this build does not provide          */
+  CPM_EUNSUPPORTED = 6,  /* valid request this build does not provide          */
+  CPM_ENOCONV = 7        /* iteration stopped at its limit above the tolerance  */
 } cpm_status;
 
 /* Boundary geometry (Sec. II.E).  All three use the Ewald sum of the
@@ -100,8 +101,12 @@ enum {
   CPM_INFO_TUNE_KS = 14,      /*   ... parts the K dimension is split into        */
   CPM_INFO_TUNE_GRID = 15,    /*   ... workgroups of the persistent launch        */
   CPM_INFO_TUNE_US = 16,      /*   ... measured microseconds per product          */
-  CPM_INFO_GROUP = 17         /* configurations per launch group of              */
+  CPM_INFO_GROUP = 17,        /* configurations per launch group of              */
                               /* cpm_potential_vector (planar electrodes)         */
+  CPM_INFO_CG_ITERS = 18,     /* last cpm_solve_cg: most iterations of a vector   */
+  CPM_INFO_CG_RESID = 19,     /*   ... largest final |r| / |r0|                   */
+  CPM_INFO_ELL_WIDTH = 20     /* entries per row of the operator's real-space     */
+                              /* part (cpm_build_operator)                        */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -142,6 +147,46 @@ cpm_status cpm_set_electrolyte(cpm_ctx* ctx, int m, const double* h_q);
 cpm_status cpm_build_elastance(cpm_ctx* ctx, int n, const double* d_xyz,
                                const int* d_electrode_id, int n_e,
                                const double* d_diag_extra);
+
+/* The elastance as an operator instead of a matrix, for the
+ * conjugate-gradient solve that Sec. II.A names as the alternative to
+ * inverting A (and Sec. IV as future work): the same electrode set-up and
+ * arguments as cpm_build_elastance, but A is never formed.  Keeps the
+ * real-space and self terms as a sparse matrix (ELL: one entry per electrode
+ * pair with a periodic image within r_c, CPM_INFO_ELL_WIDTH per row), and
+ * applies the k-space term through the electrode planes (memory
+ * O(n x columns) for the in-plane phases, which the planar b path shares).
+ * Needs electrodes on at most 64 z planes and the matrix-core k set
+ * (CPM_INFO_NLAYERS > 0, CPM_INFO_SF_MATRIX = 1), else CPM_EUNSUPPORTED.
+ * A context holds either the dense elastance or the operator (CPM_ESTATE).
+ * cpm_set_potential, cpm_set_potential_atoms and cpm_potential_vector work as
+ * after cpm_invert; cpm_solve_charges does not (no S).  Synchronous. */
+cpm_status cpm_build_operator(cpm_ctx* ctx, int n, const double* d_xyz,
+                              const int* d_electrode_id, int n_e,
+                              const double* d_diag_extra);
+
+/* y = A x for `batch` vectors (Eq. 2's elastance applied to charges, e.g.
+ * for the energy q^T A q / 2): d_x, d_y batch x n FP64 device arrays.  Uses
+ * the operator of cpm_build_operator, or the dense A after
+ * cpm_build_elastance.  Enqueued on the context stream. */
+cpm_status cpm_apply_elastance(cpm_ctx* ctx, int batch, const double* d_x, double* d_y);
+
+/* Conjugate-gradient solve (Sec. II.A's alternative to the inversion):
+ * q minimises the energy with e^T q = 0, i.e. A q = b + v + mu e, by
+ * conjugate gradients on the neutral subspace (projector I - e e^T / n),
+ * starting from q = 0, in FP64, with A applied by the operator of
+ * cpm_build_operator or, after cpm_build_elastance, by the dense A.
+ * d_b: batch x n (FP64, or FP32 with b_is_f32 = 1); v from
+ * cpm_set_potential(_atoms).  Each vector stops when |r| <= tol |r0| (r the
+ * projected residual, recursively updated); at most maxit iterations.
+ * Vectors run in groups of 32.  Writes d_q (batch x n FP64, the final
+ * iterate projected to e^T q = 0) and, unless NULL, d_Qe (batch x n_e
+ * electrode totals).  Synchronous (the host checks convergence every 8
+ * iterations).  CPM_ENOCONV if some vector ended above the tolerance (the
+ * outputs then hold the last iterates).  CPM_INFO_CG_ITERS and
+ * CPM_INFO_CG_RESID report the iterations and residual reached. */
+cpm_status cpm_solve_cg(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32, double tol,
+                        int maxit, double* d_q, double* d_Qe);
 
 /* Invert A in FP64 (blocked Cholesky A = L L^T, then A^-1 = L^-T L^-1,
  * Eq. 3), form u = A^-1 e, s = e^T u and the charge-neutral S of Eq. 4, and

@@ -16,19 +16,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libcpm.so")
 
 # status codes
-OK, EINVAL, ESTATE, ENOMEM, EHIP, ENOTPD, EUNSUPPORTED = range(7)
+OK, EINVAL, ESTATE, ENOMEM, EHIP, ENOTPD, EUNSUPPORTED, ENOCONV = range(8)
 STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_ESTATE", 3: "CPM_ENOMEM", 4: "CPM_EHIP",
-                5: "CPM_ENOTPD", 6: "CPM_EUNSUPPORTED"}
+                5: "CPM_ENOTPD", 6: "CPM_EUNSUPPORTED", 7: "CPM_ENOCONV"}
 # store flags, solve modes, info keys
 STORE_F64, STORE_F32, STORE_BF16X2 = 1, 2, 4
 SOLVE_F64, SOLVE_F32, SOLVE_BF16X2, SOLVE_REFINE, SOLVE_CCM = 0, 1, 2, 0x100, 0x200
 INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, npad=9, nruns=10,
-            nlayers=11, sf_matrix=12, tune_bm=13, tune_ks=14, tune_grid=15, tune_us=16, group=17)
+            nlayers=11, sf_matrix=12, tune_bm=13, tune_ks=14, tune_grid=15, tune_us=16, group=17,
+            cg_iters=18, cg_resid=19, ell_width=20)
 
 EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
            "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",
            "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_autotune",
-           "cpm_solve_grouped", "cpm_set_charge", "cpm_set_potential_atoms", "cpm_get_info",
+           "cpm_solve_grouped", "cpm_set_charge", "cpm_set_potential_atoms", "cpm_build_operator",
+           "cpm_apply_elastance", "cpm_solve_cg", "cpm_get_info",
            "cpm_enable_timing", "cpm_get_timing",
            "cpm_synchronize", "cpm_last_error", "cpm_destroy")
 
@@ -64,6 +66,9 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_create": ([ctypes.POINTER(CpmParams), vp, ctypes.POINTER(vp)], i),
         "cpm_set_electrolyte": ([vp, i, vp], i),
         "cpm_build_elastance": ([vp, i, vp, vp, i, vp], i),
+        "cpm_build_operator": ([vp, i, vp, vp, i, vp], i),
+        "cpm_solve_cg": ([vp, i, vp, i, d, i, vp, vp], i),
+        "cpm_apply_elastance": ([vp, i, vp, vp], i),
         "cpm_invert": ([vp, u], i),
         "cpm_set_potential": ([vp, vp], i),
         "cpm_potential_vector": ([vp, i, vp, vp, i], i),
@@ -199,6 +204,13 @@ class Context:
 
     def build_elastance(self, xyz, eid, n_e: int, diag_extra=None):
         """xyz: (n, 3) float64 CUDA tensor; eid: (n,) int32 CUDA tensor."""
+        self._build("cpm_build_elastance", xyz, eid, n_e, diag_extra)
+
+    def build_operator(self, xyz, eid, n_e: int, diag_extra=None):
+        """The matrix-free elastance operator (same arguments as build_elastance)."""
+        self._build("cpm_build_operator", xyz, eid, n_e, diag_extra)
+
+    def _build(self, fn, xyz, eid, n_e, diag_extra):
         _expect(xyz, "float64", 2)
         _expect(eid, "int32", 1)
         if xyz.shape[1] != 3 or eid.shape[0] != xyz.shape[0]:
@@ -207,8 +219,8 @@ class Context:
             _expect(diag_extra, "float64", 1)
             if diag_extra.shape[0] != xyz.shape[0]:
                 raise ValueError("diag_extra must be (n,)")
-        self._check(self._lib.cpm_build_elastance(self._h, xyz.shape[0], _ptr(xyz), _ptr(eid), n_e,
-                                                  _ptr(diag_extra)), "cpm_build_elastance")
+        self._check(getattr(self._lib, fn)(self._h, xyz.shape[0], _ptr(xyz), _ptr(eid), n_e,
+                                           _ptr(diag_extra)), fn)
 
     def invert(self, store: int = STORE_F64):
         self._check(self._lib.cpm_invert(self._h, store), "cpm_invert")
@@ -268,6 +280,32 @@ class Context:
         self._check(self._lib.cpm_solve_charges(self._h, b.shape[0], _ptr(b), f32, mode, _ptr(q_out),
                                                 _ptr(Qe_out)), "cpm_solve_charges")
         return q_out
+
+    def apply_elastance(self, x, y_out):
+        """y = A x for x (batch, n) float64 (operator or dense A)."""
+        _expect(x, "float64", 2)
+        _expect(y_out, "float64", 2)
+        if tuple(x.shape) != tuple(y_out.shape) or x.shape[1] != int(self.info("n")):
+            raise ValueError("x and y must both be (batch, n)")
+        self._check(self._lib.cpm_apply_elastance(self._h, x.shape[0], _ptr(x), _ptr(y_out)),
+                    "cpm_apply_elastance")
+        return y_out
+
+    def solve_cg(self, b, q_out, Qe_out=None, tol: float = 1e-13, maxit: int = 1000):
+        """Conjugate-gradient charges: b (batch, n) float64/float32, q_out (batch, n)
+        float64, Qe_out (batch, n_e) or None.  Returns (iterations, residual)."""
+        _expect(q_out, "float64", 2)
+        f32 = _is_f32(b)
+        n, ne = int(self.info("n")), int(self.info("ne"))
+        if n and (b.dim() != 2 or tuple(b.shape) != tuple(q_out.shape) or b.shape[1] != n):
+            raise ValueError(f"b {tuple(b.shape)} and q {tuple(q_out.shape)} must both be (batch, {n})")
+        if Qe_out is not None:
+            _expect(Qe_out, "float64", 2)
+            if tuple(Qe_out.shape) != (b.shape[0], ne):
+                raise ValueError(f"Qe must be (batch, {ne})")
+        self._check(self._lib.cpm_solve_cg(self._h, b.shape[0], _ptr(b), f32, float(tol), int(maxit),
+                                           _ptr(q_out), _ptr(Qe_out)), "cpm_solve_cg")
+        return int(self.info("cg_iters")), self.info("cg_resid")
 
     def autotune(self, batch: int, reps: int = 5) -> dict:
         """Time the split-BF16 batched product's tile shapes for `batch` vectors;
@@ -362,8 +400,9 @@ def _is_f32(t) -> int:
 
 
 def setup(w, store: int = STORE_F64, stream=None, params: Params | None = None,
-          v_electrode=None) -> Context:
-    """Create a context for a generated workload: electrolyte charges, A, S, v."""
+          v_electrode=None, matrix_free: bool = False) -> Context:
+    """Create a context for a generated workload: electrolyte charges, A, S, v
+    (matrix_free: the elastance operator for solve_cg instead of A and S)."""
     import torch
     ctx = Context(params or Params.of(w), stream)
     ctx.set_electrolyte(w.electrolyte_q)
@@ -371,7 +410,10 @@ def setup(w, store: int = STORE_F64, stream=None, params: Params | None = None,
     eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device="cuda").contiguous()
     if stream is not None:      # the copies above ran on torch's current stream
         torch.cuda.current_stream().synchronize()
-    ctx.build_elastance(xyz, eid, int(w.electrode_id.max()) + 1)
-    ctx.invert(store)
+    if matrix_free:
+        ctx.build_operator(xyz, eid, int(w.electrode_id.max()) + 1)
+    else:
+        ctx.build_elastance(xyz, eid, int(w.electrode_id.max()) + 1)
+        ctx.invert(store)
     ctx.set_potential(w.v_electrode if v_electrode is None else v_electrode)
     return ctx

@@ -255,19 +255,21 @@ void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym
                      (size_t)rows * mpad, tab);
 }
 
-// Electrolyte dipole partials of each configuration of a group, per 256
-// charges and axis: dip[((s * blocks + blk) * 3 + d] = sum q_j r_jd (raw
-// coordinates; the dipole corrections of Eqs. 10-12 and 11 use them).
+// Dipole partials of each configuration of a group, per 256 charges and
+// axis: dip[((s * blocks + blk) * 3 + d] = sum q_j r_jd (raw coordinates; the
+// dipole corrections of Eqs. 10-12 and 11 use them).  Positions and charges
+// of configuration s start xyz_stride and q_stride elements apart (0: shared).
 __global__ void __launch_bounds__(256) k_elyt_dipole(int m, const double* __restrict__ xyz,
+                                                     size_t xyz_stride,
                                                      const double* __restrict__ q,
-                                                     double* __restrict__ dip) {
+                                                     size_t q_stride, double* __restrict__ dip) {
   __shared__ double sh[3][4];
   const int j = blockIdx.x * 256 + threadIdx.x, snap = blockIdx.y;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double v[3] = {0.0, 0.0, 0.0};
   if (j < m) {
-    const double* r = xyz + ((size_t)snap * m + j) * 3;
-    const double qq = q[j];
+    const double* r = xyz + snap * xyz_stride + (size_t)j * 3;
+    const double qq = q[snap * q_stride + j];
     v[0] = qq * r[0]; v[1] = qq * r[1]; v[2] = qq * r[2];
   }
 #pragma unroll
@@ -284,7 +286,13 @@ __global__ void __launch_bounds__(256) k_elyt_dipole(int m, const double* __rest
 
 void launch_b_elyt_dipole(hipStream_t st, int g, int m, const double* xyz, const double* q,
                           double* dip) {
-  hipLaunchKernelGGL(k_elyt_dipole, dim3((m + 255) / 256, g), dim3(256), 0, st, m, xyz, q, dip);
+  launch_dipole_partials(st, g, m, xyz, (size_t)m * 3, q, 0, dip);
+}
+
+void launch_dipole_partials(hipStream_t st, int g, int m, const double* xyz, size_t xyz_stride,
+                            const double* q, size_t q_stride, double* dip) {
+  hipLaunchKernelGGL(k_elyt_dipole, dim3((m + 255) / 256, g), dim3(256), 0, st, m, xyz, xyz_stride,
+                     q, q_stride, dip);
 }
 
 // the electrolyte dipole of configuration s from its partials (fixed order)
@@ -875,6 +883,7 @@ __device__ inline double pair_g(const double* __restrict__ T, double r2, double 
 // comes from the LDS pair table, staged once per workgroup.  The next 64
 // charges are loaded while the current ones are summed.
 __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int chunk_size,
+                                                      size_t xyz_stride, size_t q_stride,
                                                       const int* __restrict__ amap, int nmap,
                                                       const double* __restrict__ ex,
                                                       const double* __restrict__ ey,
@@ -916,9 +925,9 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
   auto fetch = [&](int step) {
     const int snap = step / nblk, j = j0 + (step % nblk) * 64 + lane;
     if (j < j1) {
-      const double* r = xyz + ((size_t)snap * m + j) * 3;
+      const double* r = xyz + snap * xyz_stride + (size_t)j * 3;
       px = r[0]; py = r[1]; pzz = r[2];
-      pq = q[j];
+      pq = q[snap * q_stride + j];
     }
   };
   if (steps > 0) fetch(0);
@@ -981,10 +990,18 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
                          int nmap, const double* xyz, const double* q, double Lx, double Ly,
                          double Lz, double rc, double* part) {
+  launch_real_space_pairs(st, g, n, m, rchunks, b, nmap, xyz, (size_t)m * 3, q, 0, Lx, Ly, Lz, rc,
+                          b.rtab, part);
+}
+
+void launch_real_space_pairs(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
+                             int nmap, const double* xyz, size_t xyz_stride, const double* q,
+                             size_t q_stride, double Lx, double Ly, double Lz, double rc,
+                             const double* table, double* part) {
   const int chunk_size = (m + rchunks - 1) / rchunks;
   dim3 grid((nmap + 255) / 256, rchunks), block(256);
-  hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, chunk_size, b.amap, nmap, b.ex,
-                     b.ey, b.ez, xyz, q, Lx, Ly, Lz, rc, b.rtab, part);
+  hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, chunk_size, xyz_stride, q_stride,
+                     b.amap, nmap, b.ex, b.ey, b.ez, xyz, q, Lx, Ly, Lz, rc, table, part);
 }
 
 // b_i = -k_e (sum of k-space partials + sum of real-space partials
@@ -1106,6 +1123,14 @@ void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlay
 }
 
 int layer_combine_max_group() { return LC_MAXG; }
+
+void launch_layer_project_groups(hipStream_t st, int g, int n, int ncolsort, int nlayers,
+                                 int cgroups, const double2* E, const int* layer_of,
+                                 const double2* T, double* part) {
+  const int cpg = (ncolsort + cgroups - 1) / cgroups;
+  hipLaunchKernelGGL(k_layer_project_g, dim3((n + 63) / 64, cgroups), dim3(256), 0, st, g, n,
+                     ncolsort, cpg, nlayers, E, layer_of, T, part);
+}
 
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
                       const double* phir, const Buffers& b, const double* dip, int dip_blocks,

@@ -181,6 +181,29 @@ int sf_chunks_for(const cpm_ctx* c, int g) {
   return (base + step - 1) / step * step;
 }
 
+cpm_status ensure_vat(cpm_ctx* c) {
+  return dalloc(c, &c->b.vat, (size_t)c->npad);
+}
+
+// conjugate-gradient work: x, r, p, Ap for CG_MAXG vectors, block partials,
+// status words; the operator's plane sums and k-space partials
+cpm_status ensure_cg_buffers(cpm_ctx* c) {
+  Buffers& b = c->b;
+  if (b.cgv) return CPM_OK;
+  const int nblk = (c->n + 255) / 256;
+  TRY(dalloc(c, &b.cgv, (size_t)4 * CG_MAXG * c->npad));
+  HIP_TRY(c, hipMemset(b.cgv, 0, (size_t)4 * CG_MAXG * c->npad * sizeof(double)));
+  TRY(dalloc(c, &b.cgred, (size_t)CG_MAXG * nblk * CG_RED));
+  TRY(dalloc(c, &b.cgstat, (size_t)3 * CG_MAXG));
+  if (c->have_op) {
+    TRY(dalloc(c, &b.cgmom, (size_t)CG_MAXG * nblk * 4));
+    TRY(dalloc(c, &b.cgphi, (size_t)c->op_cgroups * CG_MAXG * c->n));
+    TRY(dalloc(c, &b.cgY, (size_t)c->ncolsort * c->nlayers * CG_MAXG));
+    TRY(dalloc(c, &b.cgT, (size_t)c->ncolsort * c->nlayers * CG_MAXG));
+  }
+  return CPM_OK;
+}
+
 cpm_status ensure_step_buffers(cpm_ctx* c) {
   Buffers& b = c->b;
   if (b.sf_part) return CPM_OK;
@@ -489,13 +512,20 @@ cpm_status cpm_set_electrolyte(cpm_ctx* c, int m, const double* h_q) {
   return CPM_OK;
 }
 
-cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
-                               const double* d_diag_extra) {
-  if (!c) return CPM_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// Electrode set-up shared by the dense elastance (dense = true: assemble A)
+// and the matrix-free operator (dense = false: keep what A x needs).
+cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
+                      const double* d_diag_extra, bool dense) {
   if (n <= 0 || n_e <= 0 || !d_xyz || !d_eid)
     return fail(c, CPM_EINVAL, "need n > 0, n_e > 0 and non-NULL coordinates and ids");
-  if (c->have_A && n != c->n)
+  if ((c->have_A || c->have_op) && n != c->n)
     return fail(c, CPM_EINVAL, "rebuild with n = %d differs from n = %d of this context", n, c->n);
+  if ((dense && c->have_op) || (!dense && c->have_A))
+    return fail(c, CPM_ESTATE, "a context holds either the dense elastance or the operator");
   TRY(ensure_uploaded(c));
   c->h_xyz.resize((size_t)3 * n);
   c->h_eid.resize(n);
@@ -518,9 +548,11 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   std::sort(zs.begin(), zs.end());
   zs.erase(std::unique(zs.begin(), zs.end()), zs.end());
   const int nlayers = (int)zs.size() <= MAX_LAYERS ? (int)zs.size() : 0;
-  if (c->have_A && (nlayers != c->nlayers))
+  if ((c->have_A || c->have_op) && (nlayers != c->nlayers))
     return fail(c, CPM_EINVAL, "rebuild changes the electrode plane structure; create a new context");
-  c->have_A = c->have_inv = c->have_v = c->have_q = false;
+  if (!dense && !(nlayers > 0 && c->sf_mfma))
+    return fail(c, CPM_EUNSUPPORTED, "the matrix-free operator needs electrodes on z planes");
+  c->have_A = c->have_op = c->have_inv = c->have_v = c->have_q = false;
   c->nlayers = nlayers;
   c->n = n;
   c->n_e = n_e;
@@ -530,7 +562,7 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   TRY(dalloc(c, &b.ex, n)); TRY(dalloc(c, &b.ey, n)); TRY(dalloc(c, &b.ez, n));
   TRY(dalloc(c, &b.efx, n)); TRY(dalloc(c, &b.efy, n)); TRY(dalloc(c, &b.efz, n));
   TRY(dalloc(c, &b.eid, n));
-  TRY(dalloc(c, &b.A, (size_t)npad * npad));
+  if (dense) TRY(dalloc(c, &b.A, (size_t)npad * npad));
   if (c->nlayers > 0) {
     std::vector<int> lay(n);
     std::vector<double> lfz(c->nlayers);
@@ -583,6 +615,64 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   const double eta_ee = p.eta / std::sqrt(2.0);
   const double diag_self = (std::sqrt(2.0) * p.eta - 2.0 * p.alpha) / std::sqrt(M_PI);
   const double background = -M_PI / (c->V * p.alpha * p.alpha);
+  if (!dense) {
+    // matrix-free A x: plane-pair weights Q, plane offsets in the atom map,
+    // the real-space + self part as a sparse ELL matrix, the diagonal extra
+    TRY(dalloc(c, &b.Qpair, (size_t)c->ncolsort * c->nlayers * c->nlayers));
+    launch_plane_pair_weights(c->stream, c->ncolsort, c->nlayers, b.sc_lo, b.sc_len, b.sc_koff,
+                              b.w2, b.layer_fz, b.Qpair);
+    std::vector<int> poff(c->nlayers + 1, 0);
+    for (int L = 0; L < c->nlayers; ++L) poff[L + 1] = poff[L] + c->h_plane_rows[L];
+    TRY(dalloc(c, &b.plane_off, poff.size()));
+    HIP_TRY(c, hipMemcpy(b.plane_off, poff.data(), poff.size() * sizeof(int), hipMemcpyHostToDevice));
+    {
+      const int jchunks = std::max(1, std::min(64, (n + 1023) / 1024));
+      int* cnt = nullptr;
+      TRY(dalloc(c, &cnt, (size_t)jchunks * n));
+      launch_ell_count(c->stream, n, jchunks, b, p.Lx, p.Ly, c->Lz, p.rcut, cnt);
+      TRY(launched(c, "ell count"));
+      std::vector<int> h_cnt((size_t)jchunks * n);
+      HIP_TRY(c, hipMemcpyAsync(h_cnt.data(), cnt, h_cnt.size() * sizeof(int), hipMemcpyDeviceToHost,
+                                c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      int width = 0;
+      for (int i = 0; i < n; ++i) {              // offsets: chunks of a row in order
+        int o = 0;
+        for (int ch = 0; ch < jchunks; ++ch) {
+          const int k = h_cnt[(size_t)ch * n + i];
+          h_cnt[(size_t)ch * n + i] = o;
+          o += k;
+        }
+        width = std::max(width, o);
+      }
+      HIP_TRY(c, hipMemcpy(cnt, h_cnt.data(), h_cnt.size() * sizeof(int), hipMemcpyHostToDevice));
+      c->ell_width = width;
+      dfree(c, b.ell_col);                        // a rebuild may change the width
+      dfree(c, b.ell_val);
+      TRY(dalloc(c, &b.ell_col, (size_t)width * n));
+      TRY(dalloc(c, &b.ell_val, (size_t)width * n));
+      launch_ell_fill(c->stream, n, jchunks, width, cnt, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha,
+                      eta_ee, diag_self, b.ell_col, b.ell_val);
+      TRY(launched(c, "ell fill"));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      dfree(c, cnt);
+    }
+    {
+      const int atom_blocks = (n + 63) / 64;
+      c->op_cgroups = std::max(1, std::min(c->ncolsort, (1536 + atom_blocks - 1) / atom_blocks));
+    }
+    TRY(dalloc(c, &b.dextra, (size_t)n));
+    if (d_diag_extra)
+      HIP_TRY(c, hipMemcpyAsync(b.dextra, d_diag_extra, (size_t)n * sizeof(double),
+                                hipMemcpyDeviceToDevice, c->stream));
+    else
+      HIP_TRY(c, hipMemsetAsync(b.dextra, 0, (size_t)n * sizeof(double), c->stream));
+    TRY(launched(c, "operator set-up"));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    c->op_background = background;
+    c->have_op = true;
+    return CPM_OK;
+  }
   launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha, eta_ee,
                       diag_self, background, c->cdip, c->ke, d_diag_extra, b.A);
   TRY(launched(c, "real_space_A"));
@@ -628,6 +718,22 @@ cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_A = true;
   return CPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpm_status cpm_build_elastance(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
+                               const double* d_diag_extra) {
+  if (!c) return CPM_EINVAL;
+  return build_impl(c, n, d_xyz, d_eid, n_e, d_diag_extra, true);
+}
+
+cpm_status cpm_build_operator(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
+                              const double* d_diag_extra) {
+  if (!c) return CPM_EINVAL;
+  return build_impl(c, n, d_xyz, d_eid, n_e, d_diag_extra, false);
 }
 
 cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
@@ -722,17 +828,19 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
 
 cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
   if (!c) return CPM_EINVAL;
-  if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_set_potential before cpm_invert");
+  if (!c->have_inv && !c->have_op) return fail(c, CPM_ESTATE, "cpm_set_potential before cpm_invert");
   if (!h_v_electrode) return fail(c, CPM_EINVAL, "h_v_electrode is NULL");
   for (int a = 0; a < c->n_e; ++a)
     if (!std::isfinite(h_v_electrode[a])) return fail(c, CPM_EINVAL, "potential %d not finite", a);
   c->h_v.assign(h_v_electrode, h_v_electrode + c->n_e);
   std::vector<double> vat(c->npad, 0.0);
   for (int i = 0; i < c->n; ++i) vat[i] = c->h_v[c->h_eid[i]];
+  TRY(ensure_vat(c));
   HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  // d = S v  (S G v~ of Eq. 6, cached)
-  launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
-                0.0, c->b.d, c->npad, 0);
+  // d = S v  (S G v~ of Eq. 6, cached; the operator path has no S)
+  if (c->have_inv)
+    launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
+                  0.0, c->b.d, c->npad, 0);
   TRY(launched(c, "set_potential"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_v = true;
@@ -741,16 +849,19 @@ cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
 
 cpm_status cpm_set_potential_atoms(cpm_ctx* c, const double* h_v) {
   if (!c) return CPM_EINVAL;
-  if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_set_potential_atoms before cpm_invert");
+  if (!c->have_inv && !c->have_op)
+    return fail(c, CPM_ESTATE, "cpm_set_potential_atoms before cpm_invert");
   if (!h_v) return fail(c, CPM_EINVAL, "h_v is NULL");
   for (int i = 0; i < c->n; ++i)
     if (!std::isfinite(h_v[i])) return fail(c, CPM_EINVAL, "potential of atom %d not finite", i);
   c->h_v.clear();
   std::vector<double> vat(c->npad, 0.0);
   for (int i = 0; i < c->n; ++i) vat[i] = h_v[i];
+  TRY(ensure_vat(c));
   HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
-                0.0, c->b.d, c->npad, 0);
+  if (c->have_inv)
+    launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
+                  0.0, c->b.d, c->npad, 0);
   TRY(launched(c, "set_potential_atoms"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_v = true;
@@ -763,7 +874,7 @@ namespace {
 
 // validation and (first-use) allocation for cpm_potential_vector
 cpm_status pv_prepare(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32) {
-  if (!c->have_A || !c->have_elyt)
+  if (!(c->have_A || c->have_op) || !c->have_elyt)
     return fail(c, CPM_ESTATE, "cpm_potential_vector needs cpm_set_electrolyte and cpm_build_elastance");
   if (batch <= 0 || !d_b || (c->m > 0 && !d_xyz))
     return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL buffers");
@@ -857,6 +968,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
 // validation and (first-use) allocation for cpm_solve_charges
 cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
                       double* d_q) {
+  if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_invert");
   if (!c->have_v) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_set_potential");
   if (batch <= 0 || !d_b || !d_q) return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL b, q");
   if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
@@ -1251,6 +1363,109 @@ cpm_status cpm_get_timing(cpm_ctx* c, const char* name, double* total_ms, long l
   return CPM_OK;
 }
 
+cpm_status cpm_apply_elastance(cpm_ctx* c, int batch, const double* d_x, double* d_y) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_op && !c->have_A)
+    return fail(c, CPM_ESTATE, "cpm_apply_elastance needs cpm_build_operator or cpm_build_elastance");
+  if (batch < 0 || (batch > 0 && (!d_x || !d_y)))
+    return fail(c, CPM_EINVAL, "need batch >= 0 and non-NULL d_x, d_y");
+  if (batch == 0) return CPM_OK;
+  TRY(ensure_cg_buffers(c));
+  Buffers& b = c->b;
+  hipStream_t st = c->stream;
+  const int n = c->n, ldp = c->npad;
+  double* P = b.cgv + (size_t)2 * CG_MAXG * ldp;
+  double* AP = P + (size_t)CG_MAXG * ldp;
+  for (int v0 = 0; v0 < batch; v0 += CG_MAXG) {
+    const int g = std::min(CG_MAXG, batch - v0);
+    launch_pad_rows(st, n, ldp, g, g, d_x + (size_t)v0 * n, 0, nullptr, P);
+    if (c->have_op)
+      launch_op_apply(c, g, P, AP);
+    else
+      launch_matvec(st, 0, n, ldp, b.A, g, P, 0, ldp, nullptr, nullptr, 0, 0.0, AP, ldp, 0);
+    TRY(launched(c, "apply elastance"));
+    HIP_TRY(c, hipMemcpy2DAsync(d_y + (size_t)v0 * n, (size_t)n * sizeof(double), AP,
+                                (size_t)ldp * sizeof(double), (size_t)n * sizeof(double), g,
+                                hipMemcpyDeviceToDevice, st));
+  }
+  return CPM_OK;
+}
+
+cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, double tol,
+                        int maxit, double* d_q, double* d_Qe) {
+  if (!c) return CPM_EINVAL;
+  if (!c->have_op && !c->have_A)
+    return fail(c, CPM_ESTATE, "cpm_solve_cg needs cpm_build_operator or cpm_build_elastance");
+  if (!c->have_v) return fail(c, CPM_ESTATE, "cpm_solve_cg before cpm_set_potential");
+  if (batch < 0 || (batch > 0 && (!d_b || !d_q)))
+    return fail(c, CPM_EINVAL, "need batch >= 0 and non-NULL d_b, d_q");
+  if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
+  if (!std::isfinite(tol) || tol < 0.0 || maxit < 1)
+    return fail(c, CPM_EINVAL, "need a finite tol >= 0 and maxit >= 1");
+  c->cg_iters = 0;
+  c->cg_resid = 0.0;
+  if (batch == 0) return CPM_OK;
+  TRY(ensure_cg_buffers(c));
+  Buffers& b = c->b;
+  hipStream_t st = c->stream;
+  const int n = c->n, ldp = c->npad;
+  double* X = b.cgv;
+  double* R = X + (size_t)CG_MAXG * ldp;
+  double* P = R + (size_t)CG_MAXG * ldp;
+  double* AP = P + (size_t)CG_MAXG * ldp;
+  const double tol2 = tol * tol;
+  const size_t bsz = b_is_f32 ? sizeof(float) : sizeof(double);
+  std::vector<double> h_stat(3 * CG_MAXG);
+  bool all_conv = true;
+  for (int v0 = 0; v0 < batch; v0 += CG_MAXG) {
+    const int g = std::min(CG_MAXG, batch - v0);
+    const void* bsrc = static_cast<const char*>(d_b) + (size_t)v0 * n * bsz;
+    launch_cg_init(st, g, n, ldp, bsrc, b_is_f32, b.vat, b.cgred, X, R, P, b.cgstat);
+    TRY(launched(c, "cg init"));
+    int it = 0;
+    bool conv = false;
+    while (it < maxit && !conv) {
+      // a block of iterations between convergence checks; vectors below the
+      // tolerance are frozen by the update kernel
+      const int blk = std::min(8, maxit - it);
+      for (int k = 0; k < blk; ++k, ++it) {
+        const int cur = it & 1;
+        if (c->have_op) {
+          launch_op_apply(c, g, P, AP);
+        } else {
+          launch_matvec(st, 0, n, ldp, b.A, g, P, 0, ldp, nullptr, nullptr, 0, 0.0, AP, ldp, 0);
+          launch_cg_dots(st, g, n, ldp, P, AP, b.cgred);
+        }
+        launch_cg_update(st, g, n, ldp, cur, tol2, b.cgred, X, R, P, AP, b.cgstat);
+        launch_cg_dir(st, g, n, ldp, cur, tol2, b.cgred, R, P);
+      }
+      TRY(launched(c, "cg iterations"));
+      launch_cg_status(st, g, n, it & 1, b.cgred, b.cgstat);
+      HIP_TRY(c, hipMemcpyAsync(h_stat.data(), b.cgstat, (size_t)3 * g * sizeof(double),
+                                hipMemcpyDeviceToHost, st));
+      HIP_TRY(c, hipStreamSynchronize(st));
+      conv = true;
+      for (int s = 0; s < g; ++s)
+        if (!(h_stat[3 * s] <= tol2 * h_stat[3 * s + 1])) conv = false;
+    }
+    for (int s = 0; s < g; ++s) {
+      c->cg_iters = std::max(c->cg_iters, (int)h_stat[3 * s + 2]);
+      const double rel = h_stat[3 * s + 1] > 0.0 ? std::sqrt(h_stat[3 * s] / h_stat[3 * s + 1])
+                                                 : (h_stat[3 * s] > 0.0 ? INFINITY : 0.0);
+      c->cg_resid = std::max(c->cg_resid, std::isnan(rel) ? INFINITY : rel);
+    }
+    all_conv = all_conv && conv;
+    launch_cg_finish(st, g, n, ldp, X, b.cgred, b.eid, c->n_e, d_q + (size_t)v0 * n,
+                     d_Qe ? d_Qe + (size_t)v0 * c->n_e : nullptr);
+    TRY(launched(c, "cg finish"));
+  }
+  HIP_TRY(c, hipStreamSynchronize(st));
+  if (!all_conv)
+    return fail(c, CPM_ENOCONV, "conjugate gradients stopped at %d iterations with relative residual %g > %g",
+                maxit, c->cg_resid, tol);
+  return CPM_OK;
+}
+
 cpm_status cpm_copy_matrix(const cpm_ctx* c, int which, double* d_out) {
   if (!c || !d_out) return CPM_EINVAL;
   const double* src = nullptr;
@@ -1269,7 +1484,7 @@ cpm_status cpm_copy_vector(const cpm_ctx* c, int which, double* d_out) {
   if (!c || !d_out) return CPM_EINVAL;
   const double* src = nullptr;
   if (which == 0 && c->have_inv) src = c->b.u;
-  if (which == 1 && c->have_v) src = c->b.d;
+  if (which == 1 && c->have_v && c->have_inv) src = c->b.d;
   if (!src) return CPM_ESTATE;
   if (hipMemcpyAsync(d_out, src, c->n * sizeof(double), hipMemcpyDeviceToDevice, c->stream) != hipSuccess)
     return CPM_EHIP;
@@ -1297,6 +1512,9 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_TUNE_GRID: *out = c->last_tune.grid; return CPM_OK;
     case CPM_INFO_TUNE_US: *out = c->last_tune.us; return CPM_OK;
     case CPM_INFO_GROUP: *out = c->pv_group; return CPM_OK;
+    case CPM_INFO_CG_ITERS: *out = c->cg_iters; return CPM_OK;
+    case CPM_INFO_CG_RESID: *out = c->cg_resid; return CPM_OK;
+    case CPM_INFO_ELL_WIDTH: *out = c->ell_width; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -1327,6 +1545,9 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.dip); dfree(b.qt);
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
+  dfree(b.Qpair); dfree(b.ell_col); dfree(b.ell_val); dfree(b.plane_off); dfree(b.dextra);
+  dfree(b.cgv); dfree(b.cgred); dfree(b.cgstat); dfree(b.cgphi); dfree(b.cgmom); dfree(b.cgY);
+  dfree(b.cgT);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

@@ -45,6 +45,8 @@ constexpr int RS_NT = 2048;        // intervals of the real-space pair table on 
 
 constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
 constexpr int MAX_LAYERS = 64;     // planar-electrode factorisation up to this many z planes
+constexpr int CG_MAXG = 32;        // vectors per conjugate-gradient group
+constexpr int CG_RED = 6;          // block partials per vector and block
 
 struct Buffers {
   // electrode geometry (internal order = caller order), SoA, x and y wrapped
@@ -101,10 +103,46 @@ struct Buffers {
   double* kpart = nullptr;         // split-K partial slices of the batched split-BF16 GEMM
   double* ccmU = nullptr;          // constrained charges: U = A^-1 G (n x n_e)
   double* ccmC = nullptr;          // C~^-1 (n_e x n_e) followed by the targets Q (n_e)
+  // matrix-free operator and conjugate gradients
+  double2* Qpair = nullptr;        // Q_c(L, L') per sorted column, [(c nL + L) nL + L']
+  int* ell_col = nullptr;          // real-space + self part of A in ELL form, [k * n + i]
+  double* ell_val = nullptr;
+  int* plane_off = nullptr;        // nlayers + 1 offsets of the planes in amap
+  double* dextra = nullptr;        // diagonal extra (n)
+  double* cgv = nullptr;           // x, r, p, Ap (4 x CG_MAXG x npad)
+  double* cgred = nullptr;         // block partials (CG_MAXG x blocks x CG_RED)
+  double* cgstat = nullptr;        // per vector: r.r, r0.r0, iterations
+  double* cgphi = nullptr;         // column-group partial k-space potentials
+  double* cgmom = nullptr;         // partials of sum p, sum p x, sum p y, sum p z
+  double2* cgY = nullptr;          // plane sums Y(c, L)
+  double2* cgT = nullptr;          // T(c, L)
   size_t kpart_len = 0;
   int bpad_rows = 0;
   double* scal = nullptr;          // small scalars (s and friends)
 };
+
+// matrix-free operator and conjugate gradients (cg.hip)
+// real-space + self part of A in ELL form: count per (j chunk, atom)
+// cnt[chunk * n + i], then fill from offsets off[chunk * n + i] (entries of a
+// row in ascending j; padding col = i, val = 0)
+void launch_ell_count(hipStream_t st, int n, int jchunks, const Buffers& b, double Lx, double Ly,
+                      double Lz, double rc, int* cnt);
+void launch_ell_fill(hipStream_t st, int n, int jchunks, int width, const int* off,
+                     const Buffers& b, double Lx, double Ly, double Lz, double rc, double alpha,
+                     double eta_ee, double diag_self, int* col, double* val);
+void launch_op_apply(cpm_ctx* c, int g, const double* P, double* AP);
+void launch_cg_dots(hipStream_t st, int g, int n, int ldp, const double* P, const double* AP,
+                    double* red);
+void launch_cg_init(hipStream_t st, int g, int n, int ldp, const void* b, int b_is_f32,
+                    const double* vat, double* red, double* X, double* R, double* P, double* stat);
+void launch_cg_update(hipStream_t st, int g, int n, int ldp, int cur, double tol2,
+                      double* red, double* X, double* R, const double* P, const double* AP,
+                      double* stat);
+void launch_cg_dir(hipStream_t st, int g, int n, int ldp, int cur, double tol2, const double* red,
+                   const double* R, double* P);
+void launch_cg_status(hipStream_t st, int g, int n, int cur, const double* red, double* stat);
+void launch_cg_finish(hipStream_t st, int g, int n, int ldp, const double* X, double* red,
+                      const int* eid, int n_e, double* q, double* Qe);
 
 }  // namespace cpm
 
@@ -113,6 +151,12 @@ struct cpm_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool have_elyt = false, have_A = false, have_inv = false, have_v = false, have_q = false;
+  bool have_op = false;            // matrix-free operator (cpm_build_operator)
+  double op_background = 0.0;      // -pi / (V alpha^2)
+  int cg_iters = 0;                // last cpm_solve_cg: iterations, max relative residual
+  double cg_resid = 0.0;
+  int ell_width = 0;               // entries per row of the real-space ELL part
+  int op_cgroups = 1;              // column groups of the operator's k-space projection
   int n = 0, npad = 0, n_e = 0, m = 0;
   double Lz = 0, V = 0, kc = 0, ke = 0;
   double cdip[3] = {0, 0, 0};      // dipole term A += k_e sum_d cdip_d r_d r_d^T (geometry)
@@ -261,6 +305,12 @@ void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym
                         double2* tab);
 void launch_b_elyt_dipole(hipStream_t st, int g, int m, const double* xyz, const double* q,
                           double* dip);
+void launch_dipole_partials(hipStream_t st, int g, int m, const double* xyz, size_t xyz_stride,
+                            const double* q, size_t q_stride, double* dip);
+void launch_real_space_pairs(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
+                             int nmap, const double* xyz, size_t xyz_stride, const double* q,
+                             size_t q_stride, double Lx, double Ly, double Lz, double rc,
+                             const double* table, double* part);
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
@@ -283,6 +333,11 @@ void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlay
                             const double* dip, int dip_blocks, const double* cdip, double ke,
                             void* out, int out_is_f32);
 int layer_combine_max_group();
+// k-space potentials of g configurations from T(c, L) only (no final sum):
+// part[(cg * g + s) * n + i]
+void launch_layer_project_groups(hipStream_t st, int g, int n, int ncolsort, int nlayers,
+                                 int cgroups, const double2* E, const int* layer_of,
+                                 const double2* T, double* part);
 int sf_table_rows(int nxm, int nym, int nbz);
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
                         const double* w2, double* sfw);

@@ -79,6 +79,9 @@ def test_null_arguments():
     assert L.cpm_set_charge(None, None) == cpm.EINVAL
     assert L.cpm_set_potential_atoms(None, None) == cpm.EINVAL
     assert L.cpm_solve_grouped(None, 1, None, None, 0, 0x102, None, None) == cpm.EINVAL
+    assert L.cpm_build_operator(None, 1, None, None, 1, None) == cpm.EINVAL
+    assert L.cpm_apply_elastance(None, 1, None, None) == cpm.EINVAL
+    assert L.cpm_solve_cg(None, 1, None, 0, 1e-12, 10, None, None) == cpm.EINVAL
     assert L.cpm_last_error(None) == b"no context"
     L.cpm_destroy(None)
 
