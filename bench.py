@@ -87,7 +87,7 @@ def main():
         out["workload_20064"] = {k: r[k] for k in ("value", "ms_per_step", "config", "roofline",
                                                    "phase_s", "solve_only_rate",
                                                    "plain_fp64_per_step_rate", "matvec_roofline",
-                                                   "max_abs_sum_q")}
+                                                   "conjugate_gradient", "max_abs_sum_q")}
     if not args.no_cpu_baseline and w.n < 10000:
         out["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(out), flush=True)
@@ -200,6 +200,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     plain_rate = n_plain / (time.perf_counter() - ts)
 
     matvec = matvec_roofline(ctx, w, xyz, dev)
+    cg = cg_measure(w, xyz, dev, ctx)
 
     # dominant kernel: the structure factors
     nk = int(ctx.info("nk"))
@@ -248,6 +249,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
         "plain_fp64_sample": f"{n_plain} snapshots, b + FP64 matvec solve one at a time, setup excluded",
         "kernel_ms_per_step": {f: v[0] for f, v in timing.items() if v[1]},
         "matvec_roofline": matvec,
+        "conjugate_gradient": cg,
         "autotune": tune,
         "max_abs_sum_q": qsum,
     }
@@ -347,6 +349,90 @@ def matvec_roofline(ctx, w, xyz, dev, reps=20):
                     "avg_launch_us": avg * 1e6}
     out["note"] = ("S held across back-to-back solves; below 256 MB (N < ~5800 in FP64) it can "
                    "stay in the last-level cache, so N = 20064 is the HBM figure")
+    return out
+
+
+CG_FAMILIES = ("cg_plane_sums", "cg_plane_mix", "cg_project", "cg_apply", "cg_update", "cg_dir",
+               "cg_init", "cg_finish")
+
+
+def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
+    """The matrix-free conjugate-gradient solve on the same workload: operator
+    set-up, then B = 64 configurations (one CG group) solved to |r| <= tol |r0|
+    per call.  Reports solves/s, iterations, the per-iteration kernel split
+    with each family's algorithmic HBM bytes (and FP64 flops for the two
+    matrix-core products), and the largest deviation from the direct FP64
+    solve q = S (b + v) of ctx_direct on the same b."""
+    import numpy as np
+    import torch
+    from paper_2203_15461_amd import cpm
+    n = w.n
+    B = min(B, xyz.shape[0])
+    ctx = cpm.Context(cpm.Params.of(w))
+    ctx.set_electrolyte(w.electrolyte_q)
+    R = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device=dev).contiguous()
+    eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device=dev).contiguous()
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    ctx.build_operator(R, eid, 2)
+    ctx.set_potential(w.v_electrode)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - ts
+    b = torch.empty((B, n), dtype=torch.float64, device=dev)
+    ctx.potential_vector(xyz[:B], b)
+    q = torch.empty_like(b)
+    Qe = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    iters, resid = ctx.solve_cg(b, q, Qe, tol=tol)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for _ in range(reps):
+        ctx.solve_cg(b, q, Qe, tol=tol)
+    torch.cuda.synchronize()
+    call_s = (time.perf_counter() - ts) / reps
+    ctx.enable_timing(True)
+    ctx.solve_cg(b, q, Qe, tol=tol)
+    fam = {f: ctx.timing(f) for f in CG_FAMILIES}
+    ctx.enable_timing(False)
+    qd = torch.empty_like(b)
+    ctx_direct.solve_charges(b, 0x000, qd)
+    torch.cuda.synchronize()
+    dev_rel = float(((q - qd).abs().max() / qd.abs().max()).item())
+    nc, nl, width = int(ctx.info("ncols")), int(ctx.info("nlayers")), int(ctx.info("ell_width"))
+    m2 = 2 * ((nc + 31) // 32 * 32)                  # rows of the phase matrix
+    nslot = int(sum(-(-c // 64) * 64 for c in np.bincount(
+        np.searchsorted(np.unique(w.electrode_xyz[:, 2]), w.electrode_xyz[:, 2]))))
+    vec = nslot * 64 * 8                             # one slot-major block of 64 vectors
+    work = {   # (algorithmic HBM bytes, FP64 flops) per launch
+        "cg_plane_sums": (m2 * nslot * 8 + vec + nl * m2 * 64 * 8, 2.0 * m2 * nslot * 64),
+        "cg_project": (m2 * nslot * 8 + nl * m2 * 64 * 8 + vec, 2.0 * m2 * nslot * 64),
+        "cg_apply": (width * nslot * 12 + 3 * vec, 2.0 * width * nslot * 64),
+        "cg_update": (6 * vec, 0.0),
+        "cg_dir": (3 * vec, 0.0),
+    }
+    per_iter = {}
+    for f, (ms, cnt) in fam.items():
+        if not cnt:
+            continue
+        us = ms / cnt * 1e3
+        e = {"us": us, "launches": cnt}
+        if f in work:
+            by, fl = work[f]
+            e["bytes"] = by
+            e["hbm_frac"] = by / (us * 1e-6) / PEAK_HBM
+            if fl:
+                e["tflops"] = fl / (us * 1e-6) / 1e12
+                e["fp64_frac"] = fl / (us * 1e-6) / PEAK_FP64_VALU
+        per_iter[f] = e
+    dom = max(per_iter, key=lambda f: per_iter[f]["us"] * per_iter[f]["launches"])
+    out = {"solves_per_s": B / call_s, "ms_per_call": call_s * 1e3, "vectors_per_call": B,
+           "tol": tol, "iterations": iters, "residual": resid, "operator_setup_s": setup_s,
+           "ell_width": width, "columns": nc, "planes": nl, "slots": nslot,
+           "max_rel_diff_vs_direct_fp64": dev_rel,
+           "max_abs_sum_q": float(q.sum(dim=1).abs().max().item()),
+           "per_launch": per_iter, "dominant": dom,
+           "workspace_bytes": ctx.info("workspace"),
+           "note": "b computed once outside the timed calls; each call starts from q = 0"}
+    ctx.close()
     return out
 
 

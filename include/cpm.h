@@ -105,8 +105,9 @@ enum {
                               /* cpm_potential_vector (planar electrodes)         */
   CPM_INFO_CG_ITERS = 18,     /* last cpm_solve_cg: most iterations of a vector   */
   CPM_INFO_CG_RESID = 19,     /*   ... largest final |r| / |r0|                   */
-  CPM_INFO_ELL_WIDTH = 20     /* entries per row of the operator's real-space     */
+  CPM_INFO_ELL_WIDTH = 20,    /* entries per row of the operator's real-space     */
                               /* part (cpm_build_operator)                        */
+  CPM_INFO_NCOLS = 21         /* (k_x, k_y) columns of the matrix-core k set      */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the

@@ -1124,14 +1124,6 @@ void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlay
 
 int layer_combine_max_group() { return LC_MAXG; }
 
-void launch_layer_project_groups(hipStream_t st, int g, int n, int ncolsort, int nlayers,
-                                 int cgroups, const double2* E, const int* layer_of,
-                                 const double2* T, double* part) {
-  const int cpg = (ncolsort + cgroups - 1) / cgroups;
-  hipLaunchKernelGGL(k_layer_project_g, dim3((n + 63) / 64, cgroups), dim3(256), 0, st, g, n,
-                     ncolsort, cpg, nlayers, E, layer_of, T, part);
-}
-
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
                       const double* phir, const Buffers& b, const double* dip, int dip_blocks,
                       const double* cdip, double ke, void* out, int out_is_f32) {

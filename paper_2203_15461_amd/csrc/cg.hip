@@ -4,8 +4,7 @@
 // (Sec. II.A; the conjugate-gradient route it names as the alternative to
 // inverting A): q solves A q = b + v + mu e with e^T q = 0.  Conjugate
 // gradients on the neutral subspace (projector P = I - e e^T / n) need only
-// products A p, never A^-1 or S, so the memory stays O(n) per vector plus the
-// fixed electrode tables:
+// products A p, never A^-1 or S:
 //   * real space + Gaussian self term: a fixed sparse matrix (every pair with
 //     some periodic image within r_c), kept in ELL form and evaluated with the
 //     same expression as the dense assembly;
@@ -13,50 +12,101 @@
 //     and Q_c(L, L') = sum_n 2W(c, n) e^{i n kz1 (z_L - z_L')},
 //       (A_k p)_i = k_e sum_c Re[conj(E_i(c)) T(c, L_i)],
 //       T(c, L) = sum_L' Q_c(L', L) Y(c, L'),  Y(c, L') = sum_{j in L'} E_j(c) p_j,
-//     (the planar regrouping of A's k-space term, applied to a vector);
+//     the planar regrouping of A's k-space term applied to vectors: Y and the
+//     projection are FP64 matrix-core products (K = the atoms of a plane, and
+//     K = 2 x columns), T a small per-column mixing of the planes;
 //   * background -pi/(V alpha^2) (sum p) and the geometry's dipole term
 //     sum_d c_d r_id (sum_j r_jd p_j) from four moments of p;
 //   * the optional per-atom diagonal.
-// Every reduction runs in a fixed order (block partials summed in block
-// order), so results do not depend on scheduling.
+//
+// Layout: vectors are slot-major, V[slot * 64 + s] for up to 64 right-hand
+// sides s, slots in the order of the atom map (the atoms of each z plane fill
+// whole 64-slot tiles, -1 pads; for the dense A, slots are the atoms in
+// caller order padded to a multiple of 64).  A wave owns one slot row at a
+// time, lane s its vector s, so per-vector sums need no cross-lane
+// reductions.  Every reduction runs in a fixed order and without
+// inter-block communication inside a kernel: each block writes partials, and
+// every block of the next kernel adds them in the same order (so all derive
+// identical CG scalars).
+#include <algorithm>
+
 #include "cpm_internal.h"
 
 namespace cpm {
 
 namespace {
 
-constexpr int CG_BLK = 256;
-// block partial fields: p.Ap, sum Ap, r.r (two slots, alternating), r0.r0, sum
-constexpr int F_PAP = 0, F_SAP = 1, F_RR = 2, F_RRI = 4, F_SUM = 5;
-static_assert(F_SUM < CG_RED, "partial fields");
+constexpr int VL = CG_MAXG;        // vectors per slot row
+constexpr int CG_WAVES = 16;       // waves per block of the vector kernels
+constexpr int CG_BLK = 64 * CG_WAVES;
 
-inline int cg_blocks(int n) { return (n + CG_BLK - 1) / CG_BLK; }
+// per-vector scalars for the host, scal[row * VL + s] (written by block 0)
+enum { S_RR = 0, S_RR0, S_ITERS };
+// block partial fields, red[(blk * CG_RED + f) * VL + s]; r.r alternates
+// between two fields by iteration parity
+enum { F_PAP = 0, F_SAP, F_RR, F_RRB, F_RRI, F_SUM, F_M0 };   // F_M0..F_M0+3: moments
+static_assert(F_M0 + 3 < CG_RED, "partial fields");
+static_assert(S_ITERS < CG_NSCAL, "scalar rows");
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// this wave's rows: r = (blk + t nblk) * CG_WAVES + wave, t = 0, 1, ...
+struct Rows {
+  int r, step;
+  __device__ Rows() {
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+    r = blockIdx.x * CG_WAVES + w;
+    step = CG_WAVES * gridDim.x;
+  }
+};
+
+// sum of 16 wave values per lane, sh[w][s] (w = 0..15), as a fixed tree
+__device__ inline double sum16(const double (*sh)[VL], int s) {
+  double a[8];
+#pragma unroll
+  for (int w = 0; w < 8; ++w) a[w] = sh[2 * w][s] + sh[2 * w + 1][s];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
 }
 
-// Block sums over 256 threads: park() leaves each wave's sum of v in
-// sh[slot][wave]; after a barrier, parked(slot) = (w0 + w1) + (w2 + w3).
-// Deterministic (lane 0's butterfly order, fixed wave order).
-__device__ inline void park(double v, int slot, double (*sh)[4]) {
-  const double t = wave_sum(v);
-  if ((threadIdx.x & 63) == 0) sh[slot][threadIdx.x >> 6] = t;
+// add the 16 waves' per-lane values v[0..NF) of this block and store them as
+// block partials of fields f[0..NF) (threads 0..63)
+template <int NF>
+__device__ void store_partials(const double (&v)[NF], const int (&f)[NF],
+                               double* __restrict__ red) {
+  __shared__ double sh[NF][CG_WAVES][VL];
+  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) sh[k][w][s] = v[k];
+  __syncthreads();
+  if (threadIdx.x < VL) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) red[((size_t)blockIdx.x * CG_RED + f[k]) * VL + s] = sum16(sh[k], s);
+  }
 }
 
-__device__ inline double parked(int slot, const double (*sh)[4]) {
-  return (sh[slot][0] + sh[slot][1]) + (sh[slot][2] + sh[slot][3]);
+// Totals over the nprod blocks of the producing kernel of fields f[0..NF),
+// computed by every block of the consuming kernel in the same fixed order
+// (wave w adds blocks w, w + 16, ..., then a fixed tree over the waves), so
+// all blocks see identical values without any inter-block communication.
+// out[k][s] is valid for all threads after the call.
+template <int NF>
+__device__ void block_totals(const double* __restrict__ red, int nprod, const int (&f)[NF],
+                             double (*out)[VL]) {
+  __shared__ double sh[NF][CG_WAVES][VL];
+  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    double a = 0.0;
+    for (int b = w; b < nprod; b += CG_WAVES) a += red[((size_t)b * CG_RED + f[k]) * VL + s];
+    sh[k][w][s] = a;
+  }
+  __syncthreads();
+  if (threadIdx.x < VL) {
+#pragma unroll
+    for (int k = 0; k < NF; ++k) out[k][s] = sum16(sh[k], s);
+  }
+  __syncthreads();
 }
 
-// sum over the blocks of vector s of partial field f (block order)
-__device__ inline double sum_partials(const double* __restrict__ red, int nblk, int s, int f) {
-  double a = 0.0;
-  for (int k = 0; k < nblk; ++k) a += red[((size_t)s * nblk + k) * CG_RED + f];
-  return a;
-}
-
-// ---- real-space + self part of A in ELL form ----------------------------------
+// ---- real-space + self part of A in ELL form (slot space) -----------------
 // The periodic-image sum of one electrode pair, written as in the dense
 // assembly: every image with 0 < r < r_c, erfc(eta_ee r) dropped once it is
 // below FP64 rounding of the difference.  Returns the number of images
@@ -97,12 +147,14 @@ __device__ inline int pair_images(double dx, double dy, double dz, double Lx, do
   return cnt;
 }
 
-// One pass over the j chunk of row i.  FILL = false counts the entries
-// (cnt[chunk n + i]); FILL = true writes them from off[chunk n + i] on, never
-// past kend (the next chunk's offset, or the width for the last chunk).  Both
-// passes run this same code, so they take the same in-range decisions.
+// One pass over the slot chunk of row r.  FILL = false counts the entries
+// (cnt[chunk nslot + r]); FILL = true writes them (row-major, r * width + k)
+// from offset cnt[chunk nslot + r] on, never past kend (the next chunk's
+// offset, or the width for the last chunk).  Both passes run this same code,
+// so they take the same in-range decisions.
 template <bool FILL>
-__global__ void __launch_bounds__(256) k_ell_pass(int n, int chunk, int width,
+__global__ void __launch_bounds__(256) k_ell_pass(int nslot, int chunk, int width,
+                                                  const int* __restrict__ slot_atom,
                                                   const double* __restrict__ ex,
                                                   const double* __restrict__ ey,
                                                   const double* __restrict__ ez, double Lx,
@@ -110,187 +162,317 @@ __global__ void __launch_bounds__(256) k_ell_pass(int n, int chunk, int width,
                                                   double eta_ee, double diag_self,
                                                   int* __restrict__ cnt, int* __restrict__ col,
                                                   double* __restrict__ val) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, ch = blockIdx.y;
-  if (i >= n) return;
-  const int j0 = ch * chunk, j1 = min(n, j0 + chunk);
-  const double xi = ex[i], yi = ey[i], zi = ez[i];
-  size_t k = FILL ? (size_t)cnt[(size_t)ch * n + i] : 0;
-  const size_t kend = FILL ? (ch + 1 < (int)gridDim.y ? (size_t)cnt[(size_t)(ch + 1) * n + i]
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, ch = blockIdx.y;
+  if (r >= nslot) return;
+  const int i = slot_atom[r];
+  size_t k = FILL ? (size_t)cnt[(size_t)ch * nslot + r] : 0;
+  const size_t kend = FILL ? (ch + 1 < (int)gridDim.y ? (size_t)cnt[(size_t)(ch + 1) * nslot + r]
                                                       : (size_t)width)
                            : 0;
-  for (int j = j0; j < j1; ++j) {
-    double s;
-    const int c = pair_images(xi - ex[j], yi - ey[j], zi - ez[j], Lx, Ly, Lz, rc, alpha, eta_ee, &s);
-    if (j == i || c > 0) {
-      if (FILL && k < kend) {
-        col[k * n + i] = j;
-        val[k * n + i] = (j == i) ? s + diag_self : s;
+  if (i >= 0) {
+    const int j0 = ch * chunk, j1 = min(nslot, j0 + chunk);
+    const double xi = ex[i], yi = ey[i], zi = ez[i];
+    for (int t = j0; t < j1; ++t) {
+      const int j = slot_atom[t];
+      if (j < 0) continue;
+      double s;
+      const int c = pair_images(xi - ex[j], yi - ey[j], zi - ez[j], Lx, Ly, Lz, rc, alpha, eta_ee, &s);
+      if (j == i || c > 0) {
+        if (FILL && k < kend) {
+          col[(size_t)r * width + k] = t;
+          val[(size_t)r * width + k] = (j == i) ? s + diag_self : s;
+        }
+        ++k;
       }
-      ++k;
     }
   }
-  if (!FILL) cnt[(size_t)ch * n + i] = (int)k;
+  if (!FILL) cnt[(size_t)ch * nslot + r] = (int)k;
 }
 
-__global__ void k_ell_init(int n, size_t total, int* __restrict__ col, double* __restrict__ val) {
+// padding entries: column = own slot, value 0
+__global__ void k_ell_init(int width, size_t total, int* __restrict__ col,
+                           double* __restrict__ val) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
-  col[e] = (int)(e % n);
+  col[e] = (int)(e / width);
   val[e] = 0.0;
 }
 
-// ---- k-space part: plane sums, plane mixing -----------------------------------
-// Y[(c nL + L) g + s] = sum over the atoms j of plane L of E_j(c) p_s[j].  One
-// wave per (column, plane); the plane's atoms are the slots
-// [plane_off[L], plane_off[L + 1]) of the atom map (-1 pads).
-__global__ void __launch_bounds__(64) k_op_plane_sums(int g, int n, int nlayers,
-                                                      const int* __restrict__ plane_off,
-                                                      const int* __restrict__ amap,
-                                                      const double2* __restrict__ E,
-                                                      const double* __restrict__ P, int ldp,
-                                                      double2* __restrict__ Y) {
-  const int c = blockIdx.x, L = blockIdx.y, lane = threadIdx.x;
-  double ar[CG_MAXG], ai[CG_MAXG];
-#pragma unroll
-  for (int s = 0; s < CG_MAXG; ++s) { ar[s] = 0.0; ai[s] = 0.0; }
-  const double2* Ec = E + (size_t)c * n;
-  for (int t = plane_off[L] + lane; t < plane_off[L + 1]; t += 64) {
-    const int j = amap[t];
-    if (j < 0) continue;
-    const double2 e = Ec[j];
-#pragma unroll
-    for (int s = 0; s < CG_MAXG; ++s)
-      if (s < g) {
-        const double pv = P[(size_t)s * ldp + j];
-        ar[s] += e.x * pv;
-        ai[s] += e.y * pv;
-      }
+// In-plane phases in slot order as a real matrix: Ecat[(2c) nslot + slot] =
+// cos th, Ecat[(2c + 1) nslot + slot] = sin th, th = kx x + ky y of column c;
+// zero for pad slots and for padding columns c >= ncolsort.
+__global__ void k_cg_ephase(int nslot, int ncolsort, const int* __restrict__ slot_atom,
+                            const int* __restrict__ sc_nx, const int* __restrict__ sc_ny,
+                            const double* __restrict__ fx, const double* __restrict__ fy,
+                            double* __restrict__ Ecat) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
+  if (r >= nslot) return;
+  const int i = slot_atom[r];
+  double cs = 0.0, sn = 0.0;
+  if (i >= 0 && c < ncolsort) {
+    double th = sc_nx[c] * fx[i] + sc_ny[c] * fy[i];
+    th -= rint(th);
+    sincospi(2.0 * th, &sn, &cs);
   }
-  double2* y = Y + ((size_t)c * nlayers + L) * g;
-#pragma unroll
-  for (int s = 0; s < CG_MAXG; ++s)
-    if (s < g) {
-      const double r = wave_sum(ar[s]), im = wave_sum(ai[s]);
-      if (lane == 0) y[s] = make_double2(r, im);
-    }
+  Ecat[(size_t)(2 * c) * nslot + r] = cs;
+  Ecat[(size_t)(2 * c + 1) * nslot + r] = sn;
 }
 
-// T[(c nL + L) g + s] = sum_L' Q_c(L', L) Y[(c nL + L') g + s]
-__global__ void k_op_plane_mix(int g, int nlayers, int ncolsort, const double2* __restrict__ Q,
-                               const double2* __restrict__ Y, double2* __restrict__ T) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ncolsort * nlayers * g) return;
-  const int s = e % g, L = (e / g) % nlayers, c = e / (g * nlayers);
+// ---- k space on matrix cores -------------------------------------------------
+// 64 x 64 output tile per 256-thread workgroup (rows m, vectors s), 4 waves in
+// 2 x 2 quadrants of 2 x 2 v_mfma_f64_16x16x4f64 blocks, K staged through LDS
+// in slabs of 16 with the next slab held in registers.
+//   PROJ = false (plane sums): tile (m0 = 64 bx, plane L = by); K = the slots
+//     of plane L; A(m, k) = Ecat[m nslot + k], B(k, s) = P[k VL + s];
+//     Y[(L M2 + m) VL + s] = sum_k A B.
+//   PROJ = true (projection): slot tile m0 = 64 bx lies in plane L =
+//     tile_plane[bx]; K = M2; A(m, k) = Ecat[k nslot + m], B(k, s) =
+//     T[(L M2 + k) VL + s];  Phi[m VL + s] = sum_k A B.
+// MFMA operand layout (lane l): A (row l % 16, k l / 16), B (k l / 16,
+// col l % 16); result register q: (row l / 16 + 4 q, col l % 16).
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+template <bool PROJ>
+__global__ void __launch_bounds__(256) k_cg_kgemm(int nslot, int M2,
+                                                  const int* __restrict__ plane_off,
+                                                  const int* __restrict__ tile_plane,
+                                                  const double* __restrict__ Ecat,
+                                                  const double* __restrict__ Bsrc,
+                                                  double* __restrict__ C) {
+  __shared__ double As[16][64 + 4];
+  __shared__ double Bs[16][64 + 4];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int m0 = blockIdx.x * 64;
+  int kb, ke;
+  const double* Bp;
+  double* Cp;
+  if (!PROJ) {
+    const int L = blockIdx.y;
+    kb = plane_off[L];
+    ke = plane_off[L + 1];
+    Bp = Bsrc;
+    Cp = C + (size_t)L * M2 * VL;
+  } else {
+    const int L = tile_plane[blockIdx.x];
+    kb = 0;
+    ke = M2;
+    Bp = Bsrc + (size_t)L * M2 * VL;
+    Cp = C;
+  }
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+    if (!PROJ) {
+      const int r = tid >> 2, c = (tid & 3) * 4;          // A rows m0 + r, k0 + c ..
+      const double* src = Ecat + (size_t)(m0 + r) * nslot + k0 + c;
+      for (int t = 0; t < 4; ++t) ra[t] = src[t];
+    } else {
+      const int r = tid >> 4, c = (tid & 15) * 4;         // A^T rows k0 + r, m0 + c ..
+      const double* src = Ecat + (size_t)(k0 + r) * nslot + m0 + c;
+      for (int t = 0; t < 4; ++t) ra[t] = src[t];
+    }
+    const int r = tid >> 4, c = (tid & 15) * 4;
+    const double* src = Bp + (size_t)(k0 + r) * VL + c;
+    for (int t = 0; t < 4; ++t) rb[t] = src[t];
+  };
+  auto store = [&]() {
+    if (!PROJ) {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      for (int t = 0; t < 4; ++t) As[c + t][r] = ra[t];
+    } else {
+      const int r = tid >> 4, c = (tid & 15) * 4;
+      for (int t = 0; t < 4; ++t) As[r][c + t] = ra[t];
+    }
+    const int r = tid >> 4, c = (tid & 15) * 4;
+    for (int t = 0; t < 4; ++t) Bs[r][c + t] = rb[t];
+  };
+  if (kb < ke) load(kb);
+  for (int k0 = kb; k0 < ke; k0 += 16) {
+    store();
+    __syncthreads();
+    if (k0 + 16 < ke) load(k0 + 16);
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+      const int kr = kk + (lane >> 4), cc = lane & 15;
+      const double a0 = As[kr][wm + cc], a1 = As[kr][wm + 16 + cc];
+      const double b0 = Bs[kr][wn + cc], b1 = Bs[kr][wn + 16 + cc];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + wm + a * 16 + (lane >> 4) + 4 * q;
+        const int s = wn + b * 16 + (lane & 15);
+        Cp[(size_t)row * VL + s] = acc[a][b][q];
+      }
+}
+
+// T for every plane: Tcat[(L M2 + 2c) VL + s] = Re, [.. 2c + 1 ..] = Im of
+// sum_L' Q_c(L', L) Y(c, L', s); zero rows for padding columns
+__global__ void k_cg_plane_mix(int nlayers, int ncp, int ncolsort, const double2* __restrict__ Q,
+                               const double* __restrict__ Y, double* __restrict__ T) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)nlayers * ncp * VL) return;
+  const int s = (int)(e % VL), c = (int)((e / VL) % ncp), L = (int)(e / ((size_t)VL * ncp));
+  const size_t M2 = 2 * (size_t)ncp;
   double tr = 0.0, ti = 0.0;
-  for (int L2 = 0; L2 < nlayers; ++L2) {
-    const double2 q = Q[((size_t)c * nlayers + L2) * nlayers + L];
-    const double2 y = Y[((size_t)c * nlayers + L2) * g + s];
-    tr += q.x * y.x - q.y * y.y;
-    ti += q.x * y.y + q.y * y.x;
-  }
-  T[e] = make_double2(tr, ti);
-}
-
-// moments of each vector per block: mom[((s nblk + blk) 4 + d)] for
-// d = 0: sum p, 1..3: sum p r_d (raw coordinates)
-__global__ void __launch_bounds__(256) k_op_moments(int g, int n, const double* __restrict__ ex,
-                                                    const double* __restrict__ ey,
-                                                    const double* __restrict__ ez,
-                                                    const double* __restrict__ P, int ldp,
-                                                    double* __restrict__ mom) {
-  __shared__ double sh[4 * CG_MAXG][4];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  double x = 0, y = 0, z = 0;
-  if (i < n) { x = ex[i]; y = ey[i]; z = ez[i]; }
-  for (int s = 0; s < g; ++s) {
-    const double pv = i < n ? P[(size_t)s * ldp + i] : 0.0;
-    park(pv, 4 * s, sh);
-    park(pv * x, 4 * s + 1, sh);
-    park(pv * y, 4 * s + 2, sh);
-    park(pv * z, 4 * s + 3, sh);
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < 4 * g) {
-    const int s = threadIdx.x / 4, d = threadIdx.x % 4;
-    mom[((size_t)s * nblk + blockIdx.x) * 4 + d] = parked(threadIdx.x, sh);
-  }
-}
-
-// Ap = k_e (k-space + ELL real space + background sum p + sum_d c_d r_d M_d)
-// + diag_extra p, and the block partials of p.Ap and sum Ap.
-__global__ void __launch_bounds__(256) k_op_final(
-    int g, int n, int ldp, int cgroups, const double* __restrict__ phik, int width,
-    const int* __restrict__ ecol, const double* __restrict__ evals,
-    const double* __restrict__ mom, const double* __restrict__ ex, const double* __restrict__ ey,
-    const double* __restrict__ ez, double background, double cx, double cy, double cz, double ke,
-    const double* __restrict__ dextra, const double* __restrict__ P, double* __restrict__ AP,
-    double* __restrict__ red) {
-  __shared__ double sM[4 * CG_MAXG];
-  __shared__ double sh[2 * CG_MAXG][4];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  if ((int)threadIdx.x < 4 * g) {
-    const int s = threadIdx.x / 4, d = threadIdx.x % 4;
-    double a = 0.0;
-    for (int k = 0; k < nblk; ++k) a += mom[((size_t)s * nblk + k) * 4 + d];
-    sM[threadIdx.x] = a;
-  }
-  __syncthreads();
-  double acc[CG_MAXG];
-#pragma unroll
-  for (int s = 0; s < CG_MAXG; ++s) acc[s] = 0.0;
-  if (i < n) {
-    for (int k = 0; k < width; ++k) {
-      const int j = ecol[(size_t)k * n + i];
-      const double a = evals[(size_t)k * n + i];
-#pragma unroll
-      for (int s = 0; s < CG_MAXG; ++s)
-        if (s < g) acc[s] += a * P[(size_t)s * ldp + j];
+  if (c < ncolsort) {
+    for (int L2 = 0; L2 < nlayers; ++L2) {
+      const double2 q = Q[((size_t)c * nlayers + L2) * nlayers + L];
+      const double yr = Y[(L2 * M2 + 2 * c) * VL + s], yi = Y[(L2 * M2 + 2 * c + 1) * VL + s];
+      tr += q.x * yr - q.y * yi;
+      ti += q.x * yi + q.y * yr;
     }
   }
-  double x = 0, y = 0, z = 0, de = 0;
-  if (i < n) { x = ex[i]; y = ey[i]; z = ez[i]; de = dextra[i]; }
+  T[(L * M2 + 2 * c) * VL + s] = tr;
+  T[(L * M2 + 2 * c + 1) * VL + s] = ti;
+}
+
+// ---- A p and the conjugate-gradient steps ---------------------------------
+// Every kernel below runs on the same grid (nblk blocks of CG_WAVES waves),
+// so the partials of one are summed by the next over the same block count.
+
+// moments (sum p, sum p x, sum p y, sum p z) of one row into v[0..4)
+__device__ inline void add_moments(double* v, double p, int i, const double* __restrict__ ex,
+                                   const double* __restrict__ ey, const double* __restrict__ ez) {
+  v[0] += p;
+  v[1] += p * ex[i];
+  v[2] += p * ey[i];
+  v[3] += p * ez[i];
+}
+
+__device__ inline void store_moments(const double (&m)[4], double* __restrict__ red) {
+  const int f[4] = {F_M0, F_M0 + 1, F_M0 + 2, F_M0 + 3};
+  store_partials<4>(m, f, red);
+}
+
+// Ap = k_e (Phi + ELL real space + background M0 + sum_d c_d r_d M_d) +
+// diag_extra p (operator; DENSE: Ap given), pad slots 0; block partials of
+// p.Ap and sum Ap.  M: the moments of p from the kernel that wrote p.
+template <bool DENSE>
+__global__ void __launch_bounds__(CG_BLK) k_cg_apply(
+    int nslot, int n, const int* __restrict__ slot_atom, const double* __restrict__ ex,
+    const double* __restrict__ ey, const double* __restrict__ ez,
+    const double* __restrict__ dextra, int width, const int* __restrict__ ecol,
+    const double* __restrict__ evals, const double* __restrict__ Phi, double background,
+    double cx, double cy, double cz, double ke, const double* __restrict__ P,
+    double* __restrict__ AP, double* __restrict__ red) {
+  __shared__ double M[4][VL];
+  const int s = threadIdx.x & 63;
+  if (!DENSE) {
+    const int f[4] = {F_M0, F_M0 + 1, F_M0 + 2, F_M0 + 3};
+    block_totals<4>(red, gridDim.x, f, M);
+  }
+  double v[2] = {0.0, 0.0};
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int r = w.r, i = slot_atom[r];
+    const double pv = P[(size_t)r * VL + s];
+    double ap = 0.0;
+    if (i >= 0) {
+      if (DENSE) {
+        ap = AP[(size_t)r * VL + s];
+      } else {
+        // width is a multiple of 8: 8 (column, value) pairs per step come
+        // in as wave-uniform scalar loads
+        const int* cr = ecol + (size_t)r * width;
+        const double* vr = evals + (size_t)r * width;
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int k = 0; k < width; k += 8) {
+          double pv8[8];
 #pragma unroll
-  for (int s = 0; s < CG_MAXG; ++s) {
-    if (s < g) {
-      double pv = 0.0, ap = 0.0;
-      if (i < n) {
-        double pk = 0.0;
-        for (int r = 0; r < cgroups; ++r) pk += phik[((size_t)r * g + s) * n + i];
-        const double* M = sM + 4 * s;
-        pv = P[(size_t)s * ldp + i];
-        ap = ke * ((pk + acc[s]) + (background * M[0] + (cx * x * M[1] + cy * y * M[2] +
-                                                         cz * z * M[3]))) + de * pv;
-        AP[(size_t)s * ldp + i] = ap;
+          for (int u = 0; u < 8; ++u) pv8[u] = P[(size_t)cr[k + u] * VL + s];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) a[u & 3] += vr[k + u] * pv8[u];
+        }
+        ap = ke * ((Phi[(size_t)r * VL + s] + ((a[0] + a[1]) + (a[2] + a[3]))) +
+                   (background * M[0][s] +
+                    (cx * ex[i] * M[1][s] + cy * ey[i] * M[2][s] + cz * ez[i] * M[3][s]))) +
+             dextra[i] * pv;
       }
-      park(pv * ap, 2 * s, sh);
-      park(ap, 2 * s + 1, sh);
     }
+    if (!DENSE) AP[(size_t)r * VL + s] = ap;
+    v[0] += pv * ap;
+    v[1] += ap;
   }
-  __syncthreads();
-  if ((int)threadIdx.x < 2 * g) {
-    const int s = threadIdx.x / 2, f = threadIdx.x % 2 ? F_SAP : F_PAP;
-    red[((size_t)s * nblk + blockIdx.x) * CG_RED + f] = parked(threadIdx.x, sh);
-  }
+  const int f[2] = {F_PAP, F_SAP};
+  store_partials<2>(v, f, red);
 }
 
-// ---- conjugate-gradient steps (grid: blocks of 256 atoms, all vectors) -------
-// partials of p.Ap and sum Ap for an Ap computed elsewhere (dense A)
-__global__ void __launch_bounds__(256) k_cg_dots(int g, int n, int ldp, const double* __restrict__ P,
-                                                 const double* __restrict__ AP,
-                                                 double* __restrict__ red) {
-  __shared__ double sh[2 * CG_MAXG][4];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  for (int s = 0; s < g; ++s) {
-    const double ap = i < n ? AP[(size_t)s * ldp + i] : 0.0;
-    const double pv = i < n ? P[(size_t)s * ldp + i] : 0.0;
-    park(pv * ap, 2 * s, sh);
-    park(ap, 2 * s + 1, sh);
+// alpha = r.r / p.Ap for vectors above tolerance (else 0: frozen);
+// x += alpha p, r -= alpha (Ap - mean Ap); partials of the new r.r into field
+// F_RR + (1 - cur).  Block 0 counts the iteration of each active vector.
+__global__ void __launch_bounds__(CG_BLK) k_cg_update(int nslot, int n, int cur, double tol2,
+                                                      const int* __restrict__ slot_atom,
+                                                      double* __restrict__ X,
+                                                      double* __restrict__ R,
+                                                      const double* __restrict__ P,
+                                                      const double* __restrict__ AP,
+                                                      double* __restrict__ red,
+                                                      double* __restrict__ scal) {
+  __shared__ double t[4][VL];
+  const int s = threadIdx.x & 63;
+  {
+    const int f[4] = {F_PAP, F_SAP, F_RR + cur, F_RRI};
+    block_totals<4>(red, gridDim.x, f, t);
   }
-  __syncthreads();
-  if ((int)threadIdx.x < 2 * g) {
-    const int s = threadIdx.x / 2, f = threadIdx.x % 2 ? F_SAP : F_PAP;
-    red[((size_t)s * nblk + blockIdx.x) * CG_RED + f] = parked(threadIdx.x, sh);
+  const double pap = t[0][s], mean = t[1][s] / n, rr = t[2][s], rr0 = t[3][s];
+  const bool active = rr > tol2 * rr0 && pap > 0.0;
+  const double a = active ? rr / pap : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x < VL && active) scal[S_ITERS * VL + s] += 1.0;
+  double v[1] = {0.0};
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int r = w.r;
+    if (slot_atom[r] < 0) continue;
+    const size_t o = (size_t)r * VL + s;
+    X[o] += a * P[o];
+    const double rn = R[o] - a * (AP[o] - mean);
+    R[o] = rn;
+    v[0] += rn * rn;
   }
+  const int f[1] = {F_RR + (1 - cur)};
+  store_partials<1>(v, f, red);
+}
+
+// beta = r'.r' / r.r (0 for frozen vectors); p = r' + beta p; moments of
+// the new p.  Block 0 records r'.r' and r0.r0 for the host.
+__global__ void __launch_bounds__(CG_BLK) k_cg_dir(int nslot, int cur, double tol2,
+                                                   const int* __restrict__ slot_atom,
+                                                   const double* __restrict__ ex,
+                                                   const double* __restrict__ ey,
+                                                   const double* __restrict__ ez,
+                                                   const double* __restrict__ R,
+                                                   double* __restrict__ P, double* __restrict__ red,
+                                                   double* __restrict__ scal) {
+  __shared__ double t[3][VL];
+  const int s = threadIdx.x & 63;
+  {
+    const int f[3] = {F_RR + cur, F_RR + (1 - cur), F_RRI};
+    block_totals<3>(red, gridDim.x, f, t);
+  }
+  const double rr = t[0][s], rn = t[1][s], rr0 = t[2][s];
+  const double beta = rr > tol2 * rr0 ? rn / rr : 0.0;
+  if (blockIdx.x == 0 && threadIdx.x < VL) {
+    scal[S_RR * VL + s] = rn;
+    scal[S_RR0 * VL + s] = rr0;
+  }
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int r = w.r, i = slot_atom[r];
+    if (i < 0) continue;
+    const size_t o = (size_t)r * VL + s;
+    const double p = R[o] + beta * P[o];
+    P[o] = p;
+    add_moments(m, p, i, ex, ey, ez);
+  }
+  store_moments(m, red);
 }
 
 __device__ inline double rhs_value(const void* b, int b_is_f32, int n, int s, int i,
@@ -300,238 +482,240 @@ __device__ inline double rhs_value(const void* b, int b_is_f32, int n, int s, in
   return bv + vat[i];
 }
 
-// partial sums of c = b + v
-__global__ void __launch_bounds__(256) k_cg_rhs_sum(int g, int n, const void* b, int b_is_f32,
-                                                    const double* __restrict__ vat,
+// partial sums of c = b + v per vector (vectors s < g; b rows n apart, atom order)
+__global__ void __launch_bounds__(CG_BLK) k_cg_rhs(int nslot, int n, int g,
+                                                   const int* __restrict__ slot_atom,
+                                                   const void* b, int b_is_f32,
+                                                   const double* __restrict__ vat,
+                                                   double* __restrict__ red) {
+  const int s = threadIdx.x & 63;
+  double v[1] = {0.0};
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int i = slot_atom[w.r];
+    if (i >= 0 && s < g) v[0] += rhs_value(b, b_is_f32, n, s, i, vat);
+  }
+  const int f[1] = {F_SUM};
+  store_partials<1>(v, f, red);
+}
+
+// x = 0, r = p = c - mean(c) (zero for pads and vectors s >= g); partials of
+// r0.r0 (fields F_RR and F_RRI) and of the moments of p; block 0 clears the
+// iteration counts and records r0.r0 for the host
+__global__ void __launch_bounds__(CG_BLK) k_cg_init(int nslot, int n, int g,
+                                                    const int* __restrict__ slot_atom,
+                                                    const double* __restrict__ ex,
+                                                    const double* __restrict__ ey,
+                                                    const double* __restrict__ ez, const void* b,
+                                                    int b_is_f32, const double* __restrict__ vat,
+                                                    double* __restrict__ X, double* __restrict__ R,
+                                                    double* __restrict__ P,
+                                                    double* __restrict__ red,
+                                                    double* __restrict__ scal) {
+  __shared__ double t[1][VL];
+  const int s = threadIdx.x & 63;
+  {
+    const int f[1] = {F_SUM};
+    block_totals<1>(red, gridDim.x, f, t);
+  }
+  const double cm = t[0][s] / n;
+  double rr[2] = {0.0, 0.0};
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int r = w.r, i = slot_atom[r];
+    const size_t o = (size_t)r * VL + s;
+    double rv = 0.0;
+    if (i >= 0 && s < g) rv = rhs_value(b, b_is_f32, n, s, i, vat) - cm;
+    X[o] = 0.0;
+    R[o] = rv;
+    P[o] = rv;
+    rr[0] += rv * rv;
+    if (i >= 0) add_moments(m, rv, i, ex, ey, ez);
+  }
+  rr[1] = rr[0];
+  const int f[2] = {F_RR, F_RRI};
+  store_partials<2>(rr, f, red);
+  store_moments(m, red);
+  if (blockIdx.x == 0 && threadIdx.x < VL) scal[S_ITERS * VL + s] = 0.0;
+}
+
+// P = x (batch x n, atom order) in slot rows, zero elsewhere; moments of it
+__global__ void __launch_bounds__(CG_BLK) k_cg_gather(int nslot, int n, int g,
+                                                      const int* __restrict__ slot_atom,
+                                                      const double* __restrict__ ex,
+                                                      const double* __restrict__ ey,
+                                                      const double* __restrict__ ez,
+                                                      const double* __restrict__ x,
+                                                      double* __restrict__ P,
+                                                      double* __restrict__ red) {
+  const int s = threadIdx.x & 63;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int r = w.r, i = slot_atom[r];
+    double p = 0.0;
+    if (i >= 0 && s < g) p = x[(size_t)s * n + i];
+    P[(size_t)r * VL + s] = p;
+    if (i >= 0) add_moments(m, p, i, ex, ey, ez);
+  }
+  store_moments(m, red);
+}
+
+// partial sums of x per vector
+__global__ void __launch_bounds__(CG_BLK) k_cg_xsum(int nslot, const int* __restrict__ slot_atom,
+                                                    const double* __restrict__ X,
                                                     double* __restrict__ red) {
-  __shared__ double sh[CG_MAXG][4];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  for (int s = 0; s < g; ++s) park(i < n ? rhs_value(b, b_is_f32, n, s, i, vat) : 0.0, s, sh);
-  __syncthreads();
-  if ((int)threadIdx.x < g)
-    red[((size_t)threadIdx.x * nblk + blockIdx.x) * CG_RED + F_SUM] = parked(threadIdx.x, sh);
+  const int s = threadIdx.x & 63;
+  double v[1] = {0.0};
+  for (Rows w; w.r < nslot; w.r += w.step)
+    if (slot_atom[w.r] >= 0) v[0] += X[(size_t)w.r * VL + s];
+  const int f[1] = {F_SUM};
+  store_partials<1>(v, f, red);
 }
 
-// x = 0, r = p = P c; partials of r.r into slot 0 and the initial field;
-// iteration counters cleared
-__global__ void __launch_bounds__(256) k_cg_init(int g, int n, int ldp, const void* b, int b_is_f32,
-                                                 const double* __restrict__ vat,
-                                                 double* __restrict__ red, double* __restrict__ X,
-                                                 double* __restrict__ R, double* __restrict__ P,
-                                                 double* __restrict__ stat) {
-  __shared__ double smean[CG_MAXG];
-  __shared__ double sh[CG_MAXG][4];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  if ((int)threadIdx.x < g) {
-    smean[threadIdx.x] = sum_partials(red, nblk, threadIdx.x, F_SUM) / n;
-    if (blockIdx.x == 0) stat[3 * threadIdx.x + 2] = 0.0;
+// y (batch x n, atom order) = the slot rows of V, minus the mean of V's
+// vectors when `center` (the neutrality projection of the CG iterate)
+__global__ void __launch_bounds__(CG_BLK) k_cg_scatter(int nslot, int n, int g, int center,
+                                                       const int* __restrict__ slot_atom,
+                                                       const double* __restrict__ V,
+                                                       const double* __restrict__ red,
+                                                       double* __restrict__ y) {
+  __shared__ double t[1][VL];
+  const int s = threadIdx.x & 63;
+  double sh = 0.0;
+  if (center) {
+    const int f[1] = {F_SUM};
+    block_totals<1>(red, gridDim.x, f, t);
+    sh = t[0][s] / n;
   }
-  __syncthreads();
-  for (int s = 0; s < g; ++s) {
-    double r = 0.0;
-    if (i < n) {
-      r = rhs_value(b, b_is_f32, n, s, i, vat) - smean[s];
-      X[(size_t)s * ldp + i] = 0.0;
-      R[(size_t)s * ldp + i] = r;
-      P[(size_t)s * ldp + i] = r;
-    }
-    park(r * r, s, sh);
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int i = slot_atom[w.r];
+    if (i >= 0 && s < g) y[(size_t)s * n + i] = V[(size_t)w.r * VL + s] - sh;
   }
-  __syncthreads();
-  if ((int)threadIdx.x < g) {
-    double* o = red + ((size_t)threadIdx.x * nblk + blockIdx.x) * CG_RED;
-    o[F_RR] = parked(threadIdx.x, sh);
-    o[F_RRI] = parked(threadIdx.x, sh);
-  }
-}
-
-// alpha = r.r / p.Ap for vectors still above tolerance (else 0: frozen);
-// x += alpha p, r -= alpha P Ap; partials of the new r.r into the other slot
-__global__ void __launch_bounds__(256) k_cg_update(int g, int n, int ldp, int cur, double tol2,
-                                                   double* __restrict__ red,
-                                                   double* __restrict__ X, double* __restrict__ R,
-                                                   const double* __restrict__ P,
-                                                   const double* __restrict__ AP,
-                                                   double* __restrict__ stat) {
-  __shared__ double salpha[CG_MAXG], smean[CG_MAXG];
-  __shared__ double sh[CG_MAXG][4];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  if ((int)threadIdx.x < g) {
-    const int s = threadIdx.x;
-    const double pap = sum_partials(red, nblk, s, F_PAP), sap = sum_partials(red, nblk, s, F_SAP);
-    const double rr = sum_partials(red, nblk, s, F_RR + cur);
-    const double rr0 = sum_partials(red, nblk, s, F_RRI);
-    const bool active = rr > tol2 * rr0 && pap > 0.0;
-    salpha[s] = active ? rr / pap : 0.0;
-    smean[s] = sap / n;
-    if (blockIdx.x == 0 && active) stat[3 * s + 2] += 1.0;
-  }
-  __syncthreads();
-  for (int s = 0; s < g; ++s) {
-    double r = 0.0;
-    if (i < n) {
-      const size_t o = (size_t)s * ldp + i;
-      const double a = salpha[s];
-      X[o] += a * P[o];
-      r = R[o] - a * (AP[o] - smean[s]);
-      R[o] = r;
-    }
-    park(r * r, s, sh);
-  }
-  __syncthreads();
-  if ((int)threadIdx.x < g)
-    red[((size_t)threadIdx.x * nblk + blockIdx.x) * CG_RED + F_RR + (1 - cur)] = parked(threadIdx.x, sh);
-}
-
-// beta = r'.r' / r.r (0 for frozen vectors); p = r' + beta p
-__global__ void __launch_bounds__(256) k_cg_dir(int g, int n, int ldp, int cur, double tol2,
-                                                const double* __restrict__ red,
-                                                const double* __restrict__ R,
-                                                double* __restrict__ P) {
-  __shared__ double sbeta[CG_MAXG];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  if ((int)threadIdx.x < g) {
-    const int s = threadIdx.x;
-    const double rr = sum_partials(red, nblk, s, F_RR + cur);
-    const double rn = sum_partials(red, nblk, s, F_RR + (1 - cur));
-    const double rr0 = sum_partials(red, nblk, s, F_RRI);
-    sbeta[s] = rr > tol2 * rr0 ? rn / rr : 0.0;
-  }
-  __syncthreads();
-  if (i >= n) return;
-  for (int s = 0; s < g; ++s) {
-    const size_t o = (size_t)s * ldp + i;
-    P[o] = R[o] + sbeta[s] * P[o];
-  }
-}
-
-// stat[3 s] = r.r (slot cur), stat[3 s + 1] = r0.r0
-__global__ void k_cg_status(int g, int nblk, int cur, const double* __restrict__ red,
-                            double* __restrict__ stat) {
-  const int s = threadIdx.x;
-  if (s >= g) return;
-  stat[3 * s] = sum_partials(red, nblk, s, F_RR + cur);
-  stat[3 * s + 1] = sum_partials(red, nblk, s, F_RRI);
-}
-
-__global__ void __launch_bounds__(256) k_cg_xsum(int g, int n, int ldp, const double* __restrict__ X,
-                                                 double* __restrict__ red) {
-  __shared__ double sh[CG_MAXG][4];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  for (int s = 0; s < g; ++s) park(i < n ? X[(size_t)s * ldp + i] : 0.0, s, sh);
-  __syncthreads();
-  if ((int)threadIdx.x < g)
-    red[((size_t)threadIdx.x * nblk + blockIdx.x) * CG_RED + F_SUM] = parked(threadIdx.x, sh);
-}
-
-// q = x - mean(x) (the neutrality projection, exact up to rounding)
-__global__ void __launch_bounds__(256) k_cg_finish(int g, int n, int ldp,
-                                                   const double* __restrict__ X,
-                                                   const double* __restrict__ red,
-                                                   double* __restrict__ q) {
-  __shared__ double smean[CG_MAXG];
-  const int i = blockIdx.x * CG_BLK + threadIdx.x, nblk = gridDim.x;
-  if ((int)threadIdx.x < g) smean[threadIdx.x] = sum_partials(red, nblk, threadIdx.x, F_SUM) / n;
-  __syncthreads();
-  if (i >= n) return;
-  for (int s = 0; s < g; ++s) q[(size_t)s * n + i] = X[(size_t)s * ldp + i] - smean[s];
 }
 
 // electrode totals Qe[s n_e + e] = sum_{i: eid_i = e} q_s[i]; block per vector
 __global__ void __launch_bounds__(256) k_cg_totals(int n, const double* __restrict__ q,
                                                    const int* __restrict__ eid, int n_e,
                                                    double* __restrict__ Qe) {
-  __shared__ double sh[1][4];
-  const int s = blockIdx.x;
+  __shared__ double sh[4];
+  const int s = blockIdx.x, lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int e = 0; e < n_e; ++e) {
     double a = 0.0;
-    for (int i = threadIdx.x; i < n; i += CG_BLK)
+    for (int i = threadIdx.x; i < n; i += 256)
       if (eid[i] == e) a += q[(size_t)s * n + i];
-    park(a, 0, sh);
+    for (int o = 32; o > 0; o >>= 1) a += __shfl_xor(a, o, 64);
+    if (lane == 0) sh[w] = a;
     __syncthreads();
-    if (threadIdx.x == 0) Qe[(size_t)s * n_e + e] = parked(0, sh);
+    if (threadIdx.x == 0) Qe[(size_t)s * n_e + e] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
     __syncthreads();
   }
 }
 
 }  // namespace
 
-void launch_ell_count(hipStream_t st, int n, int jchunks, const Buffers& b, double Lx, double Ly,
-                      double Lz, double rc, int* cnt) {
-  const int chunk = (n + jchunks - 1) / jchunks;
+int cg_blocks(int nslot, int cap) { return std::max(1, std::min(cap, nslot / CG_WAVES)); }
+
+int cg_scalar_row(int which) { return which == 0 ? S_RR : which == 1 ? S_RR0 : S_ITERS; }
+
+void launch_ell_count(hipStream_t st, int nslot, int jchunks, const int* slot_atom,
+                      const Buffers& b, double Lx, double Ly, double Lz, double rc, int* cnt) {
+  const int chunk = (nslot + jchunks - 1) / jchunks;
   // alpha, eta_ee and the self term do not enter the count
-  hipLaunchKernelGGL(k_ell_pass<false>, dim3((n + 255) / 256, jchunks), dim3(256), 0, st, n, chunk,
-                     0, b.ex, b.ey, b.ez, Lx, Ly, Lz, rc, 1.0, 1.0, 0.0, cnt, nullptr, nullptr);
+  hipLaunchKernelGGL(k_ell_pass<false>, dim3((nslot + 255) / 256, jchunks), dim3(256), 0, st,
+                     nslot, chunk, 0, slot_atom, b.ex, b.ey, b.ez, Lx, Ly, Lz, rc, 1.0, 1.0, 0.0,
+                     cnt, nullptr, nullptr);
 }
 
-// off: per-chunk starting offsets (the exclusive prefix of the counts along
-// each row, chunk-major like the counts)
-void launch_ell_fill(hipStream_t st, int n, int jchunks, int width, const int* off,
-                     const Buffers& b, double Lx, double Ly, double Lz, double rc, double alpha,
-                     double eta_ee, double diag_self, int* col, double* val) {
-  const size_t total = (size_t)width * n;
-  hipLaunchKernelGGL(k_ell_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, n, total,
-                     col, val);
-  const int chunk = (n + jchunks - 1) / jchunks;
-  hipLaunchKernelGGL(k_ell_pass<true>, dim3((n + 255) / 256, jchunks), dim3(256), 0, st, n, chunk,
-                     width, b.ex, b.ey, b.ez, Lx, Ly, Lz, rc, alpha, eta_ee, diag_self,
-                     const_cast<int*>(off), col, val);
+void launch_ell_fill(hipStream_t st, int nslot, int jchunks, int width, const int* slot_atom,
+                     const int* off, const Buffers& b, double Lx, double Ly, double Lz, double rc,
+                     double alpha, double eta_ee, double diag_self, int* col, double* val) {
+  const size_t total = (size_t)width * nslot;
+  hipLaunchKernelGGL(k_ell_init, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, width,
+                     total, col, val);
+  const int chunk = (nslot + jchunks - 1) / jchunks;
+  hipLaunchKernelGGL(k_ell_pass<true>, dim3((nslot + 255) / 256, jchunks), dim3(256), 0, st, nslot,
+                     chunk, width, slot_atom, b.ex, b.ey, b.ez, Lx, Ly, Lz, rc, alpha, eta_ee,
+                     diag_self, const_cast<int*>(off), col, val);
 }
 
-void launch_op_apply(cpm_ctx* c, int g, const double* P, double* AP) {
-  const Buffers& b = c->b;
-  hipStream_t st = c->stream;
-  const int n = c->n, ldp = c->npad, nL = c->nlayers, nc = c->ncolsort, nblk = cg_blocks(n);
-  hipLaunchKernelGGL(k_op_plane_sums, dim3(nc, nL), dim3(64), 0, st, g, n, nL, b.plane_off, b.amap,
-                     b.ephase, P, ldp, b.cgY);
-  const int tot = nc * nL * g;
-  hipLaunchKernelGGL(k_op_plane_mix, dim3((tot + 255) / 256), dim3(256), 0, st, g, nL, nc, b.Qpair,
-                     b.cgY, b.cgT);
-  launch_layer_project_groups(st, g, n, nc, nL, c->op_cgroups, b.ephase, b.layer_of, b.cgT,
-                              b.cgphi);
-  hipLaunchKernelGGL(k_op_moments, dim3(nblk), dim3(CG_BLK), 0, st, g, n, b.ex, b.ey, b.ez, P, ldp,
-                     b.cgmom);
-  hipLaunchKernelGGL(k_op_final, dim3(nblk), dim3(CG_BLK), 0, st, g, n, ldp, c->op_cgroups,
-                     b.cgphi, c->ell_width, b.ell_col, b.ell_val, b.cgmom, b.ex, b.ey, b.ez,
-                     c->op_background, c->cdip[0], c->cdip[1], c->cdip[2], c->ke, b.dextra, P, AP,
-                     b.cgred);
+void launch_cg_ephase(hipStream_t st, int nslot, int ncp, int ncolsort, const int* slot_atom,
+                      const Buffers& b, double* Ecat) {
+  hipLaunchKernelGGL(k_cg_ephase, dim3((nslot + 255) / 256, ncp), dim3(256), 0, st, nslot,
+                     ncolsort, slot_atom, b.sc_nx, b.sc_ny, b.efx, b.efy, Ecat);
 }
 
-void launch_cg_dots(hipStream_t st, int g, int n, int ldp, const double* P, const double* AP,
-                    double* red) {
-  hipLaunchKernelGGL(k_cg_dots, dim3(cg_blocks(n)), dim3(CG_BLK), 0, st, g, n, ldp, P, AP, red);
+void launch_cg_plane_sums(hipStream_t st, int nslot, int ncp, int nlayers, const int* plane_off,
+                          const double* Ecat, const double* P, double* Y) {
+  hipLaunchKernelGGL(k_cg_kgemm<false>, dim3(2 * ncp / 64, nlayers), dim3(256), 0, st, nslot,
+                     2 * ncp, plane_off, nullptr, Ecat, P, Y);
 }
 
-void launch_cg_init(hipStream_t st, int g, int n, int ldp, const void* b, int b_is_f32,
-                    const double* vat, double* red, double* X, double* R, double* P, double* stat) {
-  hipLaunchKernelGGL(k_cg_rhs_sum, dim3(cg_blocks(n)), dim3(CG_BLK), 0, st, g, n, b, b_is_f32, vat,
-                     red);
-  hipLaunchKernelGGL(k_cg_init, dim3(cg_blocks(n)), dim3(CG_BLK), 0, st, g, n, ldp, b, b_is_f32, vat,
-                     red, X, R, P, stat);
+void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, const double2* Q,
+                         const double* Y, double* T) {
+  const size_t tot = (size_t)nlayers * ncp * VL;
+  hipLaunchKernelGGL(k_cg_plane_mix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
+                     nlayers, ncp, ncolsort, Q, Y, T);
 }
 
-void launch_cg_update(hipStream_t st, int g, int n, int ldp, int cur, double tol2,
-                      double* red, double* X, double* R, const double* P, const double* AP,
-                      double* stat) {
-  hipLaunchKernelGGL(k_cg_update, dim3(cg_blocks(n)), dim3(CG_BLK), 0, st, g, n, ldp, cur, tol2,
-                     red, X, R, P, AP, stat);
+void launch_cg_project(hipStream_t st, int nslot, int ncp, const int* tile_plane,
+                       const double* Ecat, const double* T, double* Phi) {
+  hipLaunchKernelGGL(k_cg_kgemm<true>, dim3(nslot / 64), dim3(256), 0, st, nslot, 2 * ncp, nullptr,
+                     tile_plane, Ecat, T, Phi);
 }
 
-void launch_cg_dir(hipStream_t st, int g, int n, int ldp, int cur, double tol2, const double* red,
-                   const double* R, double* P) {
-  hipLaunchKernelGGL(k_cg_dir, dim3(cg_blocks(n)), dim3(CG_BLK), 0, st, g, n, ldp, cur, tol2, red,
-                     R, P);
+void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, const int* slot_atom,
+                     const Buffers& b, int width, const double* Phi, double background,
+                     const double* cdip, double ke, const double* P, double* AP, double* red) {
+  if (dense)
+    hipLaunchKernelGGL(k_cg_apply<true>, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, slot_atom,
+                       b.ex, b.ey, b.ez, b.dextra, width, b.ell_col, b.ell_val, Phi, background,
+                       cdip[0], cdip[1], cdip[2], ke, P, AP, red);
+  else
+    hipLaunchKernelGGL(k_cg_apply<false>, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, slot_atom,
+                       b.ex, b.ey, b.ez, b.dextra, width, b.ell_col, b.ell_val, Phi, background,
+                       cdip[0], cdip[1], cdip[2], ke, P, AP, red);
 }
 
-void launch_cg_status(hipStream_t st, int g, int n, int cur, const double* red, double* stat) {
-  hipLaunchKernelGGL(k_cg_status, dim3(1), dim3(64), 0, st, g, cg_blocks(n), cur, red, stat);
+void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2,
+                      const int* slot_atom, double* X, double* R, const double* P,
+                      const double* AP, double* red, double* scal) {
+  hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, cur, tol2, slot_atom,
+                     X, R, P, AP, red, scal);
 }
 
-void launch_cg_finish(hipStream_t st, int g, int n, int ldp, const double* X, double* red,
-                      const int* eid, int n_e, double* q, double* Qe) {
-  hipLaunchKernelGGL(k_cg_xsum, dim3(cg_blocks(n)), dim3(CG_BLK), 0, st, g, n, ldp, X, red);
-  hipLaunchKernelGGL(k_cg_finish, dim3(cg_blocks(n)), dim3(CG_BLK), 0, st, g, n, ldp, X, red, q);
-  if (Qe) hipLaunchKernelGGL(k_cg_totals, dim3(g), dim3(CG_BLK), 0, st, n, q, eid, n_e, Qe);
+void launch_cg_dir(hipStream_t st, int nblk, int nslot, int cur, double tol2, const int* slot_atom,
+                   const Buffers& b, const double* R, double* P, double* red, double* scal) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(nblk), dim3(CG_BLK), 0, st, nslot, cur, tol2, slot_atom, b.ex,
+                     b.ey, b.ez, R, P, red, scal);
+}
+
+void launch_cg_init(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                    const Buffers& b, const void* bsrc, int b_is_f32, double* X, double* R,
+                    double* P, double* red, double* scal) {
+  hipLaunchKernelGGL(k_cg_rhs, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, g, slot_atom, bsrc,
+                     b_is_f32, b.vat, red);
+  hipLaunchKernelGGL(k_cg_init, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, g, slot_atom, b.ex,
+                     b.ey, b.ez, bsrc, b_is_f32, b.vat, X, R, P, red, scal);
+}
+
+void launch_cg_gather(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                      const Buffers& b, const double* x, double* P, double* red) {
+  hipLaunchKernelGGL(k_cg_gather, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, g, slot_atom, b.ex,
+                     b.ey, b.ez, x, P, red);
+}
+
+void launch_cg_scatter(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                       const double* V, double* y) {
+  hipLaunchKernelGGL(k_cg_scatter, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, g, 0, slot_atom, V,
+                     nullptr, y);
+}
+
+void launch_cg_finish(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                      const double* X, double* red, const int* eid, int n_e, double* q,
+                      double* Qe) {
+  hipLaunchKernelGGL(k_cg_xsum, dim3(nblk), dim3(CG_BLK), 0, st, nslot, slot_atom, X, red);
+  hipLaunchKernelGGL(k_cg_scatter, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, g, 1, slot_atom, X,
+                     red, q);
+  if (Qe) hipLaunchKernelGGL(k_cg_totals, dim3(g), dim3(256), 0, st, n, q, eid, n_e, Qe);
 }
 
 }  // namespace cpm

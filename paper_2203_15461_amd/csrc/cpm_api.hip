@@ -185,21 +185,62 @@ cpm_status ensure_vat(cpm_ctx* c) {
   return dalloc(c, &c->b.vat, (size_t)c->npad);
 }
 
-// conjugate-gradient work: x, r, p, Ap for CG_MAXG vectors, block partials,
-// status words; the operator's plane sums and k-space partials
+// slot space of the CG vectors: the atom map for the operator (plane tiles),
+// the atoms padded to npad for the dense A
+int cg_nslot(const cpm_ctx* c) { return c->have_op ? c->nmap : c->npad; }
+const int* cg_slots(const cpm_ctx* c) { return c->have_op ? c->b.amap : c->b.cg_ident; }
+
+// blocks of the CG vector kernels (all share one grid)
+int cg_grid(const cpm_ctx* c) { return cg_blocks(cg_nslot(c), 128); }
+
+// AP = A P for the slot-major CG vectors (all CG_MAXG columns): the
+// operator's k-space products, then the ELL real space and the rest
+// (k_cg_apply); the dense A as one FP64 matrix-core product.  k_cg_apply
+// leaves the partials of p.Ap for the step length (partials = true).
+void apply_A(cpm_ctx* c, const double* P, double* AP, bool partials) {
+  Buffers& b = c->b;
+  hipStream_t st = c->stream;
+  const int n = c->n, nslot = cg_nslot(c), nblk = cg_grid(c);
+  if (c->have_op) {
+    { Timed t(c, "cg_plane_sums");
+      launch_cg_plane_sums(st, nslot, c->ncp, c->nlayers, b.plane_off, b.Ecat, P, b.cgY); }
+    { Timed t(c, "cg_plane_mix");
+      launch_cg_plane_mix(st, c->ncp, c->ncolsort, c->nlayers, b.Qpair, b.cgY, b.cgT); }
+    { Timed t(c, "cg_project");
+      launch_cg_project(st, nslot, c->ncp, b.tile_plane, b.Ecat, b.cgT, b.cgphi); }
+  } else {
+    Timed t(c, "cg_gemm_dense");
+    launch_gemm_f64(st, false, false, nslot, CG_MAXG, nslot, 1.0, b.A, c->npad, P, CG_MAXG, 0.0,
+                    AP, CG_MAXG, 0, 0);
+  }
+  if (c->have_op || partials) {
+    Timed t(c, "cg_apply");
+    launch_cg_apply(st, !c->have_op, nblk, nslot, n, cg_slots(c), b, c->ell_width, b.cgphi,
+                    c->op_background, c->cdip, c->ke, P, AP, b.cgred);
+  }
+}
+
+// conjugate-gradient work: X, R, P, AP (slot-major, CG_MAXG columns), block
+// partials, scalars, counters; the operator's k-space work arrays
 cpm_status ensure_cg_buffers(cpm_ctx* c) {
   Buffers& b = c->b;
   if (b.cgv) return CPM_OK;
-  const int nblk = (c->n + 255) / 256;
-  TRY(dalloc(c, &b.cgv, (size_t)4 * CG_MAXG * c->npad));
-  HIP_TRY(c, hipMemset(b.cgv, 0, (size_t)4 * CG_MAXG * c->npad * sizeof(double)));
-  TRY(dalloc(c, &b.cgred, (size_t)CG_MAXG * nblk * CG_RED));
-  TRY(dalloc(c, &b.cgstat, (size_t)3 * CG_MAXG));
+  const int nslot = cg_nslot(c);
+  if (!c->have_op) {
+    std::vector<int> id(c->npad, -1);
+    for (int i = 0; i < c->n; ++i) id[i] = i;
+    TRY(dalloc(c, &b.cg_ident, id.size()));
+    HIP_TRY(c, hipMemcpy(b.cg_ident, id.data(), id.size() * sizeof(int), hipMemcpyHostToDevice));
+  }
+  TRY(dalloc(c, &b.cgv, (size_t)4 * CG_MAXG * nslot));
+  HIP_TRY(c, hipMemset(b.cgv, 0, (size_t)4 * CG_MAXG * nslot * sizeof(double)));
+  TRY(dalloc(c, &b.cgred, (size_t)cg_grid(c) * CG_RED * CG_MAXG));
+  TRY(dalloc(c, &b.cgscal, (size_t)CG_NSCAL * CG_MAXG));
+  HIP_TRY(c, hipMemset(b.cgscal, 0, (size_t)CG_NSCAL * CG_MAXG * sizeof(double)));
   if (c->have_op) {
-    TRY(dalloc(c, &b.cgmom, (size_t)CG_MAXG * nblk * 4));
-    TRY(dalloc(c, &b.cgphi, (size_t)c->op_cgroups * CG_MAXG * c->n));
-    TRY(dalloc(c, &b.cgY, (size_t)c->ncolsort * c->nlayers * CG_MAXG));
-    TRY(dalloc(c, &b.cgT, (size_t)c->ncolsort * c->nlayers * CG_MAXG));
+    TRY(dalloc(c, &b.cgphi, (size_t)nslot * CG_MAXG));
+    TRY(dalloc(c, &b.cgY, (size_t)c->nlayers * 2 * c->ncp * CG_MAXG));
+    TRY(dalloc(c, &b.cgT, (size_t)c->nlayers * 2 * c->ncp * CG_MAXG));
   }
   return CPM_OK;
 }
@@ -621,45 +662,54 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     TRY(dalloc(c, &b.Qpair, (size_t)c->ncolsort * c->nlayers * c->nlayers));
     launch_plane_pair_weights(c->stream, c->ncolsort, c->nlayers, b.sc_lo, b.sc_len, b.sc_koff,
                               b.w2, b.layer_fz, b.Qpair);
-    std::vector<int> poff(c->nlayers + 1, 0);
-    for (int L = 0; L < c->nlayers; ++L) poff[L + 1] = poff[L] + c->h_plane_rows[L];
+    std::vector<int> poff(c->nlayers + 1, 0), tplane;
+    for (int L = 0; L < c->nlayers; ++L) {
+      poff[L + 1] = poff[L] + c->h_plane_rows[L];
+      for (int t = 0; t < c->h_plane_rows[L] / 64; ++t) tplane.push_back(L);
+    }
+    const int nslot = c->nmap;                    // slots: the atom map (64-slot plane tiles)
     TRY(dalloc(c, &b.plane_off, poff.size()));
     HIP_TRY(c, hipMemcpy(b.plane_off, poff.data(), poff.size() * sizeof(int), hipMemcpyHostToDevice));
+    TRY(dalloc(c, &b.tile_plane, tplane.size()));
+    HIP_TRY(c, hipMemcpy(b.tile_plane, tplane.data(), tplane.size() * sizeof(int),
+                         hipMemcpyHostToDevice));
+    // in-plane phases in slot order for the k-space products
+    c->ncp = (c->ncolsort + 31) / 32 * 32;
+    TRY(dalloc(c, &b.Ecat, (size_t)2 * c->ncp * nslot));
+    launch_cg_ephase(c->stream, nslot, c->ncp, c->ncolsort, b.amap, b, b.Ecat);
+    TRY(launched(c, "operator phases"));
     {
-      const int jchunks = std::max(1, std::min(64, (n + 1023) / 1024));
+      const int jchunks = std::max(1, std::min(64, (nslot + 1023) / 1024));
       int* cnt = nullptr;
-      TRY(dalloc(c, &cnt, (size_t)jchunks * n));
-      launch_ell_count(c->stream, n, jchunks, b, p.Lx, p.Ly, c->Lz, p.rcut, cnt);
+      TRY(dalloc(c, &cnt, (size_t)jchunks * nslot));
+      launch_ell_count(c->stream, nslot, jchunks, b.amap, b, p.Lx, p.Ly, c->Lz, p.rcut, cnt);
       TRY(launched(c, "ell count"));
-      std::vector<int> h_cnt((size_t)jchunks * n);
+      std::vector<int> h_cnt((size_t)jchunks * nslot);
       HIP_TRY(c, hipMemcpyAsync(h_cnt.data(), cnt, h_cnt.size() * sizeof(int), hipMemcpyDeviceToHost,
                                 c->stream));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
       int width = 0;
-      for (int i = 0; i < n; ++i) {              // offsets: chunks of a row in order
+      for (int r = 0; r < nslot; ++r) {          // offsets: chunks of a row in order
         int o = 0;
         for (int ch = 0; ch < jchunks; ++ch) {
-          const int k = h_cnt[(size_t)ch * n + i];
-          h_cnt[(size_t)ch * n + i] = o;
+          const int k = h_cnt[(size_t)ch * nslot + r];
+          h_cnt[(size_t)ch * nslot + r] = o;
           o += k;
         }
         width = std::max(width, o);
       }
       HIP_TRY(c, hipMemcpy(cnt, h_cnt.data(), h_cnt.size() * sizeof(int), hipMemcpyHostToDevice));
+      width = (width + 7) / 8 * 8;                // the product reads 8 entries per step
       c->ell_width = width;
       dfree(c, b.ell_col);                        // a rebuild may change the width
       dfree(c, b.ell_val);
-      TRY(dalloc(c, &b.ell_col, (size_t)width * n));
-      TRY(dalloc(c, &b.ell_val, (size_t)width * n));
-      launch_ell_fill(c->stream, n, jchunks, width, cnt, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha,
-                      eta_ee, diag_self, b.ell_col, b.ell_val);
+      TRY(dalloc(c, &b.ell_col, (size_t)width * nslot));
+      TRY(dalloc(c, &b.ell_val, (size_t)width * nslot));
+      launch_ell_fill(c->stream, nslot, jchunks, width, b.amap, cnt, b, p.Lx, p.Ly, c->Lz, p.rcut,
+                      p.alpha, eta_ee, diag_self, b.ell_col, b.ell_val);
       TRY(launched(c, "ell fill"));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
       dfree(c, cnt);
-    }
-    {
-      const int atom_blocks = (n + 63) / 64;
-      c->op_cgroups = std::max(1, std::min(c->ncolsort, (1536 + atom_blocks - 1) / atom_blocks));
     }
     TRY(dalloc(c, &b.dextra, (size_t)n));
     if (d_diag_extra)
@@ -1373,20 +1423,15 @@ cpm_status cpm_apply_elastance(cpm_ctx* c, int batch, const double* d_x, double*
   TRY(ensure_cg_buffers(c));
   Buffers& b = c->b;
   hipStream_t st = c->stream;
-  const int n = c->n, ldp = c->npad;
-  double* P = b.cgv + (size_t)2 * CG_MAXG * ldp;
-  double* AP = P + (size_t)CG_MAXG * ldp;
+  const int n = c->n, nslot = cg_nslot(c), nb = cg_grid(c);
+  double* P = b.cgv + (size_t)2 * CG_MAXG * nslot;
+  double* AP = P + (size_t)CG_MAXG * nslot;
   for (int v0 = 0; v0 < batch; v0 += CG_MAXG) {
     const int g = std::min(CG_MAXG, batch - v0);
-    launch_pad_rows(st, n, ldp, g, g, d_x + (size_t)v0 * n, 0, nullptr, P);
-    if (c->have_op)
-      launch_op_apply(c, g, P, AP);
-    else
-      launch_matvec(st, 0, n, ldp, b.A, g, P, 0, ldp, nullptr, nullptr, 0, 0.0, AP, ldp, 0);
+    launch_cg_gather(st, nb, nslot, n, g, cg_slots(c), b, d_x + (size_t)v0 * n, P, b.cgred);
+    apply_A(c, P, AP, false);
+    launch_cg_scatter(st, nb, nslot, n, g, cg_slots(c), AP, d_y + (size_t)v0 * n);
     TRY(launched(c, "apply elastance"));
-    HIP_TRY(c, hipMemcpy2DAsync(d_y + (size_t)v0 * n, (size_t)n * sizeof(double), AP,
-                                (size_t)ldp * sizeof(double), (size_t)n * sizeof(double), g,
-                                hipMemcpyDeviceToDevice, st));
   }
   return CPM_OK;
 }
@@ -1408,55 +1453,56 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
   TRY(ensure_cg_buffers(c));
   Buffers& b = c->b;
   hipStream_t st = c->stream;
-  const int n = c->n, ldp = c->npad;
+  const int n = c->n, nslot = cg_nslot(c), nb = cg_grid(c);
+  const int* slots = cg_slots(c);
   double* X = b.cgv;
-  double* R = X + (size_t)CG_MAXG * ldp;
-  double* P = R + (size_t)CG_MAXG * ldp;
-  double* AP = P + (size_t)CG_MAXG * ldp;
+  double* R = X + (size_t)CG_MAXG * nslot;
+  double* P = R + (size_t)CG_MAXG * nslot;
+  double* AP = P + (size_t)CG_MAXG * nslot;
   const double tol2 = tol * tol;
   const size_t bsz = b_is_f32 ? sizeof(float) : sizeof(double);
-  std::vector<double> h_stat(3 * CG_MAXG);
+  const int row_rr = cg_scalar_row(0), row_rr0 = cg_scalar_row(1), row_it = cg_scalar_row(2);
+  std::vector<double> h_scal((size_t)CG_NSCAL * CG_MAXG);
   bool all_conv = true;
   for (int v0 = 0; v0 < batch; v0 += CG_MAXG) {
     const int g = std::min(CG_MAXG, batch - v0);
     const void* bsrc = static_cast<const char*>(d_b) + (size_t)v0 * n * bsz;
-    launch_cg_init(st, g, n, ldp, bsrc, b_is_f32, b.vat, b.cgred, X, R, P, b.cgstat);
+    { Timed t(c, "cg_init");
+      launch_cg_init(st, nb, nslot, n, g, slots, b, bsrc, b_is_f32, X, R, P, b.cgred, b.cgscal); }
     TRY(launched(c, "cg init"));
     int it = 0;
     bool conv = false;
     while (it < maxit && !conv) {
       // a block of iterations between convergence checks; vectors below the
-      // tolerance are frozen by the update kernel
+      // tolerance are frozen (zero step) by the step-length kernel
       const int blk = std::min(8, maxit - it);
       for (int k = 0; k < blk; ++k, ++it) {
         const int cur = it & 1;
-        if (c->have_op) {
-          launch_op_apply(c, g, P, AP);
-        } else {
-          launch_matvec(st, 0, n, ldp, b.A, g, P, 0, ldp, nullptr, nullptr, 0, 0.0, AP, ldp, 0);
-          launch_cg_dots(st, g, n, ldp, P, AP, b.cgred);
-        }
-        launch_cg_update(st, g, n, ldp, cur, tol2, b.cgred, X, R, P, AP, b.cgstat);
-        launch_cg_dir(st, g, n, ldp, cur, tol2, b.cgred, R, P);
+        apply_A(c, P, AP, true);
+        { Timed t(c, "cg_update");
+          launch_cg_update(st, nb, nslot, n, cur, tol2, slots, X, R, P, AP, b.cgred, b.cgscal); }
+        { Timed t(c, "cg_dir");
+          launch_cg_dir(st, nb, nslot, cur, tol2, slots, b, R, P, b.cgred, b.cgscal); }
       }
       TRY(launched(c, "cg iterations"));
-      launch_cg_status(st, g, n, it & 1, b.cgred, b.cgstat);
-      HIP_TRY(c, hipMemcpyAsync(h_stat.data(), b.cgstat, (size_t)3 * g * sizeof(double),
+      HIP_TRY(c, hipMemcpyAsync(h_scal.data(), b.cgscal, h_scal.size() * sizeof(double),
                                 hipMemcpyDeviceToHost, st));
       HIP_TRY(c, hipStreamSynchronize(st));
       conv = true;
       for (int s = 0; s < g; ++s)
-        if (!(h_stat[3 * s] <= tol2 * h_stat[3 * s + 1])) conv = false;
+        if (!(h_scal[(size_t)row_rr * CG_MAXG + s] <= tol2 * h_scal[(size_t)row_rr0 * CG_MAXG + s]))
+          conv = false;
     }
     for (int s = 0; s < g; ++s) {
-      c->cg_iters = std::max(c->cg_iters, (int)h_stat[3 * s + 2]);
-      const double rel = h_stat[3 * s + 1] > 0.0 ? std::sqrt(h_stat[3 * s] / h_stat[3 * s + 1])
-                                                 : (h_stat[3 * s] > 0.0 ? INFINITY : 0.0);
+      const double rr = h_scal[(size_t)row_rr * CG_MAXG + s], rr0 = h_scal[(size_t)row_rr0 * CG_MAXG + s];
+      c->cg_iters = std::max(c->cg_iters, (int)h_scal[(size_t)row_it * CG_MAXG + s]);
+      const double rel = rr0 > 0.0 ? std::sqrt(rr / rr0) : (rr > 0.0 ? INFINITY : 0.0);
       c->cg_resid = std::max(c->cg_resid, std::isnan(rel) ? INFINITY : rel);
     }
     all_conv = all_conv && conv;
-    launch_cg_finish(st, g, n, ldp, X, b.cgred, b.eid, c->n_e, d_q + (size_t)v0 * n,
-                     d_Qe ? d_Qe + (size_t)v0 * c->n_e : nullptr);
+    { Timed t(c, "cg_finish");
+      launch_cg_finish(st, nb, nslot, n, g, slots, X, b.cgred, b.eid, c->n_e,
+                       d_q + (size_t)v0 * n, d_Qe ? d_Qe + (size_t)v0 * c->n_e : nullptr); }
     TRY(launched(c, "cg finish"));
   }
   HIP_TRY(c, hipStreamSynchronize(st));
@@ -1515,6 +1561,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_CG_ITERS: *out = c->cg_iters; return CPM_OK;
     case CPM_INFO_CG_RESID: *out = c->cg_resid; return CPM_OK;
     case CPM_INFO_ELL_WIDTH: *out = c->ell_width; return CPM_OK;
+    case CPM_INFO_NCOLS: *out = c->ncolsort; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -1546,8 +1593,8 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
   dfree(b.Qpair); dfree(b.ell_col); dfree(b.ell_val); dfree(b.plane_off); dfree(b.dextra);
-  dfree(b.cgv); dfree(b.cgred); dfree(b.cgstat); dfree(b.cgphi); dfree(b.cgmom); dfree(b.cgY);
-  dfree(b.cgT);
+  dfree(b.tile_plane); dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);
+  dfree(b.cgscal); dfree(b.cgphi); dfree(b.cgY); dfree(b.cgT);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

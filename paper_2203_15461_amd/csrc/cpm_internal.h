@@ -45,8 +45,9 @@ constexpr int RS_NT = 2048;        // intervals of the real-space pair table on 
 
 constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
 constexpr int MAX_LAYERS = 64;     // planar-electrode factorisation up to this many z planes
-constexpr int CG_MAXG = 32;        // vectors per conjugate-gradient group
-constexpr int CG_RED = 6;          // block partials per vector and block
+constexpr int CG_MAXG = 64;        // vectors per conjugate-gradient group (slot-row width)
+constexpr int CG_RED = 10;         // block partial fields
+constexpr int CG_NSCAL = 4;        // per-vector scalar rows reported to the host
 
 struct Buffers {
   // electrode geometry (internal order = caller order), SoA, x and y wrapped
@@ -103,46 +104,69 @@ struct Buffers {
   double* kpart = nullptr;         // split-K partial slices of the batched split-BF16 GEMM
   double* ccmU = nullptr;          // constrained charges: U = A^-1 G (n x n_e)
   double* ccmC = nullptr;          // C~^-1 (n_e x n_e) followed by the targets Q (n_e)
-  // matrix-free operator and conjugate gradients
+  // matrix-free operator and conjugate gradients (slot space: the atom map
+  // for the operator, atoms padded to npad for the dense A)
   double2* Qpair = nullptr;        // Q_c(L, L') per sorted column, [(c nL + L) nL + L']
-  int* ell_col = nullptr;          // real-space + self part of A in ELL form, [k * n + i]
+  int* ell_col = nullptr;          // real-space + self part of A, ELL rows [slot * width + k]
   double* ell_val = nullptr;
-  int* plane_off = nullptr;        // nlayers + 1 offsets of the planes in amap
+  int* plane_off = nullptr;        // nlayers + 1 slot offsets of the planes
+  int* tile_plane = nullptr;       // plane of each 64-slot tile
+  double* Ecat = nullptr;          // in-plane phases, (2 ncp) x nslot real matrix
+  int* cg_ident = nullptr;         // identity slot map of the dense A (npad, -1 pads)
   double* dextra = nullptr;        // diagonal extra (n)
-  double* cgv = nullptr;           // x, r, p, Ap (4 x CG_MAXG x npad)
-  double* cgred = nullptr;         // block partials (CG_MAXG x blocks x CG_RED)
-  double* cgstat = nullptr;        // per vector: r.r, r0.r0, iterations
-  double* cgphi = nullptr;         // column-group partial k-space potentials
-  double* cgmom = nullptr;         // partials of sum p, sum p x, sum p y, sum p z
-  double2* cgY = nullptr;          // plane sums Y(c, L)
-  double2* cgT = nullptr;          // T(c, L)
+  double* cgv = nullptr;           // X, R, P, AP: 4 x nslot x CG_MAXG (slot-major)
+  double* cgred = nullptr;         // block partials
+  double* cgscal = nullptr;        // per-vector r.r, r0.r0, iterations (CG_NSCAL x CG_MAXG)
+  double* cgphi = nullptr;         // k-space potentials (nslot x CG_MAXG)
+  double* cgY = nullptr;           // plane sums (nlayers x 2 ncp x CG_MAXG)
+  double* cgT = nullptr;           // plane-mixed sums (same shape)
   size_t kpart_len = 0;
   int bpad_rows = 0;
   double* scal = nullptr;          // small scalars (s and friends)
 };
 
-// matrix-free operator and conjugate gradients (cg.hip)
-// real-space + self part of A in ELL form: count per (j chunk, atom)
-// cnt[chunk * n + i], then fill from offsets off[chunk * n + i] (entries of a
-// row in ascending j; padding col = i, val = 0)
-void launch_ell_count(hipStream_t st, int n, int jchunks, const Buffers& b, double Lx, double Ly,
-                      double Lz, double rc, int* cnt);
-void launch_ell_fill(hipStream_t st, int n, int jchunks, int width, const int* off,
-                     const Buffers& b, double Lx, double Ly, double Lz, double rc, double alpha,
-                     double eta_ee, double diag_self, int* col, double* val);
-void launch_op_apply(cpm_ctx* c, int g, const double* P, double* AP);
-void launch_cg_dots(hipStream_t st, int g, int n, int ldp, const double* P, const double* AP,
-                    double* red);
-void launch_cg_init(hipStream_t st, int g, int n, int ldp, const void* b, int b_is_f32,
-                    const double* vat, double* red, double* X, double* R, double* P, double* stat);
-void launch_cg_update(hipStream_t st, int g, int n, int ldp, int cur, double tol2,
-                      double* red, double* X, double* R, const double* P, const double* AP,
-                      double* stat);
-void launch_cg_dir(hipStream_t st, int g, int n, int ldp, int cur, double tol2, const double* red,
-                   const double* R, double* P);
-void launch_cg_status(hipStream_t st, int g, int n, int cur, const double* red, double* stat);
-void launch_cg_finish(hipStream_t st, int g, int n, int ldp, const double* X, double* red,
-                      const int* eid, int n_e, double* q, double* Qe);
+// matrix-free operator and conjugate gradients (cg.hip); vectors are
+// slot-major rows of CG_MAXG, slot_atom maps slots to atoms (-1 pads)
+int cg_blocks(int nslot, int cap);
+int cg_scalar_row(int which);      // 0: r.r, 1: r0.r0, 2: iterations
+// real-space + self part of A in ELL form over slots: count per (slot chunk,
+// row) cnt[chunk * nslot + r], then fill from offsets off[chunk * nslot + r]
+// (entries of a row in ascending slot; padding col = own slot, val = 0)
+void launch_ell_count(hipStream_t st, int nslot, int jchunks, const int* slot_atom,
+                      const Buffers& b, double Lx, double Ly, double Lz, double rc, int* cnt);
+void launch_ell_fill(hipStream_t st, int nslot, int jchunks, int width, const int* slot_atom,
+                     const int* off, const Buffers& b, double Lx, double Ly, double Lz, double rc,
+                     double alpha, double eta_ee, double diag_self, int* col, double* val);
+void launch_cg_ephase(hipStream_t st, int nslot, int ncp, int ncolsort, const int* slot_atom,
+                      const Buffers& b, double* Ecat);
+// k space of A p: plane sums Y (MFMA), plane mixing T, projection Phi (MFMA)
+void launch_cg_plane_sums(hipStream_t st, int nslot, int ncp, int nlayers, const int* plane_off,
+                          const double* Ecat, const double* P, double* Y);
+void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, const double2* Q,
+                         const double* Y, double* T);
+void launch_cg_project(hipStream_t st, int nslot, int ncp, const int* tile_plane,
+                       const double* Ecat, const double* T, double* Phi);
+// The kernels below share one grid of nblk blocks; each sums the partials
+// of the previous one.  AP (operator; dense: AP given) with partials of p.Ap.
+void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, const int* slot_atom,
+                     const Buffers& b, int width, const double* Phi, double background,
+                     const double* cdip, double ke, const double* P, double* AP, double* red);
+// x, r update (cur: parity of the iteration), then p and its moments
+void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2,
+                      const int* slot_atom, double* X, double* R, const double* P,
+                      const double* AP, double* red, double* scal);
+void launch_cg_dir(hipStream_t st, int nblk, int nslot, int cur, double tol2, const int* slot_atom,
+                   const Buffers& b, const double* R, double* P, double* red, double* scal);
+void launch_cg_init(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                    const Buffers& b, const void* bsrc, int b_is_f32, double* X, double* R,
+                    double* P, double* red, double* scal);
+void launch_cg_gather(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                      const Buffers& b, const double* x, double* P, double* red);
+void launch_cg_scatter(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                       const double* V, double* y);
+void launch_cg_finish(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
+                      const double* X, double* red, const int* eid, int n_e, double* q,
+                      double* Qe);
 
 }  // namespace cpm
 
@@ -156,7 +180,8 @@ struct cpm_ctx {
   int cg_iters = 0;                // last cpm_solve_cg: iterations, max relative residual
   double cg_resid = 0.0;
   int ell_width = 0;               // entries per row of the real-space ELL part
-  int op_cgroups = 1;              // column groups of the operator's k-space projection
+  int ncp = 0;                     // columns of the operator's k-space products (ncolsort
+                                   // rounded up to 32)
   int n = 0, npad = 0, n_e = 0, m = 0;
   double Lz = 0, V = 0, kc = 0, ke = 0;
   double cdip[3] = {0, 0, 0};      // dipole term A += k_e sum_d cdip_d r_d r_d^T (geometry)
@@ -333,11 +358,7 @@ void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlay
                             const double* dip, int dip_blocks, const double* cdip, double ke,
                             void* out, int out_is_f32);
 int layer_combine_max_group();
-// k-space potentials of g configurations from T(c, L) only (no final sum):
-// part[(cg * g + s) * n + i]
-void launch_layer_project_groups(hipStream_t st, int g, int n, int ncolsort, int nlayers,
-                                 int cgroups, const double2* E, const int* layer_of,
-                                 const double2* T, double* part);
+
 int sf_table_rows(int nxm, int nym, int nbz);
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
                         const double* w2, double* sfw);
