@@ -352,7 +352,7 @@ def matvec_roofline(ctx, w, xyz, dev, reps=20):
     return out
 
 
-CG_FAMILIES = ("cg_plane_sums", "cg_plane_mix", "cg_project", "cg_apply", "cg_update", "cg_dir",
+CG_FAMILIES = ("cg_plane_sums", "cg_plane_mix", "cg_tiles", "cg_apply", "cg_update", "cg_dir",
                "cg_init", "cg_finish")
 
 
@@ -367,7 +367,6 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     import torch
     from paper_2203_15461_amd import cpm
     n = w.n
-    B = min(B, xyz.shape[0])
     ctx = cpm.Context(cpm.Params.of(w))
     ctx.set_electrolyte(w.electrolyte_q)
     R = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device=dev).contiguous()
@@ -378,6 +377,9 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     ctx.set_potential(w.v_electrode)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - ts
+    if xyz.shape[0] < B:                             # one full CG group of configurations
+        from paper_2203_15461_amd import inputs as I
+        xyz = synthetic_configurations(w, B, I.BASE_SEED + 2, dev)
     b = torch.empty((B, n), dtype=torch.float64, device=dev)
     ctx.potential_vector(xyz[:B], b)
     q = torch.empty_like(b)
@@ -402,10 +404,14 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     nslot = int(sum(-(-c // 64) * 64 for c in np.bincount(
         np.searchsorted(np.unique(w.electrode_xyz[:, 2]), w.electrode_xyz[:, 2]))))
     vec = nslot * 64 * 8                             # one slot-major block of 64 vectors
+    nb = int(ctx.info("bsr_blocks"))
     work = {   # (algorithmic HBM bytes, FP64 flops) per launch
         "cg_plane_sums": (m2 * nslot * 8 + vec + nl * m2 * 64 * 8, 2.0 * m2 * nslot * 64),
-        "cg_project": (m2 * nslot * 8 + nl * m2 * 64 * 8 + vec, 2.0 * m2 * nslot * 64),
-        "cg_apply": (width * nslot * 12 + 3 * vec, 2.0 * width * nslot * 64),
+        # projection (phase matrix, T, output) + block-sparse real space
+        # (64 x 64 FP64 blocks, the vector block): flops 2 K per output
+        "cg_tiles": (m2 * nslot * 8 + nl * m2 * 64 * 8 + vec + nb * 4096 * 8 + vec,
+                     2.0 * m2 * nslot * 64 + 2.0 * nb * 64 * 64 * 64),
+        "cg_apply": (3 * vec, 0.0),
         "cg_update": (6 * vec, 0.0),
         "cg_dir": (3 * vec, 0.0),
     }
@@ -426,7 +432,7 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     dom = max(per_iter, key=lambda f: per_iter[f]["us"] * per_iter[f]["launches"])
     out = {"solves_per_s": B / call_s, "ms_per_call": call_s * 1e3, "vectors_per_call": B,
            "tol": tol, "iterations": iters, "residual": resid, "operator_setup_s": setup_s,
-           "ell_width": width, "columns": nc, "planes": nl, "slots": nslot,
+           "ell_width": width, "bsr_blocks": nb, "columns": nc, "planes": nl, "slots": nslot,
            "max_rel_diff_vs_direct_fp64": dev_rel,
            "max_abs_sum_q": float(q.sum(dim=1).abs().max().item()),
            "per_launch": per_iter, "dominant": dom,

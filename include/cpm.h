@@ -107,7 +107,8 @@ enum {
   CPM_INFO_CG_RESID = 19,     /*   ... largest final |r| / |r0|                   */
   CPM_INFO_ELL_WIDTH = 20,    /* entries per row of the operator's real-space     */
                               /* part (cpm_build_operator)                        */
-  CPM_INFO_NCOLS = 21         /* (k_x, k_y) columns of the matrix-core k set      */
+  CPM_INFO_NCOLS = 21,        /* (k_x, k_y) columns of the matrix-core k set      */
+  CPM_INFO_BSR_BLOCKS = 22    /* 64 x 64 blocks of the operator's real space      */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -154,9 +155,10 @@ cpm_status cpm_build_elastance(cpm_ctx* ctx, int n, const double* d_xyz,
  * inverting A (and Sec. IV as future work): the same electrode set-up and
  * arguments as cpm_build_elastance, but A is never formed.  Keeps the
  * real-space and self terms as a sparse matrix (ELL: one entry per electrode
- * pair with a periodic image within r_c, CPM_INFO_ELL_WIDTH per row), and
- * applies the k-space term through the electrode planes (memory
- * O(n x columns) for the in-plane phases, which the planar b path shares).
+ * pair with a periodic image within r_c, at most CPM_INFO_ELL_WIDTH per
+ * atom) stored as dense 64 x 64 blocks of interacting 64-atom tiles
+ * (CPM_INFO_BSR_BLOCKS), and applies the k-space term through the electrode
+ * planes (memory O(n x columns) for the in-plane phases).
  * Needs electrodes on at most 64 z planes and the matrix-core k set
  * (CPM_INFO_NLAYERS > 0, CPM_INFO_SF_MATRIX = 1), else CPM_EUNSUPPORTED.
  * A context holds either the dense elastance or the operator (CPM_ESTATE).

@@ -6,8 +6,11 @@
 // gradients on the neutral subspace (projector P = I - e e^T / n) need only
 // products A p, never A^-1 or S:
 //   * real space + Gaussian self term: a fixed sparse matrix (every pair with
-//     some periodic image within r_c), kept in ELL form and evaluated with the
-//     same expression as the dense assembly;
+//     some periodic image within r_c), evaluated with the same expression as
+//     the dense assembly, first as ELL rows and then kept as dense 64 x 64
+//     blocks of the slot tiles that interact (the atoms of a plane are
+//     ordered in compact 64-atom tiles), applied as FP64 matrix-core products
+//     fused with the k-space projection;
 //   * k space for electrodes on z planes: with E_j(c) = e^{i (kx x_j + ky y_j)}
 //     and Q_c(L, L') = sum_n 2W(c, n) e^{i n kz1 (z_L - z_L')},
 //       (A_k p)_i = k_e sum_c Re[conj(E_i(c)) T(c, L_i)],
@@ -218,68 +221,40 @@ __global__ void k_cg_ephase(int nslot, int ncolsort, const int* __restrict__ slo
   Ecat[(size_t)(2 * c + 1) * nslot + r] = sn;
 }
 
-// ---- k space on matrix cores -------------------------------------------------
-// 64 x 64 output tile per 256-thread workgroup (rows m, vectors s), 4 waves in
-// 2 x 2 quadrants of 2 x 2 v_mfma_f64_16x16x4f64 blocks, K staged through LDS
-// in slabs of 16 with the next slab held in registers.
-//   PROJ = false (plane sums): tile (m0 = 64 bx, plane L = by); K = the slots
-//     of plane L; A(m, k) = Ecat[m nslot + k], B(k, s) = P[k VL + s];
-//     Y[(L M2 + m) VL + s] = sum_k A B.
-//   PROJ = true (projection): slot tile m0 = 64 bx lies in plane L =
-//     tile_plane[bx]; K = M2; A(m, k) = Ecat[k nslot + m], B(k, s) =
-//     T[(L M2 + k) VL + s];  Phi[m VL + s] = sum_k A B.
-// MFMA operand layout (lane l): A (row l % 16, k l / 16), B (k l / 16,
-// col l % 16); result register q: (row l / 16 + 4 q, col l % 16).
+// ---- k space and real space on matrix cores ---------------------------------
+// 64 x 64 output tiles (64 slot or column rows m, 64 vectors s) per 256-thread
+// workgroup: 4 waves in 2 x 2 quadrants of 2 x 2 v_mfma_f64_16x16x4f64
+// blocks, K staged through LDS in slabs of 16 with the next slab held in
+// registers.  MFMA operand layout (lane l): A (row l % 16, k l / 16), B
+// (k l / 16, col l % 16); result register q: (row l / 16 + 4 q, col l % 16).
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-template <bool PROJ>
-__global__ void __launch_bounds__(256) k_cg_kgemm(int nslot, int M2,
-                                                  const int* __restrict__ plane_off,
-                                                  const int* __restrict__ tile_plane,
-                                                  const double* __restrict__ Ecat,
-                                                  const double* __restrict__ Bsrc,
-                                                  double* __restrict__ C) {
-  __shared__ double As[16][64 + 4];
-  __shared__ double Bs[16][64 + 4];
+// acc += A (64 x K) B (K x 64) for one segment, K a multiple of 16.
+// A(m, k) = A[m lda + k] (ACOL = false) or A[k lda + m] (ACOL = true);
+// B(k, s) = B[k VL + s].
+template <bool ACOL>
+__device__ void seg_mfma(v4d (&acc)[2][2], const double* __restrict__ A, size_t lda,
+                         const double* __restrict__ B, int K, double (*As)[68],
+                         double (*Bs)[68]) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  const int m0 = blockIdx.x * 64;
-  int kb, ke;
-  const double* Bp;
-  double* Cp;
-  if (!PROJ) {
-    const int L = blockIdx.y;
-    kb = plane_off[L];
-    ke = plane_off[L + 1];
-    Bp = Bsrc;
-    Cp = C + (size_t)L * M2 * VL;
-  } else {
-    const int L = tile_plane[blockIdx.x];
-    kb = 0;
-    ke = M2;
-    Bp = Bsrc + (size_t)L * M2 * VL;
-    Cp = C;
-  }
-  v4d acc[2][2];
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
   double ra[4], rb[4];
   auto load = [&](int k0) {
-    if (!PROJ) {
-      const int r = tid >> 2, c = (tid & 3) * 4;          // A rows m0 + r, k0 + c ..
-      const double* src = Ecat + (size_t)(m0 + r) * nslot + k0 + c;
+    if (!ACOL) {
+      const int r = tid >> 2, c = (tid & 3) * 4;
+      const double* src = A + (size_t)r * lda + k0 + c;
       for (int t = 0; t < 4; ++t) ra[t] = src[t];
     } else {
-      const int r = tid >> 4, c = (tid & 15) * 4;         // A^T rows k0 + r, m0 + c ..
-      const double* src = Ecat + (size_t)(k0 + r) * nslot + m0 + c;
+      const int r = tid >> 4, c = (tid & 15) * 4;
+      const double* src = A + (size_t)(k0 + r) * lda + c;
       for (int t = 0; t < 4; ++t) ra[t] = src[t];
     }
     const int r = tid >> 4, c = (tid & 15) * 4;
-    const double* src = Bp + (size_t)(k0 + r) * VL + c;
+    const double* src = B + (size_t)(k0 + r) * VL + c;
     for (int t = 0; t < 4; ++t) rb[t] = src[t];
   };
   auto store = [&]() {
-    if (!PROJ) {
+    if (!ACOL) {
       const int r = tid >> 2, c = (tid & 3) * 4;
       for (int t = 0; t < 4; ++t) As[c + t][r] = ra[t];
     } else {
@@ -289,11 +264,11 @@ __global__ void __launch_bounds__(256) k_cg_kgemm(int nslot, int M2,
     const int r = tid >> 4, c = (tid & 15) * 4;
     for (int t = 0; t < 4; ++t) Bs[r][c + t] = rb[t];
   };
-  if (kb < ke) load(kb);
-  for (int k0 = kb; k0 < ke; k0 += 16) {
+  if (K > 0) load(0);
+  for (int k0 = 0; k0 < K; k0 += 16) {
     store();
     __syncthreads();
-    if (k0 + 16 < ke) load(k0 + 16);
+    if (k0 + 16 < K) load(k0 + 16);
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
       const int kr = kk + (lane >> 4), cc = lane & 15;
@@ -306,19 +281,47 @@ __global__ void __launch_bounds__(256) k_cg_kgemm(int nslot, int M2,
     }
     __syncthreads();
   }
+}
+
+__device__ inline void store_tile(const v4d (&acc)[2][2], double* __restrict__ C) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int q = 0; q < 4; ++q) {
-        const int row = m0 + wm + a * 16 + (lane >> 4) + 4 * q;
+        const int row = wm + a * 16 + (lane >> 4) + 4 * q;
         const int s = wn + b * 16 + (lane & 15);
-        Cp[(size_t)row * VL + s] = acc[a][b][q];
+        C[(size_t)row * VL + s] = acc[a][b][q];
       }
 }
 
+// Plane sums, split over the slots of each plane: workgroup (m tile bx,
+// plane L = by, part bz) adds the slots [kb, ke) of its part of plane L:
+//   Y[((part nL + L) M2 + m) VL + s] = sum_k Ecat[m][k] P[k][s].
+__global__ void __launch_bounds__(256) k_cg_plane_sums(int nslot, int M2, int nlayers, int ksplit,
+                                                       const int* __restrict__ plane_off,
+                                                       const double* __restrict__ Ecat,
+                                                       const double* __restrict__ P,
+                                                       double* __restrict__ Y) {
+  __shared__ double As[16][68];
+  __shared__ double Bs[16][68];
+  const int m0 = blockIdx.x * 64, L = blockIdx.y, part = blockIdx.z;
+  const int q16 = (plane_off[L + 1] - plane_off[L]) / 16;
+  const int kb = plane_off[L] + (q16 * part / ksplit) * 16;
+  const int ke = plane_off[L] + (q16 * (part + 1) / ksplit) * 16;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  seg_mfma<false>(acc, Ecat + (size_t)m0 * nslot + kb, nslot, P + (size_t)kb * VL, ke - kb, As, Bs);
+  store_tile(acc, Y + (((size_t)part * nlayers + L) * M2 + m0) * VL);
+}
+
 // T for every plane: Tcat[(L M2 + 2c) VL + s] = Re, [.. 2c + 1 ..] = Im of
-// sum_L' Q_c(L', L) Y(c, L', s); zero rows for padding columns
-__global__ void k_cg_plane_mix(int nlayers, int ncp, int ncolsort, const double2* __restrict__ Q,
-                               const double* __restrict__ Y, double* __restrict__ T) {
+// sum_L' Q_c(L', L) Y(c, L', s) (Y: the sum of its ksplit parts, in order);
+// zero rows for padding columns
+__global__ void k_cg_plane_mix(int nlayers, int ncp, int ncolsort, int ksplit,
+                               const double2* __restrict__ Q, const double* __restrict__ Y,
+                               double* __restrict__ T) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)nlayers * ncp * VL) return;
   const int s = (int)(e % VL), c = (int)((e / VL) % ncp), L = (int)(e / ((size_t)VL * ncp));
@@ -326,14 +329,52 @@ __global__ void k_cg_plane_mix(int nlayers, int ncp, int ncolsort, const double2
   double tr = 0.0, ti = 0.0;
   if (c < ncolsort) {
     for (int L2 = 0; L2 < nlayers; ++L2) {
+      double yr = 0.0, yi = 0.0;
+      for (int p = 0; p < ksplit; ++p) {
+        const double* y = Y + (((size_t)p * nlayers + L2) * M2 + 2 * c) * VL + s;
+        yr += y[0];
+        yi += y[VL];
+      }
       const double2 q = Q[((size_t)c * nlayers + L2) * nlayers + L];
-      const double yr = Y[(L2 * M2 + 2 * c) * VL + s], yi = Y[(L2 * M2 + 2 * c + 1) * VL + s];
       tr += q.x * yr - q.y * yi;
       ti += q.x * yi + q.y * yr;
     }
   }
   T[(L * M2 + 2 * c) * VL + s] = tr;
   T[(L * M2 + 2 * c + 1) * VL + s] = ti;
+}
+
+// Projection and real space per slot tile, one work item per workgroup:
+// item = {tile, kind, begin, end, part, plane}.
+//   kind 0: k-space projection over columns rows [begin, end) of the phase
+//     matrix: Phi_part[tile rows] = Ecat[begin:end, tile]^T T[plane][begin:end];
+//   kind 1: real space over the tile's blocks [begin, end) of the 64 x 64
+//     block-sparse part R: Phi_part[tile rows] = sum_b R_b P[col tile of b].
+// The parts of a tile are added in order by the apply kernel.
+__global__ void __launch_bounds__(256) k_cg_tiles(int nslot, int M2,
+                                                  const int* __restrict__ items,
+                                                  const double* __restrict__ Ecat,
+                                                  const double* __restrict__ T,
+                                                  const int* __restrict__ bcol,
+                                                  const double* __restrict__ bval,
+                                                  const double* __restrict__ P,
+                                                  double* __restrict__ Phi) {
+  __shared__ double As[16][68];
+  __shared__ double Bs[16][68];
+  const int* it = items + 6 * blockIdx.x;
+  const int tile = it[0], kind = it[1], beg = it[2], end = it[3], part = it[4], L = it[5];
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  if (kind == 0) {
+    seg_mfma<true>(acc, Ecat + (size_t)beg * nslot + (size_t)tile * 64, nslot,
+                   T + ((size_t)L * M2 + beg) * VL, end - beg, As, Bs);
+  } else {
+    for (int b = beg; b < end; ++b)
+      seg_mfma<false>(acc, bval + (size_t)b * 64 * 64, 64, P + (size_t)bcol[b] * 64 * VL, 64, As,
+                      Bs);
+  }
+  store_tile(acc, Phi + ((size_t)part * nslot + (size_t)tile * 64) * VL);
 }
 
 // ---- A p and the conjugate-gradient steps ---------------------------------
@@ -354,16 +395,16 @@ __device__ inline void store_moments(const double (&m)[4], double* __restrict__ 
   store_partials<4>(m, f, red);
 }
 
-// Ap = k_e (Phi + ELL real space + background M0 + sum_d c_d r_d M_d) +
-// diag_extra p (operator; DENSE: Ap given), pad slots 0; block partials of
-// p.Ap and sum Ap.  M: the moments of p from the kernel that wrote p.
+// Ap = k_e (sum of the Phi parts (k space + real space) + background M0 +
+// sum_d c_d r_d M_d) + diag_extra p (operator; DENSE: Ap given), pad slots
+// 0; block partials of p.Ap and sum Ap.  M: the moments of p from the kernel
+// that wrote p.
 template <bool DENSE>
 __global__ void __launch_bounds__(CG_BLK) k_cg_apply(
     int nslot, int n, const int* __restrict__ slot_atom, const double* __restrict__ ex,
     const double* __restrict__ ey, const double* __restrict__ ez,
-    const double* __restrict__ dextra, int width, const int* __restrict__ ecol,
-    const double* __restrict__ evals, const double* __restrict__ Phi, double background,
-    double cx, double cy, double cz, double ke, const double* __restrict__ P,
+    const double* __restrict__ dextra, int nparts, const double* __restrict__ Phi,
+    double background, double cx, double cy, double cz, double ke, const double* __restrict__ P,
     double* __restrict__ AP, double* __restrict__ red) {
   __shared__ double M[4][VL];
   const int s = threadIdx.x & 63;
@@ -380,21 +421,10 @@ __global__ void __launch_bounds__(CG_BLK) k_cg_apply(
       if (DENSE) {
         ap = AP[(size_t)r * VL + s];
       } else {
-        // width is a multiple of 8: 8 (column, value) pairs per step come
-        // in as wave-uniform scalar loads
-        const int* cr = ecol + (size_t)r * width;
-        const double* vr = evals + (size_t)r * width;
-        double a[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int k = 0; k < width; k += 8) {
-          double pv8[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) pv8[u] = P[(size_t)cr[k + u] * VL + s];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) a[u & 3] += vr[k + u] * pv8[u];
-        }
-        ap = ke * ((Phi[(size_t)r * VL + s] + ((a[0] + a[1]) + (a[2] + a[3]))) +
-                   (background * M[0][s] +
-                    (cx * ex[i] * M[1][s] + cy * ey[i] * M[2][s] + cz * ez[i] * M[3][s]))) +
+        double phi = 0.0;
+        for (int q = 0; q < nparts; ++q) phi += Phi[((size_t)q * nslot + r) * VL + s];
+        ap = ke * (phi + (background * M[0][s] +
+                          (cx * ex[i] * M[1][s] + cy * ey[i] * M[2][s] + cz * ez[i] * M[3][s]))) +
              dextra[i] * pv;
       }
     }
@@ -643,36 +673,37 @@ void launch_cg_ephase(hipStream_t st, int nslot, int ncp, int ncolsort, const in
                      ncolsort, slot_atom, b.sc_nx, b.sc_ny, b.efx, b.efy, Ecat);
 }
 
-void launch_cg_plane_sums(hipStream_t st, int nslot, int ncp, int nlayers, const int* plane_off,
-                          const double* Ecat, const double* P, double* Y) {
-  hipLaunchKernelGGL(k_cg_kgemm<false>, dim3(2 * ncp / 64, nlayers), dim3(256), 0, st, nslot,
-                     2 * ncp, plane_off, nullptr, Ecat, P, Y);
+void launch_cg_plane_sums(hipStream_t st, int nslot, int ncp, int nlayers, int ksplit,
+                          const int* plane_off, const double* Ecat, const double* P, double* Y) {
+  hipLaunchKernelGGL(k_cg_plane_sums, dim3(2 * ncp / 64, nlayers, ksplit), dim3(256), 0, st, nslot,
+                     2 * ncp, nlayers, ksplit, plane_off, Ecat, P, Y);
 }
 
-void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, const double2* Q,
-                         const double* Y, double* T) {
+void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, int ksplit,
+                         const double2* Q, const double* Y, double* T) {
   const size_t tot = (size_t)nlayers * ncp * VL;
   hipLaunchKernelGGL(k_cg_plane_mix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
-                     nlayers, ncp, ncolsort, Q, Y, T);
+                     nlayers, ncp, ncolsort, ksplit, Q, Y, T);
 }
 
-void launch_cg_project(hipStream_t st, int nslot, int ncp, const int* tile_plane,
-                       const double* Ecat, const double* T, double* Phi) {
-  hipLaunchKernelGGL(k_cg_kgemm<true>, dim3(nslot / 64), dim3(256), 0, st, nslot, 2 * ncp, nullptr,
-                     tile_plane, Ecat, T, Phi);
+void launch_cg_tiles(hipStream_t st, int nitems, int nslot, int ncp, const int* items,
+                     const double* Ecat, const double* T, const int* bcol, const double* bval,
+                     const double* P, double* Phi) {
+  hipLaunchKernelGGL(k_cg_tiles, dim3(nitems), dim3(256), 0, st, nslot, 2 * ncp, items, Ecat, T,
+                     bcol, bval, P, Phi);
 }
 
 void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, const int* slot_atom,
-                     const Buffers& b, int width, const double* Phi, double background,
+                     const Buffers& b, int nparts, const double* Phi, double background,
                      const double* cdip, double ke, const double* P, double* AP, double* red) {
   if (dense)
     hipLaunchKernelGGL(k_cg_apply<true>, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, slot_atom,
-                       b.ex, b.ey, b.ez, b.dextra, width, b.ell_col, b.ell_val, Phi, background,
-                       cdip[0], cdip[1], cdip[2], ke, P, AP, red);
+                       b.ex, b.ey, b.ez, b.dextra, nparts, Phi, background, cdip[0], cdip[1],
+                       cdip[2], ke, P, AP, red);
   else
     hipLaunchKernelGGL(k_cg_apply<false>, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, slot_atom,
-                       b.ex, b.ey, b.ez, b.dextra, width, b.ell_col, b.ell_val, Phi, background,
-                       cdip[0], cdip[1], cdip[2], ke, P, AP, red);
+                       b.ex, b.ey, b.ez, b.dextra, nparts, Phi, background, cdip[0], cdip[1],
+                       cdip[2], ke, P, AP, red);
 }
 
 void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2,

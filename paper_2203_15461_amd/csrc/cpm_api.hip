@@ -203,11 +203,14 @@ void apply_A(cpm_ctx* c, const double* P, double* AP, bool partials) {
   const int n = c->n, nslot = cg_nslot(c), nblk = cg_grid(c);
   if (c->have_op) {
     { Timed t(c, "cg_plane_sums");
-      launch_cg_plane_sums(st, nslot, c->ncp, c->nlayers, b.plane_off, b.Ecat, P, b.cgY); }
+      launch_cg_plane_sums(st, nslot, c->ncp, c->nlayers, c->cg_ksplit, b.plane_off, b.Ecat, P,
+                           b.cgY); }
     { Timed t(c, "cg_plane_mix");
-      launch_cg_plane_mix(st, c->ncp, c->ncolsort, c->nlayers, b.Qpair, b.cgY, b.cgT); }
-    { Timed t(c, "cg_project");
-      launch_cg_project(st, nslot, c->ncp, b.tile_plane, b.Ecat, b.cgT, b.cgphi); }
+      launch_cg_plane_mix(st, c->ncp, c->ncolsort, c->nlayers, c->cg_ksplit, b.Qpair, b.cgY,
+                          b.cgT); }
+    { Timed t(c, "cg_tiles");
+      launch_cg_tiles(st, c->cg_nitems, nslot, c->ncp, b.cg_items, b.Ecat, b.cgT, b.bsr_col,
+                      b.bsr_val, P, b.cgphi); }
   } else {
     Timed t(c, "cg_gemm_dense");
     launch_gemm_f64(st, false, false, nslot, CG_MAXG, nslot, 1.0, b.A, c->npad, P, CG_MAXG, 0.0,
@@ -215,7 +218,7 @@ void apply_A(cpm_ctx* c, const double* P, double* AP, bool partials) {
   }
   if (c->have_op || partials) {
     Timed t(c, "cg_apply");
-    launch_cg_apply(st, !c->have_op, nblk, nslot, n, cg_slots(c), b, c->ell_width, b.cgphi,
+    launch_cg_apply(st, !c->have_op, nblk, nslot, n, cg_slots(c), b, c->cg_nparts, b.cgphi,
                     c->op_background, c->cdip, c->ke, P, AP, b.cgred);
   }
 }
@@ -238,8 +241,11 @@ cpm_status ensure_cg_buffers(cpm_ctx* c) {
   TRY(dalloc(c, &b.cgscal, (size_t)CG_NSCAL * CG_MAXG));
   HIP_TRY(c, hipMemset(b.cgscal, 0, (size_t)CG_NSCAL * CG_MAXG * sizeof(double)));
   if (c->have_op) {
-    TRY(dalloc(c, &b.cgphi, (size_t)nslot * CG_MAXG));
-    TRY(dalloc(c, &b.cgY, (size_t)c->nlayers * 2 * c->ncp * CG_MAXG));
+    // parts a tile's work items do not use stay zero
+    const size_t phi = (size_t)c->cg_nparts * nslot * CG_MAXG;
+    TRY(dalloc(c, &b.cgphi, phi));
+    HIP_TRY(c, hipMemset(b.cgphi, 0, phi * sizeof(double)));
+    TRY(dalloc(c, &b.cgY, (size_t)c->cg_ksplit * c->nlayers * 2 * c->ncp * CG_MAXG));
     TRY(dalloc(c, &b.cgT, (size_t)c->nlayers * 2 * c->ncp * CG_MAXG));
   }
   return CPM_OK;
@@ -626,6 +632,20 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
         per[std::lower_bound(zs.begin(), zs.end(), c->h_xyz[3 * i + 2]) - zs.begin()].push_back(i);
       c->h_plane_rows.clear();
       for (auto& v : per) {
+        // spatially compact 64-atom tiles: serpentine strips along x about
+        // one tile (64 atoms at the plane's density) wide, y within a strip
+        // (only the order inside the plane changes; every sum over an atom's
+        // partners keeps its own fixed order)
+        const double Lx = c->p.Lx, Ly = c->p.Ly;
+        const double side = std::sqrt(64.0 * Lx * Ly / std::max<size_t>(v.size(), 1));
+        const int nb = std::max(1, (int)std::lround(Lx / side));
+        auto key = [&](int i) {
+          const double x = c->h_xyz[3 * i] - Lx * std::floor(c->h_xyz[3 * i] / Lx);
+          const double y = c->h_xyz[3 * i + 1] - Ly * std::floor(c->h_xyz[3 * i + 1] / Ly);
+          const int bx = std::min(nb - 1, (int)(x / (Lx / nb)));
+          return std::make_pair(bx, (bx & 1) ? -y : y);
+        };
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b2) { return key(a) < key(b2); });
         const size_t before = amap.size();
         amap.insert(amap.end(), v.begin(), v.end());
         while (amap.size() % 64) amap.push_back(-1);
@@ -670,9 +690,6 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     const int nslot = c->nmap;                    // slots: the atom map (64-slot plane tiles)
     TRY(dalloc(c, &b.plane_off, poff.size()));
     HIP_TRY(c, hipMemcpy(b.plane_off, poff.data(), poff.size() * sizeof(int), hipMemcpyHostToDevice));
-    TRY(dalloc(c, &b.tile_plane, tplane.size()));
-    HIP_TRY(c, hipMemcpy(b.tile_plane, tplane.data(), tplane.size() * sizeof(int),
-                         hipMemcpyHostToDevice));
     // in-plane phases in slot order for the k-space products
     c->ncp = (c->ncolsort + 31) / 32 * 32;
     TRY(dalloc(c, &b.Ecat, (size_t)2 * c->ncp * nslot));
@@ -710,6 +727,78 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
       TRY(launched(c, "ell fill"));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
       dfree(c, cnt);
+    }
+    {
+      // the ELL rows as dense 64 x 64 blocks of interacting slot tiles
+      // (block columns ascending within a tile row)
+      const int T = nslot / 64, width = c->ell_width;
+      std::vector<int> hcol((size_t)width * nslot);
+      std::vector<double> hval((size_t)width * nslot);
+      HIP_TRY(c, hipMemcpy(hcol.data(), b.ell_col, hcol.size() * sizeof(int), hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy(hval.data(), b.ell_val, hval.size() * sizeof(double), hipMemcpyDeviceToHost));
+      std::vector<int> bptr(T + 1, 0), bcol, pos(T, -1);
+      std::vector<double> bval;
+      for (int I = 0; I < T; ++I) {
+        std::vector<int> js;
+        for (int r = I * 64; r < I * 64 + 64; ++r)
+          for (int k = 0; k < width; ++k)
+            if (hval[(size_t)r * width + k] != 0.0) {
+              const int J = hcol[(size_t)r * width + k] / 64;
+              if (pos[J] < 0) { pos[J] = 0; js.push_back(J); }
+            }
+        std::sort(js.begin(), js.end());
+        const size_t base = bcol.size();
+        for (size_t q = 0; q < js.size(); ++q) { pos[js[q]] = (int)(base + q); bcol.push_back(js[q]); }
+        bval.resize(bcol.size() * 4096, 0.0);
+        for (int r = I * 64; r < I * 64 + 64; ++r)
+          for (int k = 0; k < width; ++k) {
+            const double v = hval[(size_t)r * width + k];
+            if (v == 0.0) continue;
+            const int col = hcol[(size_t)r * width + k];
+            bval[(size_t)pos[col / 64] * 4096 + (size_t)(r % 64) * 64 + col % 64] = v;
+          }
+        for (int J : js) pos[J] = -1;
+        bptr[I + 1] = (int)bcol.size();
+      }
+      c->bsr_blocks = (int)bcol.size();
+      dfree(c, b.bsr_col);
+      dfree(c, b.bsr_val);
+      TRY(dalloc(c, &b.bsr_col, bcol.size()));
+      TRY(dalloc(c, &b.bsr_val, bval.size()));
+      HIP_TRY(c, hipMemcpy(b.bsr_col, bcol.data(), bcol.size() * sizeof(int), hipMemcpyHostToDevice));
+      HIP_TRY(c, hipMemcpy(b.bsr_val, bval.data(), bval.size() * sizeof(double), hipMemcpyHostToDevice));
+      dfree(c, b.ell_col);
+      dfree(c, b.ell_val);
+      // work items of the fused projection / real-space kernel: about 512
+      // items of similar size (a unit: K = 64 of one 64 x 64 output tile)
+      const int kunits = 2 * c->ncp / 64;
+      const long U = (long)T * kunits + (long)bcol.size();
+      const int u = (int)std::max<long>(4, (U + 511) / 512);
+      std::vector<int> items;
+      int nparts = 1;
+      for (int I = 0; I < T; ++I) {
+        int part = 0;
+        const int nk = (kunits + u - 1) / u;
+        for (int q = 0; q < nk; ++q)
+          items.insert(items.end(), {I, 0, kunits * q / nk * 64, kunits * (q + 1) / nk * 64,
+                                     part++, tplane[I]});
+        const int nbI = bptr[I + 1] - bptr[I];
+        const int nq = (nbI + u - 1) / u;
+        for (int q = 0; q < nq; ++q)
+          items.insert(items.end(), {I, 1, bptr[I] + nbI * q / nq, bptr[I] + nbI * (q + 1) / nq,
+                                     part++, tplane[I]});
+        nparts = std::max(nparts, part);
+      }
+      c->cg_nitems = (int)(items.size() / 6);
+      c->cg_nparts = nparts;
+      dfree(c, b.cg_items);
+      TRY(dalloc(c, &b.cg_items, items.size()));
+      HIP_TRY(c, hipMemcpy(b.cg_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
+      // plane sums split over each plane's slots to about 512 workgroups
+      int q16 = 1 << 30;
+      for (int L = 0; L < c->nlayers; ++L) q16 = std::min(q16, c->h_plane_rows[L] / 16);
+      const int mt = 2 * c->ncp / 64;
+      c->cg_ksplit = std::max(1, std::min({16, q16, (512 + mt * c->nlayers - 1) / (mt * c->nlayers)}));
     }
     TRY(dalloc(c, &b.dextra, (size_t)n));
     if (d_diag_extra)
@@ -1562,6 +1651,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_CG_RESID: *out = c->cg_resid; return CPM_OK;
     case CPM_INFO_ELL_WIDTH: *out = c->ell_width; return CPM_OK;
     case CPM_INFO_NCOLS: *out = c->ncolsort; return CPM_OK;
+    case CPM_INFO_BSR_BLOCKS: *out = c->bsr_blocks; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -1593,7 +1683,8 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
   dfree(b.Qpair); dfree(b.ell_col); dfree(b.ell_val); dfree(b.plane_off); dfree(b.dextra);
-  dfree(b.tile_plane); dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);
+  dfree(b.bsr_col); dfree(b.bsr_val); dfree(b.cg_items);
+  dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);
   dfree(b.cgscal); dfree(b.cgphi); dfree(b.cgY); dfree(b.cgT);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);

@@ -108,17 +108,19 @@ struct Buffers {
   // for the operator, atoms padded to npad for the dense A)
   double2* Qpair = nullptr;        // Q_c(L, L') per sorted column, [(c nL + L) nL + L']
   int* ell_col = nullptr;          // real-space + self part of A, ELL rows [slot * width + k]
-  double* ell_val = nullptr;
+  double* ell_val = nullptr;       //   (set-up only; kept as 64 x 64 blocks below)
+  int* bsr_col = nullptr;          // column tile of each nonzero block (rows of a tile together)
+  double* bsr_val = nullptr;       // the blocks, row-major 64 x 64 each
+  int* cg_items = nullptr;         // work items of the fused projection / real-space kernel
   int* plane_off = nullptr;        // nlayers + 1 slot offsets of the planes
-  int* tile_plane = nullptr;       // plane of each 64-slot tile
   double* Ecat = nullptr;          // in-plane phases, (2 ncp) x nslot real matrix
   int* cg_ident = nullptr;         // identity slot map of the dense A (npad, -1 pads)
   double* dextra = nullptr;        // diagonal extra (n)
   double* cgv = nullptr;           // X, R, P, AP: 4 x nslot x CG_MAXG (slot-major)
   double* cgred = nullptr;         // block partials
   double* cgscal = nullptr;        // per-vector r.r, r0.r0, iterations (CG_NSCAL x CG_MAXG)
-  double* cgphi = nullptr;         // k-space potentials (nslot x CG_MAXG)
-  double* cgY = nullptr;           // plane sums (nlayers x 2 ncp x CG_MAXG)
+  double* cgphi = nullptr;         // k- and real-space potentials (nparts x nslot x CG_MAXG)
+  double* cgY = nullptr;           // plane sums (ksplit x nlayers x 2 ncp x CG_MAXG)
   double* cgT = nullptr;           // plane-mixed sums (same shape)
   size_t kpart_len = 0;
   int bpad_rows = 0;
@@ -139,17 +141,20 @@ void launch_ell_fill(hipStream_t st, int nslot, int jchunks, int width, const in
                      double alpha, double eta_ee, double diag_self, int* col, double* val);
 void launch_cg_ephase(hipStream_t st, int nslot, int ncp, int ncolsort, const int* slot_atom,
                       const Buffers& b, double* Ecat);
-// k space of A p: plane sums Y (MFMA), plane mixing T, projection Phi (MFMA)
-void launch_cg_plane_sums(hipStream_t st, int nslot, int ncp, int nlayers, const int* plane_off,
-                          const double* Ecat, const double* P, double* Y);
-void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, const double2* Q,
-                         const double* Y, double* T);
-void launch_cg_project(hipStream_t st, int nslot, int ncp, const int* tile_plane,
-                       const double* Ecat, const double* T, double* Phi);
+// A p on matrix cores: plane sums Y (split over ksplit slot ranges), plane
+// mixing T, then the projection and the block-sparse real space per slot
+// tile as work items {tile, kind, begin, end, part, plane} into Phi parts
+void launch_cg_plane_sums(hipStream_t st, int nslot, int ncp, int nlayers, int ksplit,
+                          const int* plane_off, const double* Ecat, const double* P, double* Y);
+void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, int ksplit,
+                         const double2* Q, const double* Y, double* T);
+void launch_cg_tiles(hipStream_t st, int nitems, int nslot, int ncp, const int* items,
+                     const double* Ecat, const double* T, const int* bcol, const double* bval,
+                     const double* P, double* Phi);
 // The kernels below share one grid of nblk blocks; each sums the partials
 // of the previous one.  AP (operator; dense: AP given) with partials of p.Ap.
 void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, const int* slot_atom,
-                     const Buffers& b, int width, const double* Phi, double background,
+                     const Buffers& b, int nparts, const double* Phi, double background,
                      const double* cdip, double ke, const double* P, double* AP, double* red);
 // x, r update (cur: parity of the iteration), then p and its moments
 void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2,
@@ -182,6 +187,8 @@ struct cpm_ctx {
   int ell_width = 0;               // entries per row of the real-space ELL part
   int ncp = 0;                     // columns of the operator's k-space products (ncolsort
                                    // rounded up to 32)
+  int bsr_blocks = 0;              // nonzero 64 x 64 blocks of the real-space part
+  int cg_nitems = 0, cg_nparts = 1, cg_ksplit = 1;   // work split of the operator products
   int n = 0, npad = 0, n_e = 0, m = 0;
   double Lz = 0, V = 0, kc = 0, ke = 0;
   double cdip[3] = {0, 0, 0};      // dipole term A += k_e sum_d cdip_d r_d r_d^T (geometry)
