@@ -131,10 +131,12 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     ctx.set_electrolyte(w.electrolyte_q)
 
     def step():
+        # the inversion runs on a second stream while b is computed (b does
+        # not depend on A); set_potential joins it
         ctx.build_elastance(R, eid, 2)
-        ctx.invert(store)
-        ctx.set_potential(w.v_electrode)
+        ctx.invert(store | cpm.INVERT_ASYNC)
         ctx.potential_vector(xyz, bvec)
+        ctx.set_potential(w.v_electrode)
         ctx.solve_charges(bvec, mode, q, Qe)
 
     tune = None
@@ -161,6 +163,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     step()
     fams = ["sf_tables", "structure_factor", "sf_reduce", "kspace_project", "real_space_b", "combine",
             "gemm_f64", "gemm_bf16x3", "matvec_f64", "matvec_f32", "finalize", "potrf_diag",
+            "chol_update", "trtri", "lauum", "assemble_real", "assemble_kspace",
             "row_means", "pad_rows", "make_rhs", "center_rows"]
     timing = {f: ctx.timing(f) for f in fams}
     ctx.enable_timing(False)

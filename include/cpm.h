@@ -68,6 +68,9 @@ typedef enum { CPM_GEOM_SLAB_EW3DC = 0, CPM_GEOM_WIRE = 1, CPM_GEOM_3D = 2 } cpm
 
 /* Which copies of S cpm_invert keeps (bit set).  FP64 is always kept. */
 enum { CPM_STORE_F64 = 1, CPM_STORE_F32 = 2, CPM_STORE_BF16X2 = 4 };
+/* cpm_invert flag: enqueue the inversion on a second stream of the context
+ * and return at once (see cpm_invert). */
+enum { CPM_INVERT_ASYNC = 0x100 };
 
 /* Solve modes for cpm_solve_charges.  The low byte picks the copy of S that
  * is streamed; CPM_SOLVE_REFINE adds one FP64 refinement step against A. */
@@ -196,6 +199,15 @@ cpm_status cpm_solve_cg(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32, 
  * keep the copies of S named by store_flags (CPM_STORE_*).  Synchronous;
  * returns CPM_ENOTPD (pivot via CPM_INFO_PIVOT) if A is not positive
  * definite. */
+/* With CPM_INVERT_ASYNC in store_flags the work runs on a second stream of
+ * default priority, ordered after the work already enqueued on the context
+ * stream, and the call returns without waiting: a following
+ * cpm_potential_vector (which needs no inverse) overlaps it.  The first call
+ * that needs the inverse -- cpm_set_potential(_atoms), cpm_solve_charges,
+ * cpm_set_charge, cpm_autotune, cpm_solve_grouped, cpm_capture_step,
+ * cpm_replay_step, cpm_copy_matrix/vector, cpm_get_info(S_SUM or PIVOT),
+ * cpm_synchronize -- waits for it and returns CPM_ENOTPD there if a pivot
+ * failed; a rebuild or another cpm_invert waits for it first. */
 cpm_status cpm_invert(cpm_ctx* ctx, unsigned store_flags);
 
 /* Applied potentials h_v_electrode[n_e] (V), one per electrode (v = G v~,

@@ -75,6 +75,32 @@ cpm_status launched(cpm_ctx* c, const char* what) {
   return CPM_OK;
 }
 
+// ---- asynchronous inversion ------------------------------------------------
+// cpm_invert with CPM_INVERT_ASYNC runs on c->aux and leaves inv_pending set;
+// wait_invert joins it (host wait on its event); finish_invert also reports
+// a pivot failure it found (CPM_ENOTPD) and publishes s.
+cpm_status wait_invert(cpm_ctx* c) {
+  if (!c->inv_pending) return CPM_OK;
+  c->inv_pending = false;
+  HIP_TRY(c, hipEventSynchronize(c->aux_ev));
+  c->s_sum = c->h_async->s;
+  if (c->h_async->flag != 0) {
+    c->pivot = c->h_async->flag - 1;
+    c->have_inv = false;
+    c->inv_failed = true;
+  }
+  return CPM_OK;
+}
+
+cpm_status finish_invert(cpm_ctx* c) {
+  TRY(wait_invert(c));
+  if (c->inv_failed) {
+    c->inv_failed = false;
+    return fail(c, CPM_ENOTPD, "elastance matrix not positive definite at pivot %d", c->pivot);
+  }
+  return CPM_OK;
+}
+
 // ---- kernel timing ---------------------------------------------------------
 hipEvent_t take_event(cpm_ctx* c) {
   if (!c->evpool.empty()) {
@@ -112,19 +138,21 @@ void resolve_timing(cpm_ctx* c, bool wait) {
 struct Timed {
   cpm_ctx* c;
   const char* name;
+  hipStream_t st;
   hipEvent_t a = nullptr;
-  Timed(cpm_ctx* c_, const char* n) : c(c_), name(n) {
+  Timed(cpm_ctx* c_, const char* n, hipStream_t s_ = nullptr)
+      : c(c_), name(n), st(s_ ? s_ : c_->stream) {
     if (!c->timing) return;
     if (!c->timing_only.empty() &&
         std::find(c->timing_only.begin(), c->timing_only.end(), n) == c->timing_only.end())
       return;
-    if ((a = take_event(c))) (void)hipEventRecord(a, c->stream);
+    if ((a = take_event(c))) (void)hipEventRecord(a, st);
   }
   ~Timed() {
     if (!a) return;
     hipEvent_t b = take_event(c);
     if (!b) return;
-    (void)hipEventRecord(b, c->stream);
+    (void)hipEventRecord(b, st);
     c->pending.push_back({name, a, b});
     if (c->pending.size() > 4096) resolve_timing(c, false);
   }
@@ -567,6 +595,8 @@ namespace {
 // and the matrix-free operator (dense = false: keep what A x needs).
 cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
                       const double* d_diag_extra, bool dense) {
+  TRY(wait_invert(c));                    // the pending inversion still reads A
+  c->inv_failed = false;
   if (n <= 0 || n_e <= 0 || !d_xyz || !d_eid)
     return fail(c, CPM_EINVAL, "need n > 0, n_e > 0 and non-NULL coordinates and ids");
   if ((c->have_A || c->have_op) && n != c->n)
@@ -812,33 +842,31 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     c->have_op = true;
     return CPM_OK;
   }
-  launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha, eta_ee,
-                      diag_self, background, c->cdip, c->ke, d_diag_extra, b.A);
+  { Timed t(c, "assemble_real");
+    launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha, eta_ee,
+                        diag_self, background, c->cdip, c->ke, d_diag_extra, b.A); }
   TRY(launched(c, "real_space_A"));
   if (c->nlayers > 0 && c->sf_mfma) {
-    // planar electrodes: per plane, A[rows of L] += k_e G_L F^L (K = 2 x columns)
+    // planar electrodes: per plane, A[rows of L] += k_e G_L F^L (K = 2 x columns);
+    // Q, G and F stay allocated for rebuilds of the same context
+    Timed t(c, "assemble_kspace");
     const int ldG = (2 * c->ncolsort + 15) / 16 * 16;
-    double2* Q = nullptr;
-    double* G = nullptr;
-    double* F = nullptr;
-    TRY(dalloc(c, &Q, (size_t)c->ncolsort * c->nlayers * c->nlayers));
-    TRY(dalloc(c, &G, (size_t)c->nmap * ldG));
-    TRY(dalloc(c, &F, (size_t)ldG * npad));
+    TRY(dalloc(c, &b.Qpair, (size_t)c->ncolsort * c->nlayers * c->nlayers));
+    TRY(dalloc(c, &b.asmG, (size_t)c->nmap * ldG));
+    TRY(dalloc(c, &b.asmF, (size_t)ldG * npad));
     launch_plane_pair_weights(c->stream, c->ncolsort, c->nlayers, b.sc_lo, b.sc_len, b.sc_koff,
-                              b.w2, b.layer_fz, Q);
-    launch_build_G(c->stream, c->nmap, c->ncolsort, ldG, b.amap, b.sc_nx, b.sc_ny, b, G);
+                              b.w2, b.layer_fz, b.Qpair);
+    launch_build_G(c->stream, c->nmap, c->ncolsort, ldG, b.amap, b.sc_nx, b.sc_ny, b, b.asmG);
     int row0 = 0;
     for (int L = 0; L < c->nlayers; ++L) {
       const int rows = c->h_plane_rows[L];              // this plane's rows of the map (x 64)
-      launch_build_F(c->stream, L, n, npad, c->nlayers, c->ncolsort, ldG, b.sc_nx, b.sc_ny, b, Q,
-                     F);
-      launch_gemm_f64(c->stream, false, false, rows, npad, ldG, c->ke, G + (size_t)row0 * ldG,
-                      ldG, F, npad, 1.0, b.A, npad, 0, 0, b.amap + row0);
+      launch_build_F(c->stream, L, n, npad, c->nlayers, c->ncolsort, ldG, b.sc_nx, b.sc_ny, b,
+                     b.Qpair, b.asmF);
+      launch_gemm_f64(c->stream, false, false, rows, npad, ldG, c->ke, b.asmG + (size_t)row0 * ldG,
+                      ldG, b.asmF, npad, 1.0, b.A, npad, 0, 0, b.amap + row0);
       TRY(launched(c, "kspace planes"));
       row0 += rows;
     }
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    dfree(c, Q); dfree(c, G); dfree(c, F);
   } else {
     // k space: A += T T^T over chunks of KC k-vectors (2 KC columns)
     const int KC = 2048;
@@ -877,9 +905,13 @@ cpm_status cpm_build_operator(cpm_ctx* c, int n, const double* d_xyz, const int*
 
 cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   if (!c) return CPM_EINVAL;
+  TRY(wait_invert(c));                    // a new inversion supersedes a pending one
+  c->inv_failed = false;
   if (!c->have_A) return fail(c, CPM_ESTATE, "cpm_invert before cpm_build_elastance");
-  if (store_flags & ~(unsigned)(CPM_STORE_F64 | CPM_STORE_F32 | CPM_STORE_BF16X2))
+  if (store_flags & ~(unsigned)(CPM_STORE_F64 | CPM_STORE_F32 | CPM_STORE_BF16X2 | CPM_INVERT_ASYNC))
     return fail(c, CPM_EINVAL, "unknown store flags 0x%x", store_flags);
+  const bool async = (store_flags & CPM_INVERT_ASYNC) != 0;
+  store_flags &= ~(unsigned)CPM_INVERT_ASYNC;
   const int n = c->n, npad = c->npad, nb = npad / TILE;
   Buffers& b = c->b;
   TRY(dalloc(c, &b.L, (size_t)npad * npad));
@@ -889,7 +921,25 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   TRY(dalloc(c, &b.u, npad));
   TRY(dalloc(c, &b.d, npad));
   TRY(dalloc(c, &b.vat, npad));
+  if (store_flags & CPM_STORE_F32) TRY(dalloc(c, &b.S32, (size_t)npad * npad));
+  if (store_flags & CPM_STORE_BF16X2) {
+    TRY(dalloc(c, &b.Shi, (size_t)npad * npad));
+    TRY(dalloc(c, &b.Slo, (size_t)npad * npad));
+  }
   hipStream_t st = c->stream;
+  if (async) {
+    // a second stream of default priority, ordered after the work already
+    // enqueued on the context stream (the assembly of A)
+    if (!c->aux) {
+      HIP_TRY(c, hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+      HIP_TRY(c, hipEventCreateWithFlags(&c->aux_ev, hipEventDisableTiming));
+      HIP_TRY(c, hipEventCreateWithFlags(&c->main_ev, hipEventDisableTiming));
+      HIP_TRY(c, hipHostMalloc((void**)&c->h_async, sizeof(*c->h_async), hipHostMallocDefault));
+    }
+    HIP_TRY(c, hipEventRecord(c->main_ev, c->stream));
+    HIP_TRY(c, hipStreamWaitEvent(c->aux, c->main_ev, 0));
+    st = c->aux;
+  }
   HIP_TRY(c, hipMemcpyAsync(b.L, b.A, (size_t)npad * npad * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIP_TRY(c, hipMemsetAsync(b.flag, 0, sizeof(int), st));
   HIP_TRY(c, hipMemsetAsync(b.u, 0, npad * sizeof(double), st));
@@ -897,8 +947,10 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = kb * TILE, rest = npad - k0 - TILE;
     double* diag = b.L + (size_t)k0 * npad + k0;
-    launch_potrf_diag(st, diag, npad, b.Dinv + (size_t)kb * TILE * TILE, b.flag, k0);
+    { Timed t(c, "potrf_diag", st);
+      launch_potrf_diag(st, diag, npad, b.Dinv + (size_t)kb * TILE * TILE, b.flag, k0); }
     if (rest > 0) {
+      Timed t(c, "chol_update", st);
       double* panel = b.L + (size_t)(k0 + TILE) * npad + k0;
       // L21 = A21 L11^-T
       launch_gemm_f64(st, false, true, rest, TILE, TILE, 1.0, panel, npad,
@@ -910,12 +962,15 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
     }
     TRY(launched(c, "cholesky"));
   }
-  int flag = 0;
-  HIP_TRY(c, hipMemcpyAsync(&flag, b.flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIP_TRY(c, hipStreamSynchronize(st));
-  if (flag != 0) {
-    c->pivot = flag - 1;
-    return fail(c, CPM_ENOTPD, "elastance matrix not positive definite at pivot %d", c->pivot);
+  if (!async) {
+    int flag = 0;
+    HIP_TRY(c, hipMemcpyAsync(&flag, b.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    if (flag != 0) {
+      c->pivot = flag - 1;
+      c->have_inv = false;
+      return fail(c, CPM_ENOTPD, "elastance matrix not positive definite at pivot %d", c->pivot);
+    }
   }
   // X = L^-1 by blocked forward substitution (X stored in Ainv's buffer first)
   double* X = b.Ainv;
@@ -923,6 +978,7 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   for (int kb = 0; kb < nb; ++kb) {
     const int k0 = kb * TILE, cols = k0 + TILE, rest = npad - k0 - TILE;
     double* Xk = X + (size_t)k0 * npad;
+    Timed t(c, "trtri", st);
     // X_k = L_kk^-1 X_k on the columns that can be non-zero
     launch_gemm_f64(st, false, false, TILE, cols, TILE, 1.0, b.Dinv + (size_t)kb * TILE * TILE,
                     TILE, Xk, npad, 0.0, Xk, npad, 0, 0);
@@ -936,8 +992,9 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   }
   // A^-1 = X^T X (lower tiles, k from max(row, col)), result into L's buffer,
   // then swap names so Ainv holds A^-1
-  launch_gemm_f64(st, true, false, npad, npad, npad, 1.0, X, npad, X, npad, 0.0, b.L, npad, 1, 1);
-  launch_mirror_lower(st, npad, b.L);
+  { Timed t(c, "lauum", st);
+    launch_gemm_f64(st, true, false, npad, npad, npad, 1.0, X, npad, X, npad, 0.0, b.L, npad, 1, 1);
+    launch_mirror_lower(st, npad, b.L); }
   TRY(launched(c, "lauum"));
   std::swap(b.L, b.Ainv);
   // u = A^-1 e, s = e^T u, S = A^-1 - u u^T / s (Eq. 4)
@@ -945,28 +1002,31 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   launch_sum_vector(st, n, b.u, b.scal);
   launch_make_S(st, n, npad, b.Ainv, b.u, b.scal, b.S);
   TRY(launched(c, "projection"));
-  if (store_flags & CPM_STORE_F32) {
-    TRY(dalloc(c, &b.S32, (size_t)npad * npad));
-  }
-  if (store_flags & CPM_STORE_BF16X2) {
-    TRY(dalloc(c, &b.Shi, (size_t)npad * npad));
-    TRY(dalloc(c, &b.Slo, (size_t)npad * npad));
-  }
   if (store_flags & (CPM_STORE_F32 | CPM_STORE_BF16X2))
     launch_convert_S(st, npad, b.S, (store_flags & CPM_STORE_F32) ? b.S32 : nullptr,
                      (store_flags & CPM_STORE_BF16X2) ? b.Shi : nullptr,
                      (store_flags & CPM_STORE_BF16X2) ? b.Slo : nullptr);
   TRY(launched(c, "convert"));
+  c->store = store_flags | CPM_STORE_F64;
+  c->have_q = false;                     // charge targets refer to the previous inverse
+  if (async) {
+    // results are joined by the first call that needs them (finish_invert)
+    HIP_TRY(c, hipMemcpyAsync(&c->h_async->s, b.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipMemcpyAsync(&c->h_async->flag, b.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(c, hipEventRecord(c->aux_ev, st));
+    c->inv_pending = true;
+    c->have_inv = true;
+    return CPM_OK;
+  }
   HIP_TRY(c, hipMemcpyAsync(&c->s_sum, b.scal, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(c, hipStreamSynchronize(st));
-  c->store = store_flags | CPM_STORE_F64;
   c->have_inv = true;
-  c->have_q = false;                     // charge targets refer to the previous inverse
   return CPM_OK;
 }
 
 cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
   if (!c) return CPM_EINVAL;
+  TRY(finish_invert(c));
   if (!c->have_inv && !c->have_op) return fail(c, CPM_ESTATE, "cpm_set_potential before cpm_invert");
   if (!h_v_electrode) return fail(c, CPM_EINVAL, "h_v_electrode is NULL");
   for (int a = 0; a < c->n_e; ++a)
@@ -988,6 +1048,7 @@ cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
 
 cpm_status cpm_set_potential_atoms(cpm_ctx* c, const double* h_v) {
   if (!c) return CPM_EINVAL;
+  TRY(finish_invert(c));
   if (!c->have_inv && !c->have_op)
     return fail(c, CPM_ESTATE, "cpm_set_potential_atoms before cpm_invert");
   if (!h_v) return fail(c, CPM_EINVAL, "h_v is NULL");
@@ -1107,6 +1168,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
 // validation and (first-use) allocation for cpm_solve_charges
 cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
                       double* d_q) {
+  TRY(finish_invert(c));
   if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_invert");
   if (!c->have_v) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_set_potential");
   if (batch <= 0 || !d_b || !d_q) return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL b, q");
@@ -1296,6 +1358,7 @@ cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_
 
 cpm_status cpm_replay_step(cpm_ctx* c) {
   if (!c) return CPM_EINVAL;
+  TRY(finish_invert(c));
   if (!c->graph_exec) return fail(c, CPM_ESTATE, "cpm_replay_step before cpm_capture_step");
   // the graph holds raw device addresses: any reallocation since capture
   // (a larger eager batch, a rebuild) or a dropped copy of S invalidates it
@@ -1308,6 +1371,7 @@ cpm_status cpm_replay_step(cpm_ctx* c) {
 
 cpm_status cpm_set_charge(cpm_ctx* c, const double* h_Q) {
   if (!c) return CPM_EINVAL;
+  TRY(finish_invert(c));
   if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_set_charge before cpm_invert");
   if (!h_Q) return fail(c, CPM_EINVAL, "h_Q is NULL");
   const int ne = c->n_e, n = c->n;
@@ -1360,6 +1424,7 @@ cpm_status cpm_set_charge(cpm_ctx* c, const double* h_Q) {
 
 cpm_status cpm_autotune(cpm_ctx* c, int batch, int reps) {
   if (!c) return CPM_EINVAL;
+  TRY(finish_invert(c));
   if (!c->have_inv || !(c->store & CPM_STORE_BF16X2) || !c->b.Shi)
     return fail(c, CPM_ESTATE, "cpm_autotune needs cpm_invert with the split-BF16 copy of S");
   if (batch <= 0 || reps <= 0) return fail(c, CPM_EINVAL, "need batch > 0 and reps > 0");
@@ -1603,6 +1668,7 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
 
 cpm_status cpm_copy_matrix(const cpm_ctx* c, int which, double* d_out) {
   if (!c || !d_out) return CPM_EINVAL;
+  TRY(finish_invert(const_cast<cpm_ctx*>(c)));
   const double* src = nullptr;
   if (which == 0 && c->have_A) src = c->b.A;
   if (which == 1 && c->have_inv) src = c->b.Ainv;
@@ -1617,6 +1683,7 @@ cpm_status cpm_copy_matrix(const cpm_ctx* c, int which, double* d_out) {
 
 cpm_status cpm_copy_vector(const cpm_ctx* c, int which, double* d_out) {
   if (!c || !d_out) return CPM_EINVAL;
+  TRY(finish_invert(const_cast<cpm_ctx*>(c)));
   const double* src = nullptr;
   if (which == 0 && c->have_inv) src = c->b.u;
   if (which == 1 && c->have_v && c->have_inv) src = c->b.d;
@@ -1632,8 +1699,16 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_N: *out = c->n; return CPM_OK;
     case CPM_INFO_NK: *out = c->nk; return CPM_OK;
     case CPM_INFO_NE: *out = c->n_e; return CPM_OK;
-    case CPM_INFO_S_SUM: *out = c->s_sum; return c->have_inv ? CPM_OK : CPM_ESTATE;
-    case CPM_INFO_PIVOT: *out = c->pivot; return CPM_OK;
+    case CPM_INFO_S_SUM: {
+      const cpm_status st = finish_invert(const_cast<cpm_ctx*>(c));
+      *out = c->s_sum;
+      return st != CPM_OK ? st : c->have_inv ? CPM_OK : CPM_ESTATE;
+    }
+    case CPM_INFO_PIVOT: {
+      (void)wait_invert(const_cast<cpm_ctx*>(c));
+      *out = c->pivot;
+      return CPM_OK;
+    }
     case CPM_INFO_LZ: *out = c->Lz; return CPM_OK;
     case CPM_INFO_KCUT: *out = c->kc; return CPM_OK;
     case CPM_INFO_M: *out = c->m; return CPM_OK;
@@ -1658,6 +1733,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
 
 cpm_status cpm_synchronize(cpm_ctx* c) {
   if (!c) return CPM_EINVAL;
+  TRY(finish_invert(c));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipGetLastError());
   return CPM_OK;
@@ -1670,6 +1746,11 @@ const char* cpm_last_error(const cpm_ctx* c) {
 
 void cpm_destroy(cpm_ctx* c) {
   if (!c) return;
+  (void)wait_invert(c);
+  if (c->aux) (void)hipStreamDestroy(c->aux);
+  if (c->aux_ev) (void)hipEventDestroy(c->aux_ev);
+  if (c->main_ev) (void)hipEventDestroy(c->main_ev);
+  if (c->h_async) (void)hipHostFree(c->h_async);
   Buffers& b = c->b;
   dfree(b.ex); dfree(b.ey); dfree(b.ez); dfree(b.efx); dfree(b.efy); dfree(b.efz); dfree(b.eid);
   dfree(b.layer_of); dfree(b.layer_fz); dfree(b.layerT); dfree(b.amap);
@@ -1683,7 +1764,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
   dfree(b.Qpair); dfree(b.ell_col); dfree(b.ell_val); dfree(b.plane_off); dfree(b.dextra);
-  dfree(b.bsr_col); dfree(b.bsr_val); dfree(b.cg_items);
+  dfree(b.bsr_col); dfree(b.bsr_val); dfree(b.cg_items); dfree(b.asmG); dfree(b.asmF);
   dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);
   dfree(b.cgscal); dfree(b.cgphi); dfree(b.cgY); dfree(b.cgT);
   if (c->stream) (void)hipStreamSynchronize(c->stream);

@@ -87,6 +87,8 @@ struct Buffers {
   double* d = nullptr;             // S v (npad)
   double* vat = nullptr;           // per-atom applied potential v = G v~ (npad)
   double* table = nullptr;         // k-space phase table chunk for the A SYRK
+  double* asmG = nullptr;          // planar A assembly: G (atom-map rows x 2 columns)
+  double* asmF = nullptr;          //   and F^L (2 columns x npad)
   double* elq = nullptr;           // electrolyte charges (m)
   int* flag = nullptr;             // device status word (Cholesky pivot)
   // per-step workspaces
@@ -181,6 +183,13 @@ struct cpm_ctx {
   std::string err;
   bool have_elyt = false, have_A = false, have_inv = false, have_v = false, have_q = false;
   bool have_op = false;            // matrix-free operator (cpm_build_operator)
+  // cpm_invert with CPM_INVERT_ASYNC: second stream, completion event, pinned
+  // host words for s and the pivot flag; joined by the first consumer
+  hipStream_t aux = nullptr;
+  hipEvent_t aux_ev = nullptr, main_ev = nullptr;
+  struct AsyncWords { double s; int flag; };
+  AsyncWords* h_async = nullptr;
+  bool inv_pending = false, inv_failed = false;
   double op_background = 0.0;      // -pi / (V alpha^2)
   int cg_iters = 0;                // last cpm_solve_cg: iterations, max relative residual
   double cg_resid = 0.0;

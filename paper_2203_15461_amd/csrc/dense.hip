@@ -135,56 +135,64 @@ void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int
 // triangular factor (one column per thread).  A pivot <= 0 (or NaN) records
 // 1 + its global index in *flag (first one wins) and continues with 1.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_potrf_diag(double* Lblk, int ld, double* Dinv, int* flag,
-                                                    int k0) {
-  __shared__ double a[64][65];
-  __shared__ double inv[64][65];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    a[i][j] = (j <= i) ? Lblk[(size_t)i * ld + j] : 0.0;
+__global__ void __launch_bounds__(1024) k_potrf_diag(double* Lblk, int ld, double* Dinv, int* flag,
+                                                     int k0) {
+  __shared__ double a[64][65];     // working copy (lower triangle), updated right-looking
+  __shared__ double L[64][65];     // the factor
+  __shared__ double X[64][65];     // L^-1, built row by row
+  __shared__ double rdiag[64];     // 1 / L[j][j]
+  constexpr int P = 16;            // thread groups sharing a row (16 waves)
+  const int tid = threadIdx.x, i = tid & 63, part = tid >> 6;
+  for (int e = tid; e < 64 * 64; e += 64 * P) {
+    const int r = e >> 6, c = e & 63;
+    a[r][c] = (c <= r) ? Lblk[(size_t)r * ld + c] : 0.0;
+    L[r][c] = 0.0;
+    X[r][c] = (r == c) ? 1.0 : 0.0;
   }
   __syncthreads();
+  // Column j: every thread takes the pivot itself, thread (i, part 0) writes
+  // L[i][j], and thread (i, part) updates a[i][l] for l = j+1+part,
+  // j+1+part+P, ... <= i with the unscaled column (a[i][j] a[l][j] / a[j][j]).
+  // Column j of `a` is only read in step j, so one barrier per column
+  // suffices.
   for (int j = 0; j < 64; ++j) {
-    if (tid == 0) {
-      double piv = a[j][j];
-      if (!(piv > 0.0)) {
-        atomicCAS(flag, 0, k0 + j + 1);
-        piv = 1.0;
-      }
-      a[j][j] = sqrt(piv);
+    double piv = a[j][j];
+    if (!(piv > 0.0)) {
+      if (tid == 0) atomicCAS(flag, 0, k0 + j + 1);
+      piv = 1.0;
     }
-    __syncthreads();
-    const double djj = a[j][j];
-    if (tid > j && tid < 64) a[tid][j] /= djj;
-    __syncthreads();
-    const int i = tid & 63;
+    const double d = sqrt(piv), rd = 1.0 / d, rpiv = rd * rd;
+    if (part == 0 && i >= j) {
+      L[i][j] = (i == j) ? d : a[i][j] * rd;
+      if (i == j) rdiag[j] = rd;
+    }
     if (i > j) {
-      const double lij = a[i][j];
-      for (int l = j + 1 + (tid >> 6); l <= i; l += 4) a[i][l] -= lij * a[l][j];
+      const double lij = a[i][j] * rpiv;
+      for (int l = j + 1 + part; l <= i; l += P) a[i][l] -= lij * a[l][j];
     }
     __syncthreads();
   }
-  if (tid < 64) {
-    const int c = tid;
-    for (int r = 0; r < c; ++r) inv[r][c] = 0.0;
-    inv[c][c] = 1.0 / a[c][c];
-    for (int r = c + 1; r < 64; ++r) {
-      double s = 0.0;
-      for (int t = c; t < r; ++t) s += a[r][t] * inv[t][c];
-      inv[r][c] = -s / a[r][r];
-    }
+  // X = L^-1 by forward substitution, right-looking over rows: at step r row
+  // r of X is final after scaling by 1 / L[r][r]; thread (column c = i, part)
+  // removes its contribution from rows r' = r+1+part, r+1+part+P, ...  Row r
+  // of the working X is read in step r and written (scaled) only by part 0
+  // after the barrier, so one barrier per step suffices.
+  for (int r = 0; r < 64; ++r) {
+    const double x = X[r][i] * rdiag[r];
+    for (int rr = r + 1 + part; rr < 64; rr += P) X[rr][i] -= L[rr][r] * x;
+    __syncthreads();
+    if (part == 0) X[r][i] = x;
   }
   __syncthreads();
-  for (int e = tid; e < 64 * 64; e += 256) {
-    const int i = e >> 6, j = e & 63;
-    Lblk[(size_t)i * ld + j] = (j <= i) ? a[i][j] : 0.0;
-    Dinv[e] = inv[i][j];
+  for (int e = tid; e < 64 * 64; e += 64 * P) {
+    const int r = e >> 6, c = e & 63;
+    Lblk[(size_t)r * ld + c] = L[r][c];
+    Dinv[e] = X[r][c];
   }
 }
 
 void launch_potrf_diag(hipStream_t st, double* Lblk, int ld, double* Dinv, int* flag, int k0) {
-  hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, st, Lblk, ld, Dinv, flag, k0);
+  hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(1024), 0, st, Lblk, ld, Dinv, flag, k0);
 }
 
 __global__ void k_set_identity(int npad, double* X) {
