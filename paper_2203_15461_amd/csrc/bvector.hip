@@ -318,6 +318,98 @@ __device__ inline void elyt_dipole(const double* __restrict__ dip, int blocks, i
 // e^{2 pi i 8 fz} per 16-wide block.  The 4 waves are summed in a fixed order.
 // Output, per configuration s and chunk: tile mt's 32 x 16 nb_mt block at
 // part + (s * nchunks + chunk) * pchunk + toff[mt], row-major.
+// The tile loop, the fixed-order wave sum and the store of one work item
+// with NBW n blocks (NBW is uniform per workgroup: the kernel dispatches on
+// it, so the per-block loops have no branches).  Per 4-charge k step the B
+// operand (e^{i n kz1 z} for this lane's n) is advanced by e^{2 pi i 8 fz}
+// from block to block.
+template <int NBW>
+__device__ void sf_item(SfmWave& W, double* __restrict__ red, const double2* __restrict__ tab,
+                        int mpad, int j0, int j1, const int (&xoff)[4], const int (&yoff)[4],
+                        int z8off, int z1off, int r8off, double* __restrict__ out, int ldc,
+                        int nb_lo) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t_l = lane & 15, g_l = lane >> 4;
+  const bool im = t_l & 1;
+  v4d_t acc0[NBW], acc1[NBW];
+#pragma unroll
+  for (int b = 0; b < NBW; ++b) {
+    acc0[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+    acc1[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+  }
+  // table entries of the next tile are loaded while the current one runs
+  double2 xv[4], yv[4], z8, za, zb, r8n;
+  auto fetch = [&](int jt) {                        // jt + t_l < mpad: chunks are multiples of 16
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { xv[u] = tab[xoff[u] + jt]; yv[u] = tab[yoff[u] + jt]; }
+    z8 = tab[z8off + jt]; za = tab[z1off + jt]; zb = tab[z1off + mpad + jt]; r8n = tab[r8off + jt];
+  };
+  if (j0 + wave * SFM_TJ < j1) fetch(j0 + wave * SFM_TJ);
+  for (int jt = j0 + wave * SFM_TJ; jt < j1; jt += 4 * SFM_TJ) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int cl = g_l + 4 * u;
+      const double2 cv = cmul2(xv[u], yv[u]);
+      W.C[2 * cl][t_l] = cv.x;
+      W.C[2 * cl + 1][t_l] = cv.y;
+    }
+    W.z0[2 * g_l][t_l] = cmul2(z8, za);
+    W.z0[2 * g_l + 1][t_l] = cmul2(z8, zb);
+    if (g_l == 0) W.r8[t_l] = r8n;
+    wave_lds_sync();
+    if (jt + 4 * SFM_TJ < j1) fetch(jt + 4 * SFM_TJ);
+    // k step ks uses charges 4 ks + g_l of the tile
+#pragma unroll 1
+    for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
+      const int kc = 4 * ks + g_l;
+      const double a0 = W.C[t_l][kc], a1 = W.C[16 + t_l][kc];
+      double2 zz = W.z0[t_l >> 1][kc];
+      const double2 r8 = W.r8[kc];
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) {
+        const double bv = im ? zz.y : zz.x;
+        acc0[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0[b], 0, 0, 0);
+        acc1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1[b], 0, 0, 0);
+        if (b + 1 < NBW) zz = cmul(zz, r8);
+      }
+    }
+    wave_lds_sync();
+  }
+  // fixed-order sum of the waves' accumulators (3 + 2 + 1 into wave 0)
+  for (int src = 3; src >= 1; --src) {
+    __syncthreads();
+    if (wave == src)
+#pragma unroll
+      for (int b = 0; b < NBW; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          red[((0 * SFM_NB + b) * 4 + r) * 64 + lane] = acc0[b][r];
+          red[((1 * SFM_NB + b) * 4 + r) * 64 + lane] = acc1[b][r];
+        }
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int b = 0; b < NBW; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc0[b][r] += red[((0 * SFM_NB + b) * 4 + r) * 64 + lane];
+          acc1[b][r] += red[((1 * SFM_NB + b) * 4 + r) * 64 + lane];
+        }
+  }
+  if (wave == 0) {
+    // result register r of lane l: row (l >> 4) + 4 r, column l & 15 of block b
+#pragma unroll
+    for (int b = 0; b < NBW; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = (lane >> 4) + 4 * r;
+        const int col = 16 * (nb_lo + b) + (lane & 15);
+        out[row * ldc + col] = acc0[b][r];
+        out[(16 + row) * ldc + col] = acc1[b][r];
+      }
+  }
+}
+
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 k_sf_mfma(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restrict__ items,
           const int* __restrict__ sc_nx, const int* __restrict__ sc_ny, int ncolsort, int nxm,
@@ -342,9 +434,9 @@ k_sf_mfma(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restr
   const int j0 = chunk * chunk_size, j1 = min(mpad, j0 + chunk_size);
   const int t_l = lane & 15, g_l = lane >> 4;     // this lane's charge in the tile, lane group
   const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
-  // table rows of this lane's four columns g_l + 4u (columns past the end: C = 0)
-  // (32-bit element offsets: the tables stay far below 2^31 entries);
-  // columns past the end read the zero row, so their C is zero
+  // table rows of this lane's four columns g_l + 4u (32-bit element offsets:
+  // the tables stay far below 2^31 entries); columns past the end read the
+  // zero row, so their C is zero
   const int rzero = (int)(tab_stride / mpad) - 1;
   int xoff[4], yoff[4];
 #pragma unroll
@@ -356,92 +448,14 @@ k_sf_mfma(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restr
   }
   const int z8off = (rZ8 + nb_lo) * mpad + t_l, r8off = (rZ8 + 1) * mpad + t_l;
   const int z1off = (rZ1 + 2 * g_l) * mpad + t_l;
+  const int ldc = 16 * tile_nb[mt];
+  double* out = part + ((size_t)snap * nchunks + chunk) * pchunk + toff[mt];
   SfmWave& W = wl[wave];
-  v4d_t acc0[SFM_NB], acc1[SFM_NB];
-#pragma unroll
-  for (int b = 0; b < SFM_NB; ++b) {
-    acc0[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
-    acc1[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
-  }
-  // table entries of the next tile are loaded while the current one runs
-  double2 xv[4], yv[4], z8, za, zb, r8n;
-  auto fetch = [&](int jt) {                        // jt + t_l < mpad: chunks are multiples of 16
-#pragma unroll
-    for (int u = 0; u < 4; ++u) { xv[u] = tab[xoff[u] + jt]; yv[u] = tab[yoff[u] + jt]; }
-    z8 = tab[z8off + jt]; za = tab[z1off + jt]; zb = tab[z1off + mpad + jt]; r8n = tab[r8off + jt];
-  };
-  if (j0 + wave * SFM_TJ < j1) fetch(j0 + wave * SFM_TJ);
-  for (int jt = j0 + wave * SFM_TJ; jt < j1; jt += 4 * SFM_TJ) {
-    {
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int cl = g_l + 4 * u;
-        const double2 cv = cmul2(xv[u], yv[u]);
-        W.C[2 * cl][t_l] = cv.x;
-        W.C[2 * cl + 1][t_l] = cv.y;
-      }
-      W.z0[2 * g_l][t_l] = cmul2(z8, za);
-      W.z0[2 * g_l + 1][t_l] = cmul2(z8, zb);
-      if (g_l == 0) W.r8[t_l] = r8n;
-    }
-    wave_lds_sync();
-    if (jt + 4 * SFM_TJ < j1) fetch(jt + 4 * SFM_TJ);
-#pragma unroll 1
-    for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
-      const int kc = 4 * ks + g_l;                    // k index (charge) of this lane's operands
-      const double a0 = W.C[t_l][kc];                 // rows 0..15
-      const double a1 = W.C[16 + t_l][kc];            // rows 16..31
-      double2 z = W.z0[t_l >> 1][kc];
-      const double2 r8 = W.r8[kc];
-      const bool im = t_l & 1;
-#pragma unroll
-      for (int b = 0; b < SFM_NB; ++b) {
-        if (b < nbw) {
-          const double bv = im ? z.y : z.x;
-          acc0[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0[b], 0, 0, 0);
-          acc1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1[b], 0, 0, 0);
-          z = cmul(z, r8);
-        }
-      }
-    }
-    wave_lds_sync();
-  }
-  // fixed-order sum of the waves' accumulators (3 + 2 + 1 into wave 0)
-  for (int src = 3; src >= 1; --src) {
-    __syncthreads();
-    if (wave == src)
-#pragma unroll
-      for (int b = 0; b < SFM_NB; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          red[((0 * SFM_NB + b) * 4 + r) * 64 + lane] = acc0[b][r];
-          red[((1 * SFM_NB + b) * 4 + r) * 64 + lane] = acc1[b][r];
-        }
-    __syncthreads();
-    if (wave == 0)
-#pragma unroll
-      for (int b = 0; b < SFM_NB; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          acc0[b][r] += red[((0 * SFM_NB + b) * 4 + r) * 64 + lane];
-          acc1[b][r] += red[((1 * SFM_NB + b) * 4 + r) * 64 + lane];
-        }
-  }
-  if (wave == 0) {
-    // result register r of lane l: row (l >> 4) + 4 r, column l & 15 of block b
-    const int ldc = 16 * tile_nb[mt];
-    double* out = part + ((size_t)snap * nchunks + chunk) * pchunk + toff[mt];
-#pragma unroll
-    for (int b = 0; b < SFM_NB; ++b) {
-      if (b >= nbw) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = (lane >> 4) + 4 * r;
-        const int col = 16 * (nb_lo + b) + (lane & 15);
-        out[row * ldc + col] = acc0[b][r];
-        out[(16 + row) * ldc + col] = acc1[b][r];
-      }
-    }
+  switch (nbw) {
+    case 1: sf_item<1>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
+    case 2: sf_item<2>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
+    case 3: sf_item<3>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
+    default: sf_item<SFM_NB>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
   }
 }
 
@@ -873,28 +887,32 @@ __device__ inline double pair_g(const double* __restrict__ T, double r2, double 
 }
 
 // Real-space part of phi_i over one chunk of the electrolyte, for each of the
-// g configurations of a group (xyz m x 3 apart; output rows
+// g configurations of a group (positions and charges of configuration s
+// xyz_stride and q_stride elements apart; output rows
 // part[(s * rchunks + chunk) * n + i]).  Threads map to electrode atoms
-// through amap, which groups the atoms of one z plane into whole waves (-1
-// pads), so each wave's z extent is small.  Every wave walks the chunk 64
-// charges at a time on its own: it keeps the charges within rc in z of its
-// atoms (order-preserving ballot compaction into a wave-private LDS area),
-// then each lane sums over them with all in-plane images within rc; g(r)
-// comes from the LDS pair table, staged once per workgroup.  The next 64
-// charges are loaded while the current ones are summed.
-__global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int chunk_size,
-                                                      size_t xyz_stride, size_t q_stride,
-                                                      const int* __restrict__ amap, int nmap,
-                                                      const double* __restrict__ ex,
-                                                      const double* __restrict__ ey,
-                                                      const double* __restrict__ ez,
-                                                      const double* __restrict__ xyz,
-                                                      const double* __restrict__ q, double Lx,
-                                                      double Ly, double Lz, double rc,
-                                                      const double* __restrict__ ptab,
-                                                      double* __restrict__ part) {
+// through amap, which puts the atoms of one z plane, in compact in-plane
+// tiles, into whole waves (-1 pads).  Every wave walks the chunk 64 charges
+// at a time on its own: it keeps the charges that can come within rc of its
+// atoms -- a z window, and when every cell length is >= 2 rc (one image) an
+// x and y window around the wave's atoms -- by order-preserving ballot
+// compaction into a wave-private LDS area.  In the one-image case each lane
+// then marks its possible partners in a 64-bit mask (an FP32 distance screen
+// with a margin) and evaluates g(r) only for those within rc in FP64, in
+// ascending order (the same pairs and order as a plain loop); otherwise
+// it sums over all in-range images.  g(r) comes from the LDS pair table,
+// staged once per workgroup of RS_WAVES waves.  The charges of the next
+// three steps are loaded while the current ones are summed.
+constexpr int RS_WAVES = 8;
+
+__global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
+    int g, int n, int m, int chunk_size, size_t xyz_stride, size_t q_stride,
+    const int* __restrict__ amap, int nmap, const double* __restrict__ ex,
+    const double* __restrict__ ey, const double* __restrict__ ez,
+    const double* __restrict__ xyz, const double* __restrict__ q, double Lx, double Ly,
+    double Lz, double rc, const double* __restrict__ ptab, double* __restrict__ part) {
   __shared__ double s_tab[3 * (RS_NT + 1)];
-  __shared__ double s_c[4][4][64];                     // per wave: x, y, z, q of kept charges
+  __shared__ double s_c[RS_WAVES][4][64];              // per wave: x, y, z, q of kept charges
+  __shared__ float s_cf[RS_WAVES][3][64];              // and x, y, z in FP32 for the screen
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   const int atom = slot < nmap ? amap[slot] : -1;
@@ -904,62 +922,116 @@ __global__ void __launch_bounds__(256) k_real_space_b(int g, int n, int m, int c
   const double h = rc / RS_NT, inv_h = RS_NT / rc;
   // only the nearest image can lie within rc when every cell length is >= 2 rc
   const bool single = (Lx >= 2.0 * rc) && (Ly >= 2.0 * rc) && (Lz >= 2.0 * rc);
-  for (int t = threadIdx.x; t < 3 * (RS_NT + 1); t += 256) s_tab[t] = ptab[t];
+  for (int t = threadIdx.x; t < 3 * (RS_NT + 1); t += blockDim.x) s_tab[t] = ptab[t];
   __syncthreads();
   double xi = 0, yi = 0, zi = 0;
   if (atom >= 0) { xi = ex[atom]; yi = ey[atom]; zi = ez[atom]; }
-  // this wave's z extent; charges farther than rc from it are dropped
+  // this wave's extent in z (and x, y: wrapped coordinates)
   double zlo = atom >= 0 ? zi : 1e300, zhi = atom >= 0 ? zi : -1e300;
+  double xlo = atom >= 0 ? xi : 1e300, xhi = atom >= 0 ? xi : -1e300;
+  double ylo = atom >= 0 ? yi : 1e300, yhi = atom >= 0 ? yi : -1e300;
   for (int o = 32; o > 0; o >>= 1) {
     zlo = fmin(zlo, __shfl_xor(zlo, o, 64));
     zhi = fmax(zhi, __shfl_xor(zhi, o, 64));
+    xlo = fmin(xlo, __shfl_xor(xlo, o, 64));
+    xhi = fmax(xhi, __shfl_xor(xhi, o, 64));
+    ylo = fmin(ylo, __shfl_xor(ylo, o, 64));
+    yhi = fmax(yhi, __shfl_xor(yhi, o, 64));
   }
-  // z window [wlo, whi) of charges that can come within rc (some periodic
-  // image in z of the charge must fall inside it)
+  // windows [lo - rc, hi + rc) of charges that can come within rc (some
+  // periodic image of the charge must fall inside); x and y only with one image
   const double wlo = zlo - rc, whi = zhi + rc;
-  const bool keep_all = whi - wlo >= Lz;
+  const bool keep_all_z = whi - wlo >= Lz;
+  const double xw = xhi - xlo + 2.0 * rc, yw = yhi - ylo + 2.0 * rc;
+  const bool keep_all_x = !single || xw >= Lx, keep_all_y = !single || yw >= Ly;
   double (*C)[64] = s_c[wave];
+  float (*Cf)[64] = s_cf[wave];
+  // FP32 screen of partners within rc: r2 in FP32 against rc^2 (1 + 1e-4),
+  // which exceeds its rounding error for coordinates up to ~1e3 A, then the
+  // exact FP64 test on the marked pairs
+  const float xif = (float)xi, yif = (float)yi, zif = (float)zi;
+  const float Lxf = (float)Lx, Lyf = (float)Ly, Lzf = (float)Lz;
+  const float iLxf = 1.0f / Lxf, iLyf = 1.0f / Lyf, iLzf = 1.0f / Lzf;
+  const float rc2f = (float)(rc2 * (1.0 + 1e-4));
   const int nblk = j1 > j0 ? (j1 - j0 + 63) / 64 : 0;
   const int steps = g * nblk;
-  double px = 0, py = 0, pzz = 0, pq = 0;
+  // charges of the next three steps are in flight while a step is summed
+  double4 f0 = make_double4(0, 0, 0, 0), f1 = f0, f2 = f0;
   auto fetch = [&](int step) {
+    double4 v = make_double4(0, 0, 0, 0);
     const int snap = step / nblk, j = j0 + (step % nblk) * 64 + lane;
-    if (j < j1) {
+    if (step < steps && j < j1) {
       const double* r = xyz + snap * xyz_stride + (size_t)j * 3;
-      px = r[0]; py = r[1]; pzz = r[2];
-      pq = q[snap * q_stride + j];
+      v = make_double4(r[0], r[1], r[2], q[snap * q_stride + j]);
     }
+    return v;
   };
-  if (steps > 0) fetch(0);
+  f0 = fetch(0);
+  f1 = fetch(1);
+  f2 = fetch(2);
   double acc = 0.0;
   for (int step = 0; step < steps; ++step) {
     const int snap = step / nblk, blk = step % nblk;
     const bool valid = j0 + blk * 64 + lane < j1;
-    double x = px, y = py, z = pzz, qq = pq;
-    if (step + 1 < steps) fetch(step + 1);
-    const bool keep = valid && (keep_all || (z - Lz * floor((z - wlo) * invLz)) < whi);
+    const double x = f0.x, y = f0.y, z = f0.z, qq = f0.w;
+    f0 = f1;
+    f1 = f2;
+    f2 = fetch(step + 3);
+    const double xw0 = x - Lx * floor(x * invLx), yw0 = y - Ly * floor(y * invLy);
+    bool keep = valid && (keep_all_z || (z - Lz * floor((z - wlo) * invLz)) < whi);
+    if (!keep_all_x) {
+      double d = xw0 - (xlo - rc);
+      d -= Lx * floor(d * invLx);
+      keep = keep && d < xw;
+    }
+    if (!keep_all_y) {
+      double d = yw0 - (ylo - rc);
+      d -= Ly * floor(d * invLy);
+      keep = keep && d < yw;
+    }
     const unsigned long long bal = __ballot(keep);
     const int kept = __popcll(bal);
     if (keep) {
       const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-      C[0][pos] = x - Lx * floor(x * invLx);
-      C[1][pos] = y - Ly * floor(y * invLy);
+      C[0][pos] = xw0;
+      C[1][pos] = yw0;
       C[2][pos] = z;
       C[3][pos] = qq;
+      Cf[0][pos] = (float)xw0;
+      Cf[1][pos] = (float)yw0;
+      Cf[2][pos] = (float)z;
     }
     wave_lds_sync();
     if (atom >= 0) {
-      for (int t = 0; t < kept; ++t) {
-        double dz = zi - C[2][t];
-        dz -= Lz * rint(dz * invLz);
-        if (fabs(dz) >= rc) continue;          // dz is the nearest image
-        double dx = xi - C[0][t], dy = yi - C[1][t];
-        dx -= Lx * rint(dx * invLx);
-        dy -= Ly * rint(dy * invLy);
-        if (single) {
+      if (single) {
+        // partners within rc (FP32 screen), then the exact test and g(r)
+        // for those only, in ascending t
+        unsigned long long mask = 0ull;
+        for (int t = 0; t < kept; ++t) {
+          float dz = zif - Cf[2][t], dx = xif - Cf[0][t], dy = yif - Cf[1][t];
+          dz -= Lzf * rintf(dz * iLzf);
+          dx -= Lxf * rintf(dx * iLxf);
+          dy -= Lyf * rintf(dy * iLyf);
+          if (dx * dx + dy * dy + dz * dz < rc2f) mask |= 1ull << t;
+        }
+        while (mask) {
+          const int t = __ffsll((long long)mask) - 1;
+          mask &= mask - 1ull;
+          double dz = zi - C[2][t], dx = xi - C[0][t], dy = yi - C[1][t];
+          dz -= Lz * rint(dz * invLz);
+          dx -= Lx * rint(dx * invLx);
+          dy -= Ly * rint(dy * invLy);
           const double r2 = dx * dx + dy * dy + dz * dz;
           if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
-        } else {
+        }
+      } else {
+        for (int t = 0; t < kept; ++t) {
+          double dz = zi - C[2][t];
+          dz -= Lz * rint(dz * invLz);
+          if (fabs(dz) >= rc) continue;          // dz is the nearest image
+          double dx = xi - C[0][t], dy = yi - C[1][t];
+          dx -= Lx * rint(dx * invLx);
+          dy -= Ly * rint(dy * invLy);
           const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
           const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
           const int clo = (int)ceil((-rc - dz) * invLz) - 1, chi = (int)floor((rc - dz) * invLz) + 1;
@@ -999,7 +1071,7 @@ void launch_real_space_pairs(hipStream_t st, int g, int n, int m, int rchunks, c
                              size_t q_stride, double Lx, double Ly, double Lz, double rc,
                              const double* table, double* part) {
   const int chunk_size = (m + rchunks - 1) / rchunks;
-  dim3 grid((nmap + 255) / 256, rchunks), block(256);
+  dim3 grid((nmap + 64 * RS_WAVES - 1) / (64 * RS_WAVES), rchunks), block(64 * RS_WAVES);
   hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, chunk_size, xyz_stride, q_stride,
                      b.amap, nmap, b.ex, b.ey, b.ez, xyz, q, Lx, Ly, Lz, rc, table, part);
 }
@@ -1123,6 +1195,8 @@ void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlay
 }
 
 int layer_combine_max_group() { return LC_MAXG; }
+
+int real_space_block_atoms() { return 64 * RS_WAVES; }
 
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
                       const double* phir, const Buffers& b, const double* dip, int dip_blocks,

@@ -288,9 +288,9 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   const int run_blocks = (c->nruns + 255) / 256;
   const int sf_target = c->sf_wg_target;
   c->mchunks = std::max(1, std::min((sf_target + run_blocks - 1) / run_blocks, std::max(1, c->m / 64)));
-  // real space: at most 2 workgroups per CU fit (pair table in LDS), so keep
-  // the grid within one round of 512
-  const int atom_blocks = (c->nmap + 255) / 256;
+  // real space: 2 workgroups per CU fit (pair table in LDS), so keep the
+  // grid within one round of 512
+  const int atom_blocks = (c->nmap + real_space_block_atoms() - 1) / real_space_block_atoms();
   c->rchunks = std::max(1, std::min(512 / atom_blocks, std::max(1, c->m / 32)));
   TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
   const bool fast = c->sf_mfma && c->nlayers > 0;

@@ -374,6 +374,7 @@ void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlay
                             const double* dip, int dip_blocks, const double* cdip, double ke,
                             void* out, int out_is_f32);
 int layer_combine_max_group();
+int real_space_block_atoms();      // atom-map slots per workgroup of the real-space b kernel
 
 int sf_table_rows(int nxm, int nym, int nbz);
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
