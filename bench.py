@@ -161,7 +161,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     # per-family kernel breakdown from one more step with every launch timed
     ctx.enable_timing(True)
     step()
-    fams = ["sf_tables", "structure_factor", "sf_reduce", "kspace_project", "real_space_b", "combine",
+    fams = ["sf_tables", "structure_factor", "sf_reduce", "kspace_project", "projection", "real_space_b", "combine",
             "gemm_f64", "gemm_bf16x3", "matvec_f64", "matvec_f32", "finalize", "potrf_diag",
             "chol_update", "trtri", "lauum", "assemble_real", "assemble_kspace",
             "row_means", "pad_rows", "make_rhs", "center_rows"]

@@ -527,13 +527,15 @@ void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int nchunks, int pchu
 // so that phi_i = sum_c Re[e^{-i (kx x_i + ky y_i)} T(c, L_i)].  One wave per
 // (column, configuration): lanes take n >= 0 (both signs), keep the weighted
 // S(c, +-n) in LDS, then one fixed-order wave sum per plane.
-// pz[L * nzt + n] = e^{-2 pi i n fz_L};  T[(c * nlayers + L) * g + s].
+// pz[L * nzt + n] = e^{-2 pi i n fz_L};  T is written as the real right-hand
+// operand of the projection product: Tcat[(L M2 + 2c) 64 + s] = Re T(c, L),
+// Tcat[(L M2 + 2c + 1) 64 + s] = Im T(c, L) for configuration s.
 __global__ void __launch_bounds__(64) k_sf_layer_reduce(
     int ncolsort, int nchunks, int pchunk, int nlayers, int nzt, const int* __restrict__ tile_nb,
     const int* __restrict__ toff, const int* __restrict__ sc_lo, const int* __restrict__ sc_len,
     const int* __restrict__ sc_koff, const int* __restrict__ n_index,
     const double* __restrict__ part, const double* __restrict__ w2,
-    const double2* __restrict__ pz, double2* __restrict__ T) {
+    const double2* __restrict__ pz, int M2, double* __restrict__ Tcat) {
   extern __shared__ double2 s_sw[];                    // [2][n count]: S(+n) w, S(-n) w
   const int c = blockIdx.x, snap = blockIdx.y, lane = threadIdx.x;
   const int ncnt = n_index[c + 1] - n_index[c];        // n = 0 .. ncnt - 1
@@ -575,7 +577,10 @@ __global__ void __launch_bounds__(64) k_sf_layer_reduce(
       tr += __shfl_xor(tr, o, 64);
       ti += __shfl_xor(ti, o, 64);
     }
-    if (lane == 0) T[((size_t)c * nlayers + L) * gridDim.y + snap] = make_double2(tr, ti);
+    if (lane == 0) {
+      Tcat[((size_t)L * M2 + 2 * c) * 64 + snap] = tr;
+      Tcat[((size_t)L * M2 + 2 * c + 1) * 64 + snap] = ti;
+    }
   }
 }
 
@@ -583,28 +588,15 @@ void launch_b_sf_layer_reduce(hipStream_t st, int g, int ncolsort, int nchunks, 
                               int nlayers, int nzt, int max_ncnt, const int* tile_nb,
                               const int* toff, const int* sc_lo, const int* sc_len,
                               const int* sc_koff, const int* n_index, const double* part,
-                              const double* w2, const double2* pz, double2* T) {
+                              const double* w2, const double2* pz, int M2, double* Tcat) {
   const size_t shm = (size_t)2 * max_ncnt * sizeof(double2);
   hipLaunchKernelGGL(k_sf_layer_reduce, dim3(ncolsort, g), dim3(64), shm, st, ncolsort, nchunks,
                      pchunk, nlayers, nzt, tile_nb, toff, sc_lo, sc_len, sc_koff, n_index, part,
-                     w2, pz, T);
+                     w2, pz, M2, Tcat);
 }
 
-// Electrode in-plane phases of the sorted columns, E[c * n + i] =
-// (cos, sin)(kx x_i + ky y_i), and plane phases pz[L * nzt + n] =
-// e^{-2 pi i n fz_L}; both fixed while the electrodes are.
-__global__ void k_electrode_phase(int n, const int* __restrict__ sc_nx,
-                                  const int* __restrict__ sc_ny, const double* __restrict__ fx,
-                                  const double* __restrict__ fy, double2* __restrict__ E) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, c = blockIdx.y;
-  if (i >= n) return;
-  double th = sc_nx[c] * fx[i] + sc_ny[c] * fy[i];
-  th -= rint(th);
-  double sn, cs;
-  sincospi(2.0 * th, &sn, &cs);
-  E[(size_t)c * n + i] = make_double2(cs, sn);
-}
-
+// Plane phases pz[L * nzt + n] = e^{-2 pi i n fz_L}, fixed while the
+// electrodes are.
 __global__ void k_plane_phase(int nlayers, int nzt, const double* __restrict__ layer_fz,
                               double2* __restrict__ pz) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -617,13 +609,10 @@ __global__ void k_plane_phase(int nlayers, int nzt, const double* __restrict__ l
   pz[e] = make_double2(cs, -sn);
 }
 
-void launch_electrode_phases(hipStream_t st, int n, int ncolsort, const int* sc_nx,
-                             const int* sc_ny, const Buffers& b, int nlayers, int nzt,
-                             double2* E, double2* pz) {
-  hipLaunchKernelGGL(k_electrode_phase, dim3((n + 255) / 256, ncolsort), dim3(256), 0, st, n, sc_nx,
-                     sc_ny, b.efx, b.efy, E);
+void launch_plane_phases(hipStream_t st, int nlayers, int nzt, const double* layer_fz,
+                         double2* pz) {
   hipLaunchKernelGGL(k_plane_phase, dim3((nlayers * nzt + 255) / 256), dim3(256), 0, st, nlayers,
-                     nzt, b.layer_fz, pz);
+                     nzt, layer_fz, pz);
 }
 
 // sfw[k] = 2 W(k) * sum_chunks part[chunk][k]   (fixed chunk order)
@@ -1112,67 +1101,23 @@ __global__ void __launch_bounds__(256) k_combine(int n, int kchunks, int rchunks
     reinterpret_cast<double*>(out)[i] = b;
 }
 
-// Planar electrodes, a group of g configurations, step 1: partial k-space
-// potentials phi_k = sum_c [cos th_ci Re T(c, L_i) + sin th_ci Im T(c, L_i)]
-// over one group of columns, from the precomputed electrode phases E.
-// Workgroup: 64 atoms x 4 lanes groups; lane group u takes every 4th column
-// of the workgroup's column group and accumulates all g configurations;
-// the 4 partial sums are added in a fixed order.
-// part[(cg * g + s) * n + i].
-constexpr int LC_MAXG = 32;
-
-__global__ void __launch_bounds__(256) k_layer_project_g(int g, int n, int ncolsort, int cpg,
-                                                         int nlayers,
-                                                         const double2* __restrict__ E,
-                                                         const int* __restrict__ layer_of,
-                                                         const double2* __restrict__ T,
-                                                         double* __restrict__ part) {
-  __shared__ double red[3][LC_MAXG][64];
-  const int li = threadIdx.x & 63, u = threadIdx.x >> 6;
-  const int i = blockIdx.x * 64 + li, cg = blockIdx.y;
-  const int c0 = cg * cpg, c1 = min(ncolsort, c0 + cpg);
-  const int L = i < n ? layer_of[i] : 0;
-  double acc[LC_MAXG];
-#pragma unroll
-  for (int s = 0; s < LC_MAXG; ++s) acc[s] = 0.0;
-  if (i < n) {
-    for (int c = c0 + u; c < c1; c += 4) {
-      const double2 e = E[(size_t)c * n + i];
-      const double2* tc = T + ((size_t)c * nlayers + L) * g;
-#pragma unroll
-      for (int s = 0; s < LC_MAXG; ++s)
-        if (s < g) {
-          const double2 t = tc[s];
-          acc[s] += e.x * t.x + e.y * t.y;
-        }
-    }
-  }
-  if (u > 0)
-#pragma unroll
-    for (int s = 0; s < LC_MAXG; ++s)
-      if (s < g) red[u - 1][s][li] = acc[s];
-  __syncthreads();
-  if (u == 0 && i < n)
-#pragma unroll
-    for (int s = 0; s < LC_MAXG; ++s)
-      if (s < g)
-        part[((size_t)cg * g + s) * n + i] =
-            (acc[s] + red[0][s][li]) + (red[1][s][li] + red[2][s][li]);
-}
-
-// step 2: b_i = -k_e (sum of column-group partials + sum of real-space
-// partials + sum_d c_d r_id M_d), thread per (atom, configuration).
-__global__ void k_layer_final(int g, int n, int cgroups, const double* __restrict__ phik,
-                              const double* __restrict__ phir, int rchunks,
-                              const double* __restrict__ ex, const double* __restrict__ ey,
-                              const double* __restrict__ ez, const double* __restrict__ dip,
-                              int dip_blocks, double cx, double cy, double cz, double ke,
-                              void* out, int out_is_f32) {
+// Planar electrodes, a group of g configurations: b_i = -k_e (k-space
+// potential + sum of real-space partials + sum_d c_d r_id M_d), thread per
+// (atom, configuration).  The k-space potential of atom i is the sum, in
+// order, of the nparts parts the projection product left in atom i's slot
+// row: Phi[(q nslot + slot_of[i]) 64 + s].
+__global__ void k_b_final(int g, int n, int nslot, int nparts, const int* __restrict__ slot_of,
+                          const double* __restrict__ Phi, const double* __restrict__ phir,
+                          int rchunks, const double* __restrict__ ex,
+                          const double* __restrict__ ey, const double* __restrict__ ez,
+                          const double* __restrict__ dip, int dip_blocks, double cx, double cy,
+                          double cz, double ke, void* out, int out_is_f32) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
   if (i >= n) return;
+  const size_t r = slot_of[i];
   double pk = 0.0, pr = 0.0, M[3];
-  for (int r = 0; r < cgroups; ++r) pk += phik[((size_t)r * g + s) * n + i];
-  for (int r = 0; r < rchunks; ++r) pr += phir[((size_t)s * rchunks + r) * n + i];
+  for (int q = 0; q < nparts; ++q) pk += Phi[((size_t)q * nslot + r) * 64 + s];
+  for (int k = 0; k < rchunks; ++k) pr += phir[((size_t)s * rchunks + k) * n + i];
   elyt_dipole(dip, dip_blocks, s, M);
   const double bv = -ke * ((pk + pr) + (cx * ex[i] * M[0] + cy * ey[i] * M[1] + cz * ez[i] * M[2]));
   if (out_is_f32)
@@ -1181,20 +1126,14 @@ __global__ void k_layer_final(int g, int n, int cgroups, const double* __restric
     reinterpret_cast<double*>(out)[(size_t)s * n + i] = bv;
 }
 
-void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlayers, int cgroups,
-                            const double2* E, const int* layer_of, const double2* T,
-                            double* phik, const double* phir, int rchunks, const Buffers& b,
-                            const double* dip, int dip_blocks, const double* cdip, double ke,
-                            void* out, int out_is_f32) {
-  const int cpg = (ncolsort + cgroups - 1) / cgroups;
-  hipLaunchKernelGGL(k_layer_project_g, dim3((n + 63) / 64, cgroups), dim3(256), 0, st, g, n,
-                     ncolsort, cpg, nlayers, E, layer_of, T, phik);
-  hipLaunchKernelGGL(k_layer_final, dim3((n + 255) / 256, g), dim3(256), 0, st, g, n, cgroups,
-                     phik, phir, rchunks, b.ex, b.ey, b.ez, dip, dip_blocks, cdip[0], cdip[1],
-                     cdip[2], ke, out, out_is_f32);
+void launch_b_final(hipStream_t st, int g, int n, int nslot, int nparts, const int* slot_of,
+                    const double* Phi, const double* phir, int rchunks, const Buffers& b,
+                    const double* dip, int dip_blocks, const double* cdip, double ke, void* out,
+                    int out_is_f32) {
+  hipLaunchKernelGGL(k_b_final, dim3((n + 255) / 256, g), dim3(256), 0, st, g, n, nslot, nparts,
+                     slot_of, Phi, phir, rchunks, b.ex, b.ey, b.ez, dip, dip_blocks, cdip[0],
+                     cdip[1], cdip[2], ke, out, out_is_f32);
 }
-
-int layer_combine_max_group() { return LC_MAXG; }
 
 int real_space_block_atoms() { return 64 * RS_WAVES; }
 

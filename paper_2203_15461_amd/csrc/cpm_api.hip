@@ -298,29 +298,23 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     c->mpad = std::max(16, (c->m + 15) / 16 * 16);
     c->sft_rows = sf_table_rows(c->nxm, c->nym, c->sfm_nbz);
     c->sft_blocks = (c->mpad + 255) / 256;
-    // planar electrodes: configurations per launch group, within ~512 MB of
-    // per-configuration workspace and the combine kernel's LDS
+    // planar electrodes: configurations per launch group (at most the 64
+    // columns of the projection product), within ~512 MB of per-configuration
+    // workspace
     if (fast) {
       const double per = 16.0 * c->sft_rows * c->mpad + 8.0 * c->sfm_pchunk +
-                         16.0 * c->ncolsort * c->nlayers + 8.0 * c->rchunks * c->n +
-                         24.0 * ((c->m + 255) / 256);
-      c->pv_group = std::max(1, std::min(layer_combine_max_group(),
-                                         (int)(512.0 * 1024 * 1024 / per)));
-      // column groups of the projection: ~1024 workgroups, >= 8 columns each
-      c->lp_groups = std::max(1, std::min((1024 + (c->n + 63) / 64 - 1) / ((c->n + 63) / 64),
-                                          c->ncolsort / 8));
+                         8.0 * c->rchunks * c->n + 24.0 * ((c->m + 255) / 256);
+      c->pv_group = std::max(1, std::min(CG_MAXG, (int)(512.0 * 1024 * 1024 / per)));
     }
     const int G = c->pv_group;
     size_t part_rows = 0;                 // (configuration, chunk) blocks of sfm_part
     for (int g = 1; g <= G; ++g) part_rows = std::max(part_rows, (size_t)g * sf_chunks_for(c, g));
     TRY(dalloc(c, &b.sfm_part, part_rows * c->sfm_pchunk));
     TRY(dalloc(c, &b.sft, (size_t)G * c->sft_rows * c->mpad));
-    if (fast) TRY(dalloc(c, &b.sflT, (size_t)G * c->ncolsort * c->nlayers));
   }
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
   const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
-  TRY(dalloc(c, &b.phik_part,
-             (size_t)c->n * std::max({pk_rows, c->kchunks, c->lp_groups * c->pv_group})));
+  TRY(dalloc(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
   TRY(dalloc(c, &b.phir_part, (size_t)c->pv_group * c->n * c->rchunks));
   c->dip_blocks = std::max(1, (c->m + 255) / 256);
   TRY(dalloc(c, &b.dip, (size_t)c->pv_group * c->dip_blocks * 3));
@@ -687,6 +681,7 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     }
     if (b.amap && (int)amap.size() != c->nmap) dfree(c, b.amap);
     c->nmap = (int)amap.size();
+    c->h_amap = amap;
     TRY(dalloc(c, &b.amap, amap.size()));
     HIP_TRY(c, hipMemcpy(b.amap, amap.data(), amap.size() * sizeof(int), hipMemcpyHostToDevice));
   }
@@ -695,13 +690,45 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
   launch_prep_electrodes(c->stream, n, d_xyz, p.Lx, p.Ly, c->Lz, b);
   TRY(launched(c, "prep_electrodes"));
   if (c->nlayers > 0 && c->sf_mfma) {
-    // fixed electrode phases for the planar k-space projection
-    const int nzt = c->sfm_npadc / 2;
-    TRY(dalloc(c, &b.ephase, (size_t)c->ncolsort * n));
+    // fixed data of the planar k-space products: plane phases, the in-plane
+    // phases as a real (2 ncp) x slots matrix in atom-map order, the atom ->
+    // slot map, and the work items of the b-path projection
+    const int nzt = c->sfm_npadc / 2, nslot = c->nmap, T = nslot / 64;
     TRY(dalloc(c, &b.pz, (size_t)c->nlayers * nzt));
-    launch_electrode_phases(c->stream, n, c->ncolsort, b.sc_nx, b.sc_ny, b, c->nlayers, nzt,
-                            b.ephase, b.pz);
-    TRY(launched(c, "electrode phases"));
+    launch_plane_phases(c->stream, c->nlayers, nzt, b.layer_fz, b.pz);
+    c->ncp = (c->ncolsort + 31) / 32 * 32;
+    c->h_tile_plane.clear();
+    for (int L = 0; L < c->nlayers; ++L)
+      for (int t = 0; t < c->h_plane_rows[L] / 64; ++t) c->h_tile_plane.push_back(L);
+    const int kunits = 2 * c->ncp / 64;
+    const int u = std::max(2, (T * kunits + 511) / 512);
+    const int nk = (kunits + u - 1) / u;           // projection parts per slot tile
+    std::vector<int> items, slot_of(n, -1);
+    for (int I = 0; I < T; ++I)
+      for (int q = 0; q < nk; ++q)
+        items.insert(items.end(), {I, 0, kunits * q / nk * 64, kunits * (q + 1) / nk * 64, q,
+                                   c->h_tile_plane[I]});
+    for (int r = 0; r < nslot; ++r)
+      if (c->h_amap[r] >= 0) slot_of[c->h_amap[r]] = r;
+    if (c->planar_nslot != nslot || c->b_nparts != nk) {   // sizes follow the atom map
+      dfree(c, b.Ecat); dfree(c, b.slot_of); dfree(c, b.b_items); dfree(c, b.bT);
+      dfree(c, b.bPhi);
+    }
+    c->planar_nslot = nslot;
+    c->b_nitems = T * nk;
+    c->b_nparts = nk;
+    TRY(dalloc(c, &b.Ecat, (size_t)2 * c->ncp * nslot));
+    TRY(dalloc(c, &b.slot_of, (size_t)n));
+    TRY(dalloc(c, &b.b_items, items.size()));
+    if (!b.bT) {
+      TRY(dalloc(c, &b.bT, (size_t)c->nlayers * 2 * c->ncp * CG_MAXG));
+      HIP_TRY(c, hipMemset(b.bT, 0, (size_t)c->nlayers * 2 * c->ncp * CG_MAXG * sizeof(double)));
+    }
+    TRY(dalloc(c, &b.bPhi, (size_t)nk * nslot * CG_MAXG));
+    HIP_TRY(c, hipMemcpy(b.slot_of, slot_of.data(), n * sizeof(int), hipMemcpyHostToDevice));
+    HIP_TRY(c, hipMemcpy(b.b_items, items.data(), items.size() * sizeof(int), hipMemcpyHostToDevice));
+    launch_cg_ephase(c->stream, nslot, c->ncp, c->ncolsort, b.amap, b, b.Ecat);
+    TRY(launched(c, "planar phases"));
   }
   const double eta_ee = p.eta / std::sqrt(2.0);
   const double diag_self = (std::sqrt(2.0) * p.eta - 2.0 * p.alpha) / std::sqrt(M_PI);
@@ -712,19 +739,12 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     TRY(dalloc(c, &b.Qpair, (size_t)c->ncolsort * c->nlayers * c->nlayers));
     launch_plane_pair_weights(c->stream, c->ncolsort, c->nlayers, b.sc_lo, b.sc_len, b.sc_koff,
                               b.w2, b.layer_fz, b.Qpair);
-    std::vector<int> poff(c->nlayers + 1, 0), tplane;
-    for (int L = 0; L < c->nlayers; ++L) {
-      poff[L + 1] = poff[L] + c->h_plane_rows[L];
-      for (int t = 0; t < c->h_plane_rows[L] / 64; ++t) tplane.push_back(L);
-    }
+    std::vector<int> poff(c->nlayers + 1, 0);
+    const std::vector<int>& tplane = c->h_tile_plane;
+    for (int L = 0; L < c->nlayers; ++L) poff[L + 1] = poff[L] + c->h_plane_rows[L];
     const int nslot = c->nmap;                    // slots: the atom map (64-slot plane tiles)
     TRY(dalloc(c, &b.plane_off, poff.size()));
     HIP_TRY(c, hipMemcpy(b.plane_off, poff.data(), poff.size() * sizeof(int), hipMemcpyHostToDevice));
-    // in-plane phases in slot order for the k-space products
-    c->ncp = (c->ncolsort + 31) / 32 * 32;
-    TRY(dalloc(c, &b.Ecat, (size_t)2 * c->ncp * nslot));
-    launch_cg_ephase(c->stream, nslot, c->ncp, c->ncolsort, b.amap, b, b.Ecat);
-    TRY(launched(c, "operator phases"));
     {
       const int jchunks = std::max(1, std::min(64, (nslot + 1023) / 1024));
       int* cnt = nullptr;
@@ -1131,11 +1151,13 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
         launch_b_sf_layer_reduce(st, g, c->ncolsort, nch, c->sfm_pchunk, c->nlayers,
                                  c->sfm_npadc / 2, c->sfm_maxcnt, b.tile_nb, b.tile_off, b.sc_lo,
                                  b.sc_len, b.sc_koff, b.sc_nidx, b.sfm_part, b.w2, b.pz,
-                                 b.sflT); }
+                                 2 * c->ncp, b.bT); }
+      { Timed t(c, "projection");
+        launch_cg_tiles(st, c->b_nitems, c->nmap, c->ncp, b.b_items, b.Ecat, b.bT, nullptr,
+                        nullptr, nullptr, b.bPhi); }
       { Timed t(c, "combine");
-        launch_b_layer_combine(st, g, n, c->ncolsort, c->nlayers, c->lp_groups, b.ephase,
-                               b.layer_of, b.sflT, b.phik_part, b.phir_part, c->rchunks, b,
-                               b.dip, c->dip_blocks, c->cdip, c->ke, out, b_is_f32); }
+        launch_b_final(st, g, n, c->nmap, c->b_nparts, b.slot_of, b.bPhi, b.phir_part,
+                       c->rchunks, b, b.dip, c->dip_blocks, c->cdip, c->ke, out, b_is_f32); }
       TRY(launched(c, "potential_vector"));
       continue;
     }
@@ -1756,7 +1778,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.layer_of); dfree(b.layer_fz); dfree(b.layerT); dfree(b.amap);
   dfree(b.sc_nx); dfree(b.sc_ny); dfree(b.sc_lo); dfree(b.sc_len); dfree(b.sc_koff); dfree(b.sc_n0);
   dfree(b.sc_nidx); dfree(b.tile_nb); dfree(b.sfm_part); dfree(b.sfm_items); dfree(b.sft);
-  dfree(b.tile_off); dfree(b.ephase); dfree(b.pz); dfree(b.sflT);
+  dfree(b.tile_off); dfree(b.pz); dfree(b.slot_of); dfree(b.b_items); dfree(b.bT); dfree(b.bPhi);
   dfree(b.runs); dfree(b.cols); dfree(b.chunk_col); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);

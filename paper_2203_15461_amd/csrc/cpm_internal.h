@@ -68,9 +68,11 @@ struct Buffers {
   double* sfm_part = nullptr;      // chunk partials [chunk][tile][32][npadc]
   int4* sfm_items = nullptr;       // work items {M tile, first n block, n blocks, 0}
   int* tile_off = nullptr;         // offset of each M tile's block in a chunk of sfm_part
-  double2* ephase = nullptr;       // electrode in-plane phases per sorted column (ncolsort x n)
+  int* slot_of = nullptr;          // atom -> slot of the atom map (n)
+  int* b_items = nullptr;          // work items of the b-path projection product
   double2* pz = nullptr;           // plane phases e^{-i n kz1 z_L} (nlayers x nzt)
-  double2* sflT = nullptr;         // T(c, L) per configuration of a group
+  double* bT = nullptr;             // T(c, L) of a group as the projection operand (nL x 2 ncp x 64)
+  double* bPhi = nullptr;          // projection parts (b_nparts x slots x 64)
   double2* sft = nullptr;          // per-charge phase tables (rows x mpad)
   double* w2 = nullptr;            // 2 W(k), nk (flat run order)
   int* knx = nullptr; int* kny = nullptr; int* knz = nullptr;     // nk
@@ -227,9 +229,12 @@ struct cpm_ctx {
   int sfm_pchunk = 0;              // doubles per (configuration, chunk) of sfm_part
   int sfm_maxcnt = 0;              // largest number of n >= 0 of a sorted column
   int pv_group = 1;                // configurations per launch group (planar fast path)
-  int lp_groups = 1;               // column groups of the planar projection
+  int b_nitems = 0, b_nparts = 1;  // work split of the b-path projection product
   int nmap = 0;                    // length of the real-space atom map
   std::vector<int> h_plane_rows;   // rows of the atom map per plane (multiples of 64)
+  std::vector<int> h_amap;         // the atom map (host copy)
+  std::vector<int> h_tile_plane;   // plane of each 64-slot tile of the atom map
+  int planar_nslot = 0;            // slots the planar k-space buffers were sized for
   std::vector<int> h_tile_off;
   std::vector<int4> h_sfm_items;
   std::vector<int> h_sc_nx, h_sc_ny, h_sc_lo, h_sc_len, h_sc_koff, h_sc_n0, h_sc_nidx, h_tile_nb;
@@ -364,16 +369,15 @@ void launch_b_sf_layer_reduce(hipStream_t st, int g, int ncolsort, int nchunks, 
                               int nlayers, int nzt, int max_ncnt, const int* tile_nb,
                               const int* toff, const int* sc_lo, const int* sc_len,
                               const int* sc_koff, const int* n_index, const double* part,
-                              const double* w2, const double2* pz, double2* T);
-void launch_electrode_phases(hipStream_t st, int n, int ncolsort, const int* sc_nx,
-                             const int* sc_ny, const Buffers& b, int nlayers, int nzt,
-                             double2* E, double2* pz);
-void launch_b_layer_combine(hipStream_t st, int g, int n, int ncolsort, int nlayers, int cgroups,
-                            const double2* E, const int* layer_of, const double2* T,
-                            double* phik, const double* phir, int rchunks, const Buffers& b,
-                            const double* dip, int dip_blocks, const double* cdip, double ke,
-                            void* out, int out_is_f32);
-int layer_combine_max_group();
+                              const double* w2, const double2* pz, int M2, double* Tcat);
+void launch_plane_phases(hipStream_t st, int nlayers, int nzt, const double* layer_fz,
+                         double2* pz);
+// planar electrodes: b from the projection parts (k_cg_tiles over the slot
+// tiles), the real-space partials and the dipole term
+void launch_b_final(hipStream_t st, int g, int n, int nslot, int nparts, const int* slot_of,
+                    const double* Phi, const double* phir, int rchunks, const Buffers& b,
+                    const double* dip, int dip_blocks, const double* cdip, double ke, void* out,
+                    int out_is_f32);
 int real_space_block_atoms();      // atom-map slots per workgroup of the real-space b kernel
 
 int sf_table_rows(int nxm, int nym, int nbz);
