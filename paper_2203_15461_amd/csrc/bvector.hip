@@ -875,10 +875,10 @@ __device__ inline double pair_g(const double* __restrict__ T, double r2, double 
   return g0 + t * (d0 + t * (0.5 * e0 + t * (c3 + t * (c4 + t * c5))));
 }
 
-// Real-space part of phi_i over one chunk of the electrolyte, for each of the
-// g configurations of a group (positions and charges of configuration s
-// xyz_stride and q_stride elements apart; output rows
-// part[(s * rchunks + chunk) * n + i]).  Threads map to electrode atoms
+// Real-space part of phi_i over one chunk of the electrolyte, for the
+// configurations s = blockIdx.z, blockIdx.z + gridDim.z, ... < g of a group
+// (positions and charges of configuration s xyz_stride and q_stride elements
+// apart; output rows part[(s * rchunks + chunk) * n + i]).  Threads map to electrode atoms
 // through amap, which puts the atoms of one z plane, in compact in-plane
 // tiles, into whole waves (-1 pads).  Every wave walks the chunk 64 charges
 // at a time on its own: it keeps the charges that can come within rc of its
@@ -943,12 +943,14 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
   const float iLxf = 1.0f / Lxf, iLyf = 1.0f / Lyf, iLzf = 1.0f / Lzf;
   const float rc2f = (float)(rc2 * (1.0 + 1e-4));
   const int nblk = j1 > j0 ? (j1 - j0 + 63) / 64 : 0;
-  const int steps = g * nblk;
+  const int s0 = blockIdx.z, sstep = gridDim.z;
+  const int nloc = s0 < g ? (g - s0 + sstep - 1) / sstep : 0;   // this workgroup's configurations
+  const int steps = nloc * nblk;
   // charges of the next three steps are in flight while a step is summed
   double4 f0 = make_double4(0, 0, 0, 0), f1 = f0, f2 = f0;
   auto fetch = [&](int step) {
     double4 v = make_double4(0, 0, 0, 0);
-    const int snap = step / nblk, j = j0 + (step % nblk) * 64 + lane;
+    const int snap = s0 + sstep * (step / nblk), j = j0 + (step % nblk) * 64 + lane;
     if (step < steps && j < j1) {
       const double* r = xyz + snap * xyz_stride + (size_t)j * 3;
       v = make_double4(r[0], r[1], r[2], q[snap * q_stride + j]);
@@ -960,7 +962,7 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
   f2 = fetch(2);
   double acc = 0.0;
   for (int step = 0; step < steps; ++step) {
-    const int snap = step / nblk, blk = step % nblk;
+    const int snap = s0 + sstep * (step / nblk), blk = step % nblk;
     const bool valid = j0 + blk * 64 + lane < j1;
     const double x = f0.x, y = f0.y, z = f0.z, qq = f0.w;
     f0 = f1;
@@ -1045,7 +1047,7 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
     }
   }
   if (nblk == 0 && atom >= 0)
-    for (int snap = 0; snap < g; ++snap) part[((size_t)snap * rchunks + chunk) * n + atom] = 0.0;
+    for (int snap = s0; snap < g; snap += sstep) part[((size_t)snap * rchunks + chunk) * n + atom] = 0.0;
 }
 
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
@@ -1060,7 +1062,11 @@ void launch_real_space_pairs(hipStream_t st, int g, int n, int m, int rchunks, c
                              size_t q_stride, double Lx, double Ly, double Lz, double rc,
                              const double* table, double* part) {
   const int chunk_size = (m + rchunks - 1) / rchunks;
-  dim3 grid((nmap + 64 * RS_WAVES - 1) / (64 * RS_WAVES), rchunks), block(64 * RS_WAVES);
+  // configurations spread over the third grid dimension: about two rounds of
+  // 256 workgroups in all
+  const int ablk = (nmap + 64 * RS_WAVES - 1) / (64 * RS_WAVES);
+  const int gz = std::max(1, std::min(g, (512 + ablk * rchunks - 1) / (ablk * rchunks)));
+  dim3 grid(ablk, rchunks, gz), block(64 * RS_WAVES);
   hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, chunk_size, xyz_stride, q_stride,
                      b.amap, nmap, b.ex, b.ey, b.ez, xyz, q, Lx, Ly, Lz, rc, table, part);
 }

@@ -288,8 +288,10 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   const int run_blocks = (c->nruns + 255) / 256;
   const int sf_target = c->sf_wg_target;
   c->mchunks = std::max(1, std::min((sf_target + run_blocks - 1) / run_blocks, std::max(1, c->m / 64)));
-  // real space: 2 workgroups per CU fit (pair table in LDS), so keep the
-  // grid within one round of 512
+  // real space: 2 workgroups per CU fit (pair table in LDS); the charge
+  // chunks fill about 512 workgroups together with the configurations of a
+  // launch group (the grid's third dimension), so few partials per atom
+  // remain (rchunks is set below, once the group size is known)
   const int atom_blocks = (c->nmap + real_space_block_atoms() - 1) / real_space_block_atoms();
   c->rchunks = std::max(1, std::min(512 / atom_blocks, std::max(1, c->m / 32)));
   TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
@@ -312,6 +314,9 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     TRY(dalloc(c, &b.sfm_part, part_rows * c->sfm_pchunk));
     TRY(dalloc(c, &b.sft, (size_t)G * c->sft_rows * c->mpad));
   }
+  if (fast)
+    c->rchunks = std::max(1, std::min(std::max(1, c->m / 64),
+                                      (512 + atom_blocks * c->pv_group - 1) / (atom_blocks * c->pv_group)));
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
   const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
   TRY(dalloc(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
