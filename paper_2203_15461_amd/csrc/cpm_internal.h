@@ -207,7 +207,7 @@ struct cpm_ctx {
   int nk = 0, nruns = 0;
   int mchunks = 1, kchunks = 1, rchunks = 1;
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
-  int sfm_wg_target = 768;         // the same for the matrix-core kernel
+  int sfm_wg_target = 4096;        // the same for the matrix-core kernel
   unsigned store = 0;
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;
