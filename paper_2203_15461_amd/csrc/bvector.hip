@@ -182,8 +182,7 @@ constexpr int SFM_COLS = 16;           // columns per M tile (32 GEMM rows)
 
 struct SfmWave {                        // wave-private LDS area
   double C[2 * SFM_COLS][SFM_TJ + 1];  // A operand rows (Re C, Im C) x charges
-  double2 z0[8][SFM_TJ + 1];           // e^{2 pi i (n_lo + j) fz_t}, j = 0..7 (padded rows)
-  double2 r8[SFM_TJ];                  // e^{2 pi i 8 fz_t}
+  double B[SFM_NB][16][SFM_TJ + 1];    // B operand per n block: columns (n, Re/Im) x charges
 };
 
 __device__ inline void wave_lds_sync() {
@@ -320,9 +319,10 @@ __device__ inline void elyt_dipole(const double* __restrict__ dip, int blocks, i
 // part + (s * nchunks + chunk) * pchunk + toff[mt], row-major.
 // The tile loop, the fixed-order wave sum and the store of one work item
 // with NBW n blocks (NBW is uniform per workgroup: the kernel dispatches on
-// it, so the per-block loops have no branches).  Per 4-charge k step the B
-// operand (e^{i n kz1 z} for this lane's n) is advanced by e^{2 pi i 8 fz}
-// from block to block.
+// it, so the per-block loops have no branches).  Per tile, each lane writes
+// the B operand of its charge for two n of every block (e^{i n kz1 z},
+// advanced by e^{2 pi i 8 fz} from block to block); the k steps then only
+// read LDS and issue matrix-core products.
 template <int NBW>
 __device__ void sf_item(SfmWave& W, double* __restrict__ red, const double2* __restrict__ tab,
                         int mpad, int j0, int j1, const int (&xoff)[4], const int (&yoff)[4],
@@ -330,7 +330,6 @@ __device__ void sf_item(SfmWave& W, double* __restrict__ red, const double2* __r
                         int nb_lo) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int t_l = lane & 15, g_l = lane >> 4;
-  const bool im = t_l & 1;
   v4d_t acc0[NBW], acc1[NBW];
 #pragma unroll
   for (int b = 0; b < NBW; ++b) {
@@ -353,9 +352,19 @@ __device__ void sf_item(SfmWave& W, double* __restrict__ red, const double2* __r
       W.C[2 * cl][t_l] = cv.x;
       W.C[2 * cl + 1][t_l] = cv.y;
     }
-    W.z0[2 * g_l][t_l] = cmul2(z8, za);
-    W.z0[2 * g_l + 1][t_l] = cmul2(z8, zb);
-    if (g_l == 0) W.r8[t_l] = r8n;
+    // B columns 4 g_l .. 4 g_l + 3 (n = 2 g_l, 2 g_l + 1; Re, Im) of charge t_l
+    double2 va = cmul2(z8, za), vb = cmul2(z8, zb);
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
+      W.B[b][4 * g_l][t_l] = va.x;
+      W.B[b][4 * g_l + 1][t_l] = va.y;
+      W.B[b][4 * g_l + 2][t_l] = vb.x;
+      W.B[b][4 * g_l + 3][t_l] = vb.y;
+      if (b + 1 < NBW) {
+        va = cmul2(va, r8n);
+        vb = cmul2(vb, r8n);
+      }
+    }
     wave_lds_sync();
     if (jt + 4 * SFM_TJ < j1) fetch(jt + 4 * SFM_TJ);
     // k step ks uses charges 4 ks + g_l of the tile
@@ -363,14 +372,13 @@ __device__ void sf_item(SfmWave& W, double* __restrict__ red, const double2* __r
     for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
       const int kc = 4 * ks + g_l;
       const double a0 = W.C[t_l][kc], a1 = W.C[16 + t_l][kc];
-      double2 zz = W.z0[t_l >> 1][kc];
-      const double2 r8 = W.r8[kc];
+      double bv[NBW];
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) bv[b] = W.B[b][t_l][kc];
 #pragma unroll
       for (int b = 0; b < NBW; ++b) {
-        const double bv = im ? zz.y : zz.x;
-        acc0[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv, acc0[b], 0, 0, 0);
-        acc1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv, acc1[b], 0, 0, 0);
-        if (b + 1 < NBW) zz = cmul(zz, r8);
+        acc0[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, bv[b], acc0[b], 0, 0, 0);
+        acc1[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, bv[b], acc1[b], 0, 0, 0);
       }
     }
     wave_lds_sync();
@@ -416,8 +424,11 @@ k_sf_mfma(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restr
           int nym, const double2* __restrict__ tab, size_t tab_stride,
           const int* __restrict__ tile_nb, const int* __restrict__ toff, int pchunk,
           double* __restrict__ part) {
-  __shared__ SfmWave wl[4];
-  __shared__ double red[64 * 2 * SFM_NB * 4];      // one wave's accumulators
+  // the waves' tile areas; after the tile loops, one wave's accumulators
+  __shared__ double lds[4 * sizeof(SfmWave) / sizeof(double)];
+  static_assert(64 * 2 * SFM_NB * 4 <= 4 * sizeof(SfmWave) / sizeof(double), "LDS reuse");
+  SfmWave* wl = reinterpret_cast<SfmWave*>(lds);
+  double* red = lds;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   // workgroups go round-robin to the 8 XCDs; keep every (configuration,
   // charge chunk) pair on one XCD (pair = xcd mod 8) so its table rows stay
@@ -524,32 +535,55 @@ void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int nchunks, int pchu
 // fold k_z into the electrode planes in one pass.  For sorted column c and
 // plane L,
 //   T(c, L) = sum_{n in column} 2W(c, n) S(c, n) e^{-i n kz1 z_L},
-// so that phi_i = sum_c Re[e^{-i (kx x_i + ky y_i)} T(c, L_i)].  One wave per
-// (column, configuration): lanes take n >= 0 (both signs), keep the weighted
-// S(c, +-n) in LDS, then one fixed-order wave sum per plane.
+// so that phi_i = sum_c Re[e^{-i (kx x_i + ky y_i)} T(c, L_i)].  One workgroup
+// per (column, configuration) with nw waves: wave w sums its own contiguous
+// range of charge chunks (lanes take n >= 0), the nw partial sums are added in
+// wave order, the weighted S(c, +-n) are kept in LDS, and the planes are
+// spread over the waves (one fixed-order wave sum per plane).  nw follows the
+// chunk count, so the summation order is fixed per launch shape.
 // pz[L * nzt + n] = e^{-2 pi i n fz_L};  T is written as the real right-hand
 // operand of the projection product: Tcat[(L M2 + 2c) 64 + s] = Re T(c, L),
 // Tcat[(L M2 + 2c + 1) 64 + s] = Im T(c, L) for configuration s.
-__global__ void __launch_bounds__(64) k_sf_layer_reduce(
+__global__ void __launch_bounds__(512) k_sf_layer_reduce(
     int ncolsort, int nchunks, int pchunk, int nlayers, int nzt, const int* __restrict__ tile_nb,
     const int* __restrict__ toff, const int* __restrict__ sc_lo, const int* __restrict__ sc_len,
     const int* __restrict__ sc_koff, const int* __restrict__ n_index,
     const double* __restrict__ part, const double* __restrict__ w2,
     const double2* __restrict__ pz, int M2, double* __restrict__ Tcat) {
-  extern __shared__ double2 s_sw[];                    // [2][n count]: S(+n) w, S(-n) w
-  const int c = blockIdx.x, snap = blockIdx.y, lane = threadIdx.x;
+  extern __shared__ double2 s_sw[];    // [2][ncnt]: S(+n) w, S(-n) w; then [nw][4][ncnt] sums
+  const int c = blockIdx.x, snap = blockIdx.y;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int ncnt = n_index[c + 1] - n_index[c];        // n = 0 .. ncnt - 1
+  double* s_red = reinterpret_cast<double*>(s_sw + 2 * ncnt);
   const int mt = c / SFM_COLS, cl = c % SFM_COLS, ldc = 16 * tile_nb[mt];
   const int clo = sc_lo[c], chi = sc_lo[c] + sc_len[c] - 1, koff = sc_koff[c];
   const double* base0 = part + (size_t)snap * nchunks * pchunk + toff[mt];
+  const int c0 = wave * nchunks / nw, c1 = (wave + 1) * nchunks / nw;
   for (int n = lane; n < ncnt; n += 64) {
     double pr = 0, qr = 0, pi = 0, qi = 0;
-    for (int ch = 0; ch < nchunks; ++ch) {
+#pragma unroll 4
+    for (int ch = c0; ch < c1; ++ch) {
       const double* base = base0 + (size_t)ch * pchunk;
       pr += base[(2 * cl) * ldc + 2 * n];
       qr += base[(2 * cl) * ldc + 2 * n + 1];
       pi += base[(2 * cl + 1) * ldc + 2 * n];
       qi += base[(2 * cl + 1) * ldc + 2 * n + 1];
+    }
+    double* r = s_red + (size_t)wave * 4 * ncnt;
+    r[n] = pr;
+    r[ncnt + n] = qr;
+    r[2 * ncnt + n] = pi;
+    r[3 * ncnt + n] = qi;
+  }
+  __syncthreads();
+  for (int n = threadIdx.x; n < ncnt; n += blockDim.x) {
+    double pr = 0, qr = 0, pi = 0, qi = 0;
+    for (int w = 0; w < nw; ++w) {
+      const double* r = s_red + (size_t)w * 4 * ncnt;
+      pr += r[n];
+      qr += r[ncnt + n];
+      pi += r[2 * ncnt + n];
+      qi += r[3 * ncnt + n];
     }
     double2 sp = make_double2(0.0, 0.0), sm = make_double2(0.0, 0.0);
     if (n >= clo && n <= chi) {
@@ -564,7 +598,7 @@ __global__ void __launch_bounds__(64) k_sf_layer_reduce(
     s_sw[ncnt + n] = sm;
   }
   __syncthreads();
-  for (int L = 0; L < nlayers; ++L) {
+  for (int L = wave; L < nlayers; L += nw) {
     double tr = 0.0, ti = 0.0;
     for (int n = lane; n < ncnt; n += 64) {
       const double2 p = pz[(size_t)L * nzt + n];      // e^{-i n kz1 z_L}
@@ -589,10 +623,16 @@ void launch_b_sf_layer_reduce(hipStream_t st, int g, int ncolsort, int nchunks, 
                               const int* toff, const int* sc_lo, const int* sc_len,
                               const int* sc_koff, const int* n_index, const double* part,
                               const double* w2, const double2* pz, int M2, double* Tcat) {
-  const size_t shm = (size_t)2 * max_ncnt * sizeof(double2);
-  hipLaunchKernelGGL(k_sf_layer_reduce, dim3(ncolsort, g), dim3(64), shm, st, ncolsort, nchunks,
-                     pchunk, nlayers, nzt, tile_nb, toff, sc_lo, sc_len, sc_koff, n_index, part,
-                     w2, pz, M2, Tcat);
+  // about 8 chunks per wave, at most 8 waves, within 64 KB of LDS
+  int nw = std::max(1, std::min(8, (nchunks + 7) / 8));
+  auto lds = [&](int w) {
+    return (size_t)2 * max_ncnt * sizeof(double2) + (size_t)w * 4 * max_ncnt * sizeof(double);
+  };
+  while (nw > 1 && lds(nw) > 65536) --nw;
+  const size_t shm = lds(nw);
+  hipLaunchKernelGGL(k_sf_layer_reduce, dim3(ncolsort, g), dim3(64 * nw), shm, st, ncolsort,
+                     nchunks, pchunk, nlayers, nzt, tile_nb, toff, sc_lo, sc_len, sc_koff, n_index,
+                     part, w2, pz, M2, Tcat);
 }
 
 // Plane phases pz[L * nzt + n] = e^{-2 pi i n fz_L}, fixed while the
@@ -1108,24 +1148,39 @@ __global__ void __launch_bounds__(256) k_combine(int n, int kchunks, int rchunks
 }
 
 // Planar electrodes, a group of g configurations: b_i = -k_e (k-space
-// potential + sum of real-space partials + sum_d c_d r_id M_d), thread per
-// (atom, configuration).  The k-space potential of atom i is the sum, in
-// order, of the nparts parts the projection product left in atom i's slot
-// row: Phi[(q nslot + slot_of[i]) 64 + s].
-__global__ void k_b_final(int g, int n, int nslot, int nparts, const int* __restrict__ slot_of,
-                          const double* __restrict__ Phi, const double* __restrict__ phir,
-                          int rchunks, const double* __restrict__ ex,
-                          const double* __restrict__ ey, const double* __restrict__ ez,
-                          const double* __restrict__ dip, int dip_blocks, double cx, double cy,
-                          double cz, double ke, void* out, int out_is_f32) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x, s = blockIdx.y;
-  if (i >= n) return;
-  const size_t r = slot_of[i];
-  double pk = 0.0, pr = 0.0, M[3];
-  for (int q = 0; q < nparts; ++q) pk += Phi[((size_t)q * nslot + r) * 64 + s];
-  for (int k = 0; k < rchunks; ++k) pr += phir[((size_t)s * rchunks + k) * n + i];
+// potential + sum of real-space partials + sum_d c_d r_id M_d).  A workgroup
+// takes 64 atoms of one configuration s with four lanes per atom; lane group
+// u sums the parts q = u, u + 4, ... and the real-space chunks k = u, u + 4,
+// ..., and the four sums are added in a fixed order.  The k-space parts of
+// atom i are the rows the projection product left in its slot:
+// Phi[(q nslot + slot_of[i]) 64 + s].
+__global__ void __launch_bounds__(256) k_b_final(int n, int nslot, int nparts,
+                                                 const int* __restrict__ slot_of,
+                                                 const double* __restrict__ Phi,
+                                                 const double* __restrict__ phir, int rchunks,
+                                                 const double* __restrict__ ex,
+                                                 const double* __restrict__ ey,
+                                                 const double* __restrict__ ez,
+                                                 const double* __restrict__ dip, int dip_blocks,
+                                                 double cx, double cy, double cz, double ke,
+                                                 void* out, int out_is_f32) {
+  __shared__ double sh[4][64];
+  const int sub = threadIdx.x >> 6, li = threadIdx.x & 63, s = blockIdx.y;
+  const int i = blockIdx.x * 64 + li;
+  double acc = 0.0;
+  if (i < n) {
+    const size_t r = slot_of[i];
+    for (int q = sub; q < nparts; q += 4) acc += Phi[((size_t)q * nslot + r) * 64 + s];
+#pragma unroll 4
+    for (int k = sub; k < rchunks; k += 4) acc += phir[((size_t)s * rchunks + k) * n + i];
+  }
+  sh[sub][li] = acc;
+  __syncthreads();
+  if (sub != 0 || i >= n) return;
+  double M[3];
   elyt_dipole(dip, dip_blocks, s, M);
-  const double bv = -ke * ((pk + pr) + (cx * ex[i] * M[0] + cy * ey[i] * M[1] + cz * ez[i] * M[2]));
+  const double phi = (sh[0][li] + sh[1][li]) + (sh[2][li] + sh[3][li]);
+  const double bv = -ke * (phi + (cx * ex[i] * M[0] + cy * ey[i] * M[1] + cz * ez[i] * M[2]));
   if (out_is_f32)
     reinterpret_cast<float*>(out)[(size_t)s * n + i] = (float)bv;
   else
@@ -1136,7 +1191,7 @@ void launch_b_final(hipStream_t st, int g, int n, int nslot, int nparts, const i
                     const double* Phi, const double* phir, int rchunks, const Buffers& b,
                     const double* dip, int dip_blocks, const double* cdip, double ke, void* out,
                     int out_is_f32) {
-  hipLaunchKernelGGL(k_b_final, dim3((n + 255) / 256, g), dim3(256), 0, st, g, n, nslot, nparts,
+  hipLaunchKernelGGL(k_b_final, dim3((n + 63) / 64, g), dim3(256), 0, st, n, nslot, nparts,
                      slot_of, Phi, phir, rchunks, b.ex, b.ey, b.ez, dip, dip_blocks, cdip[0],
                      cdip[1], cdip[2], ke, out, out_is_f32);
 }

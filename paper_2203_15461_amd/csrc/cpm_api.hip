@@ -199,14 +199,26 @@ void build_kset(cpm_ctx* c, std::vector<KRun>& runs, std::vector<double>& w2,
 }
 
 // charge chunks per configuration for a group of g configurations on the
-// matrix-core structure-factor path: about sfm_wg_target workgroups, and
-// g * chunks a multiple of 8 (the kernel keeps each (configuration, chunk)
-// pair on one XCD)
+// matrix-core structure-factor path: about sfm_wg_target workgroups, at
+// least sfm_min_chunk charges per chunk (small groups: fewer partials to
+// write and sum), and g * chunks a multiple of 8 (the kernel keeps each
+// (configuration, chunk) pair on one XCD)
 int sf_chunks_for(const cpm_ctx* c, int g) {
-  const int base = std::max(1, (c->sfm_wg_target + c->sfm_nitems * g - 1) / (c->sfm_nitems * g));
+  const int base = std::max(1, std::min((c->sfm_wg_target + c->sfm_nitems * g - 1) / (c->sfm_nitems * g),
+                                        c->m / c->sfm_min_chunk));
   int step = 8;
   while (step > 1 && g % (8 / step * 2) == 0) step /= 2;   // step = 8 / gcd(g, 8)
   return (base + step - 1) / step * step;
+}
+
+// real-space charge chunks for a launch group of g configurations on the
+// grouped path: the chunks and the configurations (the grid's third
+// dimension) fill about rs_wg_target workgroups together, >= 64 charges per
+// chunk
+int rchunks_for(const cpm_ctx* c, int g) {
+  const int atom_blocks = (c->nmap + real_space_block_atoms() - 1) / real_space_block_atoms();
+  const int t = c->rs_wg_target;
+  return std::max(1, std::min(std::max(1, c->m / 64), (t + atom_blocks * g - 1) / (atom_blocks * g)));
 }
 
 cpm_status ensure_vat(cpm_ctx* c) {
@@ -314,13 +326,14 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     TRY(dalloc(c, &b.sfm_part, part_rows * c->sfm_pchunk));
     TRY(dalloc(c, &b.sft, (size_t)G * c->sft_rows * c->mpad));
   }
+  // (configuration, chunk) rows of the real-space partials
+  size_t rrows = (size_t)c->rchunks;
   if (fast)
-    c->rchunks = std::max(1, std::min(std::max(1, c->m / 64),
-                                      (512 + atom_blocks * c->pv_group - 1) / (atom_blocks * c->pv_group)));
+    for (int g = 1; g <= c->pv_group; ++g) rrows = std::max(rrows, (size_t)g * rchunks_for(c, g));
   TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
   const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
   TRY(dalloc(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
-  TRY(dalloc(c, &b.phir_part, (size_t)c->pv_group * c->n * c->rchunks));
+  TRY(dalloc(c, &b.phir_part, rrows * c->n));
   c->dip_blocks = std::max(1, (c->m + 255) / 256);
   TRY(dalloc(c, &b.dip, (size_t)c->pv_group * c->dip_blocks * 3));
   TRY(dalloc(c, &b.rtab, (size_t)3 * (RS_NT + 1)));
@@ -471,6 +484,8 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (p.geometry == CPM_GEOM_WIRE) c->cdip[0] = c->cdip[1] = 2.0 * M_PI / c->V;
   if (const char* ev = std::getenv("CPM_SF_WG_TARGET")) c->sf_wg_target = std::max(64, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_WG_TARGET")) c->sfm_wg_target = std::max(8, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_SFM_MIN_CHUNK")) c->sfm_min_chunk = std::max(16, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
@@ -1131,6 +1146,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
       continue;
     }
     const int nch = mfma ? sf_chunks_for(c, g) : 0;
+    const int rch = fast ? rchunks_for(c, g) : c->rchunks;
     { Timed t(c, "dipole");
       launch_b_elyt_dipole(st, g, m, xyz, b.elq, b.dip); }
     if (mfma) {
@@ -1149,7 +1165,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
         launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
     }
     { Timed t(c, "real_space_b");
-      launch_b_real_space(st, g, n, m, c->rchunks, b, c->nmap, xyz, b.elq, p.Lx, p.Ly, c->Lz,
+      launch_b_real_space(st, g, n, m, rch, b, c->nmap, xyz, b.elq, p.Lx, p.Ly, c->Lz,
                           p.rcut, b.phir_part); }
     if (fast) {
       { Timed t(c, "sf_reduce");
@@ -1162,7 +1178,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
                         nullptr, nullptr, b.bPhi); }
       { Timed t(c, "combine");
         launch_b_final(st, g, n, c->nmap, c->b_nparts, b.slot_of, b.bPhi, b.phir_part,
-                       c->rchunks, b, b.dip, c->dip_blocks, c->cdip, c->ke, out, b_is_f32); }
+                       rch, b, b.dip, c->dip_blocks, c->cdip, c->ke, out, b_is_f32); }
       TRY(launched(c, "potential_vector"));
       continue;
     }

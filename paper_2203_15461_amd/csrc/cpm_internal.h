@@ -208,6 +208,8 @@ struct cpm_ctx {
   int mchunks = 1, kchunks = 1, rchunks = 1;
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
   int sfm_wg_target = 4096;        // the same for the matrix-core kernel
+  int sfm_min_chunk = 512;         // fewest charges per matrix-core chunk
+  int rs_wg_target = 512;          // real-space workgroups per launch group
   unsigned store = 0;
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;

@@ -228,6 +228,41 @@ __device__ inline double block_sum256(double v, double* sh) {
   return t;
 }
 
+// sum over a 1024-thread workgroup: wave sums, then the 16 in wave order
+__device__ inline double block_sum1024(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+#pragma unroll
+  for (int w = 0; w < 16; ++w) t += sh[w];
+  __syncthreads();
+  return t;
+}
+
+// four sums at once over a 1024-thread workgroup (sh: 4 x 16); every thread
+// receives the four totals
+__device__ inline void block_sum1024x4(double (&v)[4], double (*sh)[16]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) sh[k][wave] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += sh[k][w];
+    v[k] = t;
+  }
+  __syncthreads();
+}
+
 // out[i] = sum_{j<n} M[i][j] for i < n (one wave per row, fixed order)
 __global__ void k_row_sums(int n, int npad, const double* __restrict__ M, double* out) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -402,35 +437,35 @@ void launch_matvec(hipStream_t st, int which, int n, int npad, const void* M, in
 // means[b] = (1/n) sum_{i<n} x[b][i]: the uniform part of a right-hand side.
 // S e = 0, so S x = S (x - mean e); removing it first keeps the rounding of a
 // low-precision S from acting on the (large) uniform potential.
-__global__ void __launch_bounds__(256) k_row_means(int n, const void* __restrict__ x, int x_is_f32,
-                                                   int ldx, double* __restrict__ means) {
-  __shared__ double sh[4];
+__global__ void __launch_bounds__(1024) k_row_means(int n, const void* __restrict__ x, int x_is_f32,
+                                                    int ldx, double* __restrict__ means) {
+  __shared__ double sh[16];
   const int b = blockIdx.x;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256)
+  for (int i = threadIdx.x; i < n; i += 1024)
     s += x_is_f32 ? (double)reinterpret_cast<const float*>(x)[(size_t)b * ldx + i]
                   : reinterpret_cast<const double*>(x)[(size_t)b * ldx + i];
-  s = block_sum256(s, sh);
+  s = block_sum1024(s, sh);
   if (threadIdx.x == 0) means[b] = s / n;
 }
 
 void launch_row_means(hipStream_t st, int n, int batch, const void* x, int x_is_f32, int ldx,
                       double* means) {
-  hipLaunchKernelGGL(k_row_means, dim3(batch), dim3(256), 0, st, n, x, x_is_f32, ldx, means);
+  hipLaunchKernelGGL(k_row_means, dim3(batch), dim3(1024), 0, st, n, x, x_is_f32, ldx, means);
 }
 
 // x[b][i] -= mean_b over i < n (in place, FP64, stride ld)
-__global__ void __launch_bounds__(256) k_center_rows(int n, int ld, double* __restrict__ x) {
-  __shared__ double sh[4];
+__global__ void __launch_bounds__(1024) k_center_rows(int n, int ld, double* __restrict__ x) {
+  __shared__ double sh[16];
   double* row = x + (size_t)blockIdx.x * ld;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += row[i];
-  s = block_sum256(s, sh) / n;
-  for (int i = threadIdx.x; i < n; i += 256) row[i] -= s;
+  for (int i = threadIdx.x; i < n; i += 1024) s += row[i];
+  s = block_sum1024(s, sh) / n;
+  for (int i = threadIdx.x; i < n; i += 1024) row[i] -= s;
 }
 
 void launch_center_rows(hipStream_t st, int n, int ld, int batch, double* x) {
-  hipLaunchKernelGGL(k_center_rows, dim3(batch), dim3(256), 0, st, n, ld, x);
+  hipLaunchKernelGGL(k_center_rows, dim3(batch), dim3(1024), 0, st, n, ld, x);
 }
 
 // c[b] = b[b] + v (FP64, npad stride, zero padding): the right-hand side of
@@ -455,39 +490,53 @@ void launch_make_rhs(hipStream_t st, int n, int npad, int batch, const void* bsr
 // ---------------------------------------------------------------------------
 // Neutrality projection and electrode totals, one workgroup per vector:
 //   q = qt - (e^T qt / s) u,   Q_alpha = sum_{i in alpha} q_i  (FP64).
+// The totals of four electrodes are gathered in the pass that writes q (and
+// of four more per further pass); each is one fixed-order workgroup sum.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) k_finalize(int n, const double* __restrict__ qt, int ldqt,
-                                                  const double* __restrict__ add,
-                                                  const double* __restrict__ u,
-                                                  const double* __restrict__ s_dev,
-                                                  const int* __restrict__ eid, int n_e,
-                                                  double* __restrict__ q, int ldq,
-                                                  double* __restrict__ Qe) {
-  __shared__ double sh[4];
+__global__ void __launch_bounds__(1024) k_finalize(int n, const double* __restrict__ qt, int ldqt,
+                                                   const double* __restrict__ add,
+                                                   const double* __restrict__ u,
+                                                   const double* __restrict__ s_dev,
+                                                   const int* __restrict__ eid, int n_e,
+                                                   double* __restrict__ q, int ldq,
+                                                   double* __restrict__ Qe) {
+  __shared__ double sh[4][16];
   const int b = blockIdx.x;
   const double* x = qt + (size_t)b * ldqt;
   double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 256) s += add ? x[i] + add[i] : x[i];
-  s = block_sum256(s, sh);
+  for (int i = threadIdx.x; i < n; i += 1024) s += add ? x[i] + add[i] : x[i];
+  s = block_sum1024(s, sh[0]);
   const double mu = s / (*s_dev);
   double* qo = q + (size_t)b * ldq;
-  for (int i = threadIdx.x; i < n; i += 256) qo[i] = (add ? x[i] + add[i] : x[i]) - mu * u[i];
-  if (Qe) {
-    __syncthreads();
-    for (int a = 0; a < n_e; ++a) {
-      double t = 0.0;
-      for (int i = threadIdx.x; i < n; i += 256)
-        if (eid[i] == a) t += qo[i];
-      t = block_sum256(t, sh);
-      if (threadIdx.x == 0) Qe[(size_t)b * n_e + a] = t;
+  for (int a0 = 0; a0 < (Qe ? n_e : 1); a0 += 4) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int i = threadIdx.x; i < n; i += 1024) {
+      double v;
+      if (a0 == 0) {
+        v = (add ? x[i] + add[i] : x[i]) - mu * u[i];
+        qo[i] = v;
+      } else {
+        v = qo[i];                 // written by this thread in the first pass
+      }
+      if (Qe) {
+        const int e = eid[i] - a0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          if (e == k) t[k] += v;
+      }
     }
+    if (!Qe) break;
+    block_sum1024x4(t, sh);
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (threadIdx.x == k && a0 + k < n_e) Qe[(size_t)b * n_e + a0 + k] = t[k];
   }
 }
 
 void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldqt, const double* add,
                      const double* u, const double* s_dev, const int* eid, int n_e, double* q,
                      int ldq, double* Qe) {
-  hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(256), 0, st, n, qt, ldqt, add, u, s_dev, eid,
+  hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(1024), 0, st, n, qt, ldqt, add, u, s_dev, eid,
                      n_e, q, ldq, Qe);
 }
 
