@@ -983,24 +983,43 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   HIP_TRY(c, hipMemcpyAsync(b.L, b.A, (size_t)npad * npad * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIP_TRY(c, hipMemsetAsync(b.flag, 0, sizeof(int), st));
   HIP_TRY(c, hipMemsetAsync(b.u, 0, npad * sizeof(double), st));
-  // blocked right-looking Cholesky on the lower triangle of L
-  for (int kb = 0; kb < nb; ++kb) {
-    const int k0 = kb * TILE, rest = npad - k0 - TILE;
-    double* diag = b.L + (size_t)k0 * npad + k0;
-    { Timed t(c, "potrf_diag", st);
-      launch_potrf_diag(st, diag, npad, b.Dinv + (size_t)kb * TILE * TILE, b.flag, k0); }
+  // Blocked right-looking Cholesky on the lower triangle of L, two levels:
+  // 64-wide panels inside blocks of OB columns, so that the large trailing
+  // updates are rank-OB products (four times fewer passes over the trailing
+  // matrix than rank-64 ones).
+  constexpr int OB = 4 * TILE;
+  for (int K0 = 0; K0 < npad; K0 += OB) {
+    const int kend = std::min(npad, K0 + OB);
+    for (int k0 = K0; k0 < kend; k0 += TILE) {
+      const int kb = k0 / TILE, rest = npad - k0 - TILE;
+      double* diag = b.L + (size_t)k0 * npad + k0;
+      { Timed t(c, "potrf_diag", st);
+        launch_potrf_diag(st, diag, npad, b.Dinv + (size_t)kb * TILE * TILE, b.flag, k0); }
+      if (rest > 0) {
+        Timed t(c, "chol_update", st);
+        double* panel = b.L + (size_t)(k0 + TILE) * npad + k0;
+        // L21 = A21 L11^-T for every row below the panel
+        launch_gemm_f64(st, false, true, rest, TILE, TILE, 1.0, panel, npad,
+                        b.Dinv + (size_t)kb * TILE * TILE, TILE, 0.0, panel, npad, 0, 0);
+        // A22 -= L21 L21^T on the block's own remaining columns (lower tiles)
+        const int pw = kend - (k0 + TILE);
+        if (pw > 0) {
+          double* trail = b.L + (size_t)(k0 + TILE) * npad + (k0 + TILE);
+          launch_gemm_f64(st, false, true, rest, pw, TILE, -1.0, panel, npad, panel, npad, 1.0,
+                          trail, npad, 1, 0);
+        }
+      }
+      TRY(launched(c, "cholesky"));
+    }
+    // the columns right of the block: A22 -= L21 L21^T with the block's OB columns
+    const int rest = npad - kend;
     if (rest > 0) {
       Timed t(c, "chol_update", st);
-      double* panel = b.L + (size_t)(k0 + TILE) * npad + k0;
-      // L21 = A21 L11^-T
-      launch_gemm_f64(st, false, true, rest, TILE, TILE, 1.0, panel, npad,
-                      b.Dinv + (size_t)kb * TILE * TILE, TILE, 0.0, panel, npad, 0, 0);
-      // A22 -= L21 L21^T (lower tiles)
-      double* trail = b.L + (size_t)(k0 + TILE) * npad + (k0 + TILE);
-      launch_gemm_f64(st, false, true, rest, rest, TILE, -1.0, panel, npad, panel, npad, 1.0, trail,
-                      npad, 1, 0);
+      const double* P = b.L + (size_t)kend * npad + K0;
+      launch_gemm_f64(st, false, true, rest, rest, kend - K0, -1.0, P, npad, P, npad, 1.0,
+                      b.L + (size_t)kend * npad + kend, npad, 1, 0);
+      TRY(launched(c, "cholesky"));
     }
-    TRY(launched(c, "cholesky"));
   }
   if (!async) {
     int flag = 0;
@@ -1012,23 +1031,37 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
       return fail(c, CPM_ENOTPD, "elastance matrix not positive definite at pivot %d", c->pivot);
     }
   }
-  // X = L^-1 by blocked forward substitution (X stored in Ainv's buffer first)
+  // X = L^-1 by blocked forward substitution (X stored in Ainv's buffer
+  // first), grouped like the factorisation: row blocks of 64 inside blocks
+  // of OB rows, the rows below a block updated by one rank-OB product
   double* X = b.Ainv;
   launch_set_identity(st, npad, X);
-  for (int kb = 0; kb < nb; ++kb) {
-    const int k0 = kb * TILE, cols = k0 + TILE, rest = npad - k0 - TILE;
-    double* Xk = X + (size_t)k0 * npad;
-    Timed t(c, "trtri", st);
-    // X_k = L_kk^-1 X_k on the columns that can be non-zero
-    launch_gemm_f64(st, false, false, TILE, cols, TILE, 1.0, b.Dinv + (size_t)kb * TILE * TILE,
-                    TILE, Xk, npad, 0.0, Xk, npad, 0, 0);
-    if (rest > 0) {
-      // X_below -= L_below,k X_k
-      launch_gemm_f64(st, false, false, rest, cols, TILE, -1.0,
-                      b.L + (size_t)(k0 + TILE) * npad + k0, npad, Xk, npad, 1.0,
-                      X + (size_t)(k0 + TILE) * npad, npad, 0, 0);
+  for (int K0 = 0; K0 < npad; K0 += OB) {
+    const int kend = std::min(npad, K0 + OB);
+    for (int k0 = K0; k0 < kend; k0 += TILE) {
+      const int kb = k0 / TILE, cols = k0 + TILE, rin = kend - k0 - TILE;
+      double* Xk = X + (size_t)k0 * npad;
+      Timed t(c, "trtri", st);
+      // X_k = L_kk^-1 X_k on the columns that can be non-zero
+      launch_gemm_f64(st, false, false, TILE, cols, TILE, 1.0, b.Dinv + (size_t)kb * TILE * TILE,
+                      TILE, Xk, npad, 0.0, Xk, npad, 0, 0);
+      if (rin > 0) {
+        // the block's rows below: X_i -= L_ik X_k
+        launch_gemm_f64(st, false, false, rin, cols, TILE, -1.0,
+                        b.L + (size_t)(k0 + TILE) * npad + k0, npad, Xk, npad, 1.0,
+                        X + (size_t)(k0 + TILE) * npad, npad, 0, 0);
+      }
+      TRY(launched(c, "trtri"));
     }
-    TRY(launched(c, "trtri"));
+    const int rest = npad - kend;
+    if (rest > 0) {
+      // every row below the block: X_below -= L_below,block X_block (columns < kend)
+      Timed t(c, "trtri", st);
+      launch_gemm_f64(st, false, false, rest, kend, kend - K0, -1.0,
+                      b.L + (size_t)kend * npad + K0, npad, X + (size_t)K0 * npad, npad, 1.0,
+                      X + (size_t)kend * npad, npad, 0, 0);
+      TRY(launched(c, "trtri"));
+    }
   }
   // A^-1 = X^T X (lower tiles, k from max(row, col)), result into L's buffer,
   // then swap names so Ainv holds A^-1
@@ -1038,14 +1071,17 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   TRY(launched(c, "lauum"));
   std::swap(b.L, b.Ainv);
   // u = A^-1 e, s = e^T u, S = A^-1 - u u^T / s (Eq. 4)
-  launch_row_sums(st, n, npad, b.Ainv, b.u);
-  launch_sum_vector(st, n, b.u, b.scal);
-  launch_make_S(st, n, npad, b.Ainv, b.u, b.scal, b.S);
+  { Timed t(c, "make_S", st);
+    launch_row_sums(st, n, npad, b.Ainv, b.u);
+    launch_sum_vector(st, n, b.u, b.scal);
+    launch_make_S(st, n, npad, b.Ainv, b.u, b.scal, b.S); }
   TRY(launched(c, "projection"));
-  if (store_flags & (CPM_STORE_F32 | CPM_STORE_BF16X2))
+  if (store_flags & (CPM_STORE_F32 | CPM_STORE_BF16X2)) {
+    Timed t(c, "convert_S", st);
     launch_convert_S(st, npad, b.S, (store_flags & CPM_STORE_F32) ? b.S32 : nullptr,
                      (store_flags & CPM_STORE_BF16X2) ? b.Shi : nullptr,
                      (store_flags & CPM_STORE_BF16X2) ? b.Slo : nullptr);
+  }
   TRY(launched(c, "convert"));
   c->store = store_flags | CPM_STORE_F64;
   c->have_q = false;                     // charge targets refer to the previous inverse
