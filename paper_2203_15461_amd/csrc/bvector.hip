@@ -915,29 +915,136 @@ __device__ inline double pair_g(const double* __restrict__ T, double r2, double 
   return g0 + t * (d0 + t * (0.5 * e0 + t * (c3 + t * (c4 + t * c5))));
 }
 
+// Order of the electrolyte charges for the real-space pass: a stable
+// counting sort of configuration 0 by z (nbins equal bins of [0, Lz)), so
+// that the 64-charge blocks of the gathered arrays are thin in z and most of
+// them lie outside a given electrode plane's window.  One wave: bin counts by
+// LDS atomics, an exclusive scan, then the charges in index order, each 64
+// ranked among equal bins by ballots over the bin bits.  perm[pos] = j in
+// ascending (bin, j); the order only affects which blocks a wave may skip and
+// the (fixed) order of each atom's real-space sum.
+__global__ void __launch_bounds__(64) k_zsort(int m, const double* __restrict__ xyz, double Lz,
+                                              int nbins, int nbits, int* __restrict__ perm) {
+  extern __shared__ int s_zs[];                        // [nbins] counts, then bases
+  int* cnt = s_zs;
+  const int lane = threadIdx.x;
+  const double scale = nbins / Lz;
+  auto bin = [&](int j) {
+    const double z = xyz[3 * (size_t)j + 2];
+    const double zw = z - Lz * floor(z / Lz);
+    return min(nbins - 1, max(0, (int)(zw * scale)));
+  };
+  for (int k = lane; k < nbins; k += 64) cnt[k] = 0;
+  wave_lds_sync();
+  for (int j0 = 0; j0 < m; j0 += 64)
+    if (j0 + lane < m) atomicAdd(&cnt[bin(j0 + lane)], 1);
+  wave_lds_sync();
+  int running = 0;                                     // exclusive scan in place
+  for (int k0 = 0; k0 < nbins; k0 += 64) {
+    const int k = k0 + lane;
+    const int c = k < nbins ? cnt[k] : 0;
+    int incl = c;
+    for (int o = 1; o < 64; o <<= 1) {
+      const int t = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += t;
+    }
+    if (k < nbins) cnt[k] = running + incl - c;
+    running += __shfl(incl, 63, 64);
+  }
+  wave_lds_sync();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  for (int j0 = 0; j0 < m; j0 += 64) {
+    const int j = j0 + lane;
+    const int key = j < m ? bin(j) : nbins;            // nbins: no charge
+    unsigned long long same = ~0ull;
+    for (int t = 0; t < nbits; ++t) {
+      const bool bit = (key >> t) & 1;
+      const unsigned long long bal = __ballot(bit);
+      same &= bit ? bal : ~bal;
+    }
+    const int rank = __popcll(same & below);
+    int pos = 0;
+    if (key < nbins) pos = cnt[key] + rank;
+    wave_lds_sync();
+    if (key < nbins) {
+      if (pos < m) perm[pos] = j;
+      if (rank == 0) cnt[key] += __popcll(same);
+    }
+    wave_lds_sync();
+  }
+}
+
+void launch_zsort(hipStream_t st, int m, const double* xyz, double Lz, int nbins, int* perm) {
+  int nbits = 1;
+  while ((1 << nbits) <= nbins) ++nbits;
+  hipLaunchKernelGGL(k_zsort, dim3(1), dim3(64), (size_t)nbins * sizeof(int), st, m, xyz, Lz,
+                     nbins, nbits, perm);
+}
+
+// The charges of a launch group in the order perm (identity when null) as
+// (x wrapped, y wrapped, z, q), rows of mpad64 entries per configuration,
+// and the z range of each block of 64: zr[s * (mpad64 / 64) + blk].
+__global__ void __launch_bounds__(64) k_gather_charges(int m, int mpad64,
+                                                       const int* __restrict__ perm,
+                                                       const double* __restrict__ xyz,
+                                                       const double* __restrict__ q, double Lx,
+                                                       double Ly, double4* __restrict__ cq,
+                                                       double2* __restrict__ zr) {
+  const int blk = blockIdx.x, s = blockIdx.y, lane = threadIdx.x;
+  const int j = blk * 64 + lane;
+  const double invLx = 1.0 / Lx, invLy = 1.0 / Ly;
+  double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+  double zlo = 1e300, zhi = -1e300;
+  if (j < m) {
+    int src = perm ? perm[j] : j;
+    if (src < 0 || src >= m) src = j;
+    const double* r = xyz + ((size_t)s * m + src) * 3;
+    const double x = r[0], y = r[1], z = r[2];
+    v = make_double4(x - Lx * floor(x * invLx), y - Ly * floor(y * invLy), z, q[src]);
+    zlo = zhi = z;
+  }
+  cq[(size_t)s * mpad64 + j] = v;
+  for (int o = 32; o > 0; o >>= 1) {
+    zlo = fmin(zlo, __shfl_xor(zlo, o, 64));
+    zhi = fmax(zhi, __shfl_xor(zhi, o, 64));
+  }
+  if (lane == 0) zr[(size_t)s * (mpad64 / 64) + blk] = make_double2(zlo, zhi);
+}
+
+void launch_gather_charges(hipStream_t st, int g, int m, int mpad64, const int* perm,
+                           const double* xyz, const double* q, double Lx, double Ly, double4* cq,
+                           double2* zr) {
+  hipLaunchKernelGGL(k_gather_charges, dim3(mpad64 / 64, g), dim3(64), 0, st, m, mpad64, perm, xyz,
+                     q, Lx, Ly, cq, zr);
+}
+
 // Real-space part of phi_i over one chunk of the electrolyte, for the
 // configurations s = blockIdx.z, blockIdx.z + gridDim.z, ... < g of a group
-// (positions and charges of configuration s xyz_stride and q_stride elements
-// apart; output rows part[(s * rchunks + chunk) * n + i]).  Threads map to electrode atoms
-// through amap, which puts the atoms of one z plane, in compact in-plane
-// tiles, into whole waves (-1 pads).  Every wave walks the chunk 64 charges
-// at a time on its own: it keeps the charges that can come within rc of its
-// atoms -- a z window, and when every cell length is >= 2 rc (one image) an
-// x and y window around the wave's atoms -- by order-preserving ballot
-// compaction into a wave-private LDS area.  In the one-image case each lane
-// then marks its possible partners in a 64-bit mask (an FP32 distance screen
-// with a margin) and evaluates g(r) only for those within rc in FP64, in
-// ascending order (the same pairs and order as a plain loop); otherwise
-// it sums over all in-range images.  g(r) comes from the LDS pair table,
-// staged once per workgroup of RS_WAVES waves.  The charges of the next
-// three steps are loaded while the current ones are summed.
+// (gathered charges cq and block z ranges zr of configuration s, rows mpad64
+// and mpad64 / 64 apart; output rows part[(s * rchunks + chunk) * n + i]).
+// Chunk c takes the 64-charge blocks c, c + rchunks, c + 2 rchunks, ... (so
+// every chunk spans the whole z range of the ordered charges and the
+// workgroups share the work evenly).  Threads map to electrode
+// atoms through amap, which puts the atoms of one z plane, in compact
+// in-plane tiles, into whole waves (-1 pads).  Every wave walks the chunk 64
+// charges at a time on its own: a block whose z range misses the wave's z
+// window is skipped without being loaded; otherwise the wave keeps the
+// charges that can come within rc of its atoms -- the z window, and when
+// every cell length is >= 2 rc (one image) an x and y window around the
+// wave's atoms -- by order-preserving ballot compaction into a wave-private
+// LDS area.  In the one-image case each lane then marks its possible
+// partners in a 64-bit mask (an FP32 distance screen with a margin) and
+// evaluates g(r) only for those within rc in FP64, in ascending order (the
+// same pairs and order as a plain loop); otherwise it sums over all in-range
+// images.  g(r) comes from the LDS pair table, staged once per workgroup of
+// RS_WAVES waves.  The charges of the next three loaded blocks are in flight
+// while the current one is summed.
 constexpr int RS_WAVES = 8;
 
 __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
-    int g, int n, int m, int chunk_size, size_t xyz_stride, size_t q_stride,
-    const int* __restrict__ amap, int nmap, const double* __restrict__ ex,
-    const double* __restrict__ ey, const double* __restrict__ ez,
-    const double* __restrict__ xyz, const double* __restrict__ q, double Lx, double Ly,
+    int g, int n, int m, int mpad64, const int* __restrict__ amap, int nmap,
+    const double* __restrict__ ex, const double* __restrict__ ey, const double* __restrict__ ez,
+    const double4* __restrict__ cq, const double2* __restrict__ zr, double Lx, double Ly,
     double Lz, double rc, const double* __restrict__ ptab, double* __restrict__ part) {
   __shared__ double s_tab[3 * (RS_NT + 1)];
   __shared__ double s_c[RS_WAVES][4][64];              // per wave: x, y, z, q of kept charges
@@ -946,7 +1053,7 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
   const int slot = blockIdx.x * blockDim.x + threadIdx.x;
   const int atom = slot < nmap ? amap[slot] : -1;
   const int chunk = blockIdx.y, rchunks = gridDim.y;
-  const int j0 = chunk * chunk_size, j1 = min(m, j0 + chunk_size);
+  const int nb64 = mpad64 / 64, nbt = (m + 63) / 64;   // blocks in a row, blocks holding charges
   const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, invLz = 1.0 / Lz, rc2 = rc * rc;
   const double h = rc / RS_NT, inv_h = RS_NT / rc;
   // only the nearest image can lie within rc when every cell length is >= 2 rc
@@ -982,105 +1089,118 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
   const float Lxf = (float)Lx, Lyf = (float)Ly, Lzf = (float)Lz;
   const float iLxf = 1.0f / Lxf, iLyf = 1.0f / Lyf, iLzf = 1.0f / Lzf;
   const float rc2f = (float)(rc2 * (1.0 + 1e-4));
-  const int nblk = j1 > j0 ? (j1 - j0 + 63) / 64 : 0;
+  const int nblk = chunk < nbt ? (nbt - chunk + rchunks - 1) / rchunks : 0;
   const int s0 = blockIdx.z, sstep = gridDim.z;
   const int nloc = s0 < g ? (g - s0 + sstep - 1) / sstep : 0;   // this workgroup's configurations
   const int steps = nloc * nblk;
-  // charges of the next three steps are in flight while a step is summed
-  double4 f0 = make_double4(0, 0, 0, 0), f1 = f0, f2 = f0;
-  auto fetch = [&](int step) {
+  // a block can hold a charge of the window when its z range, moved into
+  // [wlo, wlo + Lz), starts below whi or wraps past wlo + Lz (a margin of
+  // 1e-9 A keeps the test conservative under rounding); wave-uniform
+  auto hit = [&](int step) {
+    if (step >= steps) return false;
+    if (keep_all_z) return true;
+    const int snap = s0 + sstep * (step / nblk), gb = chunk + rchunks * (step % nblk);
+    const double2 r = zr[(size_t)snap * nb64 + gb];
+    const double a = r.x - Lz * floor((r.x - wlo) * invLz), w = r.y - r.x;
+    return a < whi + 1e-9 || a + w >= wlo + Lz - 1e-9;
+  };
+  auto fetch = [&](int step, bool h) {
     double4 v = make_double4(0, 0, 0, 0);
-    const int snap = s0 + sstep * (step / nblk), j = j0 + (step % nblk) * 64 + lane;
-    if (step < steps && j < j1) {
-      const double* r = xyz + snap * xyz_stride + (size_t)j * 3;
-      v = make_double4(r[0], r[1], r[2], q[snap * q_stride + j]);
+    if (h) {                                           // h: step < steps, so nblk > 0
+      const int snap = s0 + sstep * (step / nblk);
+      const int j = (chunk + rchunks * (step % nblk)) * 64 + lane;
+      if (j < m) v = cq[(size_t)snap * mpad64 + j];
     }
     return v;
   };
-  f0 = fetch(0);
-  f1 = fetch(1);
-  f2 = fetch(2);
+  bool h0 = hit(0), h1 = hit(1), h2 = hit(2);
+  double4 f0 = fetch(0, h0), f1 = fetch(1, h1), f2 = fetch(2, h2);
   double acc = 0.0;
   for (int step = 0; step < steps; ++step) {
     const int snap = s0 + sstep * (step / nblk), blk = step % nblk;
-    const bool valid = j0 + blk * 64 + lane < j1;
-    const double x = f0.x, y = f0.y, z = f0.z, qq = f0.w;
+    const bool hcur = h0;
+    const double xw0 = f0.x, yw0 = f0.y, z = f0.z, qq = f0.w;
     f0 = f1;
     f1 = f2;
-    f2 = fetch(step + 3);
-    const double xw0 = x - Lx * floor(x * invLx), yw0 = y - Ly * floor(y * invLy);
-    bool keep = valid && (keep_all_z || (z - Lz * floor((z - wlo) * invLz)) < whi);
-    if (!keep_all_x) {
-      double d = xw0 - (xlo - rc);
-      d -= Lx * floor(d * invLx);
-      keep = keep && d < xw;
-    }
-    if (!keep_all_y) {
-      double d = yw0 - (ylo - rc);
-      d -= Ly * floor(d * invLy);
-      keep = keep && d < yw;
-    }
-    const unsigned long long bal = __ballot(keep);
-    const int kept = __popcll(bal);
-    if (keep) {
-      const int pos = __popcll(bal & ((1ull << lane) - 1ull));
-      C[0][pos] = xw0;
-      C[1][pos] = yw0;
-      C[2][pos] = z;
-      C[3][pos] = qq;
-      Cf[0][pos] = (float)xw0;
-      Cf[1][pos] = (float)yw0;
-      Cf[2][pos] = (float)z;
-    }
-    wave_lds_sync();
-    if (atom >= 0) {
-      if (single) {
-        // partners within rc (FP32 screen), then the exact test and g(r)
-        // for those only, in ascending t
-        unsigned long long mask = 0ull;
-        for (int t = 0; t < kept; ++t) {
-          float dz = zif - Cf[2][t], dx = xif - Cf[0][t], dy = yif - Cf[1][t];
-          dz -= Lzf * rintf(dz * iLzf);
-          dx -= Lxf * rintf(dx * iLxf);
-          dy -= Lyf * rintf(dy * iLyf);
-          if (dx * dx + dy * dy + dz * dz < rc2f) mask |= 1ull << t;
-        }
-        while (mask) {
-          const int t = __ffsll((long long)mask) - 1;
-          mask &= mask - 1ull;
-          double dz = zi - C[2][t], dx = xi - C[0][t], dy = yi - C[1][t];
-          dz -= Lz * rint(dz * invLz);
-          dx -= Lx * rint(dx * invLx);
-          dy -= Ly * rint(dy * invLy);
-          const double r2 = dx * dx + dy * dy + dz * dz;
-          if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
-        }
-      } else {
-        for (int t = 0; t < kept; ++t) {
-          double dz = zi - C[2][t];
-          dz -= Lz * rint(dz * invLz);
-          if (fabs(dz) >= rc) continue;          // dz is the nearest image
-          double dx = xi - C[0][t], dy = yi - C[1][t];
-          dx -= Lx * rint(dx * invLx);
-          dy -= Ly * rint(dy * invLy);
-          const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
-          const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
-          const int clo = (int)ceil((-rc - dz) * invLz) - 1, chi = (int)floor((rc - dz) * invLz) + 1;
-          for (int cc = clo; cc <= chi; ++cc) {
-            const double Z = dz + cc * Lz;
-            for (int a = alo; a <= ahi; ++a) {
-              const double X = dx + a * Lx;
-              for (int bb = blo; bb <= bhi; ++bb) {
-                const double Y = dy + bb * Ly;
-                const double r2 = X * X + Y * Y + Z * Z;
-                if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
+    h0 = h1;
+    h1 = h2;
+    h2 = hit(step + 3);
+    f2 = fetch(step + 3, h2);
+    if (hcur) {
+      const bool valid = (chunk + rchunks * blk) * 64 + lane < m;
+      bool keep = valid && (keep_all_z || (z - Lz * floor((z - wlo) * invLz)) < whi);
+      if (!keep_all_x) {
+        double d = xw0 - (xlo - rc);
+        d -= Lx * floor(d * invLx);
+        keep = keep && d < xw;
+      }
+      if (!keep_all_y) {
+        double d = yw0 - (ylo - rc);
+        d -= Ly * floor(d * invLy);
+        keep = keep && d < yw;
+      }
+      const unsigned long long bal = __ballot(keep);
+      const int kept = __popcll(bal);
+      if (keep) {
+        const int pos = __popcll(bal & ((1ull << lane) - 1ull));
+        C[0][pos] = xw0;
+        C[1][pos] = yw0;
+        C[2][pos] = z;
+        C[3][pos] = qq;
+        Cf[0][pos] = (float)xw0;
+        Cf[1][pos] = (float)yw0;
+        Cf[2][pos] = (float)z;
+      }
+      wave_lds_sync();
+      if (atom >= 0) {
+        if (single) {
+          // partners within rc (FP32 screen), then the exact test and g(r)
+          // for those only, in ascending t
+          unsigned long long mask = 0ull;
+          for (int t = 0; t < kept; ++t) {
+            float dz = zif - Cf[2][t], dx = xif - Cf[0][t], dy = yif - Cf[1][t];
+            dz -= Lzf * rintf(dz * iLzf);
+            dx -= Lxf * rintf(dx * iLxf);
+            dy -= Lyf * rintf(dy * iLyf);
+            if (dx * dx + dy * dy + dz * dz < rc2f) mask |= 1ull << t;
+          }
+          while (mask) {
+            const int t = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            double dz = zi - C[2][t], dx = xi - C[0][t], dy = yi - C[1][t];
+            dz -= Lz * rint(dz * invLz);
+            dx -= Lx * rint(dx * invLx);
+            dy -= Ly * rint(dy * invLy);
+            const double r2 = dx * dx + dy * dy + dz * dz;
+            if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
+          }
+        } else {
+          for (int t = 0; t < kept; ++t) {
+            double dz = zi - C[2][t];
+            dz -= Lz * rint(dz * invLz);
+            if (fabs(dz) >= rc) continue;          // dz is the nearest image
+            double dx = xi - C[0][t], dy = yi - C[1][t];
+            dx -= Lx * rint(dx * invLx);
+            dy -= Ly * rint(dy * invLy);
+            const int alo = (int)ceil((-rc - dx) * invLx) - 1, ahi = (int)floor((rc - dx) * invLx) + 1;
+            const int blo = (int)ceil((-rc - dy) * invLy) - 1, bhi = (int)floor((rc - dy) * invLy) + 1;
+            const int clo = (int)ceil((-rc - dz) * invLz) - 1, chi = (int)floor((rc - dz) * invLz) + 1;
+            for (int cc = clo; cc <= chi; ++cc) {
+              const double Z = dz + cc * Lz;
+              for (int a = alo; a <= ahi; ++a) {
+                const double X = dx + a * Lx;
+                for (int bb = blo; bb <= bhi; ++bb) {
+                  const double Y = dy + bb * Ly;
+                  const double r2 = X * X + Y * Y + Z * Z;
+                  if (r2 < rc2) acc += C[3][t] * pair_g(s_tab, r2, inv_h, h);
+                }
               }
             }
           }
         }
       }
+      wave_lds_sync();
     }
-    wave_lds_sync();
     if (blk == nblk - 1) {
       if (atom >= 0) part[((size_t)snap * rchunks + chunk) * n + atom] = acc;
       acc = 0.0;
@@ -1090,25 +1210,16 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
     for (int snap = s0; snap < g; snap += sstep) part[((size_t)snap * rchunks + chunk) * n + atom] = 0.0;
 }
 
-void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
-                         int nmap, const double* xyz, const double* q, double Lx, double Ly,
-                         double Lz, double rc, double* part) {
-  launch_real_space_pairs(st, g, n, m, rchunks, b, nmap, xyz, (size_t)m * 3, q, 0, Lx, Ly, Lz, rc,
-                          b.rtab, part);
-}
-
-void launch_real_space_pairs(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
-                             int nmap, const double* xyz, size_t xyz_stride, const double* q,
-                             size_t q_stride, double Lx, double Ly, double Lz, double rc,
-                             const double* table, double* part) {
-  const int chunk_size = (m + rchunks - 1) / rchunks;
+void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
+                         const Buffers& b, int nmap, const double4* cq, const double2* zr,
+                         double Lx, double Ly, double Lz, double rc, double* part) {
   // configurations spread over the third grid dimension: about two rounds of
   // 256 workgroups in all
   const int ablk = (nmap + 64 * RS_WAVES - 1) / (64 * RS_WAVES);
   const int gz = std::max(1, std::min(g, (512 + ablk * rchunks - 1) / (ablk * rchunks)));
   dim3 grid(ablk, rchunks, gz), block(64 * RS_WAVES);
-  hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, chunk_size, xyz_stride, q_stride,
-                     b.amap, nmap, b.ex, b.ey, b.ez, xyz, q, Lx, Ly, Lz, rc, table, part);
+  hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, mpad64, b.amap, nmap,
+                     b.ex, b.ey, b.ez, cq, zr, Lx, Ly, Lz, rc, b.rtab, part);
 }
 
 // b_i = -k_e (sum of k-space partials + sum of real-space partials

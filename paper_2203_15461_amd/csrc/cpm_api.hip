@@ -337,6 +337,10 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   c->dip_blocks = std::max(1, (c->m + 255) / 256);
   TRY(dalloc(c, &b.dip, (size_t)c->pv_group * c->dip_blocks * 3));
   TRY(dalloc(c, &b.rtab, (size_t)3 * (RS_NT + 1)));
+  const size_t mpad64 = (size_t)std::max(64, (c->m + 63) / 64 * 64);
+  TRY(dalloc(c, &b.zperm, mpad64));
+  TRY(dalloc(c, &b.cq, (size_t)c->pv_group * mpad64));
+  TRY(dalloc(c, &b.zr, (size_t)c->pv_group * (mpad64 / 64)));
   launch_pair_table(c->stream, c->p.alpha, c->p.eta, c->p.rcut, b.rtab);
   TRY(launched(c, "pair table"));
   return CPM_OK;
@@ -486,6 +490,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_SFM_WG_TARGET")) c->sfm_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_MIN_CHUNK")) c->sfm_min_chunk = std::max(16, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
@@ -900,9 +905,14 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     int row0 = 0;
     for (int L = 0; L < c->nlayers; ++L) {
       const int rows = c->h_plane_rows[L];              // this plane's rows of the map (x 64)
+      // only the lower triangle of A is kept (mirrored at the end): the
+      // plane's rows need the columns up to their largest atom index
+      int amax = 0;
+      for (int r = row0; r < row0 + rows; ++r) amax = std::max(amax, c->h_amap[r]);
+      const int ncols = std::min(npad, (amax + 64) / 64 * 64);
       launch_build_F(c->stream, L, n, npad, c->nlayers, c->ncolsort, ldG, b.sc_nx, b.sc_ny, b,
                      b.Qpair, b.asmF);
-      launch_gemm_f64(c->stream, false, false, rows, npad, ldG, c->ke, b.asmG + (size_t)row0 * ldG,
+      launch_gemm_f64(c->stream, false, false, rows, ncols, ldG, c->ke, b.asmG + (size_t)row0 * ldG,
                       ldG, b.asmF, npad, 1.0, b.A, npad, 0, 0, b.amap + row0);
       TRY(launched(c, "kspace planes"));
       row0 += rows;
@@ -1173,6 +1183,17 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   const bool mfma = c->sf_mfma && c->use_sf_mfma;
   const bool fast = mfma && c->nlayers > 0;
   const int G = fast ? c->pv_group : 1;
+  const int mpad64 = std::max(64, (m + 63) / 64 * 64);
+  // large batches: the charges ordered by z (from the first configuration)
+  // for the real-space pass, so that whole blocks fall outside the planes'
+  // windows
+  const int* perm = nullptr;
+  if (m > 0 && batch >= c->rs_sort_min) {
+    const int nbins = std::max(1, std::min(4096, (int)std::ceil(c->Lz / 0.25)));
+    Timed t(c, "zsort");
+    launch_zsort(st, m, d_xyz, c->Lz, nbins, b.zperm);
+    perm = b.zperm;
+  }
   for (int s0 = 0; s0 < batch; s0 += G) {
     const int g = std::min(G, batch - s0);
     const double* xyz = d_xyz ? d_xyz + (size_t)s0 * m * 3 : nullptr;
@@ -1201,7 +1222,8 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
         launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
     }
     { Timed t(c, "real_space_b");
-      launch_b_real_space(st, g, n, m, rch, b, c->nmap, xyz, b.elq, p.Lx, p.Ly, c->Lz,
+      launch_gather_charges(st, g, m, mpad64, perm, xyz, b.elq, p.Lx, p.Ly, b.cq, b.zr);
+      launch_b_real_space(st, g, n, m, mpad64, rch, b, c->nmap, b.cq, b.zr, p.Lx, p.Ly, c->Lz,
                           p.rcut, b.phir_part); }
     if (fast) {
       { Timed t(c, "sf_reduce");
@@ -1841,6 +1863,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.dip); dfree(b.qt);
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
+  dfree(b.zperm); dfree(b.cq); dfree(b.zr);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
   dfree(b.Qpair); dfree(b.ell_col); dfree(b.ell_val); dfree(b.plane_off); dfree(b.dextra);
   dfree(b.bsr_col); dfree(b.bsr_val); dfree(b.cg_items); dfree(b.asmG); dfree(b.asmF);

@@ -100,6 +100,9 @@ struct Buffers {
   double* phir_part = nullptr;     // m-chunk partial real-space potentials (n * rchunks)
   double* dip = nullptr;           // electrolyte dipole partials (per 256 charges, 3 axes)
   double* rtab = nullptr;          // real-space pair table (g, g', g'') x (RS_NT + 1)
+  int* zperm = nullptr;            // order of the charges for the real-space pass (m)
+  double4* cq = nullptr;           // gathered charges (x, y wrapped, z, q), pv_group x mpad64
+  double2* zr = nullptr;           // z range of each 64-charge block, pv_group x mpad64 / 64
   double* qt = nullptr;            // q-tilde (batch x npad)
   double* res = nullptr;           // refinement residual / corrections (batch x npad)
   double* bpad = nullptr;          // padded b for batched solves (bpad_rows x npad)
@@ -210,6 +213,7 @@ struct cpm_ctx {
   int sfm_wg_target = 4096;        // the same for the matrix-core kernel
   int sfm_min_chunk = 512;         // fewest charges per matrix-core chunk
   int rs_wg_target = 512;          // real-space workgroups per launch group
+  int rs_sort_min = 16;            // batches of at least this size sort the charges by z
   unsigned store = 0;
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;
@@ -355,10 +359,11 @@ void launch_b_elyt_dipole(hipStream_t st, int g, int m, const double* xyz, const
                           double* dip);
 void launch_dipole_partials(hipStream_t st, int g, int m, const double* xyz, size_t xyz_stride,
                             const double* q, size_t q_stride, double* dip);
-void launch_real_space_pairs(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
-                             int nmap, const double* xyz, size_t xyz_stride, const double* q,
-                             size_t q_stride, double Lx, double Ly, double Lz, double rc,
-                             const double* table, double* part);
+// the charges of configuration 0 ordered by z for the real-space pass
+void launch_zsort(hipStream_t st, int m, const double* xyz, double Lz, int nbins, int* perm);
+void launch_gather_charges(hipStream_t st, int g, int m, int mpad64, const int* perm,
+                           const double* xyz, const double* q, double Lx, double Ly, double4* cq,
+                           double2* zr);
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
@@ -394,9 +399,9 @@ void launch_b_layer_project(hipStream_t st, int n, int ncols, int nlayers, const
                             const double* sfw, double2* T, double* part);
 int layer_project_chunks(int ncols);
 void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab);
-void launch_b_real_space(hipStream_t st, int g, int n, int m, int rchunks, const Buffers& b,
-                         int nmap, const double* xyz, const double* q, double Lx, double Ly,
-                         double Lz, double rc, double* part);
+void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
+                         const Buffers& b, int nmap, const double4* cq, const double2* zr,
+                         double Lx, double Ly, double Lz, double rc, double* part);
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
                       const double* phir, const Buffers& b, const double* dip, int dip_blocks,
                       const double* cdip, double ke, void* out, int out_is_f32);

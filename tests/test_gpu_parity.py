@@ -280,6 +280,22 @@ def test_batched_2880_gemm(cpm, golden):
         assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
 
 
+def test_batched_2880_z_ordered_real_space(cpm, golden):
+    """A batch of 21 (>= 16: the real-space pass orders the charges by z from
+    the batch's first configuration and skips whole blocks outside each
+    plane's window) against the stored oracle b and q, FP64 GEMM solve."""
+    w = I.graphite_capacitor()
+    idx = [1, 2, 0] * 7
+    snaps = [I.snapshot(w, int(golden["snapshots"][i])) for i in idx]
+    say("graphite_capacitor_2880 batch 21, z-ordered real space")
+    g = run(cpm, w, store=1, mode=0x000, xyz_list=snaps)
+    eb, eq = rel(g["b"], golden["b"][idx]), rel(g["q"], golden["q"][idx])
+    say(f"  b err {eb:.3e}  q err {eq:.3e}")
+    assert eb < 1e-10
+    assert eq < 1e-10
+    assert np.all(np.abs(g["q"].sum(1)) <= 1e-12)
+
+
 def test_kernel_timing(cpm):
     w = I.small_capacitor("b")
     say("timing")
