@@ -918,44 +918,70 @@ __device__ inline double pair_g(const double* __restrict__ T, double r2, double 
 // Order of the electrolyte charges for the real-space pass: a stable
 // counting sort of configuration 0 by z (nbins equal bins of [0, Lz)), so
 // that the 64-charge blocks of the gathered arrays are thin in z and most of
-// them lie outside a given electrode plane's window.  One wave: bin counts by
-// LDS atomics, an exclusive scan, then the charges in index order, each 64
-// ranked among equal bins by ballots over the bin bits.  perm[pos] = j in
-// ascending (bin, j); the order only affects which blocks a wave may skip and
-// the (fixed) order of each atom's real-space sum.
-__global__ void __launch_bounds__(64) k_zsort(int m, const double* __restrict__ xyz, double Lz,
-                                              int nbins, int nbits, int* __restrict__ perm) {
-  extern __shared__ int s_zs[];                        // [nbins] counts, then bases
-  int* cnt = s_zs;
-  const int lane = threadIdx.x;
+// them lie outside a given electrode plane's window.  One workgroup of
+// ZS_WAVES waves; wave w owns the w-th contiguous segment of the charges:
+// per-wave bin counts (LDS atomics), then each wave's first position in every
+// bin (bins in order, and within a bin the segments in order), then every
+// wave places its segment 64 charges at a time, ranking equal bins by
+// ballots over the bin bits.  perm[pos] = j in ascending (bin, j); the order
+// only affects which blocks a wave may skip and the (fixed) order of each
+// atom's real-space sum.
+constexpr int ZS_WAVES = 16;
+constexpr int ZS_MAXBINS = 896;       // (ZS_WAVES + 1) x bins ints stay below 64 KB of LDS
+
+__global__ void __launch_bounds__(64 * ZS_WAVES) k_zsort(int m, const double* __restrict__ xyz,
+                                                         double Lz, int nbins, int nbits,
+                                                         int* __restrict__ perm) {
+  extern __shared__ int s_zs[];                        // [ZS_WAVES][nbins] counts; [nbins] totals
+  int* tot = s_zs + ZS_WAVES * nbins;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  int* mine = s_zs + wave * nbins;
   const double scale = nbins / Lz;
   auto bin = [&](int j) {
     const double z = xyz[3 * (size_t)j + 2];
     const double zw = z - Lz * floor(z / Lz);
     return min(nbins - 1, max(0, (int)(zw * scale)));
   };
-  for (int k = lane; k < nbins; k += 64) cnt[k] = 0;
-  wave_lds_sync();
-  for (int j0 = 0; j0 < m; j0 += 64)
-    if (j0 + lane < m) atomicAdd(&cnt[bin(j0 + lane)], 1);
-  wave_lds_sync();
-  int running = 0;                                     // exclusive scan in place
-  for (int k0 = 0; k0 < nbins; k0 += 64) {
-    const int k = k0 + lane;
-    const int c = k < nbins ? cnt[k] : 0;
-    int incl = c;
-    for (int o = 1; o < 64; o <<= 1) {
-      const int t = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += t;
-    }
-    if (k < nbins) cnt[k] = running + incl - c;
-    running += __shfl(incl, 63, 64);
+  const int seg = (m + ZS_WAVES - 1) / ZS_WAVES;
+  const int a = min(m, wave * seg), e = min(m, a + seg);
+  for (int k = tid; k < ZS_WAVES * nbins; k += blockDim.x) s_zs[k] = 0;
+  __syncthreads();
+  for (int j = a + lane; j < e; j += 64) atomicAdd(&mine[bin(j)], 1);
+  __syncthreads();
+  for (int k = tid; k < nbins; k += blockDim.x) {
+    int t = 0;
+    for (int w = 0; w < ZS_WAVES; ++w) t += s_zs[w * nbins + k];
+    tot[k] = t;
   }
-  wave_lds_sync();
+  __syncthreads();
+  if (wave == 0) {                                     // exclusive scan of the bin totals
+    int running = 0;
+    for (int k0 = 0; k0 < nbins; k0 += 64) {
+      const int k = k0 + lane;
+      const int c = k < nbins ? tot[k] : 0;
+      int incl = c;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += t;
+      }
+      if (k < nbins) tot[k] = running + incl - c;
+      running += __shfl(incl, 63, 64);
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < nbins; k += blockDim.x) {      // first position of each wave's run
+    int p = tot[k];
+    for (int w = 0; w < ZS_WAVES; ++w) {
+      const int c = s_zs[w * nbins + k];
+      s_zs[w * nbins + k] = p;
+      p += c;
+    }
+  }
+  __syncthreads();
   const unsigned long long below = (1ull << lane) - 1ull;
-  for (int j0 = 0; j0 < m; j0 += 64) {
+  for (int j0 = a; j0 < e; j0 += 64) {
     const int j = j0 + lane;
-    const int key = j < m ? bin(j) : nbins;            // nbins: no charge
+    const int key = j < e ? bin(j) : nbins;            // nbins: no charge
     unsigned long long same = ~0ull;
     for (int t = 0; t < nbits; ++t) {
       const bool bit = (key >> t) & 1;
@@ -964,21 +990,26 @@ __global__ void __launch_bounds__(64) k_zsort(int m, const double* __restrict__ 
     }
     const int rank = __popcll(same & below);
     int pos = 0;
-    if (key < nbins) pos = cnt[key] + rank;
+    if (key < nbins) pos = mine[key] + rank;
     wave_lds_sync();
     if (key < nbins) {
       if (pos < m) perm[pos] = j;
-      if (rank == 0) cnt[key] += __popcll(same);
+      if (rank == 0) mine[key] += __popcll(same);
     }
     wave_lds_sync();
   }
 }
 
+int zsort_bins(double Lz) {
+  return std::max(1, std::min(ZS_MAXBINS, (int)std::ceil(Lz / 0.25)));
+}
+
 void launch_zsort(hipStream_t st, int m, const double* xyz, double Lz, int nbins, int* perm) {
+  nbins = std::max(1, std::min(ZS_MAXBINS, nbins));
   int nbits = 1;
   while ((1 << nbits) <= nbins) ++nbits;
-  hipLaunchKernelGGL(k_zsort, dim3(1), dim3(64), (size_t)nbins * sizeof(int), st, m, xyz, Lz,
-                     nbins, nbits, perm);
+  hipLaunchKernelGGL(k_zsort, dim3(1), dim3(64 * ZS_WAVES), (size_t)(ZS_WAVES + 1) * nbins * sizeof(int),
+                     st, m, xyz, Lz, nbins, nbits, perm);
 }
 
 // The charges of a launch group in the order perm (identity when null) as

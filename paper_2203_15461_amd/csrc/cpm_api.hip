@@ -1189,9 +1189,8 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   // windows
   const int* perm = nullptr;
   if (m > 0 && batch >= c->rs_sort_min) {
-    const int nbins = std::max(1, std::min(4096, (int)std::ceil(c->Lz / 0.25)));
     Timed t(c, "zsort");
-    launch_zsort(st, m, d_xyz, c->Lz, nbins, b.zperm);
+    launch_zsort(st, m, d_xyz, c->Lz, zsort_bins(c->Lz), b.zperm);
     perm = b.zperm;
   }
   for (int s0 = 0; s0 < batch; s0 += G) {

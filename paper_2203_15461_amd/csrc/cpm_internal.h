@@ -361,6 +361,7 @@ void launch_dipole_partials(hipStream_t st, int g, int m, const double* xyz, siz
                             const double* q, size_t q_stride, double* dip);
 // the charges of configuration 0 ordered by z for the real-space pass
 void launch_zsort(hipStream_t st, int m, const double* xyz, double Lz, int nbins, int* perm);
+int zsort_bins(double Lz);         // z bins of the charge order (about 0.25 A wide)
 void launch_gather_charges(hipStream_t st, int g, int m, int mpad64, const int* perm,
                            const double* xyz, const double* q, double Lx, double Ly, double4* cq,
                            double2* zr);
