@@ -148,7 +148,11 @@ cpm_status cpm_set_electrolyte(cpm_ctx* ctx, int m, const double* h_q);
  * the slab dipole term (Eq. 12).  d_xyz: n x 3 row-major FP64 electrode
  * coordinates; d_electrode_id: n int32 ids in [0, n_e); d_diag_extra: n FP64
  * (V/e) added to the diagonal, or NULL.  Validates ids and coordinates
- * (copying them to the host once).  Synchronous. */
+ * (copying them to the host once) and prepares the electrode data; returns
+ * once the inputs have been read (they may then be freed).  The kernels that
+ * form A itself are enqueued by the first call that needs A: cpm_invert (on
+ * its own stream with CPM_INVERT_ASYNC, so the assembly overlaps b as well),
+ * cpm_copy_matrix(0), cpm_apply_elastance or cpm_solve_cg. */
 cpm_status cpm_build_elastance(cpm_ctx* ctx, int n, const double* d_xyz,
                                const int* d_electrode_id, int n_e,
                                const double* d_diag_extra);

@@ -610,6 +610,66 @@ cpm_status cpm_set_electrolyte(cpm_ctx* c, int m, const double* h_q) {
 
 namespace {
 
+// Enqueue the assembly of the dense elastance A on stream st (Eq. 2 with
+// the Ewald split; lower triangle, then mirrored) for the electrodes of the
+// last cpm_build_elastance.  Reads only context-owned buffers.
+cpm_status assemble_A(cpm_ctx* c, hipStream_t st) {
+  if (!c->A_pending) return CPM_OK;
+  c->A_pending = false;
+  const cpm_params& p = c->p;
+  const int n = c->n, npad = c->npad;
+  Buffers& b = c->b;
+  const double eta_ee = p.eta / std::sqrt(2.0);
+  const double diag_self = (std::sqrt(2.0) * p.eta - 2.0 * p.alpha) / std::sqrt(M_PI);
+  const double background = -M_PI / (c->V * p.alpha * p.alpha);
+  { Timed t(c, "assemble_real", st);
+    launch_real_space_A(st, n, npad, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha, eta_ee,
+                        diag_self, background, c->cdip, c->ke, c->A_diag_extra ? b.dextra : nullptr, b.A); }
+  TRY(launched(c, "real_space_A"));
+  if (c->nlayers > 0 && c->sf_mfma) {
+    // planar electrodes: per plane, A[rows of L] += k_e G_L F^L (K = 2 x columns);
+    // Q, G and F stay allocated for rebuilds of the same context
+    Timed t(c, "assemble_kspace", st);
+    const int ldG = (2 * c->ncolsort + 15) / 16 * 16;
+    TRY(dalloc(c, &b.Qpair, (size_t)c->ncolsort * c->nlayers * c->nlayers));
+    TRY(dalloc(c, &b.asmG, (size_t)c->nmap * ldG));
+    TRY(dalloc(c, &b.asmF, (size_t)ldG * npad));
+    launch_plane_pair_weights(st, c->ncolsort, c->nlayers, b.sc_lo, b.sc_len, b.sc_koff,
+                              b.w2, b.layer_fz, b.Qpair);
+    launch_build_G(st, c->nmap, c->ncolsort, ldG, b.amap, b.sc_nx, b.sc_ny, b, b.asmG);
+    int row0 = 0;
+    for (int L = 0; L < c->nlayers; ++L) {
+      const int rows = c->h_plane_rows[L];              // this plane's rows of the map (x 64)
+      // only the lower triangle of A is kept (mirrored at the end): the
+      // plane's rows need the columns up to their largest atom index
+      int amax = 0;
+      for (int r = row0; r < row0 + rows; ++r) amax = std::max(amax, c->h_amap[r]);
+      const int ncols = std::min(npad, (amax + 64) / 64 * 64);
+      launch_build_F(st, L, n, npad, c->nlayers, c->ncolsort, ldG, b.sc_nx, b.sc_ny, b,
+                     b.Qpair, b.asmF);
+      launch_gemm_f64(st, false, false, rows, ncols, ldG, c->ke, b.asmG + (size_t)row0 * ldG,
+                      ldG, b.asmF, npad, 1.0, b.A, npad, 0, 0, b.amap + row0);
+      TRY(launched(c, "kspace planes"));
+      row0 += rows;
+    }
+  } else {
+    // k space: A += T T^T over chunks of KC k-vectors (2 KC columns)
+    const int KC = 2048;
+    TRY(dalloc(c, &b.table, (size_t)npad * 2 * KC));
+    for (int k0 = 0; k0 < c->nk; k0 += KC) {
+      launch_phase_table(st, n, npad, k0, KC, c->nk, b, c->ke, b.table);
+      launch_gemm_f64(st, false, true, npad, npad, 2 * KC, 1.0, b.table, 2 * KC, b.table,
+                      2 * KC, 1.0, b.A, npad, /*tri=*/1, 0);
+      TRY(launched(c, "kspace syrk"));
+    }
+    HIP_TRY(c, hipStreamSynchronize(st));
+    dfree(c, b.table);
+  }
+  launch_mirror_lower(st, npad, b.A);
+  TRY(launched(c, "mirror"));
+  return CPM_OK;
+}
+
 // Electrode set-up shared by the dense elastance (dense = true: assemble A)
 // and the matrix-free operator (dense = false: keep what A x needs).
 cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
@@ -887,52 +947,17 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     c->have_op = true;
     return CPM_OK;
   }
-  { Timed t(c, "assemble_real");
-    launch_real_space_A(c->stream, n, npad, b, p.Lx, p.Ly, c->Lz, p.rcut, p.alpha, eta_ee,
-                        diag_self, background, c->cdip, c->ke, d_diag_extra, b.A); }
-  TRY(launched(c, "real_space_A"));
-  if (c->nlayers > 0 && c->sf_mfma) {
-    // planar electrodes: per plane, A[rows of L] += k_e G_L F^L (K = 2 x columns);
-    // Q, G and F stay allocated for rebuilds of the same context
-    Timed t(c, "assemble_kspace");
-    const int ldG = (2 * c->ncolsort + 15) / 16 * 16;
-    TRY(dalloc(c, &b.Qpair, (size_t)c->ncolsort * c->nlayers * c->nlayers));
-    TRY(dalloc(c, &b.asmG, (size_t)c->nmap * ldG));
-    TRY(dalloc(c, &b.asmF, (size_t)ldG * npad));
-    launch_plane_pair_weights(c->stream, c->ncolsort, c->nlayers, b.sc_lo, b.sc_len, b.sc_koff,
-                              b.w2, b.layer_fz, b.Qpair);
-    launch_build_G(c->stream, c->nmap, c->ncolsort, ldG, b.amap, b.sc_nx, b.sc_ny, b, b.asmG);
-    int row0 = 0;
-    for (int L = 0; L < c->nlayers; ++L) {
-      const int rows = c->h_plane_rows[L];              // this plane's rows of the map (x 64)
-      // only the lower triangle of A is kept (mirrored at the end): the
-      // plane's rows need the columns up to their largest atom index
-      int amax = 0;
-      for (int r = row0; r < row0 + rows; ++r) amax = std::max(amax, c->h_amap[r]);
-      const int ncols = std::min(npad, (amax + 64) / 64 * 64);
-      launch_build_F(c->stream, L, n, npad, c->nlayers, c->ncolsort, ldG, b.sc_nx, b.sc_ny, b,
-                     b.Qpair, b.asmF);
-      launch_gemm_f64(c->stream, false, false, rows, ncols, ldG, c->ke, b.asmG + (size_t)row0 * ldG,
-                      ldG, b.asmF, npad, 1.0, b.A, npad, 0, 0, b.amap + row0);
-      TRY(launched(c, "kspace planes"));
-      row0 += rows;
-    }
-  } else {
-    // k space: A += T T^T over chunks of KC k-vectors (2 KC columns)
-    const int KC = 2048;
-    TRY(dalloc(c, &b.table, (size_t)npad * 2 * KC));
-    for (int k0 = 0; k0 < c->nk; k0 += KC) {
-      launch_phase_table(c->stream, n, npad, k0, KC, c->nk, b, c->ke, b.table);
-      launch_gemm_f64(c->stream, false, true, npad, npad, 2 * KC, 1.0, b.table, 2 * KC, b.table,
-                      2 * KC, 1.0, b.A, npad, /*tri=*/1, 0);
-      TRY(launched(c, "kspace syrk"));
-    }
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
-    dfree(c, b.table);
+  // A itself is assembled by its first consumer (cpm_invert on its stream,
+  // so an asynchronous inversion also overlaps the assembly with b); only the
+  // caller's diagonal term is copied now
+  c->A_diag_extra = d_diag_extra != nullptr;
+  if (d_diag_extra) {
+    TRY(dalloc(c, &b.dextra, (size_t)n));
+    HIP_TRY(c, hipMemcpyAsync(b.dextra, d_diag_extra, (size_t)n * sizeof(double),
+                              hipMemcpyDeviceToDevice, c->stream));
   }
-  launch_mirror_lower(c->stream, npad, b.A);
-  TRY(launched(c, "mirror"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->A_pending = true;
   c->have_A = true;
   return CPM_OK;
 }
@@ -990,6 +1015,7 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
     HIP_TRY(c, hipStreamWaitEvent(c->aux, c->main_ev, 0));
     st = c->aux;
   }
+  TRY(assemble_A(c, st));
   HIP_TRY(c, hipMemcpyAsync(b.L, b.A, (size_t)npad * npad * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIP_TRY(c, hipMemsetAsync(b.flag, 0, sizeof(int), st));
   HIP_TRY(c, hipMemsetAsync(b.u, 0, npad * sizeof(double), st));
@@ -1671,6 +1697,8 @@ cpm_status cpm_apply_elastance(cpm_ctx* c, int batch, const double* d_x, double*
   if (!c) return CPM_EINVAL;
   if (!c->have_op && !c->have_A)
     return fail(c, CPM_ESTATE, "cpm_apply_elastance needs cpm_build_operator or cpm_build_elastance");
+  TRY(wait_invert(c));                    // A may be assembled on the inversion's stream
+  TRY(assemble_A(c, c->stream));
   if (batch < 0 || (batch > 0 && (!d_x || !d_y)))
     return fail(c, CPM_EINVAL, "need batch >= 0 and non-NULL d_x, d_y");
   if (batch == 0) return CPM_OK;
@@ -1695,6 +1723,8 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
   if (!c) return CPM_EINVAL;
   if (!c->have_op && !c->have_A)
     return fail(c, CPM_ESTATE, "cpm_solve_cg needs cpm_build_operator or cpm_build_elastance");
+  TRY(wait_invert(c));                    // A may be assembled on the inversion's stream
+  TRY(assemble_A(c, c->stream));
   if (!c->have_v) return fail(c, CPM_ESTATE, "cpm_solve_cg before cpm_set_potential");
   if (batch < 0 || (batch > 0 && (!d_b || !d_q)))
     return fail(c, CPM_EINVAL, "need batch >= 0 and non-NULL d_b, d_q");
@@ -1769,6 +1799,7 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
 cpm_status cpm_copy_matrix(const cpm_ctx* c, int which, double* d_out) {
   if (!c || !d_out) return CPM_EINVAL;
   TRY(finish_invert(const_cast<cpm_ctx*>(c)));
+  if (which == 0 && c->have_A) TRY(assemble_A(const_cast<cpm_ctx*>(c), c->stream));
   const double* src = nullptr;
   if (which == 0 && c->have_A) src = c->b.A;
   if (which == 1 && c->have_inv) src = c->b.Ainv;

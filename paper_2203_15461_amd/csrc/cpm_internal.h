@@ -187,6 +187,8 @@ struct cpm_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   bool have_elyt = false, have_A = false, have_inv = false, have_v = false, have_q = false;
+  bool A_pending = false;          // A's kernels not yet enqueued (done by its first consumer)
+  bool A_diag_extra = false;       // a per-atom diagonal term was given (kept in b.dextra)
   bool have_op = false;            // matrix-free operator (cpm_build_operator)
   // cpm_invert with CPM_INVERT_ASYNC: second stream, completion event, pinned
   // host words for s and the pivot flag; joined by the first consumer
