@@ -491,6 +491,8 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_SFM_MIN_CHUNK")) c->sfm_min_chunk = std::max(16, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_CHOL_BLOCK"))
+    c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
@@ -1020,10 +1022,10 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   HIP_TRY(c, hipMemsetAsync(b.flag, 0, sizeof(int), st));
   HIP_TRY(c, hipMemsetAsync(b.u, 0, npad * sizeof(double), st));
   // Blocked right-looking Cholesky on the lower triangle of L, two levels:
-  // 64-wide panels inside blocks of OB columns, so that the large trailing
-  // updates are rank-OB products (four times fewer passes over the trailing
-  // matrix than rank-64 ones).
-  constexpr int OB = 4 * TILE;
+  // 64-wide panels inside blocks of OB columns (a multiple of 64), so that
+  // the large trailing updates are rank-OB products (OB / 64 times fewer
+  // passes over the trailing matrix than rank-64 ones).
+  const int OB = c->chol_block;
   for (int K0 = 0; K0 < npad; K0 += OB) {
     const int kend = std::min(npad, K0 + OB);
     for (int k0 = K0; k0 < kend; k0 += TILE) {
