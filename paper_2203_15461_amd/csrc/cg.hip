@@ -318,7 +318,41 @@ __global__ void __launch_bounds__(256) k_cg_plane_sums(int nslot, int M2, int nl
 
 // T for every plane: Tcat[(L M2 + 2c) VL + s] = Re, [.. 2c + 1 ..] = Im of
 // sum_L' Q_c(L', L) Y(c, L', s) (Y: the sum of its ksplit parts, in order);
-// zero rows for padding columns
+// zero rows for padding columns.  Up to MIX_NL planes: one workgroup per
+// column with a wave per plane; wave L' sums Y(c, L', .) over its parts into
+// LDS, then wave L forms T(c, L, .) in plane order.  More planes: one thread
+// per (plane, column, vector).
+constexpr int MIX_NL = 16;
+
+__global__ void __launch_bounds__(64 * MIX_NL) k_cg_plane_mix_col(int nlayers, int ncp,
+                                                                 int ncolsort, int ksplit,
+                                                                 const double2* __restrict__ Q,
+                                                                 const double* __restrict__ Y,
+                                                                 double* __restrict__ T) {
+  __shared__ double2 sy[MIX_NL][VL];
+  const int c = blockIdx.x, s = threadIdx.x & 63, L = threadIdx.x >> 6;
+  const size_t M2 = 2 * (size_t)ncp;
+  double yr = 0.0, yi = 0.0;
+  if (c < ncolsort)
+    for (int p = 0; p < ksplit; ++p) {
+      const double* y = Y + (((size_t)p * nlayers + L) * M2 + 2 * c) * VL + s;
+      yr += y[0];
+      yi += y[VL];
+    }
+  sy[L][s] = make_double2(yr, yi);
+  __syncthreads();
+  double tr = 0.0, ti = 0.0;
+  if (c < ncolsort)
+    for (int L2 = 0; L2 < nlayers; ++L2) {
+      const double2 q = Q[((size_t)c * nlayers + L2) * nlayers + L];
+      const double2 y = sy[L2][s];
+      tr += q.x * y.x - q.y * y.y;
+      ti += q.x * y.y + q.y * y.x;
+    }
+  T[(L * M2 + 2 * c) * VL + s] = tr;
+  T[(L * M2 + 2 * c + 1) * VL + s] = ti;
+}
+
 __global__ void k_cg_plane_mix(int nlayers, int ncp, int ncolsort, int ksplit,
                                const double2* __restrict__ Q, const double* __restrict__ Y,
                                double* __restrict__ T) {
@@ -681,6 +715,11 @@ void launch_cg_plane_sums(hipStream_t st, int nslot, int ncp, int nlayers, int k
 
 void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, int ksplit,
                          const double2* Q, const double* Y, double* T) {
+  if (nlayers <= MIX_NL) {
+    hipLaunchKernelGGL(k_cg_plane_mix_col, dim3(ncp), dim3(64 * nlayers), 0, st, nlayers, ncp,
+                       ncolsort, ksplit, Q, Y, T);
+    return;
+  }
   const size_t tot = (size_t)nlayers * ncp * VL;
   hipLaunchKernelGGL(k_cg_plane_mix, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st,
                      nlayers, ncp, ncolsort, ksplit, Q, Y, T);

@@ -231,7 +231,12 @@ int cg_nslot(const cpm_ctx* c) { return c->have_op ? c->nmap : c->npad; }
 const int* cg_slots(const cpm_ctx* c) { return c->have_op ? c->b.amap : c->b.cg_ident; }
 
 // blocks of the CG vector kernels (all share one grid)
-int cg_grid(const cpm_ctx* c) { return cg_blocks(cg_nslot(c), 128); }
+// (the partials of one kernel are summed by every workgroup of the next, so
+// fewer, fuller workgroups pay off for small operators)
+int cg_grid(const cpm_ctx* c) {
+  const int cap = c->cg_cap > 0 ? c->cg_cap : std::min(128, std::max(32, cg_nslot(c) / 48));
+  return cg_blocks(cg_nslot(c), cap);
+}
 
 // AP = A P for the slot-major CG vectors (all CG_MAXG columns): the
 // operator's k-space products, then the ELL real space and the rest
@@ -491,6 +496,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_SFM_MIN_CHUNK")) c->sfm_min_chunk = std::max(16, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CHOL_BLOCK"))
     c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;

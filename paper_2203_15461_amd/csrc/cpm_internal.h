@@ -215,6 +215,7 @@ struct cpm_ctx {
   int sfm_wg_target = 4096;        // the same for the matrix-core kernel
   int sfm_min_chunk = 512;         // fewest charges per matrix-core chunk
   int chol_block = 256;            // columns per outer block of the Cholesky / inverse
+  int cg_cap = 0;                  // most workgroups of the CG vector kernels (0: by size)
   int rs_wg_target = 512;          // real-space workgroups per launch group
   int rs_sort_min = 16;            // batches of at least this size sort the charges by z
   unsigned store = 0;
