@@ -130,63 +130,124 @@ void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int
 }
 
 // ---------------------------------------------------------------------------
-// Diagonal 64x64 block of the Cholesky factorisation, in one workgroup:
-// unblocked right-looking factorisation in LDS, then the inverse of the
-// triangular factor (one column per thread).  A pivot <= 0 (or NaN) records
-// 1 + its global index in *flag (first one wins) and continues with 1.
+// Diagonal 64x64 block of the Cholesky factorisation, in one workgroup, in
+// four panels of 16 columns: wave 0 factors the panel's 16 x 16 diagonal
+// block right-looking (wave-level syncs only), one thread per row below
+// solves that row's 16 panel entries, then every thread updates trailing
+// elements.  The inverse of the factor: the four diagonal 16 x 16 blocks by
+// forward substitution (a wave each, a lane per column), then block rows 1..3
+// in turn, X_ik = -X_ii sum_{j=k}^{i-1} L_ij X_jk.  About 20 workgroup
+// barriers in all.  A pivot <= 0 (or NaN) records 1 + its global index in
+// *flag (first one wins) and continues with 1.
 // ---------------------------------------------------------------------------
+__device__ inline void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void __launch_bounds__(1024) k_potrf_diag(double* Lblk, int ld, double* Dinv, int* flag,
                                                      int k0) {
-  __shared__ double a[64][65];     // working copy (lower triangle), updated right-looking
-  __shared__ double L[64][65];     // the factor
-  __shared__ double X[64][65];     // L^-1, built row by row
-  __shared__ double rdiag[64];     // 1 / L[j][j]
-  constexpr int P = 16;            // thread groups sharing a row (16 waves)
-  const int tid = threadIdx.x, i = tid & 63, part = tid >> 6;
-  for (int e = tid; e < 64 * 64; e += 64 * P) {
+  __shared__ double a[64][65];     // working lower triangle, becomes L
+  __shared__ double X[64][65];     // L^-1
+  __shared__ double T[3][16][17];  // block-row products of the inverse
+  __shared__ double rd[64];        // 1 / L[j][j]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int e = tid; e < 64 * 64; e += 1024) {
     const int r = e >> 6, c = e & 63;
     a[r][c] = (c <= r) ? Lblk[(size_t)r * ld + c] : 0.0;
-    L[r][c] = 0.0;
-    X[r][c] = (r == c) ? 1.0 : 0.0;
+    X[r][c] = 0.0;
   }
   __syncthreads();
-  // Column j: every thread takes the pivot itself, thread (i, part 0) writes
-  // L[i][j], and thread (i, part) updates a[i][l] for l = j+1+part,
-  // j+1+part+P, ... <= i with the unscaled column (a[i][j] a[l][j] / a[j][j]).
-  // Column j of `a` is only read in step j, so one barrier per column
-  // suffices.
-  for (int j = 0; j < 64; ++j) {
-    double piv = a[j][j];
-    if (!(piv > 0.0)) {
-      if (tid == 0) atomicCAS(flag, 0, k0 + j + 1);
-      piv = 1.0;
+  for (int p0 = 0; p0 < 64; p0 += 16) {
+    if (wave == 0) {
+      const int r = lane & 15, part = lane >> 4;
+      for (int j = 0; j < 16; ++j) {
+        const int jj = p0 + j;
+        double piv = a[jj][jj];
+        if (!(piv > 0.0)) {
+          if (lane == 0) atomicCAS(flag, 0, k0 + jj + 1);
+          piv = 1.0;
+        }
+        const double d = sqrt(piv), rdj = 1.0 / d;
+        const double lr = a[p0 + r][jj] * rdj;
+        if (r > j)
+          for (int l = j + 1 + part; l <= r; l += 4) a[p0 + r][p0 + l] -= lr * (a[p0 + l][jj] * rdj);
+        wave_sync_lds();
+        if (part == 0 && r > j) a[p0 + r][jj] = lr;
+        if (lane == 0) {
+          a[jj][jj] = d;
+          rd[jj] = rdj;
+        }
+        wave_sync_lds();
+      }
     }
-    const double d = sqrt(piv), rd = 1.0 / d, rpiv = rd * rd;
-    if (part == 0 && i >= j) {
-      L[i][j] = (i == j) ? d : a[i][j] * rd;
-      if (i == j) rdiag[j] = rd;
+    __syncthreads();
+    const int nrem = 64 - p0 - 16;
+    if (tid < nrem) {                      // row R of the panel below the diagonal block
+      const int R = p0 + 16 + tid;
+      double row[16];
+#pragma unroll
+      for (int t = 0; t < 16; ++t) row[t] = a[R][p0 + t];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        double s = row[j];
+#pragma unroll
+        for (int t = 0; t < j; ++t) s -= row[t] * a[p0 + j][p0 + t];
+        row[j] = s * rd[p0 + j];
+      }
+#pragma unroll
+      for (int t = 0; t < 16; ++t) a[R][p0 + t] = row[t];
     }
-    if (i > j) {
-      const double lij = a[i][j] * rpiv;
-      for (int l = j + 1 + part; l <= i; l += P) a[i][l] -= lij * a[l][j];
+    __syncthreads();
+    for (int e = tid; e < nrem * nrem; e += 1024) {
+      const int R = p0 + 16 + e / nrem, C = p0 + 16 + e % nrem;
+      if (C <= R) {
+        double s = a[R][C];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s -= a[R][p0 + t] * a[C][p0 + t];
+        a[R][C] = s;
+      }
     }
     __syncthreads();
   }
-  // X = L^-1 by forward substitution, right-looking over rows: at step r row
-  // r of X is final after scaling by 1 / L[r][r]; thread (column c = i, part)
-  // removes its contribution from rows r' = r+1+part, r+1+part+P, ...  Row r
-  // of the working X is read in step r and written (scaled) only by part 0
-  // after the barrier, so one barrier per step suffices.
-  for (int r = 0; r < 64; ++r) {
-    const double x = X[r][i] * rdiag[r];
-    for (int rr = r + 1 + part; rr < 64; rr += P) X[rr][i] -= L[rr][r] * x;
-    __syncthreads();
-    if (part == 0) X[r][i] = x;
+  // diagonal blocks of X: wave k inverts L_kk, lane c solves column c
+  if (wave < 4 && lane < 16) {
+    // entries above the diagonal of the column stay zero: x[t] = 0 for t < c
+    const int p0 = 16 * wave, c = lane;
+    double x[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double s = (r == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int t = 0; t < r; ++t) s -= a[p0 + r][p0 + t] * x[t];
+      x[r] = (r >= c) ? s * rd[p0 + r] : 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < 16; ++r) X[p0 + r][p0 + c] = x[r];
   }
   __syncthreads();
-  for (int e = tid; e < 64 * 64; e += 64 * P) {
+  for (int i = 1; i < 4; ++i) {
+    const int k = tid >> 8, r = (tid >> 4) & 15, c = tid & 15;
+    if (k < i) {
+      double s = 0.0;
+      for (int j = k; j < i; ++j)
+#pragma unroll
+        for (int t = 0; t < 16; ++t) s += a[16 * i + r][16 * j + t] * X[16 * j + t][16 * k + c];
+      T[k][r][c] = s;
+    }
+    __syncthreads();
+    if (k < i) {
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < 16; ++t) s += X[16 * i + r][16 * i + t] * T[k][t][c];
+      X[16 * i + r][16 * k + c] = -s;
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < 64 * 64; e += 1024) {
     const int r = e >> 6, c = e & 63;
-    Lblk[(size_t)r * ld + c] = L[r][c];
+    Lblk[(size_t)r * ld + c] = (c <= r) ? a[r][c] : 0.0;
     Dinv[e] = X[r][c];
   }
 }
