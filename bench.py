@@ -447,9 +447,11 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
 
 def stored_traffic(workload, configs_per_launch):
     """HBM bytes per structure-factor launch from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (scaled by a 1 GiB copy), or None when the
-    kernel source changed since the counters were taken or the launch shape
-    differs by more than 5%."""
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a 1 GiB copy), per
+    configuration times the timed run's average configurations per launch
+    (a step's last launch group can be partial); None when the kernel source
+    changed since the counters were taken or the average launch holds fewer
+    than 3/4 (or more) of the profiled configurations."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "structure_factor_traffic.json")
     src = os.path.join(ROOT, "paper_2203_15461_amd", "csrc", "bvector.hip")
@@ -462,7 +464,7 @@ def stored_traffic(workload, configs_per_launch):
     if not entry or rec.get("bvector_sha256") != digest:
         return None
     per = entry.get("configurations_per_launch", 1)
-    if abs(per - configs_per_launch) > 0.05 * per:
+    if configs_per_launch > per * 1.001 or configs_per_launch < 0.75 * per:
         return None
     # per configuration, times the timed run's average configurations per launch
     return entry["bytes_per_launch"] / per * configs_per_launch
