@@ -11,6 +11,7 @@
 //   A operand: element (row l%16, k l/16); B operand: (k l/16, col l%16);
 //   result register r: element (row l/16 + 4 r, col l%16).
 #include <algorithm>
+#include <cstdlib>
 
 #include "cpm_internal.h"
 
@@ -469,14 +470,20 @@ template <typename TM>
 void launch_matvec_t(hipStream_t st, int n, int npad, const TM* M, int batch, const void* x,
                      int x_is_f32, int ldx, const double* xshift, const double* add, int add_ld,
                      double addscale, double* y, int ldy, int negate) {
-  // rows per wave: enough waves to fill the chip (>= ~2048 per vector), and
-  // as many rows as that allows so each x load serves R rows
-  const int R = npad >= 16384 ? 8 : npad >= 8192 ? 4 : npad >= 4096 ? 2 : 1;
+  // rows per wave: 4 rows share each x load (measured best from N ~ 3k,
+  // where S sits in the last-level cache, to N ~ 20k, where it streams from
+  // HBM: 75% / 71% of the HBM peak for FP64 / FP32 at N = 20064)
+  int R = npad >= 2048 ? 4 : npad >= 1024 ? 2 : 1;
+  if (const char* ev = std::getenv("CPM_MV_ROWS")) {
+    const int r = std::atoi(ev);
+    if (r == 1 || r == 2 || r == 4 || r == 8 || r == 16) R = r;
+  }
   dim3 grid((npad / R + 3) / 4, batch), block(256);
 #define CPM_MV(RR)                                                                           \
   hipLaunchKernelGGL((k_matvec<TM, RR>), grid, block, 0, st, n, npad, M, x, x_is_f32, ldx,   \
                      xshift, add, add_ld, addscale, y, ldy, negate)
-  if (R == 8) CPM_MV(8); else if (R == 4) CPM_MV(4); else if (R == 2) CPM_MV(2); else CPM_MV(1);
+  if (R == 16) CPM_MV(16); else if (R == 8) CPM_MV(8); else if (R == 4) CPM_MV(4);
+  else if (R == 2) CPM_MV(2); else CPM_MV(1);
 #undef CPM_MV
 }
 
