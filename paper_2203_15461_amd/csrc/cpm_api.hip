@@ -199,13 +199,15 @@ void build_kset(cpm_ctx* c, std::vector<KRun>& runs, std::vector<double>& w2,
 }
 
 // charge chunks per configuration for a group of g configurations on the
-// matrix-core structure-factor path: about sfm_wg_target workgroups, at
-// least sfm_min_chunk charges per chunk (small groups: fewer partials to
-// write and sum), and g * chunks a multiple of 8 (the kernel keeps each
-// (configuration, chunk) pair on one XCD)
+// matrix-core structure-factor path: about sfm_wg_target workgroups, at most
+// sfm_max_chunk charges per chunk (a chunk's table rows, ~1 KB per charge,
+// then fit one XCD's L2: large systems), at least sfm_min_chunk (small
+// groups: fewer partials to write and sum), and g * chunks a multiple of 8
+// (the kernel keeps each (configuration, chunk) pair on one XCD)
 int sf_chunks_for(const cpm_ctx* c, int g) {
-  const int base = std::max(1, std::min((c->sfm_wg_target + c->sfm_nitems * g - 1) / (c->sfm_nitems * g),
-                                        c->m / c->sfm_min_chunk));
+  const int by_wg = (c->sfm_wg_target + c->sfm_nitems * g - 1) / (c->sfm_nitems * g);
+  const int by_l2 = (c->m + c->sfm_max_chunk - 1) / c->sfm_max_chunk;
+  const int base = std::max(1, std::min(std::max(by_wg, by_l2), c->m / c->sfm_min_chunk));
   int step = 8;
   while (step > 1 && g % (8 / step * 2) == 0) step /= 2;   // step = 8 / gcd(g, 8)
   return (base + step - 1) / step * step;
@@ -494,6 +496,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_SF_WG_TARGET")) c->sf_wg_target = std::max(64, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_WG_TARGET")) c->sfm_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_MIN_CHUNK")) c->sfm_min_chunk = std::max(16, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_SFM_MAX_CHUNK")) c->sfm_max_chunk = std::max(64, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));

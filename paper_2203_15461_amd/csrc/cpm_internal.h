@@ -214,6 +214,7 @@ struct cpm_ctx {
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
   int sfm_wg_target = 4096;        // the same for the matrix-core kernel
   int sfm_min_chunk = 512;         // fewest charges per matrix-core chunk
+  int sfm_max_chunk = 4096;        // most charges per matrix-core chunk
   int chol_block = 256;            // columns per outer block of the Cholesky / inverse
   int cg_cap = 0;                  // most workgroups of the CG vector kernels (0: by size)
   int rs_wg_target = 512;          // real-space workgroups per launch group
