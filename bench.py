@@ -246,7 +246,8 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
                      "frac": achieved / peak, "traffic": traffic,
                      "flop_per_launch": flop_per_launch, "flop_per_k_charge_pair": flop_per_pair,
                      "avg_launch_us": sf_avg * 1e6,
-                     "configurations_per_launch": snaps_per_launch},
+                     "configurations_per_launch": snaps_per_launch,
+                     "launch_group": int(ctx.info("group"))},
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),
         "plain_fp64_per_step_rate": plain_rate,

@@ -320,12 +320,13 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     c->sft_rows = sf_table_rows(c->nxm, c->nym, c->sfm_nbz);
     c->sft_blocks = (c->mpad + 255) / 256;
     // planar electrodes: configurations per launch group (at most the 64
-    // columns of the projection product), within ~512 MB of per-configuration
-    // workspace
+    // columns of the projection product), within ~1 GB of per-configuration
+    // workspace (phase tables, two chunks of structure-factor partials,
+    // real-space partials, gathered charges)
     if (fast) {
-      const double per = 16.0 * c->sft_rows * c->mpad + 8.0 * c->sfm_pchunk +
-                         8.0 * c->rchunks * c->n + 24.0 * ((c->m + 255) / 256);
-      c->pv_group = std::max(1, std::min(CG_MAXG, (int)(512.0 * 1024 * 1024 / per)));
+      const double per = 16.0 * c->sft_rows * c->mpad + 16.0 * c->sfm_pchunk +
+                         16.0 * c->n + 32.0 * c->m + 24.0 * ((c->m + 255) / 256);
+      c->pv_group = std::max(1, std::min(CG_MAXG, (int)(1024.0 * 1024 * 1024 / per)));
     }
     const int G = c->pv_group;
     size_t part_rows = 0;                 // (configuration, chunk) blocks of sfm_part
