@@ -189,7 +189,7 @@ cpm_status cpm_apply_elastance(cpm_ctx* ctx, int batch, const double* d_x, doubl
  * d_b: batch x n (FP64, or FP32 with b_is_f32 = 1); v from
  * cpm_set_potential(_atoms).  Each vector stops when |r| <= tol |r0| (r the
  * projected residual, recursively updated); at most maxit iterations.
- * Vectors run in groups of 32.  Writes d_q (batch x n FP64, the final
+ * Vectors run in groups of 64.  Writes d_q (batch x n FP64, the final
  * iterate projected to e^T q = 0) and, unless NULL, d_Qe (batch x n_e
  * electrode totals).  Synchronous (the host checks convergence every 8
  * iterations).  CPM_ENOCONV if some vector ended above the tolerance (the
@@ -200,7 +200,8 @@ cpm_status cpm_solve_cg(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32, 
 
 /* Invert A in FP64 (blocked Cholesky A = L L^T, then A^-1 = L^-T L^-1,
  * Eq. 3), form u = A^-1 e, s = e^T u and the charge-neutral S of Eq. 4, and
- * keep the copies of S named by store_flags (CPM_STORE_*).  Synchronous;
+ * keep the copies of S named by store_flags (CPM_STORE_*).  The assembly of
+ * A left by cpm_build_elastance runs first, on the same stream.  Synchronous;
  * returns CPM_ENOTPD (pivot via CPM_INFO_PIVOT) if A is not positive
  * definite. */
 /* With CPM_INVERT_ASYNC in store_flags the work runs on a second stream of
