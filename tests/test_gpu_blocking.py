@@ -112,3 +112,47 @@ def test_cg_grid_sizes(cpm, monkeypatch):
         ctx.close()
     assert rel(qs[0], qs[1]) < 1e-11
     assert np.all(np.abs(qs[0].sum(1)) <= 1e-12)
+
+
+def test_z_order_with_fewer_charges_than_a_block(cpm):
+    """Two ions, a batch of 20 (z-ordered path): one partial 64-charge block,
+    so most real-space chunks are empty and must contribute zero."""
+    w = I.small_capacitor("b", n_ions=2)
+    xyz = [I.snapshot(w, s) for s in range(20)]
+    say(f"z-ordered real space with m = {w.m}, batch 20")
+    b = _b(cpm, w, xyz)
+    p = O.params_for(w)
+    ref = np.array([O.potential_vector(w.electrode_xyz, r, w.electrolyte_q, p) for r in xyz[:4]])
+    assert rel(b[:4], ref) < 1e-10
+
+
+def test_assembly_deferred_to_first_consumer(cpm):
+    """cpm_build_elastance leaves the assembly of A to its first consumer:
+    cpm_copy_matrix(0) and cpm_apply_elastance without any cpm_invert, and
+    an asynchronous cpm_invert, all see the same A (the oracle's)."""
+    w = I.small_capacitor("a")
+    p = O.params_for(w)
+    A_ref = O.elastance(w.electrode_xyz, p)
+    R = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device="cuda").contiguous()
+    eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device="cuda").contiguous()
+    say("deferred assembly: copy, apply, asynchronous inversion")
+    ctx = cpm.Context(cpm.Params.of(w))
+    ctx.set_electrolyte(w.electrolyte_q)
+    ctx.build_elastance(R, eid, 2)
+    A = ctx.copy_matrix(0, torch.empty((w.n, w.n), dtype=torch.float64, device="cuda"))
+    ctx.synchronize()
+    assert rel(A.cpu().numpy(), A_ref) < 1e-11
+    ctx.build_elastance(R, eid, 2)                     # pending again: apply assembles it
+    x = torch.as_tensor(np.random.default_rng(5).normal(size=(3, w.n)), device="cuda").contiguous()
+    y = torch.empty_like(x)
+    ctx.apply_elastance(x, y)
+    ctx.synchronize()
+    assert rel(y.cpu().numpy(), x.cpu().numpy() @ A_ref.T) < 1e-11
+    ctx.build_elastance(R, eid, 2)
+    ctx.invert(cpm.STORE_F64 | cpm.INVERT_ASYNC)       # assembly on the second stream
+    S = ctx.copy_matrix(2, torch.empty((w.n, w.n), dtype=torch.float64, device="cuda"))
+    A2 = ctx.copy_matrix(0, torch.empty((w.n, w.n), dtype=torch.float64, device="cuda"))
+    ctx.synchronize()
+    assert rel(A2.cpu().numpy(), A_ref) < 1e-11
+    assert rel(S.cpu().numpy(), O.capacitance(A_ref).S) < 1e-10
+    ctx.close()
