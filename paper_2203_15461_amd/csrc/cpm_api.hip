@@ -359,12 +359,16 @@ cpm_status ensure_solve_buffers(cpm_ctx* c, int batch) {
   if (batch > b.bpad_rows) {
     const size_t old = (size_t)b.bpad_rows * c->npad * sizeof(double);
     if (b.qt) c->bytes -= 4 * old;
+    if (b.xhi) c->bytes -= old / 2;
     dfree(c, b.qt); dfree(c, b.res); dfree(c, b.qpad); dfree(c, b.bpad);
+    dfree(c, b.xhi); dfree(c, b.xlo);
     const size_t sz = (size_t)batch * c->npad;
     TRY(dalloc(c, &b.qt, sz));
     TRY(dalloc(c, &b.res, sz));
     TRY(dalloc(c, &b.qpad, sz));
     TRY(dalloc(c, &b.bpad, sz));
+    TRY(dalloc(c, &b.xhi, sz));
+    TRY(dalloc(c, &b.xlo, sz));
     dfree(c, b.means);
     TRY(dalloc(c, &b.means, (size_t)batch));
     // padding rows and columns of these buffers are read by the GEMMs: zero them once
@@ -394,14 +398,16 @@ cpm_status ensure_kpart(cpm_ctx* c, size_t len) {
   return CPM_OK;
 }
 
-// one split-BF16 product C (+)= X S~ over `rows` rows of this context
+// one split-BF16 product C (+)= X S~ over `rows` rows of this context; X is
+// split into BF16 pairs once, before the product
 void enqueue_bf16(cpm_ctx* c, const double* x, double* y, int rows, bool accumulate,
                   const cpm_ctx::GemmCfg& cfg) {
   const int npad = c->npad;
+  launch_split_bf16(c->stream, (size_t)rows * npad, x, c->b.xhi, c->b.xlo);
   GemmGroupBf grp{};
   grp.nprob = 1;
-  grp.p[0] = gemm_bf16x3_problem(rows, npad, npad, x, npad, c->b.Shi, c->b.Slo, npad, y, npad,
-                                 accumulate ? 1 : 0, cfg.bm, cfg.ks, c->b.kpart);
+  grp.p[0] = gemm_bf16x3_problem(rows, npad, npad, c->b.xhi, c->b.xlo, npad, c->b.Shi, c->b.Slo,
+                                 npad, y, npad, accumulate ? 1 : 0, cfg.bm, cfg.ks, c->b.kpart);
   group_finish(grp);
   launch_gemm_bf16x3_group(c->stream, grp, cfg.bm, cfg.grid > 0 ? cfg.grid : grp.total);
 }
@@ -1630,10 +1636,11 @@ cpm_status cpm_solve_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
     for (int i = 0; i < n_ctx; ++i) {
       cpm_ctx* c = ctxs[i];
       const int rows = ((batch[i] + TILE - 1) / TILE) * TILE;
-      grp.p[i] = gemm_bf16x3_problem(rows, c->npad, c->npad, second ? c->b.res : c->b.bpad,
-                                     c->npad, c->b.Shi, c->b.Slo, c->npad,
-                                     second ? c->b.qt : c->b.qpad, c->npad, second ? 1 : 0, 64,
-                                     1, nullptr);
+      launch_split_bf16(st, (size_t)rows * c->npad, second ? c->b.res : c->b.bpad, c->b.xhi,
+                        c->b.xlo);
+      grp.p[i] = gemm_bf16x3_problem(rows, c->npad, c->npad, c->b.xhi, c->b.xlo, c->npad,
+                                     c->b.Shi, c->b.Slo, c->npad, second ? c->b.qt : c->b.qpad,
+                                     c->npad, second ? 1 : 0, 64, 1, nullptr);
     }
     group_finish(grp);
     Timed t(c0, "gemm_bf16x3_grouped");
@@ -1905,6 +1912,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.dip); dfree(b.qt);
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
+  dfree(b.xhi); dfree(b.xlo);
   dfree(b.zperm); dfree(b.cq); dfree(b.zr);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
   dfree(b.Qpair); dfree(b.ell_col); dfree(b.ell_val); dfree(b.plane_off); dfree(b.dextra);

@@ -107,6 +107,8 @@ struct Buffers {
   double* res = nullptr;           // refinement residual / corrections (batch x npad)
   double* bpad = nullptr;          // padded b for batched solves (bpad_rows x npad)
   double* qpad = nullptr;          // padded GEMM output (bpad_rows x npad)
+  uint16_t* xhi = nullptr;         // left operand of the split-BF16 product, BF16 pairs
+  uint16_t* xlo = nullptr;         //   (bpad_rows x npad each)
   double* means = nullptr;         // per-vector uniform part removed before S products
   double* kpart = nullptr;         // split-K partial slices of the batched split-BF16 GEMM
   double* ccmU = nullptr;          // constrained charges: U = A^-1 G (n x n_e)
@@ -338,7 +340,8 @@ void launch_pad_rows(hipStream_t st, int n, int npad, int batch, int rows, const
 // split-BF16 GEMM problems, one persistent launch per group (see dense.hip)
 constexpr int GB_MAXP = 8;
 struct GemmProbBf {
-  const double* X; const uint16_t* Shi; const uint16_t* Slo; double* C; double* part;
+  const uint16_t* Xhi; const uint16_t* Xlo;   // the left operand split into BF16 pairs
+  const uint16_t* Shi; const uint16_t* Slo; double* C; double* part;
   int M, N, K, ldx, lds, ldc, tiles_m, tiles_n, ks, accumulate;
 };
 struct GemmGroupBf {
@@ -346,9 +349,11 @@ struct GemmGroupBf {
   int start[GB_MAXP + 1];
   GemmProbBf p[GB_MAXP];
 };
-GemmProbBf gemm_bf16x3_problem(int M, int N, int K, const double* X, int ldx,
-                               const uint16_t* Shi, const uint16_t* Slo, int lds, double* C,
-                               int ldc, int accumulate, int bm, int ks, double* part);
+GemmProbBf gemm_bf16x3_problem(int M, int N, int K, const uint16_t* Xhi, const uint16_t* Xlo,
+                               int ldx, const uint16_t* Shi, const uint16_t* Slo, int lds,
+                               double* C, int ldc, int accumulate, int bm, int ks, double* part);
+// x ~ hi + lo as BF16 pairs (count FP64 values), the same split as the copies of S
+void launch_split_bf16(hipStream_t st, size_t count, const double* x, uint16_t* hi, uint16_t* lo);
 void group_finish(GemmGroupBf& grp);
 void launch_gemm_bf16x3_group(hipStream_t st, const GemmGroupBf& grp, int bm, int grid);
 

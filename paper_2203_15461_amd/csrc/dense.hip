@@ -394,6 +394,22 @@ __global__ void k_convert_S(size_t tot, const double* __restrict__ S, float* S32
   }
 }
 
+// x ~ hi + lo: hi = bf16(x), lo = bf16(x - hi) through FP32, as for S
+__global__ void k_split_bf16(size_t count, const double* __restrict__ x, uint16_t* __restrict__ hi,
+                             uint16_t* __restrict__ lo) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const float f = (float)x[e];
+  const uint16_t h = f32_to_bf16(f);
+  hi[e] = h;
+  lo[e] = f32_to_bf16(f - bf16_to_f32(h));
+}
+
+void launch_split_bf16(hipStream_t st, size_t count, const double* x, uint16_t* hi, uint16_t* lo) {
+  hipLaunchKernelGGL(k_split_bf16, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, count,
+                     x, hi, lo);
+}
+
 void launch_convert_S(hipStream_t st, int npad, const double* S, float* S32, uint16_t* hi,
                       uint16_t* lo) {
   const size_t tot = (size_t)npad * npad;
@@ -744,7 +760,6 @@ template <int BM>
 __global__ void __launch_bounds__(256) k_gemm_bf16x3(GemmGroupBf grp) {
   constexpr int P = 40;                 // LDS row pitch in BF16 elements (32 + 8)
   constexpr int FM = BM / 32;           // 16-row blocks per wave
-  constexpr int XR = BM / 64 > 0 ? BM / 64 : 1;   // X rows per thread and slab (BM >= 64)
   __shared__ __attribute__((aligned(16))) uint16_t Ah[BM * P], Al[BM * P], Bh[64 * P], Bl[64 * P];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = (wave >> 1) * (BM / 2), wn = (wave & 1) * 32;
@@ -762,22 +777,24 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(GemmGroupBf grp) {
     for (int a = 0; a < FM; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
-    // loader slots: X rows (BM x 32 FP64 per slab), S rows (64 x 32 BF16 hi and lo)
+    // loader slots: X rows (BM x 32 BF16 hi and lo per slab), S rows (64 x 32)
     const int sr = tid >> 2, sc = (tid & 3) * 8;
-    double xv[XR][8 / (BM >= 64 ? 1 : 2)];
+    constexpr int XR = BM >= 64 ? BM / 64 : 1;        // 8-element X groups per thread
+    uint4 xh[XR], xl[XR];
+    uint2 xh2, xl2;                                    // BM = 32: 4 elements per thread
     uint4 sh, sl;
     auto load = [&](int k0) {
       if constexpr (BM >= 64) {
 #pragma unroll
         for (int u = 0; u < XR; ++u) {
-          const double* src = pr.X + (size_t)(m0 + sr + 64 * u) * pr.ldx + k0 + sc;
-#pragma unroll
-          for (int q = 0; q < 8; ++q) xv[u][q] = src[q];
+          const size_t xo = (size_t)(m0 + sr + 64 * u) * pr.ldx + k0 + sc;
+          xh[u] = *reinterpret_cast<const uint4*>(pr.Xhi + xo);
+          xl[u] = *reinterpret_cast<const uint4*>(pr.Xlo + xo);
         }
       } else {
-        const double* src = pr.X + (size_t)(m0 + (tid >> 3)) * pr.ldx + k0 + (tid & 7) * 4;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) xv[0][q] = src[q];
+        const size_t xo = (size_t)(m0 + (tid >> 3)) * pr.ldx + k0 + (tid & 7) * 4;
+        xh2 = *reinterpret_cast<const uint2*>(pr.Xhi + xo);
+        xl2 = *reinterpret_cast<const uint2*>(pr.Xlo + xo);
       }
       const size_t so = (size_t)(n0 + sr) * pr.lds + k0 + sc;
       sh = *reinterpret_cast<const uint4*>(pr.Shi + so);
@@ -787,27 +804,13 @@ __global__ void __launch_bounds__(256) k_gemm_bf16x3(GemmGroupBf grp) {
       if constexpr (BM >= 64) {
 #pragma unroll
         for (int u = 0; u < XR; ++u) {
-          uint16_t hi[8], lo[8];
-#pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const float f = (float)xv[u][q];
-            hi[q] = f32_to_bf16(f);
-            lo[q] = f32_to_bf16(f - bf16_to_f32(hi[q]));
-          }
-          *reinterpret_cast<uint4*>(&Ah[(sr + 64 * u) * P + sc]) = *reinterpret_cast<const uint4*>(hi);
-          *reinterpret_cast<uint4*>(&Al[(sr + 64 * u) * P + sc]) = *reinterpret_cast<const uint4*>(lo);
+          *reinterpret_cast<uint4*>(&Ah[(sr + 64 * u) * P + sc]) = xh[u];
+          *reinterpret_cast<uint4*>(&Al[(sr + 64 * u) * P + sc]) = xl[u];
         }
       } else {
-        uint16_t hi[4], lo[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const float f = (float)xv[0][q];
-          hi[q] = f32_to_bf16(f);
-          lo[q] = f32_to_bf16(f - bf16_to_f32(hi[q]));
-        }
         const int r = tid >> 3, c4 = (tid & 7) * 4;
-        *reinterpret_cast<uint2*>(&Ah[r * P + c4]) = *reinterpret_cast<const uint2*>(hi);
-        *reinterpret_cast<uint2*>(&Al[r * P + c4]) = *reinterpret_cast<const uint2*>(lo);
+        *reinterpret_cast<uint2*>(&Ah[r * P + c4]) = xh2;
+        *reinterpret_cast<uint2*>(&Al[r * P + c4]) = xl2;
       }
       *reinterpret_cast<uint4*>(&Bh[sr * P + sc]) = sh;
       *reinterpret_cast<uint4*>(&Bl[sr * P + sc]) = sl;
@@ -888,11 +891,11 @@ void launch_gemm_bf16x3_group(hipStream_t st, const GemmGroupBf& grp, int bm, in
 
 // Fill one problem of a group: X (M x K, ld ldx), S hi/lo (N x K, ld lds),
 // C (M x ldc); part: ks x M x ldc doubles when ks > 1.
-GemmProbBf gemm_bf16x3_problem(int M, int N, int K, const double* X, int ldx,
-                               const uint16_t* Shi, const uint16_t* Slo, int lds, double* C,
-                               int ldc, int accumulate, int bm, int ks, double* part) {
+GemmProbBf gemm_bf16x3_problem(int M, int N, int K, const uint16_t* Xhi, const uint16_t* Xlo,
+                               int ldx, const uint16_t* Shi, const uint16_t* Slo, int lds,
+                               double* C, int ldc, int accumulate, int bm, int ks, double* part) {
   GemmProbBf pr{};
-  pr.X = X; pr.Shi = Shi; pr.Slo = Slo; pr.C = C; pr.part = part;
+  pr.Xhi = Xhi; pr.Xlo = Xlo; pr.Shi = Shi; pr.Slo = Slo; pr.C = C; pr.part = part;
   pr.M = M; pr.N = N; pr.K = K; pr.ldx = ldx; pr.lds = lds; pr.ldc = ldc;
   pr.tiles_m = M / bm; pr.tiles_n = N / 64; pr.ks = ks; pr.accumulate = accumulate;
   return pr;
