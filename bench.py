@@ -90,7 +90,8 @@ def main():
                                                    "plain_fp64_per_step_rate", "matvec_roofline",
                                                    "conjugate_gradient", "max_abs_sum_q")}
     if not args.no_cpu_baseline and w.n < 10000:
-        out["cpu_baseline"] = cpu_baseline(w)
+        out["cpu_baseline"], q_ref, Q_ref = cpu_baseline(w)
+        out["accuracy_vs_oracle"] = accuracy_vs_oracle(w, q_ref, Q_ref)
     print(json.dumps(out), flush=True)
 
 
@@ -489,9 +490,43 @@ def cpu_baseline(w):
     dt = time.perf_counter() - t
     assert abs(q.sum()) < 1e-10
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    Q = O.electrode_totals(q, w.electrode_id, 2)
     return {"value": 1.0 / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
             "sample": "1 snapshot of graphite_capacitor_2880: b (Ewald real+k+slab) and q = S(b+v) "
-                      f"in FP64 numpy ({dt:.1f} s); A and S built beforehand, untimed"}
+                      f"in FP64 numpy ({dt:.1f} s); A and S built beforehand, untimed"}, q, Q
+
+
+def accuracy_vs_oracle(w, q_ref, Q_ref):
+    """Error of each solve path in q and in the electrode totals against the
+    oracle's FP64 result for snapshot 0: the plain FP64 path (one vector,
+    streaming matvec), and the batched FP32 and split-BF16 paths (a batch of 8
+    snapshots, snapshot 0 first; b in FP32 for the FP32 path), each with one
+    FP64 refinement step."""
+    import numpy as np
+    import torch
+    from paper_2203_15461_amd import cpm
+    from paper_2203_15461_amd import inputs as I
+    dev = torch.device("cuda:0")
+    ctx = cpm.setup(w, store=cpm.STORE_F64 | cpm.STORE_F32 | cpm.STORE_BF16X2)
+    xyz = torch.as_tensor(np.stack([I.snapshot(w, s) for s in range(8)]), dtype=torch.float64,
+                          device=dev).contiguous()
+    b64 = torch.empty((8, w.n), dtype=torch.float64, device=dev)
+    b32 = torch.empty((8, w.n), dtype=torch.float32, device=dev)
+    ctx.potential_vector(xyz, b64)
+    ctx.potential_vector(xyz, b32)
+    out = {}
+    for name, bb, mode, rows in (("f64_plain", b64, 0x000, 1), ("f32r_batched", b32, 0x101, 8),
+                                 ("bf16r_batched", b64, 0x102, 8)):
+        q = torch.empty((rows, w.n), dtype=torch.float64, device=dev)
+        Qe = torch.empty((rows, 2), dtype=torch.float64, device=dev)
+        ctx.solve_charges(bb[:rows], mode, q, Qe)
+        ctx.synchronize()
+        q0, Q0 = q[0].cpu().numpy(), Qe[0].cpu().numpy()
+        out[name] = {"q_rel": float(np.abs(q0 - q_ref).max() / np.abs(q_ref).max()),
+                     "Q_rel": float(np.abs(Q0 - Q_ref).max() / np.abs(Q_ref).max()),
+                     "abs_sum_q": float(abs(q0.sum()))}
+    ctx.close()
+    return out
 
 
 if __name__ == "__main__":
