@@ -358,14 +358,17 @@ def matvec_roofline(ctx, w, xyz, dev, reps=20):
     return out
 
 
-CG_FAMILIES = ("cg_plane_sums", "cg_plane_mix", "cg_tiles", "cg_apply", "cg_update", "cg_dir",
-               "cg_init", "cg_finish")
+CG_FAMILIES = ("cg_plane_sums", "cg_plane_mix", "cg_tiles", "cg_apply", "cg_update", "cg_precond",
+               "cg_dir", "cg_init", "cg_finish")
 
 
 def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     """The matrix-free conjugate-gradient solve on the same workload: operator
     set-up, then B = 64 configurations (one CG group) solved to |r| <= tol |r0|
-    per call.  Reports solves/s, iterations, the per-iteration kernel split
+    per call, with the two-level preconditioner (built by the first, untimed
+    solve; its set-up time is reported on its own) and, for comparison, the
+    iteration count of plain CG.  Reports solves/s, iterations, the
+    per-iteration kernel split
     with each family's algorithmic HBM bytes (and FP64 flops for the two
     matrix-core products), and the largest deviation from the direct FP64
     solve q = S (b + v) of ctx_direct on the same b."""
@@ -390,7 +393,11 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     ctx.potential_vector(xyz[:B], b)
     q = torch.empty_like(b)
     Qe = torch.empty((B, 2), dtype=torch.float64, device=dev)
-    iters, resid = ctx.solve_cg(b, q, Qe, tol=tol)
+    ctx.enable_timing(True)
+    iters, resid = ctx.solve_cg(b, q, Qe, tol=tol)       # builds the preconditioner
+    pc_setup_ms = ctx.timing("pc_blocks")[0] + ctx.timing("pc_coarse_matrix")[0]
+    ctx.enable_timing(False)
+    pc_tiles = int(ctx.info("pc_tiles"))
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(reps):
@@ -401,16 +408,35 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     ctx.solve_cg(b, q, Qe, tol=tol)
     fam = {f: ctx.timing(f) for f in CG_FAMILIES}
     ctx.enable_timing(False)
+    nc, nl, width = int(ctx.info("ncols")), int(ctx.info("nlayers")), int(ctx.info("ell_width"))
+    nb = int(ctx.info("bsr_blocks"))
+    workspace = ctx.info("workspace")
+    ctx.close()
+    # plain CG (no preconditioner) on the same b: iterations only
+    was = os.environ.get("CPM_CG_PRECOND")
+    os.environ["CPM_CG_PRECOND"] = "0"                # read when a context is created
+    try:
+        ctx0 = cpm.Context(cpm.Params.of(w))
+    finally:
+        if was is None:
+            del os.environ["CPM_CG_PRECOND"]
+        else:
+            os.environ["CPM_CG_PRECOND"] = was
+    ctx0.set_electrolyte(w.electrolyte_q)
+    ctx0.build_operator(R, eid, 2)
+    ctx0.set_potential(w.v_electrode)
+    q0 = torch.empty_like(b)
+    plain_iters, _ = ctx0.solve_cg(b, q0, tol=tol)
+    ctx0.close()
     qd = torch.empty_like(b)
     ctx_direct.solve_charges(b, 0x000, qd)
     torch.cuda.synchronize()
     dev_rel = float(((q - qd).abs().max() / qd.abs().max()).item())
-    nc, nl, width = int(ctx.info("ncols")), int(ctx.info("nlayers")), int(ctx.info("ell_width"))
+
     m2 = 2 * ((nc + 31) // 32 * 32)                  # rows of the phase matrix
     nslot = int(sum(-(-c // 64) * 64 for c in np.bincount(
         np.searchsorted(np.unique(w.electrode_xyz[:, 2]), w.electrode_xyz[:, 2]))))
     vec = nslot * 64 * 8                             # one slot-major block of 64 vectors
-    nb = int(ctx.info("bsr_blocks"))
     work = {   # (algorithmic HBM bytes, FP64 flops) per launch
         "cg_plane_sums": (m2 * nslot * 8 + vec + nl * m2 * 64 * 8, 2.0 * m2 * nslot * 64),
         # projection (phase matrix, T, output) + block-sparse real space
@@ -420,6 +446,10 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
         "cg_apply": (3 * vec, 0.0),
         "cg_update": (6 * vec, 0.0),
         "cg_dir": (3 * vec, 0.0),
+        # inverse tile blocks and the coarse inverse, r read twice, z
+        # written, read and written again
+        "cg_precond": ((pc_tiles * 4096 + pc_tiles * pc_tiles) * 8 + 5 * vec,
+                       2.0 * pc_tiles * 64 ** 3 + 2.0 * pc_tiles ** 2 * 64),
     }
     per_iter = {}
     for f, (ms, cnt) in fam.items():
@@ -438,13 +468,14 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     dom = max(per_iter, key=lambda f: per_iter[f]["us"] * per_iter[f]["launches"])
     out = {"solves_per_s": B / call_s, "ms_per_call": call_s * 1e3, "vectors_per_call": B,
            "tol": tol, "iterations": iters, "residual": resid, "operator_setup_s": setup_s,
+           "preconditioner": {"tiles": pc_tiles, "setup_s": pc_setup_ms * 1e-3,
+                              "plain_cg_iterations": plain_iters},
            "ell_width": width, "bsr_blocks": nb, "columns": nc, "planes": nl, "slots": nslot,
            "max_rel_diff_vs_direct_fp64": dev_rel,
            "max_abs_sum_q": float(q.sum(dim=1).abs().max().item()),
            "per_launch": per_iter, "dominant": dom,
-           "workspace_bytes": ctx.info("workspace"),
+           "workspace_bytes": workspace,
            "note": "b computed once outside the timed calls; each call starts from q = 0"}
-    ctx.close()
     return out
 
 

@@ -111,7 +111,9 @@ enum {
   CPM_INFO_ELL_WIDTH = 20,    /* entries per row of the operator's real-space     */
                               /* part (cpm_build_operator)                        */
   CPM_INFO_NCOLS = 21,        /* (k_x, k_y) columns of the matrix-core k set      */
-  CPM_INFO_BSR_BLOCKS = 22    /* 64 x 64 blocks of the operator's real space      */
+  CPM_INFO_BSR_BLOCKS = 22,   /* 64 x 64 blocks of the operator's real space      */
+  CPM_INFO_PC_TILES = 23      /* last cpm_solve_cg: tiles of its preconditioner   */
+                              /*   (0: plain CG)                                  */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -189,7 +191,14 @@ cpm_status cpm_apply_elastance(cpm_ctx* ctx, int batch, const double* d_x, doubl
  * d_b: batch x n (FP64, or FP32 with b_is_f32 = 1); v from
  * cpm_set_potential(_atoms).  Each vector stops when |r| <= tol |r0| (r the
  * projected residual, recursively updated); at most maxit iterations.
- * Vectors run in groups of 64.  Writes d_q (batch x n FP64, the final
+ * Vectors run in groups of 64.  With the operator the iteration is
+ * preconditioned (built on the first solve after cpm_build_operator):
+ * M^-1 = the inverses of A's 64 x 64 diagonal blocks over the operator's
+ * 64-atom plane tiles plus the coarse correction Z (Z^T A Z)^-1 Z^T over the
+ * tile indicators Z; the stopping test stays |r| <= tol |r0| on the
+ * unpreconditioned residual.  Operators with more than 2048 tiles, the
+ * dense A, and the environment setting CPM_CG_PRECOND=0 run plain CG.
+ * Writes d_q (batch x n FP64, the final
  * iterate projected to e^T q = 0) and, unless NULL, d_Qe (batch x n_e
  * electrode totals).  Synchronous (the host checks convergence every 8
  * iterations).  CPM_ENOCONV if some vector ended above the tolerance (the

@@ -46,9 +46,11 @@ constexpr int CG_BLK = 64 * CG_WAVES;
 // per-vector scalars for the host, scal[row * VL + s] (written by block 0)
 enum { S_RR = 0, S_RR0, S_ITERS };
 // block partial fields, red[(blk * CG_RED + f) * VL + s]; r.r alternates
-// between two fields by iteration parity
-enum { F_PAP = 0, F_SAP, F_RR, F_RRB, F_RRI, F_SUM, F_M0 };   // F_M0..F_M0+3: moments
-static_assert(F_M0 + 3 < CG_RED, "partial fields");
+// between two fields by iteration parity, and so does r.z of the
+// preconditioned iteration (F_RZ, F_RZ + 1; producers: the preconditioner's
+// tile blocks)
+enum { F_PAP = 0, F_SAP, F_RR, F_RRB, F_RRI, F_SUM, F_M0, F_RZ = F_M0 + 4, F_RZB, F_ZSUM };
+static_assert(F_ZSUM < CG_RED, "partial fields");
 static_assert(S_ITERS < CG_NSCAL, "scalar rows");
 
 // this wave's rows: r = (blk + t nblk) * CG_WAVES + wave, t = 0, 1, ...
@@ -470,10 +472,13 @@ __global__ void __launch_bounds__(CG_BLK) k_cg_apply(
   store_partials<2>(v, f, red);
 }
 
-// alpha = r.r / p.Ap for vectors above tolerance (else 0: frozen);
-// x += alpha p, r -= alpha (Ap - mean Ap); partials of the new r.r into field
+// alpha = r.z / p.Ap (z = M^-1 r, the preconditioned residual, written by
+// the preconditioner's npc tile blocks; npc = 0: no preconditioner, z = r)
+// for vectors above tolerance (else 0: frozen); x += alpha p,
+// r -= alpha (Ap - mean Ap); partials of the new r.r into field
 // F_RR + (1 - cur).  Block 0 counts the iteration of each active vector.
 __global__ void __launch_bounds__(CG_BLK) k_cg_update(int nslot, int n, int cur, double tol2,
+                                                      int npc,
                                                       const int* __restrict__ slot_atom,
                                                       double* __restrict__ X,
                                                       double* __restrict__ R,
@@ -482,14 +487,20 @@ __global__ void __launch_bounds__(CG_BLK) k_cg_update(int nslot, int n, int cur,
                                                       double* __restrict__ red,
                                                       double* __restrict__ scal) {
   __shared__ double t[4][VL];
+  __shared__ double z[1][VL];
   const int s = threadIdx.x & 63;
   {
     const int f[4] = {F_PAP, F_SAP, F_RR + cur, F_RRI};
     block_totals<4>(red, gridDim.x, f, t);
   }
+  if (npc > 0) {
+    const int f[1] = {F_RZ + cur};
+    block_totals<1>(red, npc, f, z);
+  }
   const double pap = t[0][s], mean = t[1][s] / n, rr = t[2][s], rr0 = t[3][s];
+  const double rz = npc > 0 ? z[0][s] : rr;
   const bool active = rr > tol2 * rr0 && pap > 0.0;
-  const double a = active ? rr / pap : 0.0;
+  const double a = active ? rz / pap : 0.0;
   if (blockIdx.x == 0 && threadIdx.x < VL && active) scal[S_ITERS * VL + s] += 1.0;
   double v[1] = {0.0};
   for (Rows w; w.r < nslot; w.r += w.step) {
@@ -505,34 +516,47 @@ __global__ void __launch_bounds__(CG_BLK) k_cg_update(int nslot, int n, int cur,
   store_partials<1>(v, f, red);
 }
 
-// beta = r'.r' / r.r (0 for frozen vectors); p = r' + beta p; moments of
-// the new p.  Block 0 records r'.r' and r0.r0 for the host.
-__global__ void __launch_bounds__(CG_BLK) k_cg_dir(int nslot, int cur, double tol2,
+// New direction p = z' - mean(z') + beta p, beta = r'.z' / r.z (npc > 0,
+// z' = M^-1 r' in Z from the preconditioner's npc tile blocks) or
+// p = r' + beta p, beta = r'.r' / r.r (npc = 0); beta = 0 for frozen vectors
+// and on the first call (first = 1, which makes p the first direction);
+// moments of the new p.  Block 0 records r'.r' and r0.r0 for the host.
+__global__ void __launch_bounds__(CG_BLK) k_cg_dir(int nslot, int n, int cur, double tol2,
+                                                   int npc, int first,
                                                    const int* __restrict__ slot_atom,
                                                    const double* __restrict__ ex,
                                                    const double* __restrict__ ey,
                                                    const double* __restrict__ ez,
                                                    const double* __restrict__ R,
+                                                   const double* __restrict__ Z,
                                                    double* __restrict__ P, double* __restrict__ red,
                                                    double* __restrict__ scal) {
   __shared__ double t[3][VL];
+  __shared__ double u[3][VL];
   const int s = threadIdx.x & 63;
   {
     const int f[3] = {F_RR + cur, F_RR + (1 - cur), F_RRI};
     block_totals<3>(red, gridDim.x, f, t);
   }
+  if (npc > 0) {
+    const int f[3] = {F_RZ + cur, F_RZ + (1 - cur), F_ZSUM};
+    block_totals<3>(red, npc, f, u);
+  }
   const double rr = t[0][s], rn = t[1][s], rr0 = t[2][s];
-  const double beta = rr > tol2 * rr0 ? rn / rr : 0.0;
+  const bool go = !first && rr > tol2 * rr0;
+  const double beta = !go ? 0.0 : npc > 0 ? u[1][s] / u[0][s] : rn / rr;
+  const double zmean = npc > 0 ? u[2][s] / n : 0.0;
   if (blockIdx.x == 0 && threadIdx.x < VL) {
     scal[S_RR * VL + s] = rn;
     scal[S_RR0 * VL + s] = rr0;
   }
+  const double* src = npc > 0 ? Z : R;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
   for (Rows w; w.r < nslot; w.r += w.step) {
     const int r = w.r, i = slot_atom[r];
     if (i < 0) continue;
     const size_t o = (size_t)r * VL + s;
-    const double p = R[o] + beta * P[o];
+    const double p = (src[o] - zmean) + beta * P[o];
     P[o] = p;
     add_moments(m, p, i, ex, ey, ez);
   }
@@ -674,6 +698,208 @@ __global__ void __launch_bounds__(256) k_cg_totals(int n, const double* __restri
   }
 }
 
+// ---- two-level preconditioner ----------------------------------------------
+// M^-1 r = D_t^-1 r_t on every slot tile t (D_t: A's 64 x 64 diagonal block
+// of the tile's atoms, identity on pad slots) + Z C^-1 Z^T r, Z the tile
+// indicator vectors and C = Z^T A Z.  Both parts are symmetric positive
+// definite, so M^-1 is, and the neutral-subspace iteration stays a CG.
+
+// D_t^-1 for every tile (grid: tiles, 256 threads).  D_t from the operator's
+// own pieces for atoms i, j of the tile (one plane L):
+//   k_e (R_tt(i, j) + sum_c Q_c(L, L) cos(th_i - th_j) + background
+//        + sum_d c_d r_id r_jd) + delta_ij diag_extra_i,
+// R_tt the tile's real-space + self block (diag_blk[t], -1: none), th the
+// in-plane phases of column c; symmetrised, then inverted in LDS by
+// Gauss-Jordan elimination (no pivoting: D_t is positive definite).
+__global__ void __launch_bounds__(256) k_pc_blocks(
+    int nslot, int nlayers, int ncolsort, const int* __restrict__ slot_atom,
+    const int* __restrict__ tile_plane, const int* __restrict__ diag_blk,
+    const double* __restrict__ bval, const double* __restrict__ Ecat,
+    const double2* __restrict__ Q, const double* __restrict__ ex, const double* __restrict__ ey,
+    const double* __restrict__ ez, const double* __restrict__ dextra, double background,
+    double cx, double cy, double cz, double ke, double* __restrict__ Dinv) {
+  __shared__ double D[64][65];
+  __shared__ double cs[16][64], sn[16][64], qd[16];
+  __shared__ double rk[64], fk[64];
+  const int t = blockIdx.x, tid = threadIdx.x, L = tile_plane[t];
+  const int i = tid >> 2, j0 = tid & 3;        // entries (i, j0 + 4 u), u = 0..15
+  const size_t base = (size_t)t * 64;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  for (int c0 = 0; c0 < ncolsort; c0 += 16) {
+    for (int e = tid; e < 16 * 64; e += 256) {
+      const int cc = e >> 6, sl = e & 63, c = c0 + cc;
+      const bool in = c < ncolsort;
+      cs[cc][sl] = in ? Ecat[(size_t)(2 * c) * nslot + base + sl] : 0.0;
+      sn[cc][sl] = in ? Ecat[(size_t)(2 * c + 1) * nslot + base + sl] : 0.0;
+    }
+    if (tid < 16) {
+      const int c = c0 + tid;
+      qd[tid] = c < ncolsort ? Q[((size_t)c * nlayers + L) * nlayers + L].x : 0.0;
+    }
+    __syncthreads();
+    for (int cc = 0; cc < 16; ++cc) {
+      const double ci = qd[cc] * cs[cc][i], si = qd[cc] * sn[cc][i];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc[u] += ci * cs[cc][j0 + 4 * u] + si * sn[cc][j0 + 4 * u];
+    }
+    __syncthreads();
+  }
+  const int ai = slot_atom[base + i], bd = diag_blk[t];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int j = j0 + 4 * u, aj = slot_atom[base + j];
+    double d = i == j ? 1.0 : 0.0;
+    if (ai >= 0 && aj >= 0) {
+      const double rs = bd >= 0 ? bval[(size_t)bd * 4096 + i * 64 + j] : 0.0;
+      d = ke * ((acc[u] + rs) +
+                (background + (cx * ex[ai] * ex[aj] + cy * ey[ai] * ey[aj] + cz * ez[ai] * ez[aj])));
+      if (i == j) d += dextra[ai];
+    }
+    D[i][j] = d;
+  }
+  __syncthreads();
+  double sym[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) sym[u] = 0.5 * (D[i][j0 + 4 * u] + D[j0 + 4 * u][i]);
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 16; ++u) D[i][j0 + 4 * u] = sym[u];
+  __syncthreads();
+  for (int k = 0; k < 64; ++k) {
+    if (tid < 64) {
+      const double piv = D[k][k];
+      rk[tid] = (tid == k ? 1.0 : D[k][tid]) / piv;
+      fk[tid] = tid == k ? 0.0 : D[tid][k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int j = j0 + 4 * u;
+      D[i][j] = i == k ? rk[j] : (j == k ? 0.0 : D[i][j]) - fk[i] * rk[j];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int j = j0 + 4 * u;
+    Dinv[(size_t)t * 4096 + i * 64 + j] = 0.5 * (D[i][j] + D[j][i]);
+  }
+}
+
+// P = the indicator vectors of tiles t0 .. t0 + g - 1 (column s: tile t0 + s)
+// on the CG grid, with the moments of P for the operator
+__global__ void __launch_bounds__(CG_BLK) k_pc_indicator(int nslot, int t0, int g,
+                                                         const int* __restrict__ slot_atom,
+                                                         const double* __restrict__ ex,
+                                                         const double* __restrict__ ey,
+                                                         const double* __restrict__ ez,
+                                                         double* __restrict__ P,
+                                                         double* __restrict__ red) {
+  const int s = threadIdx.x & 63;
+  double m[4] = {0.0, 0.0, 0.0, 0.0};
+  for (Rows w; w.r < nslot; w.r += w.step) {
+    const int r = w.r, i = slot_atom[r];
+    const double p = (i >= 0 && s < g && (r >> 6) == t0 + s) ? 1.0 : 0.0;
+    P[(size_t)r * VL + s] = p;
+    if (i >= 0) add_moments(m, p, i, ex, ey, ez);
+  }
+  store_moments(m, red);
+}
+
+// sums over the 64 rows of tile blockIdx.x of V (256 threads; fixed order:
+// wave w adds rows w, w + 4, ..., then the 4 waves in order); thread s < 64
+// gets the sum of vector s
+__device__ inline double tile_sum(const double* __restrict__ V, double (*sh)[VL]) {
+  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const size_t base = (size_t)blockIdx.x * 64;
+  double a = 0.0;
+  for (int r = w; r < 64; r += 4) a += V[(base + r) * VL + s];
+  sh[w][s] = a;
+  __syncthreads();
+  return (sh[0][s] + sh[1][s]) + (sh[2][s] + sh[3][s]);
+}
+
+// C[t T + t0 + s] = sum over tile t of V's vector s (s < g): rows of Z^T A Z
+// from V = A (indicators of tiles t0 ..)
+__global__ void __launch_bounds__(256) k_pc_coarse_cols(int T, int t0, int g,
+                                                        const double* __restrict__ V,
+                                                        double* __restrict__ C) {
+  __shared__ double sh[4][VL];
+  const double a = tile_sum(V, sh);
+  const int s = threadIdx.x;
+  if (s < g) C[(size_t)blockIdx.x * T + t0 + s] = a;
+}
+
+// B = (C + C^T) / 2
+__global__ void k_pc_sym(int T, const double* __restrict__ C, double* __restrict__ B) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)T * T) return;
+  const int i = (int)(e / T), j = (int)(e % T);
+  B[e] = 0.5 * (C[e] + C[(size_t)j * T + i]);
+}
+
+// one Gauss-Jordan step (pivot k, no pivoting: C is positive definite) from
+// A into B; T steps turn C into C^-1
+__global__ void k_pc_gj_step(int T, int k, const double* __restrict__ A, double* __restrict__ B) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)T * T) return;
+  const int i = (int)(e / T), j = (int)(e % T);
+  const double rkj = (j == k ? 1.0 : A[(size_t)k * T + j]) / A[(size_t)k * T + k];
+  B[e] = i == k ? rkj : (j == k ? 0.0 : A[e]) - A[(size_t)i * T + k] * rkj;
+}
+
+// Local part, per tile (grid: tiles, 256 threads): Z_t = D_t^-1 R_t on the
+// matrix cores, and the tile sums Z^T R
+__global__ void __launch_bounds__(256) k_pc_local(const double* __restrict__ Dinv,
+                                                  const double* __restrict__ R,
+                                                  double* __restrict__ Z,
+                                                  double* __restrict__ ZtR) {
+  __shared__ double As[16][68];
+  __shared__ double Bs[16][68];
+  __shared__ double sh[4][VL];
+  const size_t t = blockIdx.x;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  seg_mfma<false>(acc, Dinv + t * 4096, 64, R + t * 64 * VL, 64, As, Bs);
+  store_tile(acc, Z + t * 64 * VL);
+  const double a = tile_sum(R, sh);
+  if (threadIdx.x < VL) ZtR[t * VL + threadIdx.x] = a;
+}
+
+// Coarse part and the sums the direction needs, per tile (grid: tiles,
+// CG_WAVES waves): Z_t += (C^-1 Z^T R)_t on real slots (pads 0); block
+// partials of r.z into field fnew and of sum z into F_ZSUM.
+__global__ void __launch_bounds__(CG_BLK) k_pc_coarse(int T, int fnew,
+                                                      const int* __restrict__ slot_atom,
+                                                      const double* __restrict__ Cinv,
+                                                      const double* __restrict__ ZtR,
+                                                      const double* __restrict__ R,
+                                                      double* __restrict__ Z,
+                                                      double* __restrict__ red) {
+  __shared__ double sh[CG_WAVES][VL];
+  __shared__ double cc[VL];
+  const int t = blockIdx.x, s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a = 0.0;
+  for (int u = w; u < T; u += CG_WAVES) a += Cinv[(size_t)t * T + u] * ZtR[(size_t)u * VL + s];
+  sh[w][s] = a;
+  __syncthreads();
+  if (threadIdx.x < VL) cc[s] = sum16(sh, s);
+  __syncthreads();
+  double v[2] = {0.0, 0.0};
+  for (int r = t * 64 + w; r < t * 64 + 64; r += CG_WAVES) {
+    const size_t o = (size_t)r * VL + s;
+    const double z = slot_atom[r] >= 0 ? Z[o] + cc[s] : 0.0;
+    Z[o] = z;
+    v[0] += R[o] * z;
+    v[1] += z;
+  }
+  const int f[2] = {fnew, F_ZSUM};
+  store_partials<2>(v, f, red);
+}
+
 }  // namespace
 
 int cg_blocks(int nslot, int cap) { return std::max(1, std::min(cap, nslot / CG_WAVES)); }
@@ -745,17 +971,18 @@ void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, con
                        cdip[2], ke, P, AP, red);
 }
 
-void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2,
+void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2, int npc,
                       const int* slot_atom, double* X, double* R, const double* P,
                       const double* AP, double* red, double* scal) {
-  hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, cur, tol2, slot_atom,
-                     X, R, P, AP, red, scal);
+  hipLaunchKernelGGL(k_cg_update, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, cur, tol2, npc,
+                     slot_atom, X, R, P, AP, red, scal);
 }
 
-void launch_cg_dir(hipStream_t st, int nblk, int nslot, int cur, double tol2, const int* slot_atom,
-                   const Buffers& b, const double* R, double* P, double* red, double* scal) {
-  hipLaunchKernelGGL(k_cg_dir, dim3(nblk), dim3(CG_BLK), 0, st, nslot, cur, tol2, slot_atom, b.ex,
-                     b.ey, b.ez, R, P, red, scal);
+void launch_cg_dir(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2, int npc,
+                   int first, const int* slot_atom, const Buffers& b, const double* R,
+                   const double* Z, double* P, double* red, double* scal) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, cur, tol2, npc, first,
+                     slot_atom, b.ex, b.ey, b.ez, R, Z, P, red, scal);
 }
 
 void launch_cg_init(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
@@ -786,6 +1013,46 @@ void launch_cg_finish(hipStream_t st, int nblk, int nslot, int n, int g, const i
   hipLaunchKernelGGL(k_cg_scatter, dim3(nblk), dim3(CG_BLK), 0, st, nslot, n, g, 1, slot_atom, X,
                      red, q);
   if (Qe) hipLaunchKernelGGL(k_cg_totals, dim3(g), dim3(256), 0, st, n, q, eid, n_e, Qe);
+}
+
+void launch_pc_blocks(hipStream_t st, int ntile, int nslot, int nlayers, int ncolsort,
+                      const int* slot_atom, const int* tile_plane, const int* diag_blk,
+                      const double* bval, const double* Ecat, const double2* Q, const Buffers& b,
+                      double background, const double* cdip, double ke, double* Dinv) {
+  hipLaunchKernelGGL(k_pc_blocks, dim3(ntile), dim3(256), 0, st, nslot, nlayers, ncolsort,
+                     slot_atom, tile_plane, diag_blk, bval, Ecat, Q, b.ex, b.ey, b.ez, b.dextra,
+                     background, cdip[0], cdip[1], cdip[2], ke, Dinv);
+}
+
+void launch_pc_indicator(hipStream_t st, int nblk, int nslot, int t0, int g, const int* slot_atom,
+                         const Buffers& b, double* P, double* red) {
+  hipLaunchKernelGGL(k_pc_indicator, dim3(nblk), dim3(CG_BLK), 0, st, nslot, t0, g, slot_atom,
+                     b.ex, b.ey, b.ez, P, red);
+}
+
+void launch_pc_coarse_cols(hipStream_t st, int ntile, int t0, int g, const double* V, double* C) {
+  hipLaunchKernelGGL(k_pc_coarse_cols, dim3(ntile), dim3(256), 0, st, ntile, t0, g, V, C);
+}
+
+double* launch_pc_invert(hipStream_t st, int ntile, double* C, double* W) {
+  const size_t tot = (size_t)ntile * ntile;
+  const dim3 grid((unsigned)((tot + 255) / 256));
+  hipLaunchKernelGGL(k_pc_sym, grid, dim3(256), 0, st, ntile, C, W);
+  double* a = W;
+  double* o = C;
+  for (int k = 0; k < ntile; ++k) {
+    hipLaunchKernelGGL(k_pc_gj_step, grid, dim3(256), 0, st, ntile, k, a, o);
+    std::swap(a, o);
+  }
+  return a;
+}
+
+void launch_pc_apply(hipStream_t st, int ntile, int parity, const int* slot_atom,
+                     const double* Dinv, const double* Cinv, const double* R, double* Z,
+                     double* ZtR, double* red) {
+  hipLaunchKernelGGL(k_pc_local, dim3(ntile), dim3(256), 0, st, Dinv, R, Z, ZtR);
+  hipLaunchKernelGGL(k_pc_coarse, dim3(ntile), dim3(CG_BLK), 0, st, ntile, F_RZ + parity,
+                     slot_atom, Cinv, ZtR, R, Z, red);
 }
 
 }  // namespace cpm

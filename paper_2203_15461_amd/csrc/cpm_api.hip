@@ -284,7 +284,9 @@ cpm_status ensure_cg_buffers(cpm_ctx* c) {
   }
   TRY(dalloc(c, &b.cgv, (size_t)4 * CG_MAXG * nslot));
   HIP_TRY(c, hipMemset(b.cgv, 0, (size_t)4 * CG_MAXG * nslot * sizeof(double)));
-  TRY(dalloc(c, &b.cgred, (size_t)cg_grid(c) * CG_RED * CG_MAXG));
+  // partials of the vector kernels' blocks and of the preconditioner's tiles
+  const int nred = std::max(cg_grid(c), c->have_op ? nslot / 64 : 0);
+  TRY(dalloc(c, &b.cgred, (size_t)nred * CG_RED * CG_MAXG));
   TRY(dalloc(c, &b.cgscal, (size_t)CG_NSCAL * CG_MAXG));
   HIP_TRY(c, hipMemset(b.cgscal, 0, (size_t)CG_NSCAL * CG_MAXG * sizeof(double)));
   if (c->have_op) {
@@ -295,6 +297,54 @@ cpm_status ensure_cg_buffers(cpm_ctx* c) {
     TRY(dalloc(c, &b.cgY, (size_t)c->cg_ksplit * c->nlayers * 2 * c->ncp * CG_MAXG));
     TRY(dalloc(c, &b.cgT, (size_t)c->nlayers * 2 * c->ncp * CG_MAXG));
   }
+  return CPM_OK;
+}
+
+// The two-level preconditioner of the operator's CG, built on first use:
+// inverse diagonal tile blocks, and the coarse matrix Z^T A Z from A applied
+// to the tile indicators (CG_MAXG tiles per application), inverted in place.
+// Operators with more than PC_MAX_TILES tiles run without it.
+constexpr int PC_MAX_TILES = 2048;
+
+cpm_status ensure_precond(cpm_ctx* c) {
+  if (c->pc_ready) return CPM_OK;
+  c->pc_tiles = 0;
+  const int nslot = c->nmap, T = nslot / 64;
+  if (!c->have_op || !c->cg_precond || T > PC_MAX_TILES) return CPM_OK;
+  Buffers& b = c->b;
+  hipStream_t st = c->stream;
+  TRY(dalloc(c, &b.pc_dinv, (size_t)T * 4096));
+  TRY(dalloc(c, &b.pc_C, (size_t)T * T));
+  TRY(dalloc(c, &b.pc_W, (size_t)T * T));
+  TRY(dalloc(c, &b.pc_ztr, (size_t)T * CG_MAXG));
+  TRY(dalloc(c, &b.pc_tplane, (size_t)T));
+  TRY(dalloc(c, &b.pc_dblk, (size_t)T));
+  if ((int)c->h_tile_plane.size() != T || (int)c->h_bdiag.size() != T)
+    return fail(c, CPM_ESTATE, "operator tiles (%zu planes, %zu blocks) do not match %d slots",
+                c->h_tile_plane.size(), c->h_bdiag.size(), nslot);
+  HIP_TRY(c, hipMemcpyAsync(b.pc_tplane, c->h_tile_plane.data(), T * sizeof(int),
+                            hipMemcpyHostToDevice, st));
+  HIP_TRY(c, hipMemcpyAsync(b.pc_dblk, c->h_bdiag.data(), T * sizeof(int), hipMemcpyHostToDevice,
+                            st));
+  { Timed t(c, "pc_blocks");
+    launch_pc_blocks(st, T, nslot, c->nlayers, c->ncolsort, b.amap, b.pc_tplane, b.pc_dblk,
+                     b.bsr_val, b.Ecat, b.Qpair, b, c->op_background, c->cdip, c->ke, b.pc_dinv); }
+  TRY(launched(c, "preconditioner blocks"));
+  double* P = b.cgv + (size_t)2 * CG_MAXG * nslot;
+  double* AP = P + (size_t)CG_MAXG * nslot;
+  const int nb = cg_grid(c);
+  { Timed t(c, "pc_coarse_matrix");
+    for (int t0 = 0; t0 < T; t0 += CG_MAXG) {
+      const int g = std::min(CG_MAXG, T - t0);
+      launch_pc_indicator(st, nb, nslot, t0, g, b.amap, b, P, b.cgred);
+      apply_A(c, P, AP, false);
+      launch_pc_coarse_cols(st, T, t0, g, AP, b.pc_C);
+    }
+    c->pc_Cinv = launch_pc_invert(st, T, b.pc_C, b.pc_W); }
+  TRY(launched(c, "preconditioner coarse matrix"));
+  HIP_TRY(c, hipStreamSynchronize(st));
+  c->pc_tiles = T;
+  c->pc_ready = true;
   return CPM_OK;
 }
 
@@ -507,6 +557,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_CG_PRECOND")) c->cg_precond = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_CHOL_BLOCK"))
     c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
@@ -726,7 +777,22 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
     return fail(c, CPM_EINVAL, "rebuild changes the electrode plane structure; create a new context");
   if (!dense && !(nlayers > 0 && c->sf_mfma))
     return fail(c, CPM_EUNSUPPORTED, "the matrix-free operator needs electrodes on z planes");
+  Buffers& b0 = c->b;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));   // queued work may still use what is freed
   c->have_A = c->have_op = c->have_inv = c->have_v = c->have_q = false;
+  // the CG work arrays, the preconditioner and the b-path work arrays follow
+  // the sizes of the atom map and of the operator (slots, chunks, work
+  // parts): a rebuild allocates them afresh
+  dfree(c, b0.sf_part); dfree(c, b0.sfm_part); dfree(c, b0.sft); dfree(c, b0.sfw);
+  dfree(c, b0.phik_part); dfree(c, b0.phir_part); dfree(c, b0.dip); dfree(c, b0.rtab);
+  dfree(c, b0.zperm); dfree(c, b0.cq); dfree(c, b0.zr);
+  dfree(c, b0.cg_ident); dfree(c, b0.cgv); dfree(c, b0.cgred); dfree(c, b0.cgscal);
+  dfree(c, b0.cgphi); dfree(c, b0.cgY); dfree(c, b0.cgT);
+  dfree(c, b0.pc_dinv); dfree(c, b0.pc_C); dfree(c, b0.pc_W); dfree(c, b0.pc_ztr);
+  dfree(c, b0.pc_tplane); dfree(c, b0.pc_dblk);
+  c->pc_ready = false;
+  c->pc_tiles = 0;
+  c->pc_Cinv = nullptr;
   c->nlayers = nlayers;
   c->n = n;
   c->n_e = n_e;
@@ -913,6 +979,10 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
         for (int J : js) pos[J] = -1;
         bptr[I + 1] = (int)bcol.size();
       }
+      c->h_bdiag.assign(T, -1);
+      for (int I = 0; I < T; ++I)
+        for (int q = bptr[I]; q < bptr[I + 1]; ++q)
+          if (bcol[q] == I) c->h_bdiag[I] = q;
       c->bsr_blocks = (int)bcol.size();
       dfree(c, b.bsr_col);
       dfree(c, b.bsr_val);
@@ -1754,9 +1824,11 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
   c->cg_resid = 0.0;
   if (batch == 0) return CPM_OK;
   TRY(ensure_cg_buffers(c));
+  TRY(ensure_precond(c));
   Buffers& b = c->b;
   hipStream_t st = c->stream;
   const int n = c->n, nslot = cg_nslot(c), nb = cg_grid(c);
+  const int npc = c->pc_tiles;            // 0: plain CG
   const int* slots = cg_slots(c);
   double* X = b.cgv;
   double* R = X + (size_t)CG_MAXG * nslot;
@@ -1771,7 +1843,11 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
     const int g = std::min(CG_MAXG, batch - v0);
     const void* bsrc = static_cast<const char*>(d_b) + (size_t)v0 * n * bsz;
     { Timed t(c, "cg_init");
-      launch_cg_init(st, nb, nslot, n, g, slots, b, bsrc, b_is_f32, X, R, P, b.cgred, b.cgscal); }
+      launch_cg_init(st, nb, nslot, n, g, slots, b, bsrc, b_is_f32, X, R, P, b.cgred, b.cgscal);
+      if (npc > 0) {       // p = z - mean z, z = M^-1 r0 (r.z into the parity-0 field)
+        launch_pc_apply(st, npc, 0, slots, b.pc_dinv, c->pc_Cinv, R, AP, b.pc_ztr, b.cgred);
+        launch_cg_dir(st, nb, nslot, n, 1, tol2, npc, 1, slots, b, R, AP, P, b.cgred, b.cgscal);
+      } }
     TRY(launched(c, "cg init"));
     int it = 0;
     bool conv = false;
@@ -1783,9 +1859,16 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
         const int cur = it & 1;
         apply_A(c, P, AP, true);
         { Timed t(c, "cg_update");
-          launch_cg_update(st, nb, nslot, n, cur, tol2, slots, X, R, P, AP, b.cgred, b.cgscal); }
+          launch_cg_update(st, nb, nslot, n, cur, tol2, npc, slots, X, R, P, AP, b.cgred,
+                           b.cgscal); }
+        if (npc > 0) {     // z = M^-1 r into AP (free until the next product)
+          Timed t(c, "cg_precond");
+          launch_pc_apply(st, npc, 1 - cur, slots, b.pc_dinv, c->pc_Cinv, R, AP, b.pc_ztr,
+                          b.cgred);
+        }
         { Timed t(c, "cg_dir");
-          launch_cg_dir(st, nb, nslot, cur, tol2, slots, b, R, P, b.cgred, b.cgscal); }
+          launch_cg_dir(st, nb, nslot, n, cur, tol2, npc, 0, slots, b, R, AP, P, b.cgred,
+                        b.cgscal); }
       }
       TRY(launched(c, "cg iterations"));
       HIP_TRY(c, hipMemcpyAsync(h_scal.data(), b.cgscal, h_scal.size() * sizeof(double),
@@ -1877,6 +1960,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_ELL_WIDTH: *out = c->ell_width; return CPM_OK;
     case CPM_INFO_NCOLS: *out = c->ncolsort; return CPM_OK;
     case CPM_INFO_BSR_BLOCKS: *out = c->bsr_blocks; return CPM_OK;
+    case CPM_INFO_PC_TILES: *out = c->pc_tiles; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -1919,6 +2003,8 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.bsr_col); dfree(b.bsr_val); dfree(b.cg_items); dfree(b.asmG); dfree(b.asmF);
   dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);
   dfree(b.cgscal); dfree(b.cgphi); dfree(b.cgY); dfree(b.cgT);
+  dfree(b.pc_dinv); dfree(b.pc_C); dfree(b.pc_W); dfree(b.pc_ztr); dfree(b.pc_tplane);
+  dfree(b.pc_dblk);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

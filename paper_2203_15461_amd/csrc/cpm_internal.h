@@ -46,7 +46,7 @@ constexpr int RS_NT = 2048;        // intervals of the real-space pair table on 
 constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
 constexpr int MAX_LAYERS = 64;     // planar-electrode factorisation up to this many z planes
 constexpr int CG_MAXG = 64;        // vectors per conjugate-gradient group (slot-row width)
-constexpr int CG_RED = 10;         // block partial fields
+constexpr int CG_RED = 13;         // block partial fields
 constexpr int CG_NSCAL = 4;        // per-vector scalar rows reported to the host
 
 struct Buffers {
@@ -131,6 +131,12 @@ struct Buffers {
   double* cgphi = nullptr;         // k- and real-space potentials (nparts x nslot x CG_MAXG)
   double* cgY = nullptr;           // plane sums (ksplit x nlayers x 2 ncp x CG_MAXG)
   double* cgT = nullptr;           // plane-mixed sums (same shape)
+  double* pc_dinv = nullptr;       // preconditioner: inverse tile blocks (ntile x 64 x 64)
+  double* pc_C = nullptr;          // coarse matrix and its inverse, two ntile x ntile buffers
+  double* pc_W = nullptr;
+  double* pc_ztr = nullptr;        // tile sums of r (ntile x CG_MAXG)
+  int* pc_tplane = nullptr;        // plane of each tile
+  int* pc_dblk = nullptr;          // real-space block of each tile's diagonal (-1: none)
   size_t kpart_len = 0;
   int bpad_rows = 0;
   double* scal = nullptr;          // small scalars (s and friends)
@@ -165,12 +171,33 @@ void launch_cg_tiles(hipStream_t st, int nitems, int nslot, int ncp, const int* 
 void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, const int* slot_atom,
                      const Buffers& b, int nparts, const double* Phi, double background,
                      const double* cdip, double ke, const double* P, double* AP, double* red);
-// x, r update (cur: parity of the iteration), then p and its moments
-void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2,
+// x, r update (cur: parity of the iteration; npc > 0: step length from the
+// r.z partials of the preconditioner's npc tile blocks), then p and its
+// moments (p = z - mean z + beta p with Z = M^-1 r when npc > 0; first: the
+// first direction, beta = 0)
+void launch_cg_update(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2, int npc,
                       const int* slot_atom, double* X, double* R, const double* P,
                       const double* AP, double* red, double* scal);
-void launch_cg_dir(hipStream_t st, int nblk, int nslot, int cur, double tol2, const int* slot_atom,
-                   const Buffers& b, const double* R, double* P, double* red, double* scal);
+void launch_cg_dir(hipStream_t st, int nblk, int nslot, int n, int cur, double tol2, int npc,
+                   int first, const int* slot_atom, const Buffers& b, const double* R,
+                   const double* Z, double* P, double* red, double* scal);
+// two-level preconditioner over the ntile slot tiles: inverses of A's
+// 64 x 64 diagonal tile blocks (from the operator's pieces); the coarse
+// matrix C = Z^T A Z (Z: tile indicators) column block by column block from
+// A applied to indicator vectors; C^-1 by Gauss-Jordan steps (C and W both
+// ntile x ntile; returns the one holding C^-1); and per iteration
+// Z = M^-1 R with partials of r.z (field of parity `parity`) and of sum z
+void launch_pc_blocks(hipStream_t st, int ntile, int nslot, int nlayers, int ncolsort,
+                      const int* slot_atom, const int* tile_plane, const int* diag_blk,
+                      const double* bval, const double* Ecat, const double2* Q, const Buffers& b,
+                      double background, const double* cdip, double ke, double* Dinv);
+void launch_pc_indicator(hipStream_t st, int nblk, int nslot, int t0, int g, const int* slot_atom,
+                         const Buffers& b, double* P, double* red);
+void launch_pc_coarse_cols(hipStream_t st, int ntile, int t0, int g, const double* V, double* C);
+double* launch_pc_invert(hipStream_t st, int ntile, double* C, double* W);
+void launch_pc_apply(hipStream_t st, int ntile, int parity, const int* slot_atom,
+                     const double* Dinv, const double* Cinv, const double* R, double* Z,
+                     double* ZtR, double* red);
 void launch_cg_init(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
                     const Buffers& b, const void* bsrc, int b_is_f32, double* X, double* R,
                     double* P, double* red, double* scal);
@@ -219,6 +246,11 @@ struct cpm_ctx {
   int sfm_max_chunk = 4096;        // most charges per matrix-core chunk
   int chol_block = 256;            // columns per outer block of the Cholesky / inverse
   int cg_cap = 0;                  // most workgroups of the CG vector kernels (0: by size)
+  int cg_precond = 1;              // two-level preconditioner for the operator's CG (0: none)
+  int pc_tiles = 0;                // tiles of the preconditioner in use (0: none or not built)
+  bool pc_ready = false;           // preconditioner built for the current operator
+  const double* pc_Cinv = nullptr; // whichever of pc_C / pc_W holds the coarse inverse
+  std::vector<int> h_bdiag;        // real-space block of each tile's diagonal (-1: none)
   int rs_wg_target = 512;          // real-space workgroups per launch group
   int rs_sort_min = 16;            // batches of at least this size sort the charges by z
   unsigned store = 0;

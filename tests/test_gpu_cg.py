@@ -280,3 +280,70 @@ def test_cg_wire_tubes(cpm):
     assert rel(q.cpu().numpy()[0], qo) < 1e-10
     assert abs(q.cpu().numpy().sum()) <= 1e-12
     ctx.close()
+
+
+def test_cg_preconditioner_2880(cpm, monkeypatch):
+    """The two-level preconditioner (inverse 64 x 64 diagonal tile blocks plus
+    the coarse space of tile constants) changes the iterates, not the
+    solution: with and without it the charges of the 2880-atom capacitor
+    match the stored oracle charges, and it takes fewer iterations."""
+    if not os.path.exists(GOLDEN):
+        pytest.skip("golden file missing: run tests/golden/make_golden.py")
+    g = dict(np.load(GOLDEN))
+    w = I.graphite_capacitor()
+    snaps = [int(s) for s in g["snapshots"]]
+    iters = {}
+    for pc in ("0", "1"):
+        monkeypatch.setenv("CPM_CG_PRECOND", pc)
+        say(f"cg graphite_capacitor_2880, preconditioner {pc}")
+        ctx = cpm.setup(w, matrix_free=True)
+        b = _b(ctx, w, snaps)
+        q = torch.empty_like(b)
+        Qe = torch.empty((len(snaps), 2), dtype=torch.float64, device="cuda")
+        iters[pc], res = ctx.solve_cg(b, q, Qe, tol=1e-13)
+        tiles = ctx.info("pc_tiles")
+        say(f"  iterations {iters[pc]}, residual {res:.2e}, tiles {tiles:.0f}")
+        assert res <= 1e-13
+        assert (tiles > 0) == (pc == "1")
+        assert rel(q.cpu().numpy(), g["q"]) < 1e-10
+        assert rel(Qe.cpu().numpy(), g["Q"]) < 1e-10
+        assert np.abs(q.cpu().numpy().sum(axis=1)).max() <= 1e-12
+        ctx.close()
+    assert iters["1"] < iters["0"]
+
+
+def test_operator_rebuild_with_other_plane_sizes(cpm):
+    """A rebuild of the operator with the same n and number of planes but
+    other atoms per plane (20 atoms of the lower layer moved, shifted off the
+    upper layer's sites, into the upper plane: 124 + 164 atoms, so the atom
+    map shrinks from 6 to 5 tiles) sizes the CG work, the preconditioner and
+    the b-path work anew; b and the CG charges match the oracle for the new
+    electrodes."""
+    w = I.small_capacitor("a")
+    say("operator rebuild with other plane sizes")
+    ctx = cpm.setup(w, matrix_free=True)
+    b = _b(ctx, w, [0, 1])
+    q = torch.empty_like(b)
+    ctx.solve_cg(b, q, tol=1e-13)
+    tiles0 = ctx.info("pc_tiles")
+    R = w.electrode_xyz.copy()
+    low = np.where(R[:, 2] == R[:, 2].min())[0][:20]
+    R[low] += np.array([0.31, 0.43, 30.0])
+    ctx.build_operator(_dev(R), _dev(w.electrode_id, torch.int32), 2)
+    ctx.set_potential(w.v_electrode)
+    xyz = _dev(np.stack([I.snapshot(w, s) for s in (0, 1)]))
+    b2 = torch.empty_like(b)
+    ctx.potential_vector(xyz, b2)
+    iters, res = ctx.solve_cg(b2, q, tol=1e-13)
+    say(f"  tiles {tiles0:.0f} -> {ctx.info('pc_tiles'):.0f}, iterations {iters}")
+    assert tiles0 == 6 and ctx.info("pc_tiles") == 5
+    p = O.params_for(w)
+    A = O.elastance(R, p)
+    S = O.capacitance(A).S
+    v = O.applied_potential(w.electrode_id, w.v_electrode)
+    bo = np.array([O.potential_vector(R, I.snapshot(w, s), w.electrolyte_q, p) for s in (0, 1)])
+    assert rel(b2.cpu().numpy(), bo) < 1e-10
+    qo = np.array([O.charges(S, x, v) for x in bo])
+    assert rel(q.cpu().numpy(), qo) < 1e-10
+    assert np.abs(q.cpu().numpy().sum(axis=1)).max() <= 1e-12
+    ctx.close()
