@@ -395,9 +395,9 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     Qe = torch.empty((B, 2), dtype=torch.float64, device=dev)
     ctx.enable_timing(True)
     iters, resid = ctx.solve_cg(b, q, Qe, tol=tol)       # builds the preconditioner
-    pc_setup_ms = ctx.timing("pc_blocks")[0] + ctx.timing("pc_coarse_matrix")[0]
+    pc_setup_ms = sum(ctx.timing(f)[0] for f in ("pc_blocks", "pc_coarse_matrix", "pc_balancing"))
     ctx.enable_timing(False)
-    pc_tiles = int(ctx.info("pc_tiles"))
+    pc_tiles, pc_mode = int(ctx.info("pc_tiles")), int(ctx.info("pc_mode"))
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(reps):
@@ -437,6 +437,17 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     nslot = int(sum(-(-c // 64) * 64 for c in np.bincount(
         np.searchsorted(np.unique(w.electrode_xyz[:, 2]), w.electrode_xyz[:, 2]))))
     vec = nslot * 64 * 8                             # one slot-major block of 64 vectors
+    ld = -(-pc_tiles // 64) * 64                     # coarse row stride
+    if pc_mode == 2:
+        # balancing form: inverse tile blocks, DAZ (slots x ld) twice, the
+        # two ld x ld coarse matrices; r read three times, z written
+        pc_work = ((pc_tiles * 4096 + 2 * nslot * ld + 2 * ld * ld) * 8 + 4 * vec,
+                   2.0 * pc_tiles * 64 ** 3 + 2 * 2.0 * nslot * ld * 64 + 3 * 2.0 * ld * ld * 64)
+    else:
+        # additive form: inverse tile blocks and the coarse inverse, r read
+        # twice, z written, read and written again
+        pc_work = ((pc_tiles * 4096 + pc_tiles * pc_tiles) * 8 + 5 * vec,
+                   2.0 * pc_tiles * 64 ** 3 + 2.0 * pc_tiles ** 2 * 64)
     work = {   # (algorithmic HBM bytes, FP64 flops) per launch
         "cg_plane_sums": (m2 * nslot * 8 + vec + nl * m2 * 64 * 8, 2.0 * m2 * nslot * 64),
         # projection (phase matrix, T, output) + block-sparse real space
@@ -446,10 +457,7 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
         "cg_apply": (3 * vec, 0.0),
         "cg_update": (6 * vec, 0.0),
         "cg_dir": (3 * vec, 0.0),
-        # inverse tile blocks and the coarse inverse, r read twice, z
-        # written, read and written again
-        "cg_precond": ((pc_tiles * 4096 + pc_tiles * pc_tiles) * 8 + 5 * vec,
-                       2.0 * pc_tiles * 64 ** 3 + 2.0 * pc_tiles ** 2 * 64),
+        "cg_precond": pc_work,
     }
     per_iter = {}
     for f, (ms, cnt) in fam.items():
@@ -468,7 +476,8 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     dom = max(per_iter, key=lambda f: per_iter[f]["us"] * per_iter[f]["launches"])
     out = {"solves_per_s": B / call_s, "ms_per_call": call_s * 1e3, "vectors_per_call": B,
            "tol": tol, "iterations": iters, "residual": resid, "operator_setup_s": setup_s,
-           "preconditioner": {"tiles": pc_tiles, "setup_s": pc_setup_ms * 1e-3,
+           "preconditioner": {"form": {0: "none", 1: "additive", 2: "balancing"}[pc_mode],
+                              "tiles": pc_tiles, "setup_s": pc_setup_ms * 1e-3,
                               "plain_cg_iterations": plain_iters},
            "ell_width": width, "bsr_blocks": nb, "columns": nc, "planes": nl, "slots": nslot,
            "max_rel_diff_vs_direct_fp64": dev_rel,

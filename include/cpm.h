@@ -112,8 +112,9 @@ enum {
                               /* part (cpm_build_operator)                        */
   CPM_INFO_NCOLS = 21,        /* (k_x, k_y) columns of the matrix-core k set      */
   CPM_INFO_BSR_BLOCKS = 22,   /* 64 x 64 blocks of the operator's real space      */
-  CPM_INFO_PC_TILES = 23      /* last cpm_solve_cg: tiles of its preconditioner   */
+  CPM_INFO_PC_TILES = 23,     /* last cpm_solve_cg: tiles of its preconditioner   */
                               /*   (0: plain CG)                                  */
+  CPM_INFO_PC_MODE = 24       /*   ... its form: 0 none, 1 additive, 2 balancing  */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -192,12 +193,14 @@ cpm_status cpm_apply_elastance(cpm_ctx* ctx, int batch, const double* d_x, doubl
  * cpm_set_potential(_atoms).  Each vector stops when |r| <= tol |r0| (r the
  * projected residual, recursively updated); at most maxit iterations.
  * Vectors run in groups of 64.  With the operator the iteration is
- * preconditioned (built on the first solve after cpm_build_operator):
- * M^-1 = the inverses of A's 64 x 64 diagonal blocks over the operator's
- * 64-atom plane tiles plus the coarse correction Z (Z^T A Z)^-1 Z^T over the
- * tile indicators Z; the stopping test stays |r| <= tol |r0| on the
- * unpreconditioned residual.  Operators with more than 2048 tiles, the
- * dense A, and the environment setting CPM_CG_PRECOND=0 run plain CG.
+ * preconditioned (built on the first solve after cpm_build_operator) by a
+ * two-level method over the operator's 64-atom plane tiles: the smoother
+ * B = the inverses of A's 64 x 64 diagonal tile blocks, the coarse space Z =
+ * the tile indicators, Q = Z (Z^T A Z)^-1 Z^T, in the balancing form
+ * M^-1 = Q + (I - Q A) B (I - A Q) (default) or the additive form
+ * M^-1 = B + Q (environment CPM_CG_PRECOND=1; 0: none).  The stopping test
+ * stays |r| <= tol |r0| on the unpreconditioned residual.  Operators with
+ * more than 2048 tiles and the dense A run plain CG.
  * Writes d_q (batch x n FP64, the final
  * iterate projected to e^T q = 0) and, unless NULL, d_Qe (batch x n_e
  * electrode totals).  Synchronous (the host checks convergence every 8

@@ -821,33 +821,35 @@ __device__ inline double tile_sum(const double* __restrict__ V, double (*sh)[VL]
   return (sh[0][s] + sh[1][s]) + (sh[2][s] + sh[3][s]);
 }
 
-// C[t T + t0 + s] = sum over tile t of V's vector s (s < g): rows of Z^T A Z
-// from V = A (indicators of tiles t0 ..)
-__global__ void __launch_bounds__(256) k_pc_coarse_cols(int T, int t0, int g,
+// C[t ld + t0 + s] = sum over tile t of V's vector s (s < g): rows of
+// Z^T A Z from V = A (indicators of tiles t0 ..)
+__global__ void __launch_bounds__(256) k_pc_coarse_cols(int ld, int t0, int g,
                                                         const double* __restrict__ V,
                                                         double* __restrict__ C) {
   __shared__ double sh[4][VL];
   const double a = tile_sum(V, sh);
   const int s = threadIdx.x;
-  if (s < g) C[(size_t)blockIdx.x * T + t0 + s] = a;
+  if (s < g) C[(size_t)blockIdx.x * ld + t0 + s] = a;
 }
 
-// B = (C + C^T) / 2
-__global__ void k_pc_sym(int T, const double* __restrict__ C, double* __restrict__ B) {
+// B = (C + C^T) / 2 on the leading T x T block (row stride ld)
+__global__ void k_pc_sym(int T, int ld, const double* __restrict__ C, double* __restrict__ B) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)T * T) return;
   const int i = (int)(e / T), j = (int)(e % T);
-  B[e] = 0.5 * (C[e] + C[(size_t)j * T + i]);
+  B[(size_t)i * ld + j] = 0.5 * (C[(size_t)i * ld + j] + C[(size_t)j * ld + i]);
 }
 
 // one Gauss-Jordan step (pivot k, no pivoting: C is positive definite) from
-// A into B; T steps turn C into C^-1
-__global__ void k_pc_gj_step(int T, int k, const double* __restrict__ A, double* __restrict__ B) {
+// A into B on the leading T x T block; T steps turn C into C^-1
+__global__ void k_pc_gj_step(int T, int ld, int k, const double* __restrict__ A,
+                             double* __restrict__ B) {
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)T * T) return;
   const int i = (int)(e / T), j = (int)(e % T);
-  const double rkj = (j == k ? 1.0 : A[(size_t)k * T + j]) / A[(size_t)k * T + k];
-  B[e] = i == k ? rkj : (j == k ? 0.0 : A[e]) - A[(size_t)i * T + k] * rkj;
+  const size_t o = (size_t)i * ld + j;
+  const double rkj = (j == k ? 1.0 : A[(size_t)k * ld + j]) / A[(size_t)k * ld + k];
+  B[o] = i == k ? rkj : (j == k ? 0.0 : A[o]) - A[(size_t)i * ld + k] * rkj;
 }
 
 // Local part, per tile (grid: tiles, 256 threads): Z_t = D_t^-1 R_t on the
@@ -872,7 +874,7 @@ __global__ void __launch_bounds__(256) k_pc_local(const double* __restrict__ Din
 // Coarse part and the sums the direction needs, per tile (grid: tiles,
 // CG_WAVES waves): Z_t += (C^-1 Z^T R)_t on real slots (pads 0); block
 // partials of r.z into field fnew and of sum z into F_ZSUM.
-__global__ void __launch_bounds__(CG_BLK) k_pc_coarse(int T, int fnew,
+__global__ void __launch_bounds__(CG_BLK) k_pc_coarse(int T, int ld, int fnew,
                                                       const int* __restrict__ slot_atom,
                                                       const double* __restrict__ Cinv,
                                                       const double* __restrict__ ZtR,
@@ -883,7 +885,7 @@ __global__ void __launch_bounds__(CG_BLK) k_pc_coarse(int T, int fnew,
   __shared__ double cc[VL];
   const int t = blockIdx.x, s = threadIdx.x & 63, w = threadIdx.x >> 6;
   double a = 0.0;
-  for (int u = w; u < T; u += CG_WAVES) a += Cinv[(size_t)t * T + u] * ZtR[(size_t)u * VL + s];
+  for (int u = w; u < T; u += CG_WAVES) a += Cinv[(size_t)t * ld + u] * ZtR[(size_t)u * VL + s];
   sh[w][s] = a;
   __syncthreads();
   if (threadIdx.x < VL) cc[s] = sum16(sh, s);
@@ -898,6 +900,127 @@ __global__ void __launch_bounds__(CG_BLK) k_pc_coarse(int T, int fnew,
   }
   const int f[2] = {fnew, F_ZSUM};
   store_partials<2>(v, f, red);
+}
+
+// Balancing form of the two-level preconditioner (the coarse correction on
+// both sides of the tile-block smoother B = blockdiag(D_t^-1)):
+//   M^-1 r = Q r + (I - Q A) B (I - A Q) r,   Q = Z C^-1 Z^T,
+// symmetric positive definite like the additive form.  With the set-up
+// products DAZ = B A Z (slots x Tp) and H = C^-1 + C^-1 (A Z)^T DAZ C^-1 it is
+//   t = Z^T r,  y = DAZ^T r,  w = C^-1 t,  g = H t - C^-1 y,
+//   z = B r - DAZ w + Z g,
+// two products with DAZ per iteration (the coarse arrays are Tp x 64, Tp the
+// tile count rounded up to 64, zero beyond the tiles).
+
+// y parts (KA): Ypart[(part Tp + m) VL + s] = sum over the slots of part of
+// DAZ[slot][m] R[slot][s]; grid (Tp / 64, parts), tile-aligned slot ranges
+__global__ void __launch_bounds__(256) k_bnn_y(int ntile, int ld, const double* __restrict__ DAZ,
+                                               const double* __restrict__ R,
+                                               double* __restrict__ Ypart) {
+  __shared__ double As[16][68];
+  __shared__ double Bs[16][68];
+  const int m0 = blockIdx.x * 64, part = blockIdx.y, np = gridDim.y;
+  const int kb = ntile * part / np * 64, ke = ntile * (part + 1) / np * 64;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  seg_mfma<true>(acc, DAZ + (size_t)kb * ld + m0, ld, R + (size_t)kb * VL, ke - kb, As, Bs);
+  store_tile(acc, Ypart + ((size_t)part * ld + m0) * VL);
+}
+
+// y = the sum of the parts, t = Z^T r (tile sums of R; 0 beyond the tiles);
+// grid Tp, 256 threads
+__global__ void __launch_bounds__(256) k_bnn_sum(int ntile, int ld, int nparts,
+                                                 const double* __restrict__ Ypart,
+                                                 const double* __restrict__ R,
+                                                 double* __restrict__ Y, double* __restrict__ Tt) {
+  __shared__ double sh[4][VL];
+  __shared__ double sy[4][VL];
+  const int u = blockIdx.x, s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a = 0.0;
+  for (int p = w; p < nparts; p += 4) a += Ypart[((size_t)p * ld + u) * VL + s];
+  sy[w][s] = a;
+  const double tt = u < ntile ? tile_sum(R, sh) : 0.0;   // syncs inside (uniform branch)
+  __syncthreads();
+  if (threadIdx.x < VL) {
+    Y[(size_t)u * VL + s] = (sy[0][s] + sy[1][s]) + (sy[2][s] + sy[3][s]);
+    Tt[(size_t)u * VL + s] = tt;
+  }
+}
+
+// coarse vectors (KB): Wn = -C^-1 t, G = H t - C^-1 y; grid Tp, CG_WAVES waves
+__global__ void __launch_bounds__(CG_BLK) k_bnn_coarse(int ld, const double* __restrict__ Cinv,
+                                                       const double* __restrict__ H,
+                                                       const double* __restrict__ Tt,
+                                                       const double* __restrict__ Y,
+                                                       double* __restrict__ Wn,
+                                                       double* __restrict__ G) {
+  __shared__ double s1[CG_WAVES][VL];
+  __shared__ double s2[CG_WAVES][VL];
+  const int u = blockIdx.x, s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double a = 0.0, b = 0.0;
+  for (int v = w; v < ld; v += CG_WAVES) {
+    const double c = Cinv[(size_t)u * ld + v], h = H[(size_t)u * ld + v];
+    const double tv = Tt[(size_t)v * VL + s], yv = Y[(size_t)v * VL + s];
+    a += c * tv;
+    b += h * tv - c * yv;
+  }
+  s1[w][s] = a;
+  s2[w][s] = b;
+  __syncthreads();
+  if (threadIdx.x < VL) {
+    Wn[(size_t)u * VL + s] = -sum16(s1, s);
+    G[(size_t)u * VL + s] = sum16(s2, s);
+  }
+}
+
+// z per tile (KC): Z_t = D_t^-1 R_t + DAZ_t Wn + g_t on real slots (pads 0),
+// on the matrix cores; block partials of r.z into field fnew and of sum z
+// into F_ZSUM (grid: tiles, 256 threads)
+__global__ void __launch_bounds__(256) k_bnn_z(int ld, int fnew, const int* __restrict__ slot_atom,
+                                               const double* __restrict__ Dinv,
+                                               const double* __restrict__ DAZ,
+                                               const double* __restrict__ Wn,
+                                               const double* __restrict__ G,
+                                               const double* __restrict__ R,
+                                               double* __restrict__ Z, double* __restrict__ red) {
+  __shared__ double As[16][68];
+  __shared__ double Bs[16][68];
+  __shared__ double zs[64][65];
+  __shared__ double sh[2][4][VL];
+  const size_t t = blockIdx.x;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  seg_mfma<false>(acc, Dinv + t * 4096, 64, R + t * 64 * VL, 64, As, Bs);
+  seg_mfma<false>(acc, DAZ + t * 64 * ld, ld, Wn, ld, As, Bs);
+  {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b)
+        for (int q = 0; q < 4; ++q)
+          zs[wm + a * 16 + (lane >> 4) + 4 * q][wn + b * 16 + (lane & 15)] = acc[a][b][q];
+  }
+  __syncthreads();
+  const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double gt = G[t * VL + s];
+  double rz = 0.0, zsum = 0.0;
+  for (int r = w; r < 64; r += 4) {
+    const size_t o = (t * 64 + r) * VL + s;
+    const double z = slot_atom[t * 64 + r] >= 0 ? zs[r][s] + gt : 0.0;
+    Z[o] = z;
+    rz += R[o] * z;
+    zsum += z;
+  }
+  sh[0][w][s] = rz;
+  sh[1][w][s] = zsum;
+  __syncthreads();
+  if (threadIdx.x < VL) {
+    red[(t * CG_RED + fnew) * VL + s] = (sh[0][0][s] + sh[0][1][s]) + (sh[0][2][s] + sh[0][3][s]);
+    red[(t * CG_RED + F_ZSUM) * VL + s] =
+        (sh[1][0][s] + sh[1][1][s]) + (sh[1][2][s] + sh[1][3][s]);
+  }
 }
 
 }  // namespace
@@ -1030,29 +1153,41 @@ void launch_pc_indicator(hipStream_t st, int nblk, int nslot, int t0, int g, con
                      b.ex, b.ey, b.ez, P, red);
 }
 
-void launch_pc_coarse_cols(hipStream_t st, int ntile, int t0, int g, const double* V, double* C) {
-  hipLaunchKernelGGL(k_pc_coarse_cols, dim3(ntile), dim3(256), 0, st, ntile, t0, g, V, C);
+void launch_pc_coarse_cols(hipStream_t st, int ntile, int ld, int t0, int g, const double* V,
+                           double* C) {
+  hipLaunchKernelGGL(k_pc_coarse_cols, dim3(ntile), dim3(256), 0, st, ld, t0, g, V, C);
 }
 
-double* launch_pc_invert(hipStream_t st, int ntile, double* C, double* W) {
+double* launch_pc_invert(hipStream_t st, int ntile, int ld, double* C, double* W) {
   const size_t tot = (size_t)ntile * ntile;
   const dim3 grid((unsigned)((tot + 255) / 256));
-  hipLaunchKernelGGL(k_pc_sym, grid, dim3(256), 0, st, ntile, C, W);
+  hipLaunchKernelGGL(k_pc_sym, grid, dim3(256), 0, st, ntile, ld, C, W);
   double* a = W;
   double* o = C;
   for (int k = 0; k < ntile; ++k) {
-    hipLaunchKernelGGL(k_pc_gj_step, grid, dim3(256), 0, st, ntile, k, a, o);
+    hipLaunchKernelGGL(k_pc_gj_step, grid, dim3(256), 0, st, ntile, ld, k, a, o);
     std::swap(a, o);
   }
   return a;
 }
 
-void launch_pc_apply(hipStream_t st, int ntile, int parity, const int* slot_atom,
+void launch_pc_apply(hipStream_t st, int ntile, int ld, int parity, const int* slot_atom,
                      const double* Dinv, const double* Cinv, const double* R, double* Z,
                      double* ZtR, double* red) {
   hipLaunchKernelGGL(k_pc_local, dim3(ntile), dim3(256), 0, st, Dinv, R, Z, ZtR);
-  hipLaunchKernelGGL(k_pc_coarse, dim3(ntile), dim3(CG_BLK), 0, st, ntile, F_RZ + parity,
+  hipLaunchKernelGGL(k_pc_coarse, dim3(ntile), dim3(CG_BLK), 0, st, ntile, ld, F_RZ + parity,
                      slot_atom, Cinv, ZtR, R, Z, red);
+}
+
+void launch_bnn_apply(hipStream_t st, int ntile, int ld, int nparts, int parity,
+                      const int* slot_atom, const double* Dinv, const double* DAZ,
+                      const double* Cinv, const double* H, const double* R, double* Z,
+                      double* Ypart, double* Y, double* Tt, double* Wn, double* G, double* red) {
+  hipLaunchKernelGGL(k_bnn_y, dim3(ld / 64, nparts), dim3(256), 0, st, ntile, ld, DAZ, R, Ypart);
+  hipLaunchKernelGGL(k_bnn_sum, dim3(ld), dim3(256), 0, st, ntile, ld, nparts, Ypart, R, Y, Tt);
+  hipLaunchKernelGGL(k_bnn_coarse, dim3(ld), dim3(CG_BLK), 0, st, ld, Cinv, H, Tt, Y, Wn, G);
+  hipLaunchKernelGGL(k_bnn_z, dim3(ntile), dim3(256), 0, st, ld, F_RZ + parity, slot_atom, Dinv,
+                     DAZ, Wn, G, R, Z, red);
 }
 
 }  // namespace cpm

@@ -301,27 +301,36 @@ cpm_status ensure_cg_buffers(cpm_ctx* c) {
 }
 
 // The two-level preconditioner of the operator's CG, built on first use:
-// inverse diagonal tile blocks, and the coarse matrix Z^T A Z from A applied
-// to the tile indicators (CG_MAXG tiles per application), inverted in place.
-// Operators with more than PC_MAX_TILES tiles run without it.
+// inverse diagonal tile blocks B, and the coarse matrix C = Z^T A Z from
+// A Z (A applied to the tile indicators, CG_MAXG tiles per application),
+// inverted in place; the balancing form also keeps DAZ = B A Z and
+// H = C^-1 + C^-1 (A Z)^T DAZ C^-1.  Coarse arrays have row stride
+// ld = tiles rounded up to 64 and are zero beyond the tiles.  Operators
+// with more than PC_MAX_TILES tiles run without a preconditioner.
 constexpr int PC_MAX_TILES = 2048;
 
 cpm_status ensure_precond(cpm_ctx* c) {
   if (c->pc_ready) return CPM_OK;
   c->pc_tiles = 0;
-  const int nslot = c->nmap, T = nslot / 64;
-  if (!c->have_op || !c->cg_precond || T > PC_MAX_TILES) return CPM_OK;
+  c->pc_mode = 0;
+  const int nslot = c->nmap, T = nslot / 64, ld = (T + 63) / 64 * 64;
+  if (!c->have_op || c->cg_precond <= 0 || T > PC_MAX_TILES) return CPM_OK;
+  const bool bal = c->cg_precond >= 2;
   Buffers& b = c->b;
   hipStream_t st = c->stream;
-  TRY(dalloc(c, &b.pc_dinv, (size_t)T * 4096));
-  TRY(dalloc(c, &b.pc_C, (size_t)T * T));
-  TRY(dalloc(c, &b.pc_W, (size_t)T * T));
-  TRY(dalloc(c, &b.pc_ztr, (size_t)T * CG_MAXG));
-  TRY(dalloc(c, &b.pc_tplane, (size_t)T));
-  TRY(dalloc(c, &b.pc_dblk, (size_t)T));
   if ((int)c->h_tile_plane.size() != T || (int)c->h_bdiag.size() != T)
     return fail(c, CPM_ESTATE, "operator tiles (%zu planes, %zu blocks) do not match %d slots",
                 c->h_tile_plane.size(), c->h_bdiag.size(), nslot);
+  const size_t ld2 = (size_t)ld * ld;
+  TRY(dalloc(c, &b.pc_dinv, (size_t)T * 4096));
+  TRY(dalloc(c, &b.pc_C, ld2));
+  TRY(dalloc(c, &b.pc_W, ld2));
+  TRY(dalloc(c, &b.pc_ztr, (size_t)ld * CG_MAXG));
+  TRY(dalloc(c, &b.pc_tplane, (size_t)T));
+  TRY(dalloc(c, &b.pc_dblk, (size_t)T));
+  HIP_TRY(c, hipMemsetAsync(b.pc_C, 0, ld2 * sizeof(double), st));
+  HIP_TRY(c, hipMemsetAsync(b.pc_W, 0, ld2 * sizeof(double), st));
+  HIP_TRY(c, hipMemsetAsync(b.pc_ztr, 0, (size_t)ld * CG_MAXG * sizeof(double), st));
   HIP_TRY(c, hipMemcpyAsync(b.pc_tplane, c->h_tile_plane.data(), T * sizeof(int),
                             hipMemcpyHostToDevice, st));
   HIP_TRY(c, hipMemcpyAsync(b.pc_dblk, c->h_bdiag.data(), T * sizeof(int), hipMemcpyHostToDevice,
@@ -332,20 +341,73 @@ cpm_status ensure_precond(cpm_ctx* c) {
   TRY(launched(c, "preconditioner blocks"));
   double* P = b.cgv + (size_t)2 * CG_MAXG * nslot;
   double* AP = P + (size_t)CG_MAXG * nslot;
+  double* AZ = nullptr;                   // balancing form: A Z, slots x ld (set-up only)
+  if (bal) {
+    TRY(dalloc(c, &AZ, (size_t)nslot * ld));
+    HIP_TRY(c, hipMemsetAsync(AZ, 0, (size_t)nslot * ld * sizeof(double), st));
+  }
   const int nb = cg_grid(c);
   { Timed t(c, "pc_coarse_matrix");
     for (int t0 = 0; t0 < T; t0 += CG_MAXG) {
       const int g = std::min(CG_MAXG, T - t0);
       launch_pc_indicator(st, nb, nslot, t0, g, b.amap, b, P, b.cgred);
       apply_A(c, P, AP, false);
-      launch_pc_coarse_cols(st, T, t0, g, AP, b.pc_C);
+      launch_pc_coarse_cols(st, T, ld, t0, g, AP, b.pc_C);
+      if (bal)
+        HIP_TRY(c, hipMemcpy2DAsync(AZ + t0, (size_t)ld * sizeof(double), AP,
+                                    CG_MAXG * sizeof(double), (size_t)g * sizeof(double), nslot,
+                                    hipMemcpyDeviceToDevice, st));
     }
-    c->pc_Cinv = launch_pc_invert(st, T, b.pc_C, b.pc_W); }
+    c->pc_Cinv = launch_pc_invert(st, T, ld, b.pc_C, b.pc_W); }
   TRY(launched(c, "preconditioner coarse matrix"));
+  if (bal) {
+    Timed t(c, "pc_balancing");
+    const int np = std::max(1, std::min(T, 64));
+    TRY(dalloc(c, &b.pc_daz, (size_t)nslot * ld));
+    TRY(dalloc(c, &b.pc_H, ld2));
+    TRY(dalloc(c, &b.pc_ypart, (size_t)np * ld * CG_MAXG));
+    TRY(dalloc(c, &b.pc_y, (size_t)ld * CG_MAXG));
+    TRY(dalloc(c, &b.pc_wn, (size_t)ld * CG_MAXG));
+    TRY(dalloc(c, &b.pc_g, (size_t)ld * CG_MAXG));
+    double* Gm = nullptr;                 // (A Z)^T DAZ, then C^-1 of it
+    double* X = nullptr;
+    TRY(dalloc(c, &Gm, ld2));
+    TRY(dalloc(c, &X, ld2));
+    // DAZ: each tile's rows of A Z times that tile's inverse block
+    for (int t = 0; t < T; ++t)
+      launch_gemm_f64(st, false, false, 64, ld, 64, 1.0, b.pc_dinv + (size_t)t * 4096, 64,
+                      AZ + (size_t)t * 64 * ld, ld, 0.0, b.pc_daz + (size_t)t * 64 * ld, ld, 0, 0);
+    launch_gemm_f64(st, true, false, ld, ld, nslot, 1.0, AZ, ld, b.pc_daz, ld, 0.0, Gm, ld, 0, 0);
+    launch_gemm_f64(st, false, false, ld, ld, ld, 1.0, c->pc_Cinv, ld, Gm, ld, 0.0, X, ld, 0, 0);
+    HIP_TRY(c, hipMemcpyAsync(b.pc_H, c->pc_Cinv, ld2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    launch_gemm_f64(st, false, false, ld, ld, ld, 1.0, X, ld, c->pc_Cinv, ld, 1.0, b.pc_H, ld, 0, 0);
+    TRY(launched(c, "preconditioner balancing products"));
+    HIP_TRY(c, hipStreamSynchronize(st));
+    dfree(c, Gm);
+    dfree(c, X);
+    dfree(c, AZ);
+    c->bytes -= (2 * ld2 + (size_t)nslot * ld) * sizeof(double);   // set-up temporaries
+    c->pc_nparts = np;
+  }
   HIP_TRY(c, hipStreamSynchronize(st));
   c->pc_tiles = T;
+  c->pc_ld = ld;
+  c->pc_mode = bal ? 2 : 1;
   c->pc_ready = true;
   return CPM_OK;
+}
+
+// z = M^-1 r for the CG group (into Z), with the partials of r.z (parity
+// field) and of sum z
+void precond_apply(cpm_ctx* c, int parity, const double* R, double* Z) {
+  Buffers& b = c->b;
+  if (c->pc_mode == 2)
+    launch_bnn_apply(c->stream, c->pc_tiles, c->pc_ld, c->pc_nparts, parity, b.amap, b.pc_dinv,
+                     b.pc_daz, c->pc_Cinv, b.pc_H, R, Z, b.pc_ypart, b.pc_y, b.pc_ztr, b.pc_wn,
+                     b.pc_g, b.cgred);
+  else
+    launch_pc_apply(c->stream, c->pc_tiles, c->pc_ld, parity, b.amap, b.pc_dinv, c->pc_Cinv, R, Z,
+                    b.pc_ztr, b.cgred);
 }
 
 cpm_status ensure_step_buffers(cpm_ctx* c) {
@@ -557,7 +619,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
-  if (const char* ev = std::getenv("CPM_CG_PRECOND")) c->cg_precond = std::atoi(ev) != 0;
+  if (const char* ev = std::getenv("CPM_CG_PRECOND")) c->cg_precond = std::max(0, std::min(2, std::atoi(ev)));
   if (const char* ev = std::getenv("CPM_CHOL_BLOCK"))
     c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
@@ -789,7 +851,8 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
   dfree(c, b0.cg_ident); dfree(c, b0.cgv); dfree(c, b0.cgred); dfree(c, b0.cgscal);
   dfree(c, b0.cgphi); dfree(c, b0.cgY); dfree(c, b0.cgT);
   dfree(c, b0.pc_dinv); dfree(c, b0.pc_C); dfree(c, b0.pc_W); dfree(c, b0.pc_ztr);
-  dfree(c, b0.pc_tplane); dfree(c, b0.pc_dblk);
+  dfree(c, b0.pc_tplane); dfree(c, b0.pc_dblk); dfree(c, b0.pc_daz); dfree(c, b0.pc_H);
+  dfree(c, b0.pc_ypart); dfree(c, b0.pc_y); dfree(c, b0.pc_wn); dfree(c, b0.pc_g);
   c->pc_ready = false;
   c->pc_tiles = 0;
   c->pc_Cinv = nullptr;
@@ -1845,7 +1908,7 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
     { Timed t(c, "cg_init");
       launch_cg_init(st, nb, nslot, n, g, slots, b, bsrc, b_is_f32, X, R, P, b.cgred, b.cgscal);
       if (npc > 0) {       // p = z - mean z, z = M^-1 r0 (r.z into the parity-0 field)
-        launch_pc_apply(st, npc, 0, slots, b.pc_dinv, c->pc_Cinv, R, AP, b.pc_ztr, b.cgred);
+        precond_apply(c, 0, R, AP);
         launch_cg_dir(st, nb, nslot, n, 1, tol2, npc, 1, slots, b, R, AP, P, b.cgred, b.cgscal);
       } }
     TRY(launched(c, "cg init"));
@@ -1863,8 +1926,7 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
                            b.cgscal); }
         if (npc > 0) {     // z = M^-1 r into AP (free until the next product)
           Timed t(c, "cg_precond");
-          launch_pc_apply(st, npc, 1 - cur, slots, b.pc_dinv, c->pc_Cinv, R, AP, b.pc_ztr,
-                          b.cgred);
+          precond_apply(c, 1 - cur, R, AP);
         }
         { Timed t(c, "cg_dir");
           launch_cg_dir(st, nb, nslot, n, cur, tol2, npc, 0, slots, b, R, AP, P, b.cgred,
@@ -1961,6 +2023,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_NCOLS: *out = c->ncolsort; return CPM_OK;
     case CPM_INFO_BSR_BLOCKS: *out = c->bsr_blocks; return CPM_OK;
     case CPM_INFO_PC_TILES: *out = c->pc_tiles; return CPM_OK;
+    case CPM_INFO_PC_MODE: *out = c->pc_mode; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -2004,7 +2067,8 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);
   dfree(b.cgscal); dfree(b.cgphi); dfree(b.cgY); dfree(b.cgT);
   dfree(b.pc_dinv); dfree(b.pc_C); dfree(b.pc_W); dfree(b.pc_ztr); dfree(b.pc_tplane);
-  dfree(b.pc_dblk);
+  dfree(b.pc_dblk); dfree(b.pc_daz); dfree(b.pc_H); dfree(b.pc_ypart); dfree(b.pc_y);
+  dfree(b.pc_wn); dfree(b.pc_g);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

@@ -137,6 +137,12 @@ struct Buffers {
   double* pc_ztr = nullptr;        // tile sums of r (ntile x CG_MAXG)
   int* pc_tplane = nullptr;        // plane of each tile
   int* pc_dblk = nullptr;          // real-space block of each tile's diagonal (-1: none)
+  double* pc_daz = nullptr;        // balancing form: B A Z (slots x ld)
+  double* pc_H = nullptr;          //   C^-1 + C^-1 (A Z)^T B A Z C^-1 (ld x ld)
+  double* pc_ypart = nullptr;      //   parts of (B A Z)^T r (nparts x ld x CG_MAXG)
+  double* pc_y = nullptr;          //   their sum, and the coarse vectors w, g (ld x CG_MAXG)
+  double* pc_wn = nullptr;
+  double* pc_g = nullptr;
   size_t kpart_len = 0;
   int bpad_rows = 0;
   double* scal = nullptr;          // small scalars (s and friends)
@@ -183,21 +189,29 @@ void launch_cg_dir(hipStream_t st, int nblk, int nslot, int n, int cur, double t
                    const double* Z, double* P, double* red, double* scal);
 // two-level preconditioner over the ntile slot tiles: inverses of A's
 // 64 x 64 diagonal tile blocks (from the operator's pieces); the coarse
-// matrix C = Z^T A Z (Z: tile indicators) column block by column block from
-// A applied to indicator vectors; C^-1 by Gauss-Jordan steps (C and W both
-// ntile x ntile; returns the one holding C^-1); and per iteration
-// Z = M^-1 R with partials of r.z (field of parity `parity`) and of sum z
+// matrix C = Z^T A Z (Z: tile indicators, row stride ld >= ntile) column
+// block by column block from A applied to indicator vectors; C^-1 by
+// Gauss-Jordan steps on the leading ntile x ntile block (C and W both hold
+// it; returns the one with C^-1).  Per iteration Z = M^-1 R with partials of
+// r.z (field of parity `parity`) and of sum z: additive form
+// (launch_pc_apply), or balancing form with DAZ = B A Z and H (ld a
+// multiple of 64; Ypart: nparts x ld x 64, Y, Tt, Wn, G: ld x 64)
 void launch_pc_blocks(hipStream_t st, int ntile, int nslot, int nlayers, int ncolsort,
                       const int* slot_atom, const int* tile_plane, const int* diag_blk,
                       const double* bval, const double* Ecat, const double2* Q, const Buffers& b,
                       double background, const double* cdip, double ke, double* Dinv);
 void launch_pc_indicator(hipStream_t st, int nblk, int nslot, int t0, int g, const int* slot_atom,
                          const Buffers& b, double* P, double* red);
-void launch_pc_coarse_cols(hipStream_t st, int ntile, int t0, int g, const double* V, double* C);
-double* launch_pc_invert(hipStream_t st, int ntile, double* C, double* W);
-void launch_pc_apply(hipStream_t st, int ntile, int parity, const int* slot_atom,
+void launch_pc_coarse_cols(hipStream_t st, int ntile, int ld, int t0, int g, const double* V,
+                           double* C);
+double* launch_pc_invert(hipStream_t st, int ntile, int ld, double* C, double* W);
+void launch_pc_apply(hipStream_t st, int ntile, int ld, int parity, const int* slot_atom,
                      const double* Dinv, const double* Cinv, const double* R, double* Z,
                      double* ZtR, double* red);
+void launch_bnn_apply(hipStream_t st, int ntile, int ld, int nparts, int parity,
+                      const int* slot_atom, const double* Dinv, const double* DAZ,
+                      const double* Cinv, const double* H, const double* R, double* Z,
+                      double* Ypart, double* Y, double* Tt, double* Wn, double* G, double* red);
 void launch_cg_init(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
                     const Buffers& b, const void* bsrc, int b_is_f32, double* X, double* R,
                     double* P, double* red, double* scal);
@@ -246,8 +260,11 @@ struct cpm_ctx {
   int sfm_max_chunk = 4096;        // most charges per matrix-core chunk
   int chol_block = 256;            // columns per outer block of the Cholesky / inverse
   int cg_cap = 0;                  // most workgroups of the CG vector kernels (0: by size)
-  int cg_precond = 1;              // two-level preconditioner for the operator's CG (0: none)
+  int cg_precond = 2;              // operator CG preconditioner: 0 none, 1 additive, 2 balancing
   int pc_tiles = 0;                // tiles of the preconditioner in use (0: none or not built)
+  int pc_mode = 0;                 // form in use (1 additive, 2 balancing)
+  int pc_ld = 0;                   // coarse row stride: tiles rounded up to 64
+  int pc_nparts = 1;               // slot parts of the balancing form's y product
   bool pc_ready = false;           // preconditioner built for the current operator
   const double* pc_Cinv = nullptr; // whichever of pc_C / pc_W holds the coarse inverse
   std::vector<int> h_bdiag;        // real-space block of each tile's diagonal (-1: none)

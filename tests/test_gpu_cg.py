@@ -283,17 +283,19 @@ def test_cg_wire_tubes(cpm):
 
 
 def test_cg_preconditioner_2880(cpm, monkeypatch):
-    """The two-level preconditioner (inverse 64 x 64 diagonal tile blocks plus
-    the coarse space of tile constants) changes the iterates, not the
-    solution: with and without it the charges of the 2880-atom capacitor
-    match the stored oracle charges, and it takes fewer iterations."""
+    """The two-level preconditioner (smoother: inverse 64 x 64 diagonal tile
+    blocks; coarse space: tile constants; additive form 1, balancing form 2)
+    changes the iterates, not the solution: without it and in both forms the
+    charges of the 2880-atom capacitor (48 tiles: coarse arrays padded to 64)
+    match the stored oracle charges, and each form takes fewer iterations
+    than the one before."""
     if not os.path.exists(GOLDEN):
         pytest.skip("golden file missing: run tests/golden/make_golden.py")
     g = dict(np.load(GOLDEN))
     w = I.graphite_capacitor()
     snaps = [int(s) for s in g["snapshots"]]
     iters = {}
-    for pc in ("0", "1"):
+    for pc in ("0", "1", "2"):
         monkeypatch.setenv("CPM_CG_PRECOND", pc)
         say(f"cg graphite_capacitor_2880, preconditioner {pc}")
         ctx = cpm.setup(w, matrix_free=True)
@@ -301,15 +303,15 @@ def test_cg_preconditioner_2880(cpm, monkeypatch):
         q = torch.empty_like(b)
         Qe = torch.empty((len(snaps), 2), dtype=torch.float64, device="cuda")
         iters[pc], res = ctx.solve_cg(b, q, Qe, tol=1e-13)
-        tiles = ctx.info("pc_tiles")
-        say(f"  iterations {iters[pc]}, residual {res:.2e}, tiles {tiles:.0f}")
+        tiles, mode = ctx.info("pc_tiles"), ctx.info("pc_mode")
+        say(f"  iterations {iters[pc]}, residual {res:.2e}, tiles {tiles:.0f}, form {mode:.0f}")
         assert res <= 1e-13
-        assert (tiles > 0) == (pc == "1")
+        assert mode == int(pc) and tiles == (48 if pc != "0" else 0)
         assert rel(q.cpu().numpy(), g["q"]) < 1e-10
         assert rel(Qe.cpu().numpy(), g["Q"]) < 1e-10
         assert np.abs(q.cpu().numpy().sum(axis=1)).max() <= 1e-12
         ctx.close()
-    assert iters["1"] < iters["0"]
+    assert iters["2"] < iters["1"] < iters["0"]
 
 
 def test_operator_rebuild_with_other_plane_sizes(cpm):
