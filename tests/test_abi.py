@@ -30,6 +30,15 @@ def test_library_exports_header():
     assert sorted(cpm.EXPORTS) == names
 
 
+def test_binding_constants_match_header():
+    """The binding's info keys and status codes are the header's enums."""
+    src = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "cpm.h")).read(), flags=re.S)
+    info = {k.lower(): int(v) for k, v in re.findall(r"\bCPM_INFO_([A-Z0-9_]+)\s*=\s*(\d+)", src)}
+    assert info == cpm.INFO
+    status = {int(v): "CPM_" + k for k, v in re.findall(r"\bCPM_(E[A-Z]+|OK)\s*=\s*(\d+)", src)}
+    assert status == cpm.STATUS_NAMES
+
+
 def _create(**over):
     p = cpm.Params(14.757, 25.56, 30.0)
     for k, v in over.items():
