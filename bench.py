@@ -366,7 +366,8 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     """The matrix-free conjugate-gradient solve on the same workload: operator
     set-up, then B = 64 configurations (one CG group) solved to |r| <= tol |r0|
     per call, with the two-level preconditioner (built by the first, untimed
-    solve; its set-up time is reported on its own) and, for comparison, the
+    solve; its set-up time is reported on its own; the second untimed solve
+    captures the 8-iteration graph) and, for comparison, the
     iteration count of plain CG.  Reports solves/s, iterations, the
     per-iteration kernel split
     with each family's algorithmic HBM bytes (and FP64 flops for the two
@@ -398,6 +399,7 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     pc_setup_ms = sum(ctx.timing(f)[0] for f in ("pc_blocks", "pc_coarse_matrix", "pc_balancing"))
     ctx.enable_timing(False)
     pc_tiles, pc_mode = int(ctx.info("pc_tiles")), int(ctx.info("pc_mode"))
+    ctx.solve_cg(b, q, Qe, tol=tol)                       # captures the iteration graph
     torch.cuda.synchronize()
     ts = time.perf_counter()
     for _ in range(reps):

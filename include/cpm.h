@@ -200,7 +200,11 @@ cpm_status cpm_apply_elastance(cpm_ctx* ctx, int batch, const double* d_x, doubl
  * M^-1 = Q + (I - Q A) B (I - A Q) (default) or the additive form
  * M^-1 = B + Q (environment CPM_CG_PRECOND=1; 0: none).  The stopping test
  * stays |r| <= tol |r0| on the unpreconditioned residual.  Operators with
- * more than 2048 tiles and the dense A run plain CG.
+ * more than 2048 tiles and the dense A run plain CG.  Blocks of 8
+ * iterations replay one HIP graph, captured on first use for the current
+ * buffers, tolerance and preconditioner (environment CPM_CG_GRAPH=0: plain
+ * launches; none while kernel timing is on); a context on the NULL stream
+ * runs the solve on an internal stream after draining the NULL stream.
  * Writes d_q (batch x n FP64, the final
  * iterate projected to e^T q = 0) and, unless NULL, d_Qe (batch x n_e
  * electrode totals).  Synchronous (the host checks convergence every 8

@@ -619,6 +619,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_CG_GRAPH")) c->cg_graphs = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_CG_PRECOND")) c->cg_precond = std::max(0, std::min(2, std::atoi(ev)));
   if (const char* ev = std::getenv("CPM_CHOL_BLOCK"))
     c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
@@ -1870,6 +1871,21 @@ cpm_status cpm_apply_elastance(cpm_ctx* c, int batch, const double* d_x, double*
   return CPM_OK;
 }
 
+// cpm_solve_cg is synchronous, so a context on the default (NULL) stream can
+// run it on an internal stream, where its iteration blocks can be captured as
+// graphs: the NULL stream is drained first, and the internal stream is drained
+// and the context's stream restored on every return.
+struct CgStream {
+  cpm_ctx* c;
+  hipStream_t saved;
+  bool on = false;
+  ~CgStream() {
+    if (!on) return;
+    (void)hipStreamSynchronize(c->stream);
+    c->stream = saved;
+  }
+};
+
 cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, double tol,
                         int maxit, double* d_q, double* d_Qe) {
   if (!c) return CPM_EINVAL;
@@ -1886,6 +1902,13 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
   c->cg_iters = 0;
   c->cg_resid = 0.0;
   if (batch == 0) return CPM_OK;
+  CgStream swap{c, c->stream};
+  if (!c->stream && c->cg_graphs && !c->timing) {
+    if (!c->cg_stream) HIP_TRY(c, hipStreamCreateWithFlags(&c->cg_stream, hipStreamNonBlocking));
+    HIP_TRY(c, hipStreamSynchronize(nullptr));
+    c->stream = c->cg_stream;
+    swap.on = true;
+  }
   TRY(ensure_cg_buffers(c));
   TRY(ensure_precond(c));
   Buffers& b = c->b;
@@ -1914,23 +1937,48 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
     TRY(launched(c, "cg init"));
     int it = 0;
     bool conv = false;
+    auto iteration = [&](int cur) {
+      apply_A(c, P, AP, true);
+      { Timed t(c, "cg_update");
+        launch_cg_update(st, nb, nslot, n, cur, tol2, npc, slots, X, R, P, AP, b.cgred,
+                         b.cgscal); }
+      if (npc > 0) {       // z = M^-1 r into AP (free until the next product)
+        Timed t(c, "cg_precond");
+        precond_apply(c, 1 - cur, R, AP);
+      }
+      { Timed t(c, "cg_dir");
+        launch_cg_dir(st, nb, nslot, n, cur, tol2, npc, 0, slots, b, R, AP, P, b.cgred,
+                      b.cgscal); }
+    };
     while (it < maxit && !conv) {
       // a block of iterations between convergence checks; vectors below the
-      // tolerance are frozen (zero step) by the step-length kernel
+      // tolerance are frozen (zero step) by the step-length kernel.  A full
+      // block (it even) replays one captured graph of its 8 iterations when
+      // the context has its own stream and timing is off.
       const int blk = std::min(8, maxit - it);
-      for (int k = 0; k < blk; ++k, ++it) {
-        const int cur = it & 1;
-        apply_A(c, P, AP, true);
-        { Timed t(c, "cg_update");
-          launch_cg_update(st, nb, nslot, n, cur, tol2, npc, slots, X, R, P, AP, b.cgred,
-                           b.cgscal); }
-        if (npc > 0) {     // z = M^-1 r into AP (free until the next product)
-          Timed t(c, "cg_precond");
-          precond_apply(c, 1 - cur, R, AP);
+      if (blk == 8 && c->cg_graphs && st && !c->timing) {
+        if (!c->cg_graph_exec || c->cg_graph_gen != c->alloc_gen || c->cg_graph_tol2 != tol2 ||
+            c->cg_graph_npc != npc) {
+          if (c->cg_graph_exec) { (void)hipGraphExecDestroy(c->cg_graph_exec); c->cg_graph_exec = nullptr; }
+          if (c->cg_graph) { (void)hipGraphDestroy(c->cg_graph); c->cg_graph = nullptr; }
+          HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          for (int k = 0; k < 8; ++k) iteration(k & 1);
+          hipGraph_t gr = nullptr;
+          const hipError_t e = hipStreamEndCapture(st, &gr);
+          if (e != hipSuccess) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return fail(c, CPM_EHIP, "capture of the CG iterations: %s", hipGetErrorString(e));
+          }
+          c->cg_graph = gr;
+          HIP_TRY(c, hipGraphInstantiate(&c->cg_graph_exec, gr, nullptr, nullptr, 0));
+          c->cg_graph_gen = c->alloc_gen;
+          c->cg_graph_tol2 = tol2;
+          c->cg_graph_npc = npc;
         }
-        { Timed t(c, "cg_dir");
-          launch_cg_dir(st, nb, nslot, n, cur, tol2, npc, 0, slots, b, R, AP, P, b.cgred,
-                        b.cgscal); }
+        HIP_TRY(c, hipGraphLaunch(c->cg_graph_exec, st));
+        it += 8;
+      } else {
+        for (int k = 0; k < blk; ++k, ++it) iteration(it & 1);
       }
       TRY(launched(c, "cg iterations"));
       HIP_TRY(c, hipMemcpyAsync(h_scal.data(), b.cgscal, h_scal.size() * sizeof(double),
@@ -2072,6 +2120,9 @@ void cpm_destroy(cpm_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->cg_graph_exec) (void)hipGraphExecDestroy(c->cg_graph_exec);
+  if (c->cg_graph) (void)hipGraphDestroy(c->cg_graph);
+  if (c->cg_stream) (void)hipStreamDestroy(c->cg_stream);
   for (auto& pe : c->pending) { (void)hipEventDestroy(pe.a); (void)hipEventDestroy(pe.b); }
   for (auto e : c->evpool) (void)hipEventDestroy(e);
   delete c;

@@ -311,6 +311,15 @@ struct cpm_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   unsigned long long graph_gen = 0;    // alloc_gen when the graph was captured
+  // the CG iteration block (8 iterations between convergence checks) as a
+  // graph, keyed by the buffers, the tolerance and the preconditioner
+  bool cg_graphs = true;
+  hipStream_t cg_stream = nullptr;     // internal stream of cpm_solve_cg for the NULL-stream context
+  hipGraph_t cg_graph = nullptr;
+  hipGraphExec_t cg_graph_exec = nullptr;
+  unsigned long long cg_graph_gen = 0;
+  double cg_graph_tol2 = -1.0;
+  int cg_graph_npc = -1;
   unsigned graph_store = 0;            // copies of S the captured solve reads
   bool graph_ccm = false;              // the captured solve needs the charge targets
   // kernel timing (cpm_enable_timing)

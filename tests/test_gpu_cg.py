@@ -349,3 +349,38 @@ def test_operator_rebuild_with_other_plane_sizes(cpm):
     assert rel(q.cpu().numpy(), qo) < 1e-10
     assert np.abs(q.cpu().numpy().sum(axis=1)).max() <= 1e-12
     ctx.close()
+
+
+def test_cg_iteration_graphs_match_eager(cpm, monkeypatch):
+    """The 8-iteration blocks of the CG replayed as HIP graphs (the context's
+    own stream, or the internal stream of a NULL-stream context) give the
+    same charges, bit for bit, as eager launches; two groups (35 vectors) and
+    two calls, so the graphs are replayed many times with eager kernels and
+    host checks in between, and a second tolerance captures anew."""
+    w = I.graphite_capacitor()
+    snaps = list(range(35))
+    out = {}
+    for name, env, use_stream in (("eager", "0", False), ("null", "1", False), ("own", "1", True)):
+        monkeypatch.setenv("CPM_CG_GRAPH", env)
+        say(f"cg iteration graphs: {name}")
+        stream = torch.cuda.Stream() if use_stream else None
+        ctx = cpm.setup(w, matrix_free=True, stream=stream)
+        b = _b(ctx, w, snaps)
+        if stream is not None:
+            stream.synchronize()
+        res = []
+        for tol in (1e-13, 1e-13, 1e-10):
+            q = torch.empty_like(b)
+            iters, r = ctx.solve_cg(b, q, tol=tol)
+            res.append((iters, q.cpu().numpy()))
+        out[name] = res
+        ctx.close()
+    for name in ("null", "own"):
+        for (i0, q0), (i1, q1) in zip(out["eager"], out[name]):
+            assert i0 == i1
+            assert np.array_equal(q0, q1), name
+    g = dict(np.load(GOLDEN)) if os.path.exists(GOLDEN) else None
+    if g is not None:
+        idx = [snaps.index(int(s)) for s in g["snapshots"] if int(s) in snaps]
+        if idx:
+            assert rel(out["null"][0][1][idx], g["q"][:len(idx)]) < 1e-10
