@@ -399,6 +399,7 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     pc_setup_ms = sum(ctx.timing(f)[0] for f in ("pc_blocks", "pc_coarse_matrix", "pc_balancing"))
     ctx.enable_timing(False)
     pc_tiles, pc_mode = int(ctx.info("pc_tiles")), int(ctx.info("pc_mode"))
+    pc_coarse = int(ctx.info("pc_coarse"))
     ctx.solve_cg(b, q, Qe, tol=tol)                       # captures the iteration graph
     torch.cuda.synchronize()
     ts = time.perf_counter()
@@ -439,7 +440,7 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     nslot = int(sum(-(-c // 64) * 64 for c in np.bincount(
         np.searchsorted(np.unique(w.electrode_xyz[:, 2]), w.electrode_xyz[:, 2]))))
     vec = nslot * 64 * 8                             # one slot-major block of 64 vectors
-    ld = -(-pc_tiles // 64) * 64                     # coarse row stride
+    ld = -(-pc_coarse // 64) * 64                    # coarse row stride
     if pc_mode == 2:
         # balancing form: inverse tile blocks, DAZ (slots x ld) twice, the
         # two ld x ld coarse matrices; r read three times, z written
@@ -479,7 +480,8 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     out = {"solves_per_s": B / call_s, "ms_per_call": call_s * 1e3, "vectors_per_call": B,
            "tol": tol, "iterations": iters, "residual": resid, "operator_setup_s": setup_s,
            "preconditioner": {"form": {0: "none", 1: "additive", 2: "balancing"}[pc_mode],
-                              "tiles": pc_tiles, "setup_s": pc_setup_ms * 1e-3,
+                              "tiles": pc_tiles, "coarse_columns": pc_coarse,
+                              "setup_s": pc_setup_ms * 1e-3,
                               "plain_cg_iterations": plain_iters},
            "ell_width": width, "bsr_blocks": nb, "columns": nc, "planes": nl, "slots": nslot,
            "max_rel_diff_vs_direct_fp64": dev_rel,

@@ -114,7 +114,8 @@ enum {
   CPM_INFO_BSR_BLOCKS = 22,   /* 64 x 64 blocks of the operator's real space      */
   CPM_INFO_PC_TILES = 23,     /* last cpm_solve_cg: tiles of its preconditioner   */
                               /*   (0: plain CG)                                  */
-  CPM_INFO_PC_MODE = 24       /*   ... its form: 0 none, 1 additive, 2 balancing  */
+  CPM_INFO_PC_MODE = 24,      /*   ... its form: 0 none, 1 additive, 2 balancing  */
+  CPM_INFO_PC_COARSE = 25     /*   ... its coarse-space dimension                 */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the
@@ -196,7 +197,10 @@ cpm_status cpm_apply_elastance(cpm_ctx* ctx, int batch, const double* d_x, doubl
  * preconditioned (built on the first solve after cpm_build_operator) by a
  * two-level method over the operator's 64-atom plane tiles: the smoother
  * B = the inverses of A's 64 x 64 diagonal tile blocks, the coarse space Z =
- * the tile indicators, Q = Z (Z^T A Z)^-1 Z^T, in the balancing form
+ * per tile its constant and, for the balancing form on operators of at
+ * least 128 tiles, the two in-plane offsets from the tile's centre
+ * (environment CPM_CG_COARSE=1 or 3 forces 1 or 3 functions per tile),
+ * Q = Z (Z^T A Z)^-1 Z^T, in the balancing form
  * M^-1 = Q + (I - Q A) B (I - A Q) (default) or the additive form
  * M^-1 = B + Q (environment CPM_CG_PRECOND=1; 0: none).  The stopping test
  * stays |r| <= tol |r0| on the unpreconditioned residual.  Operators with

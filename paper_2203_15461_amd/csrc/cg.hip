@@ -788,20 +788,27 @@ __global__ void __launch_bounds__(256) k_pc_blocks(
   }
 }
 
-// P = the indicator vectors of tiles t0 .. t0 + g - 1 (column s: tile t0 + s)
-// on the CG grid, with the moments of P for the operator
-__global__ void __launch_bounds__(CG_BLK) k_pc_indicator(int nslot, int t0, int g,
-                                                         const int* __restrict__ slot_atom,
-                                                         const double* __restrict__ ex,
-                                                         const double* __restrict__ ey,
-                                                         const double* __restrict__ ez,
-                                                         double* __restrict__ P,
-                                                         double* __restrict__ red) {
+// Coarse space: K basis functions per tile, phi[slot * 3 + c] (c < K; 0 on
+// pads): the tile's constant and, for K = 3, the in-plane offsets from the
+// tile's centre (scaled; 0 where a tile is too small or too thin for them).
+// Coarse column j = tile * K + c.
+
+// P = coarse columns j0 .. j0 + g - 1 (vector s: column j0 + s) on the CG
+// grid, with the moments of P for the operator
+__global__ void __launch_bounds__(CG_BLK) k_pc_basis(int nslot, int K, int j0, int g,
+                                                     const int* __restrict__ slot_atom,
+                                                     const double* __restrict__ phi,
+                                                     const double* __restrict__ ex,
+                                                     const double* __restrict__ ey,
+                                                     const double* __restrict__ ez,
+                                                     double* __restrict__ P,
+                                                     double* __restrict__ red) {
   const int s = threadIdx.x & 63;
+  const int j = j0 + s, jt = j / K, jc = j % K;
   double m[4] = {0.0, 0.0, 0.0, 0.0};
   for (Rows w; w.r < nslot; w.r += w.step) {
     const int r = w.r, i = slot_atom[r];
-    const double p = (i >= 0 && s < g && (r >> 6) == t0 + s) ? 1.0 : 0.0;
+    const double p = (i >= 0 && s < g && (r >> 6) == jt) ? phi[(size_t)r * 3 + jc] : 0.0;
     P[(size_t)r * VL + s] = p;
     if (i >= 0) add_moments(m, p, i, ex, ey, ez);
   }
@@ -809,27 +816,35 @@ __global__ void __launch_bounds__(CG_BLK) k_pc_indicator(int nslot, int t0, int 
 }
 
 // sums over the 64 rows of tile blockIdx.x of V (256 threads; fixed order:
-// wave w adds rows w, w + 4, ..., then the 4 waves in order); thread s < 64
-// gets the sum of vector s
-__device__ inline double tile_sum(const double* __restrict__ V, double (*sh)[VL]) {
+// wave w adds rows w, w + 4, ..., then the 4 waves in order), weighted by
+// the basis function c (phi = nullptr: weight 1); thread s < 64 gets the sum
+// of vector s
+__device__ inline double tile_sum(const double* __restrict__ V, double (*sh)[VL],
+                                  const double* __restrict__ phi = nullptr, int c = 0,
+                                  int tile = -1) {
   const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const size_t base = (size_t)blockIdx.x * 64;
+  const size_t base = (size_t)(tile >= 0 ? tile : blockIdx.x) * 64;
   double a = 0.0;
-  for (int r = w; r < 64; r += 4) a += V[(base + r) * VL + s];
+  for (int r = w; r < 64; r += 4)
+    a += (phi ? phi[(base + r) * 3 + c] : 1.0) * V[(base + r) * VL + s];
+  __syncthreads();
   sh[w][s] = a;
   __syncthreads();
   return (sh[0][s] + sh[1][s]) + (sh[2][s] + sh[3][s]);
 }
 
-// C[t ld + t0 + s] = sum over tile t of V's vector s (s < g): rows of
-// Z^T A Z from V = A (indicators of tiles t0 ..)
-__global__ void __launch_bounds__(256) k_pc_coarse_cols(int ld, int t0, int g,
+// C[(t K + c) ld + j0 + s] = sum over tile t of phi_c V's vector s (s < g):
+// rows of Z^T A Z from V = A (coarse columns j0 ..)
+__global__ void __launch_bounds__(256) k_pc_coarse_cols(int ld, int K, int j0, int g,
+                                                        const double* __restrict__ phi,
                                                         const double* __restrict__ V,
                                                         double* __restrict__ C) {
   __shared__ double sh[4][VL];
-  const double a = tile_sum(V, sh);
   const int s = threadIdx.x;
-  if (s < g) C[(size_t)blockIdx.x * ld + t0 + s] = a;
+  for (int c = 0; c < K; ++c) {
+    const double a = tile_sum(V, sh, phi, c);
+    if (s < g) C[((size_t)blockIdx.x * K + c) * ld + j0 + s] = a;
+  }
 }
 
 // B = (C + C^T) / 2 on the leading T x T block (row stride ld)
@@ -837,7 +852,10 @@ __global__ void k_pc_sym(int T, int ld, const double* __restrict__ C, double* __
   const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (size_t)T * T) return;
   const int i = (int)(e / T), j = (int)(e % T);
-  B[(size_t)i * ld + j] = 0.5 * (C[(size_t)i * ld + j] + C[(size_t)j * ld + i]);
+  const double v = 0.5 * (C[(size_t)i * ld + j] + C[(size_t)j * ld + i]);
+  // a basis function that is zero on its tile leaves a zero row and column:
+  // a unit diagonal there keeps C invertible and that coarse entry inert
+  B[(size_t)i * ld + j] = (i == j && v == 0.0) ? 1.0 : v;
 }
 
 // one Gauss-Jordan step (pivot k, no pivoting: C is positive definite) from
@@ -928,42 +946,80 @@ __global__ void __launch_bounds__(256) k_bnn_y(int ntile, int ld, const double* 
   store_tile(acc, Ypart + ((size_t)part * ld + m0) * VL);
 }
 
-// y = the sum of the parts, t = Z^T r (tile sums of R; 0 beyond the tiles);
-// grid Tp, 256 threads
-__global__ void __launch_bounds__(256) k_bnn_sum(int ntile, int ld, int nparts,
+// -y = minus the sum of the parts, t = Z^T r (the basis-weighted tile sums of
+// R; 0 beyond the ntile * K coarse columns); grid ld, 256 threads
+__global__ void __launch_bounds__(256) k_bnn_sum(int ntile, int K, int ld, int nparts,
+                                                 const double* __restrict__ phi,
                                                  const double* __restrict__ Ypart,
                                                  const double* __restrict__ R,
-                                                 double* __restrict__ Y, double* __restrict__ Tt) {
+                                                 double* __restrict__ Yn, double* __restrict__ Tt) {
   __shared__ double sh[4][VL];
   __shared__ double sy[4][VL];
   const int u = blockIdx.x, s = threadIdx.x & 63, w = threadIdx.x >> 6;
   double a = 0.0;
   for (int p = w; p < nparts; p += 4) a += Ypart[((size_t)p * ld + u) * VL + s];
   sy[w][s] = a;
-  const double tt = u < ntile ? tile_sum(R, sh) : 0.0;   // syncs inside (uniform branch)
+  // uniform branch: tile_sum synchronises inside
+  const double tt = u < ntile * K ? tile_sum(R, sh, K > 1 ? phi : nullptr, u % K, u / K) : 0.0;
   __syncthreads();
   if (threadIdx.x < VL) {
-    Y[(size_t)u * VL + s] = (sy[0][s] + sy[1][s]) + (sy[2][s] + sy[3][s]);
+    Yn[(size_t)u * VL + s] = -((sy[0][s] + sy[1][s]) + (sy[2][s] + sy[3][s]));
     Tt[(size_t)u * VL + s] = tt;
   }
 }
 
-// coarse vectors (KB): Wn = -C^-1 t, G = H t - C^-1 y; grid Tp, CG_WAVES waves
-__global__ void __launch_bounds__(CG_BLK) k_bnn_coarse(int ld, const double* __restrict__ Cinv,
-                                                       const double* __restrict__ H,
-                                                       const double* __restrict__ Tt,
-                                                       const double* __restrict__ Y,
-                                                       double* __restrict__ Wn,
-                                                       double* __restrict__ G) {
+// coarse vectors (KB) on the matrix cores, 64 coarse rows per workgroup:
+// blockIdx.y = 0: Wn = -C^-1 t; 1: G = H t + C^-1 (-y); grid (ld / 64, 2,
+// parts): part p adds the coarse columns [p ld / parts, (p + 1) ld / parts)
+// (multiples of 16) into its own slice of Out (parts > 1), or writes Wn and G
+// directly (parts = 1)
+__global__ void __launch_bounds__(256) k_bnn_coarse(int ld, const double* __restrict__ Cinv,
+                                                    const double* __restrict__ H,
+                                                    const double* __restrict__ Tt,
+                                                    const double* __restrict__ Yn,
+                                                    double* __restrict__ Wn,
+                                                    double* __restrict__ G,
+                                                    double* __restrict__ Out) {
+  __shared__ double As[16][68];
+  __shared__ double Bs[16][68];
+  const size_t u0 = (size_t)blockIdx.x * 64;
+  const int np = gridDim.z, p = blockIdx.z;
+  const int q16 = ld / 16, kb = q16 * p / np * 16, kl = q16 * (p + 1) / np * 16 - kb;
+  v4d acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) acc[a][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  if (blockIdx.y == 0) {
+    seg_mfma<false>(acc, Cinv + u0 * ld + kb, ld, Tt + (size_t)kb * VL, kl, As, Bs);
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) acc[a][b] = -acc[a][b];
+  } else {
+    seg_mfma<false>(acc, H + u0 * ld + kb, ld, Tt + (size_t)kb * VL, kl, As, Bs);
+    seg_mfma<false>(acc, Cinv + u0 * ld + kb, ld, Yn + (size_t)kb * VL, kl, As, Bs);
+  }
+  if (np == 1)
+    store_tile(acc, (blockIdx.y == 0 ? Wn : G) + u0 * VL);
+  else
+    store_tile(acc, Out + (((size_t)p * 2 + blockIdx.y) * ld + u0) * VL);
+}
+
+// The same for short coarse spaces (ld <= 128), on the vector units with a
+// workgroup per coarse row (more workgroups than the matrix-core form has):
+// grid ld, CG_WAVES waves
+__global__ void __launch_bounds__(CG_BLK) k_bnn_coarse_rows(int ld, const double* __restrict__ Cinv,
+                                                            const double* __restrict__ H,
+                                                            const double* __restrict__ Tt,
+                                                            const double* __restrict__ Yn,
+                                                            double* __restrict__ Wn,
+                                                            double* __restrict__ G) {
   __shared__ double s1[CG_WAVES][VL];
   __shared__ double s2[CG_WAVES][VL];
   const int u = blockIdx.x, s = threadIdx.x & 63, w = threadIdx.x >> 6;
   double a = 0.0, b = 0.0;
   for (int v = w; v < ld; v += CG_WAVES) {
     const double c = Cinv[(size_t)u * ld + v], h = H[(size_t)u * ld + v];
-    const double tv = Tt[(size_t)v * VL + s], yv = Y[(size_t)v * VL + s];
+    const double tv = Tt[(size_t)v * VL + s];
     a += c * tv;
-    b += h * tv - c * yv;
+    b += h * tv + c * Yn[(size_t)v * VL + s];
   }
   s1[w][s] = a;
   s2[w][s] = b;
@@ -974,10 +1030,25 @@ __global__ void __launch_bounds__(CG_BLK) k_bnn_coarse(int ld, const double* __r
   }
 }
 
-// z per tile (KC): Z_t = D_t^-1 R_t + DAZ_t Wn + g_t on real slots (pads 0),
+// Wn and G from the parts of k_bnn_coarse (added in part order)
+__global__ void k_bnn_coarse_sum(int ld, int np, const double* __restrict__ Out,
+                                 double* __restrict__ Wn, double* __restrict__ G) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x, m = (size_t)ld * VL;
+  if (e >= 2 * m) return;
+  const int y = (int)(e / m);
+  const size_t o = e % m;
+  double a = 0.0;
+  for (int p = 0; p < np; ++p) a += Out[((size_t)p * 2 + y) * m + o];
+  (y == 0 ? Wn : G)[o] = a;
+}
+
+// z per tile (KC): Z_t = D_t^-1 R_t + DAZ_t Wn + sum_c phi_c g_(t K + c) on
+// real slots (pads 0),
 // on the matrix cores; block partials of r.z into field fnew and of sum z
 // into F_ZSUM (grid: tiles, 256 threads)
-__global__ void __launch_bounds__(256) k_bnn_z(int ld, int fnew, const int* __restrict__ slot_atom,
+__global__ void __launch_bounds__(256) k_bnn_z(int ld, int K, int fnew,
+                                               const int* __restrict__ slot_atom,
+                                               const double* __restrict__ phi,
                                                const double* __restrict__ Dinv,
                                                const double* __restrict__ DAZ,
                                                const double* __restrict__ Wn,
@@ -1004,11 +1075,18 @@ __global__ void __launch_bounds__(256) k_bnn_z(int ld, int fnew, const int* __re
   }
   __syncthreads();
   const int s = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double gt = G[t * VL + s];
+  double gt[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < K; ++c) gt[c] = G[(t * K + c) * VL + s];
   double rz = 0.0, zsum = 0.0;
   for (int r = w; r < 64; r += 4) {
     const size_t o = (t * 64 + r) * VL + s;
-    const double z = slot_atom[t * 64 + r] >= 0 ? zs[r][s] + gt : 0.0;
+    double cg = gt[0];
+    if (K > 1) {
+      const double* ph = phi + (t * 64 + r) * 3;
+      cg = gt[0] * ph[0];
+      for (int c = 1; c < K; ++c) cg += gt[c] * ph[c];
+    }
+    const double z = slot_atom[t * 64 + r] >= 0 ? zs[r][s] + cg : 0.0;
     Z[o] = z;
     rz += R[o] * z;
     zsum += z;
@@ -1147,15 +1225,16 @@ void launch_pc_blocks(hipStream_t st, int ntile, int nslot, int nlayers, int nco
                      background, cdip[0], cdip[1], cdip[2], ke, Dinv);
 }
 
-void launch_pc_indicator(hipStream_t st, int nblk, int nslot, int t0, int g, const int* slot_atom,
-                         const Buffers& b, double* P, double* red) {
-  hipLaunchKernelGGL(k_pc_indicator, dim3(nblk), dim3(CG_BLK), 0, st, nslot, t0, g, slot_atom,
+void launch_pc_basis(hipStream_t st, int nblk, int nslot, int K, int j0, int g,
+                     const int* slot_atom, const double* phi, const Buffers& b, double* P,
+                     double* red) {
+  hipLaunchKernelGGL(k_pc_basis, dim3(nblk), dim3(CG_BLK), 0, st, nslot, K, j0, g, slot_atom, phi,
                      b.ex, b.ey, b.ez, P, red);
 }
 
-void launch_pc_coarse_cols(hipStream_t st, int ntile, int ld, int t0, int g, const double* V,
-                           double* C) {
-  hipLaunchKernelGGL(k_pc_coarse_cols, dim3(ntile), dim3(256), 0, st, ld, t0, g, V, C);
+void launch_pc_coarse_cols(hipStream_t st, int ntile, int ld, int K, int j0, int g,
+                           const double* phi, const double* V, double* C) {
+  hipLaunchKernelGGL(k_pc_coarse_cols, dim3(ntile), dim3(256), 0, st, ld, K, j0, g, phi, V, C);
 }
 
 double* launch_pc_invert(hipStream_t st, int ntile, int ld, double* C, double* W) {
@@ -1179,15 +1258,26 @@ void launch_pc_apply(hipStream_t st, int ntile, int ld, int parity, const int* s
                      slot_atom, Cinv, ZtR, R, Z, red);
 }
 
-void launch_bnn_apply(hipStream_t st, int ntile, int ld, int nparts, int parity,
-                      const int* slot_atom, const double* Dinv, const double* DAZ,
-                      const double* Cinv, const double* H, const double* R, double* Z,
-                      double* Ypart, double* Y, double* Tt, double* Wn, double* G, double* red) {
+void launch_bnn_apply(hipStream_t st, int ntile, int K, int ld, int nparts, int cparts,
+                      int parity, const int* slot_atom, const double* phi, const double* Dinv,
+                      const double* DAZ, const double* Cinv, const double* H, const double* R,
+                      double* Z, double* Ypart, double* Yn, double* Tt, double* Wn, double* G,
+                      double* Cpart, double* red) {
   hipLaunchKernelGGL(k_bnn_y, dim3(ld / 64, nparts), dim3(256), 0, st, ntile, ld, DAZ, R, Ypart);
-  hipLaunchKernelGGL(k_bnn_sum, dim3(ld), dim3(256), 0, st, ntile, ld, nparts, Ypart, R, Y, Tt);
-  hipLaunchKernelGGL(k_bnn_coarse, dim3(ld), dim3(CG_BLK), 0, st, ld, Cinv, H, Tt, Y, Wn, G);
-  hipLaunchKernelGGL(k_bnn_z, dim3(ntile), dim3(256), 0, st, ld, F_RZ + parity, slot_atom, Dinv,
-                     DAZ, Wn, G, R, Z, red);
+  hipLaunchKernelGGL(k_bnn_sum, dim3(ld), dim3(256), 0, st, ntile, K, ld, nparts, phi, Ypart, R,
+                     Yn, Tt);
+  if (ld <= 128)
+    hipLaunchKernelGGL(k_bnn_coarse_rows, dim3(ld), dim3(CG_BLK), 0, st, ld, Cinv, H, Tt, Yn, Wn, G);
+  else
+    hipLaunchKernelGGL(k_bnn_coarse, dim3(ld / 64, 2, cparts), dim3(256), 0, st, ld, Cinv, H, Tt,
+                       Yn, Wn, G, Cpart);
+  if (ld > 128 && cparts > 1) {
+    const size_t tot = (size_t)2 * ld * VL;
+    hipLaunchKernelGGL(k_bnn_coarse_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, ld,
+                       cparts, Cpart, Wn, G);
+  }
+  hipLaunchKernelGGL(k_bnn_z, dim3(ntile), dim3(256), 0, st, ld, K, F_RZ + parity, slot_atom, phi,
+                     Dinv, DAZ, Wn, G, R, Z, red);
 }
 
 }  // namespace cpm

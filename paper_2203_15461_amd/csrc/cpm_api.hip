@@ -308,14 +308,67 @@ cpm_status ensure_cg_buffers(cpm_ctx* c) {
 // ld = tiles rounded up to 64 and are zero beyond the tiles.  Operators
 // with more than PC_MAX_TILES tiles run without a preconditioner.
 constexpr int PC_MAX_TILES = 2048;
+// From this many tiles on, the balancing form also takes the in-plane
+// offsets into its coarse space: at 20064 atoms (318 tiles) 46 -> 34
+// iterations outweigh the threefold coarse products (1580 -> 1720 solves/s);
+// at 2880 atoms (48 tiles), 37 -> 29 iterations do not (13.5k -> 13.0k).
+constexpr int PC_COARSE3_TILES = 128;
 
 cpm_status ensure_precond(cpm_ctx* c) {
   if (c->pc_ready) return CPM_OK;
   c->pc_tiles = 0;
   c->pc_mode = 0;
-  const int nslot = c->nmap, T = nslot / 64, ld = (T + 63) / 64 * 64;
+  const int nslot = c->nmap, T = nslot / 64;
   if (!c->have_op || c->cg_precond <= 0 || T > PC_MAX_TILES) return CPM_OK;
   const bool bal = c->cg_precond >= 2;
+  // basis functions per tile: the constant, and for the balancing form the
+  // two in-plane offsets from the tile's centre (scaled by the tile's RMS
+  // radius; left out, as zero functions, for tiles with fewer than 8 atoms
+  // or a spread more than 10x longer than wide)
+  const int kwant = c->pc_k > 0 ? c->pc_k : (T >= PC_COARSE3_TILES ? 3 : 1);
+  const int K = bal && (size_t)T * kwant <= 2 * (size_t)PC_MAX_TILES ? kwant : 1;
+  const int Tk = T * K, ld = (Tk + 63) / 64 * 64;
+  std::vector<double> phi((size_t)nslot * 3, 0.0);
+  for (int t = 0; t < T; ++t) {
+    std::vector<int> rs;
+    for (int r = t * 64; r < t * 64 + 64; ++r)
+      if (c->h_amap[r] >= 0) rs.push_back(r);
+    for (int r : rs) phi[(size_t)r * 3] = 1.0;
+    if (K < 3 || rs.size() < 8) continue;
+    const double Lx = c->p.Lx, Ly = c->p.Ly;
+    const int i0 = c->h_amap[rs[0]];
+    std::vector<double> dx, dy;
+    double mx = 0.0, my = 0.0;
+    for (int r : rs) {
+      const int i = c->h_amap[r];
+      double ux = c->h_xyz[3 * i] - c->h_xyz[3 * i0], uy = c->h_xyz[3 * i + 1] - c->h_xyz[3 * i0 + 1];
+      ux -= Lx * std::rint(ux / Lx);
+      uy -= Ly * std::rint(uy / Ly);
+      dx.push_back(ux);
+      dy.push_back(uy);
+      mx += ux;
+      my += uy;
+    }
+    mx /= rs.size();
+    my /= rs.size();
+    double sxx = 0.0, syy = 0.0, sxy = 0.0;
+    for (size_t q = 0; q < rs.size(); ++q) {
+      dx[q] -= mx;
+      dy[q] -= my;
+      sxx += dx[q] * dx[q];
+      syy += dy[q] * dy[q];
+      sxy += dx[q] * dy[q];
+    }
+    const double tr = sxx + syy, det = sxx * syy - sxy * sxy;
+    const double disc = std::sqrt(std::max(0.0, 0.25 * tr * tr - det));
+    const double lmax = 0.5 * tr + disc, lmin = 0.5 * tr - disc;
+    if (!(lmax > 0.0) || lmin < 0.01 * lmax) continue;
+    const double h = std::sqrt(tr / rs.size());
+    for (size_t q = 0; q < rs.size(); ++q) {
+      phi[(size_t)rs[q] * 3 + 1] = dx[q] / h;
+      phi[(size_t)rs[q] * 3 + 2] = dy[q] / h;
+    }
+  }
   Buffers& b = c->b;
   hipStream_t st = c->stream;
   if ((int)c->h_tile_plane.size() != T || (int)c->h_bdiag.size() != T)
@@ -326,6 +379,9 @@ cpm_status ensure_precond(cpm_ctx* c) {
   TRY(dalloc(c, &b.pc_C, ld2));
   TRY(dalloc(c, &b.pc_W, ld2));
   TRY(dalloc(c, &b.pc_ztr, (size_t)ld * CG_MAXG));
+  TRY(dalloc(c, &b.pc_phi, phi.size()));
+  HIP_TRY(c, hipMemcpyAsync(b.pc_phi, phi.data(), phi.size() * sizeof(double),
+                            hipMemcpyHostToDevice, st));
   TRY(dalloc(c, &b.pc_tplane, (size_t)T));
   TRY(dalloc(c, &b.pc_dblk, (size_t)T));
   HIP_TRY(c, hipMemsetAsync(b.pc_C, 0, ld2 * sizeof(double), st));
@@ -348,17 +404,17 @@ cpm_status ensure_precond(cpm_ctx* c) {
   }
   const int nb = cg_grid(c);
   { Timed t(c, "pc_coarse_matrix");
-    for (int t0 = 0; t0 < T; t0 += CG_MAXG) {
-      const int g = std::min(CG_MAXG, T - t0);
-      launch_pc_indicator(st, nb, nslot, t0, g, b.amap, b, P, b.cgred);
+    for (int j0 = 0; j0 < Tk; j0 += CG_MAXG) {
+      const int g = std::min(CG_MAXG, Tk - j0);
+      launch_pc_basis(st, nb, nslot, K, j0, g, b.amap, b.pc_phi, b, P, b.cgred);
       apply_A(c, P, AP, false);
-      launch_pc_coarse_cols(st, T, ld, t0, g, AP, b.pc_C);
+      launch_pc_coarse_cols(st, T, ld, K, j0, g, b.pc_phi, AP, b.pc_C);
       if (bal)
-        HIP_TRY(c, hipMemcpy2DAsync(AZ + t0, (size_t)ld * sizeof(double), AP,
+        HIP_TRY(c, hipMemcpy2DAsync(AZ + j0, (size_t)ld * sizeof(double), AP,
                                     CG_MAXG * sizeof(double), (size_t)g * sizeof(double), nslot,
                                     hipMemcpyDeviceToDevice, st));
     }
-    c->pc_Cinv = launch_pc_invert(st, T, ld, b.pc_C, b.pc_W); }
+    c->pc_Cinv = launch_pc_invert(st, Tk, ld, b.pc_C, b.pc_W); }
   TRY(launched(c, "preconditioner coarse matrix"));
   if (bal) {
     Timed t(c, "pc_balancing");
@@ -369,6 +425,11 @@ cpm_status ensure_precond(cpm_ctx* c) {
     TRY(dalloc(c, &b.pc_y, (size_t)ld * CG_MAXG));
     TRY(dalloc(c, &b.pc_wn, (size_t)ld * CG_MAXG));
     TRY(dalloc(c, &b.pc_g, (size_t)ld * CG_MAXG));
+    // coarse products split over coarse columns in parts of ~64 once they
+    // are long (a single workgroup row would run them serially)
+    const int cp = ld >= 256 ? ld / 64 : 1;
+    if (cp > 1) TRY(dalloc(c, &b.pc_cpart, (size_t)cp * 2 * ld * CG_MAXG));
+    c->pc_cparts = cp;
     double* Gm = nullptr;                 // (A Z)^T DAZ, then C^-1 of it
     double* X = nullptr;
     TRY(dalloc(c, &Gm, ld2));
@@ -392,6 +453,7 @@ cpm_status ensure_precond(cpm_ctx* c) {
   HIP_TRY(c, hipStreamSynchronize(st));
   c->pc_tiles = T;
   c->pc_ld = ld;
+  c->pc_kuse = K;
   c->pc_mode = bal ? 2 : 1;
   c->pc_ready = true;
   return CPM_OK;
@@ -402,9 +464,9 @@ cpm_status ensure_precond(cpm_ctx* c) {
 void precond_apply(cpm_ctx* c, int parity, const double* R, double* Z) {
   Buffers& b = c->b;
   if (c->pc_mode == 2)
-    launch_bnn_apply(c->stream, c->pc_tiles, c->pc_ld, c->pc_nparts, parity, b.amap, b.pc_dinv,
-                     b.pc_daz, c->pc_Cinv, b.pc_H, R, Z, b.pc_ypart, b.pc_y, b.pc_ztr, b.pc_wn,
-                     b.pc_g, b.cgred);
+    launch_bnn_apply(c->stream, c->pc_tiles, c->pc_kuse, c->pc_ld, c->pc_nparts, c->pc_cparts,
+                     parity, b.amap, b.pc_phi, b.pc_dinv, b.pc_daz, c->pc_Cinv, b.pc_H, R, Z,
+                     b.pc_ypart, b.pc_y, b.pc_ztr, b.pc_wn, b.pc_g, b.pc_cpart, b.cgred);
   else
     launch_pc_apply(c->stream, c->pc_tiles, c->pc_ld, parity, b.amap, b.pc_dinv, c->pc_Cinv, R, Z,
                     b.pc_ztr, b.cgred);
@@ -619,6 +681,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_CG_COARSE")) c->pc_k = std::atoi(ev) >= 3 ? 3 : 1;
   if (const char* ev = std::getenv("CPM_CG_GRAPH")) c->cg_graphs = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_CG_PRECOND")) c->cg_precond = std::max(0, std::min(2, std::atoi(ev)));
   if (const char* ev = std::getenv("CPM_CHOL_BLOCK"))
@@ -851,9 +914,10 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
   dfree(c, b0.zperm); dfree(c, b0.cq); dfree(c, b0.zr);
   dfree(c, b0.cg_ident); dfree(c, b0.cgv); dfree(c, b0.cgred); dfree(c, b0.cgscal);
   dfree(c, b0.cgphi); dfree(c, b0.cgY); dfree(c, b0.cgT);
-  dfree(c, b0.pc_dinv); dfree(c, b0.pc_C); dfree(c, b0.pc_W); dfree(c, b0.pc_ztr);
+  dfree(c, b0.pc_phi); dfree(c, b0.pc_dinv); dfree(c, b0.pc_C); dfree(c, b0.pc_W); dfree(c, b0.pc_ztr);
   dfree(c, b0.pc_tplane); dfree(c, b0.pc_dblk); dfree(c, b0.pc_daz); dfree(c, b0.pc_H);
   dfree(c, b0.pc_ypart); dfree(c, b0.pc_y); dfree(c, b0.pc_wn); dfree(c, b0.pc_g);
+  dfree(c, b0.pc_cpart);
   c->pc_ready = false;
   c->pc_tiles = 0;
   c->pc_Cinv = nullptr;
@@ -2072,6 +2136,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_BSR_BLOCKS: *out = c->bsr_blocks; return CPM_OK;
     case CPM_INFO_PC_TILES: *out = c->pc_tiles; return CPM_OK;
     case CPM_INFO_PC_MODE: *out = c->pc_mode; return CPM_OK;
+    case CPM_INFO_PC_COARSE: *out = (double)c->pc_tiles * c->pc_kuse; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -2114,9 +2179,9 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.bsr_col); dfree(b.bsr_val); dfree(b.cg_items); dfree(b.asmG); dfree(b.asmF);
   dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);
   dfree(b.cgscal); dfree(b.cgphi); dfree(b.cgY); dfree(b.cgT);
-  dfree(b.pc_dinv); dfree(b.pc_C); dfree(b.pc_W); dfree(b.pc_ztr); dfree(b.pc_tplane);
+  dfree(b.pc_phi); dfree(b.pc_dinv); dfree(b.pc_C); dfree(b.pc_W); dfree(b.pc_ztr); dfree(b.pc_tplane);
   dfree(b.pc_dblk); dfree(b.pc_daz); dfree(b.pc_H); dfree(b.pc_ypart); dfree(b.pc_y);
-  dfree(b.pc_wn); dfree(b.pc_g);
+  dfree(b.pc_wn); dfree(b.pc_g); dfree(b.pc_cpart);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
   if (c->graph) (void)hipGraphDestroy(c->graph);

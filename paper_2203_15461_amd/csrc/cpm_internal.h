@@ -132,6 +132,7 @@ struct Buffers {
   double* cgY = nullptr;           // plane sums (ksplit x nlayers x 2 ncp x CG_MAXG)
   double* cgT = nullptr;           // plane-mixed sums (same shape)
   double* pc_dinv = nullptr;       // preconditioner: inverse tile blocks (ntile x 64 x 64)
+  double* pc_phi = nullptr;        //   coarse basis functions per slot (nslot x 3)
   double* pc_C = nullptr;          // coarse matrix and its inverse, two ntile x ntile buffers
   double* pc_W = nullptr;
   double* pc_ztr = nullptr;        // tile sums of r (ntile x CG_MAXG)
@@ -143,6 +144,7 @@ struct Buffers {
   double* pc_y = nullptr;          //   their sum, and the coarse vectors w, g (ld x CG_MAXG)
   double* pc_wn = nullptr;
   double* pc_g = nullptr;
+  double* pc_cpart = nullptr;      //   parts of the coarse products (cparts x 2 x ld x CG_MAXG)
   size_t kpart_len = 0;
   int bpad_rows = 0;
   double* scal = nullptr;          // small scalars (s and friends)
@@ -189,10 +191,10 @@ void launch_cg_dir(hipStream_t st, int nblk, int nslot, int n, int cur, double t
                    const double* Z, double* P, double* red, double* scal);
 // two-level preconditioner over the ntile slot tiles: inverses of A's
 // 64 x 64 diagonal tile blocks (from the operator's pieces); the coarse
-// matrix C = Z^T A Z (Z: tile indicators, row stride ld >= ntile) column
-// block by column block from A applied to indicator vectors; C^-1 by
-// Gauss-Jordan steps on the leading ntile x ntile block (C and W both hold
-// it; returns the one with C^-1).  Per iteration Z = M^-1 R with partials of
+// matrix C = Z^T A Z (Z: K basis functions per tile, phi[slot * 3 + c];
+// row stride ld >= ntile K) column block by column block from A applied to
+// the basis vectors; C^-1 by Gauss-Jordan steps on the leading block (C and
+// W both hold it; returns the one with C^-1).  Per iteration Z = M^-1 R with partials of
 // r.z (field of parity `parity`) and of sum z: additive form
 // (launch_pc_apply), or balancing form with DAZ = B A Z and H (ld a
 // multiple of 64; Ypart: nparts x ld x 64, Y, Tt, Wn, G: ld x 64)
@@ -200,18 +202,20 @@ void launch_pc_blocks(hipStream_t st, int ntile, int nslot, int nlayers, int nco
                       const int* slot_atom, const int* tile_plane, const int* diag_blk,
                       const double* bval, const double* Ecat, const double2* Q, const Buffers& b,
                       double background, const double* cdip, double ke, double* Dinv);
-void launch_pc_indicator(hipStream_t st, int nblk, int nslot, int t0, int g, const int* slot_atom,
-                         const Buffers& b, double* P, double* red);
-void launch_pc_coarse_cols(hipStream_t st, int ntile, int ld, int t0, int g, const double* V,
-                           double* C);
+void launch_pc_basis(hipStream_t st, int nblk, int nslot, int K, int j0, int g,
+                     const int* slot_atom, const double* phi, const Buffers& b, double* P,
+                     double* red);
+void launch_pc_coarse_cols(hipStream_t st, int ntile, int ld, int K, int j0, int g,
+                           const double* phi, const double* V, double* C);
 double* launch_pc_invert(hipStream_t st, int ntile, int ld, double* C, double* W);
 void launch_pc_apply(hipStream_t st, int ntile, int ld, int parity, const int* slot_atom,
                      const double* Dinv, const double* Cinv, const double* R, double* Z,
                      double* ZtR, double* red);
-void launch_bnn_apply(hipStream_t st, int ntile, int ld, int nparts, int parity,
-                      const int* slot_atom, const double* Dinv, const double* DAZ,
-                      const double* Cinv, const double* H, const double* R, double* Z,
-                      double* Ypart, double* Y, double* Tt, double* Wn, double* G, double* red);
+void launch_bnn_apply(hipStream_t st, int ntile, int K, int ld, int nparts, int cparts,
+                      int parity, const int* slot_atom, const double* phi, const double* Dinv,
+                      const double* DAZ, const double* Cinv, const double* H, const double* R,
+                      double* Z, double* Ypart, double* Yn, double* Tt, double* Wn, double* G,
+                      double* Cpart, double* red);
 void launch_cg_init(hipStream_t st, int nblk, int nslot, int n, int g, const int* slot_atom,
                     const Buffers& b, const void* bsrc, int b_is_f32, double* X, double* R,
                     double* P, double* red, double* scal);
@@ -263,8 +267,12 @@ struct cpm_ctx {
   int cg_precond = 2;              // operator CG preconditioner: 0 none, 1 additive, 2 balancing
   int pc_tiles = 0;                // tiles of the preconditioner in use (0: none or not built)
   int pc_mode = 0;                 // form in use (1 additive, 2 balancing)
-  int pc_ld = 0;                   // coarse row stride: tiles rounded up to 64
+  int pc_ld = 0;                   // coarse row stride: coarse columns rounded up to 64
+  int pc_k = 0;                    // coarse basis functions per tile (1: constant; 3: + linear;
+                                   // 0: by size, 3 from PC_COARSE3_TILES tiles on)
+  int pc_kuse = 1;                 // ... in use (the additive form uses 1)
   int pc_nparts = 1;               // slot parts of the balancing form's y product
+  int pc_cparts = 1;               // coarse-column parts of its coarse products
   bool pc_ready = false;           // preconditioner built for the current operator
   const double* pc_Cinv = nullptr; // whichever of pc_C / pc_W holds the coarse inverse
   std::vector<int> h_bdiag;        // real-space block of each tile's diagonal (-1: none)

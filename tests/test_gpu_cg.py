@@ -284,34 +284,39 @@ def test_cg_wire_tubes(cpm):
 
 def test_cg_preconditioner_2880(cpm, monkeypatch):
     """The two-level preconditioner (smoother: inverse 64 x 64 diagonal tile
-    blocks; coarse space: tile constants; additive form 1, balancing form 2)
-    changes the iterates, not the solution: without it and in both forms the
-    charges of the 2880-atom capacitor (48 tiles: coarse arrays padded to 64)
-    match the stored oracle charges, and each form takes fewer iterations
-    than the one before."""
+    blocks; coarse space: tile constants, or constants and in-plane offsets;
+    additive form 1, balancing form 2) changes the iterates, not the
+    solution: without it and in every form the charges of the 2880-atom
+    capacitor (48 tiles: coarse arrays of 48 or 144 columns padded to 64 or
+    192) match the stored oracle charges, and each variant takes fewer
+    iterations than the one before."""
     if not os.path.exists(GOLDEN):
         pytest.skip("golden file missing: run tests/golden/make_golden.py")
     g = dict(np.load(GOLDEN))
     w = I.graphite_capacitor()
     snaps = [int(s) for s in g["snapshots"]]
     iters = {}
-    for pc in ("0", "1", "2"):
+    for pc, coarse in (("0", 1), ("1", 1), ("2", 1), ("2", 3)):
         monkeypatch.setenv("CPM_CG_PRECOND", pc)
-        say(f"cg graphite_capacitor_2880, preconditioner {pc}")
+        monkeypatch.setenv("CPM_CG_COARSE", str(coarse))
+        say(f"cg graphite_capacitor_2880, preconditioner {pc}, coarse functions per tile {coarse}")
         ctx = cpm.setup(w, matrix_free=True)
         b = _b(ctx, w, snaps)
         q = torch.empty_like(b)
         Qe = torch.empty((len(snaps), 2), dtype=torch.float64, device="cuda")
-        iters[pc], res = ctx.solve_cg(b, q, Qe, tol=1e-13)
-        tiles, mode = ctx.info("pc_tiles"), ctx.info("pc_mode")
-        say(f"  iterations {iters[pc]}, residual {res:.2e}, tiles {tiles:.0f}, form {mode:.0f}")
+        key = pc + str(coarse)
+        iters[key], res = ctx.solve_cg(b, q, Qe, tol=1e-13)
+        tiles, mode, ncoarse = ctx.info("pc_tiles"), ctx.info("pc_mode"), ctx.info("pc_coarse")
+        say(f"  iterations {iters[key]}, residual {res:.2e}, tiles {tiles:.0f}, form {mode:.0f}, "
+            f"coarse columns {ncoarse:.0f}")
         assert res <= 1e-13
         assert mode == int(pc) and tiles == (48 if pc != "0" else 0)
+        assert ncoarse == tiles * coarse
         assert rel(q.cpu().numpy(), g["q"]) < 1e-10
         assert rel(Qe.cpu().numpy(), g["Q"]) < 1e-10
         assert np.abs(q.cpu().numpy().sum(axis=1)).max() <= 1e-12
         ctx.close()
-    assert iters["2"] < iters["1"] < iters["0"]
+    assert iters["23"] < iters["21"] < iters["11"] < iters["01"]
 
 
 def test_operator_rebuild_with_other_plane_sizes(cpm):
