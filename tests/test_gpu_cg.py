@@ -389,3 +389,27 @@ def test_cg_iteration_graphs_match_eager(cpm, monkeypatch):
         idx = [snaps.index(int(s)) for s in g["snapshots"] if int(s) in snaps]
         if idx:
             assert rel(out["null"][0][1][idx], g["q"][:len(idx)]) < 1e-10
+
+
+def test_cg_large_coarse_space_matches_direct(cpm):
+    """8400-atom capacitor (132 tiles): the balancing form takes the in-plane
+    offsets into its coarse space by itself (396 coarse functions, so the
+    coarse products run split over the coarse columns); its charges match
+    the direct FP64 solve q = S (b + v) on the same b, which the 2880-atom
+    case ties to the oracle."""
+    w = I.scaled_graphite_capacitor(8500)
+    say(f"cg with the large coarse space, n={w.n}")
+    direct = cpm.setup(w)
+    ctx = cpm.setup(w, matrix_free=True)
+    b = _b(direct, w, [0, 1, 2])
+    qd = torch.empty_like(b)
+    direct.solve_charges(b, 0, qd)
+    q = torch.empty_like(b)
+    iters, res = ctx.solve_cg(b, q, tol=1e-13)
+    tiles, ncoarse = ctx.info("pc_tiles"), ctx.info("pc_coarse")
+    say(f"  iterations {iters}, tiles {tiles:.0f}, coarse functions {ncoarse:.0f}")
+    assert tiles == 132 and ncoarse == 3 * 132 and ctx.info("pc_mode") == 2
+    assert rel(q.cpu().numpy(), qd.cpu().numpy()) < 1e-10
+    assert np.abs(q.cpu().numpy().sum(axis=1)).max() <= 1e-12
+    direct.close()
+    ctx.close()
