@@ -699,10 +699,11 @@ __global__ void __launch_bounds__(256) k_cg_totals(int n, const double* __restri
 }
 
 // ---- two-level preconditioner ----------------------------------------------
-// M^-1 r = D_t^-1 r_t on every slot tile t (D_t: A's 64 x 64 diagonal block
-// of the tile's atoms, identity on pad slots) + Z C^-1 Z^T r, Z the tile
-// indicator vectors and C = Z^T A Z.  Both parts are symmetric positive
-// definite, so M^-1 is, and the neutral-subspace iteration stays a CG.
+// Additive form: M^-1 r = D_t^-1 r_t on every slot tile t (D_t: A's 64 x 64
+// diagonal block of the tile's atoms, identity on pad slots) + Z C^-1 Z^T r,
+// Z the coarse basis vectors (the tile constants here) and C = Z^T A Z.
+// Both parts are symmetric positive definite, so M^-1 is, and the
+// neutral-subspace iteration stays a CG.
 
 // D_t^-1 for every tile (grid: tiles, 256 threads).  D_t from the operator's
 // own pieces for atoms i, j of the tile (one plane L):
@@ -924,14 +925,14 @@ __global__ void __launch_bounds__(CG_BLK) k_pc_coarse(int T, int ld, int fnew,
 // both sides of the tile-block smoother B = blockdiag(D_t^-1)):
 //   M^-1 r = Q r + (I - Q A) B (I - A Q) r,   Q = Z C^-1 Z^T,
 // symmetric positive definite like the additive form.  With the set-up
-// products DAZ = B A Z (slots x Tp) and H = C^-1 + C^-1 (A Z)^T DAZ C^-1 it is
+// products DAZ = B A Z (slots x ld) and H = C^-1 + C^-1 (A Z)^T DAZ C^-1 it is
 //   t = Z^T r,  y = DAZ^T r,  w = C^-1 t,  g = H t - C^-1 y,
 //   z = B r - DAZ w + Z g,
-// two products with DAZ per iteration (the coarse arrays are Tp x 64, Tp the
-// tile count rounded up to 64, zero beyond the tiles).
+// two products with DAZ per iteration (the coarse arrays are ld x 64, ld
+// the coarse-space dimension rounded up to 64, zero beyond it).
 
-// y parts (KA): Ypart[(part Tp + m) VL + s] = sum over the slots of part of
-// DAZ[slot][m] R[slot][s]; grid (Tp / 64, parts), tile-aligned slot ranges
+// y parts (KA): Ypart[(part ld + m) VL + s] = sum over the slots of part of
+// DAZ[slot][m] R[slot][s]; grid (ld / 64, parts), tile-aligned slot ranges
 __global__ void __launch_bounds__(256) k_bnn_y(int ntile, int ld, const double* __restrict__ DAZ,
                                                const double* __restrict__ R,
                                                double* __restrict__ Ypart) {

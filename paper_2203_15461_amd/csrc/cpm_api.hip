@@ -302,11 +302,11 @@ cpm_status ensure_cg_buffers(cpm_ctx* c) {
 
 // The two-level preconditioner of the operator's CG, built on first use:
 // inverse diagonal tile blocks B, and the coarse matrix C = Z^T A Z from
-// A Z (A applied to the tile indicators, CG_MAXG tiles per application),
+// A Z (A applied to the coarse basis vectors, CG_MAXG per application),
 // inverted in place; the balancing form also keeps DAZ = B A Z and
-// H = C^-1 + C^-1 (A Z)^T DAZ C^-1.  Coarse arrays have row stride
-// ld = tiles rounded up to 64 and are zero beyond the tiles.  Operators
-// with more than PC_MAX_TILES tiles run without a preconditioner.
+// H = C^-1 + C^-1 (A Z)^T DAZ C^-1.  Coarse arrays have row stride ld = the
+// coarse-space dimension rounded up to 64 and are zero beyond it.
+// Operators with more than PC_MAX_TILES tiles run without a preconditioner.
 constexpr int PC_MAX_TILES = 2048;
 // From this many tiles on, the balancing form also takes the in-plane
 // offsets into its coarse space: at 20064 atoms (318 tiles) 46 -> 34
