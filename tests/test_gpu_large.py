@@ -7,7 +7,8 @@ outputs it can compute one by one, and properties that hold at any size:
 * b for a small neutral electrolyte (60 waters) at the full electrode size and
   full k set, sampled rows against the oracle;
 * q: sum q = 0 and A q - (b + v) uniform (the Lagrange potential), with the
-  device A that the sampled elements pinned.
+  device A that the sampled elements pinned;
+* the operator CG's q against the direct FP64 q on the same b.
 """
 import sys
 
@@ -105,3 +106,37 @@ def test_large_capacitor_full_electrolyte(big):
         assert abs(float(Qe[s].sum().item())) <= 1e-12
     say(f"  Q = {Qe.cpu().numpy()[0]}")
     ctx.close()
+
+
+def test_large_capacitor_cg(big):
+    """The matrix-free CG at full size (318 operator tiles: the balancing
+    preconditioner with 954 coarse functions, coarse products split over the
+    coarse columns) on 2 full-electrolyte snapshots: its charges match the
+    direct FP64 solve q = S (b + v) on the same b, are neutral, and leave a
+    uniform residual against the device A."""
+    from paper_2203_15461_amd import cpm
+    w = big
+    n = w.n
+    say("operator CG at full size")
+    direct = cpm.setup(w)
+    A = direct.copy_matrix(0, torch.empty((n, n), dtype=torch.float64, device="cuda"))
+    xyz = torch.as_tensor(np.stack([I.snapshot(w, s) for s in range(2)]), device="cuda").contiguous()
+    b = torch.empty((2, n), dtype=torch.float64, device="cuda")
+    direct.potential_vector(xyz, b)
+    qd = torch.empty_like(b)
+    direct.solve_charges(b, 0, qd)
+    ctx = cpm.setup(w, matrix_free=True)
+    q = torch.empty_like(b)
+    iters, res = ctx.solve_cg(b, q, tol=1e-13)
+    say(f"  iterations {iters}, tiles {ctx.info('pc_tiles'):.0f}, coarse {ctx.info('pc_coarse'):.0f}")
+    assert ctx.info("pc_mode") == 2 and ctx.info("pc_coarse") == 3 * ctx.info("pc_tiles")
+    qg, qdg = q.cpu().numpy(), qd.cpu().numpy()
+    assert np.max(np.abs(qg - qdg)) <= 1e-10 * np.max(np.abs(qdg))
+    v = torch.as_tensor(O.applied_potential(w.electrode_id, w.v_electrode), device="cuda")
+    for s in range(2):
+        r = torch.mv(A, q[s]) - (b[s] + v)
+        spread = float((r - r.mean()).abs().max().item()) / float((b[s] + v).abs().max().item())
+        assert spread <= 1e-10, spread
+        assert abs(float(q[s].sum().item())) <= 1e-12
+    ctx.close()
+    direct.close()
