@@ -308,6 +308,25 @@ cpm_status ensure_cg_buffers(cpm_ctx* c) {
 // coarse-space dimension rounded up to 64 and are zero beyond it.
 // Operators with more than PC_MAX_TILES tiles run without a preconditioner.
 constexpr int PC_MAX_TILES = 2048;
+
+// a set-up temporary: freed (after the stream has drained) and taken off the
+// context's byte count on every return
+struct DevTemp {
+  cpm_ctx* c;
+  double* p = nullptr;
+  size_t count = 0;
+  explicit DevTemp(cpm_ctx* c_) : c(c_) {}
+  cpm_status alloc(size_t n) {
+    count = n;
+    return dalloc(c, &p, n);
+  }
+  ~DevTemp() {
+    if (!p) return;
+    (void)hipStreamSynchronize(c->stream);
+    dfree(c, p);
+    c->bytes -= count * sizeof(double);
+  }
+};
 // From this many tiles on, the balancing form also takes the in-plane
 // offsets into its coarse space: at 20064 atoms (318 tiles) 46 -> 34
 // iterations outweigh the threefold coarse products (1580 -> 1720 solves/s);
@@ -397,9 +416,10 @@ cpm_status ensure_precond(cpm_ctx* c) {
   TRY(launched(c, "preconditioner blocks"));
   double* P = b.cgv + (size_t)2 * CG_MAXG * nslot;
   double* AP = P + (size_t)CG_MAXG * nslot;
-  double* AZ = nullptr;                   // balancing form: A Z, slots x ld (set-up only)
+  DevTemp azt(c);                         // balancing form: A Z, slots x ld (set-up only)
+  double*& AZ = azt.p;
   if (bal) {
-    TRY(dalloc(c, &AZ, (size_t)nslot * ld));
+    TRY(azt.alloc((size_t)nslot * ld));
     HIP_TRY(c, hipMemsetAsync(AZ, 0, (size_t)nslot * ld * sizeof(double), st));
   }
   const int nb = cg_grid(c);
@@ -430,10 +450,11 @@ cpm_status ensure_precond(cpm_ctx* c) {
     const int cp = ld >= 256 ? ld / 64 : 1;
     if (cp > 1) TRY(dalloc(c, &b.pc_cpart, (size_t)cp * 2 * ld * CG_MAXG));
     c->pc_cparts = cp;
-    double* Gm = nullptr;                 // (A Z)^T DAZ, then C^-1 of it
-    double* X = nullptr;
-    TRY(dalloc(c, &Gm, ld2));
-    TRY(dalloc(c, &X, ld2));
+    DevTemp gmt(c), xt(c);                // (A Z)^T DAZ, and C^-1 times it
+    TRY(gmt.alloc(ld2));
+    TRY(xt.alloc(ld2));
+    double* Gm = gmt.p;
+    double* X = xt.p;
     // DAZ: each tile's rows of A Z times that tile's inverse block
     for (int t = 0; t < T; ++t)
       launch_gemm_f64(st, false, false, 64, ld, 64, 1.0, b.pc_dinv + (size_t)t * 4096, 64,
@@ -444,10 +465,6 @@ cpm_status ensure_precond(cpm_ctx* c) {
     launch_gemm_f64(st, false, false, ld, ld, ld, 1.0, X, ld, c->pc_Cinv, ld, 1.0, b.pc_H, ld, 0, 0);
     TRY(launched(c, "preconditioner balancing products"));
     HIP_TRY(c, hipStreamSynchronize(st));
-    dfree(c, Gm);
-    dfree(c, X);
-    dfree(c, AZ);
-    c->bytes -= (2 * ld2 + (size_t)nslot * ld) * sizeof(double);   // set-up temporaries
     c->pc_nparts = np;
   }
   HIP_TRY(c, hipStreamSynchronize(st));
