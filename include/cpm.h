@@ -206,9 +206,10 @@ cpm_status cpm_apply_elastance(cpm_ctx* ctx, int batch, const double* d_x, doubl
  * stays |r| <= tol |r0| on the unpreconditioned residual.  Operators with
  * more than 2048 tiles and the dense A run plain CG.  Blocks of 8
  * iterations replay one HIP graph, captured on first use for the current
- * buffers, tolerance and preconditioner (environment CPM_CG_GRAPH=0: plain
- * launches; none while kernel timing is on); a context on the NULL stream
- * runs the solve on an internal stream after draining the NULL stream.
+ * buffers, tolerance and preconditioner (environment CPM_CG_GRAPH=0, a
+ * capture the runtime refuses, or kernel timing: plain launches); a context
+ * on the NULL stream runs the solve on an internal stream after draining the
+ * NULL stream.
  * Writes d_q (batch x n FP64, the final
  * iterate projected to e^T q = 0) and, unless NULL, d_Qe (batch x n_e
  * electrode totals).  Synchronous (the host checks convergence every 8

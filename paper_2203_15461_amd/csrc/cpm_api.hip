@@ -2037,25 +2037,36 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
       // block (it even) replays one captured graph of its 8 iterations when
       // the context has its own stream and timing is off.
       const int blk = std::min(8, maxit - it);
-      if (blk == 8 && c->cg_graphs && st && !c->timing) {
-        if (!c->cg_graph_exec || c->cg_graph_gen != c->alloc_gen || c->cg_graph_tol2 != tol2 ||
-            c->cg_graph_npc != npc) {
-          if (c->cg_graph_exec) { (void)hipGraphExecDestroy(c->cg_graph_exec); c->cg_graph_exec = nullptr; }
-          if (c->cg_graph) { (void)hipGraphDestroy(c->cg_graph); c->cg_graph = nullptr; }
-          HIP_TRY(c, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-          for (int k = 0; k < 8; ++k) iteration(k & 1);
-          hipGraph_t gr = nullptr;
-          const hipError_t e = hipStreamEndCapture(st, &gr);
-          if (e != hipSuccess) {
-            if (gr) (void)hipGraphDestroy(gr);
-            return fail(c, CPM_EHIP, "capture of the CG iterations: %s", hipGetErrorString(e));
-          }
-          c->cg_graph = gr;
-          HIP_TRY(c, hipGraphInstantiate(&c->cg_graph_exec, gr, nullptr, nullptr, 0));
-          c->cg_graph_gen = c->alloc_gen;
-          c->cg_graph_tol2 = tol2;
-          c->cg_graph_npc = npc;
+      // (re)capture the block's graph when stale; a capture or instantiation
+      // that fails turns the graphs off for this context (nothing captured
+      // has run), and the block runs eagerly
+      auto capture = [&]() {
+        if (c->cg_graph_exec) { (void)hipGraphExecDestroy(c->cg_graph_exec); c->cg_graph_exec = nullptr; }
+        if (c->cg_graph) { (void)hipGraphDestroy(c->cg_graph); c->cg_graph = nullptr; }
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+          (void)hipGetLastError();
+          return false;
         }
+        for (int k = 0; k < 8; ++k) iteration(k & 1);
+        hipGraph_t gr = nullptr;
+        if (hipStreamEndCapture(st, &gr) != hipSuccess || !gr ||
+            hipGraphInstantiate(&c->cg_graph_exec, gr, nullptr, nullptr, 0) != hipSuccess) {
+          (void)hipGetLastError();
+          if (gr) (void)hipGraphDestroy(gr);
+          c->cg_graph_exec = nullptr;
+          return false;
+        }
+        c->cg_graph = gr;
+        c->cg_graph_gen = c->alloc_gen;
+        c->cg_graph_tol2 = tol2;
+        c->cg_graph_npc = npc;
+        return true;
+      };
+      bool use_graph = blk == 8 && c->cg_graphs && st && !c->timing;
+      if (use_graph && !(c->cg_graph_exec && c->cg_graph_gen == c->alloc_gen &&
+                         c->cg_graph_tol2 == tol2 && c->cg_graph_npc == npc))
+        use_graph = c->cg_graphs = capture();
+      if (use_graph) {
         HIP_TRY(c, hipGraphLaunch(c->cg_graph_exec, st));
         it += 8;
       } else {
