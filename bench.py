@@ -87,7 +87,8 @@ def main():
         r = run_workload(args, w20, 128, "graphite_capacitor_20064", 1, 1, False)
         out["workload_20064"] = {k: r[k] for k in ("value", "ms_per_step", "config", "roofline",
                                                    "phase_s", "solve_only_rate",
-                                                   "plain_fp64_per_step_rate", "matvec_roofline",
+                                                   "plain_fp64_per_step_rate",
+                                                   "graph_fp64_per_step", "matvec_roofline",
                                                    "conjugate_gradient", "max_abs_sum_q")}
     if not args.no_cpu_baseline and w.n < 10000:
         out["cpu_baseline"], q_ref, Q_ref = cpu_baseline(w)
@@ -203,6 +204,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
         ctx.solve_charges(b1, 0x000, q1, Qe1)
     torch.cuda.synchronize()
     plain_rate = n_plain / (time.perf_counter() - ts)
+    graph_step = graph_step_measure(w, xyz, dev, n_plain, q1)
 
     matvec = matvec_roofline(ctx, w, xyz, dev)
     cg = cg_measure(w, xyz, dev, ctx)
@@ -253,6 +255,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
         "solve_only_rate": B / (b_s + solve_s),
         "plain_fp64_per_step_rate": plain_rate,
         "plain_fp64_sample": f"{n_plain} snapshots, b + FP64 matvec solve one at a time, setup excluded",
+        "graph_fp64_per_step": graph_step,
         "kernel_ms_per_step": {f: v[0] for f, v in timing.items() if v[1]},
         "matvec_roofline": matvec,
         "conjugate_gradient": cg,
@@ -356,6 +359,42 @@ def matvec_roofline(ctx, w, xyz, dev, reps=20):
     out["note"] = ("S held across back-to-back solves; below 256 MB (N < ~5800 in FP64) it can "
                    "stay in the last-level cache, so N = 20064 is the HBM figure")
     return out
+
+
+def graph_step_measure(w, xyz, dev, n, q_last):
+    """One configuration per step as a molecular-dynamics loop would run it:
+    b and the FP64 matvec solve captured once as a HIP graph
+    (cpm_capture_step) on a context with its own stream, then per step the
+    coordinates copied into the captured input buffer and the graph
+    replayed (S built beforehand).  The last step's configuration is the
+    plain loop's last, so its charges are compared with q_last."""
+    import torch
+    from paper_2203_15461_amd import cpm
+    stream = torch.cuda.Stream()
+    ctx = cpm.setup(w, stream=stream)
+    x1 = xyz[0:1].clone()
+    b1 = torch.empty((1, w.n), dtype=torch.float64, device=dev)
+    q1 = torch.empty_like(b1)
+    Qe1 = torch.empty((1, 2), dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    ctx.capture_step(x1, b1, 0x000, q1, Qe1)
+    with torch.cuda.stream(stream):
+        for s_ in range(2):                              # warm-up replays
+            x1.copy_(xyz[s_:s_ + 1])
+            ctx.replay_step()
+    stream.synchronize()
+    ts = time.perf_counter()
+    with torch.cuda.stream(stream):
+        for s_ in range(n):
+            x1.copy_(xyz[s_:s_ + 1])
+            ctx.replay_step()
+    stream.synchronize()
+    dt = (time.perf_counter() - ts) / n
+    diff = float(((q1 - q_last).abs().max() / q_last.abs().max()).item())
+    ctx.close()
+    return {"steps_per_s": 1.0 / dt, "us_per_step": dt * 1e6, "steps": n,
+            "max_rel_diff_vs_eager_last_step": diff,
+            "note": "per step: coordinates copied into the captured buffer, then one graph replay"}
 
 
 CG_FAMILIES = ("cg_plane_sums", "cg_plane_mix", "cg_tiles", "cg_apply", "cg_update", "cg_precond",
