@@ -61,8 +61,7 @@ typedef enum {
  *     A += k_e (2 pi / V)(x x^T + y y^T), b -= k_e (2 pi / V)(x M_x + y M_y).
  *   CPM_GEOM_3D: periodic in x, y and z with no dipole term (tin foil), the
  *     setting of the finite-field method (Sec. II.F; pass slab_factor 1 and
- *     h = the cell height, and the field potential through
- *     cpm_set_potential_atoms).
+ *     h = the cell height, and the field potential through cpm_set_field).
  * Dipole terms use the coordinates as given (not wrapped). */
 typedef enum { CPM_GEOM_SLAB_EW3DC = 0, CPM_GEOM_WIRE = 1, CPM_GEOM_3D = 2 } cpm_geom;
 
@@ -237,14 +236,31 @@ cpm_status cpm_solve_cg(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32, 
 cpm_status cpm_invert(cpm_ctx* ctx, unsigned store_flags);
 
 /* Applied potentials h_v_electrode[n_e] (V), one per electrode (v = G v~,
- * Eq. 5).  Precomputes d = S v (Eq. 6 with the S G response cached), so a
- * solve only adds it.  Host pointer, copied. */
+ * Eq. 5).  Sets d = S v for the solves to add.  cpm_invert keeps the
+ * response S G (n x n_e, Eq. 6), so for n_e <= 16 this is one O(n n_e)
+ * kernel with the potentials passed by value: nothing is copied and the
+ * call does not wait (a time-varying potential costs no pass over S).
+ * More electrodes: v is uploaded and d = S v streamed, synchronously.  Host
+ * pointer, read before return. */
 cpm_status cpm_set_potential(cpm_ctx* ctx, const double* h_v_electrode);
 
 /* The same with one potential per electrode atom, h_v[n] (V, host memory):
- * d = S v for any v, e.g. the finite-field potential v = -dv0 zeta of
- * Eqs. 13-14 (zeta = normalised z positions). */
+ * d = S v for any v (one pass over S and a wait for the stream). */
 cpm_status cpm_set_potential_atoms(cpm_ctx* ctx, const double* h_v);
+
+/* Finite-field method (Sec. II.F, Eqs. 13-14; the `ffield` keyword of
+ * Sec. S-I.A): the library forms the field potential itself.  Every atom
+ * gets v_i = -dv0 zeta_i with zeta_i = z_i / Lz (Lz = slab_factor * h, the
+ * z coordinates as given to cpm_build_elastance) plus 1 for the atoms of
+ * electrode `bottom`, which puts the two electrodes next to each other
+ * across the periodic z boundary as one conductor.  dv0 (V) is the
+ * potential drop across the periodic boundary; with electrodes that do not
+ * let the field through, it is the potential difference between them.
+ * Needs CPM_GEOM_3D (CPM_EUNSUPPORTED otherwise) and 0 <= bottom < n_e
+ * (CPM_EINVAL).  The first call after cpm_invert (or with a new `bottom`)
+ * uploads zeta and forms S zeta with one pass over S; later calls with a new
+ * dv0 cost one O(n) kernel and do not wait for the stream. */
+cpm_status cpm_set_field(cpm_ctx* ctx, double dv0, int bottom);
 
 /* b for `batch` electrolyte configurations (Sec. II.A: the per-step cost).
  * d_xyz: batch x m x 3 FP64 positions (row-major, snapshot-major).
@@ -315,6 +331,42 @@ cpm_status cpm_capture_step(cpm_ctx* ctx, int batch, const double* d_xyz, void* 
  * a rebuild) or no longer keeps the copy of S the captured mode reads:
  * capture again in that case. */
 cpm_status cpm_replay_step(cpm_ctx* ctx);
+
+/* State files: the `write_mat` / `write_inv` and `read_mat` / `read_inv`
+ * keywords of Sec. S-I.A.  cpm_save writes A and, after cpm_invert, A^-1
+ * (n x n row-major FP64 each) with a 256-byte header holding n, n_e, the
+ * kept copies of S, s = e^T A^-1 e, the method knobs and a 64-bit
+ * fingerprint of everything A depends on (knobs, electrode coordinates and
+ * ids as given, diagonal term), plus a trailing checksum of the matrices.
+ * The file is written under path + ".tmp" and renamed when complete.
+ * Synchronous; CPM_ESTATE before cpm_build_elastance.
+ *
+ * cpm_load reads such a file into a context that has run
+ * cpm_build_elastance for the same electrodes and knobs: a different
+ * fingerprint, n or n_e, a damaged header, a wrong length or checksum
+ * returns CPM_EINVAL.  A file with A only replaces the assembly (call
+ * cpm_invert next); with A^-1 as well it also replaces the inversion:
+ * u, s, S, the response S G and the copies of S the saving context kept are
+ * formed from the stored A^-1 by the same kernels as cpm_invert, so charges
+ * solved after a load equal those of the saving context bit for bit.
+ * cpm_set_potential must follow.  Synchronous. */
+cpm_status cpm_save(const cpm_ctx* ctx, const char* path);
+cpm_status cpm_load(cpm_ctx* ctx, const char* path);
+
+/* What a state file holds (host only; no device work). */
+typedef struct {
+  int n, n_e;
+  int matrices;                 /* 1: A; 2: A and A^-1                            */
+  unsigned store;               /* CPM_STORE_* copies kept by the saving context  */
+  unsigned long long geometry_hash;
+  double s_sum;                 /* e^T A^-1 e (0 with A only)                     */
+  cpm_params params;            /* knobs; coulomb_k holds the k_e used            */
+} cpm_file_info;
+
+/* Read and check a state file's header and length (not the matrices'
+ * checksum).  CPM_EINVAL if the file is missing, not a state file, of
+ * another version, damaged or of the wrong length. */
+cpm_status cpm_inspect_file(const char* path, cpm_file_info* out);
 
 /* Copy a context matrix (n x n, row-major FP64) into caller memory d_out:
  * which = 0: A, 1: A^-1, 2: S.  Enqueued on the context stream. */

@@ -224,11 +224,14 @@ def check_neutral(q: np.ndarray):
 
 
 def structure_factor(r: np.ndarray, q: np.ndarray, kv: np.ndarray) -> np.ndarray:
-    """S(k) = sum_j q_j exp(i k.r_j) for every k in kv (complex)."""
+    """S(k) = sum_j q_j exp(i k.r_j) for every k in kv (complex).  The k set
+    is walked in chunks sized to bound memory; each S(k) is one sum over the
+    charges whatever the chunk."""
     out = np.zeros(len(kv), np.complex128)
-    for k0 in range(0, len(kv), 2048):
-        ph = r @ kv[k0:k0 + 2048].T
-        out[k0:k0 + 2048] = (q[:, None] * np.cos(ph)).sum(0) + 1j * (q[:, None] * np.sin(ph)).sum(0)
+    step = max(16, min(2048, (1 << 22) // max(len(r), 1)))
+    for k0 in range(0, len(kv), step):
+        ph = r @ kv[k0:k0 + step].T
+        out[k0:k0 + step] = (q[:, None] * np.cos(ph)).sum(0) + 1j * (q[:, None] * np.sin(ph)).sum(0)
     return out
 
 
@@ -342,6 +345,15 @@ def constrained_charges(Ainv: np.ndarray, eid: np.ndarray, n_e: int, b: np.ndarr
     Ct = G.T @ Ainv @ G
     vt = np.linalg.solve(Ct, Q - G.T @ y)
     return y + Ainv @ (G @ vt), vt
+
+
+def finite_field_zeta(z, eid, Lz: float, bottom: int = 0) -> np.ndarray:
+    """zeta of the finite-field method (Sec. II.F, Eqs. 13-14): the
+    normalised z position z / Lz of every electrode atom, plus one for the
+    atoms of the bottom electrode (the offset that makes the cell symmetric
+    along z, so that the two electrodes meet across the periodic boundary as
+    one conductor).  The field enters as the applied potential v = -dv0 zeta."""
+    return np.asarray(z, np.float64) / Lz + (np.asarray(eid) == bottom)
 
 
 def energy(A, b, v, q) -> float:

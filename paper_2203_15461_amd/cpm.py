@@ -33,7 +33,8 @@ EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_inve
            "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_autotune",
            "cpm_solve_grouped", "cpm_set_charge", "cpm_set_potential_atoms", "cpm_build_operator",
            "cpm_apply_elastance", "cpm_solve_cg", "cpm_get_info",
-           "cpm_enable_timing", "cpm_get_timing",
+           "cpm_enable_timing", "cpm_get_timing", "cpm_set_field", "cpm_save", "cpm_load",
+           "cpm_inspect_file",
            "cpm_synchronize", "cpm_last_error", "cpm_destroy")
 
 
@@ -43,6 +44,12 @@ class CpmParams(ctypes.Structure):
                 ("alpha", ctypes.c_double), ("rcut", ctypes.c_double),
                 ("kspace_eps", ctypes.c_double), ("kcut", ctypes.c_double),
                 ("coulomb_k", ctypes.c_double), ("geometry", ctypes.c_int)]
+
+
+class CpmFileInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int), ("n_e", ctypes.c_int), ("matrices", ctypes.c_int),
+                ("store", ctypes.c_uint), ("geometry_hash", ctypes.c_ulonglong),
+                ("s_sum", ctypes.c_double), ("params", CpmParams)]
 
 
 class CpmError(RuntimeError):
@@ -88,6 +95,10 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_enable_timing": ([vp, ctypes.c_char_p], i),
         "cpm_get_timing": ([vp, ctypes.c_char_p, ctypes.POINTER(d), ctypes.POINTER(ctypes.c_longlong)], i),
         "cpm_synchronize": ([vp], i),
+        "cpm_set_field": ([vp, d, i], i),
+        "cpm_save": ([vp, ctypes.c_char_p], i),
+        "cpm_load": ([vp, ctypes.c_char_p], i),
+        "cpm_inspect_file": ([ctypes.c_char_p, ctypes.POINTER(CpmFileInfo)], i),
         "cpm_last_error": ([vp], ctypes.c_char_p),
         "cpm_destroy": ([vp], None),
     }
@@ -245,6 +256,19 @@ class Context:
         self._check(self._lib.cpm_set_potential_atoms(
             self._h, va.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "cpm_set_potential_atoms")
 
+    def set_field(self, dv0: float, bottom: int = 0):
+        """Finite-field potential -dv0 zeta, zeta formed by the library from the
+        electrode z coordinates (3D-periodic cell; `bottom` gets the +1 offset)."""
+        self._check(self._lib.cpm_set_field(self._h, float(dv0), int(bottom)), "cpm_set_field")
+
+    def save(self, path: str):
+        """Write A (and A^-1 after invert) with the geometry fingerprint."""
+        self._check(self._lib.cpm_save(self._h, os.fsencode(path)), "cpm_save")
+
+    def load(self, path: str):
+        """Read a state file written for the same electrodes and knobs."""
+        self._check(self._lib.cpm_load(self._h, os.fsencode(path)), "cpm_load")
+
     def set_charge(self, Q_electrode):
         """Constrained charge method: total charge (e) per electrode, summing to zero."""
         import numpy as np
@@ -350,6 +374,20 @@ class Context:
             raise ValueError("need an (n,) tensor")
         self._check(self._lib.cpm_copy_vector(self._h, which, _ptr(out)), "cpm_copy_vector")
         return out
+
+
+def inspect_file(path: str) -> dict:
+    """Header of a state file written by cpm_save (host only)."""
+    out = CpmFileInfo()
+    st = lib().cpm_inspect_file(os.fsencode(path), ctypes.byref(out))
+    if st != OK:
+        raise CpmError(st, f"cpm_inspect_file: {path} is not a valid state file")
+    p = out.params
+    return dict(n=out.n, n_e=out.n_e, matrices=out.matrices, store=out.store,
+                geometry_hash=out.geometry_hash, s_sum=out.s_sum,
+                params=dict(Lx=p.Lx, Ly=p.Ly, h=p.h, slab_factor=p.slab_factor, eta=p.eta,
+                            alpha=p.alpha, rcut=p.rcut, kspace_eps=p.kspace_eps, kcut=p.kcut,
+                            coulomb_k=p.coulomb_k, geometry=p.geometry))
 
 
 def solve_grouped(ctxs, bs, mode: int, qs, Qes=None):

@@ -36,15 +36,19 @@ cpm_status fail(cpm_ctx* c, cpm_status st, const char* fmt, ...) {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// Device allocations of a context are recorded with their sizes, so that
+// CPM_INFO_WORKSPACE stays exact across frees and reallocations.
 template <typename T>
 cpm_status dalloc(cpm_ctx* c, T** p, size_t count) {
   if (*p) return CPM_OK;
   void* q = nullptr;
-  if (hipMalloc(&q, count * sizeof(T) > 0 ? count * sizeof(T) : 16) != hipSuccess) {
+  const size_t bytes = count * sizeof(T) > 0 ? count * sizeof(T) : 16;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(c, CPM_ENOMEM, "device allocation of %zu bytes failed", count * sizeof(T));
   }
-  c->bytes += count * sizeof(T);
+  c->bytes += bytes;
+  c->alloc_sizes[q] = bytes;
   ++c->alloc_gen;
   *p = static_cast<T*>(q);
   return CPM_OK;
@@ -58,7 +62,14 @@ void dfree(T*& p) {
 
 template <typename T>
 void dfree(cpm_ctx* c, T*& p) {
-  if (p) ++c->alloc_gen;
+  if (p) {
+    ++c->alloc_gen;
+    auto it = c->alloc_sizes.find((const void*)p);
+    if (it != c->alloc_sizes.end()) {
+      c->bytes -= it->second;
+      c->alloc_sizes.erase(it);
+    }
+  }
   dfree(p);
 }
 
@@ -324,7 +335,6 @@ struct DevTemp {
     if (!p) return;
     (void)hipStreamSynchronize(c->stream);
     dfree(c, p);
-    c->bytes -= count * sizeof(double);
   }
 };
 // From this many tiles on, the balancing form also takes the in-plane
@@ -548,9 +558,6 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
 cpm_status ensure_solve_buffers(cpm_ctx* c, int batch) {
   Buffers& b = c->b;
   if (batch > b.bpad_rows) {
-    const size_t old = (size_t)b.bpad_rows * c->npad * sizeof(double);
-    if (b.qt) c->bytes -= 4 * old;
-    if (b.xhi) c->bytes -= old / 2;
     dfree(c, b.qt); dfree(c, b.res); dfree(c, b.qpad); dfree(c, b.bpad);
     dfree(c, b.xhi); dfree(c, b.xlo);
     const size_t sz = (size_t)batch * c->npad;
@@ -589,16 +596,29 @@ cpm_status ensure_kpart(cpm_ctx* c, size_t len) {
   return CPM_OK;
 }
 
+// work buffers of one solve (the context's own, grown on demand, unless a
+// caller supplies another set)
+struct SolveWork {
+  double* qt; double* res; double* bpad; double* qpad; double* means; double* kpart;
+  uint16_t* xhi; uint16_t* xlo;
+  const cpm_ctx::GemmCfg* bf16 = nullptr;      // forced split-BF16 configuration
+};
+
+SolveWork ctx_work(cpm_ctx* c) {
+  Buffers& b = c->b;
+  return SolveWork{b.qt, b.res, b.bpad, b.qpad, b.means, b.kpart, b.xhi, b.xlo, nullptr};
+}
+
 // one split-BF16 product C (+)= X S~ over `rows` rows of this context; X is
 // split into BF16 pairs once, before the product
 void enqueue_bf16(cpm_ctx* c, const double* x, double* y, int rows, bool accumulate,
-                  const cpm_ctx::GemmCfg& cfg) {
+                  const cpm_ctx::GemmCfg& cfg, const SolveWork& w) {
   const int npad = c->npad;
-  launch_split_bf16(c->stream, (size_t)rows * npad, x, c->b.xhi, c->b.xlo);
+  launch_split_bf16(c->stream, (size_t)rows * npad, x, w.xhi, w.xlo);
   GemmGroupBf grp{};
   grp.nprob = 1;
-  grp.p[0] = gemm_bf16x3_problem(rows, npad, npad, c->b.xhi, c->b.xlo, npad, c->b.Shi, c->b.Slo,
-                                 npad, y, npad, accumulate ? 1 : 0, cfg.bm, cfg.ks, c->b.kpart);
+  grp.p[0] = gemm_bf16x3_problem(rows, npad, npad, w.xhi, w.xlo, npad, c->b.Shi, c->b.Slo,
+                                 npad, y, npad, accumulate ? 1 : 0, cfg.bm, cfg.ks, w.kpart);
   group_finish(grp);
   launch_gemm_bf16x3_group(c->stream, grp, cfg.bm, cfg.grid > 0 ? cfg.grid : grp.total);
 }
@@ -882,6 +902,83 @@ cpm_status assemble_A(cpm_ctx* c, hipStream_t st) {
   return CPM_OK;
 }
 
+// 64-bit FNV-1a over a byte range, continuing from h
+uint64_t fnv1a(uint64_t h, const void* data, size_t len) {
+  const unsigned char* p = static_cast<const unsigned char*>(data);
+  for (size_t i = 0; i < len; ++i) {
+    h ^= p[i];
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// Fingerprint of the elastance's inputs: the method knobs (as resolved), the
+// electrode coordinates and ids as given, and the diagonal term.
+uint64_t geometry_hash(const cpm_ctx* c, int n, int n_e, const double* xyz, const int* eid,
+                       const double* diag_extra) {
+  uint64_t h = 1469598103934665603ull;
+  const cpm_params& p = c->p;
+  const double knobs[12] = {p.Lx, p.Ly, p.h, p.slab_factor, p.eta, p.alpha, p.rcut,
+                            p.kspace_eps, p.kcut, c->ke, c->Lz, c->kc};
+  h = fnv1a(h, knobs, sizeof knobs);
+  const int ints[4] = {p.geometry, n, n_e, diag_extra ? 1 : 0};
+  h = fnv1a(h, ints, sizeof ints);
+  h = fnv1a(h, xyz, (size_t)3 * n * sizeof(double));
+  h = fnv1a(h, eid, (size_t)n * sizeof(int));
+  if (diag_extra) h = fnv1a(h, diag_extra, (size_t)n * sizeof(double));
+  return h;
+}
+
+// A^-1, S, u, d, v, the cached response S G and the reduced-precision
+// copies of S named by store_flags
+cpm_status ensure_inverse_buffers(cpm_ctx* c, unsigned store_flags) {
+  Buffers& b = c->b;
+  const int npad = c->npad;
+  TRY(dalloc(c, &b.Ainv, (size_t)npad * npad));
+  TRY(dalloc(c, &b.S, (size_t)npad * npad));
+  TRY(dalloc(c, &b.u, npad));
+  TRY(dalloc(c, &b.d, npad));
+  TRY(dalloc(c, &b.vat, npad));
+  if (c->n_e <= CCM_MAXE) TRY(dalloc(c, &b.sg, (size_t)npad * c->n_e));
+  if (store_flags & CPM_STORE_F32) TRY(dalloc(c, &b.S32, (size_t)npad * npad));
+  if (store_flags & CPM_STORE_BF16X2) {
+    TRY(dalloc(c, &b.Shi, (size_t)npad * npad));
+    TRY(dalloc(c, &b.Slo, (size_t)npad * npad));
+  }
+  return CPM_OK;
+}
+
+// From A^-1 in b.Ainv: u = A^-1 e, s = e^T u, S = A^-1 - u u^T / s (Eq. 4),
+// the response S G (Eq. 6) and the copies of S named by store_flags, on st.
+cpm_status form_S(cpm_ctx* c, hipStream_t st, unsigned store_flags) {
+  Buffers& b = c->b;
+  const int n = c->n, npad = c->npad;
+  HIP_TRY(c, hipMemsetAsync(b.u, 0, npad * sizeof(double), st));
+  { Timed t(c, "make_S", st);
+    launch_row_sums(st, n, npad, b.Ainv, b.u);
+    launch_sum_vector(st, n, b.u, b.scal);
+    launch_make_S(st, n, npad, b.Ainv, b.u, b.scal, b.S); }
+  TRY(launched(c, "projection"));
+  // the response of the charges to each electrode's potential, S G (Eq. 6):
+  // a new v~ then costs O(n n_e) instead of a pass over S
+  if (b.sg) {
+    Timed t(c, "response_SG", st);
+    launch_ccm_response(st, n, npad, b.S, b.eid, c->n_e, b.sg);
+  }
+  TRY(launched(c, "response"));
+  c->szeta_ok = false;
+  if (store_flags & (CPM_STORE_F32 | CPM_STORE_BF16X2)) {
+    Timed t(c, "convert_S", st);
+    launch_convert_S(st, npad, b.S, (store_flags & CPM_STORE_F32) ? b.S32 : nullptr,
+                     (store_flags & CPM_STORE_BF16X2) ? b.Shi : nullptr,
+                     (store_flags & CPM_STORE_BF16X2) ? b.Slo : nullptr);
+  }
+  TRY(launched(c, "convert"));
+  c->store = store_flags | CPM_STORE_F64;
+  c->have_q = false;                     // charge targets refer to the previous inverse
+  return CPM_OK;
+}
+
 // Electrode set-up shared by the dense elastance (dense = true: assemble A)
 // and the matrix-free operator (dense = false: keep what A x needs).
 cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, int n_e,
@@ -910,6 +1007,16 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
   }
   if (c->p.geometry == CPM_GEOM_SLAB_EW3DC && c->Lz - (zmax - zmin) <= c->p.rcut)
     return fail(c, CPM_EINVAL, "electrode z extent %g leaves no slab clearance in Lz = %g", zmax - zmin, c->Lz);
+  {
+    // fingerprint of everything A depends on, checked by cpm_load
+    std::vector<double> dx;
+    if (d_diag_extra) {
+      dx.resize(n);
+      HIP_TRY(c, hipMemcpy(dx.data(), d_diag_extra, (size_t)n * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    c->geom_hash = geometry_hash(c, n, n_e, c->h_xyz.data(), c->h_eid.data(),
+                                 d_diag_extra ? dx.data() : nullptr);
+  }
   // planar electrodes: atoms sharing an exact z value form a plane
   std::vector<double> zs;
   for (int i = 0; i < n; ++i) zs.push_back(c->h_xyz[3 * i + 2]);
@@ -935,6 +1042,10 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
   dfree(c, b0.pc_tplane); dfree(c, b0.pc_dblk); dfree(c, b0.pc_daz); dfree(c, b0.pc_H);
   dfree(c, b0.pc_ypart); dfree(c, b0.pc_y); dfree(c, b0.pc_wn); dfree(c, b0.pc_g);
   dfree(c, b0.pc_cpart);
+  // constrained charges and the cached responses S G follow n_e (and A)
+  dfree(c, b0.ccmU); dfree(c, b0.ccmC); dfree(c, b0.sg);
+  dfree(c, b0.zeta); dfree(c, b0.szeta);
+  c->szeta_ok = false;
   c->pc_ready = false;
   c->pc_tiles = 0;
   c->pc_Cinv = nullptr;
@@ -1224,16 +1335,7 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   Buffers& b = c->b;
   TRY(dalloc(c, &b.L, (size_t)npad * npad));
   TRY(dalloc(c, &b.Dinv, (size_t)nb * TILE * TILE));
-  TRY(dalloc(c, &b.Ainv, (size_t)npad * npad));
-  TRY(dalloc(c, &b.S, (size_t)npad * npad));
-  TRY(dalloc(c, &b.u, npad));
-  TRY(dalloc(c, &b.d, npad));
-  TRY(dalloc(c, &b.vat, npad));
-  if (store_flags & CPM_STORE_F32) TRY(dalloc(c, &b.S32, (size_t)npad * npad));
-  if (store_flags & CPM_STORE_BF16X2) {
-    TRY(dalloc(c, &b.Shi, (size_t)npad * npad));
-    TRY(dalloc(c, &b.Slo, (size_t)npad * npad));
-  }
+  TRY(ensure_inverse_buffers(c, store_flags));
   hipStream_t st = c->stream;
   if (async) {
     // a second stream of default priority, ordered after the work already
@@ -1339,21 +1441,7 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
     launch_mirror_lower(st, npad, b.L); }
   TRY(launched(c, "lauum"));
   std::swap(b.L, b.Ainv);
-  // u = A^-1 e, s = e^T u, S = A^-1 - u u^T / s (Eq. 4)
-  { Timed t(c, "make_S", st);
-    launch_row_sums(st, n, npad, b.Ainv, b.u);
-    launch_sum_vector(st, n, b.u, b.scal);
-    launch_make_S(st, n, npad, b.Ainv, b.u, b.scal, b.S); }
-  TRY(launched(c, "projection"));
-  if (store_flags & (CPM_STORE_F32 | CPM_STORE_BF16X2)) {
-    Timed t(c, "convert_S", st);
-    launch_convert_S(st, npad, b.S, (store_flags & CPM_STORE_F32) ? b.S32 : nullptr,
-                     (store_flags & CPM_STORE_BF16X2) ? b.Shi : nullptr,
-                     (store_flags & CPM_STORE_BF16X2) ? b.Slo : nullptr);
-  }
-  TRY(launched(c, "convert"));
-  c->store = store_flags | CPM_STORE_F64;
-  c->have_q = false;                     // charge targets refer to the previous inverse
+  TRY(form_S(c, st, store_flags));
   if (async) {
     // results are joined by the first call that needs them (finish_invert)
     HIP_TRY(c, hipMemcpyAsync(&c->h_async->s, b.scal, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1377,16 +1465,67 @@ cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
   for (int a = 0; a < c->n_e; ++a)
     if (!std::isfinite(h_v_electrode[a])) return fail(c, CPM_EINVAL, "potential %d not finite", a);
   c->h_v.assign(h_v_electrode, h_v_electrode + c->n_e);
+  TRY(ensure_vat(c));
+  if (c->n_e <= CCM_MAXE && (c->b.sg || !c->have_inv)) {
+    // v = G v~ and d = (S G) v~ from the cached response (Eq. 6): one small
+    // kernel, the potentials passed by value, nothing copied or awaited
+    ElectrodeValues vt{};
+    for (int a = 0; a < c->n_e; ++a) vt.v[a] = c->h_v[a];
+    launch_apply_potential(c->stream, c->n, c->npad, c->n_e, c->b.eid,
+                           c->have_inv ? c->b.sg : nullptr, vt, c->b.vat, c->b.d);
+    TRY(launched(c, "set_potential"));
+    c->have_v = true;
+    return CPM_OK;
+  }
   std::vector<double> vat(c->npad, 0.0);
   for (int i = 0; i < c->n; ++i) vat[i] = c->h_v[c->h_eid[i]];
-  TRY(ensure_vat(c));
   HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  // d = S v  (S G v~ of Eq. 6, cached; the operator path has no S)
+  // d = S v (more electrodes than the cached response holds)
   if (c->have_inv)
     launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
                   0.0, c->b.d, c->npad, 0);
   TRY(launched(c, "set_potential"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->have_v = true;
+  return CPM_OK;
+}
+
+cpm_status cpm_set_field(cpm_ctx* c, double dv0, int bottom) {
+  if (!c) return CPM_EINVAL;
+  TRY(finish_invert(c));
+  if (!c->have_inv && !c->have_op) return fail(c, CPM_ESTATE, "cpm_set_field before cpm_invert");
+  if (c->p.geometry != CPM_GEOM_3D)
+    return fail(c, CPM_EUNSUPPORTED, "the finite-field method needs the 3D-periodic cell (geometry 2)");
+  if (!std::isfinite(dv0)) return fail(c, CPM_EINVAL, "dv0 not finite");
+  if (bottom < 0 || bottom >= c->n_e)
+    return fail(c, CPM_EINVAL, "bottom electrode %d outside [0, %d)", bottom, c->n_e);
+  Buffers& b = c->b;
+  TRY(ensure_vat(c));
+  if (!b.zeta || c->field_bottom != bottom) {
+    // zeta_i = z_i / Lz, plus one cell for the bottom electrode (Sec. II.F:
+    // normalised z positions with the bottom electrode offset, so that the
+    // two electrodes meet across the periodic z boundary as one conductor)
+    TRY(dalloc(c, &b.zeta, (size_t)c->npad));
+    std::vector<double> z(c->npad, 0.0);
+    for (int i = 0; i < c->n; ++i)
+      z[i] = c->h_xyz[3 * i + 2] / c->Lz + (c->h_eid[i] == bottom ? 1.0 : 0.0);
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    HIP_TRY(c, hipMemcpy(b.zeta, z.data(), z.size() * sizeof(double), hipMemcpyHostToDevice));
+    c->field_bottom = bottom;
+    c->szeta_ok = false;
+  }
+  if (c->have_inv && !c->szeta_ok) {
+    // S zeta once per inverse (Eq. 14 with the response cached): a new dv0
+    // then costs O(n)
+    TRY(dalloc(c, &b.szeta, (size_t)c->npad));
+    launch_matvec(c->stream, 0, c->n, c->npad, b.S, 1, b.zeta, 0, c->npad, nullptr, nullptr, 0,
+                  0.0, b.szeta, c->npad, 0);
+    TRY(launched(c, "field response"));
+    c->szeta_ok = true;
+  }
+  launch_scale_field(c->stream, c->npad, dv0, b.zeta, c->have_inv ? b.szeta : nullptr, b.vat, b.d);
+  TRY(launched(c, "set_field"));
+  c->h_v.clear();
   c->have_v = true;
   return CPM_OK;
 }
@@ -1524,9 +1663,9 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   return CPM_OK;
 }
 
-// validation and (first-use) allocation for cpm_solve_charges
-cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
-                      double* d_q) {
+// validation of cpm_solve_charges' arguments and state (no allocation)
+cpm_status sc_validate(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
+                       double* d_q) {
   TRY(finish_invert(c));
   if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_invert");
   if (!c->have_v) return fail(c, CPM_ESTATE, "cpm_solve_charges before cpm_set_potential");
@@ -1542,6 +1681,14 @@ cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
   if (prec == 1 && !(c->store & CPM_STORE_F32)) return fail(c, CPM_EINVAL, "FP32 copy of S not kept");
   if (prec == 2 && !(c->store & CPM_STORE_BF16X2))
     return fail(c, CPM_EINVAL, "split-BF16 copy of S not kept");
+  return CPM_OK;
+}
+
+// validation and (first-use) allocation for cpm_solve_charges
+cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
+                      double* d_q) {
+  TRY(sc_validate(c, batch, d_b, b_is_f32, mode, d_q));
+  const unsigned prec = mode & 0xffu;
   const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
   const int rows = gemm ? ((batch + TILE - 1) / TILE) * TILE : batch;
   TRY(ensure_solve_buffers(c, rows));
@@ -1554,7 +1701,7 @@ cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
 
 // kernel launches of cpm_solve_charges (no allocation, copy or memset)
 cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsigned mode,
-                      double* d_q, double* d_Qe) {
+                      double* d_q, double* d_Qe, const SolveWork& w) {
   if (batch <= 0 || !d_b || !d_q) return fail(c, CPM_EINVAL, "need batch > 0 and non-NULL b, q");
   if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
   const unsigned prec = mode & 0xffu;
@@ -1575,17 +1722,17 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
     // correction q = y + U C~^-1 (Q - G^T y)
     if (!gemm) {
       Timed t(c, "matvec_f64");
-      launch_matvec(st, 0, n, npad, b.Ainv, batch, d_b, b_is_f32, n, nullptr, nullptr, 0, 0.0, b.qt,
+      launch_matvec(st, 0, n, npad, b.Ainv, batch, d_b, b_is_f32, n, nullptr, nullptr, 0, 0.0, w.qt,
                     npad, 0);
     } else {
       { Timed t(c, "pad_rows");
-        launch_pad_rows(st, n, npad, batch, rows, d_b, b_is_f32, nullptr, b.bpad); }
+        launch_pad_rows(st, n, npad, batch, rows, d_b, b_is_f32, nullptr, w.bpad); }
       Timed t(c, "gemm_f64");
-      launch_gemm_f64(st, false, false, rows, npad, npad, 1.0, b.bpad, npad, b.Ainv, npad, 0.0, b.qt,
+      launch_gemm_f64(st, false, false, rows, npad, npad, 1.0, w.bpad, npad, b.Ainv, npad, 0.0, w.qt,
                       npad, 0, 0);
     }
     { Timed t(c, "finalize");
-      launch_ccm_finalize(st, n, batch, b.qt, npad, b.ccmU, b.ccmC, b.ccmC + c->n_e * c->n_e, b.eid,
+      launch_ccm_finalize(st, n, batch, w.qt, npad, b.ccmU, b.ccmC, b.ccmC + c->n_e * c->n_e, b.eid,
                           c->n_e, d_q, n, d_Qe); }
     return launched(c, "solve (constrained charges)");
   }
@@ -1598,7 +1745,7 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
                       accumulate ? 1.0 : 0.0, y, npad, 0, 0);
     } else {
       Timed t(c, "gemm_bf16x3");
-      enqueue_bf16(c, x, y, rows, accumulate, bf16_cfg(c, rows));
+      enqueue_bf16(c, x, y, rows, accumulate, w.bf16 ? *w.bf16 : bf16_cfg(c, rows), w);
     }
   };
 
@@ -1608,61 +1755,61 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
   if (!gemm) {
     // q~ = S~ (b - mean(b) e) + d, one streaming pass over S~ per vector
     { Timed t(c, "row_means");
-      launch_row_means(st, n, batch, d_b, b_is_f32, n, b.means); }
+      launch_row_means(st, n, batch, d_b, b_is_f32, n, w.means); }
     { Timed t(c, mv_name);
-      launch_matvec(st, which, n, npad, Sm, batch, d_b, b_is_f32, n, b.means, b.d, 0, 1.0, b.qt,
+      launch_matvec(st, which, n, npad, Sm, batch, d_b, b_is_f32, n, w.means, b.d, 0, 1.0, w.qt,
                     npad, 0); }
     if (!refine) {
       Timed t(c, "finalize");
-      launch_finalize(st, n, batch, b.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe);
+      launch_finalize(st, n, batch, w.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe);
       return launched(c, "solve");
     }
     // one refinement step (FP64 except the products with S~):
     //   qp = P q~ (P: neutrality projection), r = (b + v) - A qp, q = P (qp + S~ r).
     // Valid because S A qp = qp when e^T qp = 0.
     { Timed t(c, "finalize");
-      launch_finalize(st, n, batch, b.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, b.qpad, npad,
+      launch_finalize(st, n, batch, w.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, w.qpad, npad,
                       nullptr); }
     { Timed t(c, "make_rhs");
-      launch_make_rhs(st, n, npad, batch, d_b, b_is_f32, b.vat, b.res); }
+      launch_make_rhs(st, n, npad, batch, d_b, b_is_f32, b.vat, w.res); }
     { Timed t(c, "matvec_f64");
-      launch_matvec(st, 0, n, npad, b.A, batch, b.qpad, 0, npad, nullptr, b.res, npad, 1.0, b.qt,
+      launch_matvec(st, 0, n, npad, b.A, batch, w.qpad, 0, npad, nullptr, w.res, npad, 1.0, w.qt,
                     npad, 1); }
     { Timed t(c, "row_means");
-      launch_row_means(st, n, batch, b.qt, 0, npad, b.means); }
+      launch_row_means(st, n, batch, w.qt, 0, npad, w.means); }
     { Timed t(c, mv_name);
-      launch_matvec(st, which, n, npad, Sm, batch, b.qt, 0, npad, b.means, b.qpad, npad, 1.0, b.res,
+      launch_matvec(st, which, n, npad, Sm, batch, w.qt, 0, npad, w.means, w.qpad, npad, 1.0, w.res,
                     npad, 0); }
     { Timed t(c, "finalize");
-      launch_finalize(st, n, batch, b.res, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
+      launch_finalize(st, n, batch, w.res, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
     return launched(c, "solve (refined)");
   }
 
   // batched: Q~ = B S~ as one MFMA GEMM over all vectors (rows padded to 64)
   { Timed t(c, "row_means");
-    launch_row_means(st, n, batch, d_b, b_is_f32, n, b.means); }
+    launch_row_means(st, n, batch, d_b, b_is_f32, n, w.means); }
   { Timed t(c, "pad_rows");
-    launch_pad_rows(st, n, npad, batch, rows, d_b, b_is_f32, b.means, b.bpad); }
-  apply_S(b.bpad, b.qpad, false);
+    launch_pad_rows(st, n, npad, batch, rows, d_b, b_is_f32, w.means, w.bpad); }
+  apply_S(w.bpad, w.qpad, false);
   if (!refine) {
     Timed t(c, "finalize");
-    launch_finalize(st, n, batch, b.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe);
+    launch_finalize(st, n, batch, w.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe);
     return launched(c, "solve (batched)");
   }
   { Timed t(c, "finalize");
-    launch_finalize(st, n, batch, b.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, b.qt, npad,
+    launch_finalize(st, n, batch, w.qpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, w.qt, npad,
                     nullptr); }
   { Timed t(c, "make_rhs");
-    launch_make_rhs(st, n, npad, batch, d_b, b_is_f32, b.vat, b.res); }
+    launch_make_rhs(st, n, npad, batch, d_b, b_is_f32, b.vat, w.res); }
   // R = C - Qp A (FP64 MFMA), centred, then Q = Qp + R S~
   { Timed t(c, "gemm_f64");
-    launch_gemm_f64(st, false, false, rows, npad, npad, -1.0, b.qt, npad, b.A, npad, 1.0, b.res,
+    launch_gemm_f64(st, false, false, rows, npad, npad, -1.0, w.qt, npad, b.A, npad, 1.0, w.res,
                     npad, 0, 0); }
   { Timed t(c, "center_rows");
-    launch_center_rows(st, n, npad, batch, b.res); }
-  apply_S(b.res, b.qt, true);
+    launch_center_rows(st, n, npad, batch, w.res); }
+  apply_S(w.res, w.qt, true);
   { Timed t(c, "finalize");
-    launch_finalize(st, n, batch, b.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
+    launch_finalize(st, n, batch, w.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
   return launched(c, "solve (batched, refined)");
 }
 
@@ -1680,7 +1827,7 @@ cpm_status cpm_solve_charges(cpm_ctx* c, int batch, const void* d_b, int b_is_f3
                              double* d_q, double* d_Qe) {
   if (!c) return CPM_EINVAL;
   TRY(sc_prepare(c, batch, d_b, b_is_f32, mode, d_q));
-  return sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe);
+  return sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe, ctx_work(c));
 }
 
 cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32,
@@ -1697,7 +1844,7 @@ cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_
   c->timing = false;                               // no event nodes in the graph
   HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   cpm_status st = pv_enqueue(c, batch, d_xyz, d_b, b_is_f32);
-  if (st == CPM_OK) st = sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe);
+  if (st == CPM_OK) st = sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe, ctx_work(c));
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->stream, &g);
   c->timing = timing;
@@ -1744,7 +1891,7 @@ cpm_status cpm_set_charge(cpm_ctx* c, const double* h_Q) {
   if (std::fabs(sum) > 1e-12 * std::max(asum, 1e-300))
     return fail(c, CPM_EINVAL, "electrode charge targets must sum to zero (sum = %g)", sum);
   Buffers& b = c->b;
-  TRY(dalloc(c, &b.ccmU, (size_t)n * ne));
+  TRY(dalloc(c, &b.ccmU, (size_t)c->npad * ne));
   TRY(dalloc(c, &b.ccmC, (size_t)ne * ne + ne));
   launch_ccm_response(c->stream, n, c->npad, b.Ainv, b.eid, ne, b.ccmU);
   TRY(launched(c, "ccm response"));
@@ -1805,9 +1952,9 @@ cpm_status cpm_autotune(cpm_ctx* c, int batch, int reps) {
       for (int grid : grids) {
         cpm_ctx::GemmCfg cfg;
         cfg.bm = bm; cfg.ks = ks; cfg.grid = grid;
-        enqueue_bf16(c, c->b.bpad, c->b.qt, rows, false, cfg);    // warm-up
+        enqueue_bf16(c, c->b.bpad, c->b.qt, rows, false, cfg, ctx_work(c));    // warm-up
         HIP_TRY(c, hipEventRecord(e0, c->stream));
-        for (int r = 0; r < reps; ++r) enqueue_bf16(c, c->b.bpad, c->b.qt, rows, false, cfg);
+        for (int r = 0; r < reps; ++r) enqueue_bf16(c, c->b.bpad, c->b.qt, rows, false, cfg, ctx_work(c));
         HIP_TRY(c, hipEventRecord(e1, c->stream));
         TRY(launched(c, "autotune"));
         HIP_TRY(c, hipEventSynchronize(e1));
@@ -2100,6 +2247,232 @@ cpm_status cpm_solve_cg(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, do
   return CPM_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---- state files (cpm_save / cpm_load) -------------------------------------
+// A 256-byte little-endian header, the matrices as n x n row-major FP64 (A,
+// then A^-1 when present), and a trailing 64-bit checksum (FNV-1a over the
+// payload's 64-bit words).
+constexpr char FILE_MAGIC[8] = {'C', 'P', 'M', 'S', 'T', 'A', 'T', 'E'};
+constexpr uint32_t FILE_VERSION = 1;
+constexpr size_t FILE_HEADER = 256;
+
+struct FileHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  int32_t n, n_e;
+  uint32_t matrices, store;
+  uint64_t geom_hash;
+  double s_sum;
+  double knobs[12];               // Lx Ly h slab_factor eta alpha rcut kspace_eps kcut k_e Lz k_c
+  int32_t geometry, pad;
+  uint64_t payload_bytes;
+  unsigned char reserved[88];
+  uint64_t header_check;          // FNV-1a of the 248 bytes before it
+};
+static_assert(sizeof(FileHeader) == FILE_HEADER, "state file header layout");
+
+uint64_t fnv1a_words(uint64_t h, const double* v, size_t count) {
+  for (size_t i = 0; i < count; ++i) {
+    uint64_t w;
+    std::memcpy(&w, v + i, 8);
+    h ^= w;
+    h *= 1099511628211ull;
+  }
+  return h;
+}
+
+// read and check a header; on success the file is positioned at the payload
+cpm_status read_header(FILE* f, FileHeader& hd, std::string& why) {
+  if (std::fread(&hd, 1, FILE_HEADER, f) != FILE_HEADER) { why = "file shorter than its header"; return CPM_EINVAL; }
+  if (std::memcmp(hd.magic, FILE_MAGIC, 8) != 0) { why = "not a cpm state file (magic)"; return CPM_EINVAL; }
+  if (hd.version != FILE_VERSION || hd.header_bytes != FILE_HEADER) {
+    why = "unsupported state file version";
+    return CPM_EINVAL;
+  }
+  if (fnv1a(1469598103934665603ull, &hd, FILE_HEADER - 8) != hd.header_check) {
+    why = "header checksum mismatch";
+    return CPM_EINVAL;
+  }
+  if (hd.n <= 0 || hd.n_e <= 0 || hd.n_e > hd.n || (hd.matrices != 1 && hd.matrices != 2) ||
+      hd.payload_bytes != (uint64_t)hd.matrices * hd.n * hd.n * sizeof(double)) {
+    why = "inconsistent sizes in the header";
+    return CPM_EINVAL;
+  }
+  const long pos = std::ftell(f);
+  if (std::fseek(f, 0, SEEK_END) != 0) { why = "cannot seek"; return CPM_EINVAL; }
+  const long end = std::ftell(f);
+  if (end < 0 || (uint64_t)end != FILE_HEADER + hd.payload_bytes + 8) {
+    why = "file length does not match the header (truncated or extended)";
+    return CPM_EINVAL;
+  }
+  std::fseek(f, pos, SEEK_SET);
+  return CPM_OK;
+}
+
+struct FileCloser {
+  FILE* f;
+  ~FileCloser() { if (f) std::fclose(f); }
+};
+
+}  // namespace
+
+extern "C" {
+
+cpm_status cpm_inspect_file(const char* path, cpm_file_info* out) {
+  if (!path || !out) return CPM_EINVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return CPM_EINVAL;
+  FileCloser fc{f};
+  FileHeader hd;
+  std::string why;
+  const cpm_status st = read_header(f, hd, why);
+  if (st != CPM_OK) return st;
+  std::memset(out, 0, sizeof *out);
+  out->n = hd.n;
+  out->n_e = hd.n_e;
+  out->matrices = (int)hd.matrices;
+  out->store = hd.store;
+  out->geometry_hash = hd.geom_hash;
+  out->s_sum = hd.s_sum;
+  cpm_params& p = out->params;
+  p.Lx = hd.knobs[0]; p.Ly = hd.knobs[1]; p.h = hd.knobs[2]; p.slab_factor = hd.knobs[3];
+  p.eta = hd.knobs[4]; p.alpha = hd.knobs[5]; p.rcut = hd.knobs[6]; p.kspace_eps = hd.knobs[7];
+  p.kcut = hd.knobs[8]; p.coulomb_k = hd.knobs[9]; p.geometry = hd.geometry;
+  return CPM_OK;
+}
+
+cpm_status cpm_save(const cpm_ctx* cc, const char* path) {
+  if (!cc) return CPM_EINVAL;
+  cpm_ctx* c = const_cast<cpm_ctx*>(cc);
+  if (!path) return fail(c, CPM_EINVAL, "path is NULL");
+  TRY(finish_invert(c));
+  if (!c->have_A) return fail(c, CPM_ESTATE, "cpm_save needs cpm_build_elastance");
+  TRY(assemble_A(c, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const int n = c->n, npad = c->npad;
+  FileHeader hd;
+  std::memset(&hd, 0, sizeof hd);
+  std::memcpy(hd.magic, FILE_MAGIC, 8);
+  hd.version = FILE_VERSION;
+  hd.header_bytes = FILE_HEADER;
+  hd.n = n;
+  hd.n_e = c->n_e;
+  hd.matrices = c->have_inv ? 2 : 1;
+  hd.store = c->have_inv ? c->store : 0;
+  hd.geom_hash = c->geom_hash;
+  hd.s_sum = c->have_inv ? c->s_sum : 0.0;
+  const cpm_params& p = c->p;
+  const double knobs[12] = {p.Lx, p.Ly, p.h, p.slab_factor, p.eta, p.alpha, p.rcut,
+                            p.kspace_eps, p.kcut, c->ke, c->Lz, c->kc};
+  std::memcpy(hd.knobs, knobs, sizeof knobs);
+  hd.geometry = p.geometry;
+  hd.payload_bytes = (uint64_t)hd.matrices * n * n * sizeof(double);
+  hd.header_check = fnv1a(1469598103934665603ull, &hd, FILE_HEADER - 8);
+  // written to a temporary name, renamed when complete
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* f = std::fopen(tmp.c_str(), "wb");
+  if (!f) return fail(c, CPM_EINVAL, "cannot open %s for writing", tmp.c_str());
+  cpm_status st = CPM_OK;
+  {
+    FileCloser fc{f};
+    if (std::fwrite(&hd, 1, FILE_HEADER, f) != FILE_HEADER)
+      st = fail(c, CPM_EINVAL, "write of %s failed", tmp.c_str());
+    const size_t rows = std::max<size_t>(1, ((size_t)8 << 20) / n);   // 64 MB chunks
+    std::vector<double> buf(rows * n);
+    uint64_t chk = 1469598103934665603ull;
+    const double* mats[2] = {c->b.A, c->b.Ainv};
+    for (uint32_t mi = 0; mi < hd.matrices && st == CPM_OK; ++mi)
+      for (size_t r0 = 0; r0 < (size_t)n && st == CPM_OK; r0 += rows) {
+        const size_t nr = std::min(rows, (size_t)n - r0);
+        if (hipMemcpy2D(buf.data(), n * sizeof(double), mats[mi] + r0 * npad, npad * sizeof(double),
+                        n * sizeof(double), nr, hipMemcpyDeviceToHost) != hipSuccess) {
+          st = fail(c, CPM_EHIP, "device-to-host copy for cpm_save failed");
+          break;
+        }
+        chk = fnv1a_words(chk, buf.data(), nr * n);
+        if (std::fwrite(buf.data(), sizeof(double), nr * n, f) != nr * n)
+          st = fail(c, CPM_EINVAL, "write of %s failed", tmp.c_str());
+      }
+    if (st == CPM_OK && std::fwrite(&chk, 1, 8, f) != 8)
+      st = fail(c, CPM_EINVAL, "write of %s failed", tmp.c_str());
+    if (st == CPM_OK && std::fflush(f) != 0) st = fail(c, CPM_EINVAL, "write of %s failed", tmp.c_str());
+  }
+  if (st != CPM_OK) {
+    std::remove(tmp.c_str());
+    return st;
+  }
+  if (std::rename(tmp.c_str(), path) != 0) {
+    std::remove(tmp.c_str());
+    return fail(c, CPM_EINVAL, "cannot rename %s to %s", tmp.c_str(), path);
+  }
+  return CPM_OK;
+}
+
+cpm_status cpm_load(cpm_ctx* c, const char* path) {
+  if (!c) return CPM_EINVAL;
+  if (!path) return fail(c, CPM_EINVAL, "path is NULL");
+  TRY(wait_invert(c));                    // a pending inversion still writes the buffers
+  c->inv_failed = false;
+  if (!c->have_A || c->have_op)
+    return fail(c, CPM_ESTATE, "cpm_load needs cpm_build_elastance (the electrodes) first");
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return fail(c, CPM_EINVAL, "cannot open %s", path);
+  FileCloser fc{f};
+  FileHeader hd;
+  std::string why;
+  if (read_header(f, hd, why) != CPM_OK) return fail(c, CPM_EINVAL, "%s: %s", path, why.c_str());
+  if (hd.n != c->n || hd.n_e != c->n_e)
+    return fail(c, CPM_EINVAL, "%s holds n = %d, n_e = %d; the context has n = %d, n_e = %d", path,
+                hd.n, hd.n_e, c->n, c->n_e);
+  if (hd.geom_hash != c->geom_hash)
+    return fail(c, CPM_EINVAL, "%s was saved for other electrodes or parameters (fingerprint mismatch)",
+                path);
+  const int n = c->n, npad = c->npad;
+  Buffers& b = c->b;
+  const unsigned store = hd.store & (unsigned)(CPM_STORE_F32 | CPM_STORE_BF16X2);
+  if (hd.matrices == 2) TRY(ensure_inverse_buffers(c, store));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->have_inv = c->have_v = c->have_q = false;
+  c->A_pending = false;
+  // padding rows and columns hold the identity, as after the assembly
+  launch_set_identity(c->stream, npad, b.A);
+  if (hd.matrices == 2) launch_set_identity(c->stream, npad, b.Ainv);
+  TRY(launched(c, "load"));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  const size_t rows = std::max<size_t>(1, ((size_t)8 << 20) / n);
+  std::vector<double> buf(rows * n);
+  uint64_t chk = 1469598103934665603ull;
+  double* mats[2] = {b.A, b.Ainv};
+  for (uint32_t mi = 0; mi < hd.matrices; ++mi)
+    for (size_t r0 = 0; r0 < (size_t)n; r0 += rows) {
+      const size_t nr = std::min(rows, (size_t)n - r0);
+      if (std::fread(buf.data(), sizeof(double), nr * n, f) != nr * n) {
+        c->have_A = false;
+        return fail(c, CPM_EINVAL, "%s: short read", path);
+      }
+      chk = fnv1a_words(chk, buf.data(), nr * n);
+      HIP_TRY(c, hipMemcpy2D(mats[mi] + r0 * npad, npad * sizeof(double), buf.data(),
+                             n * sizeof(double), n * sizeof(double), nr, hipMemcpyHostToDevice));
+    }
+  uint64_t stored = 0;
+  if (std::fread(&stored, 1, 8, f) != 8 || stored != chk) {
+    c->have_A = false;                    // the device copy is not to be trusted
+    return fail(c, CPM_EINVAL, "%s: payload checksum mismatch", path);
+  }
+  if (hd.matrices == 1) return CPM_OK;   // A only: cpm_invert follows
+  TRY(form_S(c, c->stream, store));
+  HIP_TRY(c, hipMemcpyAsync(&c->s_sum, b.scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (!(std::fabs(c->s_sum - hd.s_sum) <= 1e-12 * std::fabs(hd.s_sum)))
+    return fail(c, CPM_EINVAL, "%s: e^T A^-1 e = %.17g differs from the saved %.17g", path, c->s_sum,
+                hd.s_sum);
+  c->have_inv = true;
+  return CPM_OK;
+}
+
 cpm_status cpm_copy_matrix(const cpm_ctx* c, int which, double* d_out) {
   if (!c || !d_out) return CPM_EINVAL;
   TRY(finish_invert(const_cast<cpm_ctx*>(c)));
@@ -2202,7 +2575,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
   dfree(b.xhi); dfree(b.xlo);
   dfree(b.zperm); dfree(b.cq); dfree(b.zr);
-  dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC);
+  dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC); dfree(b.sg); dfree(b.zeta); dfree(b.szeta);
   dfree(b.Qpair); dfree(b.ell_col); dfree(b.ell_val); dfree(b.plane_off); dfree(b.dextra);
   dfree(b.bsr_col); dfree(b.bsr_val); dfree(b.cg_items); dfree(b.asmG); dfree(b.asmF);
   dfree(b.Ecat); dfree(b.cg_ident); dfree(b.cgv); dfree(b.cgred);

@@ -113,6 +113,10 @@ struct Buffers {
   double* kpart = nullptr;         // split-K partial slices of the batched split-BF16 GEMM
   double* ccmU = nullptr;          // constrained charges: U = A^-1 G (n x n_e)
   double* ccmC = nullptr;          // C~^-1 (n_e x n_e) followed by the targets Q (n_e)
+  double* sg = nullptr;            // S G: response of the charges to each electrode's
+                                   // potential (npad x n_e, Eq. 6), formed by cpm_invert
+  double* zeta = nullptr;          // finite-field zeta (npad, zero padding)
+  double* szeta = nullptr;         // S zeta of the finite-field potential (npad)
   // matrix-free operator and conjugate gradients (slot space: the atom map
   // for the operator, atoms padded to npad for the dense A)
   double2* Qpair = nullptr;        // Q_c(L, L') per sorted column, [(c nL + L) nL + L']
@@ -279,9 +283,13 @@ struct cpm_ctx {
   int rs_wg_target = 512;          // real-space workgroups per launch group
   int rs_sort_min = 16;            // batches of at least this size sort the charges by z
   unsigned store = 0;
+  uint64_t geom_hash = 0;          // fingerprint of A's inputs (cpm_save / cpm_load)
+  int field_bottom = -1;           // bottom electrode of the zeta in b.zeta
+  bool szeta_ok = false;           // b.szeta = S zeta holds for the current inverse
   double s_sum = 0;                // e^T A^-1 e
   int pivot = -1;
   size_t bytes = 0;
+  std::map<const void*, size_t> alloc_sizes;   // device allocations and their sizes
   unsigned long long alloc_gen = 0;    // bumped by every device allocation / free
   std::vector<double> h_v;         // per-electrode potential
   std::vector<double> h_xyz;       // electrode coordinates (host copy)
@@ -393,8 +401,15 @@ void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldq
                      const double* u, const double* s_dev, const int* eid, int n_e, double* q,
                      int ldq, double* Qe);
 void launch_fill_zero(hipStream_t st, size_t count, float* p);
-void launch_ccm_response(hipStream_t st, int n, int npad, const double* Ainv, const int* eid,
+// U = M G (npad x n_e) in one pass over the symmetric M (n_e <= CCM_MAXE)
+void launch_ccm_response(hipStream_t st, int n, int npad, const double* M, const int* eid,
                          int n_e, double* U);
+// one value per electrode, passed by value to a kernel
+struct ElectrodeValues { double v[CCM_MAXE]; };
+void launch_apply_potential(hipStream_t st, int n, int npad, int n_e, const int* eid,
+                            const double* SG, const ElectrodeValues& vt, double* vat, double* d);
+void launch_scale_field(hipStream_t st, int npad, double dv0, const double* zeta,
+                        const double* szeta, double* vat, double* d);
 void launch_ccm_finalize(hipStream_t st, int n, int batch, const double* yt, int ldy,
                          const double* U, const double* Cinv, const double* Qt, const int* eid,
                          int n_e, double* q, int ldq, double* Qe);

@@ -625,26 +625,90 @@ void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldq
 }
 
 // ---------------------------------------------------------------------------
-// Constrained charge method (Eq. 7).  U = A^-1 G (n x n_e, row-major): row
-// sums of A^-1 over each electrode's columns.
+// Row sums of a symmetric npad x npad matrix over each electrode's columns,
+// U = M G (npad x n_e, row-major; rows i >= n are zero), in one pass over M:
+// one wave per row, lane-strided columns, one register per electrode and a
+// fixed-order wave sum each.  M = A^-1 gives the constrained-charge response
+// of Eq. 7; M = S gives the cached potential response S G of Eq. 6.
 // ---------------------------------------------------------------------------
-__global__ void k_ccm_response(int n, int npad, const double* __restrict__ Ainv,
-                               const int* __restrict__ eid, int n_e, double* __restrict__ U) {
+template <int NE>
+__global__ void __launch_bounds__(256) k_group_row_sums(int n, int npad, const double* __restrict__ M,
+                                                        const int* __restrict__ eid, int n_e,
+                                                        double* __restrict__ U) {
   const int i = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
-  if (i >= n) return;
-  const double* row = Ainv + (size_t)i * npad;
-  for (int a = 0; a < n_e; ++a) {
-    double s = 0.0;
-    for (int j = lane; j < n; j += 64)
-      if (eid[j] == a) s += row[j];
-    s = wave_sum(s);
-    if (lane == 0) U[(size_t)i * n_e + a] = s;
+  if (i >= npad) return;
+  double acc[NE];
+#pragma unroll
+  for (int a = 0; a < NE; ++a) acc[a] = 0.0;
+  if (i < n) {
+    const double* row = M + (size_t)i * npad;
+    for (int j = lane; j < n; j += 64) {
+      const double v = row[j];
+      const int e = eid[j];
+#pragma unroll
+      for (int a = 0; a < NE; ++a)
+        if (e == a) acc[a] += v;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < NE; ++a) {
+    const double s = wave_sum(acc[a]);
+    if (lane == 0 && a < n_e) U[(size_t)i * n_e + a] = s;
   }
 }
 
-void launch_ccm_response(hipStream_t st, int n, int npad, const double* Ainv, const int* eid,
+void launch_ccm_response(hipStream_t st, int n, int npad, const double* M, const int* eid,
                          int n_e, double* U) {
-  hipLaunchKernelGGL(k_ccm_response, dim3((n + 3) / 4), dim3(256), 0, st, n, npad, Ainv, eid, n_e, U);
+  dim3 grid((npad + 3) / 4), block(256);
+  if (n_e <= 2)
+    hipLaunchKernelGGL(k_group_row_sums<2>, grid, block, 0, st, n, npad, M, eid, n_e, U);
+  else if (n_e <= 4)
+    hipLaunchKernelGGL(k_group_row_sums<4>, grid, block, 0, st, n, npad, M, eid, n_e, U);
+  else if (n_e <= 8)
+    hipLaunchKernelGGL(k_group_row_sums<8>, grid, block, 0, st, n, npad, M, eid, n_e, U);
+  else
+    hipLaunchKernelGGL(k_group_row_sums<CCM_MAXE>, grid, block, 0, st, n, npad, M, eid, n_e, U);
+}
+
+// Applied potential from the cached response (Eqs. 5, 6): v_i = v~_e(i) and
+// d_i = sum_a (S G)_ia v~_a (fixed electrode order), for i < npad (zero
+// padding); d is left alone when SG is NULL (the operator has no S).
+__global__ void k_apply_potential(int n, int npad, int n_e, const int* __restrict__ eid,
+                                  const double* __restrict__ SG, ElectrodeValues vt,
+                                  double* __restrict__ vat, double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  double v = 0.0, di = 0.0;
+  if (i < n) {
+    v = vt.v[eid[i]];
+    if (SG)
+      for (int a = 0; a < n_e; ++a) di += SG[(size_t)i * n_e + a] * vt.v[a];
+  }
+  vat[i] = v;
+  if (SG) d[i] = di;
+}
+
+void launch_apply_potential(hipStream_t st, int n, int npad, int n_e, const int* eid,
+                            const double* SG, const ElectrodeValues& vt, double* vat, double* d) {
+  hipLaunchKernelGGL(k_apply_potential, dim3((npad + 255) / 256), dim3(256), 0, st, n, npad, n_e,
+                     eid, SG, vt, vat, d);
+}
+
+// Finite-field potential (Eqs. 13, 14) from its cached pieces: v = -dv0 zeta
+// and d = S v = -dv0 (S zeta) (szeta NULL: d untouched).
+__global__ void k_scale_field(int npad, double dv0, const double* __restrict__ zeta,
+                              const double* __restrict__ szeta, double* __restrict__ vat,
+                              double* __restrict__ d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= npad) return;
+  vat[i] = -dv0 * zeta[i];
+  if (szeta) d[i] = -dv0 * szeta[i];
+}
+
+void launch_scale_field(hipStream_t st, int npad, double dv0, const double* zeta,
+                        const double* szeta, double* vat, double* d) {
+  hipLaunchKernelGGL(k_scale_field, dim3((npad + 255) / 256), dim3(256), 0, st, npad, dv0, zeta,
+                     szeta, vat, d);
 }
 
 // Per configuration b (one workgroup): y = A^-1 b is given (row b of yt);

@@ -246,15 +246,6 @@ def isolated_cluster(n_elec: int, n_ions: int, seed: int = BASE_SEED, spread: fl
     return R, eid, r, q
 
 
-def finite_field_zeta(z: np.ndarray, eid: np.ndarray, Lz: float, bottom: int = 0) -> np.ndarray:
-    """Normalised z positions of the finite-field method (Sec. II.F): z / Lz,
-    with the bottom electrode shifted by one cell (+1) so that the two
-    electrodes form one conductor across the periodic z boundary (the
-    conductor-centred supercell).  The applied potential is -dv0 * zeta."""
-    zeta = np.asarray(z, np.float64) / Lz
-    return zeta + (np.asarray(eid) == bottom)
-
-
 def coaxial_tubes(n1: int, n2: int, dcc: float = D_CC):
     """Two co-axial armchair tubes (n1,n1)@(n2,n2), one axial period
     (sqrt(3) d) along z, axis at the origin.  Returns (R, eid, R1, R2, period)."""

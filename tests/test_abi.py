@@ -145,3 +145,83 @@ def test_electrolyte_validation_on_host():
         ctx.set_electrolyte(w.electrolyte_q)
     assert ei.value.status == cpm.ESTATE
     ctx.close()
+
+
+def test_null_arguments_of_state_and_field_calls():
+    L = cpm.lib()
+    assert L.cpm_set_field(None, 1.0, 0) == cpm.EINVAL
+    assert L.cpm_save(None, b"x") == cpm.EINVAL
+    assert L.cpm_load(None, b"x") == cpm.EINVAL
+    assert L.cpm_inspect_file(None, None) == cpm.EINVAL
+
+
+def test_state_calls_out_of_order(tmp_path):
+    """Saving, loading or setting a field before the electrodes exist is a
+    call-order error, reported before any device work."""
+    from paper_2203_15461_amd import inputs as I
+    w = I.small_capacitor("a")
+    ctx = _ctx(w)
+    for call in (lambda: ctx.save(str(tmp_path / "s.cpm")), lambda: ctx.set_field(1.0, 0)):
+        with pytest.raises(cpm.CpmError) as ei:
+            call()
+        assert ei.value.status == cpm.ESTATE
+    with pytest.raises(cpm.CpmError) as ei:
+        ctx.load(str(tmp_path / "missing.cpm"))
+    assert ei.value.status == cpm.ESTATE
+    ctx.close()
+
+
+# ---- state file header (cpm_save / cpm_load layout, include/cpm.h) ----------
+
+def _fnv1a(data: bytes, h: int = 1469598103934665603) -> int:
+    for byte in data:
+        h ^= byte
+        h = (h * 1099511628211) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def _state_file(path, n=5, n_e=2, matrices=2, store=5, ghash=0x1234, s_sum=0.75, version=1,
+                magic=b"CPMSTATE", payload=None, corrupt_check=False, extra=b""):
+    """A state file laid out as cpm_save writes it: 256-byte header, the
+    matrices, the 8-byte payload checksum."""
+    import struct
+    knobs = [14.757, 25.56, 30.0, 3.0, 1.979, 0.3, 12.0, 1e-8, 0.0, 14.399645478425668, 90.0, 2.5]
+    nbytes = matrices * n * n * 8
+    head = magic + struct.pack("<IIiiIIQd", version, 256, n, n_e, matrices, store, ghash, s_sum)
+    head += struct.pack("<12d", *knobs) + struct.pack("<iiQ", 0, 0, nbytes)
+    head += bytes(256 - 8 - len(head))
+    chk = _fnv1a(head)
+    if corrupt_check:
+        chk ^= 1
+    head += struct.pack("<Q", chk)
+    assert len(head) == 256
+    body = payload if payload is not None else bytes(nbytes)
+    with open(path, "wb") as f:
+        f.write(head + body + bytes(8) + extra)
+
+
+def test_inspect_reads_a_valid_header(tmp_path):
+    p = tmp_path / "ok.cpm"
+    _state_file(p)
+    info = cpm.inspect_file(str(p))
+    assert (info["n"], info["n_e"], info["matrices"], info["store"]) == (5, 2, 2, 5)
+    assert info["geometry_hash"] == 0x1234 and info["s_sum"] == 0.75
+    assert info["params"]["eta"] == 1.979 and info["params"]["coulomb_k"] == 14.399645478425668
+
+
+@pytest.mark.parametrize("damage", ["magic", "version", "check", "truncated", "extended",
+                                    "matrices", "n_e"])
+def test_inspect_rejects_damaged_files(tmp_path, damage):
+    p = tmp_path / "bad.cpm"
+    kw = {"magic": dict(magic=b"CPMSTATX"), "version": dict(version=2),
+          "check": dict(corrupt_check=True), "truncated": dict(payload=bytes(2 * 25 * 8 - 8)),
+          "extended": dict(extra=b"\0"), "matrices": dict(matrices=3), "n_e": dict(n_e=9)}[damage]
+    _state_file(p, **kw)
+    with pytest.raises(cpm.CpmError) as ei:
+        cpm.inspect_file(str(p))
+    assert ei.value.status == cpm.EINVAL
+
+
+def test_inspect_missing_file(tmp_path):
+    with pytest.raises(cpm.CpmError):
+        cpm.inspect_file(str(tmp_path / "none.cpm"))

@@ -156,7 +156,7 @@ def test_cg_finite_field_3d(cpm):
     Lz = 45.0
     say("cg finite field, 3D periodic")
     p = O.params_for(w, Lz=Lz, geometry="tinfoil")
-    zeta = I.finite_field_zeta(w.electrode_xyz[:, 2], w.electrode_id, Lz)
+    zeta = O.finite_field_zeta(w.electrode_xyz[:, 2], w.electrode_id, Lz)
     v = -1.5 * zeta
     gp = cpm.Params(w.Lx, w.Ly, Lz, 1.0, w.eta, w.alpha, w.rcut, w.kspace_eps, geometry=2)
     ctx = cpm.Context(gp)

@@ -70,7 +70,7 @@ def test_finite_field_3d_periodic(cpm, Lz):
     w = I.small_capacitor("a")
     say(f"3D periodic small_capacitor_a Lz={Lz}")
     p = O.params_for(w, Lz=Lz, geometry="tinfoil")
-    zeta = I.finite_field_zeta(w.electrode_xyz[:, 2], w.electrode_id, Lz)
+    zeta = O.finite_field_zeta(w.electrode_xyz[:, 2], w.electrode_id, Lz)
     dv0 = 1.5
     r = I.snapshot(w, 2)
     A = O.elastance(w.electrode_xyz, p)
@@ -113,7 +113,38 @@ def test_wire_coaxial_tubes(cpm):
     assert rel(bg, b) < 1e-10
     assert rel(qg, q) < 1e-10
     assert abs(qg.sum()) <= 1e-12
-    # capacitance per length against the co-axial closed form (loose: small radii)
-    C0 = O.electrode_capacitance(cap.S, eid, 2)[0, 0]
-    ana = 2 * math.pi * O.EPS0 * per / math.log(R2 / R1)
-    assert 0 < C0 / ana - 1 < 0.2
+
+
+def _device_C0(C, R, eid, params):
+    """Vacuum capacitance g^T S g from the device's S (Scalfi's C~ of Sec. III.B)."""
+    n = len(R)
+    ctx = C.Context(params)
+    ctx.set_electrolyte(np.zeros(0))
+    ctx.build_elastance(torch.as_tensor(R, dtype=torch.float64, device="cuda").contiguous(),
+                        torch.as_tensor(eid, dtype=torch.int32, device="cuda").contiguous(), 2)
+    ctx.invert(1)
+    S = ctx.copy_matrix(2, torch.empty((n, n), dtype=torch.float64, device="cuda"))
+    ctx.synchronize()
+    S = S.cpu().numpy()
+    ctx.close()
+    g = (np.asarray(eid) == 0).astype(np.float64)
+    return float(g @ S @ g)
+
+
+def test_wire_coaxial_closed_form_on_device(cpm):
+    """Sec. III.B on the device: co-axial armchair tubes (n,n)@(2n,2n) with
+    R2/R1 = 2; C0/L from the device's S approaches 2 pi eps0 / ln 2 as the
+    radii grow, the deviation shrinking about as 1/R (under 4% at n = 16)."""
+    dev = {}
+    for n1 in (4, 8, 16):
+        R, eid, R1, R2, per = I.coaxial_tubes(n1, 2 * n1)
+        Lxy = 2 * R2 + 40.0
+        R = R + np.array([Lxy / 2, Lxy / 2, 0.0])
+        gp = cpm.Params(Lxy, Lxy, per, 1.0, 1.979, 0.3, 14.0, 1e-10, geometry=1)
+        C0 = _device_C0(cpm, R, eid, gp)
+        ana = 2 * math.pi * O.EPS0 * per / math.log(R2 / R1)
+        dev[n1] = C0 / ana - 1
+        say(f"co-axial ({n1},{n1})@({2 * n1},{2 * n1}): C0/ana - 1 = {dev[n1]:.4f}")
+    assert 0 < dev[16] < dev[8] < dev[4]
+    assert dev[16] < 0.04
+    assert 1.6 < dev[4] / dev[8] < 2.4 and 1.6 < dev[8] / dev[16] < 2.4

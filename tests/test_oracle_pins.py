@@ -11,7 +11,12 @@ worked numbers for A, b or q, so these are the anchors:
 * Ewald splitting alpha: A, b and q do not depend on it;
 * parallel plates: d(1/C0)/dd = 1/(eps0 Area) exactly (slab term in A);
 * Green reciprocity: Q_top = -C0 M_z / (eps0 Area) (slab term in b);
-* co-axial tubes: C0/L -> 2 pi eps0 / ln(R2/R1) (Sec. III.B, wire term);
+* co-axial tubes: C0/L -> 2 pi eps0 / ln(R2/R1) (Sec. III.B);
+* wire term (Eq. 11): a dipolar cluster in a wire cell whose transverse box
+  grows approaches the direct 1D-periodic sum as L^-4 (L^-2 with a wrong
+  coefficient);
+* finite field (Eqs. 13-14): the field-driven vacuum capacitor in a 3D cell
+  extrapolates to the slab CPM capacitor at the same potential difference;
 * Eq. 4 identities, invariances and an LU cross-check of the inverse.
 """
 import math
@@ -19,6 +24,7 @@ import math
 import numpy as np
 import pytest
 from scipy.special import erf
+from scipy.special import zeta as riemann_zeta
 
 from oracle import cpm_oracle as O
 from paper_2203_15461_amd import inputs as I
@@ -142,7 +148,7 @@ def test_finite_field_is_cpm_with_field_potential(small):
     A = O.elastance(small.electrode_xyz, p)
     cap = O.capacitance(A)
     b = O.potential_vector(small.electrode_xyz, small.electrolyte_xyz, small.electrolyte_q, p)
-    zeta = I.finite_field_zeta(small.electrode_xyz[:, 2], small.electrode_id, 45.0)
+    zeta = O.finite_field_zeta(small.electrode_xyz[:, 2], small.electrode_id, 45.0)
     dv0 = 1.3
     q = O.charges(cap.S, b, -dv0 * zeta)
     assert abs(q.sum()) < 1e-12
@@ -155,6 +161,172 @@ def test_finite_field_is_cpm_with_field_potential(small):
     # (zeta offset by +1, so the lower applied potential) goes negative
     Q = O.electrode_totals(O.charges(cap.S, 0 * b, -dv0 * zeta), small.electrode_id, 2)
     assert Q[0] < 0 < Q[1] and abs(Q.sum()) < 1e-12
+
+
+# --- finite field: zeta of Eq. 14 ------------------------------------------------
+
+def _ff_capacitor(layers):
+    """Two AB-stacked graphite electrodes of `layers` layers (4 x 4 cells per
+    layer), 30 A apart, no electrolyte."""
+    zb = [k * I.LAYER_SPACING for k in range(layers)]
+    zt = [zb[-1] + 30.0 + k * I.LAYER_SPACING for k in range(layers)]
+    xyz, eid, Lx, Ly = I._two_electrodes(4, 4, zb, zt, "zigzag")
+    return xyz, eid, Lx, Ly, zt[-1] - zb[0]
+
+
+def _ff_inverse_charges(xyz, eid, Lx, Ly, h, gaps, zeta_fn=None):
+    """1/Q_top of the field-driven capacitor (dv0 = 1 V) in 3D-periodic cells
+    Lz = h + g' for each outer gap g' (the vacuum between the electrodes'
+    outer layers across the periodic boundary)."""
+    zeta_fn = zeta_fn or O.finite_field_zeta
+    out = []
+    for g in gaps:
+        Lz = h + g
+        p = O.Params(Lx, Ly, Lz, geometry="tinfoil", **TIGHT)
+        S = O.capacitance(O.elastance(xyz, p)).S
+        q = O.charges(S, np.zeros(len(xyz)), -1.0 * zeta_fn(xyz[:, 2], eid, Lz))
+        out.append(1.0 / O.electrode_totals(q, eid, 2)[1])
+    return np.array(out)
+
+
+def _slab_inverse_charge(xyz, eid, Lx, Ly, h):
+    """1/Q_top of the same capacitor as a slab (EW3DC) CPM at 1 V."""
+    S = O.capacitance(O.elastance(xyz, O.Params(Lx, Ly, 3 * h, **TIGHT))).S
+    return 1.0 / O.electrode_totals(O.charges(S, np.zeros(len(xyz)),
+                                              O.applied_potential(eid, [-0.5, 0.5])), eid, 2)[1]
+
+
+def test_finite_field_single_layers_extrapolate_to_slab():
+    """Single-layer electrodes in a 3D cell, driven by -dv0 zeta alone: the
+    outer gap g' acts as a second capacitor in series, so 1/Q is linear in
+    1/g' (uniform layers, no lateral structure), and as g' grows the field
+    method becomes the slab CPM at a potential difference dv0.  The intercept
+    of 1/Q against 1/g' equals the slab 1/Q to 1e-12 (zeta's 1/Lz scale and
+    the bottom electrode's offset), and three gaps are collinear."""
+    cap = _ff_capacitor(1)
+    inv = _ff_inverse_charges(*cap, gaps=(20.0, 40.0, 80.0))
+    slab = _slab_inverse_charge(*cap)
+    x = 1.0 / np.array([20.0, 40.0, 80.0])
+    slope = (inv[1] - inv[0]) / (x[1] - x[0])
+    assert abs((inv[1] - slope * x[1]) / slab - 1) < 1e-12
+    assert abs((inv[0] + slope * (x[2] - x[0])) / inv[2] - 1) < 1e-12
+    assert inv[0] > 0
+
+
+def test_finite_field_graphite_extrapolates_to_slab():
+    """Three-layer electrodes: the field reaches the inner layers of each
+    electrode, so zeta must vary with z inside it as z / Lz.  A cubic in 1/g'
+    through g' = 20 .. 160 A meets the slab 1/Q to 1e-9."""
+    cap = _ff_capacitor(3)
+    gaps = (20.0, 40.0, 80.0, 160.0)
+    inv = _ff_inverse_charges(*cap, gaps=gaps)
+    c = np.polyfit(1.0 / np.array(gaps), inv, 3)
+    assert abs(c[-1] / _slab_inverse_charge(*cap) - 1) < 1e-9
+
+
+@pytest.mark.parametrize("mistake", ["no_offset", "scaled_by_h", "per_electrode"])
+def test_finite_field_pins_catch_planted_zeta(mistake):
+    """Plausible slips in zeta fail the extrapolation pins: no +1 offset for
+    the bottom electrode, z scaled by the slab height instead of Lz, or one
+    value per electrode (its inner layer's) instead of one per atom."""
+    def planted(z, eid, Lz, bottom=0):
+        z, eid = np.asarray(z, np.float64), np.asarray(eid)
+        if mistake == "no_offset":
+            return z / Lz
+        if mistake == "scaled_by_h":
+            return z / (z.max() - z.min()) + (eid == bottom)
+        out = np.zeros(len(z))
+        for e in (0, 1):
+            m = eid == e
+            out[m] = (z[m].max() if e == bottom else z[m].min()) / Lz + (e == bottom)
+        return out
+    layers = 3 if mistake == "per_electrode" else 1
+    cap = _ff_capacitor(layers)
+    gaps = (20.0, 40.0, 80.0, 160.0)
+    inv = _ff_inverse_charges(*cap, gaps=gaps, zeta_fn=planted)
+    c = np.polyfit(1.0 / np.array(gaps), inv, 3)
+    assert abs(c[-1] / _slab_inverse_charge(*cap) - 1) > 1e-4
+
+
+# --- wire dipole term (Eq. 11) ----------------------------------------------------
+
+WIRE_PERIOD = 8.0
+WIRE_N = 3000
+
+
+def _direct_wire_sum(d, width):
+    """sum over the z images n (|n| <= WIRE_N) of erf(width r_n)/r_n with
+    r_n = |d + n Lz z|, minus the uniform 2 H_N / Lz, plus the tail of
+    sum_{|n| > N} (1/r_n - 1/(|n| Lz)) = (3 d_z^2 - d^2) / Lz^3 sum_{n > N} n^-3
+    (+ O(N^-4)).  The subtracted part is the same for every pair, so it drops
+    out of S, and out of b for a neutral electrolyte."""
+    Lz = WIRE_PERIOD
+    ns = np.arange(-WIRE_N, WIRE_N + 1)
+    dd = d[None, :] + ns[:, None] * np.array([0.0, 0.0, Lz])
+    r = np.sqrt((dd * dd).sum(1))
+    r = r[r > 0]
+    h1 = (1.0 / np.arange(1, WIRE_N + 1)).sum()
+    h3 = riemann_zeta(3) - (1.0 / np.arange(1, WIRE_N + 1) ** 3).sum()
+    return (erf(width * r) / r).sum() - 2.0 * h1 / Lz + (3 * d[2] ** 2 - d @ d) / Lz ** 3 * h3
+
+
+def _wire_cluster():
+    """The 6-atom, 4-charge cluster of the box tests, periodic along z with
+    period 8 A, solved by direct 1D image sums (no Ewald, no dipole term)."""
+    R, eid, r, q = I.isolated_cluster(6, 4)
+    eta = 1.979
+    n = len(R)
+    A = np.zeros((n, n))
+    for i in range(n):
+        for j in range(n):
+            A[i, j] = _direct_wire_sum(R[i] - R[j], eta / math.sqrt(2.0))
+        A[i, i] += eta * math.sqrt(2.0 / math.pi)        # own Gaussian, n = 0
+    b = np.array([-sum(q[j] * _direct_wire_sum(R[i] - r[j], eta) for j in range(len(r)))
+                  for i in range(n)])
+    v = O.applied_potential(eid, [-0.5, 0.5])
+    q1d = O.charges(O.capacitance(O.KE * A).S, O.KE * b, v)
+    return R, eid, r, q, v, q1d
+
+
+def _wire_errors(cluster, Ls):
+    R, eid, r, q, v, q1d = cluster
+    errs, qs = [], []
+    for L in Ls:
+        c = np.array([L / 2, L / 2, 0.0])
+        p = O.Params(L, L, WIRE_PERIOD, alpha=0.3, geometry="wire", **TIGHT)
+        S = O.capacitance(O.elastance(R + c, p)).S
+        qq = O.charges(S, O.potential_vector(R + c, r + c, q, p), v)
+        qs.append(qq)
+        errs.append(rel(qq, q1d))
+    return errs, qs, q1d
+
+
+def test_wire_term_against_direct_1d_sum():
+    """Eq. 11: the 3D Ewald sum of a wire cell plus (pi/V)(M_x^2 + M_y^2)
+    approaches the 1D-periodic system as the transverse box L grows.  The
+    cluster carries an in-plane dipole, so the coefficient matters: the error
+    falls as L^-4 (order within 0.1 of 4), and the Richardson extrapolation
+    meets the direct sum to 1e-8."""
+    Ls = [20.0, 40.0, 80.0, 160.0]
+    errs, qs, q1d = _wire_errors(_wire_cluster(), Ls)
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(3)]
+    for o in orders[1:]:
+        assert abs(o - 4.0) < 0.1, orders
+    r1 = [qs[i + 1] + (qs[i + 1] - qs[i]) / 15.0 for i in range(3)]
+    r2 = r1[2] + (r1[2] - r1[1]) / 63.0
+    assert rel(r2, q1d) < 1e-8
+
+
+@pytest.mark.parametrize("coef", [2 * math.pi, 0.0])
+def test_wire_pin_catches_planted_coefficient(monkeypatch, coef):
+    """With the wire coefficient planted as 2 pi / V or 0 the error falls only
+    as L^-2, and the pin above fails."""
+    monkeypatch.setattr(O, "dipole_terms",
+                        lambda p: [(coef / p.volume, 0), (coef / p.volume, 1)] if coef else [])
+    errs, _, _ = _wire_errors(_wire_cluster(), [40.0, 80.0, 160.0])
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert all(abs(o - 2.0) < 0.1 for o in orders), orders
+    assert errs[-1] > 1e-4
 
 
 # --- slab dipole term ------------------------------------------------------------
