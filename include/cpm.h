@@ -282,6 +282,25 @@ cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
 cpm_status cpm_solve_charges(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32,
                              unsigned mode, double* d_q, double* d_Qe);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the same
+ * solve as cpm_solve_charges (same arguments, modes, kernels and results),
+ * with its work buffers in one fixed device array of
+ * CPM_NOALLOC_SCRATCH_BYTES per GPU instead of context memory.  Nothing is
+ * allocated or freed (the split-BF16 product runs without its split-K
+ * option).  The array is held by every GPU the library runs on until the
+ * process ends; each call clears the part it uses (a fill kernel).  Sizes:
+ * the batch (rounded up to 64 for the matrix-core modes) times the padded
+ * n, 5 doubles per element for the matrix-core modes, 4 otherwise, must fit
+ * the array (e.g. 128 configurations at n = 2880), else CPM_EINVAL with the
+ * bytes needed.  All calls on one GPU share the array: calls that overlap
+ * in time on one GPU (two streams, two threads) race and must be ordered by
+ * the caller.  The device's array address is looked up on the first call
+ * on each device (the device current at the call). */
+#define CPM_NOALLOC_SCRATCH_BYTES (16u << 20)
+cpm_status cpm_solve_charges_noalloc(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32,
+                                     unsigned mode, double* d_q, double* d_Qe);
+
 /* Constrained charge method (Sec. II.C, Eq. 7): set the total charge of
  * each electrode, h_Q[n_e] (e, host memory; must sum to zero within 1e-12
  * relative, else CPM_EINVAL; n_e <= 16).  Computes U = A^-1 G and the

@@ -34,7 +34,7 @@ EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_inve
            "cpm_solve_grouped", "cpm_set_charge", "cpm_set_potential_atoms", "cpm_build_operator",
            "cpm_apply_elastance", "cpm_solve_cg", "cpm_get_info",
            "cpm_enable_timing", "cpm_get_timing", "cpm_set_field", "cpm_save", "cpm_load",
-           "cpm_inspect_file",
+           "cpm_inspect_file", "cpm_solve_charges_noalloc",
            "cpm_synchronize", "cpm_last_error", "cpm_destroy")
 
 
@@ -50,6 +50,9 @@ class CpmFileInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int), ("n_e", ctypes.c_int), ("matrices", ctypes.c_int),
                 ("store", ctypes.c_uint), ("geometry_hash", ctypes.c_ulonglong),
                 ("s_sum", ctypes.c_double), ("params", CpmParams)]
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class CpmError(RuntimeError):
@@ -99,6 +102,7 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_save": ([vp, ctypes.c_char_p], i),
         "cpm_load": ([vp, ctypes.c_char_p], i),
         "cpm_inspect_file": ([ctypes.c_char_p, ctypes.POINTER(CpmFileInfo)], i),
+        "cpm_solve_charges_noalloc": ([vp, i, vp, i, u, vp, vp], i),
         "cpm_last_error": ([vp], ctypes.c_char_p),
         "cpm_destroy": ([vp], None),
     }
@@ -305,6 +309,23 @@ class Context:
                 raise ValueError(f"Qe must be (batch, {ne})")
         self._check(self._lib.cpm_solve_charges(self._h, b.shape[0], _ptr(b), f32, mode, _ptr(q_out),
                                                 _ptr(Qe_out)), "cpm_solve_charges")
+        return q_out
+
+    def solve_charges_noalloc(self, b, mode: int, q_out, Qe_out=None):
+        """cpm_solve_charges with the work buffers in the library's fixed
+        scratch array (allocates nothing)."""
+        _expect(q_out, "float64", 2)
+        f32 = _is_f32(b)
+        n, ne = int(self.info("n")), int(self.info("ne"))
+        if b.dim() != 2 or tuple(b.shape) != tuple(q_out.shape) or b.shape[1] != n:
+            raise ValueError(f"b {tuple(b.shape)} and q {tuple(q_out.shape)} must both be (batch, {n})")
+        if Qe_out is not None:
+            _expect(Qe_out, "float64", 2)
+            if tuple(Qe_out.shape) != (b.shape[0], ne):
+                raise ValueError(f"Qe must be (batch, {ne})")
+        self._check(self._lib.cpm_solve_charges_noalloc(self._h, b.shape[0], _ptr(b), f32, mode,
+                                                        _ptr(q_out), _ptr(Qe_out)),
+                    "cpm_solve_charges_noalloc")
         return q_out
 
     def apply_elastance(self, x, y_out):

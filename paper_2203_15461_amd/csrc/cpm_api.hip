@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include <string>
@@ -596,8 +597,8 @@ cpm_status ensure_kpart(cpm_ctx* c, size_t len) {
   return CPM_OK;
 }
 
-// work buffers of one solve (the context's own, grown on demand, unless a
-// caller supplies another set)
+// work buffers of one solve: the context's own (grown on demand), or carved
+// out of the fixed scratch array of cpm_solve_charges_noalloc
 struct SolveWork {
   double* qt; double* res; double* bpad; double* qpad; double* means; double* kpart;
   uint16_t* xhi; uint16_t* xlo;
@@ -1828,6 +1829,88 @@ cpm_status cpm_solve_charges(cpm_ctx* c, int batch, const void* d_b, int b_is_f3
   if (!c) return CPM_EINVAL;
   TRY(sc_prepare(c, batch, d_b, b_is_f32, mode, d_q));
   return sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe, ctx_work(c));
+}
+
+}  // extern "C"
+
+// the fixed work array of cpm_solve_charges_noalloc (one per GPU)
+static __device__ __align__(256) double scratch[CPM_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+
+// ---- solve without allocation (cpm_solve_charges_noalloc) -----------------
+// The work buffers live in one fixed device array per GPU.  Host code never
+// uses the array's name as an address: its device address is looked up once
+// per device with hipGetSymbolAddress (with that device current) and kept.
+constexpr size_t NOALLOC_BYTES = (size_t)CPM_NOALLOC_SCRATCH_BYTES;
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex scratch_mu;
+double* scratch_dev[NOALLOC_MAX_DEVICES] = {};
+
+cpm_status scratch_address(cpm_ctx* c, double** out) {
+  int dev = -1;
+  HIP_TRY(c, hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(c, CPM_EUNSUPPORTED, "device %d beyond the %d the scratch table holds", dev,
+                NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> lk(scratch_mu);
+  if (!scratch_dev[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(c, CPM_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    scratch_dev[dev] = static_cast<double*>(p);
+  }
+  *out = scratch_dev[dev];
+  return CPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+cpm_status cpm_solve_charges_noalloc(cpm_ctx* c, int batch, const void* d_b, int b_is_f32,
+                                     unsigned mode, double* d_q, double* d_Qe) {
+  if (!c) return CPM_EINVAL;
+  TRY(sc_validate(c, batch, d_b, b_is_f32, mode, d_q));
+  const unsigned prec = mode & 0xffu;
+  const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
+  const size_t rows = gemm ? ((size_t)(batch + TILE - 1) / TILE) * TILE : (size_t)batch;
+  const size_t sz = rows * c->npad;              // doubles per work matrix
+  // qt, res, qpad, bpad (FP64), the BF16 pairs of the left operand (half a
+  // matrix of doubles each), the row means (rounded to 256 bytes)
+  const size_t means = (rows + 31) / 32 * 32;
+  const size_t need = 4 * sz + (gemm ? sz : 0) + means;
+  if (need * sizeof(double) > NOALLOC_BYTES)
+    return fail(c, CPM_EINVAL,
+                "batch %d at n = %d needs %zu bytes of work space, more than the %zu of the fixed "
+                "scratch array; use cpm_solve_charges", batch, c->n, need * sizeof(double),
+                NOALLOC_BYTES);
+  double* base = nullptr;
+  TRY(scratch_address(c, &base));
+  SolveWork w{};
+  w.qt = base;
+  w.res = base + sz;
+  w.qpad = base + 2 * sz;
+  w.bpad = base + 3 * sz;
+  w.means = base + 4 * sz;
+  w.xhi = gemm ? reinterpret_cast<uint16_t*>(base + 4 * sz + means) : nullptr;
+  w.xlo = gemm ? w.xhi + sz : nullptr;
+  w.kpart = nullptr;
+  cpm_ctx::GemmCfg cfg = bf16_cfg(c, (int)rows);
+  if (cfg.ks != 1) { cfg.ks = 1; cfg.grid = 0; }   // no split-K partials
+  w.bf16 = &cfg;
+  // the array keeps the previous call's contents: clear it (a fill kernel,
+  // so the call can also sit inside a captured graph)
+  launch_fill_zero(c->stream, need * 2, reinterpret_cast<float*>(base));
+  TRY(launched(c, "scratch clear"));
+  const bool timing = c->timing;
+  c->timing = false;                              // no event creation on this path
+  const cpm_status st = sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe, w);
+  c->timing = timing;
+  return st;
 }
 
 cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32,

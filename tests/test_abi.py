@@ -153,6 +153,7 @@ def test_null_arguments_of_state_and_field_calls():
     assert L.cpm_save(None, b"x") == cpm.EINVAL
     assert L.cpm_load(None, b"x") == cpm.EINVAL
     assert L.cpm_inspect_file(None, None) == cpm.EINVAL
+    assert L.cpm_solve_charges_noalloc(None, 1, None, 0, 0, None, None) == cpm.EINVAL
 
 
 def test_state_calls_out_of_order(tmp_path):
