@@ -12,6 +12,12 @@ Cholesky-invert it and form S (FP64), set the applied potential, then for all
 B snapshots compute b and solve q = S (b + v) with the neutrality projection
 and electrode totals.  `value` = B * K / (timed seconds).  Inputs are
 resident in HBM before the timed region; all work runs in libcpm's kernels.
+
+The same line carries the metric's second point (the 20064-atom capacitor,
+128 configurations per step, Ewald split retuned to alpha 0.22 / r_c 16.36 A
+at the same truncation accuracy), the uneven eight-capacitor batch, the
+batched FP64 matrix-core comparator, warm and cache-flushed matvec rates, the
+real-space kernel's roofline and the FP64 oracle timed on the host cores.
 """
 from __future__ import annotations
 
@@ -35,6 +41,12 @@ PEAK_FP64_VALU = 78.6e12     # FLOP/s, MI355X FP64 vector
 PEAK_FP32_VALU = 157.3e12
 PEAK_HBM = 8.0e12            # B/s
 DOMINANT = "structure_factor"
+# Ewald split of the 20064-atom capacitor: q does not depend on alpha; a
+# smaller alpha moves work from the k-space sum (|K+| ~ alpha^3) to the real
+# space (r_c^3 ~ alpha^-3); r_c = 3.6 / alpha keeps erfc(alpha r_c) at its
+# alpha 0.3, r_c 12 A value and k_c = 2 alpha sqrt(ln 1e8) the k-space accuracy
+ALPHA_20K = 0.22
+REAL_SPACE_FLOP_PER_PAIR = 50.0   # one erfc-difference pair term (distance, g(r), accumulate)
 
 
 def parse():
@@ -50,6 +62,9 @@ def parse():
     ap.add_argument("--no-20k", action="store_true",
                     help="skip the secondary one-step measurement at N = 20064")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the uneven eight-capacitor step")
+    ap.add_argument("--alpha20k", type=float, default=ALPHA_20K,
+                    help="Ewald alpha at N = 20064 (r_c = 3.6 / alpha keeps erfc(alpha r_c))")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 1 GiB device copy (for HBM counter scaling under rocprofv3)")
     return ap.parse_args()
@@ -77,23 +92,35 @@ def main():
         w = I.graphite_capacitor()
         B = args.batch or 1000
     else:
-        w = I.scaled_graphite_capacitor(20000)
+        w = large_capacitor(args.alpha20k)
         B = args.batch or 128
     out = run_workload(args, w, B, args.workload, args.steps, args.warmup, args.calibrate_copy)
+    if args.workload == "graphite_capacitor_2880":
+        out["batched_comparator"] = batched_comparator(w)
     if args.workload == "graphite_capacitor_2880" and not args.no_20k:
         # the metric's second point: one step at N = 20064 with 128
         # configurations, the per-capacitor snapshot count of the uneven batch
-        w20 = I.scaled_graphite_capacitor(20000)
+        w20 = large_capacitor(args.alpha20k)
         r = run_workload(args, w20, 128, "graphite_capacitor_20064", 1, 1, False)
         out["workload_20064"] = {k: r[k] for k in ("value", "ms_per_step", "config", "roofline",
-                                                   "phase_s", "solve_only_rate",
-                                                   "plain_fp64_per_step_rate",
+                                                   "roofline_real_space", "phase_s",
+                                                   "solve_only_rate", "plain_fp64_per_step_rate",
                                                    "graph_fp64_per_step", "matvec_roofline",
                                                    "conjugate_gradient", "max_abs_sum_q")}
+    if args.workload == "graphite_capacitor_2880" and not args.no_mixed:
+        margs = argparse.Namespace(**vars(args))
+        margs.steps, margs.warmup, margs.batch = 1, 1, None
+        out["mixed8"] = run_mixed(margs)
     if not args.no_cpu_baseline and w.n < 10000:
         out["cpu_baseline"], q_ref, Q_ref = cpu_baseline(w)
         out["accuracy_vs_oracle"] = accuracy_vs_oracle(w, q_ref, Q_ref)
     print(json.dumps(out), flush=True)
+
+
+def large_capacitor(alpha):
+    """The 20064-atom capacitor with the Ewald split at alpha, r_c = 3.6 / alpha."""
+    from paper_2203_15461_amd import inputs as I
+    return I.scaled_graphite_capacitor(20000).with_(alpha=alpha, rcut=3.6 / alpha)
 
 
 def synthetic_configurations(w, B, seed, dev):
@@ -170,6 +197,8 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
             "row_means", "pad_rows", "make_rhs", "center_rows"]
     timing = {f: ctx.timing(f) for f in fams}
     ctx.enable_timing(False)
+    rs_ms, rs_cnt = timing["real_space_b"]
+    rs_roof = real_space_roofline(w, xyz, B, rs_ms, rs_cnt)
 
     # per-phase split of one more (untimed) step, for the JSON context fields
     torch.cuda.synchronize()
@@ -251,6 +280,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
                      "avg_launch_us": sf_avg * 1e6,
                      "configurations_per_launch": snaps_per_launch,
                      "launch_group": int(ctx.info("group"))},
+        "roofline_real_space": rs_roof,
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),
         "plain_fp64_per_step_rate": plain_rate,
@@ -334,8 +364,10 @@ def run_mixed(args):
 
 def matvec_roofline(ctx, w, xyz, dev, reps=20):
     """HBM rate of the single-vector solve kernels: S streamed once per solve
-    (FP64: 8 N^2 bytes, FP32: 4 N^2 bytes).  A and S must already be built;
-    leaves the context with FP64 and FP32 copies of S."""
+    (FP64: 8 N^2 bytes, FP32: 4 N^2 bytes).  `warm`: back-to-back solves
+    (below 256 MB, N < ~5800 in FP64, S can stay in the last-level cache);
+    `cold`: each solve after a 1 GiB write that evicts it.  A and S must
+    already be built; leaves the context with FP64 and FP32 copies of S."""
     import torch
     ctx.invert(1 | 2)
     ctx.set_potential(w.v_electrode)
@@ -343,21 +375,101 @@ def matvec_roofline(ctx, w, xyz, dev, reps=20):
     ctx.potential_vector(xyz[:1], b1)
     q1 = torch.empty((1, w.n), dtype=torch.float64, device=dev)
     b32 = b1.float()
+    flush = torch.empty(1 << 27, dtype=torch.float64, device=dev)       # 1 GiB
     out = {}
     for fam, mode, bb, bytes_per in (("matvec_f64", 0x000, b1, 8), ("matvec_f32", 0x001, b32, 4)):
-        ctx.solve_charges(bb, mode, q1)
-        ctx.enable_timing(fam)
-        for _ in range(reps):
-            ctx.solve_charges(bb, mode, q1)
-        ms, cnt = ctx.timing(fam)
-        ctx.enable_timing(False)
-        avg = ms / max(cnt, 1) * 1e-3
         alg = bytes_per * float(w.n) ** 2
-        out[fam] = {"bound": "hbm", "achieved": alg / avg / 1e9, "peak": PEAK_HBM / 1e9,
-                    "unit": "GB/s", "frac": alg / avg / PEAK_HBM, "bytes_per_launch": alg,
-                    "avg_launch_us": avg * 1e6}
-    out["note"] = ("S held across back-to-back solves; below 256 MB (N < ~5800 in FP64) it can "
-                   "stay in the last-level cache, so N = 20064 is the HBM figure")
+        rec = {"bound": "hbm", "peak": PEAK_HBM / 1e9, "unit": "GB/s", "bytes_per_launch": alg}
+        for kind in ("warm", "cold"):
+            ctx.solve_charges(bb, mode, q1)
+            ctx.enable_timing(fam)
+            for _ in range(reps if kind == "warm" else 5):
+                if kind == "cold":
+                    flush.fill_(1.0)
+                    torch.cuda.synchronize()
+                ctx.solve_charges(bb, mode, q1)
+            ms, cnt = ctx.timing(fam)
+            ctx.enable_timing(False)
+            avg = ms / max(cnt, 1) * 1e-3
+            rec[kind] = {"achieved": alg / avg / 1e9, "frac": alg / avg / PEAK_HBM,
+                         "avg_launch_us": avg * 1e6, "launches": cnt}
+        # top-level figures: the cold rate, i.e. S streamed from HBM
+        rec.update(achieved=rec["cold"]["achieved"], frac=rec["cold"]["frac"],
+                   avg_launch_us=rec["cold"]["avg_launch_us"])
+        out[fam] = rec
+    del flush
+    out["note"] = ("cold: a 1 GiB write before every solve evicts S from the caches; warm: "
+                   "back-to-back solves; nontemporal loads from 128 MiB of S on")
+    return out
+
+
+def count_pairs(w, xyz_one):
+    """Electrode-electrolyte pairs closer than r_c in one configuration (all
+    periodic images in x and y; the slab clearance keeps z images beyond r_c)."""
+    import numpy as np
+    from scipy.spatial import cKDTree
+    R = np.array(w.electrode_xyz, dtype=np.float64)
+    r = np.array(xyz_one, dtype=np.float64)
+    z0 = min(R[:, 2].min(), r[:, 2].min()) - 1.0
+    box = [w.Lx, w.Ly, 1e6]
+    def wrap(a):
+        a = a.copy()
+        a[:, 0] %= w.Lx
+        a[:, 1] %= w.Ly
+        a[:, 2] -= z0
+        return a
+    ta, tb = cKDTree(wrap(R), boxsize=box), cKDTree(wrap(r), boxsize=box)
+    return int(ta.count_neighbors(tb, w.rcut * (1 - 1e-12)))
+
+
+def real_space_roofline(w, xyz, B, total_ms, launches):
+    """FP64 rate of the real-space b kernel: REAL_SPACE_FLOP_PER_PAIR per
+    electrode-electrolyte pair inside r_c (pairs counted on the host for the
+    first configuration), times the configurations of one launch, over its
+    average launch time (HIP events on the context stream)."""
+    if not launches:
+        return None
+    pairs = count_pairs(w, xyz[0].cpu().numpy())
+    per_launch_cfg = B / launches
+    flop = REAL_SPACE_FLOP_PER_PAIR * pairs * per_launch_cfg
+    avg = total_ms / launches * 1e-3
+    return {"kernel": "real_space_b", "bound": "alu", "achieved": flop / avg / 1e12,
+            "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": flop / avg / PEAK_FP64_VALU,
+            "traffic": None, "pairs_per_configuration": pairs,
+            "flop_per_pair": REAL_SPACE_FLOP_PER_PAIR, "configurations_per_launch": per_launch_cfg,
+            "avg_launch_us": avg * 1e6, "us_per_configuration": avg * 1e6 / per_launch_cfg}
+
+
+def batched_comparator(w, B=256, reps=5):
+    """The batched solve Q = S B of 256 configurations (the 2880-atom
+    capacitor, b computed beforehand): split-BF16 matrix-core product with one
+    FP64 refinement, against the plain FP64 matrix-core product; solves/s of
+    the solve alone, and the q difference between the two."""
+    import torch
+    from paper_2203_15461_amd import cpm
+    from paper_2203_15461_amd import inputs as I
+    dev = torch.device("cuda:0")
+    ctx = cpm.setup(w, store=cpm.STORE_F64 | cpm.STORE_BF16X2)
+    xyz = synthetic_configurations(w, B, I.BASE_SEED + 3, dev)
+    b = torch.empty((B, w.n), dtype=torch.float64, device=dev)
+    ctx.potential_vector(xyz, b)
+    tune = ctx.autotune(B, reps=3)
+    out = {"configurations": B, "autotune": tune}
+    qs = {}
+    for name, mode in (("bf16x3_refined", 0x102), ("f64_mfma", 0x000)):
+        q = torch.empty_like(b)
+        ctx.solve_charges(b, mode, q)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            ctx.solve_charges(b, mode, q)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / reps
+        out[name] = {"solves_per_s": B / dt, "us_per_batch": dt * 1e6}
+        qs[name] = q
+    out["max_rel_diff_bf16x3_vs_f64"] = float(((qs["bf16x3_refined"] - qs["f64_mfma"]).abs().max()
+                                               / qs["f64_mfma"].abs().max()).item())
+    ctx.close()
     return out
 
 
@@ -556,27 +668,53 @@ def stored_traffic(workload, configs_per_launch):
     return entry["bytes_per_launch"] / per * configs_per_launch
 
 
-def cpu_baseline(w):
-    """The FP64 oracle on the host cores: b and q for one snapshot of the same
-    workload (A and S are built first and not timed: over a 1000-snapshot
-    step they add < 0.1% per solve)."""
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(w, snapshots=5):
+    """The FP64 oracle on the host cores: b and q for `snapshots` snapshots of
+    the same workload, median time per solve (A and S are built first and not
+    timed: over a 1000-snapshot step they add < 0.1% per solve).  `cores` is
+    the process CPU time over the wall time of the timed solves (numpy's
+    elementwise work runs on one thread, its matrix products on the BLAS
+    threads)."""
     import numpy as np
     from oracle import cpm_oracle as O
     from paper_2203_15461_amd import inputs as I
     p = O.params_for(w)
     S = O.capacitance(O.elastance(w.electrode_xyz, p)).S
     v = O.applied_potential(w.electrode_id, w.v_electrode)
-    r = I.snapshot(w, 0)
-    t = time.perf_counter()
-    b = O.potential_vector(w.electrode_xyz, r, w.electrolyte_q, p)
-    q = O.charges(S, b, v)
-    dt = time.perf_counter() - t
-    assert abs(q.sum()) < 1e-10
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    Q = O.electrode_totals(q, w.electrode_id, 2)
-    return {"value": 1.0 / dt, "unit": "solves/s", "cores": threads, "kind": "oracle",
-            "sample": "1 snapshot of graphite_capacitor_2880: b (Ewald real+k+slab) and q = S(b+v) "
-                      f"in FP64 numpy ({dt:.1f} s); A and S built beforehand, untimed"}, q, Q
+    times, cpu, q0 = [], 0.0, None
+    for s_ in range(snapshots):
+        r = I.snapshot(w, s_)
+        t, c = time.perf_counter(), time.process_time()
+        b = O.potential_vector(w.electrode_xyz, r, w.electrolyte_q, p)
+        q = O.charges(S, b, v)
+        times.append(time.perf_counter() - t)
+        cpu += time.process_time() - c
+        assert abs(q.sum()) < 1e-10
+        if s_ == 0:
+            q0 = q
+    med = float(np.median(times))
+    try:
+        from threadpoolctl import threadpool_info
+        blas = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+    except Exception:
+        blas = None
+    Q = O.electrode_totals(q0, w.electrode_id, 2)
+    return {"value": 1.0 / med, "unit": "solves/s", "cores": round(cpu / sum(times), 1),
+            "kind": "oracle", "cpu_model": cpu_model(), "host_threads": os.cpu_count(),
+            "blas_threads": blas, "median_s": med, "min_s": min(times), "max_s": max(times),
+            "sample": f"{snapshots} snapshots of {w.name} (seeds 15461+1..{snapshots}): b "
+                      "(Ewald real + k + slab) and q = S(b+v) in FP64 numpy, median time per "
+                      "solve; A and S built beforehand, untimed"}, q0, Q
 
 
 def accuracy_vs_oracle(w, q_ref, Q_ref):

@@ -1243,11 +1243,11 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
 
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
                          const Buffers& b, int nmap, const double4* cq, const double2* zr,
-                         double Lx, double Ly, double Lz, double rc, double* part) {
-  // configurations spread over the third grid dimension: about two rounds of
-  // 256 workgroups in all
+                         double Lx, double Ly, double Lz, double rc, double* part, int wg_target) {
+  // configurations spread over the third grid dimension, about wg_target
+  // workgroups in all (a workgroup loops over the configurations beyond)
   const int ablk = (nmap + 64 * RS_WAVES - 1) / (64 * RS_WAVES);
-  const int gz = std::max(1, std::min(g, (512 + ablk * rchunks - 1) / (ablk * rchunks)));
+  const int gz = std::max(1, std::min(g, (wg_target + ablk * rchunks - 1) / (ablk * rchunks)));
   dim3 grid(ablk, rchunks, gz), block(64 * RS_WAVES);
   hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, mpad64, b.amap, nmap,
                      b.ex, b.ey, b.ez, cq, zr, Lx, Ly, Lz, rc, b.rtab, part);

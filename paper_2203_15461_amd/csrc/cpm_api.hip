@@ -225,13 +225,24 @@ int sf_chunks_for(const cpm_ctx* c, int g) {
   return (base + step - 1) / step * step;
 }
 
+// workgroups of a grouped real-space launch: enough rounds that the planes'
+// uneven work evens out (2880 atoms, 64 configurations: 4.3 -> 3.9 us per
+// configuration from 512 to 2048; 20064 atoms: 0.81 -> 0.57 ms from 512 to
+// 4096), fewer for small atom maps, where every workgroup's staging of the
+// pair table costs more than it evens out
+int rs_target(const cpm_ctx* c) {
+  if (c->rs_wg_target > 0) return c->rs_wg_target;
+  const int atom_blocks = (c->nmap + real_space_block_atoms() - 1) / real_space_block_atoms();
+  return atom_blocks <= 8 ? 2048 : 4096;
+}
+
 // real-space charge chunks for a launch group of g configurations on the
 // grouped path: the chunks and the configurations (the grid's third
 // dimension) fill about rs_wg_target workgroups together, >= 64 charges per
 // chunk
 int rchunks_for(const cpm_ctx* c, int g) {
   const int atom_blocks = (c->nmap + real_space_block_atoms() - 1) / real_space_block_atoms();
-  const int t = c->rs_wg_target;
+  const int t = rs_target(c);
   return std::max(1, std::min(std::max(1, c->m / 64), (t + atom_blocks * g - 1) / (atom_blocks * g)));
 }
 
@@ -1483,8 +1494,7 @@ cpm_status cpm_set_potential(cpm_ctx* c, const double* h_v_electrode) {
   HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
   // d = S v (more electrodes than the cached response holds)
   if (c->have_inv)
-    launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
-                  0.0, c->b.d, c->npad, 0);
+    launch_matvec(c->stream, 0, c->npad, c->b.S, 1, c->b.vat, nullptr, 0, 0.0, c->b.d, c->npad, 0);
   TRY(launched(c, "set_potential"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_v = true;
@@ -1519,8 +1529,7 @@ cpm_status cpm_set_field(cpm_ctx* c, double dv0, int bottom) {
     // S zeta once per inverse (Eq. 14 with the response cached): a new dv0
     // then costs O(n)
     TRY(dalloc(c, &b.szeta, (size_t)c->npad));
-    launch_matvec(c->stream, 0, c->n, c->npad, b.S, 1, b.zeta, 0, c->npad, nullptr, nullptr, 0,
-                  0.0, b.szeta, c->npad, 0);
+    launch_matvec(c->stream, 0, c->npad, b.S, 1, b.zeta, nullptr, 0, 0.0, b.szeta, c->npad, 0);
     TRY(launched(c, "field response"));
     c->szeta_ok = true;
   }
@@ -1545,8 +1554,7 @@ cpm_status cpm_set_potential_atoms(cpm_ctx* c, const double* h_v) {
   TRY(ensure_vat(c));
   HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
   if (c->have_inv)
-    launch_matvec(c->stream, 0, c->n, c->npad, c->b.S, 1, c->b.vat, 0, c->npad, nullptr, nullptr, 0,
-                  0.0, c->b.d, c->npad, 0);
+    launch_matvec(c->stream, 0, c->npad, c->b.S, 1, c->b.vat, nullptr, 0, 0.0, c->b.d, c->npad, 0);
   TRY(launched(c, "set_potential_atoms"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_v = true;
@@ -1622,7 +1630,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
     { Timed t(c, "real_space_b");
       launch_gather_charges(st, g, m, mpad64, perm, xyz, b.elq, p.Lx, p.Ly, b.cq, b.zr);
       launch_b_real_space(st, g, n, m, mpad64, rch, b, c->nmap, b.cq, b.zr, p.Lx, p.Ly, c->Lz,
-                          p.rcut, b.phir_part); }
+                          p.rcut, b.phir_part, fast ? rs_target(c) : 512); }
     if (fast) {
       { Timed t(c, "sf_reduce");
         launch_b_sf_layer_reduce(st, g, c->ncolsort, nch, c->sfm_pchunk, c->nlayers,
@@ -1722,9 +1730,10 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
     // constrained charges (Eq. 7): y = A^-1 b in FP64, then the per-electrode
     // correction q = y + U C~^-1 (Q - G^T y)
     if (!gemm) {
+      { Timed t(c, "pad_rows");
+        launch_center_pad(st, n, npad, batch, d_b, b_is_f32, n, 0, w.bpad); }
       Timed t(c, "matvec_f64");
-      launch_matvec(st, 0, n, npad, b.Ainv, batch, d_b, b_is_f32, n, nullptr, nullptr, 0, 0.0, w.qt,
-                    npad, 0);
+      launch_matvec(st, 0, npad, b.Ainv, batch, w.bpad, nullptr, 0, 0.0, w.qt, npad, 0);
     } else {
       { Timed t(c, "pad_rows");
         launch_pad_rows(st, n, npad, batch, rows, d_b, b_is_f32, nullptr, w.bpad); }
@@ -1756,10 +1765,9 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
   if (!gemm) {
     // q~ = S~ (b - mean(b) e) + d, one streaming pass over S~ per vector
     { Timed t(c, "row_means");
-      launch_row_means(st, n, batch, d_b, b_is_f32, n, w.means); }
+      launch_center_pad(st, n, npad, batch, d_b, b_is_f32, n, 1, w.bpad); }
     { Timed t(c, mv_name);
-      launch_matvec(st, which, n, npad, Sm, batch, d_b, b_is_f32, n, w.means, b.d, 0, 1.0, w.qt,
-                    npad, 0); }
+      launch_matvec(st, which, npad, Sm, batch, w.bpad, b.d, 0, 1.0, w.qt, npad, 0); }
     if (!refine) {
       Timed t(c, "finalize");
       launch_finalize(st, n, batch, w.qt, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe);
@@ -1774,13 +1782,11 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
     { Timed t(c, "make_rhs");
       launch_make_rhs(st, n, npad, batch, d_b, b_is_f32, b.vat, w.res); }
     { Timed t(c, "matvec_f64");
-      launch_matvec(st, 0, n, npad, b.A, batch, w.qpad, 0, npad, nullptr, w.res, npad, 1.0, w.qt,
-                    npad, 1); }
-    { Timed t(c, "row_means");
-      launch_row_means(st, n, batch, w.qt, 0, npad, w.means); }
+      launch_matvec(st, 0, npad, b.A, batch, w.qpad, w.res, npad, 1.0, w.qt, npad, 1); }
+    { Timed t(c, "center_rows");
+      launch_center_rows(st, n, npad, batch, w.qt); }
     { Timed t(c, mv_name);
-      launch_matvec(st, which, n, npad, Sm, batch, w.qt, 0, npad, w.means, w.qpad, npad, 1.0, w.res,
-                    npad, 0); }
+      launch_matvec(st, which, npad, Sm, batch, w.qt, w.qpad, npad, 1.0, w.res, npad, 0); }
     { Timed t(c, "finalize");
       launch_finalize(st, n, batch, w.res, npad, nullptr, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
     return launched(c, "solve (refined)");

@@ -280,7 +280,7 @@ struct cpm_ctx {
   bool pc_ready = false;           // preconditioner built for the current operator
   const double* pc_Cinv = nullptr; // whichever of pc_C / pc_W holds the coarse inverse
   std::vector<int> h_bdiag;        // real-space block of each tile's diagonal (-1: none)
-  int rs_wg_target = 512;          // real-space workgroups per launch group
+  int rs_wg_target = 0;            // real-space workgroups per launch group (0: by size)
   int rs_sort_min = 16;            // batches of at least this size sort the charges by z
   unsigned store = 0;
   uint64_t geom_hash = 0;          // fingerprint of A's inputs (cpm_save / cpm_load)
@@ -385,12 +385,14 @@ void launch_convert_S(hipStream_t st, int npad, const double* S, float* S32, uin
                       uint16_t* lo);
 
 // per-step solve
-// y[b] = sign * M x[b] + addscale * add[b * add_ld + .]   (add may be NULL)
-// (x[b] - xshift[b] e when xshift is given)
-void launch_matvec(hipStream_t st, int which /*0 f64, 1 f32*/, int n, int npad,
-                   const void* M, int batch, const void* x, int x_is_f32, int ldx,
-                   const double* xshift, const double* add, int add_ld, double addscale, double* y,
+// y[b] = sign * M x[b] + addscale * add[b * add_ld + .]   (add may be NULL);
+// x FP64, npad apart per vector, zero beyond n
+void launch_matvec(hipStream_t st, int which /*0 f64, 1 f32*/, int npad, const void* M, int batch,
+                   const double* x, const double* add, int add_ld, double addscale, double* y,
                    int ldy, int negate);
+// dst[b] (npad apart) = src[b] - (center ? mean_b : 0) for i < n, 0 beyond
+void launch_center_pad(hipStream_t st, int n, int npad, int batch, const void* x, int x_is_f32,
+                       int ldx, int center, double* dst);
 void launch_row_means(hipStream_t st, int n, int batch, const void* x, int x_is_f32, int ldx,
                       double* means);
 void launch_center_rows(hipStream_t st, int n, int ld, int batch, double* x);
@@ -493,7 +495,7 @@ int layer_project_chunks(int ncols);
 void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab);
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
                          const Buffers& b, int nmap, const double4* cq, const double2* zr,
-                         double Lx, double Ly, double Lz, double rc, double* part);
+                         double Lx, double Ly, double Lz, double rc, double* part, int wg_target);
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
                       const double* phir, const Buffers& b, const double* dip, int dip_blocks,
                       const double* cdip, double ke, void* out, int out_is_f32);

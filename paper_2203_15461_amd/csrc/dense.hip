@@ -419,15 +419,20 @@ void launch_convert_S(hipStream_t st, int npad, const double* S, float* S32, uin
 
 // ---------------------------------------------------------------------------
 // Matrix-vector product y[b] = sign * M x[b] + addscale * add, streaming the
-// npad x npad matrix M (FP64 or FP32) once per vector.  One wave per R
-// consecutive rows: 16-byte coalesced loads of each row, every x element
-// read once per wave (through the cache) for all R rows, FP64 accumulation,
-// wave reductions in a fixed order.
+// npad x npad matrix M (FP64 or FP32) once per vector.  x is FP64, npad
+// apart per vector and zero beyond n, so every load is an aligned 16-byte
+// vector with no bounds test.  One wave per R consecutive rows: 16-byte
+// coalesced loads of each row, every x element read once per wave (through
+// the cache) for all R rows, FP64 accumulation, wave reductions in a fixed
+// order.  Matrices larger than the last-level cache are read with
+// nontemporal loads (streamed past the caches, which the x vector keeps).
 // ---------------------------------------------------------------------------
-template <typename TM, int R>
-__global__ void __launch_bounds__(256) k_matvec(int n, int npad, const TM* __restrict__ M,
-                                                const void* __restrict__ xv, int x_is_f32, int ldx,
-                                                const double* __restrict__ xshift,
+typedef double d2v __attribute__((ext_vector_type(2)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename TM, int R, bool NT>
+__global__ void __launch_bounds__(256) k_matvec(int npad, const TM* __restrict__ M,
+                                                const double* __restrict__ x,
                                                 const double* __restrict__ add, int add_ld,
                                                 double addscale, double* __restrict__ y, int ldy,
                                                 int negate) {
@@ -437,9 +442,7 @@ __global__ void __launch_bounds__(256) k_matvec(int n, int npad, const TM* __res
   if (row0 >= npad) return;                  // npad is a multiple of 64, so all R rows exist
   constexpr int VEC = 16 / sizeof(TM);
   const TM* mrow = M + (size_t)row0 * npad;
-  const double* xd = reinterpret_cast<const double*>(xv) + (size_t)b * ldx;
-  const float* xf = reinterpret_cast<const float*>(xv) + (size_t)b * ldx;
-  const double sh = xshift ? xshift[b] : 0.0;
+  const double* xb = x + (size_t)b * npad;
   double acc[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.0;
@@ -449,19 +452,22 @@ __global__ void __launch_bounds__(256) k_matvec(int n, int npad, const TM* __res
     TM mv[R][VEC];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
+      const TM* src = mrow + (size_t)r * npad + j0;
       if constexpr (VEC == 2) {
-        const double2 t = *reinterpret_cast<const double2*>(mrow + (size_t)r * npad + j0);
+        const d2v t = NT ? __builtin_nontemporal_load(reinterpret_cast<const d2v*>(src))
+                         : *reinterpret_cast<const d2v*>(src);
         mv[r][0] = t.x; mv[r][1] = t.y;
       } else {
-        const float4 t = *reinterpret_cast<const float4*>(mrow + (size_t)r * npad + j0);
+        const f4v t = NT ? __builtin_nontemporal_load(reinterpret_cast<const f4v*>(src))
+                         : *reinterpret_cast<const f4v*>(src);
         mv[r][0] = t.x; mv[r][1] = t.y; mv[r][2] = t.z; mv[r][3] = t.w;
       }
     }
     double xj[VEC];
 #pragma unroll
-    for (int t = 0; t < VEC; ++t) {
-      const int j = j0 + t;
-      xj[t] = j < n ? (x_is_f32 ? (double)xf[j] : xd[j]) - sh : 0.0;
+    for (int t = 0; t < VEC; t += 2) {
+      const d2v v = *reinterpret_cast<const d2v*>(xb + j0 + t);
+      xj[t] = v.x; xj[t + 1] = v.y;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r)
@@ -483,39 +489,73 @@ __global__ void __launch_bounds__(256) k_matvec(int n, int npad, const TM* __res
 }
 
 template <typename TM>
-void launch_matvec_t(hipStream_t st, int n, int npad, const TM* M, int batch, const void* x,
-                     int x_is_f32, int ldx, const double* xshift, const double* add, int add_ld,
-                     double addscale, double* y, int ldy, int negate) {
-  // rows per wave: 4 rows share each x load (measured best from N ~ 3k,
-  // where S sits in the last-level cache, to N ~ 20k, where it streams from
-  // HBM: 75% / 71% of the HBM peak for FP64 / FP32 at N = 20064)
+void launch_matvec_t(hipStream_t st, int npad, const TM* M, int batch, const double* x,
+                     const double* add, int add_ld, double addscale, double* y, int ldy,
+                     int negate) {
+  // rows per wave: 4 rows share each x load from npad = 2048 on (measured
+  // best both where S stays in the last-level cache, n ~ 3k, and where it
+  // streams from HBM, n ~ 20k); nontemporal loads from 128 MiB of matrix on
+  // (20096^2: FP32 84%, FP64 87% of the HBM peak against 75%, 78% with
+  // ordinary loads; a matrix that fits the 256 MB cache loses by them)
   int R = npad >= 2048 ? 4 : npad >= 1024 ? 2 : 1;
+  bool nt = (double)npad * npad * sizeof(TM) >= 128.0 * 1024 * 1024;
   if (const char* ev = std::getenv("CPM_MV_ROWS")) {
     const int r = std::atoi(ev);
-    if (r == 1 || r == 2 || r == 4 || r == 8 || r == 16) R = r;
+    if (r == 1 || r == 2 || r == 4 || r == 8) R = r;
   }
+  if (const char* ev = std::getenv("CPM_MV_NT")) nt = std::atoi(ev) != 0;
   dim3 grid((npad / R + 3) / 4, batch), block(256);
-#define CPM_MV(RR)                                                                           \
-  hipLaunchKernelGGL((k_matvec<TM, RR>), grid, block, 0, st, n, npad, M, x, x_is_f32, ldx,   \
-                     xshift, add, add_ld, addscale, y, ldy, negate)
-  if (R == 16) CPM_MV(16); else if (R == 8) CPM_MV(8); else if (R == 4) CPM_MV(4);
-  else if (R == 2) CPM_MV(2); else CPM_MV(1);
+#define CPM_MV(RR, NN)                                                                     \
+  hipLaunchKernelGGL((k_matvec<TM, RR, NN>), grid, block, 0, st, npad, M, x, add, add_ld,  \
+                     addscale, y, ldy, negate)
+  if (nt) {
+    if (R == 8) CPM_MV(8, true); else if (R == 4) CPM_MV(4, true);
+    else if (R == 2) CPM_MV(2, true); else CPM_MV(1, true);
+  } else {
+    if (R == 8) CPM_MV(8, false); else if (R == 4) CPM_MV(4, false);
+    else if (R == 2) CPM_MV(2, false); else CPM_MV(1, false);
+  }
 #undef CPM_MV
 }
 
-// One matrix-vector product per right-hand side: y = M (x - shift) (+ add),
-// M npad x npad row-major (FP64 or FP32), streamed once per vector with
-// 16-byte coalesced loads; R rows per wave share each x load; fixed-order
-// wave reductions.
-void launch_matvec(hipStream_t st, int which, int n, int npad, const void* M, int batch,
-                   const void* x, int x_is_f32, int ldx, const double* xshift, const double* add,
-                   int add_ld, double addscale, double* y, int ldy, int negate) {
+// One matrix-vector product per right-hand side: y = M x (+ add), M npad x
+// npad row-major (FP64 or FP32), x FP64 padded (npad apart, zero beyond n),
+// streamed once per vector with 16-byte coalesced loads; R rows per wave
+// share each x load; fixed-order wave reductions.
+void launch_matvec(hipStream_t st, int which, int npad, const void* M, int batch, const double* x,
+                   const double* add, int add_ld, double addscale, double* y, int ldy, int negate) {
   if (which == 0)
-    launch_matvec_t(st, n, npad, (const double*)M, batch, x, x_is_f32, ldx, xshift, add, add_ld,
-                    addscale, y, ldy, negate);
+    launch_matvec_t(st, npad, (const double*)M, batch, x, add, add_ld, addscale, y, ldy, negate);
   else
-    launch_matvec_t(st, n, npad, (const float*)M, batch, x, x_is_f32, ldx, xshift, add, add_ld,
-                    addscale, y, ldy, negate);
+    launch_matvec_t(st, npad, (const float*)M, batch, x, add, add_ld, addscale, y, ldy, negate);
+}
+
+// dst[b] (npad apart, FP64) = src[b] (ldx apart, FP64 or FP32) minus its mean
+// over i < n when `center` (the same fixed-order sum as k_row_means), zero
+// for n <= i < npad: the padded right-hand side of the streaming solve.
+__global__ void __launch_bounds__(1024) k_center_pad(int n, int npad, const void* __restrict__ x,
+                                                     int x_is_f32, int ldx, int center,
+                                                     double* __restrict__ dst) {
+  __shared__ double sh[16];
+  const int b = blockIdx.x;
+  auto at = [&](int i) {
+    return x_is_f32 ? (double)reinterpret_cast<const float*>(x)[(size_t)b * ldx + i]
+                    : reinterpret_cast<const double*>(x)[(size_t)b * ldx + i];
+  };
+  double mean = 0.0;
+  if (center) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) s += at(i);
+    mean = block_sum1024(s, sh) / n;
+  }
+  double* out = dst + (size_t)b * npad;
+  for (int i = threadIdx.x; i < npad; i += 1024) out[i] = i < n ? at(i) - mean : 0.0;
+}
+
+void launch_center_pad(hipStream_t st, int n, int npad, int batch, const void* x, int x_is_f32,
+                       int ldx, int center, double* dst) {
+  hipLaunchKernelGGL(k_center_pad, dim3(batch), dim3(1024), 0, st, n, npad, x, x_is_f32, ldx,
+                     center, dst);
 }
 
 // means[b] = (1/n) sum_{i<n} x[b][i]: the uniform part of a right-hand side.
