@@ -31,10 +31,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 MODES = {
-    # name: (store flags, b in fp32, solve mode, dtype label)
+    # name: (store flags, b in fp32, solve mode, dtype label).  The reduced-
+    # precision modes keep b in FP32 (structure factors on FP32 matrix cores)
+    # and refine q once against A in FP64.
     "f64": (1, False, 0x000, "f64"),
-    "f32r": (1 | 2, True, 0x101, "f32+f64-refine"),
-    "bf16r": (1 | 4, False, 0x102, "bf16x3+f64-refine"),
+    "f32r": (1 | 2, True, 0x101, "b f32, S f32, f64 refine"),
+    "bf16r": (1 | 4, True, 0x102, "b f32, S bf16x3 (f32 accumulation), f64 refine"),
+    "bf16r64": (1 | 4, False, 0x102, "b f64, S bf16x3 (f32 accumulation), f64 refine"),
 }
 # dominant kernel families and their algorithmic work per launch
 PEAK_FP64_VALU = 78.6e12     # FLOP/s, MI355X FP64 vector
@@ -721,8 +724,8 @@ def accuracy_vs_oracle(w, q_ref, Q_ref):
     """Error of each solve path in q and in the electrode totals against the
     oracle's FP64 result for snapshot 0: the plain FP64 path (one vector,
     streaming matvec), and the batched FP32 and split-BF16 paths (a batch of 8
-    snapshots, snapshot 0 first; b in FP32 for the FP32 path), each with one
-    FP64 refinement step."""
+    snapshots, snapshot 0 first; b in FP32 from the FP32 structure factors,
+    and for split-BF16 also b in FP64), each with one FP64 refinement step."""
     import numpy as np
     import torch
     from paper_2203_15461_amd import cpm
@@ -737,7 +740,8 @@ def accuracy_vs_oracle(w, q_ref, Q_ref):
     ctx.potential_vector(xyz, b32)
     out = {}
     for name, bb, mode, rows in (("f64_plain", b64, 0x000, 1), ("f32r_batched", b32, 0x101, 8),
-                                 ("bf16r_batched", b64, 0x102, 8)):
+                                 ("bf16r_batched", b32, 0x102, 8),
+                                 ("bf16r_batched_b_f64", b64, 0x102, 8)):
         q = torch.empty((rows, w.n), dtype=torch.float64, device=dev)
         Qe = torch.empty((rows, 2), dtype=torch.float64, device=dev)
         ctx.solve_charges(bb[:rows], mode, q, Qe)

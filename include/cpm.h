@@ -264,10 +264,15 @@ cpm_status cpm_set_field(cpm_ctx* ctx, double dv0, int bottom);
 
 /* b for `batch` electrolyte configurations (Sec. II.A: the per-step cost).
  * d_xyz: batch x m x 3 FP64 positions (row-major, snapshot-major).
- * d_b: batch x n output, FP64 (b_is_f32 = 0) or FP32 (b_is_f32 = 1; the
- * k-space sums then accumulate in FP32, phases are still FP64).  b includes
- * the real-space erfc sum, the k-space structure-factor term and the
- * electrolyte cross term of the slab correction (Eq. 12). */
+ * d_b: batch x n output, FP64 (b_is_f32 = 0) or FP32 (b_is_f32 = 1, for
+ * the reduced-precision solve modes).  With FP32 output the structure
+ * factors run on FP32 matrix cores: the phase tables are computed in FP64
+ * and rounded to FP32, products are summed in FP32 over 128 charges and in
+ * FP64 beyond, and the rest of b stays FP64 until the final rounding; b is
+ * then within a few 1e-6 (relative to its largest entry) of the FP64 result
+ * (CPM_SF_FP32=0 in the environment keeps FP64 structure factors).  b
+ * includes the real-space erfc sum, the k-space structure-factor term and
+ * the electrolyte cross term of the slab correction (Eq. 12). */
 cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
                                 void* d_b, int b_is_f32);
 

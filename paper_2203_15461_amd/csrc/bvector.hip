@@ -205,11 +205,12 @@ __device__ inline double2 cmul2(double2 a, double2 b) {
 //   last row                   zero (the C operand of absent columns)
 // blockIdx.z selects the configuration of the group (tables tab_stride
 // apart).
+template <typename T2>
 __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int nym,
                                                    const double* __restrict__ xyz,
                                                    const double* __restrict__ q, double Lx,
                                                    double Ly, double Lz, size_t tab_stride,
-                                                   double2* __restrict__ tab) {
+                                                   T2* __restrict__ tab) {
   const int row = blockIdx.y, snap = blockIdx.z;
   const int j = blockIdx.x * 256 + threadIdx.x;
   const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
@@ -218,7 +219,7 @@ __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int
   double qq = 0.0, zz = 0.0;
   if (j < m) { qq = q[j]; zz = xyz[3 * j + 2]; }
   if (j < mpad) {
-    double2 v = make_double2(0.0, 0.0);
+    double2 v = make_double2(0.0, 0.0);              // rounded once to T2 when stored
     if (j < m) {
       double f, idx, scale = 1.0;
       if (row < rY) {
@@ -238,7 +239,10 @@ __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int
       sincospi(2.0 * th, &sn, &cs);
       v = make_double2(scale * cs, scale * sn);
     }
-    tab[(size_t)row * mpad + j] = v;
+    T2 t;
+    t.x = v.x;
+    t.y = v.y;
+    tab[(size_t)row * mpad + j] = t;
   }
 }
 
@@ -246,12 +250,16 @@ int sf_table_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) 
 
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
-                        double2* tab) {
+                        double2* tab, int fp32) {
   const int rows = sf_table_rows(nxm, nym, nbz);
   const int blocks = (mpad + 255) / 256;
   dim3 grid(blocks, rows, g), block(256);
-  hipLaunchKernelGGL(k_sf_tables, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly, Lz,
-                     (size_t)rows * mpad, tab);
+  if (fp32)
+    hipLaunchKernelGGL(k_sf_tables<float2>, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly,
+                       Lz, (size_t)rows * mpad, reinterpret_cast<float2*>(tab));
+  else
+    hipLaunchKernelGGL(k_sf_tables<double2>, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly,
+                       Lz, (size_t)rows * mpad, tab);
 }
 
 // Dipole partials of each configuration of a group, per 256 charges and
@@ -470,14 +478,201 @@ k_sf_mfma(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restr
   }
 }
 
+// The same structure factors on FP32 matrix cores, for b stored in FP32
+// (the reduced-precision solve path): FP32 phase tables (each entry the FP64
+// sincospi value rounded once), the C and B operands formed in FP32, and
+// v_mfma_f32_16x16x4f32 products summed in FP32 over SF32_FLUSH tiles of a
+// wave (128 charges), then added to FP64 accumulators, which the workgroup
+// reduction and the partials keep.  The error this adds to b is a few 1e-7
+// relative, below the rounding of b to FP32 itself.  Result register r of
+// lane l: row 4 (l >> 4) + r, column l & 15.
+typedef float v4f_t __attribute__((ext_vector_type(4)));
+constexpr int SF32_FLUSH = 8;
+
+struct SfmWave32 {                      // wave-private LDS area
+  float C[2 * SFM_COLS][SFM_TJ + 1];
+  float B[SFM_NB][16][SFM_TJ + 1];
+};
+
+__device__ inline float2 cmul2f(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+template <int NBW>
+__device__ void sf_item32(SfmWave32& W, double* __restrict__ red, const float2* __restrict__ tab,
+                          int mpad, int j0, int j1, const int (&xoff)[4], const int (&yoff)[4],
+                          int z8off, int z1off, int r8off, double* __restrict__ out, int ldc,
+                          int nb_lo) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int t_l = lane & 15, g_l = lane >> 4;
+  v4d_t acc0[NBW], acc1[NBW];
+  v4f_t f0[NBW], f1[NBW];
+#pragma unroll
+  for (int b = 0; b < NBW; ++b) {
+    acc0[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+    acc1[b] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+    f0[b] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+    f1[b] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+  }
+  auto flush = [&]() {
+#pragma unroll
+    for (int b = 0; b < NBW; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        acc0[b][r] += (double)f0[b][r];
+        acc1[b][r] += (double)f1[b][r];
+      }
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
+      f0[b] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+      f1[b] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+    }
+  };
+  float2 xv[4], yv[4], z8, za, zb, r8n;
+  auto fetch = [&](int jt) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) { xv[u] = tab[xoff[u] + jt]; yv[u] = tab[yoff[u] + jt]; }
+    z8 = tab[z8off + jt]; za = tab[z1off + jt]; zb = tab[z1off + mpad + jt]; r8n = tab[r8off + jt];
+  };
+  if (j0 + wave * SFM_TJ < j1) fetch(j0 + wave * SFM_TJ);
+  int since = 0;
+  for (int jt = j0 + wave * SFM_TJ; jt < j1; jt += 4 * SFM_TJ) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int cl = g_l + 4 * u;
+      const float2 cv = cmul2f(xv[u], yv[u]);
+      W.C[2 * cl][t_l] = cv.x;
+      W.C[2 * cl + 1][t_l] = cv.y;
+    }
+    float2 va = cmul2f(z8, za), vb = cmul2f(z8, zb);
+#pragma unroll
+    for (int b = 0; b < NBW; ++b) {
+      W.B[b][4 * g_l][t_l] = va.x;
+      W.B[b][4 * g_l + 1][t_l] = va.y;
+      W.B[b][4 * g_l + 2][t_l] = vb.x;
+      W.B[b][4 * g_l + 3][t_l] = vb.y;
+      if (b + 1 < NBW) {
+        va = cmul2f(va, r8n);
+        vb = cmul2f(vb, r8n);
+      }
+    }
+    wave_lds_sync();
+    if (jt + 4 * SFM_TJ < j1) fetch(jt + 4 * SFM_TJ);
+#pragma unroll 1
+    for (int ks = 0; ks < SFM_TJ / 4; ++ks) {
+      const int kc = 4 * ks + g_l;
+      const float a0 = W.C[t_l][kc], a1 = W.C[16 + t_l][kc];
+      float bv[NBW];
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) bv[b] = W.B[b][t_l][kc];
+#pragma unroll
+      for (int b = 0; b < NBW; ++b) {
+        f0[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, bv[b], f0[b], 0, 0, 0);
+        f1[b] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, bv[b], f1[b], 0, 0, 0);
+      }
+    }
+    wave_lds_sync();
+    if (++since == SF32_FLUSH) {
+      flush();
+      since = 0;
+    }
+  }
+  flush();
+  // fixed-order sum of the waves' accumulators (3 + 2 + 1 into wave 0)
+  for (int src = 3; src >= 1; --src) {
+    __syncthreads();
+    if (wave == src)
+#pragma unroll
+      for (int b = 0; b < NBW; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          red[((0 * SFM_NB + b) * 4 + r) * 64 + lane] = acc0[b][r];
+          red[((1 * SFM_NB + b) * 4 + r) * 64 + lane] = acc1[b][r];
+        }
+    __syncthreads();
+    if (wave == 0)
+#pragma unroll
+      for (int b = 0; b < NBW; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          acc0[b][r] += red[((0 * SFM_NB + b) * 4 + r) * 64 + lane];
+          acc1[b][r] += red[((1 * SFM_NB + b) * 4 + r) * 64 + lane];
+        }
+  }
+  if (wave == 0) {
+#pragma unroll
+    for (int b = 0; b < NBW; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * (lane >> 4) + r;
+        const int col = 16 * (nb_lo + b) + (lane & 15);
+        out[row * ldc + col] = acc0[b][r];
+        out[(16 + row) * ldc + col] = acc1[b][r];
+      }
+  }
+}
+
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+k_sf_mfma32(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restrict__ items,
+            const int* __restrict__ sc_nx, const int* __restrict__ sc_ny, int ncolsort, int nxm,
+            int nym, const float2* __restrict__ tab, size_t tab_stride,
+            const int* __restrict__ tile_nb, const int* __restrict__ toff, int pchunk,
+            double* __restrict__ part) {
+  // the waves' tile areas; after the tile loops, one wave's accumulators
+  constexpr int LDS_D = (4 * sizeof(SfmWave32) + 7) / 8 > 64 * 2 * SFM_NB * 4
+                            ? (4 * sizeof(SfmWave32) + 7) / 8 : 64 * 2 * SFM_NB * 4;
+  __shared__ double lds[LDS_D];
+  SfmWave32* wl = reinterpret_cast<SfmWave32*>(lds);
+  double* red = lds;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int item = slot % nitems;
+  const int pair = xcd + 8 * (slot / nitems);
+  const int snap = pair / nchunks, chunk = pair % nchunks;
+  tab += (size_t)snap * tab_stride;
+  const int4 it = items[item];
+  const int mt = it.x, nb_lo = it.y, nbw = it.z;
+  const int c_base = mt * SFM_COLS;
+  const int ncol = min(SFM_COLS, ncolsort - c_base);
+  const int j0 = chunk * chunk_size, j1 = min(mpad, j0 + chunk_size);
+  const int t_l = lane & 15, g_l = lane >> 4;
+  const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
+  const int rzero = (int)(tab_stride / mpad) - 1;
+  int xoff[4], yoff[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int cl = g_l + 4 * u;
+    const bool ok = cl < ncol;
+    xoff[u] = (ok ? sc_nx[c_base + cl] : rzero) * mpad + t_l;
+    yoff[u] = (ok ? rY + sc_ny[c_base + cl] + nym : rzero) * mpad + t_l;
+  }
+  const int z8off = (rZ8 + nb_lo) * mpad + t_l, r8off = (rZ8 + 1) * mpad + t_l;
+  const int z1off = (rZ1 + 2 * g_l) * mpad + t_l;
+  const int ldc = 16 * tile_nb[mt];
+  double* out = part + ((size_t)snap * nchunks + chunk) * pchunk + toff[mt];
+  SfmWave32& W = wl[wave];
+  switch (nbw) {
+    case 1: sf_item32<1>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
+    case 2: sf_item32<2>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
+    case 3: sf_item32<3>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
+    default: sf_item32<SFM_NB>(W, red, tab, mpad, j0, j1, xoff, yoff, z8off, z1off, r8off, out, ldc, nb_lo); break;
+  }
+}
+
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
-                      double* part) {
+                      double* part, int fp32) {
   // nchunks is a multiple of 8 (one residue class of pairs per XCD)
   const int chunk_size = sf_mfma_chunk(mpad, nchunks);
   const size_t tab_stride = (size_t)sf_table_rows(nxm, nym, nbz) * mpad;
   dim3 grid(nitems * nchunks * g), block(256);
+  if (fp32) {
+    hipLaunchKernelGGL(k_sf_mfma32, grid, block, 0, st, mpad, chunk_size, nchunks, nitems, items,
+                       sc_nx, sc_ny, ncolsort, nxm, nym, reinterpret_cast<const float2*>(tab),
+                       tab_stride, tile_nb, toff, pchunk, part);
+    return;
+  }
   hipLaunchKernelGGL(k_sf_mfma, grid, block, 0, st, mpad, chunk_size, nchunks, nitems, items, sc_nx,
                      sc_ny, ncolsort, nxm, nym, tab, tab_stride, tile_nb, toff, pchunk, part);
 }

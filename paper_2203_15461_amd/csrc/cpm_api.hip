@@ -736,6 +736,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_CHOL_BLOCK"))
     c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
+  if (const char* ev = std::getenv("CPM_SF_FP32")) c->sf32_ok = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
 
@@ -1589,6 +1590,9 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   // launch, k_z folded into the planes, projection fused into the combine)
   const bool mfma = c->sf_mfma && c->use_sf_mfma;
   const bool fast = mfma && c->nlayers > 0;
+  // b stored in FP32 (the reduced-precision solve path): structure factors on
+  // FP32 matrix cores, FP32 phase tables (switch: CPM_SF_FP32=0)
+  const int sf32 = (b_is_f32 && c->sf32_ok) ? 1 : 0;
   const int G = fast ? c->pv_group : 1;
   const int mpad64 = std::max(64, (m + 63) / 64 * 64);
   // large batches: the charges ordered by z (from the first configuration)
@@ -1615,11 +1619,11 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
     if (mfma) {
       { Timed t(c, "sf_tables");
         launch_b_sf_tables(st, g, m, c->mpad, c->nxm, c->nym, c->sfm_nbz, xyz, b.elq, p.Lx, p.Ly,
-                           c->Lz, b.sft); }
+                           c->Lz, b.sft, sf32); }
       { Timed t(c, "structure_factor");
         launch_b_sf_mfma(st, g, c->mpad, nch, c->sfm_nitems, b.sfm_items, b.sc_nx, b.sc_ny,
                          c->ncolsort, c->nxm, c->nym, c->sfm_nbz, b.sft, b.tile_nb, b.tile_off,
-                         c->sfm_pchunk, b.sfm_part); }
+                         c->sfm_pchunk, b.sfm_part, sf32); }
     } else {
       { Timed t(c, "structure_factor");
         launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz,

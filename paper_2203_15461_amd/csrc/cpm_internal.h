@@ -302,6 +302,7 @@ struct cpm_ctx {
   int nlayers = 0;                 // > 0: electrodes lie on this many z planes (factorised projection)
   bool sf_mfma = false;            // structure factors on FP64 matrix cores (k set fits)
   bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
+  bool sf32_ok = true;             // FP32 structure factors when b is stored in FP32
   int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_ntot = 0;
   int sfm_nbz = 2, sfm_nitems = 0, mpad = 0, sft_rows = 0, sft_blocks = 1;
   int sfm_pchunk = 0;              // doubles per (configuration, chunk) of sfm_part
@@ -445,9 +446,10 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
                                int m, int mchunks, const double* xyz, const double* q,
                                double Lx, double Ly, double Lz, int nxm, int nym, int nzm,
                                double* part);
+// per-charge phase tables; fp32: stored as float2 (the same rows, half the bytes)
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
-                        double2* tab);
+                        double2* tab, int fp32);
 void launch_b_elyt_dipole(hipStream_t st, int g, int m, const double* xyz, const double* q,
                           double* dip);
 void launch_dipole_partials(hipStream_t st, int g, int m, const double* xyz, size_t xyz_stride,
@@ -458,10 +460,11 @@ int zsort_bins(double Lz);         // z bins of the charge order (about 0.25 A w
 void launch_gather_charges(hipStream_t st, int g, int m, int mpad64, const int* perm,
                            const double* xyz, const double* q, double Lx, double Ly, double4* cq,
                            double2* zr);
+// fp32: FP32 tables and matrix cores, FP32 sums over 128 charges, FP64 beyond
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
-                      double* part);
+                      double* part, int fp32);
 void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int nchunks, int pchunk,
                              const int* tile_nb, const int* toff, const int* sc_lo,
                              const int* sc_len, const int* sc_koff, const int* n_index,

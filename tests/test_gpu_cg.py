@@ -396,7 +396,7 @@ def test_cg_large_coarse_space_matches_direct(cpm):
     offsets into its coarse space by itself (396 coarse functions, so the
     coarse products run split over the coarse columns); its charges match
     the direct FP64 solve q = S (b + v) on the same b, which the 2880-atom
-    case ties to the oracle."""
+    case ties to the oracle, and the oracle's own sampled rows of b and A."""
     w = I.scaled_graphite_capacitor(8500)
     say(f"cg with the large coarse space, n={w.n}")
     direct = cpm.setup(w)
@@ -411,5 +411,13 @@ def test_cg_large_coarse_space_matches_direct(cpm):
     assert tiles == 132 and ncoarse == 3 * 132 and ctx.info("pc_mode") == 2
     assert rel(q.cpu().numpy(), qd.cpu().numpy()) < 1e-10
     assert np.abs(q.cpu().numpy().sum(axis=1)).max() <= 1e-12
+    # against the oracle's stored rows of b and A for snapshots 0-2: b rows at
+    # 1e-10, and A q - b - v uniform on every stored row
+    gl = np.load(os.path.join(os.path.dirname(GOLDEN), "scaled_graphite_capacitor_8400_rows_alpha0.30.npz"))
+    rows, qc, bc = gl["rows"], q.cpu().numpy(), b.cpu().numpy()
+    assert rel(bc[:, rows], gl["b_rows"]) < 1e-10
+    for s in range(3):
+        r = gl["A_rows"] @ qc[s] - gl["b_rows"][s] - gl["v_rows"]
+        assert np.abs(r - r.mean()).max() <= 1e-10 * np.abs(gl["b_rows"][s] + gl["v_rows"]).max()
     direct.close()
     ctx.close()
