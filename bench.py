@@ -201,7 +201,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     timing = {f: ctx.timing(f) for f in fams}
     ctx.enable_timing(False)
     rs_ms, rs_cnt = timing["real_space_b"]
-    rs_roof = real_space_roofline(w, xyz, B, rs_ms, rs_cnt)
+    rs_roof = real_space_roofline(w, xyz, B, rs_ms, rs_cnt, name)
 
     # per-phase split of one more (untimed) step, for the JSON context fields
     torch.cuda.synchronize()
@@ -251,11 +251,15 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     # complex rotation and a complex accumulate)
     snaps_per_launch = B * steps / max(sf_cnt, 1)
     matrix = ctx.info("sf_matrix") == 1.0
+    sf_fp32 = b_f32 and matrix and ctx.info("sf_fp32") == 1.0
     flop_per_pair = 4.0 if matrix else 8.0
     flop_per_launch = flop_per_pair * nk * w.m * snaps_per_launch
     achieved = flop_per_launch / sf_avg if sf_avg > 0 else 0.0
-    peak = PEAK_FP64_VALU      # FP64 MFMA and FP64 vector peaks are both 78.6 TFLOP/s
-    traffic = stored_traffic(name, snaps_per_launch)
+    # FP64 MFMA and FP64 vector peaks are both 78.6 TFLOP/s; with b stored in
+    # FP32 the structure factors run on FP32 matrix cores (157.3 TFLOP/s)
+    peak = PEAK_FP32_VALU if sf_fp32 else PEAK_FP64_VALU
+    traffic = stored_traffic(name, "cpm::k_sf_mfma32" if sf_fp32 else "cpm::k_sf_mfma",
+                             snaps_per_launch)
     sf_bound = "mfma" if matrix else "alu"
 
     value = B * steps / elapsed
@@ -282,7 +286,8 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
                      "flop_per_launch": flop_per_launch, "flop_per_k_charge_pair": flop_per_pair,
                      "avg_launch_us": sf_avg * 1e6,
                      "configurations_per_launch": snaps_per_launch,
-                     "launch_group": int(ctx.info("group"))},
+                     "launch_group": int(ctx.info("group")),
+                     "precision": "fp32" if sf_fp32 else "fp64"},
         "roofline_real_space": rs_roof,
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),
@@ -425,7 +430,7 @@ def count_pairs(w, xyz_one):
     return int(ta.count_neighbors(tb, w.rcut * (1 - 1e-12)))
 
 
-def real_space_roofline(w, xyz, B, total_ms, launches):
+def real_space_roofline(w, xyz, B, total_ms, launches, name):
     """FP64 rate of the real-space b kernel: REAL_SPACE_FLOP_PER_PAIR per
     electrode-electrolyte pair inside r_c (pairs counted on the host for the
     first configuration), times the configurations of one launch, over its
@@ -438,7 +443,8 @@ def real_space_roofline(w, xyz, B, total_ms, launches):
     avg = total_ms / launches * 1e-3
     return {"kernel": "real_space_b", "bound": "alu", "achieved": flop / avg / 1e12,
             "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": flop / avg / PEAK_FP64_VALU,
-            "traffic": None, "pairs_per_configuration": pairs,
+            "traffic": stored_traffic(name, "cpm::k_real_space_b", per_launch_cfg),
+            "pairs_per_configuration": pairs,
             "flop_per_pair": REAL_SPACE_FLOP_PER_PAIR, "configurations_per_launch": per_launch_cfg,
             "avg_launch_us": avg * 1e6, "us_per_configuration": avg * 1e6 / per_launch_cfg}
 
@@ -646,13 +652,14 @@ def cg_measure(w, xyz, dev, ctx_direct, B=64, tol=1e-13, reps=3):
     return out
 
 
-def stored_traffic(workload, configs_per_launch):
-    """HBM bytes per structure-factor launch from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary (scaled by a 1 GiB copy), per
-    configuration times the timed run's average configurations per launch
-    (a step's last launch group can be partial); None when the kernel source
-    changed since the counters were taken or the average launch holds fewer
-    than 3/4 (or more) of the profiled configurations."""
+def stored_traffic(workload, kernel, configs_per_launch):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (each counter scaled by what it reads for
+    a 1 GiB device copy), per configuration times the timed run's average
+    configurations per launch (a step's last launch group can be partial);
+    None when the kernel source changed since the counters were taken, when
+    no record covers this kernel and workload, or when the average launch
+    holds fewer than 3/4 (or more) of the profiled configurations."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "structure_factor_traffic.json")
     src = os.path.join(ROOT, "paper_2203_15461_amd", "csrc", "bvector.hip")
@@ -661,7 +668,7 @@ def stored_traffic(workload, configs_per_launch):
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, ValueError):
         return None
-    entry = rec.get(workload)
+    entry = rec.get("kernels", {}).get(kernel, {}).get(workload)
     if not entry or rec.get("bvector_sha256") != digest:
         return None
     per = entry.get("configurations_per_launch", 1)

@@ -1,5 +1,5 @@
 // The electrolyte vector b, recomputed for every electrolyte configuration
-// (ELECTRODE paper, Sec. II.A: "the main computational burden").  b is minus
+// (Sec. II.A: the dominant cost of each step).  b is minus
 // the electrolyte potential at the Gaussian electrode atoms:
 //
 //   b_i = -k_e { sum_j q_j sum_t [erfc(alpha r) - erfc(eta r)] / r     (real space)
@@ -18,6 +18,9 @@
 //
 // Every sum is split into fixed chunks whose partials are added in a fixed
 // order, so results are bitwise reproducible.
+#include <algorithm>
+#include <cmath>
+
 #include "cpm_internal.h"
 
 namespace cpm {
@@ -1436,16 +1439,267 @@ __global__ void __launch_bounds__(64 * RS_WAVES) k_real_space_b(
     for (int snap = s0; snap < g; snap += sstep) part[((size_t)snap * rchunks + chunk) * n + atom] = 0.0;
 }
 
+// ---------------------------------------------------------------------------
+// Real-space pair sum for electrodes on z planes when one periodic image at
+// most lies within rc (every cell length >= 2 rc).
+//
+// g(r) = (erfc(alpha r) - erfc(eta r)) / r as a polynomial in s = r^2 on each
+// of RP_N intervals of [0, rc] (uniform in r): degree RP_DEG in
+// (s - s_mid), interpolated at the Chebyshev nodes of the interval, so no
+// square root is taken in FP64 (an FP32 one picks the interval; a neighbouring
+// interval's polynomial is as accurate just past its ends).  Absolute error a
+// few 1e-14 against g(0) ~ 2 (alpha 0.18 .. 0.3, eta 1.979, rc = 3.6 / alpha).
+// ---------------------------------------------------------------------------
+namespace {
+double pair_g_host(double r, double alpha, double eta) {
+  const double two_rpi = 1.1283791670955126;   // 2 / sqrt(pi)
+  if (r * std::max(alpha, eta) < 1.5) {
+    // Taylor series in r^2 (no cancellation while eta r < 1.5)
+    double a2k1 = alpha, e2k1 = eta, fact = 1.0, r2k = 1.0, g = 0.0;
+    const double a2 = alpha * alpha, e2 = eta * eta, r2 = r * r;
+    for (int k = 0; k < 40; ++k) {
+      g += two_rpi * ((k & 1) ? -1.0 : 1.0) * (e2k1 - a2k1) / (fact * (2 * k + 1)) * r2k;
+      a2k1 *= a2; e2k1 *= e2; fact *= (k + 1); r2k *= r2;
+    }
+    return g;
+  }
+  return (std::erfc(alpha * r) - std::erfc(eta * r)) / r;
+}
+}  // namespace
+
+void pair_poly_table(double alpha, double eta, double rc, std::vector<double>& tab) {
+  constexpr int D = RP_DEG;
+  tab.assign((size_t)RP_N * RP_REC, 0.0);
+  const double h = rc / RP_N, pi = 3.14159265358979323846;
+  double node[D + 1];
+  for (int i = 0; i <= D; ++i) node[i] = std::cos((2 * i + 1) * pi / (2.0 * (D + 1)));
+  // monomial coefficients of the Chebyshev polynomials T_0 .. T_D
+  double T[D + 1][D + 1] = {};
+  T[0][0] = 1.0;
+  T[1][1] = 1.0;
+  for (int j = 2; j <= D; ++j)
+    for (int p = 0; p <= D; ++p)
+      T[j][p] = (p > 0 ? 2.0 * T[j - 1][p - 1] : 0.0) - T[j - 2][p];
+  for (int k = 0; k < RP_N; ++k) {
+    // s in [(k h)^2, ((k + 1) h)^2] = s_mid + hw [-1, 1]
+    const double smid = h * h * ((double)k * (k + 1) + 0.5), hw = h * h * (k + 0.5);
+    double f[D + 1], c[D + 1], b[D + 1] = {};
+    for (int i = 0; i <= D; ++i) f[i] = pair_g_host(std::sqrt(smid + hw * node[i]), alpha, eta);
+    for (int j = 0; j <= D; ++j) {
+      double acc = 0.0;
+      for (int i = 0; i <= D; ++i) acc += f[i] * std::cos(j * (2 * i + 1) * pi / (2.0 * (D + 1)));
+      c[j] = acc * (j == 0 ? 1.0 : 2.0) / (D + 1);
+    }
+    for (int j = 0; j <= D; ++j)
+      for (int p = 0; p <= D; ++p) b[p] += c[j] * T[j][p];
+    double* rec = tab.data() + (size_t)k * RP_REC;
+    double scale = 1.0;
+    for (int p = 0; p <= D; ++p) {
+      rec[p] = b[p] / scale;                         // coefficient of (s - s_mid)^p
+      scale *= hw;
+    }
+    rec[RP_REC - 1] = smid;
+  }
+}
+
+// One wave per 64 atom-map slots of one z plane (slot tiles are compact in
+// x and y).  The charges of a chunk arrive 64 at a time (z-sorted blocks; a
+// block whose z range misses [z_p - rc, z_p + rc] is skipped unread).  A
+// charge within rc of the plane in z is taken relative to the tile centre,
+// in each image (x, y shifted by at most one cell length) that can come
+// within rc of the tile's bounding box, and appended to the wave's ring of
+// 128 entries:
+//   FP32  (-2 dx, -2 dy) and W = dx^2 + dy^2 - (rc^2 - dz^2) - margin, so that
+//         an atom at (ax, ay) from the centre is within rc when
+//         ax (-2 dx) + ay (-2 dy) + W < -(ax^2 + ay^2)  (screen, margin
+//         above its rounding error);
+//   FP64  (dx, dy, dz^2, q) for the exact test and g.
+// Every 64 entries each lane screens them into a 64-bit mask and evaluates
+// the marked ones in FP64 (s < rc^2 exactly).  Two images of one charge are
+// 2 rc or more apart, so an atom meets at most one of them within rc.  The
+// summation order of an atom is fixed by the data (deterministic).
+constexpr int RP_RING = 128;
+struct RpWave {
+  float2 c[RP_RING];
+  float w[RP_RING];
+  double4 d[RP_RING];
+};
+
+__global__ void __launch_bounds__(64 * RS_WAVES, 4) k_real_space_plane(
+    int g, int n, int m, int mpad64, const int* __restrict__ amap, int nmap,
+    const double* __restrict__ ex, const double* __restrict__ ey, const double* __restrict__ ez,
+    const double4* __restrict__ cq, const double2* __restrict__ zr, double Lx, double Ly,
+    double Lz, double rc, const double* __restrict__ ptab, double* __restrict__ part) {
+  __shared__ __align__(16) double s_tab[RP_N * RP_REC];
+  __shared__ RpWave s_w[RS_WAVES];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int slot = blockIdx.x * blockDim.x + threadIdx.x;
+  const int atom = slot < nmap ? amap[slot] : -1;
+  const int chunk = blockIdx.y, rchunks = gridDim.y;
+  const int nb64 = mpad64 / 64, nbt = (m + 63) / 64;
+  for (int t = threadIdx.x; t < RP_N * RP_REC / 2; t += blockDim.x)
+    reinterpret_cast<double2*>(s_tab)[t] = reinterpret_cast<const double2*>(ptab)[t];
+  __syncthreads();
+  const unsigned long long valid_atoms = __ballot(atom >= 0);
+  if (!valid_atoms) return;                      // a wave of padding slots only
+  const double invLx = 1.0 / Lx, invLy = 1.0 / Ly, invLz = 1.0 / Lz, rc2 = rc * rc;
+  double xi = 0, yi = 0, zi = 0;
+  if (atom >= 0) { xi = ex[atom]; yi = ey[atom]; zi = ez[atom]; }
+  xi -= Lx * floor(xi * invLx);
+  yi -= Ly * floor(yi * invLy);
+  // the plane's z (every atom of the wave shares it) and the tile's box
+  const int first = __ffsll((long long)valid_atoms) - 1;
+  const double zp = __shfl(zi, first, 64);
+  double xlo = atom >= 0 ? xi : 1e300, xhi = atom >= 0 ? xi : -1e300;
+  double ylo = atom >= 0 ? yi : 1e300, yhi = atom >= 0 ? yi : -1e300;
+  for (int o = 32; o > 0; o >>= 1) {
+    xlo = fmin(xlo, __shfl_xor(xlo, o, 64));
+    xhi = fmax(xhi, __shfl_xor(xhi, o, 64));
+    ylo = fmin(ylo, __shfl_xor(ylo, o, 64));
+    yhi = fmax(yhi, __shfl_xor(yhi, o, 64));
+  }
+  const double cx = 0.5 * (xlo + xhi), cy = 0.5 * (ylo + yhi);
+  const double hx = 0.5 * (xhi - xlo), hy = 0.5 * (yhi - ylo);
+  const double ax = xi - cx, ay = yi - cy;
+  const float axf = (float)ax, ayf = (float)ay, nAf = -(float)(ax * ax + ay * ay);
+  // FP32 screen margin: its rounding error is below 50 u M^2 (u = 2^-24,
+  // M the largest coordinate magnitude, rc + the tile's half extent)
+  const double M = rc + fmax(hx, hy);
+  const double marg = 4e-6 * M * M;
+  RpWave& W = s_w[wave];
+  const float inv_hf = (float)(RP_N / rc);
+  const int nblk = chunk < nbt ? (nbt - chunk + rchunks - 1) / rchunks : 0;
+  const int s0 = blockIdx.z, sstep = gridDim.z;
+  const int nloc = s0 < g ? (g - s0 + sstep - 1) / sstep : 0;
+  const int steps = nloc * nblk;
+  const double wlo = zp - rc, whi = zp + rc;
+  auto hit = [&](int step) {
+    if (step >= steps) return false;
+    const int snap = s0 + sstep * (step / nblk), gb = chunk + rchunks * (step % nblk);
+    const double2 r = zr[(size_t)snap * nb64 + gb];
+    const double a = r.x - Lz * floor((r.x - wlo) * invLz), w = r.y - r.x;
+    return a < whi + 1e-9 || a + w >= wlo + Lz - 1e-9;
+  };
+  auto fetch = [&](int step, bool h) {
+    double4 v = make_double4(0, 0, 0, 0);
+    if (h) {
+      const int snap = s0 + sstep * (step / nblk);
+      const int j = (chunk + rchunks * (step % nblk)) * 64 + lane;
+      if (j < m) v = cq[(size_t)snap * mpad64 + j];
+    }
+    return v;
+  };
+  // screen entries [base, base + len) of the ring and add the marked pairs
+  double acc = 0.0;
+  auto process = [&](int base, int len) {
+    if (atom >= 0) {
+      unsigned long long mk = 0ull;
+#pragma unroll 1
+      for (int q4 = 0; q4 < 64; q4 += 16) {
+        unsigned int mq = 0u;
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const float2 c = W.c[base + q4 + t];
+          const float v = fmaf(axf, c.x, fmaf(ayf, c.y, W.w[base + q4 + t]));
+          mq |= (v < nAf) ? (1u << t) : 0u;
+        }
+        mk |= (unsigned long long)mq << q4;
+      }
+      if (len < 64) mk &= (1ull << len) - 1ull;
+      while (mk) {
+        const int t = __builtin_ctzll(mk);
+        mk &= mk - 1ull;
+        const double4 e = W.d[base + t];
+        const double rx = ax - e.x, ry = ay - e.y;
+        const double sv = fma(rx, rx, fma(ry, ry, e.z));
+        const float rf = __builtin_sqrtf((float)sv);
+        const int k = min((int)(rf * inv_hf), RP_N - 1);
+        const double* T = s_tab + k * RP_REC;
+        const double x = sv - T[RP_REC - 1];
+        double p = T[RP_DEG];
+#pragma unroll
+        for (int j = RP_DEG - 1; j >= 0; --j) p = fma(p, x, T[j]);
+        acc = fma(sv < rc2 ? e.w : 0.0, p, acc);
+      }
+    }
+    wave_lds_sync();                             // the ring's entries are reused next
+  };
+  bool h0 = hit(0), h1 = hit(1);
+  double4 f0 = fetch(0, h0), f1 = fetch(1, h1);
+  int head = 0, tail = 0;                        // ring window [head, tail), head in {0, 64}
+  for (int step = 0; step < steps; ++step) {
+    const int snap = s0 + sstep * (step / nblk), blk = step % nblk;
+    const bool hcur = h0;
+    const double4 cur = f0;
+    f0 = f1; h0 = h1;
+    h1 = hit(step + 2);
+    f1 = fetch(step + 2, h1);
+    if (hcur) {
+      const bool valid = (chunk + rchunks * blk) * 64 + lane < m;
+      double dz = cur.z - zp;
+      dz -= Lz * rint(dz * invLz);
+      const double rho2 = rc2 - dz * dz;
+      double dx = cur.x - cx, dy = cur.y - cy;
+      dx -= Lx * rint(dx * invLx);
+      dy -= Ly * rint(dy * invLy);
+      const double dx2 = dx - copysign(Lx, dx), dy2 = dy - copysign(Ly, dy);
+      // images whose distance from the tile's box can be below sqrt(rho2)
+      auto near = [&](double px, double py) {
+        const double ux = fmax(fabs(px) - hx, 0.0), uy = fmax(fabs(py) - hy, 0.0);
+        return ux * ux + uy * uy < rho2 + marg;
+      };
+      int cand = 0;
+      if (valid && fabs(dz) < rc) {
+        cand = (near(dx, dy) ? 1 : 0) | (near(dx2, dy) ? 2 : 0) | (near(dx, dy2) ? 4 : 0) |
+               (near(dx2, dy2) ? 8 : 0);
+      }
+      while (true) {
+        const bool has = cand != 0;
+        const unsigned long long bal = __ballot(has);
+        if (!bal) break;
+        if (has) {
+          const int which = __builtin_ctz(cand);
+          cand &= cand - 1;
+          const double px = (which & 1) ? dx2 : dx, py = (which & 2) ? dy2 : dy;
+          const int pos = (tail + __popcll(bal & ((1ull << lane) - 1ull))) & (RP_RING - 1);
+          W.c[pos] = make_float2((float)(-2.0 * px), (float)(-2.0 * py));
+          W.w[pos] = (float)(px * px + py * py - rho2 - marg);
+          W.d[pos] = make_double4(px, py, dz * dz, cur.w);
+        }
+        tail += __popcll(bal);
+        wave_lds_sync();
+        if (tail - head >= 64) {
+          process(head & (RP_RING - 1), 64);
+          head += 64;
+        }
+      }
+    }
+    if (blk == nblk - 1) {
+      if (tail > head) process(head & (RP_RING - 1), tail - head);
+      head = tail = 0;
+      if (atom >= 0) part[((size_t)snap * rchunks + chunk) * n + atom] = acc;
+      acc = 0.0;
+    }
+  }
+  if (nblk == 0 && atom >= 0)
+    for (int snap = s0; snap < g; snap += sstep) part[((size_t)snap * rchunks + chunk) * n + atom] = 0.0;
+}
+
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
                          const Buffers& b, int nmap, const double4* cq, const double2* zr,
-                         double Lx, double Ly, double Lz, double rc, double* part, int wg_target) {
+                         double Lx, double Ly, double Lz, double rc, double* part, int wg_target,
+                         const double* plane_tab) {
   // configurations spread over the third grid dimension, about wg_target
   // workgroups in all (a workgroup loops over the configurations beyond)
   const int ablk = (nmap + 64 * RS_WAVES - 1) / (64 * RS_WAVES);
   const int gz = std::max(1, std::min(g, (wg_target + ablk * rchunks - 1) / (ablk * rchunks)));
   dim3 grid(ablk, rchunks, gz), block(64 * RS_WAVES);
-  hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, mpad64, b.amap, nmap,
-                     b.ex, b.ey, b.ez, cq, zr, Lx, Ly, Lz, rc, b.rtab, part);
+  if (plane_tab)
+    hipLaunchKernelGGL(k_real_space_plane, grid, block, 0, st, g, n, m, mpad64, b.amap, nmap,
+                       b.ex, b.ey, b.ez, cq, zr, Lx, Ly, Lz, rc, plane_tab, part);
+  else
+    hipLaunchKernelGGL(k_real_space_b, grid, block, 0, st, g, n, m, mpad64, b.amap, nmap,
+                       b.ex, b.ey, b.ez, cq, zr, Lx, Ly, Lz, rc, b.rtab, part);
 }
 
 // b_i = -k_e (sum of k-space partials + sum of real-space partials

@@ -74,6 +74,20 @@ void dfree(cpm_ctx* c, T*& p) {
   dfree(p);
 }
 
+// Work arrays whose sizes follow the geometry: an allocation that is large
+// enough is kept (no hipFree / hipMalloc, which would wait for the device,
+// when a rebuild keeps the sizes), a smaller one is replaced.
+template <typename T>
+cpm_status dalloc_cap(cpm_ctx* c, T** p, size_t count) {
+  if (*p) {
+    const auto it = c->alloc_sizes.find((const void*)*p);
+    const size_t need = count * sizeof(T) > 0 ? count * sizeof(T) : 16;
+    if (it != c->alloc_sizes.end() && it->second >= need) return CPM_OK;
+    dfree(c, *p);
+  }
+  return dalloc(c, p, count);
+}
+
 #define TRY(expr)                  \
   do {                             \
     cpm_status s_ = (expr);        \
@@ -244,6 +258,14 @@ int rchunks_for(const cpm_ctx* c, int g) {
   const int atom_blocks = (c->nmap + real_space_block_atoms() - 1) / real_space_block_atoms();
   const int t = rs_target(c);
   return std::max(1, std::min(std::max(1, c->m / 64), (t + atom_blocks * g - 1) / (atom_blocks * g)));
+}
+
+// the planar real-space kernel: atoms on z planes (whole waves per plane in
+// the atom map) and at most one periodic image within rc
+bool rs_plane(const cpm_ctx* c) {
+  const double two_rc = 2.0 * c->p.rcut;
+  return c->rs_plane_ok && c->nlayers > 0 && c->p.Lx >= two_rc && c->p.Ly >= two_rc &&
+         c->Lz >= two_rc;
 }
 
 cpm_status ensure_vat(cpm_ctx* c) {
@@ -513,7 +535,7 @@ void precond_apply(cpm_ctx* c, int parity, const double* R, double* Z) {
 
 cpm_status ensure_step_buffers(cpm_ctx* c) {
   Buffers& b = c->b;
-  if (b.sf_part) return CPM_OK;
+  if (c->step_ready) return CPM_OK;
   // chunking of the per-snapshot sums (fixed per context, so results are
   // reproducible): ~512 workgroups per kernel, >= 64 charges per SF chunk,
   // >= 32 charges per real-space chunk
@@ -526,7 +548,7 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   // remain (rchunks is set below, once the group size is known)
   const int atom_blocks = (c->nmap + real_space_block_atoms() - 1) / real_space_block_atoms();
   c->rchunks = std::max(1, std::min(512 / atom_blocks, std::max(1, c->m / 32)));
-  TRY(dalloc(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
+  TRY(dalloc_cap(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
   const bool fast = c->sf_mfma && c->nlayers > 0;
   if (c->sf_mfma) {
     c->mpad = std::max(16, (c->m + 15) / 16 * 16);
@@ -544,26 +566,35 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     const int G = c->pv_group;
     size_t part_rows = 0;                 // (configuration, chunk) blocks of sfm_part
     for (int g = 1; g <= G; ++g) part_rows = std::max(part_rows, (size_t)g * sf_chunks_for(c, g));
-    TRY(dalloc(c, &b.sfm_part, part_rows * c->sfm_pchunk));
-    TRY(dalloc(c, &b.sft, (size_t)G * c->sft_rows * c->mpad));
+    TRY(dalloc_cap(c, &b.sfm_part, part_rows * c->sfm_pchunk));
+    TRY(dalloc_cap(c, &b.sft, (size_t)G * c->sft_rows * c->mpad));
   }
   // (configuration, chunk) rows of the real-space partials
   size_t rrows = (size_t)c->rchunks;
   if (fast)
     for (int g = 1; g <= c->pv_group; ++g) rrows = std::max(rrows, (size_t)g * rchunks_for(c, g));
-  TRY(dalloc(c, &b.sfw, (size_t)2 * c->nk));
+  TRY(dalloc_cap(c, &b.sfw, (size_t)2 * c->nk));
   const int pk_rows = c->nlayers > 0 ? layer_project_chunks((int)c->h_cols.size()) : c->kchunks;
-  TRY(dalloc(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
-  TRY(dalloc(c, &b.phir_part, rrows * c->n));
+  TRY(dalloc_cap(c, &b.phik_part, (size_t)c->n * std::max(pk_rows, c->kchunks)));
+  TRY(dalloc_cap(c, &b.phir_part, rrows * c->n));
   c->dip_blocks = std::max(1, (c->m + 255) / 256);
-  TRY(dalloc(c, &b.dip, (size_t)c->pv_group * c->dip_blocks * 3));
-  TRY(dalloc(c, &b.rtab, (size_t)3 * (RS_NT + 1)));
+  TRY(dalloc_cap(c, &b.dip, (size_t)c->pv_group * c->dip_blocks * 3));
+  TRY(dalloc_cap(c, &b.rtab, (size_t)3 * (RS_NT + 1)));
   const size_t mpad64 = (size_t)std::max(64, (c->m + 63) / 64 * 64);
-  TRY(dalloc(c, &b.zperm, mpad64));
-  TRY(dalloc(c, &b.cq, (size_t)c->pv_group * mpad64));
-  TRY(dalloc(c, &b.zr, (size_t)c->pv_group * (mpad64 / 64)));
+  TRY(dalloc_cap(c, &b.zperm, mpad64));
+  TRY(dalloc_cap(c, &b.cq, (size_t)c->pv_group * mpad64));
+  TRY(dalloc_cap(c, &b.zr, (size_t)c->pv_group * (mpad64 / 64)));
   launch_pair_table(c->stream, c->p.alpha, c->p.eta, c->p.rcut, b.rtab);
   TRY(launched(c, "pair table"));
+  if (!b.ptab) {
+    // pair polynomials of the planar real-space kernel: they depend on the
+    // context's parameters only, so they are formed once
+    std::vector<double> t;
+    pair_poly_table(c->p.alpha, c->p.eta, c->p.rcut, t);
+    TRY(dalloc(c, &b.ptab, t.size()));
+    HIP_TRY(c, hipMemcpy(b.ptab, t.data(), t.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  c->step_ready = true;
   return CPM_OK;
 }
 
@@ -737,6 +768,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
     c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_SF_FP32")) c->sf32_ok = std::atoi(ev) != 0;
+  if (const char* ev = std::getenv("CPM_RS_PLANE")) c->rs_plane_ok = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
 
@@ -952,7 +984,7 @@ cpm_status ensure_inverse_buffers(cpm_ctx* c, unsigned store_flags) {
   TRY(dalloc(c, &b.u, npad));
   TRY(dalloc(c, &b.d, npad));
   TRY(dalloc(c, &b.vat, npad));
-  if (c->n_e <= CCM_MAXE) TRY(dalloc(c, &b.sg, (size_t)npad * c->n_e));
+  if (c->n_e <= CCM_MAXE) TRY(dalloc_cap(c, &b.sg, (size_t)npad * c->n_e));
   if (store_flags & CPM_STORE_F32) TRY(dalloc(c, &b.S32, (size_t)npad * npad));
   if (store_flags & CPM_STORE_BF16X2) {
     TRY(dalloc(c, &b.Shi, (size_t)npad * npad));
@@ -1043,12 +1075,12 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
   Buffers& b0 = c->b;
   HIP_TRY(c, hipStreamSynchronize(c->stream));   // queued work may still use what is freed
   c->have_A = c->have_op = c->have_inv = c->have_v = c->have_q = false;
-  // the CG work arrays, the preconditioner and the b-path work arrays follow
-  // the sizes of the atom map and of the operator (slots, chunks, work
-  // parts): a rebuild allocates them afresh
-  dfree(c, b0.sf_part); dfree(c, b0.sfm_part); dfree(c, b0.sft); dfree(c, b0.sfw);
-  dfree(c, b0.phik_part); dfree(c, b0.phir_part); dfree(c, b0.dip); dfree(c, b0.rtab);
-  dfree(c, b0.zperm); dfree(c, b0.cq); dfree(c, b0.zr);
+  // the b-path work arrays follow the sizes of the atom map and of the
+  // k-set (chunks, launch groups): sized again on first use, keeping
+  // allocations that are large enough
+  c->step_ready = false;
+  // the CG work arrays and the preconditioner follow the atom map and the
+  // operator (slots, chunks, work parts): a rebuild allocates them afresh
   dfree(c, b0.cg_ident); dfree(c, b0.cgv); dfree(c, b0.cgred); dfree(c, b0.cgscal);
   dfree(c, b0.cgphi); dfree(c, b0.cgY); dfree(c, b0.cgT);
   dfree(c, b0.pc_phi); dfree(c, b0.pc_dinv); dfree(c, b0.pc_C); dfree(c, b0.pc_W); dfree(c, b0.pc_ztr);
@@ -1056,7 +1088,8 @@ cpm_status build_impl(cpm_ctx* c, int n, const double* d_xyz, const int* d_eid, 
   dfree(c, b0.pc_ypart); dfree(c, b0.pc_y); dfree(c, b0.pc_wn); dfree(c, b0.pc_g);
   dfree(c, b0.pc_cpart);
   // constrained charges and the cached responses S G follow n_e (and A)
-  dfree(c, b0.ccmU); dfree(c, b0.ccmC); dfree(c, b0.sg);
+  dfree(c, b0.ccmU); dfree(c, b0.ccmC);
+  if (n_e > CCM_MAXE) dfree(c, b0.sg);   // else resized by the next inversion
   dfree(c, b0.zeta); dfree(c, b0.szeta);
   c->szeta_ok = false;
   c->pc_ready = false;
@@ -1634,7 +1667,8 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
     { Timed t(c, "real_space_b");
       launch_gather_charges(st, g, m, mpad64, perm, xyz, b.elq, p.Lx, p.Ly, b.cq, b.zr);
       launch_b_real_space(st, g, n, m, mpad64, rch, b, c->nmap, b.cq, b.zr, p.Lx, p.Ly, c->Lz,
-                          p.rcut, b.phir_part, fast ? rs_target(c) : 512); }
+                          p.rcut, b.phir_part, fast ? rs_target(c) : 512,
+                          rs_plane(c) ? b.ptab : nullptr); }
     if (fast) {
       { Timed t(c, "sf_reduce");
         launch_b_sf_layer_reduce(st, g, c->ncolsort, nch, c->sfm_pchunk, c->nlayers,
@@ -2631,6 +2665,8 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_PC_TILES: *out = c->pc_tiles; return CPM_OK;
     case CPM_INFO_PC_MODE: *out = c->pc_mode; return CPM_OK;
     case CPM_INFO_PC_COARSE: *out = (double)c->pc_tiles * c->pc_kuse; return CPM_OK;
+    case CPM_INFO_SF_FP32:
+      *out = (c->sf_mfma && c->use_sf_mfma && c->sf32_ok) ? 1.0 : 0.0; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
@@ -2665,7 +2701,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);
   dfree(b.Slo); dfree(b.u); dfree(b.d); dfree(b.vat); dfree(b.table); dfree(b.elq); dfree(b.flag);
   dfree(b.sf_part); dfree(b.sfw); dfree(b.phik_part); dfree(b.phir_part); dfree(b.dip); dfree(b.qt);
-  dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab);
+  dfree(b.res); dfree(b.bpad); dfree(b.qpad); dfree(b.scal); dfree(b.means); dfree(b.rtab); dfree(b.ptab);
   dfree(b.xhi); dfree(b.xlo);
   dfree(b.zperm); dfree(b.cq); dfree(b.zr);
   dfree(b.kpart); dfree(b.ccmU); dfree(b.ccmC); dfree(b.sg); dfree(b.zeta); dfree(b.szeta);

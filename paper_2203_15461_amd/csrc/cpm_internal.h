@@ -42,6 +42,9 @@ inline int sf_mfma_chunk(int mpad, int mchunks) {
 }
 
 constexpr int RS_NT = 2048;        // intervals of the real-space pair table on [0, rc]
+constexpr int RP_N = 512;          // intervals of the planar pair polynomials on [0, rc]
+constexpr int RP_DEG = 6;          // their degree in s = r^2
+constexpr int RP_REC = 8;          // doubles per interval: coefficients, then s_mid
 
 constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
 constexpr int MAX_LAYERS = 64;     // planar-electrode factorisation up to this many z planes
@@ -100,6 +103,7 @@ struct Buffers {
   double* phir_part = nullptr;     // m-chunk partial real-space potentials (n * rchunks)
   double* dip = nullptr;           // electrolyte dipole partials (per 256 charges, 3 axes)
   double* rtab = nullptr;          // real-space pair table (g, g', g'') x (RS_NT + 1)
+  double* ptab = nullptr;          // planar pair polynomials (RP_N x RP_REC), set once
   int* zperm = nullptr;            // order of the charges for the real-space pass (m)
   double4* cq = nullptr;           // gathered charges (x, y wrapped, z, q), pv_group x mpad64
   double2* zr = nullptr;           // z range of each 64-charge block, pv_group x mpad64 / 64
@@ -261,6 +265,7 @@ struct cpm_ctx {
   double cdip[3] = {0, 0, 0};      // dipole term A += k_e sum_d cdip_d r_d r_d^T (geometry)
   int dip_blocks = 1;              // electrolyte dipole partials per configuration
   int nk = 0, nruns = 0;
+  bool step_ready = false;         // b-path work arrays sized for the current geometry
   int mchunks = 1, kchunks = 1, rchunks = 1;
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
   int sfm_wg_target = 4096;        // the same for the matrix-core kernel
@@ -303,6 +308,7 @@ struct cpm_ctx {
   bool sf_mfma = false;            // structure factors on FP64 matrix cores (k set fits)
   bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
   bool sf32_ok = true;             // FP32 structure factors when b is stored in FP32
+  bool rs_plane_ok = true;         // planar real-space kernel (pair polynomials in r^2)
   int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_ntot = 0;
   int sfm_nbz = 2, sfm_nitems = 0, mpad = 0, sft_rows = 0, sft_blocks = 1;
   int sfm_pchunk = 0;              // doubles per (configuration, chunk) of sfm_part
@@ -498,7 +504,11 @@ int layer_project_chunks(int ncols);
 void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab);
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
                          const Buffers& b, int nmap, const double4* cq, const double2* zr,
-                         double Lx, double Ly, double Lz, double rc, double* part, int wg_target);
+                         double Lx, double Ly, double Lz, double rc, double* part, int wg_target,
+                         const double* plane_tab);
+// coefficients of g(r) as polynomials in r^2 on RP_N intervals of [0, rc]
+// (RP_N x RP_REC doubles), for the planar real-space kernel
+void pair_poly_table(double alpha, double eta, double rc, std::vector<double>& tab);
 void launch_b_combine(hipStream_t st, int n, int kchunks, int rchunks, const double* phik,
                       const double* phir, const Buffers& b, const double* dip, int dip_blocks,
                       const double* cdip, double ke, void* out, int out_is_f32);
