@@ -14,7 +14,7 @@ and electrode totals.  `value` = B * K / (timed seconds).  Inputs are
 resident in HBM before the timed region; all work runs in libcpm's kernels.
 
 The same line carries the metric's second point (the 20064-atom capacitor,
-128 configurations per step, Ewald split retuned to alpha 0.22 / r_c 16.36 A
+128 configurations per step, Ewald split retuned to alpha 0.19 / r_c 18.95 A
 at the same truncation accuracy), the uneven eight-capacitor batch, the
 batched FP64 matrix-core comparator, warm and cache-flushed matvec rates, the
 real-space kernel's roofline and the FP64 oracle timed on the host cores.
@@ -48,7 +48,7 @@ DOMINANT = "structure_factor"
 # smaller alpha moves work from the k-space sum (|K+| ~ alpha^3) to the real
 # space (r_c^3 ~ alpha^-3); r_c = 3.6 / alpha keeps erfc(alpha r_c) at its
 # alpha 0.3, r_c 12 A value and k_c = 2 alpha sqrt(ln 1e8) the k-space accuracy
-ALPHA_20K = 0.22
+ALPHA_20K = 0.19
 REAL_SPACE_FLOP_PER_PAIR = 50.0   # one erfc-difference pair term (distance, g(r), accumulate)
 
 

@@ -1612,7 +1612,7 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 4) k_real_space_plane(
         const double4 e = W.d[base + t];
         const double rx = ax - e.x, ry = ay - e.y;
         const double sv = fma(rx, rx, fma(ry, ry, e.z));
-        const float rf = __builtin_sqrtf((float)sv);
+        const float rf = __builtin_amdgcn_sqrtf((float)sv);   // picks the interval only
         const int k = min((int)(rf * inv_hf), RP_N - 1);
         const double* T = s_tab + k * RP_REC;
         const double x = sv - T[RP_REC - 1];
