@@ -110,6 +110,8 @@ def main():
                                                    "solve_only_rate", "plain_fp64_per_step_rate",
                                                    "graph_fp64_per_step", "matvec_roofline",
                                                    "conjugate_gradient", "max_abs_sum_q")}
+        out["workload_20064_factor"] = run_factor_step(w20, 128, 1, 1, True)
+        out["workload_20064_factor_f64"] = run_factor_step(w20, 128, 1, 1, False)
     if args.workload == "graphite_capacitor_2880" and not args.no_mixed:
         margs = argparse.Namespace(**vars(args))
         margs.steps, margs.warmup, margs.batch = 1, 1, None
@@ -118,6 +120,65 @@ def main():
         out["cpu_baseline"], q_ref, Q_ref = cpu_baseline(w)
         out["accuracy_vs_oracle"] = accuracy_vs_oracle(w, q_ref, Q_ref)
     print(json.dumps(out), flush=True)
+
+
+def run_factor_step(w, B, steps, warmup, b_f32):
+    """The same step with the factor-only inverse (CPM_INVERT_FACTOR): A is
+    assembled and Cholesky-factored on the second stream while b runs, and
+    q = P A^-1 b + d comes from forward and back substitution with the
+    factor for all B configurations (FP64 solve; no L^-1, A^-1 or S); b in
+    FP64, or in FP32 from the FP32 structure factors (b_f32)."""
+    import torch
+    from paper_2203_15461_amd import cpm
+    from paper_2203_15461_amd import inputs as I
+    dev = torch.device("cuda:0")
+    xyz = synthetic_configurations(w, B, I.BASE_SEED + 1, dev)
+    R = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device=dev).contiguous()
+    eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device=dev).contiguous()
+    bvec = torch.empty((B, w.n), dtype=torch.float32 if b_f32 else torch.float64, device=dev)
+    q = torch.empty((B, w.n), dtype=torch.float64, device=dev)
+    Qe = torch.empty((B, 2), dtype=torch.float64, device=dev)
+    ctx = cpm.Context(cpm.Params.of(w))
+    ctx.set_electrolyte(w.electrolyte_q)
+    flags = cpm.STORE_F64 | cpm.INVERT_FACTOR
+
+    def step():
+        ctx.build_elastance(R, eid, 2)
+        ctx.invert(flags | cpm.INVERT_ASYNC)
+        ctx.potential_vector(xyz, bvec)
+        ctx.set_potential(w.v_electrode)
+        ctx.solve_charges(bvec, 0x000, q, Qe)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    # phases of one more step, serialised
+    ts = time.perf_counter()
+    ctx.build_elastance(R, eid, 2)
+    ctx.invert(flags)
+    ctx.set_potential(w.v_electrode)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - ts
+    ts = time.perf_counter()
+    ctx.potential_vector(xyz, bvec)
+    torch.cuda.synchronize()
+    b_s = time.perf_counter() - ts
+    ts = time.perf_counter()
+    ctx.solve_charges(bvec, 0x000, q, Qe)
+    torch.cuda.synchronize()
+    solve_s = time.perf_counter() - ts
+    out = {"value": B * steps / elapsed, "ms_per_step": elapsed / steps * 1e3,
+           "dtype": "b f32, f64 factor solve" if b_f32 else "f64",
+           "solver": "Cholesky factor, forward and back substitution for all configurations",
+           "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
+           "max_abs_sum_q": float(q.sum(dim=1).abs().max().item())}
+    ctx.close()
+    return out
 
 
 def large_capacitor(alpha):

@@ -67,9 +67,10 @@ typedef enum { CPM_GEOM_SLAB_EW3DC = 0, CPM_GEOM_WIRE = 1, CPM_GEOM_3D = 2 } cpm
 
 /* Which copies of S cpm_invert keeps (bit set).  FP64 is always kept. */
 enum { CPM_STORE_F64 = 1, CPM_STORE_F32 = 2, CPM_STORE_BF16X2 = 4 };
-/* cpm_invert flag: enqueue the inversion on a second stream of the context
- * and return at once (see cpm_invert). */
-enum { CPM_INVERT_ASYNC = 0x100 };
+/* cpm_invert flags: enqueue the inversion on a second stream of the context
+ * and return at once; stop at the Cholesky factor instead of forming S
+ * (see cpm_invert). */
+enum { CPM_INVERT_ASYNC = 0x100, CPM_INVERT_FACTOR = 0x200 };
 
 /* Solve modes for cpm_solve_charges.  The low byte picks the copy of S that
  * is streamed; CPM_SOLVE_REFINE adds one FP64 refinement step against A. */
@@ -235,6 +236,19 @@ cpm_status cpm_solve_cg(cpm_ctx* ctx, int batch, const void* d_b, int b_is_f32, 
  * cpm_replay_step, cpm_copy_matrix/vector, cpm_get_info(S_SUM or PIVOT),
  * cpm_synchronize -- waits for it and returns CPM_ENOTPD there if a pivot
  * failed; a rebuild or another cpm_invert waits for it first. */
+/* With CPM_INVERT_FACTOR (store_flags then names no copy of S) the work
+ * stops at the factor: A = L L^T is kept (FP64, with the inverses of its
+ * 64 x 64 diagonal blocks) and A^-1 x is formed by forward and back
+ * substitution, 2 n^2 flop per vector and direction, instead of the
+ * 2 n^3 / 3 flop of L^-1 and L^-T L^-1: u, s and the response S G come from
+ * the solves with the n_e electrode indicators (n_e <= 16, else
+ * CPM_EUNSUPPORTED), and cpm_solve_charges (CPM_SOLVE_F64 only) forms
+ * S (b + v) = P A^-1 b + d with P = I - u e^T / s.  For few configurations
+ * per electrode geometry this saves most of the set-up.  cpm_set_potential,
+ * cpm_set_potential_atoms and cpm_set_field work as with S; calls that need
+ * S itself or A^-1 (other solve modes, cpm_set_charge, cpm_autotune,
+ * cpm_solve_grouped, cpm_capture_step, cpm_save, cpm_copy_matrix of A^-1 or
+ * S, cpm_solve_charges_noalloc) return CPM_ESTATE. */
 cpm_status cpm_invert(cpm_ctx* ctx, unsigned store_flags);
 
 /* Applied potentials h_v_electrode[n_e] (V), one per electrode (v = G v~,

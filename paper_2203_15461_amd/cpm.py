@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "CPM_OK", 1: "CPM_EINVAL", 2: "CPM_ESTATE", 3: "CPM_ENOMEM", 
 # store flags, solve modes, info keys
 STORE_F64, STORE_F32, STORE_BF16X2 = 1, 2, 4
 INVERT_ASYNC = 0x100
+INVERT_FACTOR = 0x200
 SOLVE_F64, SOLVE_F32, SOLVE_BF16X2, SOLVE_REFINE, SOLVE_CCM = 0, 1, 2, 0x100, 0x200
 INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, npad=9, nruns=10,
             nlayers=11, sf_matrix=12, tune_bm=13, tune_ks=14, tune_grid=15, tune_us=16, group=17,

@@ -976,9 +976,17 @@ uint64_t geometry_hash(const cpm_ctx* c, int n, int n_e, const double* xyz, cons
 
 // A^-1, S, u, d, v, the cached response S G and the reduced-precision
 // copies of S named by store_flags
-cpm_status ensure_inverse_buffers(cpm_ctx* c, unsigned store_flags) {
+cpm_status ensure_inverse_buffers(cpm_ctx* c, unsigned store_flags, bool factor = false) {
   Buffers& b = c->b;
   const int npad = c->npad;
+  if (factor) {
+    TRY(dalloc(c, &b.u, npad));
+    TRY(dalloc(c, &b.d, npad));
+    TRY(dalloc(c, &b.vat, npad));
+    TRY(dalloc_cap(c, &b.sg, (size_t)npad * c->n_e));
+    TRY(dalloc_cap(c, &b.fwork, (size_t)2 * TILE * npad));
+    return CPM_OK;
+  }
   TRY(dalloc(c, &b.Ainv, (size_t)npad * npad));
   TRY(dalloc(c, &b.S, (size_t)npad * npad));
   TRY(dalloc(c, &b.u, npad));
@@ -991,6 +999,71 @@ cpm_status ensure_inverse_buffers(cpm_ctx* c, unsigned store_flags) {
     TRY(dalloc(c, &b.Slo, (size_t)npad * npad));
   }
   return CPM_OK;
+}
+
+// X <- X A^-1 for `rows` right-hand sides stored as rows (stride npad,
+// rows a multiple of 64) with the Cholesky factor A = L L^T (b.L, lower;
+// b.Dinv the inverses of its 64 x 64 diagonal blocks): Y L^T = X by blocks
+// left to right, then Z L = Y right to left, Z into X (Y: work of the same
+// shape).  Each block step is two MFMA GEMMs: the block times its diagonal
+// inverse, then the update of the blocks still to come with one panel of L.
+// 2 rows n^2 flop per direction; every sum in a fixed order.
+cpm_status factor_solve_rows(cpm_ctx* c, hipStream_t st, int rows, double* X, double* Y) {
+  const int npad = c->npad, nb = npad / TILE;
+  const Buffers& b = c->b;
+  Timed t(c, "factor_solve", st);
+  for (int k = 0; k < nb; ++k) {
+    const int c0 = k * TILE, rest = npad - c0 - TILE;
+    const double* Dk = b.Dinv + (size_t)k * TILE * TILE;
+    launch_gemm_f64(st, false, true, rows, TILE, TILE, 1.0, X + c0, npad, Dk, TILE, 0.0, Y + c0,
+                    npad, 0, 0);
+    if (rest > 0)
+      launch_gemm_f64(st, false, true, rows, rest, TILE, -1.0, Y + c0, npad,
+                      b.L + (size_t)(c0 + TILE) * npad + c0, npad, 1.0, X + c0 + TILE, npad, 0, 0);
+  }
+  for (int k = nb - 1; k >= 0; --k) {
+    const int c0 = k * TILE;
+    const double* Dk = b.Dinv + (size_t)k * TILE * TILE;
+    launch_gemm_f64(st, false, false, rows, TILE, TILE, 1.0, Y + c0, npad, Dk, TILE, 0.0, X + c0,
+                    npad, 0, 0);
+    if (c0 > 0)
+      launch_gemm_f64(st, false, false, rows, c0, TILE, -1.0, X + c0, npad, b.L + (size_t)c0 * npad,
+                      npad, 1.0, Y, npad, 0, 0);
+  }
+  return launched(c, "factor solve");
+}
+
+// factor-only inverse: u = A^-1 e, s = e^T u and the response S G (Eqs. 4,
+// 6) from the solves with the electrode indicators
+cpm_status factor_response(cpm_ctx* c, hipStream_t st) {
+  Buffers& b = c->b;
+  const int npad = c->npad;
+  double* X = b.fwork;
+  double* Y = b.fwork + (size_t)TILE * npad;
+  launch_group_indicator(st, c->n, npad, TILE, b.eid, c->n_e, X);
+  TRY(factor_solve_rows(c, st, TILE, X, Y));
+  launch_factor_response(st, c->n, npad, c->n_e, X, npad, b.u, b.scal, b.sg);
+  c->szeta_ok = false;
+  c->have_q = false;
+  return launched(c, "factor response");
+}
+
+// y = S x for one vector (npad, padding zero): one pass over S, or with the
+// factor-only inverse x A^-1 by substitution and the projection P
+cpm_status apply_S_one(cpm_ctx* c, const double* x, double* y) {
+  if (!c->factor_only) {
+    launch_matvec(c->stream, 0, c->npad, c->b.S, 1, x, nullptr, 0, 0.0, y, c->npad, 0);
+    return launched(c, "S x");
+  }
+  Buffers& b = c->b;
+  const int npad = c->npad;
+  double* X = b.fwork;
+  double* Y = b.fwork + (size_t)TILE * npad;
+  launch_pad_rows(c->stream, npad, npad, 1, TILE, x, 0, nullptr, X);
+  TRY(factor_solve_rows(c, c->stream, TILE, X, Y));
+  launch_finalize(c->stream, c->n, 1, X, npad, nullptr, b.u, b.scal, b.eid, c->n_e, y, npad,
+                  nullptr);
+  return launched(c, "S x (factor)");
 }
 
 // From A^-1 in b.Ainv: u = A^-1 e, s = e^T u, S = A^-1 - u u^T / s (Eq. 4),
@@ -1373,15 +1446,22 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
   TRY(wait_invert(c));                    // a new inversion supersedes a pending one
   c->inv_failed = false;
   if (!c->have_A) return fail(c, CPM_ESTATE, "cpm_invert before cpm_build_elastance");
-  if (store_flags & ~(unsigned)(CPM_STORE_F64 | CPM_STORE_F32 | CPM_STORE_BF16X2 | CPM_INVERT_ASYNC))
+  if (store_flags & ~(unsigned)(CPM_STORE_F64 | CPM_STORE_F32 | CPM_STORE_BF16X2 | CPM_INVERT_ASYNC |
+                                CPM_INVERT_FACTOR))
     return fail(c, CPM_EINVAL, "unknown store flags 0x%x", store_flags);
   const bool async = (store_flags & CPM_INVERT_ASYNC) != 0;
-  store_flags &= ~(unsigned)CPM_INVERT_ASYNC;
+  const bool factor = (store_flags & CPM_INVERT_FACTOR) != 0;
+  store_flags &= ~(unsigned)(CPM_INVERT_ASYNC | CPM_INVERT_FACTOR);
+  if (factor && (store_flags & (CPM_STORE_F32 | CPM_STORE_BF16X2)))
+    return fail(c, CPM_EINVAL, "CPM_INVERT_FACTOR keeps no copy of S");
+  if (factor && c->n_e > CCM_MAXE)
+    return fail(c, CPM_EUNSUPPORTED, "CPM_INVERT_FACTOR supports at most %d electrodes", CCM_MAXE);
   const int n = c->n, npad = c->npad, nb = npad / TILE;
   Buffers& b = c->b;
   TRY(dalloc(c, &b.L, (size_t)npad * npad));
   TRY(dalloc(c, &b.Dinv, (size_t)nb * TILE * TILE));
-  TRY(ensure_inverse_buffers(c, store_flags));
+  TRY(ensure_inverse_buffers(c, store_flags, factor));
+  c->factor_only = false;
   hipStream_t st = c->stream;
   if (async) {
     // a second stream of default priority, ordered after the work already
@@ -1448,46 +1528,53 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
       return fail(c, CPM_ENOTPD, "elastance matrix not positive definite at pivot %d", c->pivot);
     }
   }
-  // X = L^-1 by blocked forward substitution (X stored in Ainv's buffer
-  // first), grouped like the factorisation: row blocks of 64 inside blocks
-  // of OB rows, the rows below a block updated by one rank-OB product
-  double* X = b.Ainv;
-  launch_set_identity(st, npad, X);
-  for (int K0 = 0; K0 < npad; K0 += OB) {
-    const int kend = std::min(npad, K0 + OB);
-    for (int k0 = K0; k0 < kend; k0 += TILE) {
-      const int kb = k0 / TILE, cols = k0 + TILE, rin = kend - k0 - TILE;
-      double* Xk = X + (size_t)k0 * npad;
-      Timed t(c, "trtri", st);
-      // X_k = L_kk^-1 X_k on the columns that can be non-zero
-      launch_gemm_f64(st, false, false, TILE, cols, TILE, 1.0, b.Dinv + (size_t)kb * TILE * TILE,
-                      TILE, Xk, npad, 0.0, Xk, npad, 0, 0);
-      if (rin > 0) {
-        // the block's rows below: X_i -= L_ik X_k
-        launch_gemm_f64(st, false, false, rin, cols, TILE, -1.0,
-                        b.L + (size_t)(k0 + TILE) * npad + k0, npad, Xk, npad, 1.0,
-                        X + (size_t)(k0 + TILE) * npad, npad, 0, 0);
+  if (factor) {
+    // keep L: u, s and S G from triangular solves, no L^-1 or A^-1
+    TRY(factor_response(c, st));
+    c->store = CPM_STORE_F64;
+  } else {
+    // X = L^-1 by blocked forward substitution (X stored in Ainv's buffer
+    // first), grouped like the factorisation: row blocks of 64 inside blocks
+    // of OB rows, the rows below a block updated by one rank-OB product
+    double* X = b.Ainv;
+    launch_set_identity(st, npad, X);
+    for (int K0 = 0; K0 < npad; K0 += OB) {
+      const int kend = std::min(npad, K0 + OB);
+      for (int k0 = K0; k0 < kend; k0 += TILE) {
+        const int kb = k0 / TILE, cols = k0 + TILE, rin = kend - k0 - TILE;
+        double* Xk = X + (size_t)k0 * npad;
+        Timed t(c, "trtri", st);
+        // X_k = L_kk^-1 X_k on the columns that can be non-zero
+        launch_gemm_f64(st, false, false, TILE, cols, TILE, 1.0, b.Dinv + (size_t)kb * TILE * TILE,
+                        TILE, Xk, npad, 0.0, Xk, npad, 0, 0);
+        if (rin > 0) {
+          // the block's rows below: X_i -= L_ik X_k
+          launch_gemm_f64(st, false, false, rin, cols, TILE, -1.0,
+                          b.L + (size_t)(k0 + TILE) * npad + k0, npad, Xk, npad, 1.0,
+                          X + (size_t)(k0 + TILE) * npad, npad, 0, 0);
+        }
+        TRY(launched(c, "trtri"));
       }
-      TRY(launched(c, "trtri"));
+      const int rest = npad - kend;
+      if (rest > 0) {
+        // every row below the block: X_below -= L_below,block X_block (columns < kend)
+        Timed t(c, "trtri", st);
+        launch_gemm_f64(st, false, false, rest, kend, kend - K0, -1.0,
+                        b.L + (size_t)kend * npad + K0, npad, X + (size_t)K0 * npad, npad, 1.0,
+                        X + (size_t)kend * npad, npad, 0, 0);
+        TRY(launched(c, "trtri"));
+      }
     }
-    const int rest = npad - kend;
-    if (rest > 0) {
-      // every row below the block: X_below -= L_below,block X_block (columns < kend)
-      Timed t(c, "trtri", st);
-      launch_gemm_f64(st, false, false, rest, kend, kend - K0, -1.0,
-                      b.L + (size_t)kend * npad + K0, npad, X + (size_t)K0 * npad, npad, 1.0,
-                      X + (size_t)kend * npad, npad, 0, 0);
-      TRY(launched(c, "trtri"));
-    }
+    // A^-1 = X^T X (lower tiles, k from max(row, col)), result into L's buffer,
+    // then swap names so Ainv holds A^-1
+    { Timed t(c, "lauum", st);
+      launch_gemm_f64(st, true, false, npad, npad, npad, 1.0, X, npad, X, npad, 0.0, b.L, npad, 1, 1);
+      launch_mirror_lower(st, npad, b.L); }
+    TRY(launched(c, "lauum"));
+    std::swap(b.L, b.Ainv);
+    TRY(form_S(c, st, store_flags));
   }
-  // A^-1 = X^T X (lower tiles, k from max(row, col)), result into L's buffer,
-  // then swap names so Ainv holds A^-1
-  { Timed t(c, "lauum", st);
-    launch_gemm_f64(st, true, false, npad, npad, npad, 1.0, X, npad, X, npad, 0.0, b.L, npad, 1, 1);
-    launch_mirror_lower(st, npad, b.L); }
-  TRY(launched(c, "lauum"));
-  std::swap(b.L, b.Ainv);
-  TRY(form_S(c, st, store_flags));
+  c->factor_only = factor;
   if (async) {
     // results are joined by the first call that needs them (finish_invert)
     HIP_TRY(c, hipMemcpyAsync(&c->h_async->s, b.scal, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1563,8 +1650,7 @@ cpm_status cpm_set_field(cpm_ctx* c, double dv0, int bottom) {
     // S zeta once per inverse (Eq. 14 with the response cached): a new dv0
     // then costs O(n)
     TRY(dalloc(c, &b.szeta, (size_t)c->npad));
-    launch_matvec(c->stream, 0, c->npad, b.S, 1, b.zeta, nullptr, 0, 0.0, b.szeta, c->npad, 0);
-    TRY(launched(c, "field response"));
+    TRY(apply_S_one(c, b.zeta, b.szeta));
     c->szeta_ok = true;
   }
   launch_scale_field(c->stream, c->npad, dv0, b.zeta, c->have_inv ? b.szeta : nullptr, b.vat, b.d);
@@ -1587,8 +1673,7 @@ cpm_status cpm_set_potential_atoms(cpm_ctx* c, const double* h_v) {
   for (int i = 0; i < c->n; ++i) vat[i] = h_v[i];
   TRY(ensure_vat(c));
   HIP_TRY(c, hipMemcpyAsync(c->b.vat, vat.data(), c->npad * sizeof(double), hipMemcpyHostToDevice, c->stream));
-  if (c->have_inv)
-    launch_matvec(c->stream, 0, c->npad, c->b.S, 1, c->b.vat, nullptr, 0, 0.0, c->b.d, c->npad, 0);
+  if (c->have_inv) TRY(apply_S_one(c, c->b.vat, c->b.d));
   TRY(launched(c, "set_potential_atoms"));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->have_v = true;
@@ -1725,6 +1810,8 @@ cpm_status sc_validate(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, uns
       return fail(c, CPM_EUNSUPPORTED, "constrained charges run in FP64 without refinement");
     if (!c->have_q) return fail(c, CPM_ESTATE, "CPM_SOLVE_CCM before cpm_set_charge");
   }
+  if (c->factor_only && mode != CPM_SOLVE_F64)
+    return fail(c, CPM_ESTATE, "the factor-only inverse (CPM_INVERT_FACTOR) solves in mode 0 only");
   if (prec == 1 && !(c->store & CPM_STORE_F32)) return fail(c, CPM_EINVAL, "FP32 copy of S not kept");
   if (prec == 2 && !(c->store & CPM_STORE_BF16X2))
     return fail(c, CPM_EINVAL, "split-BF16 copy of S not kept");
@@ -1736,7 +1823,7 @@ cpm_status sc_prepare(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
                       double* d_q) {
   TRY(sc_validate(c, batch, d_b, b_is_f32, mode, d_q));
   const unsigned prec = mode & 0xffu;
-  const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
+  const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2 || c->factor_only;
   const int rows = gemm ? ((batch + TILE - 1) / TILE) * TILE : batch;
   TRY(ensure_solve_buffers(c, rows));
   if (prec == 2) {
@@ -1763,6 +1850,18 @@ cpm_status sc_enqueue(cpm_ctx* c, int batch, const void* d_b, int b_is_f32, unsi
   const void* Sm = (prec == 1) ? (const void*)b.S32 : (const void*)b.S;
   const int which = (prec == 1) ? 1 : 0;
   const char* mv_name = (prec == 1) ? "matvec_f32" : "matvec_f64";
+
+  if (c->factor_only) {
+    // S (b + v) = P A^-1 b + d: the batch as rows (padded to 64), A^-1 by
+    // substitution with the Cholesky factor, then P and d in the finalize
+    const int frows = ((batch + TILE - 1) / TILE) * TILE;
+    { Timed t(c, "pad_rows");
+      launch_pad_rows(st, n, npad, batch, frows, d_b, b_is_f32, nullptr, w.bpad); }
+    TRY(factor_solve_rows(c, st, frows, w.bpad, w.qpad));
+    { Timed t(c, "finalize");
+      launch_finalize(st, n, batch, w.bpad, npad, b.d, b.u, b.scal, b.eid, c->n_e, d_q, n, d_Qe); }
+    return launched(c, "solve (factor)");
+  }
 
   if (mode & CPM_SOLVE_CCM) {
     // constrained charges (Eq. 7): y = A^-1 b in FP64, then the per-electrode
@@ -1919,6 +2018,7 @@ cpm_status cpm_solve_charges_noalloc(cpm_ctx* c, int batch, const void* d_b, int
                                      unsigned mode, double* d_q, double* d_Qe) {
   if (!c) return CPM_EINVAL;
   TRY(sc_validate(c, batch, d_b, b_is_f32, mode, d_q));
+  if (c->factor_only) return fail(c, CPM_ESTATE, "the no-allocation solve needs S (not CPM_INVERT_FACTOR)");
   const unsigned prec = mode & 0xffu;
   const bool gemm = (batch >= GEMM_MIN_BATCH && prec == 0) || prec == 2;
   const size_t rows = gemm ? ((size_t)(batch + TILE - 1) / TILE) * TILE : (size_t)batch;
@@ -1964,6 +2064,7 @@ cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_
     return fail(c, CPM_EINVAL, "graph capture needs a non-default stream for the context");
   TRY(pv_prepare(c, batch, d_xyz, d_b, b_is_f32));
   TRY(sc_prepare(c, batch, d_b, b_is_f32, mode, d_q));
+  if (c->factor_only) return fail(c, CPM_ESTATE, "graph capture needs S (not CPM_INVERT_FACTOR)");
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (c->graph_exec) { (void)hipGraphExecDestroy(c->graph_exec); c->graph_exec = nullptr; }
   if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
@@ -2006,6 +2107,7 @@ cpm_status cpm_set_charge(cpm_ctx* c, const double* h_Q) {
   if (!c) return CPM_EINVAL;
   TRY(finish_invert(c));
   if (!c->have_inv) return fail(c, CPM_ESTATE, "cpm_set_charge before cpm_invert");
+  if (c->factor_only) return fail(c, CPM_ESTATE, "constrained charges need A^-1 (not CPM_INVERT_FACTOR)");
   if (!h_Q) return fail(c, CPM_EINVAL, "h_Q is NULL");
   const int ne = c->n_e, n = c->n;
   if (ne > CCM_MAXE) return fail(c, CPM_EUNSUPPORTED, "at most %d electrodes for constrained charges", CCM_MAXE);
@@ -2058,7 +2160,7 @@ cpm_status cpm_set_charge(cpm_ctx* c, const double* h_Q) {
 cpm_status cpm_autotune(cpm_ctx* c, int batch, int reps) {
   if (!c) return CPM_EINVAL;
   TRY(finish_invert(c));
-  if (!c->have_inv || !(c->store & CPM_STORE_BF16X2) || !c->b.Shi)
+  if (!c->have_inv || c->factor_only || !(c->store & CPM_STORE_BF16X2) || !c->b.Shi)
     return fail(c, CPM_ESTATE, "cpm_autotune needs cpm_invert with the split-BF16 copy of S");
   if (batch <= 0 || reps <= 0) return fail(c, CPM_EINVAL, "need batch > 0 and reps > 0");
   const int rows = ((batch + TILE - 1) / TILE) * TILE, npad = c->npad;
@@ -2487,7 +2589,7 @@ cpm_status cpm_save(const cpm_ctx* cc, const char* path) {
   hd.header_bytes = FILE_HEADER;
   hd.n = n;
   hd.n_e = c->n_e;
-  hd.matrices = c->have_inv ? 2 : 1;
+  hd.matrices = (c->have_inv && !c->factor_only) ? 2 : 1;   // A^-1 only when it was formed
   hd.store = c->have_inv ? c->store : 0;
   hd.geom_hash = c->geom_hash;
   hd.s_sum = c->have_inv ? c->s_sum : 0.0;
@@ -2606,8 +2708,8 @@ cpm_status cpm_copy_matrix(const cpm_ctx* c, int which, double* d_out) {
   if (which == 0 && c->have_A) TRY(assemble_A(const_cast<cpm_ctx*>(c), c->stream));
   const double* src = nullptr;
   if (which == 0 && c->have_A) src = c->b.A;
-  if (which == 1 && c->have_inv) src = c->b.Ainv;
-  if (which == 2 && c->have_inv) src = c->b.S;
+  if (which == 1 && c->have_inv && !c->factor_only) src = c->b.Ainv;
+  if (which == 2 && c->have_inv && !c->factor_only) src = c->b.S;
   if (!src) return CPM_ESTATE;
   const int n = c->n, npad = c->npad;
   if (hipMemcpy2DAsync(d_out, n * sizeof(double), src, npad * sizeof(double), n * sizeof(double), n,

@@ -104,6 +104,7 @@ struct Buffers {
   double* dip = nullptr;           // electrolyte dipole partials (per 256 charges, 3 axes)
   double* rtab = nullptr;          // real-space pair table (g, g', g'') x (RS_NT + 1)
   double* ptab = nullptr;          // planar pair polynomials (RP_N x RP_REC), set once
+  double* fwork = nullptr;         // factor-only inverse: two 64 x npad right-hand-side blocks
   int* zperm = nullptr;            // order of the charges for the real-space pass (m)
   double4* cq = nullptr;           // gathered charges (x, y wrapped, z, q), pv_group x mpad64
   double2* zr = nullptr;           // z range of each 64-charge block, pv_group x mpad64 / 64
@@ -309,6 +310,7 @@ struct cpm_ctx {
   bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
   bool sf32_ok = true;             // FP32 structure factors when b is stored in FP32
   bool rs_plane_ok = true;         // planar real-space kernel (pair polynomials in r^2)
+  bool factor_only = false;        // cpm_invert kept the Cholesky factor, not S
   int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_ntot = 0;
   int sfm_nbz = 2, sfm_nitems = 0, mpad = 0, sft_rows = 0, sft_blocks = 1;
   int sfm_pchunk = 0;              // doubles per (configuration, chunk) of sfm_part
@@ -501,6 +503,13 @@ void launch_b_layer_project(hipStream_t st, int n, int ncols, int nlayers, const
                             const int* layer_of, const double* layer_fz, const Buffers& b,
                             const double* sfw, double2* T, double* part);
 int layer_project_chunks(int ncols);
+// factor-only inverse: X[r][j] = 1 for atom j < n of electrode r < n_e (rows
+// x npad), and from Y = G^T A^-1 (rows a < n_e, stride ldy): u = A^-1 e,
+// s = e^T u and the response S G (npad x n_e, row-major)
+void launch_group_indicator(hipStream_t st, int n, int npad, int rows, const int* eid, int n_e,
+                            double* X);
+void launch_factor_response(hipStream_t st, int n, int npad, int n_e, const double* Y, int ldy,
+                            double* u, double* s, double* sg);
 void launch_pair_table(hipStream_t st, double alpha, double eta, double rc, double* tab);
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
                          const Buffers& b, int nmap, const double4* cq, const double2* zr,

@@ -664,6 +664,62 @@ void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldq
                      n_e, q, ldq, Qe);
 }
 
+
+// ---------------------------------------------------------------------------
+// Inverse kept as the Cholesky factor (the solves are GEMMs with the factor's
+// panels, driven from the host).  Electrode indicators as right-hand-side
+// rows, and the quantities of Eqs. 4 and 6 from their solutions
+// Y_a = g_a^T A^-1 (A symmetric): u = A^-1 e = sum_a Y_a^T (every atom is in
+// one electrode), s = e^T u, and S g_a = Y_a^T - u (e^T Y_a^T) / s, since
+// u^T g_a = e^T A^-1 g_a.  One workgroup; every sum in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ void k_group_indicator(int n, int npad, int rows, const int* __restrict__ eid, int n_e,
+                                  double* __restrict__ X) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)rows * npad) return;
+  const int r = (int)(e / npad), j = (int)(e % npad);
+  X[e] = (r < n_e && j < n && eid[j] == r) ? 1.0 : 0.0;
+}
+
+void launch_group_indicator(hipStream_t st, int n, int npad, int rows, const int* eid, int n_e,
+                            double* X) {
+  const size_t tot = (size_t)rows * npad;
+  hipLaunchKernelGGL(k_group_indicator, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n,
+                     npad, rows, eid, n_e, X);
+}
+
+__global__ void __launch_bounds__(1024) k_factor_response(int n, int npad, int n_e,
+                                                          const double* __restrict__ Y, int ldy,
+                                                          double* __restrict__ u,
+                                                          double* __restrict__ s_out,
+                                                          double* __restrict__ sg) {
+  __shared__ double sh[16];
+  __shared__ double tot[CCM_MAXE];
+  for (int a = 0; a < n_e; ++a) {
+    double t = 0.0;
+    for (int i = threadIdx.x; i < n; i += 1024) t += Y[(size_t)a * ldy + i];
+    t = block_sum1024(t, sh);
+    if (threadIdx.x == 0) tot[a] = t;
+  }
+  __syncthreads();
+  double s = 0.0;
+  for (int a = 0; a < n_e; ++a) s += tot[a];           // e^T u
+  for (int i = threadIdx.x; i < npad; i += 1024) {
+    double ui = 0.0;
+    if (i < n)
+      for (int a = 0; a < n_e; ++a) ui += Y[(size_t)a * ldy + i];
+    u[i] = ui;
+    for (int a = 0; a < n_e; ++a)
+      sg[(size_t)i * n_e + a] = i < n ? Y[(size_t)a * ldy + i] - ui * (tot[a] / s) : 0.0;
+  }
+  if (threadIdx.x == 0) *s_out = s;
+}
+
+void launch_factor_response(hipStream_t st, int n, int npad, int n_e, const double* Y, int ldy,
+                            double* u, double* s, double* sg) {
+  hipLaunchKernelGGL(k_factor_response, dim3(1), dim3(1024), 0, st, n, npad, n_e, Y, ldy, u, s, sg);
+}
+
 // ---------------------------------------------------------------------------
 // Row sums of a symmetric npad x npad matrix over each electrode's columns,
 // U = M G (npad x n_e, row-major; rows i >= n are zero), in one pass over M:
