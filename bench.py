@@ -368,9 +368,11 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
 def run_mixed(args):
     """Eight capacitors of uneven size (N from U{2000..20000}, snapped to whole
     graphene cells; electrolyte 10 N water charges + 1 M ions), 128
-    configurations each: per step every A is assembled and inverted, b is
-    computed per instance, and all instances are solved by cpm_solve_grouped
-    (split-BF16, refined) in one persistent launch per S~ product."""
+    configurations each: per step every A is assembled and inverted (on the
+    context's second stream, beside the b of the instances), b is computed
+    per instance (FP32, from the FP32 structure factors), and all instances
+    are solved by cpm_solve_grouped (split-BF16, refined) in one persistent
+    launch per S~ product."""
     import numpy as np
     import torch
     from paper_2203_15461_amd import cpm
@@ -388,7 +390,7 @@ def run_mixed(args):
         xyz = synthetic_configurations(w, B, I.BASE_SEED + 1 + k, dev)
         R = torch.as_tensor(w.electrode_xyz, dtype=torch.float64, device=dev).contiguous()
         eid = torch.as_tensor(w.electrode_id, dtype=torch.int32, device=dev).contiguous()
-        data.append((xyz, R, eid, torch.empty((B, w.n), dtype=torch.float64, device=dev),
+        data.append((xyz, R, eid, torch.empty((B, w.n), dtype=torch.float32, device=dev),
                      torch.empty((B, w.n), dtype=torch.float64, device=dev)))
         ctxs.append(c)
     torch.cuda.synchronize()
@@ -399,9 +401,9 @@ def run_mixed(args):
         with torch.cuda.stream(s):
             for c, w, (xyz, R, eid, b, q) in zip(ctxs, ws, data):
                 c.build_elastance(R, eid, 2)
-                c.invert(1 | 4)
-                c.set_potential(w.v_electrode)
+                c.invert(1 | 4 | cpm.INVERT_ASYNC)
                 c.potential_vector(xyz, b)
+                c.set_potential(w.v_electrode)
             cpm.solve_grouped(ctxs, [d[3] for d in data], 0x102, [d[4] for d in data])
 
     for i in range(args.warmup):
@@ -422,7 +424,8 @@ def run_mixed(args):
             "value": nconf * args.steps / elapsed, "unit": "solves/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-            "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3+f64-refine",
+            "scaling": "weak", "vs_baseline": None,
+            "dtype": "b f32, S bf16x3 (f32 accumulation), f64 refine",
             "data": "synthetic",
             "config": {"workload": "mixed8", "n_elec": [w.n for w in ws],
                        "m_elyt": [w.m for w in ws], "snapshots_per_step_per_instance": B,

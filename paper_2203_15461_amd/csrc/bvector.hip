@@ -20,6 +20,7 @@
 // order, so results are bitwise reproducible.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 
 #include "cpm_internal.h"
 
@@ -1492,13 +1493,19 @@ void pair_poly_table(double alpha, double eta, double rc, std::vector<double>& t
     }
     for (int j = 0; j <= D; ++j)
       for (int p = 0; p <= D; ++p) b[p] += c[j] * T[j][p];
-    double* rec = tab.data() + (size_t)k * RP_REC;
+    // coefficients of (s - s_mid)^p: p <= 3 in FP64, p >= 4 in FP32 (those
+    // terms stay below 2e-7 of g, so FP32 adds < 1e-14 of g); 48 bytes per
+    // interval, so the intervals of a wave's lanes spread over the LDS banks
+    double a[D + 1];
     double scale = 1.0;
     for (int p = 0; p <= D; ++p) {
-      rec[p] = b[p] / scale;                         // coefficient of (s - s_mid)^p
+      a[p] = b[p] / scale;
       scale *= hw;
     }
-    rec[RP_REC - 1] = smid;
+    double* rec = tab.data() + (size_t)k * RP_REC;
+    for (int p = 0; p < 4; ++p) rec[p] = a[p];
+    const float hi[4] = {(float)a[4], (float)a[5], (float)a[6], 0.0f};
+    std::memcpy(rec + 4, hi, sizeof hi);
   }
 }
 
@@ -1568,6 +1575,7 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 4) k_real_space_plane(
   const double marg = 4e-6 * M * M;
   RpWave& W = s_w[wave];
   const float inv_hf = (float)(RP_N / rc);
+  const double hh = (rc / RP_N) * (rc / RP_N);   // s_mid of interval k: hh (k (k + 1) + 1/2)
   const int nblk = chunk < nbt ? (nbt - chunk + rchunks - 1) / rchunks : 0;
   const int s0 = blockIdx.z, sstep = gridDim.z;
   const int nloc = s0 < g ? (g - s0 + sstep - 1) / sstep : 0;
@@ -1615,10 +1623,16 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 4) k_real_space_plane(
         const float rf = __builtin_amdgcn_sqrtf((float)sv);   // picks the interval only
         const int k = min((int)(rf * inv_hf), RP_N - 1);
         const double* T = s_tab + k * RP_REC;
-        const double x = sv - T[RP_REC - 1];
-        double p = T[RP_DEG];
-#pragma unroll
-        for (int j = RP_DEG - 1; j >= 0; --j) p = fma(p, x, T[j]);
+        const double2 c01 = *reinterpret_cast<const double2*>(T);
+        const double2 c23 = *reinterpret_cast<const double2*>(T + 2);
+        const float4 c46 = *reinterpret_cast<const float4*>(T + 4);
+        const double x = sv - hh * ((double)k * (double)(k + 1) + 0.5);   // s - s_mid
+        const float xf = (float)x;
+        const float th = fmaf(fmaf(c46.z, xf, c46.y), xf, c46.x);       // a6 x^2 + a5 x + a4
+        double p = fma((double)th, x, c23.y);
+        p = fma(p, x, c23.x);
+        p = fma(p, x, c01.y);
+        p = fma(p, x, c01.x);
         acc = fma(sv < rc2 ? e.w : 0.0, p, acc);
       }
     }

@@ -44,7 +44,7 @@ inline int sf_mfma_chunk(int mpad, int mchunks) {
 constexpr int RS_NT = 2048;        // intervals of the real-space pair table on [0, rc]
 constexpr int RP_N = 512;          // intervals of the planar pair polynomials on [0, rc]
 constexpr int RP_DEG = 6;          // their degree in s = r^2
-constexpr int RP_REC = 8;          // doubles per interval: coefficients, then s_mid
+constexpr int RP_REC = 6;          // 8-byte words per interval: a0..a3 FP64, a4..a6 FP32 (48 B)
 
 constexpr int PJ_MAXK = 1024;      // weighted k values staged per projection chunk
 constexpr int MAX_LAYERS = 64;     // planar-electrode factorisation up to this many z planes
