@@ -536,6 +536,7 @@ void precond_apply(cpm_ctx* c, int parity, const double* R, double* Z) {
 cpm_status ensure_step_buffers(cpm_ctx* c) {
   Buffers& b = c->b;
   if (c->step_ready) return CPM_OK;
+  c->zperm_ok = false;
   // chunking of the per-snapshot sums (fixed per context, so results are
   // reproducible): ~512 workgroups per kernel, >= 64 charges per SF chunk,
   // >= 32 charges per real-space chunk
@@ -760,6 +761,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_SFM_MAX_CHUNK")) c->sfm_max_chunk = std::max(64, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_PV_FAST_MIN")) c->pv_fast_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_COARSE")) c->pc_k = std::atoi(ev) >= 3 ? 3 : 1;
   if (const char* ev = std::getenv("CPM_CG_GRAPH")) c->cg_graphs = std::atoi(ev) != 0;
@@ -1707,21 +1709,24 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   // electrodes then take the grouped path (pv_group configurations per
   // launch, k_z folded into the planes, projection fused into the combine)
   const bool mfma = c->sf_mfma && c->use_sf_mfma;
-  const bool fast = mfma && c->nlayers > 0;
+  const bool fast = mfma && c->nlayers > 0 && batch >= c->pv_fast_min;
   // b stored in FP32 (the reduced-precision solve path): structure factors on
   // FP32 matrix cores, FP32 phase tables (switch: CPM_SF_FP32=0)
   const int sf32 = (b_is_f32 && c->sf32_ok) ? 1 : 0;
   const int G = fast ? c->pv_group : 1;
   const int mpad64 = std::max(64, (m + 63) / 64 * 64);
-  // large batches: the charges ordered by z (from the first configuration)
-  // for the real-space pass, so that whole blocks fall outside the planes'
-  // windows
+  // the charges ordered by z (from the first configuration of a large
+  // batch) for the real-space pass, so that whole blocks fall outside the
+  // planes' windows; small batches (a single configuration per MD step)
+  // reuse the last order: the block z ranges come from the actual positions,
+  // so an order that has aged only costs skipped blocks, never a pair
   const int* perm = nullptr;
-  if (m > 0 && batch >= c->rs_sort_min) {
+  if (m > 0 && (batch >= c->rs_sort_min || !c->zperm_ok)) {
     Timed t(c, "zsort");
     launch_zsort(st, m, d_xyz, c->Lz, zsort_bins(c->Lz), b.zperm);
-    perm = b.zperm;
+    c->zperm_ok = true;
   }
+  if (m > 0 && c->zperm_ok) perm = b.zperm;
   for (int s0 = 0; s0 < batch; s0 += G) {
     const int g = std::min(G, batch - s0);
     const double* xyz = d_xyz ? d_xyz + (size_t)s0 * m * 3 : nullptr;

@@ -288,6 +288,8 @@ struct cpm_ctx {
   std::vector<int> h_bdiag;        // real-space block of each tile's diagonal (-1: none)
   int rs_wg_target = 0;            // real-space workgroups per launch group (0: by size)
   int rs_sort_min = 16;            // batches of at least this size sort the charges by z
+  bool zperm_ok = false;           // b.zperm holds an order of the charges by z
+  int pv_fast_min = 1;             // batches from this size take the grouped b path
   unsigned store = 0;
   uint64_t geom_hash = 0;          // fingerprint of A's inputs (cpm_save / cpm_load)
   int field_bottom = -1;           // bottom electrode of the zeta in b.zeta
