@@ -762,6 +762,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_PV_FAST_MIN")) c->pv_fast_min = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_RS_CONCURRENT")) c->rs_conc_ok = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_COARSE")) c->pc_k = std::atoi(ev) >= 3 ? 3 : 1;
   if (const char* ev = std::getenv("CPM_CG_GRAPH")) c->cg_graphs = std::atoi(ev) != 0;
@@ -1687,6 +1688,16 @@ cpm_status cpm_set_potential_atoms(cpm_ctx* c, const double* h_v) {
 namespace {
 
 // validation and (first-use) allocation for cpm_potential_vector
+// the real-space stream and its two events, created on first use (default
+// priority, like every stream of the library)
+cpm_status ensure_rs_stream(cpm_ctx* c) {
+  if (c->rs_stream) return CPM_OK;
+  HIP_TRY(c, hipStreamCreateWithFlags(&c->rs_stream, hipStreamNonBlocking));
+  HIP_TRY(c, hipEventCreateWithFlags(&c->rs_ev_in, hipEventDisableTiming));
+  HIP_TRY(c, hipEventCreateWithFlags(&c->rs_ev_out, hipEventDisableTiming));
+  return CPM_OK;
+}
+
 cpm_status pv_prepare(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int b_is_f32) {
   if (!(c->have_A || c->have_op) || !c->have_elyt)
     return fail(c, CPM_ESTATE, "cpm_potential_vector needs cpm_set_electrolyte and cpm_build_elastance");
@@ -1695,6 +1706,7 @@ cpm_status pv_prepare(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   if (b_is_f32 != 0 && b_is_f32 != 1) return fail(c, CPM_EINVAL, "b_is_f32 must be 0 or 1");
   TRY(ensure_uploaded(c));
   TRY(ensure_step_buffers(c));
+  if (c->rs_conc_ok) TRY(ensure_rs_stream(c));
   return CPM_OK;
 }
 
@@ -1737,6 +1749,23 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
     }
     const int nch = mfma ? sf_chunks_for(c, g) : 0;
     const int rch = fast ? rchunks_for(c, g) : c->rchunks;
+    // grouped path: the real-space pass runs on its own stream beside the
+    // structure factors (VALU/LDS-bound beside MFMA-bound work); it starts
+    // after everything enqueued so far (the previous group's final sum,
+    // which read its partials) and the final sum of this group waits for it
+    const bool conc = fast && c->rs_stream && !c->capturing;
+    hipStream_t rst = st;
+    if (conc) {
+      HIP_TRY(c, hipEventRecord(c->rs_ev_in, st));
+      HIP_TRY(c, hipStreamWaitEvent(c->rs_stream, c->rs_ev_in, 0));
+      rst = c->rs_stream;
+    }
+    { Timed t(c, "real_space_b", rst);
+      launch_gather_charges(rst, g, m, mpad64, perm, xyz, b.elq, p.Lx, p.Ly, b.cq, b.zr);
+      launch_b_real_space(rst, g, n, m, mpad64, rch, b, c->nmap, b.cq, b.zr, p.Lx, p.Ly, c->Lz,
+                          p.rcut, b.phir_part, fast ? rs_target(c) : 512,
+                          rs_plane(c) ? b.ptab : nullptr); }
+    if (conc) HIP_TRY(c, hipEventRecord(c->rs_ev_out, rst));
     { Timed t(c, "dipole");
       launch_b_elyt_dipole(st, g, m, xyz, b.elq, b.dip); }
     if (mfma) {
@@ -1754,11 +1783,6 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
       { Timed t(c, "sf_reduce");
         launch_b_sf_reduce(st, c->nk, c->mchunks, b.sf_part, b.w2, b.sfw); }
     }
-    { Timed t(c, "real_space_b");
-      launch_gather_charges(st, g, m, mpad64, perm, xyz, b.elq, p.Lx, p.Ly, b.cq, b.zr);
-      launch_b_real_space(st, g, n, m, mpad64, rch, b, c->nmap, b.cq, b.zr, p.Lx, p.Ly, c->Lz,
-                          p.rcut, b.phir_part, fast ? rs_target(c) : 512,
-                          rs_plane(c) ? b.ptab : nullptr); }
     if (fast) {
       { Timed t(c, "sf_reduce");
         launch_b_sf_layer_reduce(st, g, c->ncolsort, nch, c->sfm_pchunk, c->nlayers,
@@ -1768,6 +1792,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
       { Timed t(c, "projection");
         launch_cg_tiles(st, c->b_nitems, c->nmap, c->ncp, b.b_items, b.Ecat, b.bT, nullptr,
                         nullptr, nullptr, b.bPhi); }
+      if (conc) HIP_TRY(c, hipStreamWaitEvent(st, c->rs_ev_out, 0));
       { Timed t(c, "combine");
         launch_b_final(st, g, n, c->nmap, c->b_nparts, b.slot_of, b.bPhi, b.phir_part,
                        rch, b, b.dip, c->dip_blocks, c->cdip, c->ke, out, b_is_f32); }
@@ -2076,7 +2101,9 @@ cpm_status cpm_capture_step(cpm_ctx* c, int batch, const double* d_xyz, void* d_
   const bool timing = c->timing;
   c->timing = false;                               // no event nodes in the graph
   HIP_TRY(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  c->capturing = true;                             // one stream in the graph
   cpm_status st = pv_enqueue(c, batch, d_xyz, d_b, b_is_f32);
+  c->capturing = false;
   if (st == CPM_OK) st = sc_enqueue(c, batch, d_b, b_is_f32, mode, d_q, d_Qe, ctx_work(c));
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->stream, &g);
@@ -2796,6 +2823,9 @@ void cpm_destroy(cpm_ctx* c) {
   (void)wait_invert(c);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   if (c->aux_ev) (void)hipEventDestroy(c->aux_ev);
+  if (c->rs_stream) (void)hipStreamDestroy(c->rs_stream);
+  if (c->rs_ev_in) (void)hipEventDestroy(c->rs_ev_in);
+  if (c->rs_ev_out) (void)hipEventDestroy(c->rs_ev_out);
   if (c->main_ev) (void)hipEventDestroy(c->main_ev);
   if (c->h_async) (void)hipHostFree(c->h_async);
   Buffers& b = c->b;

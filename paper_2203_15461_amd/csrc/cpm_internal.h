@@ -250,6 +250,12 @@ struct cpm_ctx {
   // host words for s and the pivot flag; joined by the first consumer
   hipStream_t aux = nullptr;
   hipEvent_t aux_ev = nullptr, main_ev = nullptr;
+  // real-space pass of cpm_potential_vector on a stream of its own, beside
+  // the structure factors (events: inputs ready, real space done)
+  hipStream_t rs_stream = nullptr;
+  hipEvent_t rs_ev_in = nullptr, rs_ev_out = nullptr;
+  bool rs_conc_ok = true;          // CPM_RS_CONCURRENT=0 keeps it on the context stream
+  bool capturing = false;          // inside cpm_capture_step (one stream only)
   struct AsyncWords { double s; int flag; };
   AsyncWords* h_async = nullptr;
   bool inv_pending = false, inv_failed = false;
