@@ -418,6 +418,18 @@ def run_mixed(args):
     elapsed = time.perf_counter() - t_start
     qsum = max(float(d[4].sum(dim=1).abs().max().item()) for d in data)
     nconf = 8 * B
+    # b of all instances and the grouped solve as one captured graph, replayed
+    # (A and S kept from the last step: the fixed-electrode case)
+    cpm.capture_grouped(ctxs, [d[0] for d in data], [d[3] for d in data], 0x102,
+                        [d[4] for d in data])
+    cpm.replay_grouped(ctxs)
+    s.synchronize()
+    reps = 3
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        cpm.replay_grouped(ctxs)
+    s.synchronize()
+    replay_rate = nconf * reps / (time.perf_counter() - t0)
     for c in ctxs:
         c.close()
     return {"metric": "charge solves/sec (8 capacitors, N_elec 2000-20000)",
@@ -426,6 +438,8 @@ def run_mixed(args):
             "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None,
             "dtype": "b f32, S bf16x3 (f32 accumulation), f64 refine",
+            "graph_replay_rate": replay_rate,
+            "graph_replay": "b of all instances + grouped split-BF16 solve replayed from one HIP graph, A and S fixed",
             "data": "synthetic",
             "config": {"workload": "mixed8", "n_elec": [w.n for w in ws],
                        "m_elyt": [w.m for w in ws], "snapshots_per_step_per_instance": B,

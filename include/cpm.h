@@ -372,6 +372,30 @@ cpm_status cpm_capture_step(cpm_ctx* ctx, int batch, const double* d_xyz, void* 
  * capture again in that case. */
 cpm_status cpm_replay_step(cpm_ctx* ctx);
 
+/* The grouped step of several contexts (electrodes of uneven size, Sec. II.B
+ * and the batched solve of cpm_solve_grouped) as one HIP graph:
+ * cpm_potential_vector of every context (ctxs[i]: batch[i] configurations
+ * d_xyz[i] into d_b[i]), then cpm_solve_grouped over all of them (split-BF16
+ * mode 0x2 or 0x102), captured from the stream the contexts share (not the
+ * default stream).  Every context needs its inverse with the split-BF16
+ * copy of S and its potential set; work buffers are allocated before
+ * capture, the graph holds kernel launches only and is kept by ctxs[0],
+ * replacing its earlier grouped capture.  Nothing runs until
+ * cpm_replay_grouped. */
+cpm_status cpm_capture_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
+                               const double* const* d_xyz, void* const* d_b, int b_is_f32,
+                               unsigned mode, double* const* d_q, double* const* d_Qe);
+
+/* Launch the graph of cpm_capture_grouped on the shared stream
+ * (asynchronous); ctxs must list the captured contexts in the captured
+ * order (CPM_EINVAL otherwise).  As for cpm_replay_step: new coordinates go
+ * into the captured d_xyz buffers, stream-ordered before the replay, and
+ * cpm_set_potential or a same-size cpm_invert between replays are seen; a
+ * context that allocated or freed device memory since the capture, lost its
+ * split-BF16 copy of S or holds only the factor makes the call return
+ * CPM_ESTATE without launching. */
+cpm_status cpm_replay_grouped(cpm_ctx* const* ctxs, int n_ctx);
+
 /* State files: the `write_mat` / `write_inv` and `read_mat` / `read_inv`
  * keywords of Sec. S-I.A.  cpm_save writes A and, after cpm_invert, A^-1
  * (n x n row-major FP64 each) with a 256-byte header holding n, n_e, the

@@ -32,7 +32,7 @@ INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, n
 EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
            "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",
            "cpm_copy_vector", "cpm_capture_step", "cpm_replay_step", "cpm_autotune",
-           "cpm_solve_grouped", "cpm_set_charge", "cpm_set_potential_atoms", "cpm_build_operator",
+           "cpm_solve_grouped", "cpm_capture_grouped", "cpm_replay_grouped", "cpm_set_charge", "cpm_set_potential_atoms", "cpm_build_operator",
            "cpm_apply_elastance", "cpm_solve_cg", "cpm_get_info",
            "cpm_enable_timing", "cpm_get_timing", "cpm_set_field", "cpm_save", "cpm_load",
            "cpm_inspect_file", "cpm_solve_charges_noalloc",
@@ -94,6 +94,9 @@ def lib(path: str | None = None) -> ctypes.CDLL:
         "cpm_set_potential_atoms": ([vp, ctypes.POINTER(d)], i),
         "cpm_solve_grouped": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(vp), i, u,
                                ctypes.POINTER(vp), ctypes.POINTER(vp)], i),
+        "cpm_capture_grouped": ([ctypes.POINTER(vp), i, ctypes.POINTER(i), ctypes.POINTER(vp),
+                                 ctypes.POINTER(vp), i, u, ctypes.POINTER(vp), ctypes.POINTER(vp)], i),
+        "cpm_replay_grouped": ([ctypes.POINTER(vp), i], i),
         "cpm_copy_vector": ([vp, i, vp], i),
         "cpm_get_info": ([vp, i, ctypes.POINTER(d)], i),
         "cpm_enable_timing": ([vp, ctypes.c_char_p], i),
@@ -440,6 +443,57 @@ def solve_grouped(ctxs, bs, mode: int, qs, Qes=None):
     if st != OK:
         raise CpmError(st, "cpm_solve_grouped: " + lib().cpm_last_error(ctxs[0]._h).decode(errors="replace"))
     return qs
+
+
+def _group_args(ctxs, bs, qs, Qes):
+    """Shared checks and ctypes arrays of the grouped calls."""
+    k = len(ctxs)
+    if not (len(bs) == len(qs) == k) or (Qes is not None and len(Qes) != k):
+        raise ValueError("one b, q (and Qe) per context")
+    f32 = {_is_f32(b) for b in bs}
+    if len(f32) != 1:
+        raise ValueError("all b must have the same dtype")
+    for c, b, q, i in zip(ctxs, bs, qs, range(k)):
+        _expect(q, "float64", 2)
+        n, ne = int(c.info("n")), int(c.info("ne"))
+        if b.dim() != 2 or tuple(b.shape) != tuple(q.shape) or b.shape[1] != n:
+            raise ValueError(f"context {i}: b and q must both be (batch, {n})")
+        if Qes is not None and Qes[i] is not None:
+            _expect(Qes[i], "float64", 2)
+            if tuple(Qes[i].shape) != (b.shape[0], ne):
+                raise ValueError(f"context {i}: Qe must be (batch, {ne})")
+    vp = ctypes.c_void_p
+    H = (vp * k)(*[c._h.value for c in ctxs])
+    Bt = (ctypes.c_int * k)(*[b.shape[0] for b in bs])
+    Bp = (vp * k)(*[_ptr(b) for b in bs])
+    Qp = (vp * k)(*[_ptr(q) for q in qs])
+    Ep = (vp * k)(*[_ptr(e) for e in Qes]) if Qes is not None else None
+    return k, H, Bt, Bp, f32.pop(), Qp, Ep
+
+
+def capture_grouped(ctxs, xyzs, bs, mode: int, qs, Qes=None):
+    """cpm_capture_grouped: b of every context and their grouped solve as one
+    HIP graph (contexts sharing one non-default stream); xyzs[i]
+    (batch_i, m_i, 3) float64, bs/qs/Qes as for solve_grouped."""
+    if len(xyzs) != len(ctxs):
+        raise ValueError("one coordinate tensor per context")
+    for c, x, b, i in zip(ctxs, xyzs, bs, range(len(ctxs))):
+        _expect(x, "float64", 3)
+        if tuple(x.shape) != (b.shape[0], int(c.info("m")), 3):
+            raise ValueError(f"context {i}: xyz must be (batch, m, 3)")
+    k, H, Bt, Bp, f32, Qp, Ep = _group_args(ctxs, bs, qs, Qes)
+    Xp = (ctypes.c_void_p * k)(*[_ptr(x) for x in xyzs])
+    st = lib().cpm_capture_grouped(H, k, Bt, Xp, Bp, f32, mode, Qp, Ep)
+    if st != OK:
+        raise CpmError(st, "cpm_capture_grouped: " + lib().cpm_last_error(ctxs[0]._h).decode(errors="replace"))
+
+
+def replay_grouped(ctxs):
+    """cpm_replay_grouped: launch the captured grouped step (asynchronous)."""
+    H = (ctypes.c_void_p * len(ctxs))(*[c._h.value for c in ctxs])
+    st = lib().cpm_replay_grouped(H, len(ctxs))
+    if st != OK:
+        raise CpmError(st, "cpm_replay_grouped: " + lib().cpm_last_error(ctxs[0]._h).decode(errors="replace"))
 
 
 def _expect(t, dtype: str, ndim: int):

@@ -250,6 +250,55 @@ __global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int
   }
 }
 
+// FP32 tables (b stored in FP32): one thread per (charge, row family,
+// configuration) forms the family's entries as powers of its first phase in
+// FP64 (complex products: a few 1e-15 relative after 30 powers, far below the
+// FP32 rounding of each entry) instead of a sincospi per entry.  Families: X
+// (n_x = 0..nxm), q Y (n_y = -nym..nym: powers and their conjugates), Z1
+// (n = 0..7), Z8 (8 n, n = 0..nbz-1) with the zero row.
+__global__ void __launch_bounds__(256) k_sf_tables32(int m, int mpad, int nxm, int nym, int nbz,
+                                                     const double* __restrict__ xyz,
+                                                     const double* __restrict__ q, double Lx,
+                                                     double Ly, double Lz, size_t tab_stride,
+                                                     float2* __restrict__ tab) {
+  const int fam = blockIdx.y, snap = blockIdx.z;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= mpad) return;
+  const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
+  xyz += (size_t)snap * m * 3;
+  tab += (size_t)snap * tab_stride + j;
+  const bool live = j < m;
+  double f = 0.0, scale = live ? 1.0 : 0.0;
+  int row0 = 0, count = 0;
+  double step = 1.0;                                 // power of the first phase per row
+  if (fam == 0) {
+    if (live) { f = xyz[3 * j] / Lx; f -= floor(f); }
+    row0 = 0; count = nxm + 1;
+  } else if (fam == 1) {
+    if (live) { f = xyz[3 * j + 1] / Ly; f -= floor(f); scale = q[j]; }
+    row0 = rY + nym; count = nym + 1;                // n_y = 0..nym here, conjugates below
+  } else if (fam == 2) {
+    if (live) { f = xyz[3 * j + 2] / Lz; f -= floor(f); }
+    row0 = rZ1; count = 8;
+  } else {
+    if (live) { f = xyz[3 * j + 2] / Lz; f -= floor(f); }
+    row0 = rZ8; count = nbz; step = 8.0;
+    tab[(size_t)(rZ8 + nbz) * mpad] = make_float2(0.f, 0.f);   // the zero row
+  }
+  double th = step * f;
+  th -= rint(th);
+  double sn, cs;
+  sincospi(2.0 * th, &sn, &cs);
+  double pr = scale, pi = 0.0;                       // scale * phase^0
+  for (int k = 0; k < count; ++k) {
+    tab[(size_t)(row0 + k) * mpad] = make_float2((float)pr, (float)pi);
+    if (fam == 1 && k > 0) tab[(size_t)(row0 - k) * mpad] = make_float2((float)pr, (float)-pi);
+    const double nr = pr * cs - pi * sn, ni = pr * sn + pi * cs;
+    pr = nr;
+    pi = ni;
+  }
+}
+
 int sf_table_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) + 8 + nbz + 1; }
 
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
@@ -259,8 +308,8 @@ void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym
   const int blocks = (mpad + 255) / 256;
   dim3 grid(blocks, rows, g), block(256);
   if (fp32)
-    hipLaunchKernelGGL(k_sf_tables<float2>, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly,
-                       Lz, (size_t)rows * mpad, reinterpret_cast<float2*>(tab));
+    hipLaunchKernelGGL(k_sf_tables32, dim3(blocks, 4, g), block, 0, st, m, mpad, nxm, nym, nbz, xyz,
+                       q, Lx, Ly, Lz, (size_t)rows * mpad, reinterpret_cast<float2*>(tab));
   else
     hipLaunchKernelGGL(k_sf_tables<double2>, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly,
                        Lz, (size_t)rows * mpad, tab);

@@ -2233,9 +2233,14 @@ cpm_status cpm_autotune(cpm_ctx* c, int batch, int reps) {
   return CPM_OK;
 }
 
-cpm_status cpm_solve_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
-                             const void* const* d_b, int b_is_f32, unsigned mode,
-                             double* const* d_q, double* const* d_Qe) {
+}  // extern "C"
+
+namespace {
+
+// validation and (first-use) allocation of a grouped solve
+cpm_status grouped_prepare(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
+                           const void* const* d_b, int b_is_f32, unsigned mode,
+                           double* const* d_q) {
   if (!ctxs || n_ctx <= 0 || !batch || !d_b || !d_q) return CPM_EINVAL;
   cpm_ctx* c0 = ctxs[0];
   if (!c0) return CPM_EINVAL;
@@ -2250,6 +2255,14 @@ cpm_status cpm_solve_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
       if (ctxs[j] == ctxs[i]) return fail(c0, CPM_EINVAL, "context %d appears twice", i);
     TRY(sc_prepare(ctxs[i], batch[i], d_b[i], b_is_f32, mode, d_q[i]));
   }
+  return CPM_OK;
+}
+
+// the launches of a grouped solve (no allocation, copy or memset)
+cpm_status grouped_enqueue(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
+                           const void* const* d_b, int b_is_f32, unsigned mode,
+                           double* const* d_q, double* const* d_Qe) {
+  cpm_ctx* c0 = ctxs[0];
   const bool refine = (mode & CPM_SOLVE_REFINE) != 0;
   hipStream_t st = c0->stream;
   // one persistent launch of S~ products over every context's tiles
@@ -2301,6 +2314,82 @@ cpm_status cpm_solve_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
     }
   }
   return launched(c0, "grouped solve");
+}
+
+}  // namespace
+
+extern "C" {
+
+cpm_status cpm_solve_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
+                             const void* const* d_b, int b_is_f32, unsigned mode,
+                             double* const* d_q, double* const* d_Qe) {
+  if (!ctxs || n_ctx <= 0 || !batch || !d_b || !d_q) return CPM_EINVAL;
+  TRY(grouped_prepare(ctxs, n_ctx, batch, d_b, b_is_f32, mode, d_q));
+  return grouped_enqueue(ctxs, n_ctx, batch, d_b, b_is_f32, mode, d_q, d_Qe);
+}
+
+cpm_status cpm_capture_grouped(cpm_ctx* const* ctxs, int n_ctx, const int* batch,
+                               const double* const* d_xyz, void* const* d_b, int b_is_f32,
+                               unsigned mode, double* const* d_q, double* const* d_Qe) {
+  if (!ctxs || n_ctx <= 0 || !batch || !d_xyz || !d_b || !d_q || !ctxs[0]) return CPM_EINVAL;
+  cpm_ctx* c0 = ctxs[0];
+  if (!c0->stream)
+    return fail(c0, CPM_EINVAL, "graph capture needs a non-default stream for the contexts");
+  for (int i = 0; i < n_ctx; ++i) {
+    if (!ctxs[i]) return fail(c0, CPM_EINVAL, "context %d is NULL", i);
+    TRY(pv_prepare(ctxs[i], batch[i], d_xyz[i], d_b[i], b_is_f32));
+  }
+  TRY(grouped_prepare(ctxs, n_ctx, batch, d_b, b_is_f32, mode, d_q));
+  HIP_TRY(c0, hipStreamSynchronize(c0->stream));
+  if (c0->ggraph_exec) { (void)hipGraphExecDestroy(c0->ggraph_exec); c0->ggraph_exec = nullptr; }
+  if (c0->ggraph) { (void)hipGraphDestroy(c0->ggraph); c0->ggraph = nullptr; }
+  c0->ggroup.clear();
+  std::vector<char> timing(n_ctx);
+  for (int i = 0; i < n_ctx; ++i) {
+    timing[i] = ctxs[i]->timing;
+    ctxs[i]->timing = false;                       // no event nodes in the graph
+    ctxs[i]->capturing = true;                     // one stream in the graph
+  }
+  cpm_status st = CPM_OK;
+  const hipError_t eb = hipStreamBeginCapture(c0->stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) st = fail(c0, CPM_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(eb));
+  for (int i = 0; i < n_ctx && st == CPM_OK && eb == hipSuccess; ++i)
+    st = pv_enqueue(ctxs[i], batch[i], d_xyz[i], d_b[i], b_is_f32);
+  if (st == CPM_OK) st = grouped_enqueue(ctxs, n_ctx, batch, d_b, b_is_f32, mode, d_q, d_Qe);
+  hipGraph_t g = nullptr;
+  const hipError_t e = eb == hipSuccess ? hipStreamEndCapture(c0->stream, &g) : eb;
+  for (int i = 0; i < n_ctx; ++i) {
+    ctxs[i]->timing = timing[i] != 0;
+    ctxs[i]->capturing = false;
+  }
+  if (st != CPM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return fail(c0, CPM_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  c0->ggraph = g;
+  HIP_TRY(c0, hipGraphInstantiate(&c0->ggraph_exec, c0->ggraph, nullptr, nullptr, 0));
+  for (int i = 0; i < n_ctx; ++i) c0->ggroup.push_back({ctxs[i], ctxs[i]->alloc_gen});
+  return CPM_OK;
+}
+
+cpm_status cpm_replay_grouped(cpm_ctx* const* ctxs, int n_ctx) {
+  if (!ctxs || n_ctx <= 0 || !ctxs[0]) return CPM_EINVAL;
+  cpm_ctx* c0 = ctxs[0];
+  if (!c0->ggraph_exec) return fail(c0, CPM_ESTATE, "cpm_replay_grouped before cpm_capture_grouped");
+  if ((int)c0->ggroup.size() != n_ctx)
+    return fail(c0, CPM_EINVAL, "the group differs from the captured one");
+  for (int i = 0; i < n_ctx; ++i) {
+    cpm_ctx* c = ctxs[i];
+    if (c != c0->ggroup[i].first) return fail(c0, CPM_EINVAL, "context %d differs from the capture", i);
+    TRY(finish_invert(c));
+    // the graph holds raw device addresses of every context's buffers
+    if (c->alloc_gen != c0->ggroup[i].second || !c->have_inv || c->factor_only || !c->have_v ||
+        !(c->store & CPM_STORE_BF16X2))
+      return fail(c0, CPM_ESTATE, "context %d changed since cpm_capture_grouped; capture again", i);
+  }
+  HIP_TRY(c0, hipGraphLaunch(c0->ggraph_exec, c0->stream));
+  return CPM_OK;
 }
 
 cpm_status cpm_enable_timing(cpm_ctx* c, const char* families) {
@@ -2823,6 +2912,8 @@ void cpm_destroy(cpm_ctx* c) {
   (void)wait_invert(c);
   if (c->aux) (void)hipStreamDestroy(c->aux);
   if (c->aux_ev) (void)hipEventDestroy(c->aux_ev);
+  if (c->ggraph_exec) (void)hipGraphExecDestroy(c->ggraph_exec);
+  if (c->ggraph) (void)hipGraphDestroy(c->ggraph);
   if (c->rs_stream) (void)hipStreamDestroy(c->rs_stream);
   if (c->rs_ev_in) (void)hipEventDestroy(c->rs_ev_in);
   if (c->rs_ev_out) (void)hipEventDestroy(c->rs_ev_out);

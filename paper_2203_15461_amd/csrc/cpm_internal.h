@@ -344,6 +344,11 @@ struct cpm_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   unsigned long long graph_gen = 0;    // alloc_gen when the graph was captured
+  // graph of a grouped step (cpm_capture_grouped), held by the first context:
+  // the contexts in order with their alloc_gen at capture
+  hipGraph_t ggraph = nullptr;
+  hipGraphExec_t ggraph_exec = nullptr;
+  std::vector<std::pair<cpm_ctx*, unsigned long long>> ggroup;
   // the CG iteration block (8 iterations between convergence checks) as a
   // graph, keyed by the buffers, the tolerance and the preconditioner
   bool cg_graphs = true;

@@ -148,3 +148,59 @@ def test_capture_errors(cpm):
         ctx.capture_step(xyz, b, 0, q)
     assert ei.value.status == cpm.EINVAL
     ctx.close()
+
+
+def test_grouped_replay_matches_eager(cpm):
+    """cpm_capture_grouped / cpm_replay_grouped: b of two capacitors of
+    uneven size (n = 2304 and 3840, the uneven batch's form) and their
+    grouped split-BF16 solve as one graph, replayed with new positions and
+    FP32 b; eager b and grouped solve on the same contexts between replays
+    must give the same b, q and Q bit for bit, and the smaller capacitor's
+    charges of the stored oracle snapshots must match the full oracle run
+    to 1e-5."""
+    import os
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "scaled_graphite_capacitor_2304.npz")
+    ws = [I.scaled_graphite_capacitor(2407), I.scaled_graphite_capacitor(4000)]
+    say(f"grouped graph: n = {[w.n for w in ws]}")
+    s = torch.cuda.Stream()
+    ctxs = [cpm.setup(w, store=1 | 4, stream=s) for w in ws]
+    B = 3
+    with torch.cuda.stream(s):
+        xyz = [torch.empty((B, w.m, 3), dtype=torch.float64, device="cuda") for w in ws]
+        b = [torch.empty((B, w.n), dtype=torch.float32, device="cuda") for w in ws]
+        q = [torch.full((B, w.n), float("nan"), dtype=torch.float64, device="cuda") for w in ws]
+        Qe = [torch.empty((B, 2), dtype=torch.float64, device="cuda") for w in ws]
+        b2 = [torch.empty_like(x) for x in b]
+        q2 = [torch.empty_like(x) for x in q]
+        Qe2 = [torch.empty_like(x) for x in Qe]
+    s.synchronize()
+    cpm.capture_grouped(ctxs, xyz, b, 0x102, q, Qe)
+    assert all(torch.isnan(x).all() for x in q), "capture must not run the step"
+    for r in range(3):
+        with torch.cuda.stream(s):
+            for w, x in zip(ws, xyz):
+                x.copy_(torch.as_tensor(_positions(w, 5 * r, B), dtype=torch.float64))
+        cpm.replay_grouped(ctxs)
+        s.synchronize()
+        got = [(x.cpu().numpy(), y.cpu().numpy(), z.cpu().numpy()) for x, y, z in zip(b, q, Qe)]
+        with torch.cuda.stream(s):
+            for c, x, bb in zip(ctxs, xyz, b2):
+                c.potential_vector(x, bb)
+            cpm.solve_grouped(ctxs, b2, 0x102, q2, Qe2)
+        s.synchronize()
+        for k in range(2):
+            assert np.array_equal(got[k][0], b2[k].cpu().numpy()), f"replay {r}: b of {k} differs"
+            assert np.array_equal(got[k][1], q2[k].cpu().numpy()), f"replay {r}: q of {k} differs"
+            assert np.array_equal(got[k][2], Qe2[k].cpu().numpy()), f"replay {r}: Q of {k} differs"
+        if r == 0 and os.path.exists(golden):
+            g = np.load(golden)
+            snaps = [int(k) for k in g["snapshots"]]
+            assert snaps == list(range(B))
+            e = float(np.abs(got[0][1] - g["q"]).max() / np.abs(g["q"]).max())
+            say(f"  replay 0, n = 2304: q vs oracle {e:.2e}")
+            assert e < 1e-5
+    with pytest.raises(cpm.CpmError):
+        cpm.replay_grouped(ctxs[::-1])
+    for c in ctxs:
+        c.close()
