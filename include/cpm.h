@@ -116,8 +116,10 @@ enum {
                               /*   (0: plain CG)                                  */
   CPM_INFO_PC_MODE = 24,      /*   ... its form: 0 none, 1 additive, 2 balancing  */
   CPM_INFO_PC_COARSE = 25,    /*   ... its coarse-space dimension                 */
-  CPM_INFO_SF_FP32 = 26       /* 1: cpm_potential_vector with b_is_f32 forms the  */
+  CPM_INFO_SF_FP32 = 26,      /* 1: cpm_potential_vector with b_is_f32 forms the  */
                               /* structure factors on FP32 matrix cores           */
+  CPM_INFO_RS_PLANE = 27      /* 1: the real-space part of b runs the planar      */
+                              /* kernel (atoms on z planes, one image within r_c) */
 };
 
 /* Method knobs; they map onto the paper's `fix electrode` keywords and the

@@ -27,7 +27,7 @@ SOLVE_F64, SOLVE_F32, SOLVE_BF16X2, SOLVE_REFINE, SOLVE_CCM = 0, 1, 2, 0x100, 0x
 INFO = dict(n=0, nk=1, ne=2, s_sum=3, pivot=4, lz=5, kcut=6, m=7, workspace=8, npad=9, nruns=10,
             nlayers=11, sf_matrix=12, tune_bm=13, tune_ks=14, tune_grid=15, tune_us=16, group=17,
             cg_iters=18, cg_resid=19, ell_width=20, ncols=21,
-            bsr_blocks=22, pc_tiles=23, pc_mode=24, pc_coarse=25, sf_fp32=26)
+            bsr_blocks=22, pc_tiles=23, pc_mode=24, pc_coarse=25, sf_fp32=26, rs_plane=27)
 
 EXPORTS = ("cpm_create", "cpm_set_electrolyte", "cpm_build_elastance", "cpm_invert",
            "cpm_set_potential", "cpm_potential_vector", "cpm_solve_charges", "cpm_copy_matrix",

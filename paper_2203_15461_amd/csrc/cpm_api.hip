@@ -2890,6 +2890,7 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_PC_COARSE: *out = (double)c->pc_tiles * c->pc_kuse; return CPM_OK;
     case CPM_INFO_SF_FP32:
       *out = (c->sf_mfma && c->use_sf_mfma && c->sf32_ok) ? 1.0 : 0.0; return CPM_OK;
+    case CPM_INFO_RS_PLANE: *out = rs_plane(c) ? 1.0 : 0.0; return CPM_OK;
     default: return CPM_EINVAL;
   }
 }
