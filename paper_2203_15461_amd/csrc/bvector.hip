@@ -299,6 +299,122 @@ __global__ void __launch_bounds__(256) k_sf_tables32(int m, int mpad, int nxm, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// The structure factors for b stored in FP32 on FP16 matrix cores with split
+// operands.  Every operand value a (|a| <= max |q_j|) is carried as a pair of
+// FP16 numbers, a_h = fp16(a) and a_l = fp16((a - a_h) 2^11) (the 2^11 keeps
+// a_l in the normal FP16 range; below 2^-14 a_h may flush and a_l holds a),
+// and a product of two values as
+//   a b ~= a_h b_h + 2^-11 (a_h b_l + a_l b_h),
+// three v_mfma_f32_16x16x32_f16 products into two FP32 accumulators.  Each
+// value is kept to about 2^-22 relative (the dropped a_l b_l term is 2^-22 of
+// the product), close to the FP32 rounding of the tables themselves.
+//
+// Tables of one configuration (float2 rows of mpad entries, then the z
+// operand):
+//   rows [0, nxm]                     X_a(j) = e^{2 pi i a fx_j}
+//   rows nxm+1 + [0, 2 nym]           Y_b(j) = q_j e^{2 pi i (b - nym) fy_j}
+//   next row                          zero (absent columns)
+//   then nbz blocks of 8 mpad float2: the z operand of k_z block bb,
+//     e^{2 pi i (8 bb + n) fz_j} (n = 0..7; column 2n + (0: Re, 1: Im)),
+//     split into FP16 pairs, in matrix-core order: for charge group
+//     jg = j / 8 and part h (0: a_h, 1: a_l) the 16 columns x 8 charges
+//     at halfs ((bb (mpad / 8) + jg) 2 + h) 128 + 8 column + j % 8.
+// ---------------------------------------------------------------------------
+typedef _Float16 v8h_t __attribute__((ext_vector_type(8)));
+
+int sf16_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) + 1 + 8 * nbz; }
+
+constexpr int ZS_ROW = 264;              // halfs per LDS row of the z-operand staging
+
+// the pair of an FP64 value, formed from its FP32 rounding (2^-24 relative,
+// below the 2^-22 of the pair); the clamp to the FP16 range (a no-op here)
+// keeps the compiler from fusing the two roundings into one FP64 -> FP16
+// conversion, which it would expand into integer code
+__device__ inline void split_f16(double v, _Float16& h, _Float16& l) {
+  const float vf = __builtin_amdgcn_fmed3f((float)v, -65504.f, 65504.f);
+  h = (_Float16)vf;
+  l = (_Float16)((vf - (float)h) * 2048.f);
+}
+
+// grid (charge blocks of 256, 2 + nbz, configurations): y = 0 the X rows
+// and the zero row, y = 1 the Y rows, y = 2 + bb the z operand of block bb.
+// Phases are powers of a first one in FP64 (a few 1e-15 relative).
+__global__ void __launch_bounds__(256) k_sf_tables16(int m, int mpad, int nxm, int nym, int nbz,
+                                                     const double* __restrict__ xyz,
+                                                     const double* __restrict__ q, double Lx,
+                                                     double Ly, double Lz, size_t tab_stride,
+                                                     float2* __restrict__ tab) {
+  __shared__ __align__(16) _Float16 zs[32 * ZS_ROW];
+  const int fam = blockIdx.y, snap = blockIdx.z;
+  const int jb = blockIdx.x * 256, jl = threadIdx.x, j = jb + jl;
+  const int rY = nxm + 1, rzero = rY + 2 * nym + 1;
+  xyz += (size_t)snap * m * 3;
+  tab += (size_t)snap * tab_stride;
+  const bool live = j < m;
+  if (fam < 2) {
+    if (j >= mpad) return;
+    double f = 0.0, scale = live ? 1.0 : 0.0;
+    int count;
+    if (fam == 0) {
+      if (live) { f = xyz[3 * j] / Lx; f -= floor(f); }
+      count = nxm + 1;
+      tab[(size_t)rzero * mpad + j] = make_float2(0.f, 0.f);
+    } else {
+      if (live) { f = xyz[3 * j + 1] / Ly; f -= floor(f); scale = q[j]; }
+      count = nym + 1;
+    }
+    double sn, cs;
+    sincospi(2.0 * f, &sn, &cs);
+    double pr = scale, pi = 0.0;
+    for (int k = 0; k < count; ++k) {
+      if (fam == 0) {
+        tab[(size_t)k * mpad + j] = make_float2((float)pr, (float)pi);
+      } else {
+        tab[(size_t)(rY + nym + k) * mpad + j] = make_float2((float)pr, (float)pi);
+        if (k > 0) tab[(size_t)(rY + nym - k) * mpad + j] = make_float2((float)pr, (float)-pi);
+      }
+      const double nr = pr * cs - pi * sn, ni = pr * sn + pi * cs;
+      pr = nr;
+      pi = ni;
+    }
+    return;
+  }
+  // z operand of block bb = fam - 2: staged in LDS as 32 rows (part h,
+  // column) of the block's 256 charges (rows ZS_ROW halfs apart, so the
+  // 16-byte reads of the copy hit distinct banks), then stored as whole
+  // 16-byte runs; every thread stays to the end (block barrier)
+  const int bb = fam - 2;
+  double f = 0.0;
+  if (live) { f = xyz[3 * j + 2] / Lz; f -= floor(f); }
+  double th = 8.0 * bb * f;
+  th -= rint(th);
+  double pr, pi, s1, c1;
+  sincospi(2.0 * th, &pi, &pr);
+  sincospi(2.0 * f, &s1, &c1);
+  if (!live) { pr = 0.0; pi = 0.0; }
+  for (int n = 0; n < 8; ++n) {
+    _Float16 h, l;
+    split_f16(pr, h, l);
+    zs[(2 * n) * ZS_ROW + jl] = h;
+    zs[(16 + 2 * n) * ZS_ROW + jl] = l;
+    split_f16(pi, h, l);
+    zs[(2 * n + 1) * ZS_ROW + jl] = h;
+    zs[(16 + 2 * n + 1) * ZS_ROW + jl] = l;
+    const double nr = pr * c1 - pi * s1, ni = pr * s1 + pi * c1;
+    pr = nr;
+    pi = ni;
+  }
+  __syncthreads();
+  // block bb, charge groups jb/8 ..: per group 32 runs of 16 bytes (part h,
+  // column), the runs of one group contiguous
+  const int nvalid = min(256, mpad - jb);           // a multiple of 64
+  uint4* dst = reinterpret_cast<uint4*>(tab + (size_t)(rzero + 1) * mpad) +
+               ((size_t)bb * (mpad / 8) + jb / 8) * 32;
+  for (int u = jl; u < nvalid * 4; u += 256)
+    dst[u] = *reinterpret_cast<const uint4*>(zs + (u & 31) * ZS_ROW + (u >> 5) * 8);
+}
+
 int sf_table_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) + 8 + nbz + 1; }
 
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
@@ -307,6 +423,12 @@ void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym
   const int rows = sf_table_rows(nxm, nym, nbz);
   const int blocks = (mpad + 255) / 256;
   dim3 grid(blocks, rows, g), block(256);
+  if (fp32 == 2) {
+    hipLaunchKernelGGL(k_sf_tables16, dim3(blocks, 2 + nbz, g), block, 0, st, m, mpad, nxm, nym, nbz,
+                       xyz, q, Lx, Ly, Lz, (size_t)sf16_rows(nxm, nym, nbz) * mpad,
+                       reinterpret_cast<float2*>(tab));
+    return;
+  }
   if (fp32)
     hipLaunchKernelGGL(k_sf_tables32, dim3(blocks, 4, g), block, 0, st, m, mpad, nxm, nym, nbz, xyz,
                        q, Lx, Ly, Lz, (size_t)rows * mpad, reinterpret_cast<float2*>(tab));
@@ -712,14 +834,217 @@ k_sf_mfma32(int mpad, int chunk_size, int nchunks, int nitems, const int4* __res
   }
 }
 
+// One work item (M tile of 16 columns, nbw <= SF16_NB blocks of 8 n) over
+// one chunk of charges, in tiles of 32 charges (one matrix-core k step).  Per
+// tile the four waves form the A operand together (wave w: charges 8w..8w+7,
+// lane l: column l & 15 and two charges; Re C to row 2c, Im C to row 2c+1,
+// split in FP32) into a double-buffered LDS area, one barrier, then each
+// wave runs the products of its own blocks w, w + 4, w + 8 (the B operand
+// read pre-split from the z operand, the next tile's entries in flight).
+// Sums stay in FP32 over the chunk (at most a few thousand charges: tiles of
+// 32 are summed inside the matrix core, the error grows as the square root
+// of the tiles) and go to FP64 at the store.
+constexpr int SF16_ROW = 40;             // halfs per LDS row of A (32 charges + pad)
+
+// One wave's part: KW of the item's blocks (blk0 + 4k) for its NT M tiles
+// (the B operand of a block serves them all); every wave forms its share of
+// A and meets the one barrier per tile, whatever its KW.  Tiles go in pairs
+// (chunks are multiples of 64 charges) with two register sets for the B
+// operand, so each tile's loads are issued a tile ahead and no copy between
+// the sets makes them complete early; the last pair loads itself again
+// instead of testing.
+template <int KW, int NT>
+__device__ void sf_wave16(_Float16 (*As)[NT][2][32][SF16_ROW], const float2* __restrict__ tab,
+                          const v8h_t* __restrict__ zop, int mpad, int j0, int j1,
+                          const int (&xrow)[NT], const int (&yrow)[NT], double* const (&out)[NT],
+                          const int (&ldc)[NT], const int (&nbt)[NT], int blk0) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int i_l = lane & 15, g_l = lane >> 4;
+  constexpr int K = KW > 0 ? KW : 1;
+  v4f_t fh[NT][2][K], fl[NT][2][K];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        fh[t][rb][k] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+        fl[t][rb][k] = (v4f_t){0.f, 0.f, 0.f, 0.f};
+      }
+  // A share: column i_l of every M tile, charges c0, c0 + 1 of the tile
+  const int c0 = 8 * wave + 2 * g_l;
+  const float4* xp[NT];
+  const float4* yp[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    xp[t] = reinterpret_cast<const float4*>(tab + xrow[t] + c0);
+    yp[t] = reinterpret_cast<const float4*>(tab + yrow[t] + c0);
+  }
+  // B: block blk0 + 4k, charge group (jt >> 3) + g_l, column i_l (v8h units)
+  const v8h_t* zp = zop + ((size_t)blk0 * (mpad / 8) + g_l) * 32 + i_l;
+  const size_t zstep = (size_t)(mpad / 8) * 32 * 4;
+  typedef _Float16 v2h_t __attribute__((ext_vector_type(2)));
+  float4 xv[NT], yv[NT];
+  auto load_a = [&](int jt) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      xv[t] = xp[t][jt / 2];
+      yv[t] = yp[t][jt / 2];
+    }
+  };
+  // A share of the tile whose operands are in xv, yv into LDS buffer buf
+  auto form_a = [&](int buf) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t) {
+      const float4 x = xv[t], y = yv[t];
+      const float r0 = x.x * y.x - x.y * y.y, i0 = x.x * y.y + x.y * y.x;
+      const float r1 = x.z * y.z - x.w * y.w, i1 = x.z * y.w + x.w * y.z;
+      const _Float16 hr0 = (_Float16)r0, hr1 = (_Float16)r1, hi0 = (_Float16)i0, hi1 = (_Float16)i1;
+      *reinterpret_cast<v2h_t*>(&As[buf][t][0][2 * i_l][c0]) = (v2h_t){hr0, hr1};
+      *reinterpret_cast<v2h_t*>(&As[buf][t][1][2 * i_l][c0]) =
+          (v2h_t){(_Float16)((r0 - (float)hr0) * 2048.f), (_Float16)((r1 - (float)hr1) * 2048.f)};
+      *reinterpret_cast<v2h_t*>(&As[buf][t][0][2 * i_l + 1][c0]) = (v2h_t){hi0, hi1};
+      *reinterpret_cast<v2h_t*>(&As[buf][t][1][2 * i_l + 1][c0]) =
+          (v2h_t){(_Float16)((i0 - (float)hi0) * 2048.f), (_Float16)((i1 - (float)hi1) * 2048.f)};
+    }
+  };
+  auto load_b = [&](v8h_t (&bh)[K], v8h_t (&bl)[K], int jt) {
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      bh[k] = zp[k * zstep + (size_t)(jt >> 3) * 32];
+      bl[k] = zp[k * zstep + (size_t)(jt >> 3) * 32 + 16];
+    }
+  };
+  auto products = [&](int buf, const v8h_t (&bh)[K], const v8h_t (&bl)[K]) {
+#pragma unroll
+    for (int t = 0; t < NT; ++t)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb) {
+        const v8h_t ah = *reinterpret_cast<const v8h_t*>(&As[buf][t][0][16 * rb + i_l][8 * g_l]);
+        const v8h_t al = *reinterpret_cast<const v8h_t*>(&As[buf][t][1][16 * rb + i_l][8 * g_l]);
+#pragma unroll
+        for (int k = 0; k < KW; ++k) {
+          fh[t][rb][k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh[k], fh[t][rb][k], 0, 0, 0);
+          fl[t][rb][k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl[k], fl[t][rb][k], 0, 0, 0);
+          fl[t][rb][k] = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh[k], fl[t][rb][k], 0, 0, 0);
+        }
+      }
+  };
+  v8h_t b0h[K], b0l[K], b1h[K], b1l[K];
+  load_a(j0);
+  load_b(b0h, b0l, j0);
+  for (int jt = j0; jt < j1; jt += 64) {
+    // tile jt (buffer 0, set 0); tile jt + 32 loads ahead
+    form_a(0);
+    load_a(jt + 32);
+    load_b(b1h, b1l, jt + 32);
+    __syncthreads();
+    if (KW > 0) products(0, b0h, b0l);
+    // tile jt + 32 (buffer 1, set 1); the next pair's first tile loads ahead
+    const int jn = min(jt + 64, j1 - 64);
+    form_a(1);
+    load_a(jn);
+    load_b(b0h, b0l, jn);
+    __syncthreads();
+    if (KW > 0) products(1, b1h, b1l);
+  }
+  // result register r of lane l: row 4 (l >> 4) + r, column l & 15; a
+  // tile's blocks past its own extent are dropped
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int k = 0; k < KW; ++k) {
+      if (blk0 + 4 * k >= nbt[t]) continue;
+      const int col = 16 * (blk0 + 4 * k) + i_l;
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          out[t][(16 * rb + 4 * g_l + r) * ldc[t] + col] =
+              (double)fh[t][rb][k][r] + (double)fl[t][rb][k][r] * (1.0 / 2048.0);
+    }
+}
+
+// Items {M tile mt, first block, blocks, M tiles (1 or 2: mt and mt + 1)}.
+template <int NT>
+__device__ void sf_item16(const float2* __restrict__ tab, int mpad, int chunk_size, int nchunks,
+                          int snap, int chunk, int4 it, const int* __restrict__ sc_nx,
+                          const int* __restrict__ sc_ny, int ncolsort, int nxm, int nym,
+                          const int* __restrict__ tile_nb, const int* __restrict__ toff,
+                          int pchunk, double* __restrict__ part,
+                          _Float16 (*As)[NT][2][32][SF16_ROW]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, i_l = lane & 15;
+  const int mt = it.x, nb_lo = it.y, nbw = it.z, nt = it.w;
+  const int rY = nxm + 1, rzero = rY + 2 * nym + 1;
+  // chunk_size and mpad are multiples of 64: every tile pair lies inside [0, mpad)
+  const int j0 = chunk * chunk_size, j1 = min(mpad, j0 + chunk_size);
+  int xrow[NT], yrow[NT], ldc[NT], nbt[NT];
+  double* out[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    // absent tiles and columns read the zero row; an absent tile stores nothing
+    const bool tile = t < nt;
+    const int c_base = (mt + t) * SFM_COLS;
+    const bool ok = tile && i_l < min(SFM_COLS, ncolsort - c_base);
+    xrow[t] = (ok ? sc_nx[c_base + i_l] : rzero) * mpad;
+    yrow[t] = (ok ? rY + sc_ny[c_base + i_l] + nym : rzero) * mpad;
+    ldc[t] = tile ? 16 * tile_nb[mt + t] : 0;
+    nbt[t] = tile ? tile_nb[mt + t] : 0;
+    out[t] = part + ((size_t)snap * nchunks + chunk) * pchunk + (tile ? toff[mt + t] : 0);
+  }
+  if (j0 >= j1) {
+    // an empty chunk: zero partials of this item's blocks
+    for (int t = 0; t < NT; ++t)
+      for (int k = nb_lo + wave; k < min(nb_lo + nbw, nbt[t]); k += 4)
+        for (int e = lane; e < 32 * 16; e += 64) out[t][(e >> 4) * ldc[t] + 16 * k + (e & 15)] = 0.0;
+    return;
+  }
+  const v8h_t* zop = reinterpret_cast<const v8h_t*>(tab + (size_t)(rzero + 1) * mpad);
+  // this wave's blocks: nb_lo + wave + 4k, k < kw (nbw <= SF16_NB = 12)
+  const int kw = wave < nbw ? (nbw - wave + 3) / 4 : 0;
+  const int blk0 = nb_lo + wave;
+  switch (kw) {
+    case 0: sf_wave16<0, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
+    case 1: sf_wave16<1, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
+    case 2: sf_wave16<2, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
+    default: sf_wave16<3, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT == 1 ? 3 : 2)))
+k_sf_mfma16(int mpad, int chunk_size, int nchunks, int nitems, const int4* __restrict__ items,
+            const int* __restrict__ sc_nx, const int* __restrict__ sc_ny, int ncolsort, int nxm,
+            int nym, const float2* __restrict__ tab, size_t tab_stride,
+            const int* __restrict__ tile_nb, const int* __restrict__ toff, int pchunk,
+            double* __restrict__ part) {
+  __shared__ __align__(16) _Float16 As[2][NT][2][32][SF16_ROW];
+  // (configuration, chunk) pairs stay on one XCD, as in the other kernels
+  const int xcd = blockIdx.x & 7, slot = blockIdx.x >> 3;
+  const int item = slot % nitems;
+  const int pair = xcd + 8 * (slot / nitems);
+  const int snap = pair / nchunks, chunk = pair % nchunks;
+  sf_item16<NT>(tab + (size_t)snap * tab_stride, mpad, chunk_size, nchunks, snap, chunk,
+                items[item], sc_nx, sc_ny, ncolsort, nxm, nym, tile_nb, toff, pchunk, part, As);
+}
+
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
-                      double* part, int fp32) {
+                      double* part, int fp32, bool sf16_pair) {
   // nchunks is a multiple of 8 (one residue class of pairs per XCD)
   const int chunk_size = sf_mfma_chunk(mpad, nchunks);
   const size_t tab_stride = (size_t)sf_table_rows(nxm, nym, nbz) * mpad;
   dim3 grid(nitems * nchunks * g), block(256);
+  if (fp32 == 2) {
+    // tile pairs of 64 charges: chunk bounds on multiples of 64 (mpad is one)
+    const int chunk32 = ((mpad + nchunks - 1) / nchunks + 63) / 64 * 64;
+    hipLaunchKernelGGL(sf16_pair ? k_sf_mfma16<2> : k_sf_mfma16<1>, grid, block, 0, st, mpad,
+                       chunk32, nchunks, nitems, items, sc_nx, sc_ny, ncolsort, nxm, nym,
+                       reinterpret_cast<const float2*>(tab), (size_t)sf16_rows(nxm, nym, nbz) * mpad,
+                       tile_nb, toff, pchunk, part);
+    return;
+  }
   if (fp32) {
     hipLaunchKernelGGL(k_sf_mfma32, grid, block, 0, st, mpad, chunk_size, nchunks, nitems, items,
                        sc_nx, sc_ny, ncolsort, nxm, nym, reinterpret_cast<const float2*>(tab),

@@ -230,8 +230,10 @@ void build_kset(cpm_ctx* c, std::vector<KRun>& runs, std::vector<double>& w2,
 // then fit one XCD's L2: large systems), at least sfm_min_chunk (small
 // groups: fewer partials to write and sum), and g * chunks a multiple of 8
 // (the kernel keeps each (configuration, chunk) pair on one XCD)
-int sf_chunks_for(const cpm_ctx* c, int g) {
-  const int by_wg = (c->sfm_wg_target + c->sfm_nitems * g - 1) / (c->sfm_nitems * g);
+int sf_chunks_for(const cpm_ctx* c, int g, bool f16) {
+  const int items = f16 ? c->sf16_nitems : c->sfm_nitems;
+  const int target = f16 ? c->sf16_wg_target : c->sfm_wg_target;
+  const int by_wg = (target + items * g - 1) / (items * g);
   const int by_l2 = (c->m + c->sfm_max_chunk - 1) / c->sfm_max_chunk;
   const int base = std::max(1, std::min(std::max(by_wg, by_l2), c->m / c->sfm_min_chunk));
   int step = 8;
@@ -552,8 +554,11 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
   TRY(dalloc_cap(c, &b.sf_part, (size_t)2 * c->nk * c->mchunks));
   const bool fast = c->sf_mfma && c->nlayers > 0;
   if (c->sf_mfma) {
-    c->mpad = std::max(16, (c->m + 15) / 16 * 16);
-    c->sft_rows = sf_table_rows(c->nxm, c->nym, c->sfm_nbz);
+    c->mpad = std::max(64, (c->m + 63) / 64 * 64);
+    // table rows per configuration in double2 units: the FP64 / FP32 layout
+    // or the split-FP16 one (float2 rows and the z operand), the larger
+    c->sft_rows = std::max(sf_table_rows(c->nxm, c->nym, c->sfm_nbz),
+                           (sf16_rows(c->nxm, c->nym, c->sfm_nbz) + 1) / 2);
     c->sft_blocks = (c->mpad + 255) / 256;
     // planar electrodes: configurations per launch group (at most the 64
     // columns of the projection product), within ~1 GB of per-configuration
@@ -566,7 +571,9 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     }
     const int G = c->pv_group;
     size_t part_rows = 0;                 // (configuration, chunk) blocks of sfm_part
-    for (int g = 1; g <= G; ++g) part_rows = std::max(part_rows, (size_t)g * sf_chunks_for(c, g));
+    for (int g = 1; g <= G; ++g)
+      part_rows = std::max(part_rows, (size_t)g * std::max(sf_chunks_for(c, g, false),
+                                                           sf_chunks_for(c, g, true)));
     TRY(dalloc_cap(c, &b.sfm_part, part_rows * c->sfm_pchunk));
     TRY(dalloc_cap(c, &b.sft, (size_t)G * c->sft_rows * c->mpad));
   }
@@ -690,6 +697,9 @@ cpm_status ensure_uploaded(cpm_ctx* c) {
       TRY(dalloc(c, &b.sfm_items, c->h_sfm_items.size()));
       HIP_TRY(c, hipMemcpy(b.sfm_items, c->h_sfm_items.data(), c->h_sfm_items.size() * sizeof(int4),
                            hipMemcpyHostToDevice));
+      TRY(dalloc(c, &b.sf16_items, c->h_sf16_items.size()));
+      HIP_TRY(c, hipMemcpy(b.sf16_items, c->h_sf16_items.data(),
+                           c->h_sf16_items.size() * sizeof(int4), hipMemcpyHostToDevice));
     }
     TRY(dalloc(c, &b.chunk_col, c->h_chunk_col.size()));
     TRY(dalloc(c, &b.flag, 4));
@@ -757,6 +767,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (p.geometry == CPM_GEOM_WIRE) c->cdip[0] = c->cdip[1] = 2.0 * M_PI / c->V;
   if (const char* ev = std::getenv("CPM_SF_WG_TARGET")) c->sf_wg_target = std::max(64, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_WG_TARGET")) c->sfm_wg_target = std::max(8, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_SF16_WG_TARGET")) c->sf16_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_MIN_CHUNK")) c->sfm_min_chunk = std::max(16, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_SFM_MAX_CHUNK")) c->sfm_max_chunk = std::max(64, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
@@ -771,6 +782,8 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
     c->chol_block = std::max(1, std::min(32, std::atoi(ev) / TILE)) * TILE;
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_SF_FP32")) c->sf32_ok = std::atoi(ev) != 0;
+  if (const char* ev = std::getenv("CPM_SF_F16")) c->sf16_ok = std::atoi(ev) != 0;
+  if (const char* ev = std::getenv("CPM_SF16_PAIR")) c->sf16_pair = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_RS_PLANE")) c->rs_plane_ok = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
@@ -851,6 +864,19 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
         c->h_sfm_items.push_back(make_int4(mt, lo, hi - lo, 0));
       }
     }
+    // split-FP16 items: one or two M tiles (mt, mt + 1; tile extents do not
+    // grow with mt, so mt's blocks cover both), blocks in parts of <= SF16_NB
+    const int nt16 = c->sf16_pair ? 2 : 1;
+    for (int mt = 0; mt < c->sfm_tiles; mt += nt16) {
+      const int nb = c->h_tile_nb[mt];
+      const int nt = std::min(nt16, c->sfm_tiles - mt);
+      const int parts = (nb + SF16_NB - 1) / SF16_NB;
+      for (int q = 0; q < parts; ++q) {
+        const int lo = nb * q / parts, hi = nb * (q + 1) / parts;
+        c->h_sf16_items.push_back(make_int4(mt, lo, hi - lo, nt));
+      }
+    }
+    c->sf16_nitems = (int)c->h_sf16_items.size();
     c->sfm_nitems = (int)c->h_sfm_items.size();
     c->sf_mfma = c->sfm_nitems > 0;
     // compact partial layout: tile mt holds a 32 x 16 nb_mt block
@@ -1724,7 +1750,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
   const bool fast = mfma && c->nlayers > 0 && batch >= c->pv_fast_min;
   // b stored in FP32 (the reduced-precision solve path): structure factors on
   // FP32 matrix cores, FP32 phase tables (switch: CPM_SF_FP32=0)
-  const int sf32 = (b_is_f32 && c->sf32_ok) ? 1 : 0;
+  const int sf32 = (b_is_f32 && c->sf32_ok) ? (c->sf16_ok ? 2 : 1) : 0;
   const int G = fast ? c->pv_group : 1;
   const int mpad64 = std::max(64, (m + 63) / 64 * 64);
   // the charges ordered by z (from the first configuration of a large
@@ -1747,7 +1773,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
       launch_fill_zero(st, (size_t)g * n * esz / sizeof(float), static_cast<float*>(out));
       continue;
     }
-    const int nch = mfma ? sf_chunks_for(c, g) : 0;
+    const int nch = mfma ? sf_chunks_for(c, g, sf32 == 2) : 0;
     const int rch = fast ? rchunks_for(c, g) : c->rchunks;
     // grouped path: the real-space pass runs on its own stream beside the
     // structure factors (VALU/LDS-bound beside MFMA-bound work); it starts
@@ -1773,9 +1799,10 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
         launch_b_sf_tables(st, g, m, c->mpad, c->nxm, c->nym, c->sfm_nbz, xyz, b.elq, p.Lx, p.Ly,
                            c->Lz, b.sft, sf32); }
       { Timed t(c, "structure_factor");
-        launch_b_sf_mfma(st, g, c->mpad, nch, c->sfm_nitems, b.sfm_items, b.sc_nx, b.sc_ny,
+        launch_b_sf_mfma(st, g, c->mpad, nch, sf32 == 2 ? c->sf16_nitems : c->sfm_nitems,
+                         sf32 == 2 ? b.sf16_items : b.sfm_items, b.sc_nx, b.sc_ny,
                          c->ncolsort, c->nxm, c->nym, c->sfm_nbz, b.sft, b.tile_nb, b.tile_off,
-                         c->sfm_pchunk, b.sfm_part, sf32); }
+                         c->sfm_pchunk, b.sfm_part, sf32, c->sf16_pair); }
     } else {
       { Timed t(c, "structure_factor");
         launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz,
@@ -2889,7 +2916,8 @@ cpm_status cpm_get_info(const cpm_ctx* c, int key, double* out) {
     case CPM_INFO_PC_MODE: *out = c->pc_mode; return CPM_OK;
     case CPM_INFO_PC_COARSE: *out = (double)c->pc_tiles * c->pc_kuse; return CPM_OK;
     case CPM_INFO_SF_FP32:
-      *out = (c->sf_mfma && c->use_sf_mfma && c->sf32_ok) ? 1.0 : 0.0; return CPM_OK;
+      *out = (c->sf_mfma && c->use_sf_mfma && c->sf32_ok) ? (c->sf16_ok ? 2.0 : 1.0) : 0.0;
+      return CPM_OK;
     case CPM_INFO_RS_PLANE: *out = rs_plane(c) ? 1.0 : 0.0; return CPM_OK;
     default: return CPM_EINVAL;
   }
@@ -2924,7 +2952,7 @@ void cpm_destroy(cpm_ctx* c) {
   dfree(b.ex); dfree(b.ey); dfree(b.ez); dfree(b.efx); dfree(b.efy); dfree(b.efz); dfree(b.eid);
   dfree(b.layer_of); dfree(b.layer_fz); dfree(b.layerT); dfree(b.amap);
   dfree(b.sc_nx); dfree(b.sc_ny); dfree(b.sc_lo); dfree(b.sc_len); dfree(b.sc_koff); dfree(b.sc_n0);
-  dfree(b.sc_nidx); dfree(b.tile_nb); dfree(b.sfm_part); dfree(b.sfm_items); dfree(b.sft);
+  dfree(b.sc_nidx); dfree(b.tile_nb); dfree(b.sfm_part); dfree(b.sfm_items); dfree(b.sf16_items); dfree(b.sft);
   dfree(b.tile_off); dfree(b.pz); dfree(b.slot_of); dfree(b.b_items); dfree(b.bT); dfree(b.bPhi);
   dfree(b.runs); dfree(b.cols); dfree(b.chunk_col); dfree(b.w2); dfree(b.knx); dfree(b.kny); dfree(b.knz);
   dfree(b.A); dfree(b.L); dfree(b.Dinv); dfree(b.Ainv); dfree(b.S); dfree(b.S32); dfree(b.Shi);

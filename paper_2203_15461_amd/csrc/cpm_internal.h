@@ -35,6 +35,7 @@ struct KCol {
 
 constexpr int CCM_MAXE = 16;       // electrodes supported by the constrained charge method
 constexpr int SFM_NB = 4;          // 16-wide n blocks per matrix-core structure-factor work item
+constexpr int SF16_NB = 12;        // ... per item of the split-FP16 kernel (3 per wave)
 
 // charges per chunk of the matrix-core structure factors (a multiple of 16)
 inline int sf_mfma_chunk(int mpad, int mchunks) {
@@ -70,6 +71,7 @@ struct Buffers {
   int* sc_koff = nullptr; int* sc_n0 = nullptr; int* sc_nidx = nullptr; int* tile_nb = nullptr;
   double* sfm_part = nullptr;      // chunk partials [chunk][tile][32][npadc]
   int4* sfm_items = nullptr;       // work items {M tile, first n block, n blocks, 0}
+  int4* sf16_items = nullptr;      // the same with <= SF16_NB blocks (split-FP16 kernel)
   int* tile_off = nullptr;         // offset of each M tile's block in a chunk of sfm_part
   int* slot_of = nullptr;          // atom -> slot of the atom map (n)
   int* b_items = nullptr;          // work items of the b-path projection product
@@ -276,6 +278,7 @@ struct cpm_ctx {
   int mchunks = 1, kchunks = 1, rchunks = 1;
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
   int sfm_wg_target = 4096;        // the same for the matrix-core kernel
+  int sf16_wg_target = 4096;       // ... and for the split-FP16 one
   int sfm_min_chunk = 512;         // fewest charges per matrix-core chunk
   int sfm_max_chunk = 4096;        // most charges per matrix-core chunk
   int chol_block = 256;            // columns per outer block of the Cholesky / inverse
@@ -317,10 +320,12 @@ struct cpm_ctx {
   bool sf_mfma = false;            // structure factors on FP64 matrix cores (k set fits)
   bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
   bool sf32_ok = true;             // FP32 structure factors when b is stored in FP32
+  bool sf16_ok = true;             // ... on FP16 matrix cores with split operands
+  bool sf16_pair = true;           // ... two M tiles per work item
   bool rs_plane_ok = true;         // planar real-space kernel (pair polynomials in r^2)
   bool factor_only = false;        // cpm_invert kept the Cholesky factor, not S
   int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_ntot = 0;
-  int sfm_nbz = 2, sfm_nitems = 0, mpad = 0, sft_rows = 0, sft_blocks = 1;
+  int sfm_nbz = 2, sfm_nitems = 0, sf16_nitems = 0, mpad = 0, sft_rows = 0, sft_blocks = 1;
   int sfm_pchunk = 0;              // doubles per (configuration, chunk) of sfm_part
   int sfm_maxcnt = 0;              // largest number of n >= 0 of a sorted column
   int pv_group = 1;                // configurations per launch group (planar fast path)
@@ -331,7 +336,7 @@ struct cpm_ctx {
   std::vector<int> h_tile_plane;   // plane of each 64-slot tile of the atom map
   int planar_nslot = 0;            // slots the planar k-space buffers were sized for
   std::vector<int> h_tile_off;
-  std::vector<int4> h_sfm_items;
+  std::vector<int4> h_sfm_items, h_sf16_items;
   std::vector<int> h_sc_nx, h_sc_ny, h_sc_lo, h_sc_len, h_sc_koff, h_sc_n0, h_sc_nidx, h_tile_nb;
   std::vector<double> h_w2;
   std::vector<int> h_kx, h_ky, h_kz;
@@ -485,7 +490,7 @@ void launch_gather_charges(hipStream_t st, int g, int m, int mpad64, const int* 
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
-                      double* part, int fp32);
+                      double* part, int fp32, bool sf16_pair);
 void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int nchunks, int pchunk,
                              const int* tile_nb, const int* toff, const int* sc_lo,
                              const int* sc_len, const int* sc_koff, const int* n_index,
@@ -506,6 +511,7 @@ void launch_b_final(hipStream_t st, int g, int n, int nslot, int nparts, const i
 int real_space_block_atoms();      // atom-map slots per workgroup of the real-space b kernel
 
 int sf_table_rows(int nxm, int nym, int nbz);
+int sf16_rows(int nxm, int nym, int nbz);      // float2 rows of the split-FP16 tables
 void launch_b_sf_reduce(hipStream_t st, int nk, int mchunks, const double* part,
                         const double* w2, double* sfw);
 void launch_b_kspace_project(hipStream_t st, int fp32, int n, int kchunks, const KCol* cols,
