@@ -42,6 +42,7 @@ MODES = {
 # dominant kernel families and their algorithmic work per launch
 PEAK_FP64_VALU = 78.6e12     # FLOP/s, MI355X FP64 vector
 PEAK_FP32_VALU = 157.3e12
+PEAK_FP16_MFMA = 2.5e15      # FLOP/s, MI355X dense FP16 matrix cores
 PEAK_HBM = 8.0e12            # B/s
 DOMINANT = "structure_factor"
 # Ewald split of the 20064-atom capacitor: q does not depend on alpha; a
@@ -311,15 +312,19 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     # complex rotation and a complex accumulate)
     snaps_per_launch = B * steps / max(sf_cnt, 1)
     matrix = ctx.info("sf_matrix") == 1.0
-    sf_fp32 = b_f32 and matrix and ctx.info("sf_fp32") == 1.0
+    sf_prec = ctx.info("sf_fp32") if (b_f32 and matrix) else 0.0
+    sf_fp32, sf_f16 = sf_prec == 1.0, sf_prec == 2.0
     flop_per_pair = 4.0 if matrix else 8.0
     flop_per_launch = flop_per_pair * nk * w.m * snaps_per_launch
     achieved = flop_per_launch / sf_avg if sf_avg > 0 else 0.0
     # FP64 MFMA and FP64 vector peaks are both 78.6 TFLOP/s; with b stored in
-    # FP32 the structure factors run on FP32 matrix cores (157.3 TFLOP/s)
-    peak = PEAK_FP32_VALU if sf_fp32 else PEAK_FP64_VALU
-    traffic = stored_traffic(name, "cpm::k_sf_mfma32" if sf_fp32 else "cpm::k_sf_mfma",
-                             snaps_per_launch)
+    # FP32 the structure factors run on FP16 matrix cores with split operands
+    # (2.5 PFLOP/s dense; three products per algorithmic one) or, switched
+    # to, on FP32 matrix cores (157.3 TFLOP/s)
+    peak = PEAK_FP16_MFMA if sf_f16 else PEAK_FP32_VALU if sf_fp32 else PEAK_FP64_VALU
+    sf_kernel = ("cpm::k_sf_mfma16<2>" if sf_f16 else "cpm::k_sf_mfma32" if sf_fp32
+                 else "cpm::k_sf_mfma")
+    traffic = stored_traffic(name, sf_kernel, snaps_per_launch)
     sf_bound = "mfma" if matrix else "alu"
 
     value = B * steps / elapsed
@@ -347,7 +352,10 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
                      "avg_launch_us": sf_avg * 1e6,
                      "configurations_per_launch": snaps_per_launch,
                      "launch_group": int(ctx.info("group")),
-                     "precision": "fp32" if sf_fp32 else "fp64"},
+                     "precision": "fp16 split pairs (3 products)" if sf_f16 else
+                                  "fp32" if sf_fp32 else "fp64",
+                     "matrix_core_frac_executed": achieved * (3.0 if sf_f16 else 1.0) / peak,
+                     "sf_kernel": sf_kernel.split("::")[1]},
         "roofline_real_space": rs_roof,
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),

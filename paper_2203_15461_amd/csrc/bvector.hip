@@ -326,6 +326,7 @@ typedef _Float16 v8h_t __attribute__((ext_vector_type(8)));
 int sf16_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) + 1 + 8 * nbz; }
 
 constexpr int ZS_ROW = 264;              // halfs per LDS row of the z-operand staging
+constexpr float SF16_LO = 2048.f;         // scale of the low FP16 part
 
 // the pair of an FP64 value, formed from its FP32 rounding (2^-24 relative,
 // below the 2^-22 of the pair); the clamp to the FP16 range (a no-op here)
@@ -334,7 +335,7 @@ constexpr int ZS_ROW = 264;              // halfs per LDS row of the z-operand s
 __device__ inline void split_f16(double v, _Float16& h, _Float16& l) {
   const float vf = __builtin_amdgcn_fmed3f((float)v, -65504.f, 65504.f);
   h = (_Float16)vf;
-  l = (_Float16)((vf - (float)h) * 2048.f);
+  l = (_Float16)((vf - (float)h) * SF16_LO);
 }
 
 // grid (charge blocks of 256, 2 + nbz, configurations): y = 0 the X rows
@@ -902,10 +903,10 @@ __device__ void sf_wave16(_Float16 (*As)[NT][2][32][SF16_ROW], const float2* __r
       const _Float16 hr0 = (_Float16)r0, hr1 = (_Float16)r1, hi0 = (_Float16)i0, hi1 = (_Float16)i1;
       *reinterpret_cast<v2h_t*>(&As[buf][t][0][2 * i_l][c0]) = (v2h_t){hr0, hr1};
       *reinterpret_cast<v2h_t*>(&As[buf][t][1][2 * i_l][c0]) =
-          (v2h_t){(_Float16)((r0 - (float)hr0) * 2048.f), (_Float16)((r1 - (float)hr1) * 2048.f)};
+          (v2h_t){(_Float16)((r0 - (float)hr0) * SF16_LO), (_Float16)((r1 - (float)hr1) * SF16_LO)};
       *reinterpret_cast<v2h_t*>(&As[buf][t][0][2 * i_l + 1][c0]) = (v2h_t){hi0, hi1};
       *reinterpret_cast<v2h_t*>(&As[buf][t][1][2 * i_l + 1][c0]) =
-          (v2h_t){(_Float16)((i0 - (float)hi0) * 2048.f), (_Float16)((i1 - (float)hi1) * 2048.f)};
+          (v2h_t){(_Float16)((i0 - (float)hi0) * SF16_LO), (_Float16)((i1 - (float)hi1) * SF16_LO)};
     }
   };
   auto load_b = [&](v8h_t (&bh)[K], v8h_t (&bl)[K], int jt) {
@@ -961,11 +962,11 @@ __device__ void sf_wave16(_Float16 (*As)[NT][2][32][SF16_ROW], const float2* __r
 #pragma unroll
         for (int r = 0; r < 4; ++r)
           out[t][(16 * rb + 4 * g_l + r) * ldc[t] + col] =
-              (double)fh[t][rb][k][r] + (double)fl[t][rb][k][r] * (1.0 / 2048.0);
+              (double)fh[t][rb][k][r] + (double)fl[t][rb][k][r] / SF16_LO;
     }
 }
 
-// Items {M tile mt, first block, blocks, M tiles (1 or 2: mt and mt + 1)}.
+// Items {M tile mt, first block, blocks, M tiles nt <= NT (mt .. mt + nt - 1)}.
 template <int NT>
 __device__ void sf_item16(const float2* __restrict__ tab, int mpad, int chunk_size, int nchunks,
                           int snap, int chunk, int4 it, const int* __restrict__ sc_nx,
@@ -1003,11 +1004,12 @@ __device__ void sf_item16(const float2* __restrict__ tab, int mpad, int chunk_si
   // this wave's blocks: nb_lo + wave + 4k, k < kw (nbw <= SF16_NB = 12)
   const int kw = wave < nbw ? (nbw - wave + 3) / 4 : 0;
   const int blk0 = nb_lo + wave;
+  // (items of four M tiles hold at most 8 blocks: kw <= 2)
   switch (kw) {
     case 0: sf_wave16<0, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
     case 1: sf_wave16<1, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
     case 2: sf_wave16<2, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
-    default: sf_wave16<3, NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
+    default: sf_wave16<(NT == 4 ? 2 : 3), NT>(As, tab, zop, mpad, j0, j1, xrow, yrow, out, ldc, nbt, blk0); break;
   }
 }
 
@@ -1031,7 +1033,7 @@ k_sf_mfma16(int mpad, int chunk_size, int nchunks, int nitems, const int4* __res
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
-                      double* part, int fp32, bool sf16_pair) {
+                      double* part, int fp32, int sf16_nt) {
   // nchunks is a multiple of 8 (one residue class of pairs per XCD)
   const int chunk_size = sf_mfma_chunk(mpad, nchunks);
   const size_t tab_stride = (size_t)sf_table_rows(nxm, nym, nbz) * mpad;
@@ -1039,7 +1041,8 @@ void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, 
   if (fp32 == 2) {
     // tile pairs of 64 charges: chunk bounds on multiples of 64 (mpad is one)
     const int chunk32 = ((mpad + nchunks - 1) / nchunks + 63) / 64 * 64;
-    hipLaunchKernelGGL(sf16_pair ? k_sf_mfma16<2> : k_sf_mfma16<1>, grid, block, 0, st, mpad,
+    hipLaunchKernelGGL(sf16_nt == 4 ? k_sf_mfma16<4> : sf16_nt == 2 ? k_sf_mfma16<2> : k_sf_mfma16<1>,
+                       grid, block, 0, st, mpad,
                        chunk32, nchunks, nitems, items, sc_nx, sc_ny, ncolsort, nxm, nym,
                        reinterpret_cast<const float2*>(tab), (size_t)sf16_rows(nxm, nym, nbz) * mpad,
                        tile_nb, toff, pchunk, part);

@@ -783,7 +783,10 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_SF_MFMA")) c->use_sf_mfma = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_SF_FP32")) c->sf32_ok = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_SF_F16")) c->sf16_ok = std::atoi(ev) != 0;
-  if (const char* ev = std::getenv("CPM_SF16_PAIR")) c->sf16_pair = std::atoi(ev) != 0;
+  if (const char* ev = std::getenv("CPM_SF16_NT")) {
+    const int v = std::atoi(ev);
+    c->sf16_nt = v >= 4 ? 4 : v >= 2 ? 2 : 1;
+  }
   if (const char* ev = std::getenv("CPM_RS_PLANE")) c->rs_plane_ok = std::atoi(ev) != 0;
   c->kc = (p.kcut > 0.0) ? p.kcut : 2.0 * p.alpha * std::sqrt(std::log(1.0 / p.kspace_eps));
   c->ke = (p.coulomb_k > 0.0) ? p.coulomb_k : KE_DEFAULT;
@@ -864,13 +867,14 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
         c->h_sfm_items.push_back(make_int4(mt, lo, hi - lo, 0));
       }
     }
-    // split-FP16 items: one or two M tiles (mt, mt + 1; tile extents do not
-    // grow with mt, so mt's blocks cover both), blocks in parts of <= SF16_NB
-    const int nt16 = c->sf16_pair ? 2 : 1;
+    // split-FP16 items: sf16_nt M tiles (mt, mt + 1, ..; tile extents do not
+    // grow with mt, so mt's blocks cover them all), blocks in parts of
+    // <= SF16_NB (<= 8 with four tiles)
+    const int nt16 = c->sf16_nt, nbmax16 = nt16 == 4 ? 8 : SF16_NB;
     for (int mt = 0; mt < c->sfm_tiles; mt += nt16) {
       const int nb = c->h_tile_nb[mt];
       const int nt = std::min(nt16, c->sfm_tiles - mt);
-      const int parts = (nb + SF16_NB - 1) / SF16_NB;
+      const int parts = (nb + nbmax16 - 1) / nbmax16;
       for (int q = 0; q < parts; ++q) {
         const int lo = nb * q / parts, hi = nb * (q + 1) / parts;
         c->h_sf16_items.push_back(make_int4(mt, lo, hi - lo, nt));
@@ -1802,7 +1806,7 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
         launch_b_sf_mfma(st, g, c->mpad, nch, sf32 == 2 ? c->sf16_nitems : c->sfm_nitems,
                          sf32 == 2 ? b.sf16_items : b.sfm_items, b.sc_nx, b.sc_ny,
                          c->ncolsort, c->nxm, c->nym, c->sfm_nbz, b.sft, b.tile_nb, b.tile_off,
-                         c->sfm_pchunk, b.sfm_part, sf32, c->sf16_pair); }
+                         c->sfm_pchunk, b.sfm_part, sf32, c->sf16_nt); }
     } else {
       { Timed t(c, "structure_factor");
         launch_b_structure_factor(st, b_is_f32, c->nruns, b.runs, c->nk, m, c->mchunks, xyz,

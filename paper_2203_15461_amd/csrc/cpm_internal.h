@@ -278,7 +278,7 @@ struct cpm_ctx {
   int mchunks = 1, kchunks = 1, rchunks = 1;
   int sf_wg_target = 512;          // structure-factor workgroups per snapshot (tuning)
   int sfm_wg_target = 4096;        // the same for the matrix-core kernel
-  int sf16_wg_target = 4096;       // ... and for the split-FP16 one
+  int sf16_wg_target = 2048;       // ... and for the split-FP16 one
   int sfm_min_chunk = 512;         // fewest charges per matrix-core chunk
   int sfm_max_chunk = 4096;        // most charges per matrix-core chunk
   int chol_block = 256;            // columns per outer block of the Cholesky / inverse
@@ -321,7 +321,7 @@ struct cpm_ctx {
   bool use_sf_mfma = true;         // tuning switch (CPM_SF_MFMA=0 keeps the VALU kernel)
   bool sf32_ok = true;             // FP32 structure factors when b is stored in FP32
   bool sf16_ok = true;             // ... on FP16 matrix cores with split operands
-  bool sf16_pair = true;           // ... two M tiles per work item
+  int sf16_nt = 2;                 // ... M tiles per work item (1, 2 or 4)
   bool rs_plane_ok = true;         // planar real-space kernel (pair polynomials in r^2)
   bool factor_only = false;        // cpm_invert kept the Cholesky factor, not S
   int ncolsort = 0, sfm_tiles = 0, sfm_npadc = 0, sfm_ntot = 0;
@@ -490,7 +490,7 @@ void launch_gather_charges(hipStream_t st, int g, int m, int mpad64, const int* 
 void launch_b_sf_mfma(hipStream_t st, int g, int mpad, int nchunks, int nitems, const int4* items,
                       const int* sc_nx, const int* sc_ny, int ncolsort, int nxm, int nym, int nbz,
                       const double2* tab, const int* tile_nb, const int* toff, int pchunk,
-                      double* part, int fp32, bool sf16_pair);
+                      double* part, int fp32, int sf16_nt);
 void launch_b_sf_mfma_reduce(hipStream_t st, int ncolsort, int nchunks, int pchunk,
                              const int* tile_nb, const int* toff, const int* sc_lo,
                              const int* sc_len, const int* sc_koff, const int* n_index,
