@@ -8,7 +8,10 @@ of 104 = 64 + 40 configurations (the three stored oracle snapshots, cycled)
 runs the same step: b within 1e-10 of the oracle's for every
 configuration, q within 1e-10 (FP64) and 1e-5 (split-BF16 + refinement),
 |sum q| <= 1e-12 e.  The bench's reduced-precision path keeps b in FP32
-from the FP32 structure factors: b within 5e-6 and q within 1e-5.
+from the structure factors on FP16 matrix cores with split operands: b
+within 5e-6 and q within 1e-5; the same for its other work-item widths
+(one or four M tiles) and for the FP32 matrix-core kernel it can be switched
+to.
 
 The 20064-atom capacitor (two configurations per launch group by default)
 is checked against stored oracle rows: sampled rows of b with the full
@@ -101,6 +104,29 @@ def test_2880_bench_step_against_golden(cpm, mode, store, b_f32, tol_b, tol):
     say(f"  launch group {group}: b {eb:.3e} q {eq:.3e} Q {eQ:.3e}")
     assert eb < tol_b
     assert eq < tol and eQ < tol
+    assert np.abs(q.sum(axis=1)).max() <= 1e-12
+
+
+# structure-factor kernels of the reduced-precision path (switches read when
+# a context is created): split-FP16 items of one and of four M tiles, and
+# the FP32 matrix-core kernel
+SF_SWITCHES = [{"CPM_SF16_NT": "1"}, {"CPM_SF16_NT": "4"}, {"CPM_SF_F16": "0"}]
+
+
+@pytest.mark.parametrize("env", SF_SWITCHES, ids=lambda e: ",".join(f"{k}={v}" for k, v in e.items()))
+def test_2880_reduced_precision_kernels_against_golden(cpm, env, monkeypatch):
+    g = np.load(os.path.join(GOLDEN, "graphite_capacitor_2880.npz"))
+    w = I.graphite_capacitor()
+    idx = [k % 3 for k in range(104)]
+    xyz = torch.as_tensor(np.stack([I.snapshot(w, int(g["snapshots"][k])) for k in idx]),
+                          dtype=torch.float64, device="cuda").contiguous()
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    say(f"2880 bench step, 104 configurations, b FP32, {env}")
+    b, q, Qe, group = _bench_step(cpm, w, xyz, 1 | 4, 0x102, b_f32=True)
+    eb, eq, eQ = rel(b, g["b"][idx]), rel(q, g["q"][idx]), rel(Qe, g["Q"][idx])
+    say(f"  b {eb:.3e} q {eq:.3e} Q {eQ:.3e}")
+    assert eb < 5e-6 and eq < 1e-5 and eQ < 1e-5
     assert np.abs(q.sum(axis=1)).max() <= 1e-12
 
 
