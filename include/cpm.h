@@ -116,8 +116,9 @@ enum {
                               /*   (0: plain CG)                                  */
   CPM_INFO_PC_MODE = 24,      /*   ... its form: 0 none, 1 additive, 2 balancing  */
   CPM_INFO_PC_COARSE = 25,    /*   ... its coarse-space dimension                 */
-  CPM_INFO_SF_FP32 = 26,      /* 1: cpm_potential_vector with b_is_f32 forms the  */
-                              /* structure factors on FP32 matrix cores           */
+  CPM_INFO_SF_FP32 = 26,      /* cpm_potential_vector with b_is_f32 forms the     */
+                              /* structure factors on FP16 matrix cores with      */
+                              /* split operands (2) or FP32 matrix cores (1)      */
   CPM_INFO_RS_PLANE = 27      /* 1: the real-space part of b runs the planar      */
                               /* kernel (atoms on z planes, one image within r_c) */
 };
@@ -284,11 +285,15 @@ cpm_status cpm_set_field(cpm_ctx* ctx, double dv0, int bottom);
  * d_xyz: batch x m x 3 FP64 positions (row-major, snapshot-major).
  * d_b: batch x n output, FP64 (b_is_f32 = 0) or FP32 (b_is_f32 = 1, for
  * the reduced-precision solve modes).  With FP32 output the structure
- * factors run on FP32 matrix cores: the phase tables are computed in FP64
- * and rounded to FP32, products are summed in FP32 over 128 charges and in
- * FP64 beyond, and the rest of b stays FP64 until the final rounding; b is
- * then within a few 1e-6 (relative to its largest entry) of the FP64 result
- * (CPM_SF_FP32=0 in the environment keeps FP64 structure factors).  b
+ * factors run on FP16 matrix cores with split operands: every operand value
+ * (phases formed in FP64, products of them in FP32) is carried as two FP16
+ * numbers, hi and 2^11 (value - hi), a product as three FP16 products summed
+ * in FP32 over a charge chunk (each value kept to about 2^-22 relative),
+ * then in FP64; the rest of b stays FP64 until the final rounding.  b is
+ * then within about 1e-6 (relative to its largest entry) of the FP64
+ * result.  Switches read when a context is created: CPM_SF_F16=0 takes the
+ * FP32 matrix-core kernel instead (FP32 phase tables and products, FP32
+ * sums over 128 charges); CPM_SF_FP32=0 keeps FP64 structure factors.  b
  * includes the real-space erfc sum, the k-space structure-factor term and
  * the electrolyte cross term of the slab correction (Eq. 12). */
 cpm_status cpm_potential_vector(cpm_ctx* ctx, int batch, const double* d_xyz,
