@@ -199,73 +199,57 @@ __device__ inline double2 cmul2(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// Per-charge phase tables of one configuration, rows of mpad double2
-// (charges j >= m are zero), each entry an exact FP64 sincospi of the reduced
-// fractional phase:
+// Dipole partials of one configuration for the 256 charges of this block
+// (every thread of the block calls it): dip[d] = sum q_j r_jd in raw
+// coordinates, the same sums in the same order as k_elyt_dipole.
+__device__ inline void block_dipole(int m, int j, const double* __restrict__ xyz,
+                                    const double* __restrict__ q, double* __restrict__ dip) {
+  __shared__ double sh[3][4];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (j < m) {
+    const double qq = q[j];
+    v[0] = qq * xyz[3 * j]; v[1] = qq * xyz[3 * j + 1]; v[2] = qq * xyz[3 * j + 2];
+  }
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    for (int o = 32; o > 0; o >>= 1) v[d] += __shfl_xor(v[d], o, 64);
+    if (lane == 0) sh[d][wave] = v[d];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int d = threadIdx.x;
+    dip[d] = (sh[d][0] + sh[d][1]) + (sh[d][2] + sh[d][3]);
+  }
+}
+
+// Per-charge phase tables of one configuration, rows of mpad T2 entries
+// (charges j >= m are zero):
 //   rows [0, nxm]              X_a(j) = e^{2 pi i a fx_j}
 //   rows nxm+1 + [0, 2 nym]    Y_b(j) = q_j e^{2 pi i (b - nym) fy_j}
 //   next 8 rows                Z1_i(j) = e^{2 pi i i fz_j}
 //   next nbz rows              Z8_c(j) = e^{2 pi i 8 c fz_j}
 //   last row                   zero (the C operand of absent columns)
-// blockIdx.z selects the configuration of the group (tables tab_stride
-// apart).
+// One thread per (charge, row family, configuration) forms the family's
+// entries as powers of its first phase in FP64 (complex products: a few
+// 1e-15 relative after 30 powers), rounded once to T2 when stored.
+// Families: X (n_x = 0..nxm), q Y (n_y = -nym..nym: powers and their
+// conjugates), Z1 (n = 0..7), Z8 (8 n, n = 0..nbz-1) with the zero row.
+// The X family's blocks also write the dipole partials of their 256 charges
+// (blocks x 3 per configuration).  blockIdx.z selects the configuration of
+// the group (tables tab_stride apart).
 template <typename T2>
-__global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int nym,
+__global__ void __launch_bounds__(256) k_sf_tables(int m, int mpad, int nxm, int nym, int nbz,
                                                    const double* __restrict__ xyz,
                                                    const double* __restrict__ q, double Lx,
                                                    double Ly, double Lz, size_t tab_stride,
-                                                   T2* __restrict__ tab) {
-  const int row = blockIdx.y, snap = blockIdx.z;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
-  xyz += (size_t)snap * m * 3;
-  tab += (size_t)snap * tab_stride;
-  double qq = 0.0, zz = 0.0;
-  if (j < m) { qq = q[j]; zz = xyz[3 * j + 2]; }
-  if (j < mpad) {
-    double2 v = make_double2(0.0, 0.0);              // rounded once to T2 when stored
-    if (j < m) {
-      double f, idx, scale = 1.0;
-      if (row < rY) {
-        f = xyz[3 * j] / Lx; f -= floor(f); idx = row;
-      } else if (row < rZ1) {
-        f = xyz[3 * j + 1] / Ly; f -= floor(f); idx = row - rY - nym; scale = qq;
-      } else if (row < rZ8) {
-        f = zz / Lz; f -= floor(f); idx = row - rZ1;
-      } else if (row < (int)gridDim.y - 1) {
-        f = zz / Lz; f -= floor(f); idx = 8.0 * (row - rZ8);
-      } else {
-        f = 0.0; idx = 0.0; scale = 0.0;
-      }
-      double th = idx * f;
-      th -= rint(th);
-      double sn, cs;
-      sincospi(2.0 * th, &sn, &cs);
-      v = make_double2(scale * cs, scale * sn);
-    }
-    T2 t;
-    t.x = v.x;
-    t.y = v.y;
-    tab[(size_t)row * mpad + j] = t;
-  }
-}
-
-// FP32 tables (b stored in FP32): one thread per (charge, row family,
-// configuration) forms the family's entries as powers of its first phase in
-// FP64 (complex products: a few 1e-15 relative after 30 powers, far below the
-// FP32 rounding of each entry) instead of a sincospi per entry.  Families: X
-// (n_x = 0..nxm), q Y (n_y = -nym..nym: powers and their conjugates), Z1
-// (n = 0..7), Z8 (8 n, n = 0..nbz-1) with the zero row.
-__global__ void __launch_bounds__(256) k_sf_tables32(int m, int mpad, int nxm, int nym, int nbz,
-                                                     const double* __restrict__ xyz,
-                                                     const double* __restrict__ q, double Lx,
-                                                     double Ly, double Lz, size_t tab_stride,
-                                                     float2* __restrict__ tab) {
+                                                   T2* __restrict__ tab, double* __restrict__ dip) {
   const int fam = blockIdx.y, snap = blockIdx.z;
   const int j = blockIdx.x * 256 + threadIdx.x;
+  xyz += (size_t)snap * m * 3;
+  if (fam == 0) block_dipole(m, j, xyz, q, dip + ((size_t)snap * gridDim.x + blockIdx.x) * 3);
   if (j >= mpad) return;
   const int rY = nxm + 1, rZ1 = rY + 2 * nym + 1, rZ8 = rZ1 + 8;
-  xyz += (size_t)snap * m * 3;
   tab += (size_t)snap * tab_stride + j;
   const bool live = j < m;
   double f = 0.0, scale = live ? 1.0 : 0.0;
@@ -283,7 +267,9 @@ __global__ void __launch_bounds__(256) k_sf_tables32(int m, int mpad, int nxm, i
   } else {
     if (live) { f = xyz[3 * j + 2] / Lz; f -= floor(f); }
     row0 = rZ8; count = nbz; step = 8.0;
-    tab[(size_t)(rZ8 + nbz) * mpad] = make_float2(0.f, 0.f);   // the zero row
+    T2 zero;
+    zero.x = 0.0; zero.y = 0.0;
+    tab[(size_t)(rZ8 + nbz) * mpad] = zero;          // the zero row
   }
   double th = step * f;
   th -= rint(th);
@@ -291,8 +277,13 @@ __global__ void __launch_bounds__(256) k_sf_tables32(int m, int mpad, int nxm, i
   sincospi(2.0 * th, &sn, &cs);
   double pr = scale, pi = 0.0;                       // scale * phase^0
   for (int k = 0; k < count; ++k) {
-    tab[(size_t)(row0 + k) * mpad] = make_float2((float)pr, (float)pi);
-    if (fam == 1 && k > 0) tab[(size_t)(row0 - k) * mpad] = make_float2((float)pr, (float)-pi);
+    T2 e;
+    e.x = pr; e.y = pi;
+    tab[(size_t)(row0 + k) * mpad] = e;
+    if (fam == 1 && k > 0) {
+      e.y = -pi;
+      tab[(size_t)(row0 - k) * mpad] = e;
+    }
     const double nr = pr * cs - pi * sn, ni = pr * sn + pi * cs;
     pr = nr;
     pi = ni;
@@ -338,20 +329,23 @@ __device__ inline void split_f16(double v, _Float16& h, _Float16& l) {
   l = (_Float16)((vf - (float)h) * SF16_LO);
 }
 
-// grid (charge blocks of 256, 2 + nbz, configurations): y = 0 the X rows
-// and the zero row, y = 1 the Y rows, y = 2 + bb the z operand of block bb.
-// Phases are powers of a first one in FP64 (a few 1e-15 relative).
+// grid (charge blocks of 256, 2 + nbz, configurations): y = 0 the X rows,
+// the zero row and the dipole partials of the block's charges, y = 1 the Y
+// rows, y = 2 + bb the z operand of block bb.  Phases are powers of a first
+// one in FP64 (a few 1e-15 relative).
 __global__ void __launch_bounds__(256) k_sf_tables16(int m, int mpad, int nxm, int nym, int nbz,
                                                      const double* __restrict__ xyz,
                                                      const double* __restrict__ q, double Lx,
                                                      double Ly, double Lz, size_t tab_stride,
-                                                     float2* __restrict__ tab) {
+                                                     float2* __restrict__ tab,
+                                                     double* __restrict__ dip) {
   __shared__ __align__(16) _Float16 zs[32 * ZS_ROW];
   const int fam = blockIdx.y, snap = blockIdx.z;
   const int jb = blockIdx.x * 256, jl = threadIdx.x, j = jb + jl;
   const int rY = nxm + 1, rzero = rY + 2 * nym + 1;
   xyz += (size_t)snap * m * 3;
   tab += (size_t)snap * tab_stride;
+  if (fam == 0) block_dipole(m, j, xyz, q, dip + ((size_t)snap * gridDim.x + blockIdx.x) * 3);
   const bool live = j < m;
   if (fam < 2) {
     if (j >= mpad) return;
@@ -420,22 +414,24 @@ int sf_table_rows(int nxm, int nym, int nbz) { return (nxm + 1) + (2 * nym + 1) 
 
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
-                        double2* tab, int fp32) {
-  const int rows = sf_table_rows(nxm, nym, nbz);
+                        double2* tab, int fp32, double* dip) {
+  // blocks of 256 charges: as many as the dipole partials have (mpad is at
+  // most the multiple of 256 above m)
   const int blocks = (mpad + 255) / 256;
-  dim3 grid(blocks, rows, g), block(256);
+  dim3 block(256);
   if (fp32 == 2) {
     hipLaunchKernelGGL(k_sf_tables16, dim3(blocks, 2 + nbz, g), block, 0, st, m, mpad, nxm, nym, nbz,
                        xyz, q, Lx, Ly, Lz, (size_t)sf16_rows(nxm, nym, nbz) * mpad,
-                       reinterpret_cast<float2*>(tab));
+                       reinterpret_cast<float2*>(tab), dip);
     return;
   }
+  const size_t stride = (size_t)sf_table_rows(nxm, nym, nbz) * mpad;
   if (fp32)
-    hipLaunchKernelGGL(k_sf_tables32, dim3(blocks, 4, g), block, 0, st, m, mpad, nxm, nym, nbz, xyz,
-                       q, Lx, Ly, Lz, (size_t)rows * mpad, reinterpret_cast<float2*>(tab));
+    hipLaunchKernelGGL(k_sf_tables<float2>, dim3(blocks, 4, g), block, 0, st, m, mpad, nxm, nym, nbz,
+                       xyz, q, Lx, Ly, Lz, stride, reinterpret_cast<float2*>(tab), dip);
   else
-    hipLaunchKernelGGL(k_sf_tables<double2>, grid, block, 0, st, m, mpad, nxm, nym, xyz, q, Lx, Ly,
-                       Lz, (size_t)rows * mpad, tab);
+    hipLaunchKernelGGL(k_sf_tables<double2>, dim3(blocks, 4, g), block, 0, st, m, mpad, nxm, nym,
+                       nbz, xyz, q, Lx, Ly, Lz, stride, tab, dip);
 }
 
 // Dipole partials of each configuration of a group, per 256 charges and

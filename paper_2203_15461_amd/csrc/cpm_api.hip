@@ -1796,12 +1796,15 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
                           p.rcut, b.phir_part, fast ? rs_target(c) : 512,
                           rs_plane(c) ? b.ptab : nullptr); }
     if (conc) HIP_TRY(c, hipEventRecord(c->rs_ev_out, rst));
-    { Timed t(c, "dipole");
-      launch_b_elyt_dipole(st, g, m, xyz, b.elq, b.dip); }
+    if (!mfma) {
+      Timed t(c, "dipole");
+      launch_b_elyt_dipole(st, g, m, xyz, b.elq, b.dip);
+    }
     if (mfma) {
+      // the table kernel also writes the dipole partials
       { Timed t(c, "sf_tables");
         launch_b_sf_tables(st, g, m, c->mpad, c->nxm, c->nym, c->sfm_nbz, xyz, b.elq, p.Lx, p.Ly,
-                           c->Lz, b.sft, sf32); }
+                           c->Lz, b.sft, sf32, b.dip); }
       { Timed t(c, "structure_factor");
         launch_b_sf_mfma(st, g, c->mpad, nch, sf32 == 2 ? c->sf16_nitems : c->sfm_nitems,
                          sf32 == 2 ? b.sf16_items : b.sfm_items, b.sc_nx, b.sc_ny,

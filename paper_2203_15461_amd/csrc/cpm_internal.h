@@ -475,7 +475,7 @@ void launch_b_structure_factor(hipStream_t st, int fp32, int nruns, const KRun* 
 // per-charge phase tables; fp32: stored as float2 (the same rows, half the bytes)
 void launch_b_sf_tables(hipStream_t st, int g, int m, int mpad, int nxm, int nym, int nbz,
                         const double* xyz, const double* q, double Lx, double Ly, double Lz,
-                        double2* tab, int fp32);
+                        double2* tab, int fp32, double* dip);
 void launch_b_elyt_dipole(hipStream_t st, int g, int m, const double* xyz, const double* q,
                           double* dip);
 void launch_dipole_partials(hipStream_t st, int g, int m, const double* xyz, size_t xyz_stride,
