@@ -32,8 +32,8 @@ sys.path.insert(0, ROOT)
 
 MODES = {
     # name: (store flags, b in fp32, solve mode, dtype label).  The reduced-
-    # precision modes keep b in FP32 (structure factors on FP32 matrix cores)
-    # and refine q once against A in FP64.
+    # precision modes keep b in FP32 (structure factors on FP16 matrix cores
+    # with split operands) and refine q once against A in FP64.
     "f64": (1, False, 0x000, "f64"),
     "f32r": (1 | 2, True, 0x101, "b f32, S f32, f64 refine"),
     "bf16r": (1 | 4, True, 0x102, "b f32, S bf16x3 (f32 accumulation), f64 refine"),
@@ -297,6 +297,20 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
         ctx.solve_charges(b1, 0x000, q1, Qe1)
     torch.cuda.synchronize()
     plain_rate = n_plain / (time.perf_counter() - ts)
+    # the same loop with b in FP32 (the split-FP16 structure factors), still
+    # solved by the FP64 matvec: the reduced-precision single-configuration
+    # step; its charges are compared with the FP64 loop's last ones
+    b1f = torch.empty((1, w.n), dtype=torch.float32, device=dev)
+    q1f = torch.empty_like(q1)
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    for s_ in range(n_plain):
+        ctx.potential_vector(xyz[s_:s_ + 1], b1f)
+        ctx.solve_charges(b1f, 0x000, q1f, Qe1)
+    torch.cuda.synchronize()
+    plain_f32b = {"steps_per_s": n_plain / (time.perf_counter() - ts),
+                  "max_rel_diff_vs_fp64_last_step":
+                      float(((q1f - q1).abs().max() / q1.abs().max()).item())}
     graph_step = graph_step_measure(w, xyz, dev, n_plain, q1)
 
     matvec = matvec_roofline(ctx, w, xyz, dev)
@@ -361,6 +375,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
         "solve_only_rate": B / (b_s + solve_s),
         "plain_fp64_per_step_rate": plain_rate,
         "plain_fp64_sample": f"{n_plain} snapshots, b + FP64 matvec solve one at a time, setup excluded",
+        "plain_b_f32_per_step": plain_f32b,
         "graph_fp64_per_step": graph_step,
         "kernel_ms_per_step": {f: v[0] for f, v in timing.items() if v[1]},
         "matvec_roofline": matvec,
