@@ -148,3 +148,60 @@ def test_wire_coaxial_closed_form_on_device(cpm):
     assert 0 < dev[16] < dev[8] < dev[4]
     assert dev[16] < 0.04
     assert 1.6 < dev[4] / dev[8] < 2.4 and 1.6 < dev[8] / dev[16] < 2.4
+
+
+def _b_f32(C, params, R, eid, xyz_list, qy):
+    """b in FP32 (the structure factors on FP16 matrix cores with split
+    operands) for a batch of configurations."""
+    dev = "cuda"
+    ctx = C.Context(params)
+    ctx.set_electrolyte(qy)
+    ctx.build_elastance(torch.as_tensor(R, dtype=torch.float64, device=dev).contiguous(),
+                        torch.as_tensor(eid, dtype=torch.int32, device=dev).contiguous(),
+                        int(eid.max()) + 1)
+    xyz = torch.as_tensor(np.stack([np.asarray(r, np.float64) for r in xyz_list]),
+                          device=dev).contiguous()
+    b = torch.empty((len(xyz_list), len(R)), dtype=torch.float32, device=dev)
+    ctx.potential_vector(xyz, b)
+    ctx.synchronize()
+    prec = ctx.info("sf_fp32")
+    ctx.close()
+    return b.double().cpu().numpy(), prec
+
+
+def test_b_fp32_wire_and_3d_against_oracle(cpm):
+    """The reduced-precision b (split-FP16 structure factors) in the wire and
+    the 3D-periodic geometries, where the k set is not folded into planes
+    (general reduction and projection after the same kernel): within 5e-6 of
+    the oracle's FP64 b, one configuration and a batch of three."""
+    R, eid, R1, R2, per = I.coaxial_tubes(4, 8)
+    Lxy = 2 * R2 + 40.0
+    c = np.array([Lxy / 2, Lxy / 2, 0.0])
+    R = R + c
+    rad = 0.5 * (R1 + R2)
+    rs = []
+    for k in range(3):
+        ang = np.array([0.3, 1.9, 3.4, 5.0]) + 0.2 * k
+        rs.append(np.column_stack([c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang),
+                                   np.array([0.2, 0.9, 1.5, 2.1])]))
+    qy = np.array([1.0, -1.0, 1.0, -1.0])
+    p = O.Params(Lxy, Lxy, per, eta=1.979, alpha=0.3, rcut=12.0, kspace_eps=1e-8, geometry="wire")
+    bo = np.stack([O.potential_vector(R, r, qy, p) for r in rs])
+    gp = cpm.Params(Lxy, Lxy, per, 1.0, 1.979, 0.3, 12.0, 1e-8, geometry=1)
+    for sel in ([0], [0, 1, 2]):
+        bg, prec = _b_f32(cpm, gp, R, eid, [rs[k] for k in sel], qy)
+        err = rel(bg, bo[sel])
+        say(f"wire b FP32 ({len(sel)} configurations, structure factors {prec}): {err:.2e}")
+        assert err < 5e-6
+    w = I.small_capacitor("a")
+    Lz = 35.0
+    p = O.params_for(w, Lz=Lz, geometry="tinfoil")
+    snaps = [I.snapshot(w, s) for s in (0, 1, 2)]
+    bo = np.stack([O.potential_vector(w.electrode_xyz, r, w.electrolyte_q, p) for r in snaps])
+    gp = cpm.Params(w.Lx, w.Ly, Lz, 1.0, w.eta, w.alpha, w.rcut, w.kspace_eps, geometry=2)
+    for sel in ([1], [0, 1, 2]):
+        bg, prec = _b_f32(cpm, gp, w.electrode_xyz, w.electrode_id, [snaps[k] for k in sel],
+                          w.electrolyte_q)
+        err = rel(bg, bo[sel])
+        say(f"3D b FP32 ({len(sel)} configurations, structure factors {prec}): {err:.2e}")
+        assert err < 5e-6
