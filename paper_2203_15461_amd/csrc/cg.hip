@@ -413,6 +413,33 @@ __global__ void __launch_bounds__(256) k_cg_tiles(int nslot, int M2,
   store_tile(acc, Phi + ((size_t)part * nslot + (size_t)tile * 64) * VL);
 }
 
+// The same projection for one right-hand side (lane 0 of T): a matrix-core
+// tile would compute 64 lanes to keep one, so the product runs on the vector
+// units.  One workgroup per item, as above; its four waves split the item's
+// rows into contiguous quarters, lane l takes slot 64 tile + l, and the four
+// partial sums are added in wave order.  T's entries are uniform across the
+// wave.  Writes lane 0 of the item's Phi rows only.
+__global__ void __launch_bounds__(256) k_proj_one(int nslot, int M2, const int* __restrict__ items,
+                                                  const double* __restrict__ Ecat,
+                                                  const double* __restrict__ T,
+                                                  double* __restrict__ Phi) {
+  __shared__ double part[4][64];
+  const int* it = items + 6 * blockIdx.x;
+  const int tile = it[0], beg = it[2], end = it[3], q = it[4], L = it[5];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r0 = beg + (end - beg) * wave / 4, r1 = beg + (end - beg) * (wave + 1) / 4;
+  const double* e = Ecat + (size_t)tile * 64 + lane;
+  const double* t = T + (size_t)L * M2 * VL;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int r = r0; r < r1; ++r) acc += e[(size_t)r * nslot] * t[(size_t)r * VL];
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0)
+    Phi[((size_t)q * nslot + (size_t)tile * 64 + lane) * VL] =
+        (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+}
+
 // ---- A p and the conjugate-gradient steps ---------------------------------
 // Every kernel below runs on the same grid (nblk blocks of CG_WAVES waves),
 // so the partials of one are summed by the next over the same block count.
@@ -1158,6 +1185,12 @@ void launch_cg_tiles(hipStream_t st, int nitems, int nslot, int ncp, const int* 
                      const double* P, double* Phi) {
   hipLaunchKernelGGL(k_cg_tiles, dim3(nitems), dim3(256), 0, st, nslot, 2 * ncp, items, Ecat, T,
                      bcol, bval, P, Phi);
+}
+
+void launch_proj_one(hipStream_t st, int nitems, int nslot, int ncp, const int* items,
+                     const double* Ecat, const double* T, double* Phi) {
+  hipLaunchKernelGGL(k_proj_one, dim3(nitems), dim3(256), 0, st, nslot, 2 * ncp, items, Ecat, T,
+                     Phi);
 }
 
 void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, const int* slot_atom,

@@ -1824,8 +1824,12 @@ cpm_status pv_enqueue(cpm_ctx* c, int batch, const double* d_xyz, void* d_b, int
                                  b.sc_len, b.sc_koff, b.sc_nidx, b.sfm_part, b.w2, b.pz,
                                  2 * c->ncp, b.bT); }
       { Timed t(c, "projection");
-        launch_cg_tiles(st, c->b_nitems, c->nmap, c->ncp, b.b_items, b.Ecat, b.bT, nullptr,
-                        nullptr, nullptr, b.bPhi); }
+        // one configuration: vector units (a matrix-core tile would fill 64 lanes for one)
+        if (g == 1)
+          launch_proj_one(st, c->b_nitems, c->nmap, c->ncp, b.b_items, b.Ecat, b.bT, b.bPhi);
+        else
+          launch_cg_tiles(st, c->b_nitems, c->nmap, c->ncp, b.b_items, b.Ecat, b.bT, nullptr,
+                          nullptr, nullptr, b.bPhi); }
       if (conc) HIP_TRY(c, hipStreamWaitEvent(st, c->rs_ev_out, 0));
       { Timed t(c, "combine");
         launch_b_final(st, g, n, c->nmap, c->b_nparts, b.slot_of, b.bPhi, b.phir_part,

@@ -185,6 +185,9 @@ void launch_cg_plane_mix(hipStream_t st, int ncp, int ncolsort, int nlayers, int
 void launch_cg_tiles(hipStream_t st, int nitems, int nslot, int ncp, const int* items,
                      const double* Ecat, const double* T, const int* bcol, const double* bval,
                      const double* P, double* Phi);
+// the b projection for a single configuration (lane 0 of T and Phi), same items
+void launch_proj_one(hipStream_t st, int nitems, int nslot, int ncp, const int* items,
+                     const double* Ecat, const double* T, double* Phi);
 // The kernels below share one grid of nblk blocks; each sums the partials
 // of the previous one.  AP (operator; dense: AP given) with partials of p.Ap.
 void launch_cg_apply(hipStream_t st, bool dense, int nblk, int nslot, int n, const int* slot_atom,

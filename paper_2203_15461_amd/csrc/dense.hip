@@ -304,27 +304,6 @@ __device__ inline double block_sum1024(double v, double* sh) {
   return t;
 }
 
-// four sums at once over a 1024-thread workgroup (sh: 4 x 16); every thread
-// receives the four totals
-__device__ inline void block_sum1024x4(double (&v)[4], double (*sh)[16]) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < 4; ++k) sh[k][wave] = v[k];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < 16; ++w) t += sh[k][w];
-    v[k] = t;
-  }
-  __syncthreads();
-}
-
 // out[i] = sum_{j<n} M[i][j] for i < n (one wave per row, fixed order)
 __global__ void k_row_sums(int n, int npad, const double* __restrict__ M, double* out) {
   const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -533,29 +512,47 @@ void launch_matvec(hipStream_t st, int which, int npad, const void* M, int batch
 // dst[b] (npad apart, FP64) = src[b] (ldx apart, FP64 or FP32) minus its mean
 // over i < n when `center` (the same fixed-order sum as k_row_means), zero
 // for n <= i < npad: the padded right-hand side of the streaming solve.
-__global__ void __launch_bounds__(1024) k_center_pad(int n, int npad, const void* __restrict__ x,
-                                                     int x_is_f32, int ldx, int center,
+// Grid (batch, parts): every workgroup of a vector forms the same mean (the
+// same order; four loads per thread in flight) and writes its own part, so a
+// single vector is not left to one workgroup.
+template <typename TX>
+__global__ void __launch_bounds__(1024) k_center_pad(int n, int npad, const TX* __restrict__ x,
+                                                     int ldx, int center,
                                                      double* __restrict__ dst) {
   __shared__ double sh[16];
-  const int b = blockIdx.x;
-  auto at = [&](int i) {
-    return x_is_f32 ? (double)reinterpret_cast<const float*>(x)[(size_t)b * ldx + i]
-                    : reinterpret_cast<const double*>(x)[(size_t)b * ldx + i];
-  };
+  const TX* xb = x + (size_t)blockIdx.x * ldx;
   double mean = 0.0;
   if (center) {
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += 1024) s += at(i);
+    for (int i0 = threadIdx.x; i0 < n; i0 += 4096) {
+      double v[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) v[j] = (double)xb[min(i0 + 1024 * j, n - 1)];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s += i0 + 1024 * j < n ? v[j] : 0.0;
+    }
     mean = block_sum1024(s, sh) / n;
   }
-  double* out = dst + (size_t)b * npad;
-  for (int i = threadIdx.x; i < npad; i += 1024) out[i] = i < n ? at(i) - mean : 0.0;
+  double* out = dst + (size_t)blockIdx.x * npad;
+  for (int i = blockIdx.y * 1024 + threadIdx.x; i < npad; i += 1024 * gridDim.y)
+    out[i] = i < n ? (double)xb[i] - mean : 0.0;
+}
+
+// workgroups per vector of the two per-vector passes: all of the vector's
+// 1024-element parts for small batches, one otherwise
+static int vector_parts(int batch, int len) {
+  return batch < 16 ? std::max(1, (len + 1023) / 1024) : 1;
 }
 
 void launch_center_pad(hipStream_t st, int n, int npad, int batch, const void* x, int x_is_f32,
                        int ldx, int center, double* dst) {
-  hipLaunchKernelGGL(k_center_pad, dim3(batch), dim3(1024), 0, st, n, npad, x, x_is_f32, ldx,
-                     center, dst);
+  const dim3 grid(batch, vector_parts(batch, npad));
+  if (x_is_f32)
+    hipLaunchKernelGGL(k_center_pad<float>, grid, dim3(1024), 0, st, n, npad,
+                       static_cast<const float*>(x), ldx, center, dst);
+  else
+    hipLaunchKernelGGL(k_center_pad<double>, grid, dim3(1024), 0, st, n, npad,
+                       static_cast<const double*>(x), ldx, center, dst);
 }
 
 // means[b] = (1/n) sum_{i<n} x[b][i]: the uniform part of a right-hand side.
@@ -612,11 +609,15 @@ void launch_make_rhs(hipStream_t st, int n, int npad, int batch, const void* bsr
 }
 
 // ---------------------------------------------------------------------------
-// Neutrality projection and electrode totals, one workgroup per vector:
-//   q = qt - (e^T qt / s) u,   Q_alpha = sum_{i in alpha} q_i  (FP64).
-// The totals of four electrodes are gathered in the pass that writes q (and
-// of four more per further pass); each is one fixed-order workgroup sum.
+// Neutrality projection and electrode totals (FP64):
+//   mu = e^T qt / s,  q = qt - mu u,  Q_alpha = T_alpha - mu U_alpha,
+// with T_alpha and U_alpha the sums of qt and u over electrode alpha (equal
+// to the sum of q over alpha).  Grid (batch, parts): every workgroup of a
+// vector forms the same e^T qt (one fixed-order workgroup sum) and writes its
+// own part of q; workgroup 0 also forms the electrode sums, four electrodes
+// per pass, the first four in the pass that sums e^T qt.
 // ---------------------------------------------------------------------------
+template <bool ADD>
 __global__ void __launch_bounds__(1024) k_finalize(int n, const double* __restrict__ qt, int ldqt,
                                                    const double* __restrict__ add,
                                                    const double* __restrict__ u,
@@ -624,44 +625,97 @@ __global__ void __launch_bounds__(1024) k_finalize(int n, const double* __restri
                                                    const int* __restrict__ eid, int n_e,
                                                    double* __restrict__ q, int ldq,
                                                    double* __restrict__ Qe) {
-  __shared__ double sh[4][16];
+  __shared__ double sh[16];
+  __shared__ double shq[8][16];
   const int b = blockIdx.x;
   const double* x = qt + (size_t)b * ldqt;
-  double s = 0.0;
-  for (int i = threadIdx.x; i < n; i += 1024) s += add ? x[i] + add[i] : x[i];
-  s = block_sum1024(s, sh[0]);
+  auto val = [&](int i) { return ADD ? x[i] + add[i] : x[i]; };
+  const bool totals = Qe && blockIdx.y == 0;
+  double s = 0.0, t[4] = {0.0, 0.0, 0.0, 0.0}, w[4] = {0.0, 0.0, 0.0, 0.0};
+  // four elements per thread in flight: i0 + 1024 j, in increasing order
+  for (int i0 = threadIdx.x; i0 < n; i0 += 4096) {
+    double v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = val(min(i0 + 1024 * j, n - 1));
+    if (totals) {
+      double uu[4];
+      int e[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int i = min(i0 + 1024 * j, n - 1);
+        uu[j] = u[i];
+        e[j] = i0 + 1024 * j < n ? eid[i] : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          t[k] += e[j] == k ? v[j] : 0.0;
+          w[k] += e[j] == k ? uu[j] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s += i0 + 1024 * j < n ? v[j] : 0.0;
+  }
+  s = block_sum1024(s, sh);
   const double mu = s / (*s_dev);
   double* qo = q + (size_t)b * ldq;
-  for (int a0 = 0; a0 < (Qe ? n_e : 1); a0 += 4) {
-    double t[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i = threadIdx.x; i < n; i += 1024) {
-      double v;
-      if (a0 == 0) {
-        v = (add ? x[i] + add[i] : x[i]) - mu * u[i];
-        qo[i] = v;
-      } else {
-        v = qo[i];                 // written by this thread in the first pass
-      }
-      if (Qe) {
-        const int e = eid[i] - a0;
+  for (int i = blockIdx.y * 1024 + threadIdx.x; i < n; i += 1024 * gridDim.y)
+    qo[i] = val(i) - mu * u[i];
+  if (!totals) return;
+#pragma unroll 1
+  for (int a0 = 0; a0 < n_e; a0 += 4) {
+    if (a0 > 0) {                   // electrodes beyond the first four
 #pragma unroll
-        for (int k = 0; k < 4; ++k)
-          if (e == k) t[k] += v;
+      for (int k = 0; k < 4; ++k) t[k] = w[k] = 0.0;
+#pragma unroll 1
+      for (int i = threadIdx.x; i < n; i += 1024) {
+        const int e = eid[i] - a0;
+        const double v = val(i), ui = u[i];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          t[k] += e == k ? v : 0.0;
+          w[k] += e == k ? ui : 0.0;
+        }
       }
     }
-    if (!Qe) break;
-    block_sum1024x4(t, sh);
+    // wave sums, then thread k < 4 adds electrode a0 + k's 16 wave sums in order
 #pragma unroll
-    for (int k = 0; k < 4; ++k)
-      if (threadIdx.x == k && a0 + k < n_e) Qe[(size_t)b * n_e + a0 + k] = t[k];
+    for (int k = 0; k < 4; ++k) {
+      t[k] = wave_sum(t[k]);
+      w[k] = wave_sum(w[k]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        shq[k][wave] = t[k];
+        shq[4 + k][wave] = w[k];
+      }
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < 4 && a0 + k < n_e) {
+      double tt = 0.0, ww = 0.0;
+      for (int v = 0; v < 16; ++v) {
+        tt += shq[k][v];
+        ww += shq[4 + k][v];
+      }
+      Qe[(size_t)b * n_e + a0 + k] = tt - mu * ww;
+    }
+    __syncthreads();
   }
 }
 
 void launch_finalize(hipStream_t st, int n, int batch, const double* qt, int ldqt, const double* add,
                      const double* u, const double* s_dev, const int* eid, int n_e, double* q,
                      int ldq, double* Qe) {
-  hipLaunchKernelGGL(k_finalize, dim3(batch), dim3(1024), 0, st, n, qt, ldqt, add, u, s_dev, eid,
-                     n_e, q, ldq, Qe);
+  const dim3 grid(batch, vector_parts(batch, n));
+  if (add)
+    hipLaunchKernelGGL(k_finalize<true>, grid, dim3(1024), 0, st, n, qt, ldqt, add, u, s_dev, eid,
+                       n_e, q, ldq, Qe);
+  else
+    hipLaunchKernelGGL(k_finalize<false>, grid, dim3(1024), 0, st, n, qt, ldqt, add, u, s_dev, eid,
+                       n_e, q, ldq, Qe);
 }
 
 
