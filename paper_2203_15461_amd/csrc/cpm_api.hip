@@ -567,7 +567,8 @@ cpm_status ensure_step_buffers(cpm_ctx* c) {
     if (fast) {
       const double per = 16.0 * c->sft_rows * c->mpad + 16.0 * c->sfm_pchunk +
                          16.0 * c->n + 32.0 * c->m + 24.0 * ((c->m + 255) / 256);
-      c->pv_group = std::max(1, std::min(CG_MAXG, (int)(1024.0 * 1024 * 1024 / per)));
+      c->pv_group = std::max(1, std::min(std::min(CG_MAXG, c->pv_group_cap),
+                                         (int)(1024.0 * 1024 * 1024 / per)));
     }
     const int G = c->pv_group;
     size_t part_rows = 0;                 // (configuration, chunk) blocks of sfm_part
@@ -773,6 +774,7 @@ cpm_status cpm_create(const cpm_params* params, void* hip_stream, cpm_ctx** out)
   if (const char* ev = std::getenv("CPM_RS_WG_TARGET")) c->rs_wg_target = std::max(8, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_SORT_MIN")) c->rs_sort_min = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_PV_FAST_MIN")) c->pv_fast_min = std::max(1, std::atoi(ev));
+  if (const char* ev = std::getenv("CPM_PV_GROUP")) c->pv_group_cap = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_RS_CONCURRENT")) c->rs_conc_ok = std::atoi(ev) != 0;
   if (const char* ev = std::getenv("CPM_CG_BLOCKS")) c->cg_cap = std::max(1, std::atoi(ev));
   if (const char* ev = std::getenv("CPM_CG_COARSE")) c->pc_k = std::atoi(ev) >= 3 ? 3 : 1;

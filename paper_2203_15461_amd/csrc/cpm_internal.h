@@ -332,6 +332,7 @@ struct cpm_ctx {
   int sfm_pchunk = 0;              // doubles per (configuration, chunk) of sfm_part
   int sfm_maxcnt = 0;              // largest number of n >= 0 of a sorted column
   int pv_group = 1;                // configurations per launch group (planar fast path)
+  int pv_group_cap = 64;           // most configurations per launch group (CPM_PV_GROUP)
   int b_nitems = 0, b_nparts = 1;  // work split of the b-path projection product
   int nmap = 0;                    // length of the real-space atom map
   std::vector<int> h_plane_rows;   // rows of the atom map per plane (multiples of 64)
