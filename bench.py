@@ -295,8 +295,12 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
     for s_ in range(n_plain):
         ctx.potential_vector(xyz[s_:s_ + 1], b1)
         ctx.solve_charges(b1, 0x000, q1, Qe1)
+    t_host = time.perf_counter()
     torch.cuda.synchronize()
     plain_rate = n_plain / (time.perf_counter() - ts)
+    # host time to enqueue the loop: close to the wall time when the host,
+    # not the GPU, bounds one configuration per step
+    plain_host_us = (t_host - ts) / n_plain * 1e6
     # the same loop with b in FP32 (the split-FP16 structure factors), still
     # solved by the FP64 matvec: the reduced-precision single-configuration
     # step; its charges are compared with the FP64 loop's last ones
@@ -374,6 +378,7 @@ def run_workload(args, w, B, name, steps, warmup, calibrate_copy):
         "phase_s": {"setup": setup_s, "b_all_snapshots": b_s, "solve_all_snapshots": solve_s},
         "solve_only_rate": B / (b_s + solve_s),
         "plain_fp64_per_step_rate": plain_rate,
+        "plain_fp64_host_enqueue_us_per_step": plain_host_us,
         "plain_fp64_sample": f"{n_plain} snapshots, b + FP64 matvec solve one at a time, setup excluded",
         "plain_b_f32_per_step": plain_f32b,
         "graph_fp64_per_step": graph_step,
