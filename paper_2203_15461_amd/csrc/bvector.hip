@@ -1952,20 +1952,17 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 4) k_real_space_plane(
   const int nblk = chunk < nbt ? (nbt - chunk + rchunks - 1) / rchunks : 0;
   const int s0 = blockIdx.z, sstep = gridDim.z;
   const int nloc = s0 < g ? (g - s0 + sstep - 1) / sstep : 0;
-  const int steps = nloc * nblk;
   const double wlo = zp - rc, whi = zp + rc;
-  auto hit = [&](int step) {
-    if (step >= steps) return false;
-    const int snap = s0 + sstep * (step / nblk), gb = chunk + rchunks * (step % nblk);
-    const double2 r = zr[(size_t)snap * nb64 + gb];
+  // does block blk of configuration snap reach the plane's z window?
+  auto hit = [&](int snap, int blk) {
+    const double2 r = zr[(size_t)snap * nb64 + chunk + rchunks * blk];
     const double a = r.x - Lz * floor((r.x - wlo) * invLz), w = r.y - r.x;
     return a < whi + 1e-9 || a + w >= wlo + Lz - 1e-9;
   };
-  auto fetch = [&](int step, bool h) {
+  auto fetch = [&](int snap, int blk) {
     double4 v = make_double4(0, 0, 0, 0);
-    if (h) {
-      const int snap = s0 + sstep * (step / nblk);
-      const int j = (chunk + rchunks * (step % nblk)) * 64 + lane;
+    if (blk >= 0) {
+      const int j = (chunk + rchunks * blk) * 64 + lane;
       if (j < m) v = cq[(size_t)snap * mpad64 + j];
     }
     return v;
@@ -2011,65 +2008,74 @@ __global__ void __launch_bounds__(64 * RS_WAVES, 4) k_real_space_plane(
     }
     wave_lds_sync();                             // the ring's entries are reused next
   };
-  bool h0 = hit(0), h1 = hit(1);
-  double4 f0 = fetch(0, h0), f1 = fetch(1, h1);
+  // per configuration: the blocks that reach the window, found 64 at a time
+  // (one z-range load per lane, no load waits on another), then taken in
+  // order with the charges of the next two in flight
   int head = 0, tail = 0;                        // ring window [head, tail), head in {0, 64}
-  for (int step = 0; step < steps; ++step) {
-    const int snap = s0 + sstep * (step / nblk), blk = step % nblk;
-    const bool hcur = h0;
-    const double4 cur = f0;
-    f0 = f1; h0 = h1;
-    h1 = hit(step + 2);
-    f1 = fetch(step + 2, h1);
-    if (hcur) {
-      const bool valid = (chunk + rchunks * blk) * 64 + lane < m;
-      double dz = cur.z - zp;
-      dz -= Lz * rint(dz * invLz);
-      const double rho2 = rc2 - dz * dz;
-      double dx = cur.x - cx, dy = cur.y - cy;
-      dx -= Lx * rint(dx * invLx);
-      dy -= Ly * rint(dy * invLy);
-      const double dx2 = dx - copysign(Lx, dx), dy2 = dy - copysign(Ly, dy);
-      // images whose distance from the tile's box can be below sqrt(rho2)
-      auto near = [&](double px, double py) {
-        const double ux = fmax(fabs(px) - hx, 0.0), uy = fmax(fabs(py) - hy, 0.0);
-        return ux * ux + uy * uy < rho2 + marg;
+  for (int li = 0; li < nloc; ++li) {
+    const int snap = s0 + sstep * li;
+    for (int b0 = 0; b0 < nblk; b0 += 64) {
+      unsigned long long hm = __ballot(b0 + lane < nblk && hit(snap, b0 + lane));
+      auto pop = [&]() {
+        if (!hm) return -1;
+        const int t = __builtin_ctzll(hm);
+        hm &= hm - 1ull;
+        return b0 + t;
       };
-      int cand = 0;
-      if (valid && fabs(dz) < rc) {
-        cand = (near(dx, dy) ? 1 : 0) | (near(dx2, dy) ? 2 : 0) | (near(dx, dy2) ? 4 : 0) |
-               (near(dx2, dy2) ? 8 : 0);
-      }
-      while (true) {
-        const bool has = cand != 0;
-        const unsigned long long bal = __ballot(has);
-        if (!bal) break;
-        if (has) {
-          const int which = __builtin_ctz(cand);
-          cand &= cand - 1;
-          const double px = (which & 1) ? dx2 : dx, py = (which & 2) ? dy2 : dy;
-          const int pos = (tail + __popcll(bal & ((1ull << lane) - 1ull))) & (RP_RING - 1);
-          W.c[pos] = make_float2((float)(-2.0 * px), (float)(-2.0 * py));
-          W.w[pos] = (float)(px * px + py * py - rho2 - marg);
-          W.d[pos] = make_double4(px, py, dz * dz, cur.w);
+      int bA = pop(), bB = pop();
+      double4 fA = fetch(snap, bA), fB = fetch(snap, bB);
+      while (bA >= 0) {
+        const int blk = bA;
+        const double4 cur = fA;
+        bA = bB;
+        fA = fB;
+        bB = pop();
+        fB = fetch(snap, bB);
+        const bool valid = (chunk + rchunks * blk) * 64 + lane < m;
+        double dz = cur.z - zp;
+        dz -= Lz * rint(dz * invLz);
+        const double rho2 = rc2 - dz * dz;
+        double dx = cur.x - cx, dy = cur.y - cy;
+        dx -= Lx * rint(dx * invLx);
+        dy -= Ly * rint(dy * invLy);
+        const double dx2 = dx - copysign(Lx, dx), dy2 = dy - copysign(Ly, dy);
+        // images whose distance from the tile's box can be below sqrt(rho2)
+        auto near = [&](double px, double py) {
+          const double ux = fmax(fabs(px) - hx, 0.0), uy = fmax(fabs(py) - hy, 0.0);
+          return ux * ux + uy * uy < rho2 + marg;
+        };
+        int cand = 0;
+        if (valid && fabs(dz) < rc) {
+          cand = (near(dx, dy) ? 1 : 0) | (near(dx2, dy) ? 2 : 0) | (near(dx, dy2) ? 4 : 0) |
+                 (near(dx2, dy2) ? 8 : 0);
         }
-        tail += __popcll(bal);
-        wave_lds_sync();
-        if (tail - head >= 64) {
-          process(head & (RP_RING - 1), 64);
-          head += 64;
+        while (true) {
+          const bool has = cand != 0;
+          const unsigned long long bal = __ballot(has);
+          if (!bal) break;
+          if (has) {
+            const int which = __builtin_ctz(cand);
+            cand &= cand - 1;
+            const double px = (which & 1) ? dx2 : dx, py = (which & 2) ? dy2 : dy;
+            const int pos = (tail + __popcll(bal & ((1ull << lane) - 1ull))) & (RP_RING - 1);
+            W.c[pos] = make_float2((float)(-2.0 * px), (float)(-2.0 * py));
+            W.w[pos] = (float)(px * px + py * py - rho2 - marg);
+            W.d[pos] = make_double4(px, py, dz * dz, cur.w);
+          }
+          tail += __popcll(bal);
+          wave_lds_sync();
+          if (tail - head >= 64) {
+            process(head & (RP_RING - 1), 64);
+            head += 64;
+          }
         }
       }
     }
-    if (blk == nblk - 1) {
-      if (tail > head) process(head & (RP_RING - 1), tail - head);
-      head = tail = 0;
-      if (atom >= 0) part[((size_t)snap * rchunks + chunk) * n + atom] = acc;
-      acc = 0.0;
-    }
+    if (tail > head) process(head & (RP_RING - 1), tail - head);
+    head = tail = 0;
+    if (atom >= 0) part[((size_t)snap * rchunks + chunk) * n + atom] = acc;
+    acc = 0.0;
   }
-  if (nblk == 0 && atom >= 0)
-    for (int snap = s0; snap < g; snap += sstep) part[((size_t)snap * rchunks + chunk) * n + atom] = 0.0;
 }
 
 void launch_b_real_space(hipStream_t st, int g, int n, int m, int mpad64, int rchunks,
