@@ -1131,6 +1131,61 @@ __global__ void __launch_bounds__(512) k_sf_layer_reduce(
   const int clo = sc_lo[c], chi = sc_lo[c] + sc_len[c] - 1, koff = sc_koff[c];
   const double* base0 = part + (size_t)snap * nchunks * pchunk + toff[mt];
   const int c0 = wave * nchunks / nw, c1 = (wave + 1) * nchunks / nw;
+  if (nw == 1 && ncnt <= 128) {
+    // one wave: each lane keeps the weighted S(c, +-n) of its (at most two)
+    // n in registers, so the chunk sums, the weights and the plane phases
+    // are all in flight at once and no LDS is used; the same sums in the
+    // same order as the general path below
+    double2 sp[2], sm[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int n = lane + 64 * h;
+      sp[h] = sm[h] = make_double2(0.0, 0.0);
+      if (n >= ncnt) continue;
+      double pr = 0, qr = 0, pi = 0, qi = 0;
+#pragma unroll 4
+      for (int ch = 0; ch < nchunks; ++ch) {
+        const double* base = base0 + (size_t)ch * pchunk;
+        pr += base[(2 * cl) * ldc + 2 * n];
+        qr += base[(2 * cl) * ldc + 2 * n + 1];
+        pi += base[(2 * cl + 1) * ldc + 2 * n];
+        qi += base[(2 * cl + 1) * ldc + 2 * n + 1];
+      }
+      double tpr = 0, tqr = 0, tpi = 0, tqi = 0;
+      tpr += pr;
+      tqr += qr;
+      tpi += pi;
+      tqi += qi;
+      if (n >= clo && n <= chi) {
+        const double w = w2[koff + (n - clo)];
+        sp[h] = make_double2(w * (tpr - tqi), w * (tpi + tqr));
+      }
+      if (n > 0 && -n >= clo && -n <= chi) {
+        const double w = w2[koff + (-n - clo)];
+        sm[h] = make_double2(w * (tpr + tqi), w * (tpi - tqr));
+      }
+    }
+    for (int L = 0; L < nlayers; ++L) {
+      double tr = 0.0, ti = 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int n = lane + 64 * h;
+        if (n >= ncnt) continue;
+        const double2 p = pz[(size_t)L * nzt + n];      // e^{-i n kz1 z_L}
+        tr += (sp[h].x * p.x - sp[h].y * p.y) + (sm[h].x * p.x + sm[h].y * p.y);
+        ti += (sp[h].x * p.y + sp[h].y * p.x) + (sm[h].y * p.x - sm[h].x * p.y);
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        tr += __shfl_xor(tr, o, 64);
+        ti += __shfl_xor(ti, o, 64);
+      }
+      if (lane == 0) {
+        Tcat[((size_t)L * M2 + 2 * c) * 64 + snap] = tr;
+        Tcat[((size_t)L * M2 + 2 * c + 1) * 64 + snap] = ti;
+      }
+    }
+    return;
+  }
   for (int n = lane; n < ncnt; n += 64) {
     double pr = 0, qr = 0, pi = 0, qi = 0;
 #pragma unroll 4
