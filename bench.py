@@ -78,7 +78,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a "
+        print(json.dumps({"error": "bench.py runs on one GPU only; multi-GPU sharding is a "
                                    "design note, not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 

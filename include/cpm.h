@@ -48,7 +48,7 @@ typedef enum {
   CPM_ENOMEM = 3,        /* device allocation failed                            */
   CPM_EHIP = 4,          /* HIP runtime error (launch, fault, copy)             */
   CPM_ENOTPD = 5,        /* A is not positive definite (Cholesky pivot <= 0)     */
-  CPM_EUNSUPPORTED = 6,  /* valid request this build does not provide          */
+  CPM_EUNSUPPORTED = 6,  /* valid request the library does not provide         */
   CPM_ENOCONV = 7        /* iteration stopped at its limit above the tolerance  */
 } cpm_status;
 
