@@ -130,6 +130,29 @@ def test_2880_reduced_precision_kernels_against_golden(cpm, env, monkeypatch):
     assert np.abs(q.sum(axis=1)).max() <= 1e-12
 
 
+# real-space chunking of a 64-configuration group (switch read when a context
+# is created): one chunk per atom block, so that each wave walks all 96
+# charge blocks of a configuration in two windows of 64, and many chunks of
+# one or two blocks each
+RS_TARGETS = ["64", "65536"]
+
+
+@pytest.mark.parametrize("target", RS_TARGETS)
+def test_2880_real_space_chunking_against_golden(cpm, target, monkeypatch):
+    g = np.load(os.path.join(GOLDEN, "graphite_capacitor_2880.npz"))
+    w = I.graphite_capacitor()
+    idx = [k % 3 for k in range(64)]
+    xyz = torch.as_tensor(np.stack([I.snapshot(w, int(g["snapshots"][k])) for k in idx]),
+                          dtype=torch.float64, device="cuda").contiguous()
+    monkeypatch.setenv("CPM_RS_WG_TARGET", target)
+    say(f"2880, 64 configurations, b FP64, real-space workgroup target {target}")
+    b, q, Qe, group = _bench_step(cpm, w, xyz, 1, 0x000, b_f32=False)
+    eb, eq, eQ = rel(b, g["b"][idx]), rel(q, g["q"][idx]), rel(Qe, g["Q"][idx])
+    say(f"  b {eb:.3e} q {eq:.3e} Q {eQ:.3e}")
+    assert eb < 1e-10 and eq < 1e-10 and eQ < 1e-10
+    assert np.abs(q.sum(axis=1)).max() <= 1e-12
+
+
 def _golden_20064(alpha):
     path = os.path.join(GOLDEN, f"scaled_graphite_capacitor_20064_rows_alpha{alpha:.2f}.npz")
     if not os.path.exists(path):
