@@ -133,7 +133,7 @@ void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int
 // ---------------------------------------------------------------------------
 // Diagonal 64x64 block of the Cholesky factorisation, in one workgroup, in
 // four panels of 16 columns: wave 0 factors the panel's 16 x 16 diagonal
-// block right-looking (wave-level syncs only), one thread per row below
+// block right-looking in registers (cross-lane moves), one thread per row below
 // solves that row's 16 panel entries, then every thread updates trailing
 // elements.  The inverse of the factor: the four diagonal 16 x 16 blocks by
 // forward substitution (a wave each, a lane per column), then block rows 1..3
@@ -141,10 +141,12 @@ void launch_gemm_f64(hipStream_t st, bool transA, bool transB, int M, int N, int
 // barriers in all.  A pivot <= 0 (or NaN) records 1 + its global index in
 // *flag (first one wins) and continues with 1.
 // ---------------------------------------------------------------------------
-__device__ inline void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+// lane l's value of v, in every lane (l uniform)
+__device__ inline double readlane_f64(double v, int l) {
+  const unsigned long long x = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)x, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(x >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
 __global__ void __launch_bounds__(1024) k_potrf_diag(double* Lblk, int ld, double* Dinv, int* flag,
@@ -162,26 +164,44 @@ __global__ void __launch_bounds__(1024) k_potrf_diag(double* Lblk, int ld, doubl
   __syncthreads();
   for (int p0 = 0; p0 < 64; p0 += 16) {
     if (wave == 0) {
+      // lane (r, part) keeps row p0 + r, columns p0 + 4 part .. + 3, of the
+      // panel's diagonal block in registers; step j reads the pivot and the
+      // entries of column j from the lanes that own them (cross-lane moves),
+      // so no step waits on LDS
       const int r = lane & 15, part = lane >> 4;
+      double v[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[s] = a[p0 + r][p0 + 4 * part + s];
+      double rdl = 0.0;                    // 1 / L[p0 + r][p0 + r]
+#pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const int jj = p0 + j;
-        double piv = a[jj][jj];
+        const int pj = j >> 2, sj = j & 3;   // owner part and slot of column j
+        double piv = readlane_f64(v[sj], j + 16 * pj);
         if (!(piv > 0.0)) {
-          if (lane == 0) atomicCAS(flag, 0, k0 + jj + 1);
+          if (lane == 0) atomicCAS(flag, 0, k0 + p0 + j + 1);
           piv = 1.0;
         }
         const double d = sqrt(piv), rdj = 1.0 / d;
-        const double lr = a[p0 + r][jj] * rdj;
-        if (r > j)
-          for (int l = j + 1 + part; l <= r; l += 4) a[p0 + r][p0 + l] -= lr * (a[p0 + l][jj] * rdj);
-        wave_sync_lds();
-        if (part == 0 && r > j) a[p0 + r][jj] = lr;
-        if (lane == 0) {
-          a[jj][jj] = d;
-          rd[jj] = rdj;
+        const double arj = __shfl(v[sj], r + 16 * pj, 64);       // L[r][j] before scaling
+        double acj[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) acj[s] = __shfl(v[sj], 4 * part + s + 16 * pj, 64);
+        const double lr = arj * rdj;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          const int c = 4 * part + s;
+          if (c > j && c <= r) v[s] -= lr * (acj[s] * rdj);
         }
-        wave_sync_lds();
+        if (part == pj) {
+          if (r > j) v[sj] = lr;
+          else if (r == j) v[sj] = d;
+        }
+        if (r == j) rdl = rdj;
       }
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+        if (4 * part + s <= r) a[p0 + r][p0 + 4 * part + s] = v[s];
+      if (part == 0) rd[p0 + r] = rdl;
     }
     __syncthreads();
     const int nrem = 64 - p0 - 16;
