@@ -156,10 +156,20 @@ __global__ void __launch_bounds__(1024) k_potrf_diag(double* Lblk, int ld, doubl
   __shared__ double T[3][16][17];  // block-row products of the inverse
   __shared__ double rd[64];        // 1 / L[j][j]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int e = tid; e < 64 * 64; e += 1024) {
-    const int r = e >> 6, c = e & 63;
-    a[r][c] = (c <= r) ? Lblk[(size_t)r * ld + c] : 0.0;
-    X[r][c] = 0.0;
+  {
+    // four entries per thread, their loads all in flight at once
+    double t[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 1024 * u, r = e >> 6, c = e & 63;
+      t[u] = (c <= r) ? Lblk[(size_t)r * ld + c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + 1024 * u, r = e >> 6, c = e & 63;
+      a[r][c] = t[u];
+      X[r][c] = 0.0;
+    }
   }
   __syncthreads();
   for (int p0 = 0; p0 < 64; p0 += 16) {
