@@ -284,7 +284,7 @@ struct cpm_ctx {
   int sf16_wg_target = 2048;       // ... and for the split-FP16 one
   int sfm_min_chunk = 512;         // fewest charges per matrix-core chunk
   int sfm_max_chunk = 4096;        // most charges per matrix-core chunk
-  int chol_block = 256;            // columns per outer block of the Cholesky / inverse
+  int chol_block = 512;            // columns per outer block of the Cholesky / inverse (CPM_CHOL_BLOCK)
   int cg_cap = 0;                  // most workgroups of the CG vector kernels (0: by size)
   int cg_precond = 2;              // operator CG preconditioner: 0 none, 1 additive, 2 balancing
   int pc_tiles = 0;                // tiles of the preconditioner in use (0: none or not built)
