@@ -1491,7 +1491,7 @@ cpm_status cpm_invert(cpm_ctx* c, unsigned store_flags) {
     return fail(c, CPM_EINVAL, "CPM_INVERT_FACTOR keeps no copy of S");
   if (factor && c->n_e > CCM_MAXE)
     return fail(c, CPM_EUNSUPPORTED, "CPM_INVERT_FACTOR supports at most %d electrodes", CCM_MAXE);
-  const int n = c->n, npad = c->npad, nb = npad / TILE;
+  const int npad = c->npad, nb = npad / TILE;
   Buffers& b = c->b;
   TRY(dalloc(c, &b.L, (size_t)npad * npad));
   TRY(dalloc(c, &b.Dinv, (size_t)nb * TILE * TILE));
